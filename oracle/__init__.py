@@ -1,0 +1,234 @@
+"""Plain FP64 CPU oracle of the multiresolution-adapted lattice Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. The GPU library
+never calls it and shares no code with it; the two meet only through the seeded
+inputs of ``paper_2103_02903_amd.workloads``, which hold none of the method's
+arithmetic.
+
+The C source ``mr_oracle.c`` follows the paper (arXiv 2103.02903) operation by
+operation on dense per-level arrays; this module only marshals numpy arrays.
+
+Flat layouts (all levels jmin..J concatenated, cell index x + N_l * y):
+  tree   uint8   [level][cell]       1 = cell in the complete tree
+  values float64 [level][h][cell]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_BUILD = os.path.join(_HERE, "_build")
+_SO = os.path.join(_BUILD, "liborc.so")
+_SRC = os.path.join(_HERE, "mr_oracle.c")
+
+SCHEMES = {"D1Q2": (1, 1, 2), "D1Q3": (2, 1, 3), "D2Q9": (3, 2, 9)}  # id, dim, q
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("q", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("jmin", ctypes.c_int), ("jmax", ctypes.c_int), ("pad_", ctypes.c_int),
+                ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
+                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double),
+                ("s", ctypes.c_double * 9)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER(_Params)
+        u8 = ctypes.c_void_p
+        dp = ctypes.c_void_p
+        L.orc_total_cells.argtypes = [P]; L.orc_total_cells.restype = ctypes.c_int64
+        L.orc_level_offset.argtypes = [P, ctypes.c_int]; L.orc_level_offset.restype = ctypes.c_int64
+        for name, args in [("orc_init", [P, dp, u8, dp]), ("orc_reconstruct", [P, u8, dp]),
+                           ("orc_details", [P, u8, dp, dp]), ("orc_adapt_tree", [P, u8, dp, u8]),
+                           ("orc_step", [P, u8, dp]), ("orc_transfer", [P, u8, dp, u8, dp]),
+                           ("orc_transport", [P, u8, dp, dp, ctypes.c_int]),
+                           ("orc_collide", [P, u8, dp]), ("orc_uniform_step", [P, dp]),
+                           ("orc_moment_matrix_inverse", [P, dp]), ("orc_leaf_counts", [P, u8, dp]),
+                           ("orc_check_tree", [P, u8])]:
+            f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
+        L.orc_predict.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_predict.restype = ctypes.c_double
+        L.orc_collide_cell.argtypes = [P, dp]; L.orc_collide_cell.restype = None
+        L.orc_moment_matrix.argtypes = [P, dp]; L.orc_moment_matrix.restype = None
+        L.orc_equilibrium.argtypes = [P, dp, dp]; L.orc_equilibrium.restype = None
+        L.orc_velocities.argtypes = [P, dp]; L.orc_velocities.restype = None
+        L.orc_mass.argtypes = [P, u8, dp]; L.orc_mass.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Oracle:
+    """One oracle instance for a parameter set (see ``workloads`` for the dict keys)."""
+
+    def __init__(self, cfg: dict):
+        scheme_id, dim, q = SCHEMES[cfg["scheme"]]
+        s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        self.p = _Params(dim, q, scheme_id, int(cfg["jmin"]), int(cfg["jmax"]), 0,
+                         float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)),
+                         float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s))
+        self.dim, self.q, self.jmin, self.jmax = dim, q, int(cfg["jmin"]), int(cfg["jmax"])
+        self.L = lib()
+        self.total = int(self.L.orc_total_cells(ctypes.byref(self.p)))
+
+    # ---- layout helpers ----
+    def ncells(self, l: int) -> int:
+        return 1 << (self.dim * l)
+
+    def level_offset(self, l: int) -> int:
+        return int(self.L.orc_level_offset(ctypes.byref(self.p), l))
+
+    def tree_level(self, tree: np.ndarray, l: int) -> np.ndarray:
+        o = self.level_offset(l)
+        t = tree[o:o + self.ncells(l)]
+        return t.reshape((1 << l, 1 << l)) if self.dim == 2 else t
+
+    def values_level(self, values: np.ndarray, l: int) -> np.ndarray:
+        o = self.q * self.level_offset(l)
+        v = values[o:o + self.q * self.ncells(l)].reshape(self.q, self.ncells(l))
+        return v.reshape(self.q, 1 << l, 1 << l) if self.dim == 2 else v
+
+    def new_state(self):
+        return np.zeros(self.total, np.uint8), np.zeros(self.q * self.total, np.float64)
+
+    # ---- operations ----
+    def init(self, m0: np.ndarray):
+        tree, values = self.new_state()
+        m0 = np.ascontiguousarray(m0, dtype=np.float64)
+        self._chk(self.L.orc_init(ctypes.byref(self.p), _ptr(m0), _ptr(tree), _ptr(values)))
+        return tree, values
+
+    def step(self, tree: np.ndarray, values: np.ndarray, nsteps: int = 1):
+        for _ in range(nsteps):
+            self._chk(self.L.orc_step(ctypes.byref(self.p), _ptr(tree), _ptr(values)))
+        return tree, values
+
+    def reconstruct(self, tree, values):
+        v = values.copy()
+        self._chk(self.L.orc_reconstruct(ctypes.byref(self.p), _ptr(tree), _ptr(v)))
+        return v
+
+    def details(self, tree, dense_values):
+        D = np.empty(self.total, np.float64)
+        self._chk(self.L.orc_details(ctypes.byref(self.p), _ptr(tree), _ptr(dense_values), _ptr(D)))
+        return D
+
+    def adapt_tree(self, tree, D):
+        tnew = np.zeros(self.total, np.uint8)
+        self._chk(self.L.orc_adapt_tree(ctypes.byref(self.p), _ptr(tree), _ptr(D), _ptr(tnew)))
+        return tnew
+
+    def new_tree_from_state(self, tree, values):
+        """Mesh adaptation G(H(T(tree))) with details of the given leaf values."""
+        dense = self.reconstruct(tree, values)
+        return self.adapt_tree(tree, self.details(tree, dense))
+
+    def transfer(self, told, dense_old, tnew):
+        vnew = np.zeros(self.q * self.total, np.float64)
+        self._chk(self.L.orc_transfer(ctypes.byref(self.p), _ptr(told), _ptr(dense_old),
+                                      _ptr(tnew), _ptr(vnew)))
+        return vnew
+
+    def transport(self, tree, dense, definition_form=False):
+        out = np.zeros(self.q * self.total, np.float64)
+        self._chk(self.L.orc_transport(ctypes.byref(self.p), _ptr(tree), _ptr(dense), _ptr(out),
+                                       int(definition_form)))
+        return out
+
+    def collide(self, tree, values):
+        v = values.copy()
+        self._chk(self.L.orc_collide(ctypes.byref(self.p), _ptr(tree), _ptr(v)))
+        return v
+
+    def collide_cell(self, f):
+        f = np.array(f, dtype=np.float64)
+        self.L.orc_collide_cell(ctypes.byref(self.p), _ptr(f))
+        return f
+
+    def predict(self, parent_level: np.ndarray, l: int, cx: int, cy: int = 0) -> float:
+        a = np.ascontiguousarray(parent_level, dtype=np.float64).ravel()
+        return float(self.L.orc_predict(ctypes.byref(self.p), _ptr(a), l, cx, cy))
+
+    def uniform_step(self, fJ: np.ndarray, nsteps: int = 1):
+        for _ in range(nsteps):
+            self._chk(self.L.orc_uniform_step(ctypes.byref(self.p), _ptr(fJ)))
+        return fJ
+
+    def moment_matrix(self):
+        M = np.zeros(self.q * self.q, np.float64)
+        self.L.orc_moment_matrix(ctypes.byref(self.p), _ptr(M))
+        return M.reshape(self.q, self.q)
+
+    def moment_matrix_inverse(self):
+        M = np.zeros(self.q * self.q, np.float64)
+        self._chk(self.L.orc_moment_matrix_inverse(ctypes.byref(self.p), _ptr(M)))
+        return M.reshape(self.q, self.q)
+
+    def equilibrium(self, m):
+        m = np.array(m, dtype=np.float64)
+        meq = np.zeros(self.q, np.float64)
+        self.L.orc_equilibrium(ctypes.byref(self.p), _ptr(m), _ptr(meq))
+        return meq
+
+    def velocities(self):
+        eta = np.zeros(2 * self.q, np.int32)
+        self.L.orc_velocities(ctypes.byref(self.p), _ptr(eta))
+        return eta.reshape(self.q, 2)
+
+    def leaf_counts(self, tree):
+        c = np.zeros(self.jmax + 1, np.int64)
+        self._chk(self.L.orc_leaf_counts(ctypes.byref(self.p), _ptr(tree), _ptr(c)))
+        return c
+
+    def mass(self, tree, values) -> float:
+        return float(self.L.orc_mass(ctypes.byref(self.p), _ptr(tree), _ptr(values)))
+
+    def check_tree(self, tree) -> int:
+        return int(self.L.orc_check_tree(ctypes.byref(self.p), _ptr(tree)))
+
+    def leaf_mask(self, tree, l):
+        t = self.tree_level(tree, l).astype(bool)
+        if l == self.jmax:
+            return t
+        tc = self.tree_level(tree, l + 1).astype(bool)
+        if self.dim == 1:
+            return t & ~tc[0::2]
+        return t & ~tc[0::2, 0::2]
+
+    def finest(self, tree, values):
+        """Reconstruction f^hat-hat on the finest level, shape (q, N_J[, N_J])."""
+        return self.values_level(self.reconstruct(tree, values), self.jmax).copy()
+
+    @staticmethod
+    def _chk(rc):
+        if rc != 0:
+            raise RuntimeError("oracle call failed with status %d" % rc)

@@ -1,0 +1,574 @@
+/*
+ * Plain FP64 CPU oracle of the multiresolution-adapted lattice Boltzmann step
+ * (Bellotti, Gouarin, Graille, Massot, arXiv 2103.02903).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the GPU library, with which it shares
+ * no code. Build with -ffp-contract=off and without fast-math: the prediction,
+ * projection and detail expressions below are evaluated in the order written.
+ *
+ * Readings of the paper taken here (each is listed with its justification in
+ * the design notes of the repository):
+ *  - 2D prediction: the cross term enters with the tensor-product sign
+ *    +(-1)^{dx+dy} Q_xy (Appendix 2 builds the 2D operator as a Kronecker
+ *    product of the 1D one); only this sign is exact on the monomial x*y.
+ *  - The thresholded set is closed under ancestors (parent group of every kept
+ *    group) before the enlargement H_eps, so that H_eps acts on a tree.
+ *  - Neighbour addition shifts by eta^h in cells of the kept cell's own level.
+ *  - At the finest level (n = J - l = 0) the transport is the plain shift
+ *    f(k - eta), which the E/A formula equals in exact arithmetic.
+ *  - Collision is written m + S (m_eq - m), equal to (I - S) m + S m_eq.
+ *  - D2Q9: diagonal logical velocities are (+-1, +-1) as the rows of M imply;
+ *    the equilibrium uses |q|^2 and c_s^4 rho where the printed text is garbled.
+ *  - All index arithmetic is periodic.
+ */
+#include "mr_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXQ 9
+
+/* ---- Level geometry (section "Nested lattices"): N_l = 2^l cells per axis ---- */
+
+static int side(int l) { return 1 << l; }
+static int64_t ncells(const orc_params *P, int l) { return (int64_t)1 << (P->dim * l); }
+static int wrapi(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+
+int64_t orc_level_offset(const orc_params *P, int l) {
+  int64_t off = 0;
+  for (int m = P->jmin; m < l; ++m) off += ncells(P, m);
+  return off;
+}
+
+int64_t orc_total_cells(const orc_params *P) { return orc_level_offset(P, P->jmax + 1); }
+
+static uint8_t *tree_at(const orc_params *P, const uint8_t *tree, int l) {
+  return (uint8_t *)tree + orc_level_offset(P, l);
+}
+static double *val_at(const orc_params *P, const double *v, int l, int h) {
+  return (double *)v + (int64_t)P->q * orc_level_offset(P, l) + (int64_t)h * ncells(P, l);
+}
+static int64_t cell_index(const orc_params *P, int l, int x, int y) {
+  return P->dim == 1 ? x : (int64_t)x + (int64_t)side(l) * y;
+}
+static int64_t cell_index_wrapped(const orc_params *P, int l, int x, int y) {
+  int n = side(l);
+  return P->dim == 1 ? wrapi(x, n) : (int64_t)wrapi(x, n) + (int64_t)n * wrapi(y, n);
+}
+static void cell_coords(const orc_params *P, int l, int64_t c, int *x, int *y) {
+  if (P->dim == 1) { *x = (int)c; *y = 0; }
+  else { *x = (int)(c % side(l)); *y = (int)(c / side(l)); }
+}
+static int nchildren(const orc_params *P) { return 1 << P->dim; }
+/* Child sigma of (x, y): sigma bit 0 is the x offset, bit 1 the y offset. */
+static int64_t child_index(const orc_params *P, int l, int x, int y, int sigma) {
+  int cx = 2 * x + (sigma & 1), cy = 2 * y + ((sigma >> 1) & 1);
+  return cell_index(P, l + 1, cx, cy);
+}
+static int is_leaf(const orc_params *P, const uint8_t *tree, int l, int64_t c) {
+  if (!tree_at(P, tree, l)[c]) return 0;
+  if (l == P->jmax) return 1;
+  int x, y;
+  cell_coords(P, l, c, &x, &y);
+  return !tree_at(P, tree, l + 1)[child_index(P, l, x, y, 0)];
+}
+static int is_internal(const orc_params *P, const uint8_t *tree, int l, int64_t c) {
+  return tree_at(P, tree, l)[c] && !is_leaf(P, tree, l, c);
+}
+
+/* ---- Scheme data (section "Collision and transport"; D2Q9 in the von Karman
+ *      section, Lallemand-Luo) ---- */
+
+void orc_velocities(const orc_params *P, int *eta) {
+  static const int d1q2[2][2] = {{1, 0}, {-1, 0}};
+  static const int d1q3[3][2] = {{0, 0}, {1, 0}, {-1, 0}};
+  static const int d2q9[9][2] = {{0, 0},  {1, 0},  {0, 1},   {-1, 0}, {0, -1},
+                                 {1, 1},  {-1, 1}, {-1, -1}, {1, -1}};
+  const int(*t)[2] = P->scheme == 1 ? d1q2 : P->scheme == 2 ? d1q3 : d2q9;
+  for (int h = 0; h < P->q; ++h) { eta[2 * h] = t[h][0]; eta[2 * h + 1] = t[h][1]; }
+}
+
+void orc_moment_matrix(const orc_params *P, double *M) {
+  const double L = P->lambda, L2 = L * L, L3 = L2 * L, L4 = L2 * L2;
+  memset(M, 0, sizeof(double) * P->q * P->q);
+  if (P->scheme == 1) {
+    const double m[2][2] = {{1, 1}, {L, -L}};
+    memcpy(M, m, sizeof m);
+  } else if (P->scheme == 2) {
+    const double m[3][3] = {{1, 1, 1}, {0, L, -L}, {0, L2, L2}};
+    memcpy(M, m, sizeof m);
+  } else {
+    const double m[9][9] = {
+        {1, 1, 1, 1, 1, 1, 1, 1, 1},
+        {0, L, 0, -L, 0, L, -L, -L, L},
+        {0, 0, L, 0, -L, L, L, -L, -L},
+        {-4 * L2, -L2, -L2, -L2, -L2, 2 * L2, 2 * L2, 2 * L2, 2 * L2},
+        {0, -2 * L3, 0, 2 * L3, 0, L3, -L3, -L3, L3},
+        {0, 0, -2 * L3, 0, 2 * L3, L3, L3, -L3, -L3},
+        {4 * L4, -2 * L4, -2 * L4, -2 * L4, -2 * L4, L4, L4, L4, L4},
+        {0, L2, -L2, L2, -L2, 0, 0, 0, 0},
+        {0, 0, 0, 0, 0, L2, -L2, L2, -L2}};
+    memcpy(M, m, sizeof m);
+  }
+}
+
+/* Gauss-Jordan elimination with partial pivoting. Returns 0 on success. */
+int orc_moment_matrix_inverse(const orc_params *P, double *Minv) {
+  const int q = P->q;
+  double A[MAXQ][2 * MAXQ];
+  double M[MAXQ * MAXQ];
+  orc_moment_matrix(P, M);
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < 2 * q; ++j) A[i][j] = j < q ? M[i * q + j] : (j - q == i ? 1.0 : 0.0);
+  for (int col = 0; col < q; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < q; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (A[piv][col] == 0.0) return -1;
+    if (piv != col)
+      for (int j = 0; j < 2 * q; ++j) { double t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t; }
+    const double d = A[col][col];
+    for (int j = 0; j < 2 * q; ++j) A[col][j] /= d;
+    for (int r = 0; r < q; ++r) {
+      if (r == col || A[r][col] == 0.0) continue;
+      const double f = A[r][col];
+      for (int j = 0; j < 2 * q; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) Minv[i * q + j] = A[i][q + j];
+  return 0;
+}
+
+/* Equilibrium moments as functions of the conserved ones. */
+void orc_equilibrium(const orc_params *P, const double *m, double *meq) {
+  const double L = P->lambda;
+  if (P->scheme == 1) {
+    meq[0] = m[0];
+    meq[1] = P->eq_param * m[0];
+  } else if (P->scheme == 2) {
+    meq[0] = m[0];
+    meq[1] = 0.5 * m[0] * m[0];
+    meq[2] = P->eq_param * L * L * m[0];
+  } else {
+    const double rho = m[0], qx = m[1], qy = m[2];
+    const double cs2 = L * L / 3.0;
+    const double q2 = qx * qx + qy * qy;
+    meq[0] = rho;
+    meq[1] = qx;
+    meq[2] = qy;
+    meq[3] = 3.0 * (-2.0 * cs2 * rho + q2 / rho);
+    meq[4] = -3.0 * cs2 * qx;
+    meq[5] = -3.0 * cs2 * qy;
+    meq[6] = 9.0 * (cs2 * cs2 * rho - cs2 * q2 / rho);
+    meq[7] = (qx * qx - qy * qy) / rho;
+    meq[8] = qx * qy / rho;
+  }
+}
+
+/* Collision in moment space (eq. CollisionOnFinest / AdaptiveCollision). */
+static void collide_with(const orc_params *P, const double *M, const double *Minv, double *f) {
+  const int q = P->q;
+  double m[MAXQ] = {0}, meq[MAXQ] = {0};
+  for (int i = 0; i < q; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < q; ++j) acc += M[i * q + j] * f[j];
+    m[i] = acc;
+  }
+  orc_equilibrium(P, m, meq);
+  for (int i = 0; i < q; ++i) m[i] = m[i] + P->s[i] * (meq[i] - m[i]);
+  for (int i = 0; i < q; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < q; ++j) acc += Minv[i * q + j] * m[j];
+    f[i] = acc;
+  }
+}
+
+void orc_collide_cell(const orc_params *P, double *f) {
+  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ];
+  orc_moment_matrix(P, M);
+  orc_moment_matrix_inverse(P, Minv);
+  collide_with(P, M, Minv, f);
+}
+
+/* ---- Multiresolution operators (section "Projection and prediction operators") ---- */
+
+/* Table 1, gamma = 1. */
+static const double C1 = -0.125;
+
+/* Prediction of child (cx, cy) at level l from the dense data Fp of level l-1:
+ * 1D:  f_parent + (-1)^dx * c1 * (f_{p+1} - f_{p-1});
+ * 2D:  tensor product, f + (-1)^dx Qx + (-1)^dy Qy + (-1)^(dx+dy) Qxy. */
+double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy) {
+  const int n = side(l - 1);
+  const int px = cx >> 1;
+  const double sx = (cx & 1) ? -1.0 : 1.0;
+  if (P->dim == 1) {
+    const double Q = C1 * (Fp[wrapi(px + 1, n)] - Fp[wrapi(px - 1, n)]);
+    return Fp[px] + sx * Q;
+  }
+  const int py = cy >> 1;
+  const double sy = (cy & 1) ? -1.0 : 1.0;
+#define AT(a, b) Fp[(int64_t)wrapi((a), n) + (int64_t)n * wrapi((b), n)]
+  const double Qx = C1 * (AT(px + 1, py) - AT(px - 1, py));
+  const double Qy = C1 * (AT(px, py + 1) - AT(px, py - 1));
+  const double Qxy =
+      (C1 * C1) * (((AT(px + 1, py + 1) - AT(px - 1, py + 1)) - AT(px + 1, py - 1)) + AT(px - 1, py - 1));
+  return ((AT(px, py) + sx * Qx) + sy * Qy) + (sx * sy) * Qxy;
+#undef AT
+}
+
+/* Projection: average of the 2^d children of (px, py), children read from the
+ * dense data Fc of level l+1. */
+static double project(const orc_params *P, const double *Fc, int l, int px, int py) {
+  if (P->dim == 1) return 0.5 * (Fc[2 * px] + Fc[2 * px + 1]);
+  const int64_t n = side(l + 1);
+  const double a00 = Fc[2 * px + n * (2 * py)];
+  const double a10 = Fc[2 * px + 1 + n * (2 * py)];
+  const double a01 = Fc[2 * px + n * (2 * py + 1)];
+  const double a11 = Fc[2 * px + 1 + n * (2 * py + 1)];
+  return 0.25 * (((a00 + a10) + a01) + a11);
+}
+
+int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values) {
+  /* Upward: internal tree cells hold the projection of their children. */
+  for (int l = P->jmax - 1; l >= P->jmin; --l) {
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_internal(P, tree, l, c)) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      for (int h = 0; h < P->q; ++h)
+        val_at(P, values, l, h)[c] = project(P, val_at(P, values, l + 1, h), l, x, y);
+    }
+  }
+  /* Downward: cells outside the tree receive the zero-detail prediction. */
+  for (int l = P->jmin + 1; l <= P->jmax; ++l) {
+    const uint8_t *t = tree_at(P, tree, l);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (t[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      for (int h = 0; h < P->q; ++h)
+        val_at(P, values, l, h)[c] = orc_predict(P, val_at(P, values, l - 1, h), l, x, y);
+    }
+  }
+  return 0;
+}
+
+/* ---- Details and the sibling l-infinity metric (sections "Details and local
+ *      regularity" and "Mesh coarsening") ---- */
+
+int orc_details(const orc_params *P, const uint8_t *tree, const double *values, double *D) {
+  const int64_t total = orc_total_cells(P);
+  for (int64_t i = 0; i < total; ++i) D[i] = -1.0;
+  for (int l = P->jmin + 1; l <= P->jmax; ++l) {
+    const uint8_t *tp = tree_at(P, tree, l - 1), *tc = tree_at(P, tree, l);
+    double *Dp = D + orc_level_offset(P, l - 1);
+    for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
+      int px, py;
+      cell_coords(P, l - 1, p, &px, &py);
+      if (!tp[p] || !tc[child_index(P, l - 1, px, py, 0)]) continue;
+      double dmax = 0.0;
+      for (int h = 0; h < P->q; ++h) {
+        const double *Fc = val_at(P, values, l, h), *Fp = val_at(P, values, l - 1, h);
+        for (int sigma = 0; sigma < nchildren(P); ++sigma) {
+          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
+          const double d = Fc[cell_index(P, l, cx, cy)] - orc_predict(P, Fp, l, cx, cy);
+          if (fabs(d) > dmax) dmax = fabs(d);
+        }
+      }
+      Dp[p] = dmax;
+    }
+  }
+  return 0;
+}
+
+/* ---- Time-adaptive mesh: G o H_eps o T_eps (section "Construction of the time
+ *      adaptive mesh", eq. Thresholding, eq. AdditionNeigh, refinement rule,
+ *      grading definition) ---- */
+
+static void mark_group(const orc_params *P, uint8_t *tl, int l, int gx, int gy) {
+  /* all children at level l of the cell (gx, gy) of level l-1 */
+  for (int sigma = 0; sigma < nchildren(P); ++sigma) tl[child_index(P, l - 1, gx, gy, sigma)] = 1;
+}
+
+int orc_adapt_tree(const orc_params *P, const uint8_t *told, const double *D, uint8_t *tnew) {
+  const int J = P->jmax, jmin = P->jmin, d = P->dim;
+  const int64_t total = orc_total_cells(P);
+  int eta[2 * MAXQ];
+  orc_velocities(P, eta);
+  uint8_t *keep = calloc((size_t)total, 1);
+  if (!keep) return -1;
+
+  /* T_eps: level jmin always; deeper cells of the old tree whose sibling-group
+   * metric reaches eps_l = 2^{d(l-J)} eps. */
+  memset(tree_at(P, keep, jmin), 1, (size_t)ncells(P, jmin));
+  for (int l = jmin + 1; l <= J; ++l) {
+    const double eps_l = ldexp(P->eps, d * (l - J));
+    const uint8_t *t = tree_at(P, told, l);
+    const double *Dp = D + orc_level_offset(P, l - 1);
+    uint8_t *k = tree_at(P, keep, l);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!t[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      if (Dp[cell_index(P, l - 1, x >> 1, y >> 1)] >= eps_l) k[c] = 1;
+    }
+  }
+  /* Ancestor closure: a kept group keeps the group of its parent. */
+  for (int l = J; l >= jmin + 2; --l) {
+    const uint8_t *k = tree_at(P, keep, l);
+    uint8_t *kp = tree_at(P, keep, l - 1);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!k[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      mark_group(P, kp, l - 1, x >> 2, y >> 2);
+    }
+  }
+  /* H_eps: neighbours along every velocity, and children of groups whose metric
+   * reaches 2^{mu_bar + d} eps_l. */
+  memset(tnew, 0, (size_t)total);
+  for (int l = jmin; l <= J; ++l) {
+    const uint8_t *k = tree_at(P, keep, l);
+    uint8_t *tn = tree_at(P, tnew, l);
+    const double eps_l = ldexp(P->eps, d * (l - J));
+    const double refine_thr = ldexp(eps_l, d) * exp2(P->mu_bar);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!k[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      tn[c] = 1;
+      for (int h = 0; h < P->q; ++h)
+        tn[cell_index_wrapped(P, l, x - eta[2 * h], y - eta[2 * h + 1])] = 1;
+      if (l > jmin && l < J) {
+        const double Dg = D[orc_level_offset(P, l - 1) + cell_index(P, l - 1, x >> 1, y >> 1)];
+        if (Dg >= refine_thr) mark_group(P, tree_at(P, tnew, l + 1), l + 1, x, y);
+      }
+    }
+  }
+  /* G: minimal graded complete tree, swept from the finest level down. */
+  for (int l = J; l >= jmin + 1; --l) {
+    uint8_t *tn = tree_at(P, tnew, l), *tp = tree_at(P, tnew, l - 1);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!tn[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      mark_group(P, tn, l, x >> 1, y >> 1);
+    }
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!tn[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      const int px = x >> 1, py = y >> 1;
+      for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
+        for (int ax = -1; ax <= 1; ++ax) tp[cell_index_wrapped(P, l - 1, px + ax, py + ay)] = 1;
+    }
+  }
+  memset(tree_at(P, tnew, jmin), 1, (size_t)ncells(P, jmin));
+  free(keep);
+  return 0;
+}
+
+/* ---- Data transfer to the new mesh ---- */
+
+int orc_transfer(const orc_params *P, const uint8_t *told, const double *vold, const uint8_t *tnew,
+                 double *vnew) {
+  (void)told; /* the dense reconstruction already holds copy, projection and prediction values */
+  for (int l = P->jmin; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tnew, l, c)) continue;
+      for (int h = 0; h < P->q; ++h) val_at(P, vnew, l, h)[c] = val_at(P, vold, l, h)[c];
+    }
+  return 0;
+}
+
+/* ---- MR transport (eq. AdaptiveAdvectionPhase with the sets E and A built
+ *      from the cell splitting B, eq. CellSplitting) ---- */
+
+int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, double *out,
+                  int definition_form) {
+  const int J = P->jmax, d = P->dim;
+  int eta[2 * MAXQ];
+  orc_velocities(P, eta);
+  for (int l = P->jmin; l <= J; ++l) {
+    const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tree, l, c)) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      const int bx0 = x * w, by0 = y * wy; /* B = [bx0, bx0+w) x [by0, by0+wy) */
+      for (int h = 0; h < P->q; ++h) {
+        const int ex = eta[2 * h], ey = eta[2 * h + 1];
+        const double *FJ = val_at(P, vs, J, h);
+        const double fl = val_at(P, vs, l, h)[c];
+        double res;
+        if (ex == 0 && ey == 0) {
+          res = fl;
+        } else if (n == 0) {
+          res = FJ[cell_index_wrapped(P, J, x - ex, y - ey)];
+        } else if (definition_form) {
+          double s = 0.0;
+          for (int ky = by0; ky < by0 + wy; ++ky)
+            for (int kx = bx0; kx < bx0 + w; ++kx) s += FJ[cell_index_wrapped(P, J, kx - ex, ky - ey)];
+          res = ldexp(s, -d * n);
+        } else {
+          double sE = 0.0, sA = 0.0;
+          for (int ky = by0; ky < by0 + wy; ++ky)
+            for (int kx = bx0; kx < bx0 + w; ++kx) {
+              /* E = (B - eta) \ B: the cell k - eta, if it left B */
+              const int jx = kx - ex, jy = ky - ey;
+              if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy))
+                sE += FJ[cell_index_wrapped(P, J, jx, jy)];
+            }
+          for (int ky = by0; ky < by0 + wy; ++ky)
+            for (int kx = bx0; kx < bx0 + w; ++kx) {
+              /* A = B \ (B - eta): the cell k whose image k + eta left B */
+              const int ix = kx + ex, iy = ky + ey;
+              if (!(ix >= bx0 && ix < bx0 + w && iy >= by0 && iy < by0 + wy))
+                sA += FJ[cell_index(P, J, kx, ky)];
+            }
+          res = fl + ldexp(sE - sA, -d * n);
+        }
+        val_at(P, out, l, h)[c] = res;
+      }
+    }
+  }
+  return 0;
+}
+
+int orc_collide(const orc_params *P, const uint8_t *tree, double *values) {
+  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ], f[MAXQ];
+  orc_moment_matrix(P, M);
+  if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  for (int l = P->jmin; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tree, l, c)) continue;
+      for (int h = 0; h < P->q; ++h) f[h] = val_at(P, values, l, h)[c];
+      collide_with(P, M, Minv, f);
+      for (int h = 0; h < P->q; ++h) val_at(P, values, l, h)[c] = f[h];
+    }
+  return 0;
+}
+
+/* ---- Algorithm 1 (Overall solver) ---- */
+
+int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *values) {
+  const int J = P->jmax, q = P->q;
+  const int nc = P->scheme == 3 ? 3 : 1;
+  const int64_t NJ = ncells(P, J);
+  double Minv[MAXQ * MAXQ], m[MAXQ], meq[MAXQ];
+  if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  memset(tree, 1, (size_t)orc_total_cells(P));
+  memset(values, 0, sizeof(double) * (size_t)(q * orc_total_cells(P)));
+  for (int64_t c = 0; c < NJ; ++c) {
+    for (int i = 0; i < q; ++i) m[i] = i < nc ? m0[(int64_t)i * NJ + c] : 0.0;
+    orc_equilibrium(P, m, meq);
+    for (int i = 0; i < q; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < q; ++j) acc += Minv[i * q + j] * meq[j];
+      val_at(P, values, J, i)[c] = acc;
+    }
+  }
+  return 0;
+}
+
+int orc_step(const orc_params *P, uint8_t *tree, double *values) {
+  const int64_t total = orc_total_cells(P);
+  double *D = malloc(sizeof(double) * (size_t)total);
+  double *vnew = calloc((size_t)(P->q * total), sizeof(double));
+  uint8_t *tnew = malloc((size_t)total);
+  int rc = -1;
+  if (!D || !vnew || !tnew) goto done;
+  /* mesh adaptation with details of the old solution */
+  orc_reconstruct(P, tree, values);
+  orc_details(P, tree, values, D);
+  orc_adapt_tree(P, tree, D, tnew);
+  /* data transfer to the new leaves */
+  orc_transfer(P, tree, values, tnew, vnew);
+  /* transport on the new leaves from the reconstruction of the transferred data */
+  orc_reconstruct(P, tnew, vnew);
+  orc_transport(P, tnew, vnew, values, 0);
+  /* collision on the new leaves */
+  orc_collide(P, tnew, values);
+  memcpy(tree, tnew, (size_t)total);
+  rc = 0;
+done:
+  free(D);
+  free(vnew);
+  free(tnew);
+  return rc;
+}
+
+int orc_uniform_step(const orc_params *P, double *fJ) {
+  const int J = P->jmax, q = P->q;
+  const int64_t NJ = ncells(P, J);
+  int eta[2 * MAXQ];
+  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ], f[MAXQ];
+  orc_velocities(P, eta);
+  orc_moment_matrix(P, M);
+  if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  double *g = malloc(sizeof(double) * (size_t)(q * NJ));
+  if (!g) return -1;
+  for (int h = 0; h < q; ++h)
+    for (int64_t c = 0; c < NJ; ++c) {
+      int x, y;
+      cell_coords(P, J, c, &x, &y);
+      g[h * NJ + c] = fJ[h * NJ + cell_index_wrapped(P, J, x - eta[2 * h], y - eta[2 * h + 1])];
+    }
+  for (int64_t c = 0; c < NJ; ++c) {
+    for (int h = 0; h < q; ++h) f[h] = g[h * NJ + c];
+    collide_with(P, M, Minv, f);
+    for (int h = 0; h < q; ++h) fJ[h * NJ + c] = f[h];
+  }
+  free(g);
+  return 0;
+}
+
+/* ---- Diagnostics ---- */
+
+int orc_leaf_counts(const orc_params *P, const uint8_t *tree, int64_t *counts) {
+  for (int l = 0; l <= P->jmax; ++l) counts[l] = 0;
+  for (int l = P->jmin; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) counts[l] += is_leaf(P, tree, l, c);
+  return 0;
+}
+
+double orc_mass(const orc_params *P, const uint8_t *tree, const double *values) {
+  double mass = 0.0;
+  for (int l = P->jmin; l <= P->jmax; ++l) {
+    const double vol = ldexp(1.0, P->dim * (P->jmax - l)); /* in finest-cell volumes */
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tree, l, c)) continue;
+      for (int h = 0; h < P->q; ++h) mass += vol * val_at(P, values, l, h)[c];
+    }
+  }
+  return mass;
+}
+
+/* Bit 1: level jmin incomplete; bit 2: a sibling group incomplete; bit 4: a
+ * cell without its parent; bit 8: a prediction stencil outside the tree. */
+int orc_check_tree(const orc_params *P, const uint8_t *tree) {
+  int bad = 0;
+  const int d = P->dim;
+  const uint8_t *t0 = tree_at(P, tree, P->jmin);
+  for (int64_t c = 0; c < ncells(P, P->jmin); ++c)
+    if (!t0[c]) bad |= 1;
+  for (int l = P->jmin + 1; l <= P->jmax; ++l) {
+    const uint8_t *t = tree_at(P, tree, l), *tp = tree_at(P, tree, l - 1);
+    for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
+      int px, py, cnt = 0;
+      cell_coords(P, l - 1, p, &px, &py);
+      for (int sigma = 0; sigma < nchildren(P); ++sigma) cnt += t[child_index(P, l - 1, px, py, sigma)];
+      if (cnt != 0 && cnt != nchildren(P)) bad |= 2;
+      if (cnt && !tp[p]) bad |= 4;
+      if (cnt)
+        for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
+          for (int ax = -1; ax <= 1; ++ax)
+            if (!tp[cell_index_wrapped(P, l - 1, px + ax, py + ay)]) bad |= 8;
+    }
+  }
+  return bad;
+}

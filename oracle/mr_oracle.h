@@ -1,0 +1,99 @@
+/*
+ * Plain FP64 CPU oracle of the multiresolution-adapted lattice Boltzmann step
+ * (Bellotti, Gouarin, Graille, Massot, arXiv 2103.02903).
+ *
+ * TEST INFRASTRUCTURE ONLY. This code is the slow, obviously correct reference
+ * that the GPU library is checked against. Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it. It shares no code,
+ * header, table or helper with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * Storage is dense per level: every level l = jmin..J keeps a value for every
+ * one of its N_l^d cells (N_l = 2^l), so every reconstruction is a plain array
+ * lookup. This costs O(q * sum_l 2^{dl}) per step, which is the point: nothing
+ * is blocked, fused or reordered beyond what the paper states.
+ *
+ * Flat array layouts shared with the Python wrapper:
+ *   tree   uint8  [level jmin..J][cell]        1 = cell is in the complete tree
+ *   values double [level jmin..J][h][cell]     cell index = x (1D), x + N_l*y (2D)
+ *   detail double [level jmin..J][cell]        D(parent) stored at the parent's slot
+ */
+#ifndef MR_ORACLE_H
+#define MR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int dim;        /* 1 or 2 */
+  int q;          /* 2 (D1Q2), 3 (D1Q3), 9 (D2Q9) */
+  int scheme;     /* 1 = D1Q2 advection, 2 = D1Q3 Burgers, 3 = D2Q9 Lallemand-Luo MRT */
+  int jmin, jmax; /* coarsest and finest level */
+  int pad_;
+  double lambda;   /* lattice velocity, Delta x / Delta t */
+  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: unused */
+  double eps;      /* threshold epsilon >= 0 */
+  double mu_bar;   /* regularity guess in [0, 2*gamma+1] */
+  double s[9];     /* relaxation rate of each moment (0 for conserved moments) */
+} orc_params;
+
+/* Number of cells summed over levels jmin..J, and the offset of level l. */
+int64_t orc_total_cells(const orc_params *P);
+int64_t orc_level_offset(const orc_params *P, int l);
+
+/* Initial datum at equilibrium on the full finest mesh (Algorithm 1):
+ * m0 holds the conserved moments at the finest cells, layout [nc][N_J^d]
+ * (nc = 1 for D1Q2/D1Q3, 3 for D2Q9: rho, q_x, q_y). */
+int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *values);
+
+/* Reconstruction on every cell of every level: projection upward on internal
+ * tree cells, then zero-detail prediction downward on cells outside the tree.
+ * `values` must hold the leaf values; on return it is dense on every level. */
+int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values);
+
+/* Prediction of one child cell (level l, index cx[,cy]) from the dense data of
+ * level l-1 of one population. */
+double orc_predict(const orc_params *P, const double *parent_level, int l, int cx, int cy);
+
+/* Details: for every parent p at level l-1 whose children are in the tree,
+ * D[l-1][p] = max_h max_children |f - prediction|. Other slots are set to -1.
+ * `values` must be dense (output of orc_reconstruct). */
+int orc_details(const orc_params *P, const uint8_t *tree, const double *values, double *D);
+
+/* New tree G(H_eps(T_eps(tree))) from the old tree and its details. */
+int orc_adapt_tree(const orc_params *P, const uint8_t *told, const double *D, uint8_t *tnew);
+
+/* One full time step of Algorithm 1, in place: adapt, transfer, transport,
+ * collide. `values` holds leaf values (post-collision) before and after. */
+int orc_step(const orc_params *P, uint8_t *tree, double *values);
+
+/* Pieces of the step, exposed for the tests. */
+int orc_transfer(const orc_params *P, const uint8_t *told, const double *values_old_dense,
+                 const uint8_t *tnew, double *values_new);
+int orc_transport(const orc_params *P, const uint8_t *tree, const double *values_dense,
+                  double *values_out, int definition_form);
+int orc_collide(const orc_params *P, const uint8_t *tree, double *values);
+void orc_collide_cell(const orc_params *P, double *f);
+
+/* Uniform reference scheme on level J only: values layout [h][N_J^d]. */
+int orc_uniform_step(const orc_params *P, double *fJ);
+
+/* Moment matrix M and its inverse (q*q, row-major), and equilibrium moments. */
+void orc_moment_matrix(const orc_params *P, double *M);
+int orc_moment_matrix_inverse(const orc_params *P, double *Minv);
+void orc_equilibrium(const orc_params *P, const double *m, double *meq);
+/* Logical velocities eta^h, layout [q][2] (y component 0 in 1D). */
+void orc_velocities(const orc_params *P, int *eta);
+
+/* Diagnostics. */
+int orc_leaf_counts(const orc_params *P, const uint8_t *tree, int64_t *counts /* [J+1] */);
+double orc_mass(const orc_params *P, const uint8_t *tree, const double *values);
+int orc_check_tree(const orc_params *P, const uint8_t *tree); /* 0 = graded complete tree */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

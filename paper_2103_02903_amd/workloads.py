@@ -1,0 +1,169 @@
+"""Seeded synthetic workloads: scheme parameters and initial conserved moments.
+
+This module is shared by the GPU path and by the FP64 oracle. It holds none of
+the method's arithmetic: it only builds parameter dictionaries and initial
+fields (point values at finest-cell centres, generated once on the host with
+numpy so that both sides receive identical bits).
+
+Parameter dictionary keys:
+  scheme   "D1Q2" | "D1Q3" | "D2Q9"
+  jmin, jmax, eps, mu_bar, lam (lattice velocity), eq_param (V or alpha),
+  s        relaxation rate of every moment (0 for conserved moments)
+  domain   (lo, hi) of the periodic box along each axis
+Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D) or 3 (rho, q_x, q_y),
+cell index x + N_J * y.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3)}  # dim, q, conserved
+
+
+def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0, lam: float = 1.0,
+           eq_param: float = 0.0, domain=(0.0, 1.0)) -> dict:
+    dim, q, _ = SCHEME_DIMS[scheme]
+    s = [float(v) for v in s]
+    assert len(s) == q
+    return dict(scheme=scheme, dim=dim, q=q, jmin=int(jmin), jmax=int(jmax), eps=float(eps),
+                mu_bar=float(mu_bar), lam=float(lam), eq_param=float(eq_param), s=s,
+                domain=tuple(domain))
+
+
+def cell_centres(jmax: int, domain=(0.0, 1.0)) -> np.ndarray:
+    lo, hi = domain
+    n = 1 << jmax
+    return lo + (np.arange(n) + 0.5) * (hi - lo) / n
+
+
+def d2q9_s(s1: float, s2: float) -> list:
+    """Relaxation vector diag(0, 0, 0, s1, s1, s1, s1, s2, s2) of the D2Q9 scheme."""
+    return [0.0, 0.0, 0.0, s1, s1, s1, s1, s2, s2]
+
+
+def s2_from_reynolds(re: float, u0: float, length: float, jmax: int, lam: float = 1.0) -> float:
+    """Shear relaxation rate giving kinematic viscosity u0*length/re on level jmax
+    (acoustic scaling, dt = dx/lam, c_s^2 = lam^2/3)."""
+    nu = u0 * length / re
+    dt = (length / (1 << jmax)) / lam
+    cs2 = lam * lam / 3.0
+    return 1.0 / (0.5 + nu / (cs2 * dt))
+
+
+# ---------------------------------------------------------------- 1D workloads
+
+def advection_d1q2(jmin=2, jmax=10, eps=1e-4, s=1.9, mu_bar=0.0, velocity=1.0):
+    """D1Q2 linear advection on the periodic box [-1, 1]: indicator of [-0.3, 0.3]
+    plus the bump exp(-50 x^2)."""
+    cfg = params("D1Q2", jmin, jmax, eps, [0.0, s], mu_bar=mu_bar, lam=1.0, eq_param=velocity,
+                 domain=(-1.0, 1.0))
+    x = cell_centres(jmax, cfg["domain"])
+    u0 = (np.abs(x) <= 0.3).astype(np.float64) + np.exp(-50.0 * x * x)
+    return cfg, u0[None, :].copy()
+
+
+def burgers_d1q3(jmin=2, jmax=14, eps=1e-4, s=1.5, mu_bar=0.0, alpha=0.5, seed=0, nmodes=8):
+    """D1Q3 inviscid Burgers on the periodic box [-1, 1]: 0.5 * a normalised sum of
+    `nmodes` sines with seeded U(-1, 1) amplitudes."""
+    cfg = params("D1Q3", jmin, jmax, eps, [0.0, s, s], mu_bar=mu_bar, lam=1.0, eq_param=alpha,
+                 domain=(-1.0, 1.0))
+    x = cell_centres(jmax, cfg["domain"])
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, nmodes)
+    u = sum(a[n - 1] * np.sin(np.pi * n * x) for n in range(1, nmodes + 1))
+    u0 = 0.5 * u / np.max(np.abs(u))
+    return cfg, u0[None, :].copy()
+
+
+# ---------------------------------------------------------------- 2D workloads
+
+def shear_layer_d2q9(jmin=3, jmax=10, eps=1e-3, mu_bar=1.0, re=1e4, u0=0.1, s1=1.5, width=1.0 / 80,
+                     pert=0.05, seed=0):
+    """D2Q9 double shear layer on the periodic unit square: u_x = u0 tanh((y-1/4)/w) for
+    y <= 1/2 and u0 tanh((3/4-y)/w) above; u_y = pert*u0*sin(2 pi (x + phi)), phi seeded."""
+    s2 = s2_from_reynolds(re, u0, 1.0, jmax)
+    cfg = params("D2Q9", jmin, jmax, eps, d2q9_s(s1, s2), mu_bar=mu_bar, lam=1.0, domain=(0.0, 1.0))
+    cfg.update(re=float(re), u0=float(u0))
+    xc = cell_centres(jmax)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")  # [y][x]
+    phi = np.random.default_rng(seed).uniform(0.0, 1.0)
+    ux = np.where(Y <= 0.5, u0 * np.tanh((Y - 0.25) / width), u0 * np.tanh((0.75 - Y) / width))
+    uy = pert * u0 * np.sin(2.0 * np.pi * (X + phi))
+    rho = np.ones_like(ux)
+    m0 = np.stack([rho.ravel(), (rho * ux).ravel(), (rho * uy).ravel()])
+    return cfg, np.ascontiguousarray(m0)
+
+
+def shear_layer_batch(n=96, jmin=3, seed=0, jmax_choices=(7, 8, 9, 10), eps_choices=(1e-2, 1e-3, 1e-4),
+                      re_range=(1e3, 3e4)):
+    """Independent D2Q9 shear layers with per-instance Re ~ U[1e3, 3e4], J in {7..10},
+    eps in {1e-2, 1e-3, 1e-4}; instance i uses seed `seed + i` for its draws."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed + i)
+        re = float(rng.uniform(*re_range))
+        jmax = int(rng.choice(jmax_choices))
+        eps = float(rng.choice(eps_choices))
+        out.append(shear_layer_d2q9(jmin=jmin, jmax=jmax, eps=eps, re=re, seed=seed + 1000 + i))
+    return out
+
+
+def random_vortex_d2q9(jmin=3, jmax=8, eps=1e-3, mu_bar=1.0, u0=0.05, s1=1.5, s2=1.8, seed=0, kmax=4):
+    """D2Q9 on the periodic unit square with a smooth solenoidal velocity u0 * curl(psi)/|.|_inf,
+    psi = sum over kx, ky in 1..kmax of a_k sin(2 pi (kx x + ky y) + phi_k), a_k ~ N(0,1)/|k|^2."""
+    cfg = params("D2Q9", jmin, jmax, eps, d2q9_s(s1, s2), mu_bar=mu_bar, lam=1.0, domain=(0.0, 1.0))
+    rng = np.random.default_rng(seed)
+    ks = [(kx, ky) for ky in range(1, kmax + 1) for kx in range(1, kmax + 1)]
+    amp = np.array([rng.normal() / (kx * kx + ky * ky) for kx, ky in ks])
+    phs = rng.uniform(0.0, 2.0 * np.pi, len(ks))
+    xc = cell_centres(jmax)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    ux = np.zeros_like(X)
+    uy = np.zeros_like(X)
+    for (kx, ky), a, p in zip(ks, amp, phs):
+        c = np.cos(2.0 * np.pi * (kx * X + ky * Y) + p) * 2.0 * np.pi * a
+        ux += c * ky      # d psi / dy
+        uy -= c * kx      # -d psi / dx
+    scale = u0 / max(np.max(np.abs(ux)), np.max(np.abs(uy)))
+    ux *= scale
+    uy *= scale
+    rho = np.ones_like(ux)
+    m0 = np.stack([rho.ravel(), ux.ravel(), uy.ravel()])
+    cfg.update(modes=ks, amplitudes=amp.tolist(), phases=phs.tolist(), u0=float(u0))
+    return cfg, np.ascontiguousarray(m0)
+
+
+def random_field(cfg: dict, seed: int, kind: str = "smooth") -> np.ndarray:
+    """Generic seeded initial conserved moments for tests: smooth random modes plus,
+    for kind="jump", a step, so that meshes get several levels."""
+    dim, q, nc = SCHEME_DIMS[cfg["scheme"]]
+    n = 1 << cfg["jmax"]
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(n) + 0.5) / n
+    if dim == 1:
+        grids = (xc,)
+    else:
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        grids = (X, Y)
+    fields = []
+    for c in range(nc):
+        f = np.zeros_like(grids[0])
+        for _ in range(3):
+            k = rng.integers(1, 4, size=dim)
+            ph = rng.uniform(0, 2 * np.pi)
+            arg = sum(int(k[i]) * grids[i] for i in range(dim)) * 2 * np.pi + ph
+            f = f + rng.uniform(-1, 1) * np.sin(arg)
+        if kind == "jump":
+            f = f + (grids[0] > 0.5 + 0.1 * rng.uniform(-1, 1)) * rng.uniform(0.5, 1.0)
+        fields.append(f)
+    if cfg["scheme"] == "D2Q9":
+        rho = 1.0 + 0.05 * fields[0]
+        ux = 0.05 * fields[1]
+        uy = 0.05 * fields[2]
+        m0 = np.stack([rho.ravel(), (rho * ux).ravel(), (rho * uy).ravel()])
+    elif cfg["scheme"] == "D1Q3":
+        u = fields[0]
+        m0 = (0.4 * u / np.max(np.abs(u)))[None, :]
+    else:
+        m0 = fields[0][None, :]
+    return np.ascontiguousarray(m0, dtype=np.float64)

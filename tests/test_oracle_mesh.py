@@ -1,0 +1,169 @@
+"""Pins of the oracle's mesh adaptation G o H_eps o T_eps (no GPU): special
+cases, invariants, and a brute-force fixed-point construction on tiny meshes."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02903_amd import workloads as W
+
+
+def _cfg(scheme, jmin, jmax, eps, mu_bar=1.0):
+    s = {"D1Q2": [0, 1.9], "D1Q3": [0, 1.5, 1.5], "D2Q9": W.d2q9_s(1.5, 1.8)}[scheme]
+    return W.params(scheme, jmin, jmax, eps, s, mu_bar=mu_bar, eq_param=0.5 if scheme == "D1Q3" else 1.0)
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax", [("D1Q2", 2, 8), ("D1Q3", 2, 8), ("D2Q9", 2, 5)])
+def test_eps_zero_keeps_full_finest_mesh(scheme, jmin, jmax):
+    cfg = _cfg(scheme, jmin, jmax, 0.0)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 0, "jump"))
+    o.step(tree, v, 3)
+    assert tree.all()
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax", [("D1Q3", 2, 8), ("D2Q9", 2, 5)])
+def test_huge_eps_gives_uniform_coarsest_mesh(scheme, jmin, jmax):
+    cfg = _cfg(scheme, jmin, jmax, 1e300)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 0, "jump"))
+    o.step(tree, v, 1)
+    counts = o.leaf_counts(tree)
+    assert counts[jmin] == o.ncells(jmin) and counts.sum() == o.ncells(jmin)
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,eps", [("D1Q2", 2, 10, 1e-4), ("D1Q3", 2, 10, 1e-4),
+                                                  ("D2Q9", 3, 6, 1e-3), ("D2Q9", 2, 6, 1e-4)])
+def test_adapted_tree_invariants(scheme, jmin, jmax, eps):
+    """Graded complete tree whose complete leaves partition the domain."""
+    cfg = _cfg(scheme, jmin, jmax, eps)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 7, "jump"))
+    for _ in range(6):
+        o.step(tree, v)
+        assert o.check_tree(tree) == 0
+        counts = o.leaf_counts(tree)
+        vol = sum(int(counts[l]) << (o.dim * (jmax - l)) for l in range(jmin, jmax + 1))
+        assert vol == o.ncells(jmax)
+
+
+def _random_graded_tree(o, rng, steps=2):
+    tree = np.ones(o.total, np.uint8)
+    for _ in range(steps):
+        D = 10.0 ** rng.uniform(-4, 0, o.total)
+        tree = o.adapt_tree(tree, D)
+    return tree
+
+
+def _brute_adapt(o, cfg, told, D):
+    """The mesh G(H_eps(T_eps(told))) built from the definitions with naive
+    fixed-point closures on sets of (level, coords)."""
+    jmin, J, d = o.jmin, o.jmax, o.dim
+    eta = [tuple(e[:d]) for e in o.velocities()]
+
+    def N(l):
+        return 1 << l
+
+    def cells(l):
+        if d == 1:
+            return [(x,) for x in range(N(l))]
+        return [(x, y) for y in range(N(l)) for x in range(N(l))]
+
+    def idx(l, c):
+        return o.level_offset(l) + (c[0] if d == 1 else c[0] + N(l) * c[1])
+
+    def parent(c):
+        return tuple(v >> 1 for v in c)
+
+    def children(c):
+        if d == 1:
+            return [(2 * c[0] + s,) for s in (0, 1)]
+        return [(2 * c[0] + sx, 2 * c[1] + sy) for sy in (0, 1) for sx in (0, 1)]
+
+    def wrap(l, c):
+        return tuple(v % N(l) for v in c)
+
+    def D_of(l, c):  # metric of the group of (l, c), stored at the parent's slot
+        return D[idx(l - 1, parent(c))]
+
+    def eps_l(l):
+        return np.ldexp(cfg["eps"], d * (l - J))
+
+    old = {(l, c) for l in range(jmin, J + 1) for c in cells(l) if told[idx(l, c)]}
+    K = {(jmin, c) for c in cells(jmin)}
+    K |= {(l, c) for (l, c) in old if l > jmin and D_of(l, c) >= eps_l(l)}
+    changed = True
+    while changed:  # smallest tree (parents and siblings) containing K
+        changed = False
+        for (l, c) in list(K):
+            if l > jmin:
+                for s in children(parent(c)) + [None]:
+                    item = (l - 1, parent(c)) if s is None else (l, s)
+                    if item not in K:
+                        K.add(item)
+                        changed = True
+    H = set(K)
+    for (l, c) in K:
+        for e in eta:
+            H.add((l, wrap(l, tuple(ci - ei for ci, ei in zip(c, e)))))
+        if jmin < l < J and D_of(l, c) >= np.ldexp(eps_l(l), d) * 2.0 ** cfg["mu_bar"]:
+            for ch in children(c):
+                H.add((l + 1, ch))
+    changed = True
+    while changed:  # smallest graded complete tree containing H
+        changed = False
+        for (l, c) in list(H):
+            if l == jmin:
+                continue
+            p = parent(c)
+            need = [(l, s) for s in children(p)]
+            rng_ = range(-1, 2)
+            if d == 1:
+                need += [(l - 1, wrap(l - 1, (p[0] + a,))) for a in rng_]
+            else:
+                need += [(l - 1, wrap(l - 1, (p[0] + a, p[1] + b))) for b in rng_ for a in rng_]
+            for item in need:
+                if item not in H:
+                    H.add(item)
+                    changed = True
+    H |= {(jmin, c) for c in cells(jmin)}
+    out = np.zeros(o.total, np.uint8)
+    for (l, c) in H:
+        out[idx(l, c)] = 1
+    return out
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,mu_bar,seed", [("D1Q2", 2, 6, 0.0, 0), ("D1Q3", 1, 6, 1.0, 1),
+                                                          ("D1Q3", 2, 6, 2.0, 2), ("D2Q9", 1, 4, 1.0, 3),
+                                                          ("D2Q9", 2, 4, 0.0, 4)])
+def test_adapt_equals_brute_force_fixed_point(scheme, jmin, jmax, mu_bar, seed):
+    cfg = _cfg(scheme, jmin, jmax, 1e-2, mu_bar)
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(seed)
+    for trial in range(4):
+        told = _random_graded_tree(o, rng, steps=trial % 3 + 1)
+        assert o.check_tree(told) == 0
+        D = 10.0 ** rng.uniform(-5, 0, o.total)
+        assert np.array_equal(o.adapt_tree(told, D), _brute_adapt(o, cfg, told, D))
+
+
+def test_enlargement_keeps_upwind_neighbours_and_refines():
+    """eq. AdditionNeigh and the refinement rule, checked on the result."""
+    cfg = _cfg("D2Q9", 2, 5, 1e-2, 1.0)
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(11)
+    told = _random_graded_tree(o, rng, 2)
+    D = 10.0 ** rng.uniform(-5, 0, o.total)
+    tnew = o.adapt_tree(told, D)
+    eta = o.velocities()
+    for l in range(o.jmin + 1, o.jmax + 1):
+        t_old, t_new = o.tree_level(told, l), o.tree_level(tnew, l)
+        Dp = D[o.level_offset(l - 1):o.level_offset(l - 1) + o.ncells(l - 1)].reshape(1 << (l - 1), -1)
+        epsl = np.ldexp(1e-2, 2 * (l - o.jmax))
+        n = 1 << l
+        for y in range(n):
+            for x in range(n):
+                if t_old[y, x] and Dp[y >> 1, x >> 1] >= epsl:
+                    for ex, ey in eta:
+                        assert t_new[(y - ey) % n, (x - ex) % n]
+                    if l < o.jmax and Dp[y >> 1, x >> 1] >= np.ldexp(epsl, 2) * 2.0:
+                        assert o.tree_level(tnew, l + 1)[2 * y, 2 * x]
