@@ -1,0 +1,149 @@
+/*
+ * mrlbm: multiresolution-adapted lattice Boltzmann hot path for MI355X (gfx950).
+ *
+ * The method is the adaptive lattice Boltzmann scheme of Bellotti, Gouarin,
+ * Graille and Massot (arXiv 2103.02903). One time step follows Algorithm 1
+ * ("Overall solver") of the paper:
+ *   1. mesh adaptation Lambda(t+dt) = G(H_eps(T_eps(Lambda(t)))) with details of
+ *      the current solution (sections "Details and local regularity", "Mesh
+ *      coarsening", "Construction of the time adaptive mesh"), followed by the
+ *      transfer of the leaf data to the new complete leaves;
+ *   2. on every complete leaf, the MR transport of eq. (AdaptiveAdvectionPhase),
+ *      evaluated with the flattened weights of eq. (PredictionWithMatrixNew) and
+ *      the detail correction next to finer neighbours (section "A non-recursive
+ *      implementation of the reconstruction operator");
+ *   3. the collision of eq. (AdaptiveCollision) on the same leaf.
+ * Boundary conditions are periodic; the prediction stencil half-width is gamma = 1.
+ *
+ * Data layout (shared by every host<->device exchange below):
+ *   levels l = jmin..jmax are concatenated; level l holds N_l^d cells, N_l = 2^l,
+ *   cell index c = x (1D) or x + N_l * y (2D), periodic in every axis;
+ *   tree    uint8  [level][cell]      1 = the cell belongs to the complete tree;
+ *   values  real   [level][h][cell]   real = double (precision 8) or float (4);
+ *                                     only complete leaves carry meaningful data.
+ *   moments real   [nc][N_J^d]        conserved moments on the finest level:
+ *                                     nc = 1 (u) for D1Q2 / D1Q3,
+ *                                     nc = 3 (rho, q_x, q_y) for D2Q9.
+ *
+ * Ownership: the caller allocates the workspace (size from
+ * mrlbm_workspace_size) on the device, and owns every input and output buffer.
+ * The library never allocates or frees device memory; the context points into
+ * the workspace, which must outlive it. All device work is enqueued on the
+ * stream given at creation (a hipStream_t); calls that return results to host
+ * memory synchronise that stream. A context is not thread-safe.
+ *
+ * Errors: every function returns a status (0 = OK, < 0 = error, see below);
+ * no exception or abort crosses the boundary. After an error the context stays
+ * valid for mrlbm_destroy.
+ */
+#ifndef MRLBM_H
+#define MRLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRLBM_OK 0
+#define MRLBM_ERR_INVALID (-1)   /* bad argument or parameter */
+#define MRLBM_ERR_CAPACITY (-2)  /* workspace or output buffer too small */
+#define MRLBM_ERR_NONFINITE (-3) /* a leaf value is NaN or infinite */
+#define MRLBM_ERR_HIP (-4)       /* a HIP runtime call failed */
+#define MRLBM_ERR_STATE (-5)     /* call out of order (e.g. step before init) */
+
+#define MRLBM_D1Q2 1 /* linear advection, eta = (+1, -1), m_eq = (u, V u) */
+#define MRLBM_D1Q3 2 /* Burgers, eta = (0, +1, -1), m_eq = (u, u^2/2, alpha lambda^2 u) */
+#define MRLBM_D2Q9 3 /* Lallemand-Luo MRT of the von Karman section of the paper */
+
+typedef struct mrlbm_ctx mrlbm_ctx;
+
+typedef struct {
+  int scheme;      /* MRLBM_D1Q2, MRLBM_D1Q3 or MRLBM_D2Q9 */
+  int jmin, jmax;  /* coarsest and finest level: 1 <= jmin <= jmax, jmax <= 13 (2D) / 25 (1D) */
+  int precision;   /* 8: populations, details and weights in double; 4: in float */
+  double lambda;   /* lattice velocity dx/dt (> 0) */
+  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: ignored */
+  double eps;      /* threshold epsilon >= 0 of eq. (Thresholding) */
+  double mu_bar;   /* regularity guess in [0, 3] of the refinement rule */
+  double s[9];     /* relaxation rate of each moment; conserved moments must be 0 */
+} mrlbm_params;
+
+/* Bytes of device workspace a context with these parameters needs.
+ * Errors: MRLBM_ERR_INVALID for invalid parameters or a null pointer. */
+int mrlbm_workspace_size(const mrlbm_params *p, size_t *bytes);
+
+/* Create a context inside `workspace` (device memory, >= mrlbm_workspace_size
+ * bytes, 256-byte aligned) that enqueues its work on `stream` (a hipStream_t,
+ * NULL = the default stream). Uploads the parameter-dependent tables; does not
+ * set an initial state. Errors: MRLBM_ERR_INVALID, MRLBM_ERR_CAPACITY,
+ * MRLBM_ERR_HIP. */
+int mrlbm_create(const mrlbm_params *p, void *workspace, size_t ws_bytes, void *stream,
+                 mrlbm_ctx **out);
+
+/* Initial state of Algorithm 1: the full finest mesh with f = M^{-1} m_eq(m0)
+ * on every finest cell. `moments` is a device buffer in the context precision,
+ * layout [nc][N_J^d] (see above). Asynchronous. */
+int mrlbm_init_equilibrium(mrlbm_ctx *ctx, const void *moments);
+
+/* Mesh adaptation only: new tree G(H_eps(T_eps(tree))) with details of the
+ * current leaf values, then the transfer of the data to the new complete leaves
+ * (projection on merged cells, prediction on created ones). Asynchronous. */
+int mrlbm_adapt(mrlbm_ctx *ctx);
+
+/* Transport and collision on the current complete leaves, without adaptation
+ * (the mesh is frozen for this call). Asynchronous. */
+int mrlbm_transport_collide(mrlbm_ctx *ctx);
+
+/* `nsteps` full time steps of Algorithm 1 (adapt, transport, collide).
+ * Asynchronous; nsteps >= 0. */
+int mrlbm_step(mrlbm_ctx *ctx, int nsteps);
+
+/* Copy the current tree and values to host buffers (layouts above; `values`
+ * holds q * total_cells reals of the context precision). Synchronous. */
+int mrlbm_get_state(mrlbm_ctx *ctx, uint8_t *tree, void *values);
+
+/* Replace the current state by a host-side tree (must be a graded complete
+ * tree: level jmin full, sibling groups complete, every tree cell's prediction
+ * stencil in the tree) and leaf values. Synchronous.
+ * Errors: MRLBM_ERR_INVALID if the tree is not graded and complete. */
+int mrlbm_set_state(mrlbm_ctx *ctx, const uint8_t *tree, const void *values);
+
+/* Total number of cells over levels jmin..jmax and number of populations. */
+int mrlbm_sizes(const mrlbm_ctx *ctx, int64_t *total_cells, int *q);
+
+/* Diagnostics of the current state (synchronous): mass = sum over complete
+ * leaves of |C_l| / |C_J| * sum_h f^h, accumulated in double with a fixed
+ * order; per-level counts of complete leaves, internal tree cells and ghost
+ * cells ([jmax + 1] each, any of them may be NULL).
+ * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite. */
+int mrlbm_stats(mrlbm_ctx *ctx, double *mass, int64_t *leaves, int64_t *internal, int64_t *ghosts);
+
+/* Export of the complete leaves to device buffers, in the order (level, cell):
+ * `cells` receives (level << 26) | cell as uint32 and `values` receives q reals
+ * per leaf ([leaf][h], context precision). `capacity` is the number of leaves
+ * the buffers hold; *count receives the number of leaves. Synchronous.
+ * Errors: MRLBM_ERR_CAPACITY if capacity < count (nothing is written). */
+int mrlbm_leaves(mrlbm_ctx *ctx, uint32_t *cells, void *values, int64_t capacity, int64_t *count);
+
+/* Destroy the context (the workspace is the caller's to free). */
+int mrlbm_destroy(mrlbm_ctx *ctx);
+
+/* Human-readable text of a status code (static storage). */
+const char *mrlbm_status_string(int status);
+
+/* Host-side flattened transport weights of eq. (PredictionWithMatrixNew) for a
+ * leaf n = jmax - l >= 1 levels above the finest, velocity h of `scheme`:
+ *   W[h][25]: weight of the leaf-level value at offset (a, b) in [-2, 2]^2,
+ *             index (b + 2) * 5 + (a + 2) (1D: b = 0 only, W[h][a + 2]), of
+ *             sum_E f^hat-hat - sum_A f^hat-hat;
+ *   C[h][36]: weight of the detail of the level-(l+1) cell at offset (y1, y2)
+ *             in [-2, 3]^2 from 2k, index (y2 + 2) * 6 + (y1 + 2) (1D: C[h][y1 + 2]).
+ * Pure host computation (no device, no context). Errors: MRLBM_ERR_INVALID. */
+int mrlbm_transport_tables(int scheme, int n, double *W, double *C);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,245 @@
+// Device-side building blocks of the MR-LBM step: level geometry, the gamma = 1
+// projection / prediction operators, and the collision of each scheme.
+//
+// Storage is dense-addressed per level: level l owns N_l^d slots (N_l = 2^l) per
+// population, laid out [level][h][cell] with cell = x + (y << l). Only cells of
+// the complete tree, ghost cells and leaves are ever read or written, so the
+// traffic is proportional to the number of leaves while every neighbour lookup
+// is a plain address computation (no hashing, no rank tables).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrlbm {
+
+constexpr int MAXLEV = 32;
+constexpr int LEVEL_SHIFT = 26;                      // list entry = (level << 26) | cell
+constexpr uint32_t CELL_MASK = (1u << LEVEL_SHIFT) - 1;
+constexpr int LVL_STRIDE = MAXLEV + 2;               // per-category stride of level offsets
+
+// Cell codes of a mesh.
+enum : uint8_t { C_NONE = 0, C_GHOST = 1, C_INTERNAL = 2, C_LEAF = 3 };
+// List categories produced by the compaction.
+enum { CAT_LEAF = 0, CAT_INTERNAL = 1, CAT_GHOST = 2, NCAT = 3 };
+
+struct Geo {
+  int dim, q, jmin, jmax;
+  long long loff[MAXLEV + 2];  // first cell of level l; loff[jmax + 1] = total cells
+  int bstart[MAXLEV + 2];      // first compaction block of level l; bstart[jmax + 1] = blocks
+};
+
+template <typename T>
+struct Thresholds {
+  T eps_l[MAXLEV + 2];  // eps_l = 2^{d (l - J)} eps, indexed by the level of the children
+  T ref_l[MAXLEV + 2];  // 2^{mu_bar + d} eps_l
+};
+
+template <typename T>
+struct SchemeC {
+  T lam, inv_lam, eq;  // lattice velocity, its inverse, V (D1Q2) or alpha (D1Q3)
+  T s[9];
+};
+
+__device__ __forceinline__ long long ncells(const Geo &g, int l) { return 1ll << (g.dim * l); }
+__device__ __forceinline__ long long foff(const Geo &g, int l, int h) {
+  return (long long)g.q * g.loff[l] + (long long)h * ncells(g, l);
+}
+__device__ __forceinline__ int wrapl(int x, int l) { return x & ((1 << l) - 1); }
+template <int DIM>
+__device__ __forceinline__ long long cidx(int l, int x, int y) {
+  return DIM == 1 ? (long long)x : (long long)x + ((long long)y << l);
+}
+template <int DIM>
+__device__ __forceinline__ void coords(int l, uint32_t c, int &x, int &y) {
+  if (DIM == 1) { x = (int)c; y = 0; }
+  else { x = (int)(c & ((1u << l) - 1)); y = (int)(c >> l); }
+}
+__device__ __forceinline__ int level_of_cell(const Geo &g, long long gc) {
+  int l = g.jmin;
+  while (l < g.jmax && gc >= g.loff[l + 1]) ++l;
+  return l;
+}
+
+// ---------------------------------------------------------------- MR operators
+// Prediction (gamma = 1, c_1 = -1/8): with P the data of level l-1 around the
+// parent (px, py) of a child,
+//   1D: child = P(p) + s_x Qx,                      Qx = c_1 (P(p+1) - P(p-1)),
+//   2D: child = ((P(p) + s_x Qx) + s_y Qy) + s_x s_y Qxy,
+//       Qxy = c_1^2 (((P(+,+) - P(-,+)) - P(+,-)) + P(-,-)),
+// with s = +1 for the lower child and -1 for the upper one along each axis
+// (tensor product of the 1D operator). The evaluation order is part of the
+// contract: details decide the mesh, which must not depend on rounding order.
+template <int DIM, typename T>
+struct ParentStencil {
+  T c, qx, qy, qxy;
+  __device__ __forceinline__ void load(const T *__restrict__ P, int lp, int px, int py) {
+    const T c1 = T(-0.125);
+    if (DIM == 1) {
+      c = P[px];
+      qx = c1 * (P[wrapl(px + 1, lp)] - P[wrapl(px - 1, lp)]);
+      qy = T(0);
+      qxy = T(0);
+    } else {
+      const int xm = wrapl(px - 1, lp), xp = wrapl(px + 1, lp);
+      const int ym = wrapl(py - 1, lp), yp = wrapl(py + 1, lp);
+      c = P[cidx<2>(lp, px, py)];
+      qx = c1 * (P[cidx<2>(lp, xp, py)] - P[cidx<2>(lp, xm, py)]);
+      qy = c1 * (P[cidx<2>(lp, px, yp)] - P[cidx<2>(lp, px, ym)]);
+      qxy = T(0.015625) * (((P[cidx<2>(lp, xp, yp)] - P[cidx<2>(lp, xm, yp)]) - P[cidx<2>(lp, xp, ym)]) +
+                           P[cidx<2>(lp, xm, ym)]);
+    }
+  }
+  // child offset (dx, dy) in {0, 1}^d
+  __device__ __forceinline__ T child(int dx, int dy) const {
+    const T sx = dx ? T(-1) : T(1);
+    if (DIM == 1) return c + sx * qx;
+    const T sy = dy ? T(-1) : T(1);
+    return ((c + sx * qx) + sy * qy) + (sx * sy) * qxy;
+  }
+};
+
+template <int DIM, typename T>
+__device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy) {
+  ParentStencil<DIM, T> s;
+  s.load(P, l - 1, cx >> 1, cy >> 1);
+  return s.child(cx & 1, cy & 1);
+}
+
+// Projection: average of the 2^d children, 1D 0.5 (a0 + a1),
+// 2D 0.25 (((a00 + a10) + a01) + a11) with x fastest.
+template <int DIM, typename T>
+__device__ __forceinline__ T project(const T *__restrict__ C, int lc, int px, int py) {
+  if (DIM == 1) return T(0.5) * (C[2 * px] + C[2 * px + 1]);
+  const long long r0 = cidx<2>(lc, 2 * px, 2 * py), r1 = cidx<2>(lc, 2 * px, 2 * py + 1);
+  return T(0.25) * (((C[r0] + C[r0 + 1]) + C[r1]) + C[r1 + 1]);
+}
+
+// ---------------------------------------------------------------- schemes
+template <int SCHEME>
+struct Vel;
+template <>
+struct Vel<1> {  // D1Q2
+  static constexpr int Q = 2, DIM = 1, NC = 1;
+  __host__ __device__ static constexpr int ex(int h) { return h == 0 ? 1 : -1; }
+  __host__ __device__ static constexpr int ey(int) { return 0; }
+};
+template <>
+struct Vel<2> {  // D1Q3
+  static constexpr int Q = 3, DIM = 1, NC = 1;
+  __host__ __device__ static constexpr int ex(int h) { return h == 0 ? 0 : (h == 1 ? 1 : -1); }
+  __host__ __device__ static constexpr int ey(int) { return 0; }
+};
+template <>
+struct Vel<3> {  // D2Q9: rest, four axis velocities, four diagonals
+  static constexpr int Q = 9, DIM = 2, NC = 3;
+  __host__ __device__ static constexpr int ex(int h) {
+    return h == 1 || h == 5 || h == 8 ? 1 : (h == 3 || h == 6 || h == 7 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int ey(int h) {
+    return h == 2 || h == 5 || h == 6 ? 1 : (h == 4 || h == 7 || h == 8 ? -1 : 0);
+  }
+};
+
+// D2Q9 moments m = M f (Lallemand-Luo basis, rows scaled by powers of lambda).
+template <typename T>
+__device__ __forceinline__ void d2q9_moments(const T *f, T *m, T L) {
+  const T L2 = L * L, L3 = L2 * L, L4 = L2 * L2;
+  const T sa = f[1] + f[2] + f[3] + f[4], sd = f[5] + f[6] + f[7] + f[8];
+  m[0] = f[0] + sa + sd;
+  m[1] = L * (f[1] - f[3] + f[5] - f[6] - f[7] + f[8]);
+  m[2] = L * (f[2] - f[4] + f[5] + f[6] - f[7] - f[8]);
+  m[3] = L2 * (T(-4) * f[0] - sa + T(2) * sd);
+  m[4] = L3 * (T(-2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8]);
+  m[5] = L3 * (T(-2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8]);
+  m[6] = L4 * (T(4) * f[0] - T(2) * sa + sd);
+  m[7] = L2 * (f[1] - f[2] + f[3] - f[4]);
+  m[8] = L2 * (f[5] - f[6] + f[7] - f[8]);
+}
+
+// Lallemand-Luo equilibrium of the non-conserved moments 3..8, c_s^2 = lambda^2 / 3.
+template <typename T>
+__device__ __forceinline__ void d2q9_equilibrium(T rho, T qx, T qy, T L, T *e) {
+  const T cs2 = (L * L) / T(3), irho = T(1) / rho, q2 = qx * qx + qy * qy;
+  e[3] = T(3) * (T(-2) * cs2 * rho + q2 * irho);
+  e[4] = T(-3) * cs2 * qx;
+  e[5] = T(-3) * cs2 * qy;
+  e[6] = T(9) * (cs2 * cs2 * rho - cs2 * q2 * irho);
+  e[7] = (qx * qx - qy * qy) * irho;
+  e[8] = qx * qy * irho;
+}
+
+// f = M^{-1} m. The rows of M are orthogonal, so M^{-1} = M^T diag(1 / |row|^2).
+template <typename T>
+__device__ __forceinline__ void d2q9_populations(const T *m, T *f, T il) {
+  const T il2 = il * il, il3 = il2 * il, il4 = il2 * il2;
+  const T a0 = m[0] * T(1.0 / 9.0), a1 = m[1] * il * T(1.0 / 6.0), a2 = m[2] * il * T(1.0 / 6.0);
+  const T a3 = m[3] * il2 * T(1.0 / 36.0), a4 = m[4] * il3 * T(1.0 / 12.0), a5 = m[5] * il3 * T(1.0 / 12.0);
+  const T a6 = m[6] * il4 * T(1.0 / 36.0), a7 = m[7] * il2 * T(0.25), a8 = m[8] * il2 * T(0.25);
+  f[0] = a0 - T(4) * a3 + T(4) * a6;
+  f[1] = a0 + a1 - a3 - T(2) * a4 - T(2) * a6 + a7;
+  f[2] = a0 + a2 - a3 - T(2) * a5 - T(2) * a6 - a7;
+  f[3] = a0 - a1 - a3 + T(2) * a4 - T(2) * a6 + a7;
+  f[4] = a0 - a2 - a3 + T(2) * a5 - T(2) * a6 - a7;
+  f[5] = a0 + a1 + a2 + T(2) * a3 + a4 + a5 + a6 + a8;
+  f[6] = a0 - a1 + a2 + T(2) * a3 - a4 + a5 + a6 - a8;
+  f[7] = a0 - a1 - a2 + T(2) * a3 - a4 - a5 + a6 + a8;
+  f[8] = a0 + a1 - a2 + T(2) * a3 + a4 - a5 + a6 - a8;
+}
+
+// Collision in moment space: f^* = M^{-1} (m + S (m_eq(m) - m)), m = M f; the
+// conserved moments (s = 0) are passed through untouched.
+template <int SCHEME, typename T>
+__device__ __forceinline__ void collide(T *f, const SchemeC<T> &sc) {
+  if constexpr (SCHEME == 1) {
+    const T m0 = f[0] + f[1];
+    T m1 = sc.lam * (f[0] - f[1]);
+    m1 = m1 + sc.s[1] * (sc.eq * m0 - m1);
+    const T a = m1 * sc.inv_lam;
+    f[0] = T(0.5) * (m0 + a);
+    f[1] = T(0.5) * (m0 - a);
+  } else if constexpr (SCHEME == 2) {
+    const T m0 = f[0] + f[1] + f[2];
+    T m1 = sc.lam * (f[1] - f[2]);
+    T m2 = (sc.lam * sc.lam) * (f[1] + f[2]);
+    m1 = m1 + sc.s[1] * (T(0.5) * m0 * m0 - m1);
+    m2 = m2 + sc.s[2] * (sc.eq * (sc.lam * sc.lam) * m0 - m2);
+    const T a = m2 * (sc.inv_lam * sc.inv_lam), b = m1 * sc.inv_lam;
+    f[0] = m0 - a;
+    f[1] = T(0.5) * (a + b);
+    f[2] = T(0.5) * (a - b);
+  } else {
+    T m[9], e[9];
+    d2q9_moments(f, m, sc.lam);
+    d2q9_equilibrium(m[0], m[1], m[2], sc.lam, e);
+#pragma unroll
+    for (int i = 3; i < 9; ++i) m[i] = m[i] + sc.s[i] * (e[i] - m[i]);
+    d2q9_populations(m, f, sc.inv_lam);
+  }
+}
+
+// f = M^{-1} m_eq(m) from the conserved moments (initial datum of Algorithm 1).
+template <int SCHEME, typename T>
+__device__ __forceinline__ void equilibrium_populations(const T *mc, T *f, const SchemeC<T> &sc) {
+  if constexpr (SCHEME == 1) {
+    const T a = (sc.eq * mc[0]) * sc.inv_lam;
+    f[0] = T(0.5) * (mc[0] + a);
+    f[1] = T(0.5) * (mc[0] - a);
+  } else if constexpr (SCHEME == 2) {
+    const T u = mc[0];
+    const T m1 = T(0.5) * u * u, m2 = sc.eq * (sc.lam * sc.lam) * u;
+    const T a = m2 * (sc.inv_lam * sc.inv_lam), b = m1 * sc.inv_lam;
+    f[0] = u - a;
+    f[1] = T(0.5) * (a + b);
+    f[2] = T(0.5) * (a - b);
+  } else {
+    T m[9];
+    m[0] = mc[0];
+    m[1] = mc[1];
+    m[2] = mc[2];
+    d2q9_equilibrium(mc[0], mc[1], mc[2], sc.lam, m);
+    d2q9_populations(m, f, sc.inv_lam);
+  }
+}
+
+}  // namespace mrlbm

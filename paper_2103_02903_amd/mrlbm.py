@@ -1,0 +1,190 @@
+"""ctypes binding of the C-ABI in ``include/mrlbm.h`` (argument marshalling only).
+
+Every step of the method runs in the HIP library ``libmrlbm.so``; PyTorch only
+provides device memory (the workspace, input and output buffers) and the HIP
+stream. There is no fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .workloads import SCHEME_DIMS
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmrlbm.so")
+
+SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3}
+STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-finite leaf value",
+          -4: "HIP runtime error", -5: "call out of order"}
+EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mrlbm_adapt",
+           "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
+           "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables"]
+
+
+class MrlbmError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__("%s failed: %s (%d)" % (fn, STATUS.get(status, "unknown"), status))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
+                ("precision", ctypes.c_int), ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
+                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 9)]
+
+    @classmethod
+    def from_cfg(cls, cfg: dict, precision: int = 8) -> "Params":
+        s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        return cls(SCHEME_IDS[cfg["scheme"]], int(cfg["jmin"]), int(cfg["jmax"]), int(precision),
+                   float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)), float(cfg["eps"]),
+                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s))
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libmrlbm.so`` (built in-tree by ``build.build()``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run paper_2103_02903_amd.build.build() "
+                               "(or __graft_entry__.build()) first" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+        sig = {
+            "mrlbm_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+            "mrlbm_create": [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+            "mrlbm_init_equilibrium": [vp, vp], "mrlbm_adapt": [vp], "mrlbm_transport_collide": [vp],
+            "mrlbm_step": [vp, ctypes.c_int], "mrlbm_get_state": [vp, vp, vp], "mrlbm_set_state": [vp, vp, vp],
+            "mrlbm_sizes": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
+            "mrlbm_stats": [vp, ctypes.POINTER(ctypes.c_double), vp, vp, vp],
+            "mrlbm_leaves": [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+            "mrlbm_destroy": [vp], "mrlbm_transport_tables": [ctypes.c_int, ctypes.c_int, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.mrlbm_status_string.argtypes = [ctypes.c_int]
+        L.mrlbm_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != 0:
+        raise MrlbmError(fn, rc)
+
+
+def transport_tables(scheme: str, n: int):
+    """Host-side flattened transport weights W[q][25] and detail weights C[q][36]."""
+    q = SCHEME_DIMS[scheme][1]
+    W = np.zeros((q, 25), np.float64)
+    C = np.zeros((q, 36), np.float64)
+    _check("mrlbm_transport_tables",
+           lib().mrlbm_transport_tables(SCHEME_IDS[scheme], int(n), W.ctypes.data, C.ctypes.data))
+    return W, C
+
+
+class Sim:
+    """One MR-LBM instance on a GPU. ``cfg`` is a parameter dictionary of
+    ``workloads``; ``precision`` is 8 (FP64) or 4 (FP32)."""
+
+    def __init__(self, cfg: dict, precision: int = 8, device: str = "cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.cfg = dict(cfg)
+        self.precision = int(precision)
+        self.dim, self.q, self.nc = SCHEME_DIMS[cfg["scheme"]]
+        self.jmin, self.jmax = int(cfg["jmin"]), int(cfg["jmax"])
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == 8 else torch.float32
+        self.np_dtype = np.float64 if precision == 8 else np.float32
+        L = lib()
+        self._p = Params.from_cfg(cfg, precision)
+        nbytes = ctypes.c_size_t(0)
+        _check("mrlbm_workspace_size", L.mrlbm_workspace_size(ctypes.byref(self._p), ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p(0)
+        _check("mrlbm_create", L.mrlbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.workspace.data_ptr()),
+                                              self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(ctx)))
+        self._ctx = ctx
+        tot = ctypes.c_int64(0)
+        q = ctypes.c_int(0)
+        _check("mrlbm_sizes", L.mrlbm_sizes(ctx, ctypes.byref(tot), ctypes.byref(q)))
+        self.total_cells = int(tot.value)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().mrlbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- time stepping
+    def init_equilibrium(self, m0):
+        t = self.torch
+        m = t.as_tensor(np.ascontiguousarray(m0), dtype=self.dtype).to(self.device).contiguous()
+        assert m.numel() == self.nc * (1 << (self.dim * self.jmax))
+        self._m0 = m  # kept alive until the asynchronous kernel has read it
+        _check("mrlbm_init_equilibrium", lib().mrlbm_init_equilibrium(self._ctx, ctypes.c_void_p(m.data_ptr())))
+
+    def step(self, n: int = 1):
+        _check("mrlbm_step", lib().mrlbm_step(self._ctx, int(n)))
+
+    def adapt(self):
+        _check("mrlbm_adapt", lib().mrlbm_adapt(self._ctx))
+
+    def transport_collide(self):
+        _check("mrlbm_transport_collide", lib().mrlbm_transport_collide(self._ctx))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ---- state exchange (host arrays in the layouts of include/mrlbm.h)
+    def get_state(self):
+        tree = np.zeros(self.total_cells, np.uint8)
+        values = np.zeros(self.q * self.total_cells, self.np_dtype)
+        _check("mrlbm_get_state", lib().mrlbm_get_state(self._ctx, tree.ctypes.data, values.ctypes.data))
+        return tree, values
+
+    def set_state(self, tree, values):
+        tree = np.ascontiguousarray(tree, dtype=np.uint8)
+        values = np.ascontiguousarray(values, dtype=self.np_dtype)
+        assert tree.size == self.total_cells and values.size == self.q * self.total_cells
+        _check("mrlbm_set_state", lib().mrlbm_set_state(self._ctx, tree.ctypes.data, values.ctypes.data))
+
+    def stats(self):
+        mass = ctypes.c_double(0.0)
+        n = self.jmax + 1
+        leaves, internal, ghosts = (np.zeros(n, np.int64) for _ in range(3))
+        _check("mrlbm_stats", lib().mrlbm_stats(self._ctx, ctypes.byref(mass), leaves.ctypes.data,
+                                                internal.ctypes.data, ghosts.ctypes.data))
+        return dict(mass=float(mass.value), leaves=leaves, internal=internal, ghosts=ghosts)
+
+    def leaves(self):
+        """(cells uint32 tensor of (level << 26) | cell, values [n][q] tensor) on the device."""
+        t = self.torch
+        count = ctypes.c_int64(0)
+        rc = lib().mrlbm_leaves(self._ctx, None, None, 0, ctypes.byref(count))
+        if rc not in (0, -2):
+            _check("mrlbm_leaves", rc)
+        n = int(count.value)
+        cells = t.empty(max(n, 1), dtype=t.int32, device=self.device)
+        vals = t.empty((max(n, 1), self.q), dtype=self.dtype, device=self.device)
+        _check("mrlbm_leaves", lib().mrlbm_leaves(self._ctx, ctypes.c_void_p(cells.data_ptr()),
+                                                  ctypes.c_void_p(vals.data_ptr()), n, ctypes.byref(count)))
+        return cells[:n], vals[:n]

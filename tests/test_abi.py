@@ -1,0 +1,125 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function that
+include/mrlbm.h declares, rejects invalid parameters, and its host-side
+transport weights equal the exact sums of eq. (PredictionWithMatrixNew)."""
+import ctypes
+import os
+import re
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from paper_2103_02903_amd import mrlbm
+from paper_2103_02903_amd import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mrlbm.h")
+
+
+def test_library_exports_every_declared_function():
+    decl = set(re.findall(r"^\s*(?:int|const char \*)\s*(mrlbm_\w+)\s*\(", open(HEADER).read(), re.M))
+    assert decl == set(mrlbm.EXPORTS)
+    L = mrlbm.lib()
+    for name in decl:
+        assert hasattr(L, name)
+
+
+def test_status_strings():
+    L = mrlbm.lib()
+    for code, text in mrlbm.STATUS.items():
+        assert L.mrlbm_status_string(code).decode() == text
+
+
+def _wsize(**kw):
+    cfg = W.params("D2Q9", 3, 6, 1e-3, W.d2q9_s(1.5, 1.8), mu_bar=1.0)
+    cfg.update(kw)
+    p = mrlbm.Params.from_cfg(cfg, kw.pop("precision", 8))
+    n = ctypes.c_size_t(0)
+    return mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)), n.value
+
+
+def test_workspace_size_and_parameter_validation():
+    rc, n = _wsize()
+    assert rc == 0 and n > 2 * 9 * 8 * sum(4 ** l for l in range(3, 7))
+    assert _wsize(jmin=7)[0] == -1            # jmin > jmax
+    assert _wsize(jmax=14)[0] == -1           # beyond the 2D level limit
+    assert _wsize(eps=-1.0)[0] == -1
+    assert _wsize(mu_bar=4.0)[0] == -1
+    assert _wsize(s=[0.1] + [0.0] * 8)[0] == -1   # a conserved moment must not relax
+    p = mrlbm.Params.from_cfg(W.params("D1Q2", 2, 5, 1e-3, [0, 1.9]), 16)
+    n = ctypes.c_size_t(0)
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_create_rejects_small_workspace_without_touching_it():
+    cfg = W.params("D1Q2", 2, 5, 1e-3, [0, 1.9])
+    p = mrlbm.Params.from_cfg(cfg, 8)
+    n = ctypes.c_size_t(0)
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    buf = ctypes.create_string_buffer(16)
+    ctx = ctypes.c_void_p(0)
+    rc = mrlbm.lib().mrlbm_create(ctypes.byref(p), ctypes.cast(buf, ctypes.c_void_p), 16, None, ctypes.byref(ctx))
+    assert rc == -2 and not ctx.value
+
+
+# ------------------------------------------------------------ transport weights
+
+def _pred_down(vals, lo, m):
+    """Exact 1D prediction (c1 = -1/8) of a dict {index: Fraction}, m levels down."""
+    for _ in range(m):
+        keys = range(min(vals) - 1, max(vals) + 2)
+        nv = {}
+        for i in keys:
+            q = Fr(-1, 8) * (vals.get(i + 1, Fr(0)) - vals.get(i - 1, Fr(0)))
+            nv[2 * i] = vals.get(i, Fr(0)) + q
+            nv[2 * i + 1] = vals.get(i, Fr(0)) - q
+        vals = nv
+    return vals
+
+
+def _exact_sum(n, m, e, a):
+    v = _pred_down({a: Fr(1)}, 0, m)
+    return sum(v.get(i, Fr(0)) for i in range(-e, (1 << n) - e))
+
+
+@pytest.mark.parametrize("scheme", ["D1Q2", "D1Q3", "D2Q9"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_transport_tables_are_exact(scheme, n):
+    """W = (sum over B - eta) - (sum over B) of the reconstruction of each leaf-level
+    impulse, C = the same for impulses one level finer; all entries are exact
+    dyadic rationals, so the double tables must hold them exactly."""
+    Wt, Ct = mrlbm.transport_tables(scheme, n)
+    dim, q, _ = W.SCHEME_DIMS[scheme]
+    import oracle
+    eta = oracle.Oracle(W.params(scheme, 1, 3, 0.0, {"D1Q2": [0, 1], "D1Q3": [0, 1, 1],
+                                                     "D2Q9": [0] * 9}[scheme])).velocities()
+    for h in range(q):
+        ex, ey = (int(v) for v in eta[h])
+        if ex == 0 and ey == 0:
+            assert not Wt[h].any() and not Ct[h].any()
+            continue
+        Sx = {a: _exact_sum(n, n, ex, a) for a in range(-2, 3)}
+        Sy = {b: (_exact_sum(n, n, ey, b) if dim == 2 else Fr(int(b == 0))) for b in range(-2, 3)}
+        Tx = {y: _exact_sum(n, n - 1, ex, y) for y in range(-2, 4)}
+        Ty = {y: (_exact_sum(n, n - 1, ey, y) if dim == 2 else Fr(int(y == 0))) for y in range(-2, 4)}
+        for b in range(-2, 3):
+            for a in range(-2, 3):
+                want = Sx[a] * Sy[b] - (Fr(2) ** (dim * n) if a == 0 and b == 0 else 0)
+                assert Fr(Wt[h, (b + 2) * 5 + a + 2]) == want
+        for y2 in range(-2, 4):
+            for y1 in range(-2, 4):
+                assert Fr(Ct[h, (y2 + 2) * 6 + y1 + 2]) == Tx[y1] * Ty[y2]
+
+
+def test_transport_table_support_at_most_25_values():
+    """At most 25 leaf-level values per flux for D2Q9 (section 'A non-recursive
+    implementation of the reconstruction operator'); axis velocities use at most 5,
+    all on the leaf's own row or column."""
+    for n in range(1, 8):
+        Wt, _ = mrlbm.transport_tables("D2Q9", n)
+        nz = (Wt != 0).sum(axis=1)
+        assert nz[0] == 0 and all(nz[1:5] <= 5) and all(nz[5:9] <= 25)
+        grid = (Wt != 0).reshape(9, 5, 5)
+        for h in (1, 3):
+            assert not grid[h][[0, 1, 3, 4]].any()
+        for h in (2, 4):
+            assert not grid[h][:, [0, 1, 3, 4]].any()
