@@ -70,22 +70,29 @@ typedef struct {
   double s[9];     /* relaxation rate of each moment; conserved moments must be 0 */
 } mrlbm_params;
 
+/* A context runs a batch of `batch` independent instances (1 <= batch <= 256),
+ * p[0..batch-1], that share the scheme, the precision and jmin; jmax, eps,
+ * mu_bar, lambda and the relaxation rates may differ per instance. Every step
+ * advances all of them with one set of launches. Their total cell count
+ * (sum over instances and levels of N_l^d) must stay below 2^31. */
+
 /* Bytes of device workspace a context with these parameters needs.
  * Errors: MRLBM_ERR_INVALID for invalid parameters or a null pointer. */
-int mrlbm_workspace_size(const mrlbm_params *p, size_t *bytes);
+int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes);
 
 /* Create a context inside `workspace` (device memory, >= mrlbm_workspace_size
  * bytes, 256-byte aligned) that enqueues its work on `stream` (a hipStream_t,
  * NULL = the default stream). Uploads the parameter-dependent tables; does not
  * set an initial state. Errors: MRLBM_ERR_INVALID, MRLBM_ERR_CAPACITY,
  * MRLBM_ERR_HIP. */
-int mrlbm_create(const mrlbm_params *p, void *workspace, size_t ws_bytes, void *stream,
+int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream,
                  mrlbm_ctx **out);
 
-/* Initial state of Algorithm 1: the full finest mesh with f = M^{-1} m_eq(m0)
- * on every finest cell. `moments` is a device buffer in the context precision,
- * layout [nc][N_J^d] (see above). Asynchronous. */
-int mrlbm_init_equilibrium(mrlbm_ctx *ctx, const void *moments);
+/* Initial state of Algorithm 1 for one instance: the full finest mesh with
+ * f = M^{-1} m_eq(m0) on every finest cell. `moments` is a device buffer in the
+ * context precision, layout [nc][N_J^d] (see above). Every instance must be
+ * initialised (or set) before the first step. Asynchronous. */
+int mrlbm_init_equilibrium(mrlbm_ctx *ctx, int instance, const void *moments);
 
 /* Mesh adaptation only: new tree G(H_eps(T_eps(tree))) with details of the
  * current leaf values, then the transfer of the data to the new complete leaves
@@ -100,32 +107,54 @@ int mrlbm_transport_collide(mrlbm_ctx *ctx);
  * Asynchronous; nsteps >= 0. */
 int mrlbm_step(mrlbm_ctx *ctx, int nsteps);
 
-/* Copy the current tree and values to host buffers (layouts above; `values`
- * holds q * total_cells reals of the context precision). Synchronous. */
-int mrlbm_get_state(mrlbm_ctx *ctx, uint8_t *tree, void *values);
+/* Copy the current tree and values of one instance to host buffers (layouts
+ * above; `values` holds q * total_cells reals of the context precision).
+ * Synchronous. */
+int mrlbm_get_state(mrlbm_ctx *ctx, int instance, uint8_t *tree, void *values);
 
 /* Replace the current state by a host-side tree (must be a graded complete
  * tree: level jmin full, sibling groups complete, every tree cell's prediction
  * stencil in the tree) and leaf values. Synchronous.
  * Errors: MRLBM_ERR_INVALID if the tree is not graded and complete. */
-int mrlbm_set_state(mrlbm_ctx *ctx, const uint8_t *tree, const void *values);
+int mrlbm_set_state(mrlbm_ctx *ctx, int instance, const uint8_t *tree, const void *values);
 
-/* Total number of cells over levels jmin..jmax and number of populations. */
-int mrlbm_sizes(const mrlbm_ctx *ctx, int64_t *total_cells, int *q);
+/* Total number of cells of one instance over levels jmin..jmax, and the number
+ * of populations. */
+int mrlbm_sizes(const mrlbm_ctx *ctx, int instance, int64_t *total_cells, int *q);
 
-/* Diagnostics of the current state (synchronous): mass = sum over complete
+/* Diagnostics of one instance (synchronous): mass = sum over complete
  * leaves of |C_l| / |C_J| * sum_h f^h, accumulated in double with a fixed
  * order; per-level counts of complete leaves, internal tree cells and ghost
  * cells ([jmax + 1] each, any of them may be NULL).
  * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite. */
-int mrlbm_stats(mrlbm_ctx *ctx, double *mass, int64_t *leaves, int64_t *internal, int64_t *ghosts);
+int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int64_t *internal,
+                int64_t *ghosts);
 
-/* Export of the complete leaves to device buffers, in the order (level, cell):
+/* Export of the complete leaves of one instance to device buffers, in the order (level, cell):
  * `cells` receives (level << 26) | cell as uint32 and `values` receives q reals
  * per leaf ([leaf][h], context precision). `capacity` is the number of leaves
  * the buffers hold; *count receives the number of leaves. Synchronous.
  * Errors: MRLBM_ERR_CAPACITY if capacity < count (nothing is written). */
-int mrlbm_leaves(mrlbm_ctx *ctx, uint32_t *cells, void *values, int64_t capacity, int64_t *count);
+int mrlbm_leaves(mrlbm_ctx *ctx, int instance, uint32_t *cells, void *values, int64_t capacity,
+                 int64_t *count);
+
+/* Counters of the work done since the last mrlbm_profile call (all instances). */
+typedef struct {
+  uint64_t leaf_updates;       /* complete leaves transported and collided, summed over launches */
+  uint64_t transport_launches; /* launches of the transport-collision kernel */
+  double transport_ms;         /* HIP-event time of the transport-collision kernel alone */
+  double reconstruct_ms;       /* HIP-event time of the reconstructions before transport */
+  double adapt_ms;             /* HIP-event time of the mesh adaptation and transfer */
+  uint64_t timed_launches;     /* transport launches covered by the event timings */
+} mrlbm_counters;
+
+/* Reset the counters and switch per-phase HIP-event timing on (enable = 1) or
+ * off (0). Leaf updates are always counted (on the device, by the transport
+ * kernel). Timing records events on the context stream around each phase. */
+int mrlbm_profile(mrlbm_ctx *ctx, int enable);
+
+/* Read the counters (synchronous). */
+int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
 
 /* Destroy the context (the workspace is the caller's to free). */
 int mrlbm_destroy(mrlbm_ctx *ctx);

@@ -23,27 +23,37 @@ enum : uint8_t { C_NONE = 0, C_GHOST = 1, C_INTERNAL = 2, C_LEAF = 3 };
 // List categories produced by the compaction.
 enum { CAT_LEAF = 0, CAT_INTERNAL = 1, CAT_GHOST = 2, NCAT = 3 };
 
-struct Geo {
-  int dim, q, jmin, jmax;
-  long long loff[MAXLEV + 2];  // first cell of level l; loff[jmax + 1] = total cells
-  int bstart[MAXLEV + 2];      // first compaction block of level l; bstart[jmax + 1] = blocks
-};
-
-template <typename T>
-struct Thresholds {
-  T eps_l[MAXLEV + 2];  // eps_l = 2^{d (l - J)} eps, indexed by the level of the children
-  T ref_l[MAXLEV + 2];  // 2^{mu_bar + d} eps_l
-};
-
 template <typename T>
 struct SchemeC {
   T lam, inv_lam, eq;  // lattice velocity, its inverse, V (D1Q2) or alpha (D1Q3)
   T s[9];
 };
 
-__device__ __forceinline__ long long ncells(const Geo &g, int l) { return 1ll << (g.dim * l); }
-__device__ __forceinline__ long long foff(const Geo &g, int l, int h) {
-  return (long long)g.q * g.loff[l] + (long long)h * ncells(g, l);
+// One simulation of a batch. Per-cell arrays (codes, flags, lists) of all
+// instances are concatenated; instance i owns cells [cbase, cbase + total) and
+// the list slots with the same indices in every category. Populations are laid
+// out [instance][level][h][cell].
+template <typename T>
+struct Inst {
+  int jmin, jmax;
+  long long cbase, total;
+  long long loff[MAXLEV + 2];  // absolute first cell of level l; loff[jmax + 1] = cbase + total
+  int bstart[MAXLEV + 2];      // absolute first compaction block of level l; bstart[jmax + 1] = end
+  T eps_l[MAXLEV + 2];         // eps_l = 2^{d (l - J)} eps, indexed by the level of the children
+  T ref_l[MAXLEV + 2];         // 2^{mu_bar + d} eps_l
+  SchemeC<T> sc;
+};
+
+// Batch-wide constants (passed by value).
+struct Batch {
+  int B, dim, q, jmin, maxJ;
+  long long ctotal;  // cells of all instances
+};
+
+__device__ __forceinline__ long long ncells_d(int dim, int l) { return 1ll << (dim * l); }
+template <typename T>
+__device__ __forceinline__ long long foff(const Inst<T> &I, int dim, int q, int l, int h) {
+  return (long long)q * I.loff[l] + (long long)h * ncells_d(dim, l);
 }
 __device__ __forceinline__ int wrapl(int x, int l) { return x & ((1 << l) - 1); }
 template <int DIM>
@@ -55,10 +65,15 @@ __device__ __forceinline__ void coords(int l, uint32_t c, int &x, int &y) {
   if (DIM == 1) { x = (int)c; y = 0; }
   else { x = (int)(c & ((1u << l) - 1)); y = (int)(c >> l); }
 }
-__device__ __forceinline__ int level_of_cell(const Geo &g, long long gc) {
-  int l = g.jmin;
-  while (l < g.jmax && gc >= g.loff[l + 1]) ++l;
-  return l;
+// Largest i in [0, n) with a[i] <= v (a non-decreasing, a[0] <= v).
+template <typename I>
+__device__ __forceinline__ int upper_index(const I *a, int n, long long v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((long long)a[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---------------------------------------------------------------- MR operators

@@ -1,6 +1,6 @@
 // C-ABI of the MR-LBM hot path (declared in include/mrlbm.h): context set-up in a
-// caller-owned workspace, the flattened transport weights, and the per-step
-// launch sequence of Algorithm 1 of arXiv 2103.02903.
+// caller-owned workspace for a batch of instances, the flattened transport
+// weights, and the per-step launch sequence of Algorithm 1 of arXiv 2103.02903.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "mr_kernels.h"
@@ -19,7 +20,6 @@ namespace {
 
 int scheme_dim(int s) { return s == MRLBM_D2Q9 ? 2 : 1; }
 int scheme_q(int s) { return s == MRLBM_D1Q2 ? 2 : s == MRLBM_D1Q3 ? 3 : 9; }
-int scheme_nc(int s) { return s == MRLBM_D2Q9 ? 3 : 1; }
 void scheme_eta(int s, int h, int &ex, int &ey) {
   static const int d1q2[2] = {1, -1};
   static const int d1q3[3] = {0, 1, -1};
@@ -31,7 +31,7 @@ void scheme_eta(int s, int h, int &ex, int &ey) {
 }
 bool conserved(int s, int i) { return s == MRLBM_D2Q9 ? i < 3 : i == 0; }
 
-int validate(const mrlbm_params *p) {
+int validate_one(const mrlbm_params *p) {
   if (!p) return MRLBM_ERR_INVALID;
   if (p->scheme < MRLBM_D1Q2 || p->scheme > MRLBM_D2Q9) return MRLBM_ERR_INVALID;
   const int dim = scheme_dim(p->scheme);
@@ -45,6 +45,20 @@ int validate(const mrlbm_params *p) {
     if (!std::isfinite(p->s[i])) return MRLBM_ERR_INVALID;
     if (conserved(p->scheme, i) && p->s[i] != 0.0) return MRLBM_ERR_INVALID;
   }
+  return MRLBM_OK;
+}
+
+int validate(const mrlbm_params *p, int batch) {
+  if (!p || batch < 1 || batch > MAXB) return MRLBM_ERR_INVALID;
+  long long cells = 0;
+  for (int i = 0; i < batch; ++i) {
+    const int rc = validate_one(&p[i]);
+    if (rc) return rc;
+    if (p[i].scheme != p[0].scheme || p[i].precision != p[0].precision || p[i].jmin != p[0].jmin)
+      return MRLBM_ERR_INVALID;
+    for (int l = p[i].jmin; l <= p[i].jmax; ++l) cells += 1ll << (scheme_dim(p[i].scheme) * l);
+  }
+  if (cells >= (1ll << 31)) return MRLBM_ERR_INVALID;  // list positions are 32-bit
   return MRLBM_OK;
 }
 
@@ -102,83 +116,132 @@ void transport_tables(int scheme, int n, double *W, double *C) {
       Ty[y + 2] = dim == 2 ? impulse_sum(n, n - 1, ey, y) : (y == 0 ? 1.0 : 0.0);
     }
     const double full = std::ldexp(1.0, dim * n);
+    const bool rest = ex == 0 && ey == 0;
     for (int b = -2; b <= 2; ++b)
       for (int a = -2; a <= 2; ++a) {
         double w = Sx[a + 2] * Sy[b + 2];
-        if (a == 0 && b == 0) w -= (ex == 0 && ey == 0) ? w : full;  // E - A form; rest velocity: 0
+        if (a == 0 && b == 0) w -= rest ? w : full;  // E - A form; rest velocity: 0
         W[h * 25 + (b + 2) * 5 + (a + 2)] = w;
       }
     for (int y2 = -2; y2 <= 3; ++y2)
-      for (int y1 = -2; y1 <= 3; ++y1) C[h * 36 + (y2 + 2) * 6 + (y1 + 2)] = (ex == 0 && ey == 0) ? 0.0 : Tx[y1 + 2] * Ty[y2 + 2];
+      for (int y1 = -2; y1 <= 3; ++y1) C[h * 36 + (y2 + 2) * 6 + (y1 + 2)] = rest ? 0.0 : Tx[y1 + 2] * Ty[y2 + 2];
   }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct Layout {
-  long long total;
-  int nb, nmax, q, dim;
-  size_t rs;  // sizeof(real)
-  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_bcnt, off_boff,
-      off_W, off_C, off_red, off_bad, bytes;
+// Static description of a batch: instance descriptors (double-precision
+// thresholds; converted to the working precision on upload), block tables, and
+// the workspace layout.
+struct Plan {
+  int B, dim, q, jmin, maxJ, nmax, nblocks;
+  size_t rs;
+  long long ctotal;
+  std::vector<Inst<double>> inst;
+  std::vector<long long> cb;   // [B + 1] first cell of each instance
+  std::vector<int> cbp;        // [B + 1] first compaction block of each instance
+  std::vector<int> dtab;       // [3][LVL_STRIDE][B + 1] dense-level block prefixes
+  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_bcnt, off_boff, off_W,
+      off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, bytes;
+  int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
+  const int *dtab_row(const int *dev, int off, int L) const { return dev + ((size_t)off * LVL_STRIDE + L) * (B + 1); }
 };
 
-void make_geo(const mrlbm_params *p, Geo &g, Layout &L) {
-  std::memset(&g, 0, sizeof g);
-  g.dim = scheme_dim(p->scheme);
-  g.q = scheme_q(p->scheme);
-  g.jmin = p->jmin;
-  g.jmax = p->jmax;
-  long long off = 0;
+void make_plan(const mrlbm_params *p, int B, Plan &P) {
+  P.B = B;
+  P.dim = scheme_dim(p[0].scheme);
+  P.q = scheme_q(p[0].scheme);
+  P.jmin = p[0].jmin;
+  P.maxJ = 0;
+  P.rs = p[0].precision == 8 ? 8 : 4;
+  P.inst.assign(B, Inst<double>());
+  P.cb.assign(B + 1, 0);
+  P.cbp.assign(B + 1, 0);
+  long long cells = 0;
   int blocks = 0;
-  for (int l = 0; l <= MAXLEV + 1; ++l) {
-    g.loff[l] = off;
-    g.bstart[l] = blocks;
-    if (l >= p->jmin && l <= p->jmax) {
-      const long long n = 1ll << (g.dim * l);
-      off += n;
-      blocks += (int)((n + CCHUNK - 1) / CCHUNK);
+  for (int i = 0; i < B; ++i) {
+    Inst<double> &I = P.inst[i];
+    std::memset(&I, 0, sizeof I);
+    I.jmin = p[i].jmin;
+    I.jmax = p[i].jmax;
+    P.maxJ = std::max(P.maxJ, I.jmax);
+    I.cbase = cells;
+    P.cb[i] = cells;
+    P.cbp[i] = blocks;
+    long long off = cells;
+    for (int l = 0; l < LVL_STRIDE; ++l) {
+      I.loff[l] = off;
+      I.bstart[l] = blocks;
+      if (l >= I.jmin && l <= I.jmax) {
+        const long long n = 1ll << (P.dim * l);
+        off += n;
+        blocks += (int)((n + CCHUNK - 1) / CCHUNK);
+      }
     }
+    I.total = off - cells;
+    cells = off;
+    for (int l = 0; l < LVL_STRIDE; ++l) {
+      I.eps_l[l] = std::ldexp(p[i].eps, P.dim * (l - p[i].jmax));
+      I.ref_l[l] = std::ldexp(I.eps_l[l], P.dim) * std::exp2(p[i].mu_bar);
+    }
+    I.sc.lam = p[i].lambda;
+    I.sc.inv_lam = 1.0 / p[i].lambda;
+    I.sc.eq = p[i].eq_param;
+    for (int k = 0; k < 9; ++k) I.sc.s[k] = p[i].s[k];
   }
-  L.total = g.loff[p->jmax + 1];
-  L.nb = g.bstart[p->jmax + 1];
-  L.nmax = p->jmax - p->jmin;
-  L.q = g.q;
-  L.dim = g.dim;
-  L.rs = p->precision == 8 ? 8 : 4;
+  P.cb[B] = cells;
+  P.cbp[B] = blocks;
+  P.ctotal = cells;
+  P.nblocks = blocks;
+  P.nmax = P.maxJ - P.jmin;
+  // dense passes over level L of every instance where jmin <= L <= jmax - off
+  P.dtab.assign((size_t)3 * LVL_STRIDE * (B + 1), 0);
+  for (int off = 0; off < 3; ++off)
+    for (int L = 0; L < LVL_STRIDE; ++L) {
+      int *row = &P.dtab[((size_t)off * LVL_STRIDE + L) * (B + 1)];
+      int acc = 0;
+      for (int i = 0; i < B; ++i) {
+        row[i] = acc;
+        if (L >= P.jmin && L <= P.inst[i].jmax - off) acc += (int)(((1ll << (P.dim * L)) + BLK - 1) / BLK);
+      }
+      row[B] = acc;
+    }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-  for (int k = 0; k < 2; ++k) L.off_F[k] = take(L.rs * L.q * L.total);
-  for (int k = 0; k < 2; ++k) L.off_code[k] = take(L.total);
-  for (int k = 0; k < 2; ++k) L.off_lists[k] = take(sizeof(uint32_t) * NCAT * L.total);
-  for (int k = 0; k < 2; ++k) L.off_lvl[k] = take(sizeof(int) * NCAT * LVL_STRIDE);
-  L.off_keep = take(L.total);
-  L.off_refg = take(L.total);
-  L.off_tnew = take(L.total);
-  L.off_bcnt = take(sizeof(int) * NCAT * L.nb);
-  L.off_boff = take(sizeof(int) * NCAT * L.nb);
-  const int ws = g.dim == 2 ? 25 : 5, cs = g.dim == 2 ? 36 : 6;
-  L.off_W = take(L.rs * std::max(1, L.nmax) * L.q * ws);
-  L.off_C = take(L.rs * std::max(1, L.nmax) * L.q * cs);
-  L.off_red = take(sizeof(double) * RED_BLOCKS);
-  L.off_bad = take(sizeof(int) * 4);
-  L.bytes = o + 256;  // slack for aligning the base pointer
+  for (int k = 0; k < 2; ++k) P.off_F[k] = take(P.rs * P.q * P.ctotal);
+  for (int k = 0; k < 2; ++k) P.off_code[k] = take(P.ctotal);
+  for (int k = 0; k < 2; ++k) P.off_lists[k] = take(sizeof(uint32_t) * NCAT * P.ctotal);
+  for (int k = 0; k < 2; ++k) P.off_lvl[k] = take(sizeof(int) * B * NCAT * LVL_STRIDE);
+  P.off_keep = take(P.ctotal);
+  P.off_refg = take(P.ctotal);
+  P.off_tnew = take(P.ctotal);
+  P.off_bcnt = take(sizeof(int) * NCAT * P.nblocks);
+  P.off_boff = take(sizeof(int) * NCAT * P.nblocks);
+  const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
+  P.off_W = take(P.rs * std::max(1, P.nmax) * P.q * ws);
+  P.off_C = take(P.rs * std::max(1, P.nmax) * P.q * cs);
+  P.off_red = take(sizeof(double) * RED_BLOCKS * B);
+  P.off_bad = take(sizeof(int) * 4);
+  P.off_cnt = take(sizeof(unsigned long long) * 4);
+  P.off_inst = take(std::max(sizeof(Inst<double>), sizeof(Inst<float>)) * B);
+  P.off_cb = take(sizeof(long long) * (B + 1));
+  P.off_cbp = take(sizeof(int) * (B + 1));
+  P.off_dtab = take(sizeof(int) * P.dtab.size());
+  P.bytes = o + 256;  // slack for aligning the base pointer
 }
 
-unsigned grid_for(long long n, unsigned cap = 4096) {
-  long long b = (n + BLK - 1) / BLK;
-  if (b < 1) b = 1;
-  return (unsigned)(b > cap ? cap : b);
+unsigned grid_cap(long long n, unsigned cap) {
+  if (n < 1) n = 1;
+  return (unsigned)(n > cap ? cap : n);
 }
 
 }  // namespace
 
 struct mrlbm_ctx {
-  mrlbm_params p;
-  Geo geo;
-  Layout L;
+  std::vector<mrlbm_params> p;
+  Plan P;
+  Batch bt;
   hipStream_t stream;
-  char *base;
   void *F[2];
   uint8_t *code[2];
   uint32_t *lists[2];
@@ -188,168 +251,237 @@ struct mrlbm_ctx {
   void *W, *C;
   double *red;
   int *bad;
+  unsigned long long *cnt;  // device counters: leaf updates, transport launches
+  void *inst;               // Inst<T>[B]
+  long long *cb;
+  int *cbp, *dtab;
   int cur;   // F[cur] holds the state
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
-  bool has_state;
-  double eps_l[MAXLEV + 2], ref_l[MAXLEV + 2];
+  std::vector<char> has_state;
+  bool profiling;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of the first of two events)
+  bool all_ready() const {
+    for (char h : has_state)
+      if (!h) return false;
+    return true;
+  }
 };
 
 namespace {
 
-#define HIPCHK(x)                                      \
-  do {                                                 \
-    if ((x) != hipSuccess) return MRLBM_ERR_HIP;       \
+#define HIPCHK(x)                                \
+  do {                                           \
+    if ((x) != hipSuccess) return MRLBM_ERR_HIP; \
   } while (0)
 
-template <typename T>
-Thresholds<T> thresholds(const mrlbm_ctx *c) {
-  Thresholds<T> t;
-  for (int l = 0; l < MAXLEV + 2; ++l) {
-    t.eps_l[l] = (T)c->eps_l[l];
-    t.ref_l[l] = (T)c->ref_l[l];
+enum { PH_TRANSPORT = 0, PH_RECON = 1, PH_ADAPT = 2 };
+
+// Start (begin = true) or end a timed phase: two events on the context stream.
+void phase_mark(mrlbm_ctx *c, int phase, bool begin) {
+  if (!c->profiling) return;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    c->ev_pool.push_back(e);
   }
-  return t;
+  if (begin) c->ev_marks.push_back({phase, c->ev_used});
+  hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
 }
 
-template <typename T>
-SchemeC<T> scheme_consts(const mrlbm_params &p) {
-  SchemeC<T> s;
-  s.lam = (T)p.lambda;
-  s.inv_lam = (T)(1.0 / p.lambda);
-  s.eq = (T)p.eq_param;
-  for (int i = 0; i < 9; ++i) s.s[i] = (T)p.s[i];
-  return s;
-}
-
-// Leaves / internal cells / ghosts of the mesh `code[m]` into lists[m], lvl[m].
-int compact(mrlbm_ctx *c, int m) {
-  const Geo &g = c->geo;
-  k_compact_count<<<dim3(c->L.nb), dim3(BLK), 0, c->stream>>>(g, c->code[m], c->bcnt);
-  k_compact_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(g, c->bcnt, c->boff, c->lvl[m]);
-  k_compact_scatter<<<dim3(c->L.nb), dim3(BLK), 0, c->stream>>>(g, c->code[m], c->boff, c->lists[m], (long long)c->L.total);
-  return MRLBM_OK;
-}
-
-// Codes (leaf / internal / ghost) of the membership array tnew into code[m].
-template <int DIM>
-int classify(mrlbm_ctx *c, int m) {
-  const Geo &g = c->geo;
-  k_classify_tree<DIM><<<dim3(grid_for(c->L.total)), dim3(BLK), 0, c->stream>>>(g, c->tnew, c->code[m]);
-  for (int l = g.jmax; l > g.jmin; --l)
-    k_classify_ghost<DIM><<<dim3(grid_for(1ll << (DIM * l))), dim3(BLK), 0, c->stream>>>(g, c->code[m], l);
-  return compact(c, m);
-}
-
-// Reconstruction on the mesh m inside buffer F: projections upward, ghost
-// predictions downward.
-template <int DIM, typename T>
-void reconstruct(mrlbm_ctx *c, T *F, int m) {
-  const Geo &g = c->geo;
-  for (int l = g.jmax - 1; l >= g.jmin; --l)
-    k_project<DIM, T><<<dim3(grid_for(1ll << (DIM * l), 1024)), dim3(BLK), 0, c->stream>>>(g, F, c->lists[m] + (size_t)CAT_INTERNAL * c->L.total, c->lvl[m], l);
-  for (int l = g.jmin + 1; l <= g.jmax; ++l)
-    k_ghost<DIM, T><<<dim3(grid_for(1ll << (DIM * l), 1024)), dim3(BLK), 0, c->stream>>>(g, F, c->lists[m] + (size_t)CAT_GHOST * c->L.total, c->lvl[m], l);
-}
+constexpr unsigned LIST_GRID_LEVEL = 1024, LIST_GRID_ALL = 2048, DENSE_GRID = 4096;
 
 template <int DIM, int SCHEME, typename T>
-int adapt_impl(mrlbm_ctx *c) {
-  const Geo &g = c->geo;
-  const int mo = c->mcur, mn = 1 - c->mcur;
-  T *Fc = (T *)c->F[c->cur];
-  T *Fn = (T *)c->F[1 - c->cur];
-  const long long tot = c->L.total;
-  reconstruct<DIM, T>(c, Fc, mo);
-  // keep and refg are adjacent byte arrays; clear both (256-byte aligned) with one fill
-  {
-    const long long n4 = (long long)(2 * align256((size_t)tot) / 4);
-    k_fill_u32<<<dim3(grid_for(n4)), dim3(BLK), 0, c->stream>>>((uint32_t *)c->keep, n4, 0u);
+struct Engine {
+  static constexpr int Q = Vel<SCHEME>::Q;
+  static constexpr unsigned QB = 64 * Q;
+
+  static const Inst<T> *I(mrlbm_ctx *c) { return (const Inst<T> *)c->inst; }
+  static unsigned chunks_level(mrlbm_ctx *c, int l) {  // capacity of the per-level lists in chunks
+    long long n = 0;
+    for (int i = 0; i < c->P.B; ++i)
+      if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (DIM * l)) + CHUNK - 1) / CHUNK;
+    return grid_cap(n, LIST_GRID_LEVEL);
   }
-  k_details<DIM, T><<<dim3(grid_for(tot)), dim3(BLK), 0, c->stream>>>(g, Fc, c->lists[mo] + (size_t)CAT_INTERNAL * tot, c->lvl[mo], thresholds<T>(c), c->keep, c->refg);
-  for (int l = g.jmax; l >= g.jmin + 2; --l)
-    k_ancestor<DIM><<<dim3(grid_for(1ll << (DIM * (l - 2)))), dim3(BLK), 0, c->stream>>>(g, c->keep, l);
-  k_enlarge<DIM, SCHEME><<<dim3(grid_for(tot)), dim3(BLK), 0, c->stream>>>(g, c->keep, c->refg, c->tnew);
-  for (int l = g.jmax; l >= g.jmin + 1; --l)
-    k_grade<DIM><<<dim3(grid_for(1ll << (DIM * (l - 1)))), dim3(BLK), 0, c->stream>>>(g, c->tnew, l);
-  classify<DIM>(c, mn);
-  k_transfer<DIM, T><<<dim3(grid_for(tot)), dim3(BLK), 0, c->stream>>>(g, Fc, Fn, c->code[mo], c->lists[mn] + (size_t)CAT_LEAF * tot, c->lvl[mn]);
-  c->mcur = mn;
-  c->cur = 1 - c->cur;
-  return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
-}
+  static unsigned chunks_all(mrlbm_ctx *c) { return grid_cap((c->P.ctotal + CHUNK - 1) / CHUNK, LIST_GRID_ALL); }
 
-template <int DIM, int SCHEME, typename T>
-int transport_impl(mrlbm_ctx *c) {
-  const Geo &g = c->geo;
-  const int m = c->mcur;
-  T *Fc = (T *)c->F[c->cur];
-  T *Fn = (T *)c->F[1 - c->cur];
-  reconstruct<DIM, T>(c, Fc, m);
-  k_transport_collide<DIM, SCHEME, T><<<dim3(grid_for(c->L.total)), dim3(BLK), 0, c->stream>>>(g, Fc, Fn, c->code[m], c->lists[m] + (size_t)CAT_LEAF * c->L.total, c->lvl[m], (const T *)c->W, (const T *)c->C, scheme_consts<T>(c->p));
-  c->cur = 1 - c->cur;
-  return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
-}
+  static void compact(mrlbm_ctx *c, int m) {
+    const Plan &P = c->P;
+    k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->cbp, c->code[m], c->bcnt, P.nblocks);
+    k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks);
+    k_compact_scatter<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->cbp, c->code[m], c->boff,
+                                                                c->lists[m], P.nblocks);
+  }
 
-template <int DIM, int SCHEME, typename T>
-int init_impl(mrlbm_ctx *c, const void *mom) {
-  const Geo &g = c->geo;
-  T *F = (T *)c->F[c->cur];
-  k_init_equilibrium<DIM, SCHEME, T><<<dim3(grid_for(1ll << (DIM * g.jmax))), dim3(BLK), 0, c->stream>>>(g, F, (const T *)mom, scheme_consts<T>(c->p));
-  k_full_tree<<<dim3(grid_for(c->L.total)), dim3(BLK), 0, c->stream>>>(g, c->code[c->mcur]);
-  compact(c, c->mcur);
-  c->has_state = true;
-  return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
-}
+  // Codes (leaf / internal / ghost) of the membership array tnew into code[m].
+  static void classify(mrlbm_ctx *c, int m) {
+    const Plan &P = c->P;
+    k_classify_tree<DIM, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        c->bt, I(c), c->cb, c->tnew, c->code[m]);
+    for (int l = P.maxJ; l > P.jmin; --l) {
+      const int nb = P.dtab_total(0, l);
+      if (nb) k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dtab_row(c->dtab, 0, l), l);
+    }
+    compact(c, m);
+  }
 
-// Dispatch on (scheme, precision).
+  // Reconstruction on mesh m inside F: projections upward, ghost predictions downward.
+  static void reconstruct(mrlbm_ctx *c, T *F, int m) {
+    const Plan &P = c->P;
+    const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
+    const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
+    for (int l = P.maxJ - 1; l >= P.jmin; --l)
+      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, c->lvl[m], l);
+    for (int l = P.jmin + 1; l <= P.maxJ; ++l)
+      k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
+  }
+
+  static int adapt(mrlbm_ctx *c) {
+    const Plan &P = c->P;
+    const int mo = c->mcur, mn = 1 - c->mcur;
+    T *Fc = (T *)c->F[c->cur];
+    T *Fn = (T *)c->F[1 - c->cur];
+    phase_mark(c, PH_ADAPT, true);
+    reconstruct(c, Fc, mo);
+    {  // keep and refg are adjacent, 256-byte aligned byte arrays: clear both
+      const long long n4 = (long long)(2 * align256((size_t)P.ctotal) / 4);
+      k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>((uint32_t *)c->keep, n4, 0u);
+    }
+    k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
+        c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
+    for (int l = P.maxJ; l >= P.jmin + 2; --l) {
+      const int nb = P.dtab_total(2, l - 2);
+      if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dtab_row(c->dtab, 2, l - 2), l);
+    }
+    k_enlarge<DIM, SCHEME, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        c->bt, I(c), c->cb, c->keep, c->refg, c->tnew);
+    for (int l = P.maxJ; l >= P.jmin + 1; --l) {
+      const int nb = P.dtab_total(1, l - 1);
+      if (nb) k_grade<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dtab_row(c->dtab, 1, l - 1), l);
+    }
+    classify(c, mn);
+    k_transfer<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(c->bt, I(c), Fc, Fn, c->code[mo],
+                                                               c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn]);
+    phase_mark(c, PH_ADAPT, false);
+    c->mcur = mn;
+    c->cur = 1 - c->cur;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int transport(mrlbm_ctx *c) {
+    const Plan &P = c->P;
+    const int m = c->mcur;
+    T *Fc = (T *)c->F[c->cur];
+    T *Fn = (T *)c->F[1 - c->cur];
+    phase_mark(c, PH_RECON, true);
+    reconstruct(c, Fc, m);
+    phase_mark(c, PH_RECON, false);
+    phase_mark(c, PH_TRANSPORT, true);
+    k_transport_collide<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
+        c->bt, I(c), Fc, Fn, c->code[m], c->lists[m] + (size_t)CAT_LEAF * P.ctotal, c->lvl[m], (const T *)c->W,
+        (const T *)c->C, c->cnt);
+    phase_mark(c, PH_TRANSPORT, false);
+    c->cur = 1 - c->cur;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int init(mrlbm_ctx *c, int i, const void *mom) {
+    const Plan &P = c->P;
+    T *F = (T *)c->F[c->cur];
+    const long long nf = 1ll << (DIM * P.inst[i].jmax);
+    k_init_equilibrium<DIM, SCHEME, T><<<grid_cap((nf + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        I(c), i, F, (const T *)mom);
+    k_full_tree<T><<<grid_cap((P.inst[i].total + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(I(c), i,
+                                                                                                  c->code[c->mcur]);
+    compact(c, c->mcur);
+    c->has_state[i] = 1;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int mass(mrlbm_ctx *c) {
+    k_mass_partial<DIM, Q, T><<<dim3(RED_BLOCKS, c->P.B), BLK, 0, c->stream>>>(
+        c->bt, I(c), (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal, c->lvl[c->mcur],
+        c->red, c->bad);
+    return MRLBM_OK;
+  }
+
+  static int exportl(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) {
+    k_export<DIM, Q, T><<<grid_cap((c->P.inst[i].total + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        I(c), i, (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal, c->lvl[c->mcur], cells,
+        (T *)vals);
+    return MRLBM_OK;
+  }
+
+  static int upload_inst(mrlbm_ctx *c) {
+    std::vector<Inst<T>> v(c->P.B);
+    for (int i = 0; i < c->P.B; ++i) {
+      const Inst<double> &s = c->P.inst[i];
+      Inst<T> &d = v[i];
+      std::memset(&d, 0, sizeof d);
+      d.jmin = s.jmin;
+      d.jmax = s.jmax;
+      d.cbase = s.cbase;
+      d.total = s.total;
+      for (int l = 0; l < LVL_STRIDE; ++l) {
+        d.loff[l] = s.loff[l];
+        d.bstart[l] = s.bstart[l];
+        d.eps_l[l] = (T)s.eps_l[l];
+        d.ref_l[l] = (T)s.ref_l[l];
+      }
+      d.sc.lam = (T)s.sc.lam;
+      d.sc.inv_lam = (T)s.sc.inv_lam;
+      d.sc.eq = (T)s.sc.eq;
+      for (int k = 0; k < 9; ++k) d.sc.s[k] = (T)s.sc.s[k];
+    }
+    HIPCHK(hipMemcpy(c->inst, v.data(), sizeof(Inst<T>) * v.size(), hipMemcpyHostToDevice));
+    return MRLBM_OK;
+  }
+};
+
 template <template <int, int, typename> class Op, typename... A>
 int dispatch(mrlbm_ctx *c, A... a) {
-  const bool dbl = c->p.precision == 8;
-  switch (c->p.scheme) {
+  const bool dbl = c->p[0].precision == 8;
+  switch (c->p[0].scheme) {
     case MRLBM_D1Q2: return dbl ? Op<1, 1, double>::run(c, a...) : Op<1, 1, float>::run(c, a...);
     case MRLBM_D1Q3: return dbl ? Op<1, 2, double>::run(c, a...) : Op<1, 2, float>::run(c, a...);
     default: return dbl ? Op<2, 3, double>::run(c, a...) : Op<2, 3, float>::run(c, a...);
   }
 }
 template <int D, int S, typename T>
-struct AdaptOp { static int run(mrlbm_ctx *c) { return adapt_impl<D, S, T>(c); } };
+struct AdaptOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::adapt(c); } };
 template <int D, int S, typename T>
-struct TransportOp { static int run(mrlbm_ctx *c) { return transport_impl<D, S, T>(c); } };
+struct TransportOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::transport(c); } };
 template <int D, int S, typename T>
-struct InitOp { static int run(mrlbm_ctx *c, const void *m) { return init_impl<D, S, T>(c, m); } };
+struct InitOp { static int run(mrlbm_ctx *c, int i, const void *m) { return Engine<D, S, T>::init(c, i, m); } };
 template <int D, int S, typename T>
-struct ClassifyOp { static int run(mrlbm_ctx *c, int m) { return classify<D>(c, m); } };
+struct ClassifyOp { static int run(mrlbm_ctx *c, int m) { Engine<D, S, T>::classify(c, m); return MRLBM_OK; } };
 template <int D, int S, typename T>
-struct MassOp {
-  static int run(mrlbm_ctx *c, int) {
-    k_mass_partial<T><<<dim3(RED_BLOCKS), dim3(BLK), 0, c->stream>>>(c->geo, (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->L.total, c->lvl[c->mcur], c->red, c->bad);
-    return MRLBM_OK;
-  }
-};
+struct MassOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::mass(c); } };
 template <int D, int S, typename T>
 struct ExportOp {
-  static int run(mrlbm_ctx *c, uint32_t *cells, void *vals) {
-    k_export<T><<<dim3(grid_for(c->L.total)), dim3(BLK), 0, c->stream>>>(c->geo, (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->L.total, c->lvl[c->mcur], cells, (T *)vals);
-    return MRLBM_OK;
-  }
+  static int run(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) { return Engine<D, S, T>::exportl(c, i, cells, vals); }
 };
+template <int D, int S, typename T>
+struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::upload_inst(c); } };
 
-// Host check of a 0/1 tree: level jmin complete, sibling groups complete, every
-// tree cell's parent and prediction stencil present.
-bool tree_is_graded(const mrlbm_ctx *c, const uint8_t *t) {
-  const Geo &g = c->geo;
-  const int d = g.dim;
-  for (long long i = 0; i < (1ll << (d * g.jmin)); ++i)
-    if (!t[g.loff[g.jmin] + i]) return false;
-  for (int l = g.jmin + 1; l <= g.jmax; ++l) {
+// Host check of a 0/1 tree of instance i: level jmin complete, sibling groups
+// complete, every tree cell's parent and prediction stencil present.
+bool tree_is_graded(const mrlbm_ctx *c, int inst, const uint8_t *t) {
+  const Inst<double> &I = c->P.inst[inst];
+  const int d = c->P.dim;
+  auto at = [&](int l, long long k) { return t[I.loff[l] - I.cbase + k]; };
+  for (long long k = 0; k < (1ll << (d * I.jmin)); ++k)
+    if (!at(I.jmin, k)) return false;
+  for (int l = I.jmin + 1; l <= I.jmax; ++l) {
     const int np = 1 << (l - 1);
-    const uint8_t *tl = t + g.loff[l], *tp = t + g.loff[l - 1];
     for (int py = 0; py < (d == 2 ? np : 1); ++py)
       for (int px = 0; px < np; ++px) {
         int cnt = 0;
         for (int dy = 0; dy < (d == 2 ? 2 : 1); ++dy)
           for (int dx = 0; dx < 2; ++dx) {
             const long long ci = d == 2 ? (long long)(2 * px + dx) + ((long long)(2 * py + dy) << l) : 2 * px + dx;
-            cnt += tl[ci] ? 1 : 0;
+            cnt += at(l, ci) ? 1 : 0;
           }
         if (cnt == 0) continue;
         if (cnt != (1 << d)) return false;
@@ -357,12 +489,19 @@ bool tree_is_graded(const mrlbm_ctx *c, const uint8_t *t) {
           for (int a = -1; a <= 1; ++a) {
             const int x = (px + a) & (np - 1), y = (py + b) & (np - 1);
             const long long pi = d == 2 ? (long long)x + ((long long)y << (l - 1)) : x;
-            if (!tp[pi]) return false;
+            if (!at(l - 1, pi)) return false;
           }
       }
   }
   return true;
 }
+
+__global__ void k_membership(const uint8_t *__restrict__ code, uint8_t *__restrict__ t, long long n) {
+  for (long long i = blockIdx.x * (long long)BLK + threadIdx.x; i < n; i += (long long)gridDim.x * BLK)
+    t[i] = code[i] >= C_INTERNAL ? 1 : 0;
+}
+
+bool bad_instance(const mrlbm_ctx *c, int i) { return !c || i < 0 || i >= c->P.B; }
 
 }  // namespace
 
@@ -370,67 +509,73 @@ bool tree_is_graded(const mrlbm_ctx *c, const uint8_t *t) {
 
 extern "C" {
 
-int mrlbm_workspace_size(const mrlbm_params *p, size_t *bytes) {
+int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes) {
   if (!bytes) return MRLBM_ERR_INVALID;
-  const int rc = validate(p);
+  const int rc = validate(p, batch);
   if (rc) return rc;
-  Geo g;
-  Layout L;
-  make_geo(p, g, L);
-  *bytes = L.bytes;
+  Plan P;
+  make_plan(p, batch, P);
+  *bytes = P.bytes;
   return MRLBM_OK;
 }
 
-int mrlbm_create(const mrlbm_params *p, void *workspace, size_t ws_bytes, void *stream, mrlbm_ctx **out) {
+int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream, mrlbm_ctx **out) {
   if (!out || !workspace) return MRLBM_ERR_INVALID;
   *out = nullptr;
-  const int rc = validate(p);
+  const int rc = validate(p, batch);
   if (rc) return rc;
   mrlbm_ctx *c = new (std::nothrow) mrlbm_ctx();
   if (!c) return MRLBM_ERR_INVALID;
-  c->p = *p;
-  make_geo(p, c->geo, c->L);
-  if (ws_bytes < c->L.bytes) { delete c; return MRLBM_ERR_CAPACITY; }
+  c->p.assign(p, p + batch);
+  make_plan(p, batch, c->P);
+  const Plan &P = c->P;
+  if (ws_bytes < P.bytes) { delete c; return MRLBM_ERR_CAPACITY; }
+  c->bt.B = P.B;
+  c->bt.dim = P.dim;
+  c->bt.q = P.q;
+  c->bt.jmin = P.jmin;
+  c->bt.maxJ = P.maxJ;
+  c->bt.ctotal = P.ctotal;
   c->stream = (hipStream_t)stream;
   char *b = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-  c->base = b;
-  const Layout &L = c->L;
   for (int k = 0; k < 2; ++k) {
-    c->F[k] = b + L.off_F[k];
-    c->code[k] = (uint8_t *)(b + L.off_code[k]);
-    c->lists[k] = (uint32_t *)(b + L.off_lists[k]);
-    c->lvl[k] = (int *)(b + L.off_lvl[k]);
+    c->F[k] = b + P.off_F[k];
+    c->code[k] = (uint8_t *)(b + P.off_code[k]);
+    c->lists[k] = (uint32_t *)(b + P.off_lists[k]);
+    c->lvl[k] = (int *)(b + P.off_lvl[k]);
   }
-  c->keep = (uint8_t *)(b + L.off_keep);
-  c->refg = (uint8_t *)(b + L.off_refg);
-  c->tnew = (uint8_t *)(b + L.off_tnew);
-  c->bcnt = (int *)(b + L.off_bcnt);
-  c->boff = (int *)(b + L.off_boff);
-  c->W = b + L.off_W;
-  c->C = b + L.off_C;
-  c->red = (double *)(b + L.off_red);
-  c->bad = (int *)(b + L.off_bad);
+  c->keep = (uint8_t *)(b + P.off_keep);
+  c->refg = (uint8_t *)(b + P.off_refg);
+  c->tnew = (uint8_t *)(b + P.off_tnew);
+  c->bcnt = (int *)(b + P.off_bcnt);
+  c->boff = (int *)(b + P.off_boff);
+  c->W = b + P.off_W;
+  c->C = b + P.off_C;
+  c->red = (double *)(b + P.off_red);
+  c->bad = (int *)(b + P.off_bad);
+  c->cnt = (unsigned long long *)(b + P.off_cnt);
+  c->inst = b + P.off_inst;
+  c->cb = (long long *)(b + P.off_cb);
+  c->cbp = (int *)(b + P.off_cbp);
+  c->dtab = (int *)(b + P.off_dtab);
   c->cur = 0;
   c->mcur = 0;
-  c->has_state = false;
-  const int d = c->geo.dim;
-  for (int l = 0; l < MAXLEV + 2; ++l) {
-    c->eps_l[l] = std::ldexp(p->eps, d * (l - p->jmax));
-    c->ref_l[l] = std::ldexp(c->eps_l[l], d) * std::exp2(p->mu_bar);
-  }
+  c->has_state.assign(P.B, 0);
+  c->profiling = false;
+  c->ev_used = 0;
   // transport weight tables, rounded once to the working precision
-  const int q = L.q, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
-  const int nn = std::max(1, L.nmax);
+  const int q = P.q, d = P.dim, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
+  const int nn = std::max(1, P.nmax);
   std::vector<double> W((size_t)nn * q * ws, 0.0), C((size_t)nn * q * cs, 0.0), w25(q * 25), c36(q * 36);
-  for (int n = 1; n <= L.nmax; ++n) {
-    transport_tables(p->scheme, n, w25.data(), c36.data());
+  for (int n = 1; n <= P.nmax; ++n) {
+    transport_tables(p[0].scheme, n, w25.data(), c36.data());
     for (int h = 0; h < q; ++h) {
       for (int k = 0; k < ws; ++k) W[((size_t)(n - 1) * q + h) * ws + k] = d == 2 ? w25[h * 25 + k] : w25[h * 25 + 10 + k];
       for (int k = 0; k < cs; ++k) C[((size_t)(n - 1) * q + h) * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
     }
   }
   hipError_t e;
-  if (p->precision == 8) {
+  if (P.rs == 8) {
     e = hipMemcpy(c->W, W.data(), W.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->C, C.data(), C.size() * 8, hipMemcpyHostToDevice);
   } else {
@@ -438,31 +583,36 @@ int mrlbm_create(const mrlbm_params *p, void *workspace, size_t ws_bytes, void *
     e = hipMemcpy(c->W, Wf.data(), Wf.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->C, Cf.data(), Cf.size() * 4, hipMemcpyHostToDevice);
   }
-  if (e != hipSuccess) { delete c; return MRLBM_ERR_HIP; }
+  if (e == hipSuccess) e = hipMemcpy(c->cb, P.cb.data(), sizeof(long long) * P.cb.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->cbp, P.cbp.data(), sizeof(int) * P.cbp.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->dtab, P.dtab.data(), sizeof(int) * P.dtab.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
+  if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) { delete c; return MRLBM_ERR_HIP; }
   *out = c;
   return MRLBM_OK;
 }
 
-int mrlbm_init_equilibrium(mrlbm_ctx *c, const void *moments) {
-  if (!c || !moments) return MRLBM_ERR_INVALID;
-  return dispatch<InitOp>(c, moments);
+int mrlbm_init_equilibrium(mrlbm_ctx *c, int instance, const void *moments) {
+  if (bad_instance(c, instance) || !moments) return MRLBM_ERR_INVALID;
+  return dispatch<InitOp>(c, instance, moments);
 }
 
 int mrlbm_adapt(mrlbm_ctx *c) {
   if (!c) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
+  if (!c->all_ready()) return MRLBM_ERR_STATE;
   return dispatch<AdaptOp>(c);
 }
 
 int mrlbm_transport_collide(mrlbm_ctx *c) {
   if (!c) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
+  if (!c->all_ready()) return MRLBM_ERR_STATE;
   return dispatch<TransportOp>(c);
 }
 
 int mrlbm_step(mrlbm_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
+  if (!c->all_ready()) return MRLBM_ERR_STATE;
   for (int s = 0; s < nsteps; ++s) {
     int rc = dispatch<AdaptOp>(c);
     if (rc) return rc;
@@ -472,83 +622,123 @@ int mrlbm_step(mrlbm_ctx *c, int nsteps) {
   return MRLBM_OK;
 }
 
-int mrlbm_get_state(mrlbm_ctx *c, uint8_t *tree, void *values) {
-  if (!c || !tree || !values) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
-  const long long tot = c->L.total;
+int mrlbm_get_state(mrlbm_ctx *c, int instance, uint8_t *tree, void *values) {
+  if (bad_instance(c, instance) || !tree || !values) return MRLBM_ERR_INVALID;
+  if (!c->has_state[instance]) return MRLBM_ERR_STATE;
+  const Inst<double> &I = c->P.inst[instance];
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(tree, c->code[c->mcur], tot, hipMemcpyDeviceToHost));
-  for (long long i = 0; i < tot; ++i) tree[i] = tree[i] >= C_INTERNAL ? 1 : 0;
-  HIPCHK(hipMemcpy(values, c->F[c->cur], c->L.rs * c->L.q * tot, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(tree, c->code[c->mcur] + I.cbase, I.total, hipMemcpyDeviceToHost));
+  for (long long k = 0; k < I.total; ++k) tree[k] = tree[k] >= C_INTERNAL ? 1 : 0;
+  HIPCHK(hipMemcpy(values, (char *)c->F[c->cur] + c->P.rs * c->P.q * I.cbase, c->P.rs * c->P.q * I.total,
+                   hipMemcpyDeviceToHost));
   return MRLBM_OK;
 }
 
-int mrlbm_set_state(mrlbm_ctx *c, const uint8_t *tree, const void *values) {
-  if (!c || !tree || !values) return MRLBM_ERR_INVALID;
-  if (!tree_is_graded(c, tree)) return MRLBM_ERR_INVALID;
-  const long long tot = c->L.total;
+int mrlbm_set_state(mrlbm_ctx *c, int instance, const uint8_t *tree, const void *values) {
+  if (bad_instance(c, instance) || !tree || !values) return MRLBM_ERR_INVALID;
+  if (!tree_is_graded(c, instance, tree)) return MRLBM_ERR_INVALID;
+  const Inst<double> &I = c->P.inst[instance];
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(c->tnew, tree, tot, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->F[c->cur], values, c->L.rs * c->L.q * tot, hipMemcpyHostToDevice));
+  k_membership<<<grid_cap((c->P.ctotal + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(c->code[c->mcur], c->tnew,
+                                                                                          c->P.ctotal);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->tnew + I.cbase, tree, I.total, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((char *)c->F[c->cur] + c->P.rs * c->P.q * I.cbase, values, c->P.rs * c->P.q * I.total,
+                   hipMemcpyHostToDevice));
   int rc = dispatch<ClassifyOp>(c, c->mcur);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
-  c->has_state = true;
+  c->has_state[instance] = 1;
   return MRLBM_OK;
 }
 
-int mrlbm_sizes(const mrlbm_ctx *c, int64_t *total_cells, int *q) {
-  if (!c) return MRLBM_ERR_INVALID;
-  if (total_cells) *total_cells = c->L.total;
-  if (q) *q = c->L.q;
+int mrlbm_sizes(const mrlbm_ctx *c, int instance, int64_t *total_cells, int *q) {
+  if (!c || instance < 0 || instance >= c->P.B) return MRLBM_ERR_INVALID;
+  if (total_cells) *total_cells = c->P.inst[instance].total;
+  if (q) *q = c->P.q;
   return MRLBM_OK;
 }
 
-int mrlbm_stats(mrlbm_ctx *c, double *mass, int64_t *leaves, int64_t *internal, int64_t *ghosts) {
-  if (!c) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
-  int lvl[NCAT * LVL_STRIDE];
+int mrlbm_stats(mrlbm_ctx *c, int instance, double *mass, int64_t *leaves, int64_t *internal, int64_t *ghosts) {
+  if (bad_instance(c, instance)) return MRLBM_ERR_INVALID;
+  if (!c->has_state[instance]) return MRLBM_ERR_STATE;
+  const Inst<double> &I = c->P.inst[instance];
   int rc = MRLBM_OK;
   if (mass) {
-    HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
-    dispatch<MassOp>(c, 0);
-    double part[RED_BLOCKS];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemset(c->bad, 0, sizeof(int)));
+    dispatch<MassOp>(c);
+    std::vector<double> part(RED_BLOCKS * c->P.B);
     int bad = 0;
     HIPCHK(hipStreamSynchronize(c->stream));
-    HIPCHK(hipMemcpy(part, c->red, sizeof part, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(part.data(), c->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost));
     double s = 0.0;
-    for (int i = 0; i < RED_BLOCKS; ++i) s += part[i];
+    for (int k = 0; k < RED_BLOCKS; ++k) s += part[instance * RED_BLOCKS + k];
     *mass = s;
     if (bad) rc = MRLBM_ERR_NONFINITE;
   }
+  int lvl[NCAT * LVL_STRIDE];
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur], sizeof lvl, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur] + instance * NCAT * LVL_STRIDE, sizeof lvl, hipMemcpyDeviceToHost));
   int64_t *outs[NCAT] = {leaves, internal, ghosts};
   for (int k = 0; k < NCAT; ++k) {
     if (!outs[k]) continue;
-    for (int l = 0; l <= c->p.jmax; ++l)
-      outs[k][l] = l < c->p.jmin ? 0 : lvl[k * LVL_STRIDE + l + 1] - lvl[k * LVL_STRIDE + l];
+    for (int l = 0; l <= I.jmax; ++l)
+      outs[k][l] = l < I.jmin ? 0 : lvl[k * LVL_STRIDE + l + 1] - lvl[k * LVL_STRIDE + l];
   }
   return rc;
 }
 
-int mrlbm_leaves(mrlbm_ctx *c, uint32_t *cells, void *values, int64_t capacity, int64_t *count) {
-  if (!c || !count) return MRLBM_ERR_INVALID;
-  if (!c->has_state) return MRLBM_ERR_STATE;
-  int lvl[NCAT * LVL_STRIDE];
+int mrlbm_leaves(mrlbm_ctx *c, int instance, uint32_t *cells, void *values, int64_t capacity, int64_t *count) {
+  if (bad_instance(c, instance) || !count) return MRLBM_ERR_INVALID;
+  if (!c->has_state[instance]) return MRLBM_ERR_STATE;
+  const Inst<double> &I = c->P.inst[instance];
+  int lvl[LVL_STRIDE];
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur], sizeof lvl, hipMemcpyDeviceToHost));
-  const int64_t n = lvl[CAT_LEAF * LVL_STRIDE + c->p.jmax + 1] - lvl[CAT_LEAF * LVL_STRIDE + c->p.jmin];
+  HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur] + (instance * NCAT + CAT_LEAF) * LVL_STRIDE, sizeof lvl,
+                   hipMemcpyDeviceToHost));
+  const int64_t n = lvl[I.jmax + 1] - lvl[I.jmin];
   *count = n;
   if (capacity < n) return MRLBM_ERR_CAPACITY;
   if (!cells || !values) return MRLBM_ERR_INVALID;
-  dispatch<ExportOp>(c, cells, values);
+  dispatch<ExportOp>(c, instance, cells, values);
   HIPCHK(hipStreamSynchronize(c->stream));
   return MRLBM_OK;
 }
 
+int mrlbm_profile(mrlbm_ctx *c, int enable) {
+  if (!c) return MRLBM_ERR_INVALID;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long)));
+  c->profiling = enable != 0;
+  c->ev_used = 0;
+  c->ev_marks.clear();
+  return MRLBM_OK;
+}
+
+int mrlbm_read_counters(mrlbm_ctx *c, mrlbm_counters *out) {
+  if (!c || !out) return MRLBM_ERR_INVALID;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  unsigned long long cnt[4];
+  HIPCHK(hipMemcpy(cnt, c->cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->leaf_updates = cnt[0];
+  out->transport_launches = cnt[1];
+  for (const auto &m : c->ev_marks) {
+    float ms = 0.f;
+    if (m.second + 1 >= c->ev_used) continue;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
+    if (m.first == PH_TRANSPORT) { out->transport_ms += ms; out->timed_launches++; }
+    else if (m.first == PH_RECON) out->reconstruct_ms += ms;
+    else out->adapt_ms += ms;
+  }
+  return MRLBM_OK;
+}
+
 int mrlbm_destroy(mrlbm_ctx *c) {
+  if (c)
+    for (auto e : c->ev_pool) hipEventDestroy(e);
   delete c;
   return MRLBM_OK;
 }

@@ -21,7 +21,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-fini
           -4: "HIP runtime error", -5: "call out of order"}
 EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mrlbm_adapt",
            "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
-           "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables"]
+           "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
+           "mrlbm_profile", "mrlbm_read_counters"]
 
 
 class MrlbmError(RuntimeError):
@@ -43,6 +44,12 @@ class Params(ctypes.Structure):
                    float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s))
 
 
+class Counters(ctypes.Structure):
+    _fields_ = [("leaf_updates", ctypes.c_uint64), ("transport_launches", ctypes.c_uint64),
+                ("transport_ms", ctypes.c_double), ("reconstruct_ms", ctypes.c_double),
+                ("adapt_ms", ctypes.c_double), ("timed_launches", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -55,15 +62,17 @@ def lib() -> ctypes.CDLL:
                                "(or __graft_entry__.build()) first" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+        ci = ctypes.c_int
         sig = {
-            "mrlbm_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
-            "mrlbm_create": [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
-            "mrlbm_init_equilibrium": [vp, vp], "mrlbm_adapt": [vp], "mrlbm_transport_collide": [vp],
-            "mrlbm_step": [vp, ctypes.c_int], "mrlbm_get_state": [vp, vp, vp], "mrlbm_set_state": [vp, vp, vp],
-            "mrlbm_sizes": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
-            "mrlbm_stats": [vp, ctypes.POINTER(ctypes.c_double), vp, vp, vp],
-            "mrlbm_leaves": [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+            "mrlbm_workspace_size": [P, ci, ctypes.POINTER(ctypes.c_size_t)],
+            "mrlbm_create": [P, ci, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+            "mrlbm_init_equilibrium": [vp, ci, vp], "mrlbm_adapt": [vp], "mrlbm_transport_collide": [vp],
+            "mrlbm_step": [vp, ci], "mrlbm_get_state": [vp, ci, vp, vp], "mrlbm_set_state": [vp, ci, vp, vp],
+            "mrlbm_sizes": [vp, ci, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
+            "mrlbm_stats": [vp, ci, ctypes.POINTER(ctypes.c_double), vp, vp, vp],
+            "mrlbm_leaves": [vp, ci, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
             "mrlbm_destroy": [vp], "mrlbm_transport_tables": [ctypes.c_int, ctypes.c_int, vp, vp],
+            "mrlbm_profile": [vp, ctypes.c_int], "mrlbm_read_counters": [vp, ctypes.POINTER(Counters)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -90,38 +99,42 @@ def transport_tables(scheme: str, n: int):
     return W, C
 
 
-class Sim:
-    """One MR-LBM instance on a GPU. ``cfg`` is a parameter dictionary of
-    ``workloads``; ``precision`` is 8 (FP64) or 4 (FP32)."""
+class Batch:
+    """A batch of independent MR-LBM instances advanced together on one GPU.
+    ``cfgs`` are parameter dictionaries of ``workloads`` sharing the scheme and
+    jmin; ``precision`` is 8 (FP64) or 4 (FP32)."""
 
-    def __init__(self, cfg: dict, precision: int = 8, device: str = "cuda:0"):
+    def __init__(self, cfgs, precision: int = 8, device: str = "cuda:0"):
         import torch
 
         self.torch = torch
-        self.cfg = dict(cfg)
+        self.cfgs = [dict(c) for c in cfgs]
+        self.B = len(self.cfgs)
         self.precision = int(precision)
-        self.dim, self.q, self.nc = SCHEME_DIMS[cfg["scheme"]]
-        self.jmin, self.jmax = int(cfg["jmin"]), int(cfg["jmax"])
+        self.dim, self.q, self.nc = SCHEME_DIMS[self.cfgs[0]["scheme"]]
         self.device = torch.device(device)
         self.dtype = torch.float64 if precision == 8 else torch.float32
         self.np_dtype = np.float64 if precision == 8 else np.float32
         L = lib()
-        self._p = Params.from_cfg(cfg, precision)
+        self._p = (Params * self.B)(*[Params.from_cfg(c, precision) for c in self.cfgs])
         nbytes = ctypes.c_size_t(0)
-        _check("mrlbm_workspace_size", L.mrlbm_workspace_size(ctypes.byref(self._p), ctypes.byref(nbytes)))
+        _check("mrlbm_workspace_size", L.mrlbm_workspace_size(self._p, self.B, ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p(0)
-        _check("mrlbm_create", L.mrlbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.workspace.data_ptr()),
+        _check("mrlbm_create", L.mrlbm_create(self._p, self.B, ctypes.c_void_p(self.workspace.data_ptr()),
                                               self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream),
                                               ctypes.byref(ctx)))
         self._ctx = ctx
-        tot = ctypes.c_int64(0)
-        q = ctypes.c_int(0)
-        _check("mrlbm_sizes", L.mrlbm_sizes(ctx, ctypes.byref(tot), ctypes.byref(q)))
-        self.total_cells = int(tot.value)
+        self.total_cells = []
+        for i in range(self.B):
+            tot = ctypes.c_int64(0)
+            q = ctypes.c_int(0)
+            _check("mrlbm_sizes", L.mrlbm_sizes(ctx, i, ctypes.byref(tot), ctypes.byref(q)))
+            self.total_cells.append(int(tot.value))
+        self._keep = []
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -135,12 +148,12 @@ class Sim:
             pass
 
     # ---- time stepping
-    def init_equilibrium(self, m0):
+    def init_equilibrium(self, i: int, m0):
         t = self.torch
         m = t.as_tensor(np.ascontiguousarray(m0), dtype=self.dtype).to(self.device).contiguous()
-        assert m.numel() == self.nc * (1 << (self.dim * self.jmax))
-        self._m0 = m  # kept alive until the asynchronous kernel has read it
-        _check("mrlbm_init_equilibrium", lib().mrlbm_init_equilibrium(self._ctx, ctypes.c_void_p(m.data_ptr())))
+        assert m.numel() == self.nc * (1 << (self.dim * int(self.cfgs[i]["jmax"])))
+        self._keep.append(m)  # kept alive until the asynchronous kernel has read it
+        _check("mrlbm_init_equilibrium", lib().mrlbm_init_equilibrium(self._ctx, int(i), ctypes.c_void_p(m.data_ptr())))
 
     def step(self, n: int = 1):
         _check("mrlbm_step", lib().mrlbm_step(self._ctx, int(n)))
@@ -153,38 +166,72 @@ class Sim:
 
     def synchronize(self):
         self.stream.synchronize()
+        self._keep.clear()
+
+    # ---- measurement
+    def profile(self, enable: bool = True):
+        _check("mrlbm_profile", lib().mrlbm_profile(self._ctx, int(bool(enable))))
+
+    def counters(self) -> dict:
+        c = Counters()
+        _check("mrlbm_read_counters", lib().mrlbm_read_counters(self._ctx, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in Counters._fields_}
 
     # ---- state exchange (host arrays in the layouts of include/mrlbm.h)
-    def get_state(self):
-        tree = np.zeros(self.total_cells, np.uint8)
-        values = np.zeros(self.q * self.total_cells, self.np_dtype)
-        _check("mrlbm_get_state", lib().mrlbm_get_state(self._ctx, tree.ctypes.data, values.ctypes.data))
+    def get_state(self, i: int):
+        tree = np.zeros(self.total_cells[i], np.uint8)
+        values = np.zeros(self.q * self.total_cells[i], self.np_dtype)
+        _check("mrlbm_get_state", lib().mrlbm_get_state(self._ctx, int(i), tree.ctypes.data, values.ctypes.data))
         return tree, values
 
-    def set_state(self, tree, values):
+    def set_state(self, i: int, tree, values):
         tree = np.ascontiguousarray(tree, dtype=np.uint8)
         values = np.ascontiguousarray(values, dtype=self.np_dtype)
-        assert tree.size == self.total_cells and values.size == self.q * self.total_cells
-        _check("mrlbm_set_state", lib().mrlbm_set_state(self._ctx, tree.ctypes.data, values.ctypes.data))
+        assert tree.size == self.total_cells[i] and values.size == self.q * self.total_cells[i]
+        _check("mrlbm_set_state", lib().mrlbm_set_state(self._ctx, int(i), tree.ctypes.data, values.ctypes.data))
 
-    def stats(self):
+    def stats(self, i: int):
         mass = ctypes.c_double(0.0)
-        n = self.jmax + 1
+        n = int(self.cfgs[i]["jmax"]) + 1
         leaves, internal, ghosts = (np.zeros(n, np.int64) for _ in range(3))
-        _check("mrlbm_stats", lib().mrlbm_stats(self._ctx, ctypes.byref(mass), leaves.ctypes.data,
+        _check("mrlbm_stats", lib().mrlbm_stats(self._ctx, int(i), ctypes.byref(mass), leaves.ctypes.data,
                                                 internal.ctypes.data, ghosts.ctypes.data))
         return dict(mass=float(mass.value), leaves=leaves, internal=internal, ghosts=ghosts)
 
-    def leaves(self):
-        """(cells uint32 tensor of (level << 26) | cell, values [n][q] tensor) on the device."""
+    def leaves(self, i: int):
+        """(cells int32 tensor of (level << 26) | cell, values [n][q] tensor) on the device."""
         t = self.torch
         count = ctypes.c_int64(0)
-        rc = lib().mrlbm_leaves(self._ctx, None, None, 0, ctypes.byref(count))
+        rc = lib().mrlbm_leaves(self._ctx, int(i), None, None, 0, ctypes.byref(count))
         if rc not in (0, -2):
             _check("mrlbm_leaves", rc)
         n = int(count.value)
         cells = t.empty(max(n, 1), dtype=t.int32, device=self.device)
         vals = t.empty((max(n, 1), self.q), dtype=self.dtype, device=self.device)
-        _check("mrlbm_leaves", lib().mrlbm_leaves(self._ctx, ctypes.c_void_p(cells.data_ptr()),
+        _check("mrlbm_leaves", lib().mrlbm_leaves(self._ctx, int(i), ctypes.c_void_p(cells.data_ptr()),
                                                   ctypes.c_void_p(vals.data_ptr()), n, ctypes.byref(count)))
         return cells[:n], vals[:n]
+
+
+class Sim(Batch):
+    """A single MR-LBM instance (a batch of one)."""
+
+    def __init__(self, cfg: dict, precision: int = 8, device: str = "cuda:0"):
+        super().__init__([cfg], precision, device)
+        self.cfg = self.cfgs[0]
+        self.jmin, self.jmax = int(cfg["jmin"]), int(cfg["jmax"])
+
+    def init_equilibrium(self, m0):
+        super().init_equilibrium(0, m0)
+
+    def get_state(self):
+        return super().get_state(0)
+
+    def set_state(self, tree, values):
+        super().set_state(0, tree, values)
+
+    def stats(self):
+        return super().stats(0)
+
+    def leaves(self):
+        return super().leaves(0)

@@ -34,7 +34,7 @@ def _wsize(**kw):
     cfg.update(kw)
     p = mrlbm.Params.from_cfg(cfg, kw.pop("precision", 8))
     n = ctypes.c_size_t(0)
-    return mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)), n.value
+    return mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)), n.value
 
 
 def test_workspace_size_and_parameter_validation():
@@ -47,17 +47,34 @@ def test_workspace_size_and_parameter_validation():
     assert _wsize(s=[0.1] + [0.0] * 8)[0] == -1   # a conserved moment must not relax
     p = mrlbm.Params.from_cfg(W.params("D1Q2", 2, 5, 1e-3, [0, 1.9]), 16)
     n = ctypes.c_size_t(0)
-    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == -1
+
+
+def test_batch_validation():
+    a = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8)), 4)
+    b = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 9, 1e-4, W.d2q9_s(1.5, 1.9)), 4)
+    arr = (mrlbm.Params * 2)(a, b)
+    n = ctypes.c_size_t(0)
+    assert mrlbm.lib().mrlbm_workspace_size(arr, 2, ctypes.byref(n)) == 0
+    one = ctypes.c_size_t(0)
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(b), 1, ctypes.byref(one)) == 0
+    assert n.value > one.value
+    c = mrlbm.Params.from_cfg(W.params("D2Q9", 2, 7, 1e-3, W.d2q9_s(1.5, 1.8)), 4)   # other jmin
+    assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, c), 2, ctypes.byref(n)) == -1
+    d = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8)), 8)   # other precision
+    assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, d), 2, ctypes.byref(n)) == -1
+    assert mrlbm.lib().mrlbm_workspace_size(arr, 0, ctypes.byref(n)) == -1
+    assert mrlbm.lib().mrlbm_workspace_size(arr, 257, ctypes.byref(n)) == -1
 
 
 def test_create_rejects_small_workspace_without_touching_it():
     cfg = W.params("D1Q2", 2, 5, 1e-3, [0, 1.9])
     p = mrlbm.Params.from_cfg(cfg, 8)
     n = ctypes.c_size_t(0)
-    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == 0
     buf = ctypes.create_string_buffer(16)
     ctx = ctypes.c_void_p(0)
-    rc = mrlbm.lib().mrlbm_create(ctypes.byref(p), ctypes.cast(buf, ctypes.c_void_p), 16, None, ctypes.byref(ctx))
+    rc = mrlbm.lib().mrlbm_create(ctypes.byref(p), 1, ctypes.cast(buf, ctypes.c_void_p), 16, None, ctypes.byref(ctx))
     assert rc == -2 and not ctx.value
 
 
