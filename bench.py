@@ -26,22 +26,32 @@ KERNEL_SOURCES = ["paper_2103_02903_amd/csrc/mr_kernels.h", "paper_2103_02903_am
 
 
 def workload(name: str):
+    """(list of (cfg, m0), description, default precision in bytes)."""
     from paper_2103_02903_amd import workloads as W
 
     if name == "d2q9_shear_1024":
-        cfg, m0 = W.shear_layer_d2q9()  # levels 3..10, eps 1e-3, Re 1e4, width 1/80
+        items = [W.shear_layer_d2q9()]  # levels 3..10, eps 1e-3, Re 1e4, width 1/80
         desc = "D2Q9 MRT double shear layer, periodic unit square, levels 3..10 (1024^2 finest), gamma=1, " \
                "eps=1e-3, mu_bar=1, Re=1e4, U0=0.1, tanh width 1/80, seeded 0.05 sinusoidal perturbation"
+        prec = 8
+    elif name == "d2q9_shear_batch96":
+        items = W.shear_layer_batch(96)
+        desc = "96 independent D2Q9 MRT double shear layers, levels 3..J with J drawn in {7,8,9,10}, " \
+               "eps drawn in {1e-2,1e-3,1e-4}, Re uniform in [1e3,3e4], seeded perturbations; one launch " \
+               "sequence per step for all instances"
+        prec = 4
     elif name == "d1q3_burgers_16384":
-        cfg, m0 = W.burgers_d1q3()
+        items = [W.burgers_d1q3()]
         desc = "D1Q3 inviscid Burgers, periodic [-1,1], levels 2..14 (16384 finest), gamma=1, eps=1e-4, " \
                "s=1.5, 8 seeded random-amplitude sines"
+        prec = 8
     elif name == "d1q2_advection_1024":
-        cfg, m0 = W.advection_d1q2()
+        items = [W.advection_d1q2()]
         desc = "D1Q2 advection at Courant 1, periodic [-1,1], levels 2..10, gamma=1, eps=1e-4, s=1.9"
+        prec = 8
     else:
         raise SystemExit("unknown workload %s" % name)
-    return cfg, m0, desc
+    return items, desc, prec
 
 
 def kernel_source_hash() -> str:
@@ -95,7 +105,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="d2q9_shear_1024")
-    ap.add_argument("--precision", type=int, default=8, choices=[4, 8])
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 4, 8], help="0: the workload's default")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -112,12 +122,16 @@ def main():
         from paper_2103_02903_amd import build as hip_build
 
         hip_build.build(force=False)
-    cfg, m0, desc = workload(args.workload)
-    sim = mrlbm.Sim(cfg, precision=args.precision)
-    sim.init_equilibrium(m0)
+    items, desc, prec = workload(args.workload)
+    precision = args.precision or prec
+    sim = mrlbm.Batch([c for c, _ in items], precision=precision)
+    for i, (_, m0) in enumerate(items):
+        sim.init_equilibrium(i, m0)
     sim.step(args.warmup)
     sim.synchronize()
-    state0 = None if args.no_cpu_baseline else sim.get_state()
+    # the CPU baseline steps the largest instance from its state at the start of the timed region
+    big = max(range(len(items)), key=lambda i: items[i][0]["jmax"])
+    state0 = None if args.no_cpu_baseline else sim.get_state(big)
 
     sim.profile(True)
     stream = sim.stream
@@ -129,9 +143,9 @@ def main():
     torch.cuda.synchronize()
     elapsed_ms = t_start.elapsed_time(t_end)
     cnt = sim.counters()
-    st = sim.stats()
+    stats = [sim.stats(i) for i in range(sim.B)]
 
-    q, rs = sim.q, args.precision
+    q, rs = sim.q, precision
     leaf_updates = int(cnt["leaf_updates"])
     value = leaf_updates / (elapsed_ms * 1e-3)
     bytes_per_leaf = 2 * q * rs  # read q populations, write q (neighbours are cache reuse)
@@ -139,8 +153,8 @@ def main():
     avg_ms = cnt["transport_ms"] / launches
     bytes_per_launch = leaf_updates * bytes_per_leaf / max(1, int(cnt["transport_launches"]))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    finest = 1 << (sim.dim * sim.jmax)
-    leaves_now = int(st["leaves"].sum())
+    finest = sum(1 << (sim.dim * int(c["jmax"])) for c, _ in items)
+    leaves_now = sum(int(st["leaves"].sum()) for st in stats)
     out = {
         "metric": METRIC,
         "value": value,
@@ -152,9 +166,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 8 else "f32",
+        "dtype": "f64" if precision == 8 else "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "name": args.workload, "precision": "fp%d" % (8 * args.precision)},
+        "config": {"workload": desc, "name": args.workload, "precision": "fp%d" % (8 * precision),
+                   "instances": sim.B},
         "roofline": {
             "kernel": "k_transport_collide",
             "bound": "hbm",
@@ -162,7 +177,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.precision),
+            "traffic": measured_traffic(args.workload, precision),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
         },
@@ -172,10 +187,13 @@ def main():
         "phase_ms_per_step": {"adapt": cnt["adapt_ms"] / args.steps, "reconstruct": cnt["reconstruct_ms"] / args.steps,
                               "transport_collide": cnt["transport_ms"] / args.steps},
         "transport_kernel_leaf_updates_per_s": leaf_updates / (cnt["transport_ms"] * 1e-3),
-        "mass_final": st["mass"],
+        "mass_final": sum(st["mass"] for st in stats),
     }
     if state0 is not None:
-        out["cpu_baseline"] = cpu_baseline(cfg, state0[0], state0[1], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(items[big][0], state0[0], state0[1], args.cpu_seconds)
+        if sim.B > 1:
+            out["cpu_baseline"]["sample"] += " (instance %d of %d, levels %d..%d)" % (
+                big, sim.B, items[big][0]["jmin"], items[big][0]["jmax"])
     print(json.dumps(out))
 
 

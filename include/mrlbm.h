@@ -83,8 +83,11 @@ int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes);
 /* Create a context inside `workspace` (device memory, >= mrlbm_workspace_size
  * bytes, 256-byte aligned) that enqueues its work on `stream` (a hipStream_t,
  * NULL = the default stream). Uploads the parameter-dependent tables; does not
- * set an initial state. Errors: MRLBM_ERR_INVALID, MRLBM_ERR_CAPACITY,
- * MRLBM_ERR_HIP. */
+ * set an initial state. The environment variable MRLBM_TRANSPORT=leaf|pop, read
+ * here, forces one of the two transport kernels (one thread per leaf, or one
+ * wavefront per population; they give bit-identical results), which are
+ * otherwise chosen by problem size. Errors: MRLBM_ERR_INVALID,
+ * MRLBM_ERR_CAPACITY, MRLBM_ERR_HIP. */
 int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream,
                  mrlbm_ctx **out);
 

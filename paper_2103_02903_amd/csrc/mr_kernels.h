@@ -18,6 +18,8 @@ namespace mrlbm {
 constexpr int BLK = 256;
 constexpr int MAXB = 256;  // instances per batch
 constexpr int CHUNK = 64;  // list items per chunk (one per lane)
+constexpr int CITER = 4;   // cells per thread of an all-level dense pass
+constexpr int CCHUNK = BLK * CITER;
 
 // ---------------------------------------------------------------- list segments
 // Per-instance list segments of one category: of one level (l >= 0) or of all
@@ -161,11 +163,21 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
   }
 }
 
-// Block -> (instance, first cell) of a dense pass over one level per instance.
-template <typename T>
-__device__ __forceinline__ int dense_block(const int *__restrict__ row, int B, int &i) {
-  i = upper_index(row, B, blockIdx.x);
-  return (blockIdx.x - row[i]) * BLK + threadIdx.x;
+// Block -> (instance, first cell) of a dense pass over one level per instance:
+// one static info word per block, instance | (chunk << 8).
+__device__ __forceinline__ long long dense_block(const uint32_t *__restrict__ info, int &i) {
+  const uint32_t w = info[blockIdx.x];
+  i = (int)(w & 0xffu);
+  return (long long)(w >> 8) * BLK + threadIdx.x;
+}
+
+// Block of an all-level dense pass: CCHUNK cells of one (instance, level), from
+// one static info word instance | (level << 8) | (chunk << 13).
+__device__ __forceinline__ void chunk_block(const uint32_t *__restrict__ binfo, int &i, int &l, long long &base) {
+  const uint32_t w = binfo[blockIdx.x];
+  i = (int)(w & 0xffu);
+  l = (int)((w >> 8) & 0x1fu);
+  base = (long long)(w >> 13) * CCHUNK;
 }
 
 // Ancestor closure of the thresholded set: the group of the parent of every kept
@@ -173,9 +185,9 @@ __device__ __forceinline__ int dense_block(const int *__restrict__ row, int B, i
 // grandchildren are read).
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
-                                                  const int *__restrict__ row, int l) {
+                                                  const uint32_t *__restrict__ info, int l) {
   int i;
-  const long long cell = dense_block<T>(row, bt.B, i);
+  const long long cell = dense_block(info, i);
   const int lg = l - 2;
   if (cell >= ncells_d(DIM, lg)) return;
   const uint8_t *kl = keep + I[i].loff[l];
@@ -200,19 +212,24 @@ __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__res
 // Level jmin is always complete. One thread per cell of every instance.
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__restrict__ I,
-                                                 const long long *__restrict__ cb, const uint8_t *__restrict__ keep,
+                                                 const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ keep,
                                                  const uint8_t *__restrict__ refg, uint8_t *__restrict__ tnew) {
-  for (long long gc = blockIdx.x * (long long)BLK + threadIdx.x; gc < bt.ctotal; gc += (long long)gridDim.x * BLK) {
-    const int i = upper_index(cb, bt.B, gc);
-    const Inst<T> &In = I[i];
-    int l = In.jmin;
-    while (l < In.jmax && gc >= In.loff[l + 1]) ++l;
-    const uint32_t c = (uint32_t)(gc - In.loff[l]);
+  int i, l;
+  long long base;
+  chunk_block(binfo, i, l, base);
+  const Inst<T> &In = I[i];
+  const long long nl = ncells_d(DIM, l);
+  const uint8_t *kl = keep + In.loff[l];
+  const uint8_t *rg = l >= In.jmin + 2 ? refg + In.loff[l - 2] : nullptr;
+  uint8_t *tl = tnew + In.loff[l];
+#pragma unroll
+  for (int it = 0; it < CITER; ++it) {
+    const long long c = base + it * BLK + threadIdx.x;
+    if (c >= nl) continue;
     uint8_t v = 1;
     if (l > In.jmin) {
       int x, y;
-      coords<DIM>(l, c, x, y);
-      const uint8_t *kl = keep + In.loff[l];
+      coords<DIM>(l, (uint32_t)c, x, y);
       v = kl[c];
 #pragma unroll
       for (int h = 0; h < Vel<SCHEME>::Q; ++h) {
@@ -220,9 +237,9 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
         if (ex == 0 && ey == 0) continue;
         v |= kl[cidx<DIM>(l, wrapl(x + ex, l), wrapl(y + ey, l))];
       }
-      if (l >= In.jmin + 2) v |= refg[In.loff[l - 2] + cidx<DIM>(l - 2, x >> 2, y >> 2)];
+      if (rg) v |= rg[cidx<DIM>(l - 2, x >> 2, y >> 2)];
     }
-    tnew[gc] = v ? 1 : 0;
+    tl[c] = v ? 1 : 0;
   }
 }
 
@@ -231,9 +248,9 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
 // tree cell joins the tree. One thread per cell of level l-1.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
-                                               const int *__restrict__ row, int l) {
+                                               const uint32_t *__restrict__ info, int l) {
   int i;
-  const long long cell = dense_block<T>(row, bt.B, i);
+  const long long cell = dense_block(info, i);
   const int lp = l - 1;
   if (cell >= ncells_d(DIM, lp)) return;
   uint8_t *tl = tnew + I[i].loff[l];
@@ -259,52 +276,93 @@ __global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restri
 // Codes of the tree cells of a 0/1 membership array: leaf or internal.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *__restrict__ I,
-                                                       const long long *__restrict__ cb,
+                                                       const uint32_t *__restrict__ binfo,
                                                        const uint8_t *__restrict__ tnew, uint8_t *__restrict__ code) {
-  for (long long gc = blockIdx.x * (long long)BLK + threadIdx.x; gc < bt.ctotal; gc += (long long)gridDim.x * BLK) {
+  int i, l;
+  long long base;
+  chunk_block(binfo, i, l, base);
+  const Inst<T> &In = I[i];
+  const long long nl = ncells_d(DIM, l);
+  const uint8_t *tl = tnew + In.loff[l];
+  const uint8_t *tf = l < In.jmax ? tnew + In.loff[l + 1] : nullptr;
+  uint8_t *cl = code + In.loff[l];
+#pragma unroll
+  for (int it = 0; it < CITER; ++it) {
+    const long long c = base + it * BLK + threadIdx.x;
+    if (c >= nl) continue;
     uint8_t v = C_NONE;
-    if (tnew[gc]) {
-      const int i = upper_index(cb, bt.B, gc);
-      const Inst<T> &In = I[i];
-      int l = In.jmin;
-      while (l < In.jmax && gc >= In.loff[l + 1]) ++l;
+    if (tl[c]) {
       v = C_LEAF;
-      if (l < In.jmax) {
+      if (tf) {
         int x, y;
-        coords<DIM>(l, (uint32_t)(gc - In.loff[l]), x, y);
-        if (tnew[In.loff[l + 1] + cidx<DIM>(l + 1, 2 * x, 2 * y)]) v = C_INTERNAL;
+        coords<DIM>(l, (uint32_t)c, x, y);
+        if (tf[cidx<DIM>(l + 1, 2 * x, 2 * y)]) v = C_INTERNAL;
       }
     }
-    code[gc] = v;
+    cl[c] = v;
   }
+}
+
+// Four consecutive codes starting at p (byte loads if p is not 4-byte aligned).
+__device__ __forceinline__ uint32_t load4(const uint8_t *__restrict__ p) {
+  if (((uintptr_t)p & 3u) == 0) return *reinterpret_cast<const uint32_t *>(p);
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+// Bit j set where byte j of w equals v.
+__device__ __forceinline__ uint32_t byte_eq_mask(uint32_t w, uint32_t v) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) m |= (((w >> (8 * j)) & 0xffu) == v ? 1u : 0u) << j;
+  return m;
 }
 
 // Ghost cells of level l (run from the finest level down): a cell outside the
 // tree is a ghost if a leaf of its own level lies in its 5^d box (transport and
 // transfer stencils), or if it lies in the 3^d parent box of a ghost of level
-// l+1 (prediction of that ghost).
+// l+1 (prediction of that ghost). Each thread classifies 4 consecutive cells of
+// a row (level l >= 2) from aligned 4-cell words of the rows around them.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> *__restrict__ I,
-                                                        uint8_t *__restrict__ code, const int *__restrict__ row,
+                                                        uint8_t *__restrict__ code, const uint32_t *__restrict__ info,
                                                         int l) {
-  int i;
-  const long long cell = dense_block<T>(row, bt.B, i);
-  if (cell >= ncells_d(DIM, l)) return;
+  const uint32_t w = info[blockIdx.x];
+  const int i = (int)(w & 0xffu);
+  const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
+  if (c0 >= ncells_d(DIM, l)) return;
   uint8_t *cl = code + I[i].loff[l];
-  if (cl[cell] != C_NONE) return;
-  int x, y;
-  coords<DIM>(l, (uint32_t)cell, x, y);
-  bool need = false;
-  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0) && !need; ++b)
-    for (int a = -2; a <= 2; ++a)
-      need |= cl[cidx<DIM>(l, wrapl(x + a, l), DIM == 2 ? wrapl(y + b, l) : 0)] == C_LEAF;
-  if (!need && l < I[i].jmax) {
-    const uint8_t *cf = code + I[i].loff[l + 1];
-    for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 3 : 0) && !need; ++b)
-      for (int a = -2; a <= 3; ++a)
-        need |= cf[cidx<DIM>(l + 1, wrapl(2 * x + a, l + 1), DIM == 2 ? wrapl(2 * y + b, l + 1) : 0)] == C_GHOST;
+  const uint32_t own = load4(cl + c0);
+  if (byte_eq_mask(own, C_NONE) == 0) return;
+  int x0, y;
+  coords<DIM>(l, (uint32_t)c0, x0, y);
+  const int nw = (1 << l) >> 2;  // words per row of level l
+  const int k = x0 >> 2;
+  // leaves of level l: columns x0-4 .. x0+7 (three words) of rows y-2 .. y+2
+  uint32_t leafm = 0;
+  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b) {
+    const uint8_t *row = cl + (DIM == 2 ? ((long long)wrapl(y + b, l) << l) : 0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) leafm |= byte_eq_mask(load4(row + 4 * ((k - 1 + j + nw) % nw)), C_LEAF) << (4 * j);
   }
-  if (need) cl[cell] = C_GHOST;
+  // ghosts of level l+1: columns 2x0-4 .. 2x0+11 (four words) of rows 2y-2 .. 2y+3
+  uint32_t ghostm = 0;
+  if (l < I[i].jmax) {
+    const uint8_t *cf = code + I[i].loff[l + 1];
+    const int lf = l + 1, nwf = 2 * nw;
+    for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 3 : 0); ++b) {
+      const uint8_t *row = cf + (DIM == 2 ? ((long long)wrapl(2 * y + b, lf) << lf) : 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        ghostm |= byte_eq_mask(load4(row + 4 * ((2 * k - 1 + j + nwf) % nwf)), C_GHOST) << (4 * j);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (((own >> (8 * t)) & 0xffu) != C_NONE) continue;
+    // cell x0+t: leaf columns x0+t-2 .. x0+t+2 -> bits t+2 .. t+6; ghost columns
+    // 2(x0+t)-2 .. 2(x0+t)+3 -> bits 2t+2 .. 2t+7
+    const bool need = ((leafm >> (t + 2)) & 0x1fu) || ((ghostm >> (2 * t + 2)) & 0x3fu);
+    if (need) cl[c0 + t] = C_GHOST;
+  }
 }
 
 // Codes of the initial full finest mesh of instance i: internal below jmax,
@@ -327,39 +385,29 @@ __global__ void __launch_bounds__(BLK) k_fill_u32(uint32_t *__restrict__ p, long
 // Lists of leaves, internal cells and ghosts in (instance, level, cell) order:
 // per-block counts, one exclusive scan per instance, then a scatter with
 // wavefront ballots.
-constexpr int CITER = 4;
-constexpr int CCHUNK = BLK * CITER;
-
 __device__ __forceinline__ int cat_of(uint8_t v) {
   return v == C_LEAF ? CAT_LEAF : v == C_INTERNAL ? CAT_INTERNAL : v == C_GHOST ? CAT_GHOST : -1;
 }
 
-template <typename T>
-__device__ __forceinline__ void compact_block(const Inst<T> *__restrict__ I, const int *__restrict__ cbp, int B, int b,
-                                              int &i, int &l, long long &base) {
-  i = upper_index(cbp, B, b);
-  const Inst<T> &In = I[i];
-  l = In.jmin;
-  while (l < In.jmax && b >= In.bstart[l + 1]) ++l;
-  base = (long long)(b - In.bstart[l]) * CCHUNK;
-}
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_count(Batch bt, const Inst<T> *__restrict__ I,
-                                                       const int *__restrict__ cbp, const uint8_t *__restrict__ code,
+                                                       const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                        int *__restrict__ bcnt, int nblocks) {
   __shared__ int cnt[NCAT];
   int i, l;
   long long base;
-  compact_block(I, cbp, bt.B, blockIdx.x, i, l, base);
+  chunk_block(binfo, i, l, base);
   const long long nl = ncells_d(DIM, l);
   if (threadIdx.x < NCAT) cnt[threadIdx.x] = 0;
   __syncthreads();
+  const long long c0 = base + 4 * threadIdx.x;
   int mine[NCAT] = {0, 0, 0};
-  for (int it = 0; it < CITER; ++it) {
-    const long long c = base + it * BLK + threadIdx.x;
-    if (c < nl) {
-      const int k = cat_of(code[I[i].loff[l] + c]);
+  if (c0 < nl) {
+    const uint32_t w = load4(code + I[i].loff[l] + c0);
+    const int valid = nl - c0 >= 4 ? 4 : (int)(nl - c0);
+    for (int t = 0; t < valid; ++t) {
+      const int k = cat_of((uint8_t)(w >> (8 * t)));
       if (k >= 0) mine[k]++;
     }
   }
@@ -412,38 +460,46 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T> *__restrict__ I,
-                                                         const int *__restrict__ cbp, const uint8_t *__restrict__ code,
+                                                         const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                          const int *__restrict__ boff, uint32_t *__restrict__ lists,
                                                          int nblocks) {
-  __shared__ int wcnt[NCAT][BLK / 64];
+  __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
-  compact_block(I, cbp, bt.B, blockIdx.x, i, l, base);
+  chunk_block(binfo, i, l, base);
   const long long nl = ncells_d(DIM, l);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  int off[NCAT];
-  for (int k = 0; k < NCAT; ++k) off[k] = boff[k * nblocks + blockIdx.x];
-  for (int it = 0; it < CITER; ++it) {
-    const long long c = base + it * BLK + threadIdx.x;
-    const int k = c < nl ? cat_of(code[I[i].loff[l] + c]) : -1;
-    int rank[NCAT];
-    for (int kk = 0; kk < NCAT; ++kk) {
-      const unsigned long long m = __ballot(k == kk);
-      rank[kk] = __popcll(m & lt);
-      if (lane == 0) wcnt[kk][wave] = __popcll(m);
+  const long long c0 = base + 4 * threadIdx.x;
+  uint32_t w = 0;
+  int valid = 0;
+  if (c0 < nl) {
+    w = load4(code + I[i].loff[l] + c0);
+    valid = nl - c0 >= 4 ? 4 : (int)(nl - c0);
+  }
+  int cnt[NCAT] = {0, 0, 0}, incl[NCAT];
+  for (int t = 0; t < valid; ++t) {
+    const int k = cat_of((uint8_t)(w >> (8 * t)));
+    if (k >= 0) cnt[k]++;
+  }
+  for (int k = 0; k < NCAT; ++k) {  // inclusive scan over the wavefront
+    int v = cnt[k];
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
     }
-    __syncthreads();
-    for (int kk = 0; kk < NCAT; ++kk) {
-      int before = 0, tot = 0;
-      for (int w = 0; w < BLK / 64; ++w) {
-        before += w < wave ? wcnt[kk][w] : 0;
-        tot += wcnt[kk][w];
-      }
-      if (k == kk) lists[kk * bt.ctotal + off[kk] + before + rank[kk]] = ((uint32_t)l << LEVEL_SHIFT) | (uint32_t)c;
-      off[kk] += tot;
-    }
-    __syncthreads();
+    incl[k] = v;
+    if (lane == 63) wsum[k][wave] = v;
+  }
+  __syncthreads();
+  int pos[NCAT];
+  for (int k = 0; k < NCAT; ++k) {
+    int before = 0;
+    for (int ww = 0; ww < wave; ++ww) before += wsum[k][ww];
+    pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - cnt[k];
+  }
+  for (int t = 0; t < valid; ++t) {
+    const int k = cat_of((uint8_t)(w >> (8 * t)));
+    if (k >= 0) lists[k * bt.ctotal + pos[k]++] = ((uint32_t)l << LEVEL_SHIFT) | (uint32_t)(c0 + t);
   }
 }
 
@@ -484,19 +540,88 @@ __global__ void __launch_bounds__(64 * Q) k_transfer(Batch bt, const Inst<T> *__
 // level's 5^d neighbourhood with the flattened weights W[n][h]
 // (eq. PredictionWithMatrixNew), plus, for every neighbour refined one level
 // further, its children's details weighted by C[n][h]. Finest leaves stream by
-// the plain shift f(k - eta). Wavefront h transports population h of 64 leaves;
-// the collision of each leaf then runs in wavefront 0 through LDS.
+// the plain shift f(k - eta).
+//
+// Population h of the leaf (l, c): Fl / Ff point at population h of levels l and
+// l+1, cl at the codes of level l, W / Cw at the weights of (n, h).
+template <int DIM, int SCHEME, typename T>
+__device__ __forceinline__ T transport_pop(int h, int l, int J, uint32_t c, int x, int y, const T *__restrict__ Fl,
+                                           const T *__restrict__ Ff, const uint8_t *__restrict__ cl,
+                                           const T *__restrict__ W, const T *__restrict__ Cw, unsigned nbr) {
+  using V = Vel<SCHEME>;
+  const int ex = V::ex(h), ey = V::ey(h);
+  const int n = J - l;
+  if (ex == 0 && ey == 0) return Fl[c];
+  if (n == 0) return Fl[cidx<DIM>(J, wrapl(x - ex, J), wrapl(y - ey, J))];
+  T acc = T(0);
+  if (DIM == 1) {
+#pragma unroll
+    for (int a = -2; a <= 2; ++a) acc = fma(W[a + 2], Fl[wrapl(x + a, l)], acc);
+  } else if (ey == 0) {  // x-axis velocity: the y sums collapse on the leaf's row
+    const long long row = (long long)y << l;
+#pragma unroll
+    for (int a = -2; a <= 2; ++a) acc = fma(W[10 + a + 2], Fl[row + wrapl(x + a, l)], acc);
+  } else if (ex == 0) {  // y-axis velocity: the leaf's column
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) acc = fma(W[(b + 2) * 5 + 2], Fl[((long long)wrapl(y + b, l) << l) + x], acc);
+  } else {
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) {
+      const long long row = (long long)wrapl(y + b, l) << l;
+#pragma unroll
+      for (int a = -2; a <= 2; ++a) acc = fma(W[(b + 2) * 5 + a + 2], Fl[row + wrapl(x + a, l)], acc);
+    }
+  }
+  if (nbr) {  // neighbours refined one level further: their children's details
+    for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
+      for (int a = -1; a <= 1; ++a) {
+        if (a == 0 && b == 0) continue;
+        const int k = bit++;
+        if (!(nbr & (1u << k))) continue;
+        const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
+        ParentStencil<DIM, T> st;
+        st.load(Fl, l, px, py);
+        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
+            const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
+            acc = fma(Cw[y2 * 6 + y1], d, acc);
+          }
+      }
+  }
+  return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
+}
+
+// Bit k (over the 3^d - 1 neighbours, x fastest) set if that neighbour of (x, y)
+// at level l is an internal cell.
+template <int DIM>
+__device__ __forceinline__ unsigned refined_neighbours(const uint8_t *__restrict__ cl, int l, int x, int y) {
+  unsigned nbr = 0;
+  for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if (a == 0 && b == 0) continue;
+      if (cl[cidx<DIM>(l, wrapl(x + a, l), DIM == 2 ? wrapl(y + b, l) : 0)] == C_INTERNAL) nbr |= 1u << bit;
+      ++bit;
+    }
+  return nbr;
+}
+
+// Variant for small leaf sets: wavefront h transports population h of 64 leaves
+// (nine times the parallelism), the collision of each leaf then runs in
+// wavefront 0 through LDS.
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
-    k_transport_collide(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
-                        const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
-                        const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                        unsigned long long *__restrict__ counters) {
+    k_transport_collide_pop(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
+                            const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
+                            const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
+                            unsigned long long *__restrict__ counters) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q;
   constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
   __shared__ SegLDS s;
   __shared__ T fl[Q][64];
+  __shared__ long long sloff[LVL_STRIDE];
+  __shared__ int sjmax;
   load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     unsigned long long tot = 0;
@@ -505,81 +630,88 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     atomicAdd(&counters[1], 1ull);
   }
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ex = V::ex(h), ey = V::ey(h);
   for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     const bool valid = item < s.cnt[i];
-    const Inst<T> &In = I[i];
-    int l = 0, x = 0, y = 0;
-    uint32_t c = 0;
+    const uint32_t e = valid ? leaves[s.beg[i] + item] : 0u;
+    if (threadIdx.x < LVL_STRIDE) sloff[threadIdx.x] = I[i].loff[threadIdx.x];
+    if (threadIdx.x == 0) sjmax = I[i].jmax;
+    __syncthreads();
+    const int l = (int)(e >> LEVEL_SHIFT);
+    const uint32_t c = e & CELL_MASK;
     if (valid) {
-      const uint32_t e = leaves[s.beg[i] + item];
-      l = (int)(e >> LEVEL_SHIFT);
-      c = e & CELL_MASK;
+      int x, y;
       coords<DIM>(l, c, x, y);
-      const int J = In.jmax, n = J - l;
-      const T *Fl = Fs + foff(In, DIM, Q, l, h);
-      T f = Fl[c];
-      if (ex != 0 || ey != 0) {
-        if (n == 0) {
-          f = Fl[cidx<DIM>(J, wrapl(x - ex, J), wrapl(y - ey, J))];
-        } else {
-          const T *W = Wt + ((long long)(n - 1) * Q + h) * WS;
-          T acc = T(0);
-          if (DIM == 1) {
-#pragma unroll
-            for (int a = -2; a <= 2; ++a) acc = fma(W[a + 2], Fl[wrapl(x + a, l)], acc);
-          } else if (ey == 0) {  // x-axis velocity: the y sums collapse on the leaf's row
-            const long long row = (long long)y << l;
-#pragma unroll
-            for (int a = -2; a <= 2; ++a) acc = fma(W[10 + a + 2], Fl[row + wrapl(x + a, l)], acc);
-          } else if (ex == 0) {  // y-axis velocity: the leaf's column
-#pragma unroll
-            for (int b = -2; b <= 2; ++b) acc = fma(W[(b + 2) * 5 + 2], Fl[((long long)wrapl(y + b, l) << l) + x], acc);
-          } else {
-#pragma unroll
-            for (int b = -2; b <= 2; ++b) {
-              const long long row = (long long)wrapl(y + b, l) << l;
-#pragma unroll
-              for (int a = -2; a <= 2; ++a) acc = fma(W[(b + 2) * 5 + a + 2], Fl[row + wrapl(x + a, l)], acc);
-            }
-          }
-          // neighbours refined one level further: their children's details
-          const uint8_t *cl = code + In.loff[l];
-          const T *Cw = Ct + ((long long)(n - 1) * Q + h) * CS;
-          const T *Ff = Fs + foff(In, DIM, Q, l + 1, h);
-          for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
-            for (int a = -1; a <= 1; ++a) {
-              if (a == 0 && b == 0) continue;
-              const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
-              if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
-              ParentStencil<DIM, T> st;
-              st.load(Fl, l, px, py);
-              for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                  const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
-                  const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
-                  acc = fma(Cw[y2 * 6 + y1], d, acc);
-                }
-            }
-          f = fma((T)ldexp(1.0, -DIM * n), acc, f);
-        }
-      }
-      fl[h][lane] = f;
+      const int J = sjmax, n = J - l;
+      const uint8_t *cl = code + sloff[l];
+      const unsigned nbr = n > 0 ? refined_neighbours<DIM>(cl, l, x, y) : 0u;
+      const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
+      const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
+      const int nn = n > 0 ? n - 1 : 0;
+      fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
+                                                  Ct + ((long long)nn * Q + h) * CS, nbr);
     }
     __syncthreads();
     if (h == 0 && valid) {
       T g[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) g[k] = fl[k][lane];
-      collide<SCHEME, T>(g, In.sc);
+      collide<SCHEME, T>(g, I[i].sc);
 #pragma unroll
       for (int k = 0; k < Q; ++k) fl[k][lane] = g[k];
     }
     __syncthreads();
-    if (valid) Fo[foff(In, DIM, Q, l, h) + c] = fl[h][lane];
+    if (valid) Fo[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     __syncthreads();
+  }
+}
+
+// Variant for large leaf sets: one thread per leaf, all populations in
+// registers, no barriers; every wavefront takes a chunk of 64 leaves.
+template <int DIM, int SCHEME, typename T>
+__global__ void __launch_bounds__(BLK)
+    k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
+                             const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
+                             const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
+                             unsigned long long *__restrict__ counters) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q;
+  constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  constexpr int WPB = BLK / 64;
+  __shared__ SegLDS s;
+  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int i = 0; i < bt.B; ++i) tot += (unsigned long long)s.cnt[i];
+    atomicAdd(&counters[0], tot);
+    atomicAdd(&counters[1], 1ull);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int ch = blockIdx.x * WPB + wave; ch < s.pre[bt.B]; ch += gridDim.x * WPB) {
+    const int i = upper_index(s.pre, bt.B, ch);
+    const int item = (ch - s.pre[i]) * CHUNK + lane;
+    if (item >= s.cnt[i]) continue;
+    const Inst<T> &In = I[i];
+    const uint32_t e = leaves[s.beg[i] + item];
+    const int l = (int)(e >> LEVEL_SHIFT);
+    const uint32_t c = e & CELL_MASK;
+    int x, y;
+    coords<DIM>(l, c, x, y);
+    const int J = In.jmax, n = J - l;
+    const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
+    const uint8_t *cl = code + In.loff[l];
+    const unsigned nbr = n > 0 ? refined_neighbours<DIM>(cl, l, x, y) : 0u;
+    const long long of = n > 0 ? (long long)Q * In.loff[l + 1] : ol, nf = ncells_d(DIM, l + 1);
+    const int nn = n > 0 ? n - 1 : 0;
+    T f[Q];
+#pragma unroll
+    for (int h = 0; h < Q; ++h)
+      f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fs + ol + h * nl, Fs + of + h * nf, cl,
+                                           Wt + ((long long)nn * Q + h) * WS, Ct + ((long long)nn * Q + h) * CS, nbr);
+    collide<SCHEME, T>(f, In.sc);
+#pragma unroll
+    for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
   }
 }
 

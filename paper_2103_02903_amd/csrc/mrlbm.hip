@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -130,6 +131,10 @@ void transport_tables(int scheme, int n, double *W, double *C) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Cells per block of the dense per-level passes: ghost classification (off 0)
+// takes 4 cells per thread, grading (1) and ancestor closure (2) one.
+long long dense_cells(int off) { return off == 0 ? (long long)CCHUNK : (long long)BLK; }
+
 // Static description of a batch: instance descriptors (double-precision
 // thresholds; converted to the working precision on upload), block tables, and
 // the workspace layout.
@@ -141,10 +146,15 @@ struct Plan {
   std::vector<long long> cb;   // [B + 1] first cell of each instance
   std::vector<int> cbp;        // [B + 1] first compaction block of each instance
   std::vector<int> dtab;       // [3][LVL_STRIDE][B + 1] dense-level block prefixes
+  std::vector<uint32_t> binfo; // [nblocks] instance | level << 8 | chunk << 13 of all-level passes
+  std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
+  std::vector<long long> dstart;  // [3][LVL_STRIDE] first entry of each (off, L) row in dinfo
   size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_bcnt, off_boff, off_W,
-      off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, bytes;
+      off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
-  const int *dtab_row(const int *dev, int off, int L) const { return dev + ((size_t)off * LVL_STRIDE + L) * (B + 1); }
+  const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
+    return dev + dstart[(size_t)off * LVL_STRIDE + L];
+  }
 };
 
 void make_plan(const mrlbm_params *p, int B, Plan &P) {
@@ -191,6 +201,12 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   }
   P.cb[B] = cells;
   P.cbp[B] = blocks;
+  P.binfo.clear();
+  for (int i = 0; i < B; ++i)
+    for (int l = P.inst[i].jmin; l <= P.inst[i].jmax; ++l) {
+      const int nb = P.inst[i].bstart[l + 1] - P.inst[i].bstart[l];
+      for (int k = 0; k < nb; ++k) P.binfo.push_back((uint32_t)i | ((uint32_t)l << 8) | ((uint32_t)k << 13));
+    }
   P.ctotal = cells;
   P.nblocks = blocks;
   P.nmax = P.maxJ - P.jmin;
@@ -202,9 +218,20 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
       int acc = 0;
       for (int i = 0; i < B; ++i) {
         row[i] = acc;
-        if (L >= P.jmin && L <= P.inst[i].jmax - off) acc += (int)(((1ll << (P.dim * L)) + BLK - 1) / BLK);
+        if (L >= P.jmin && L <= P.inst[i].jmax - off) acc += (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
       }
       row[B] = acc;
+    }
+  P.dinfo.clear();
+  P.dstart.assign((size_t)3 * LVL_STRIDE, 0);
+  for (int off = 0; off < 3; ++off)
+    for (int L = 0; L < LVL_STRIDE; ++L) {
+      P.dstart[(size_t)off * LVL_STRIDE + L] = (long long)P.dinfo.size();
+      for (int i = 0; i < B; ++i)
+        if (L >= P.jmin && L <= P.inst[i].jmax - off) {
+          const int nb = (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
+          for (int k = 0; k < nb; ++k) P.dinfo.push_back((uint32_t)i | ((uint32_t)k << 8));
+        }
     }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -227,6 +254,8 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_cb = take(sizeof(long long) * (B + 1));
   P.off_cbp = take(sizeof(int) * (B + 1));
   P.off_dtab = take(sizeof(int) * P.dtab.size());
+  P.off_binfo = take(sizeof(uint32_t) * P.binfo.size());
+  P.off_dinfo = take(sizeof(uint32_t) * std::max<size_t>(1, P.dinfo.size()));
   P.bytes = o + 256;  // slack for aligning the base pointer
 }
 
@@ -255,9 +284,11 @@ struct mrlbm_ctx {
   void *inst;               // Inst<T>[B]
   long long *cb;
   int *cbp, *dtab;
+  uint32_t *binfo, *dinfo;
   int cur;   // F[cur] holds the state
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
   std::vector<char> has_state;
+  int transport_variant;  // 0: by size, 1: one thread per leaf, 2: one wavefront per population
   bool profiling;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
@@ -287,10 +318,14 @@ void phase_mark(mrlbm_ctx *c, int phase, bool begin) {
     c->ev_pool.push_back(e);
   }
   if (begin) c->ev_marks.push_back({phase, c->ev_used});
-  hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
+  (void)hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
 }
 
-constexpr unsigned LIST_GRID_LEVEL = 1024, LIST_GRID_ALL = 2048, DENSE_GRID = 4096;
+constexpr unsigned LIST_GRID_LEVEL = 1024, LIST_GRID_ALL = 4096, DENSE_GRID = 4096;
+// Above this many cells (all instances and levels) the transport runs one
+// thread per leaf; below, one wavefront per population (more parallelism for
+// small leaf sets). Both variants compute bit-identical results.
+constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
 
 template <int DIM, int SCHEME, typename T>
 struct Engine {
@@ -308,20 +343,19 @@ struct Engine {
 
   static void compact(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
-    k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->cbp, c->code[m], c->bcnt, P.nblocks);
+    k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks);
     k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks);
-    k_compact_scatter<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->cbp, c->code[m], c->boff,
+    k_compact_scatter<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
                                                                 c->lists[m], P.nblocks);
   }
 
   // Codes (leaf / internal / ghost) of the membership array tnew into code[m].
   static void classify(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
-    k_classify_tree<DIM, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
-        c->bt, I(c), c->cb, c->tnew, c->code[m]);
+    k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m]);
     for (int l = P.maxJ; l > P.jmin; --l) {
       const int nb = P.dtab_total(0, l);
-      if (nb) k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dtab_row(c->dtab, 0, l), l);
+      if (nb) k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l);
     }
     compact(c, m);
   }
@@ -352,13 +386,12 @@ struct Engine {
         c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
     for (int l = P.maxJ; l >= P.jmin + 2; --l) {
       const int nb = P.dtab_total(2, l - 2);
-      if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dtab_row(c->dtab, 2, l - 2), l);
+      if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);
     }
-    k_enlarge<DIM, SCHEME, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
-        c->bt, I(c), c->cb, c->keep, c->refg, c->tnew);
+    k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
     for (int l = P.maxJ; l >= P.jmin + 1; --l) {
       const int nb = P.dtab_total(1, l - 1);
-      if (nb) k_grade<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dtab_row(c->dtab, 1, l - 1), l);
+      if (nb) k_grade<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dinfo_row(c->dinfo, 1, l - 1), l);
     }
     classify(c, mn);
     k_transfer<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(c->bt, I(c), Fc, Fn, c->code[mo],
@@ -378,9 +411,15 @@ struct Engine {
     reconstruct(c, Fc, m);
     phase_mark(c, PH_RECON, false);
     phase_mark(c, PH_TRANSPORT, true);
-    k_transport_collide<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
-        c->bt, I(c), Fc, Fn, c->code[m], c->lists[m] + (size_t)CAT_LEAF * P.ctotal, c->lvl[m], (const T *)c->W,
-        (const T *)c->C, c->cnt);
+    const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
+    const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
+    if (per_leaf)
+      k_transport_collide_leaf<DIM, SCHEME, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, LIST_GRID_ALL), BLK, 0,
+                                                 c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
+                                                              (const T *)c->W, (const T *)c->C, c->cnt);
+    else
+      k_transport_collide_pop<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
+          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt);
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -558,11 +597,17 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->cb = (long long *)(b + P.off_cb);
   c->cbp = (int *)(b + P.off_cbp);
   c->dtab = (int *)(b + P.off_dtab);
+  c->binfo = (uint32_t *)(b + P.off_binfo);
+  c->dinfo = (uint32_t *)(b + P.off_dinfo);
   c->cur = 0;
   c->mcur = 0;
   c->has_state.assign(P.B, 0);
   c->profiling = false;
   c->ev_used = 0;
+  {
+    const char *v = std::getenv("MRLBM_TRANSPORT");
+    c->transport_variant = v && !std::strcmp(v, "leaf") ? 1 : v && !std::strcmp(v, "pop") ? 2 : 0;
+  }
   // transport weight tables, rounded once to the working precision
   const int q = P.q, d = P.dim, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
   const int nn = std::max(1, P.nmax);
@@ -586,6 +631,9 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   if (e == hipSuccess) e = hipMemcpy(c->cb, P.cb.data(), sizeof(long long) * P.cb.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->cbp, P.cbp.data(), sizeof(int) * P.cbp.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dtab, P.dtab.data(), sizeof(int) * P.dtab.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->binfo, P.binfo.data(), sizeof(uint32_t) * P.binfo.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.dinfo.empty())
+    e = hipMemcpy(c->dinfo, P.dinfo.data(), sizeof(uint32_t) * P.dinfo.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
   if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) { delete c; return MRLBM_ERR_HIP; }
@@ -738,7 +786,7 @@ int mrlbm_read_counters(mrlbm_ctx *c, mrlbm_counters *out) {
 
 int mrlbm_destroy(mrlbm_ctx *c) {
   if (c)
-    for (auto e : c->ev_pool) hipEventDestroy(e);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return MRLBM_OK;
 }

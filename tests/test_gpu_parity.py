@@ -242,3 +242,19 @@ def test_batch_instance_equals_single_run(mr):
         sim.step(15)
         a, b = bat.get_state(i), sim.get_state()
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_transport_variants_bit_identical(mr, monkeypatch):
+    """The per-leaf and per-population transport kernels compute the same bits."""
+    cfg, m0 = W.shear_layer_d2q9(jmin=3, jmax=8, eps=1e-4, re=1000.0, width=1.0 / 40)
+    out = {}
+    for v in ("leaf", "pop"):
+        monkeypatch.setenv("MRLBM_TRANSPORT", v)
+        for prec in (8, 4):
+            sim = mr.Sim(cfg, precision=prec)
+            sim.init_equilibrium(m0)
+            sim.step(12)
+            out[(v, prec)] = sim.get_state()
+    for prec in (8, 4):
+        a, b = out[("leaf", prec)], out[("pop", prec)]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
