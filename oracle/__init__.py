@@ -71,6 +71,8 @@ def lib():
                            ("orc_moment_matrix_inverse", [P, dp]), ("orc_leaf_counts", [P, u8, dp]),
                            ("orc_check_tree", [P, u8])]:
             f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
+        for name, args in [("orc_new_tree_f32", [P, u8, dp, u8, dp]), ("orc_step_frozen", [P, u8, u8, dp])]:
+            f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
         L.orc_predict.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_predict.restype = ctypes.c_double
         L.orc_collide_cell.argtypes = [P, dp]; L.orc_collide_cell.restype = None
@@ -151,6 +153,20 @@ class Oracle:
         """Mesh adaptation G(H(T(tree))) with details of the given leaf values."""
         dense = self.reconstruct(tree, values)
         return self.adapt_tree(tree, self.details(tree, dense))
+
+    def new_tree_f32(self, tree, values_f32, return_details=False):
+        """Mesh adaptation decided in single precision from float leaf values."""
+        tnew = np.zeros(self.total, np.uint8)
+        v = np.ascontiguousarray(values_f32, dtype=np.float32)
+        D = np.empty(self.total, np.float64)
+        self._chk(self.L.orc_new_tree_f32(ctypes.byref(self.p), _ptr(tree), _ptr(v), _ptr(tnew), _ptr(D)))
+        return (tnew, D) if return_details else tnew
+
+    def step_frozen(self, tree, tnew, values):
+        """One step on the given new mesh (in place)."""
+        self._chk(self.L.orc_step_frozen(ctypes.byref(self.p), _ptr(tree), _ptr(np.ascontiguousarray(tnew)),
+                                         _ptr(values)))
+        return tree, values
 
     def transfer(self, told, dense_old, tnew):
         vnew = np.zeros(self.q * self.total, np.float64)

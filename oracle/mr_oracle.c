@@ -294,7 +294,25 @@ static void mark_group(const orc_params *P, uint8_t *tl, int l, int gx, int gy) 
   for (int sigma = 0; sigma < nchildren(P); ++sigma) tl[child_index(P, l - 1, gx, gy, sigma)] = 1;
 }
 
+/* Thresholds eps_l = 2^{d(l-J)} eps and 2^{mu_bar + d} eps_l, indexed by level. */
+static void thresholds(const orc_params *P, double *eps_l, double *ref_l) {
+  for (int l = 0; l <= P->jmax; ++l) {
+    eps_l[l] = ldexp(P->eps, P->dim * (l - P->jmax));
+    ref_l[l] = ldexp(eps_l[l], P->dim) * exp2(P->mu_bar);
+  }
+}
+
+static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double *D, const double *eps_lv,
+                          const double *ref_lv, uint8_t *tnew);
+
 int orc_adapt_tree(const orc_params *P, const uint8_t *told, const double *D, uint8_t *tnew) {
+  double eps_l[64], ref_l[64];
+  thresholds(P, eps_l, ref_l);
+  return adapt_tree_thr(P, told, D, eps_l, ref_l, tnew);
+}
+
+static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double *D, const double *eps_lv,
+                          const double *ref_lv, uint8_t *tnew) {
   const int J = P->jmax, jmin = P->jmin, d = P->dim;
   const int64_t total = orc_total_cells(P);
   int eta[2 * MAXQ];
@@ -306,7 +324,7 @@ int orc_adapt_tree(const orc_params *P, const uint8_t *told, const double *D, ui
    * metric reaches eps_l = 2^{d(l-J)} eps. */
   memset(tree_at(P, keep, jmin), 1, (size_t)ncells(P, jmin));
   for (int l = jmin + 1; l <= J; ++l) {
-    const double eps_l = ldexp(P->eps, d * (l - J));
+    const double eps_l = eps_lv[l];
     const uint8_t *t = tree_at(P, told, l);
     const double *Dp = D + orc_level_offset(P, l - 1);
     uint8_t *k = tree_at(P, keep, l);
@@ -334,8 +352,7 @@ int orc_adapt_tree(const orc_params *P, const uint8_t *told, const double *D, ui
   for (int l = jmin; l <= J; ++l) {
     const uint8_t *k = tree_at(P, keep, l);
     uint8_t *tn = tree_at(P, tnew, l);
-    const double eps_l = ldexp(P->eps, d * (l - J));
-    const double refine_thr = ldexp(eps_l, d) * exp2(P->mu_bar);
+    const double refine_thr = ref_lv[l];
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!k[c]) continue;
       int x, y;
@@ -571,4 +588,108 @@ int orc_check_tree(const orc_params *P, const uint8_t *tree) {
     }
   }
   return bad;
+}
+
+/* ---- The mesh decision in single precision (for a single-precision solver):
+ *      the same projection, prediction and detail expressions evaluated in float,
+ *      thresholds rounded to float. ---- */
+
+static float *valf_at(const orc_params *P, const float *v, int l, int h) {
+  return (float *)v + (int64_t)P->q * orc_level_offset(P, l) + (int64_t)h * ncells(P, l);
+}
+
+static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, int cy) {
+  const int n = side(l - 1);
+  const int px = cx >> 1;
+  const float sx = (cx & 1) ? -1.0f : 1.0f;
+  const float c1 = -0.125f;
+  if (P->dim == 1) {
+    const float Q = c1 * (Fp[wrapi(px + 1, n)] - Fp[wrapi(px - 1, n)]);
+    return Fp[px] + sx * Q;
+  }
+  const int py = cy >> 1;
+  const float sy = (cy & 1) ? -1.0f : 1.0f;
+#define AT(a, b) Fp[(int64_t)wrapi((a), n) + (int64_t)n * wrapi((b), n)]
+  const float Qx = c1 * (AT(px + 1, py) - AT(px - 1, py));
+  const float Qy = c1 * (AT(px, py + 1) - AT(px, py - 1));
+  const float Qxy =
+      0.015625f * (((AT(px + 1, py + 1) - AT(px - 1, py + 1)) - AT(px + 1, py - 1)) + AT(px - 1, py - 1));
+  return ((AT(px, py) + sx * Qx) + sy * Qy) + (sx * sy) * Qxy;
+#undef AT
+}
+
+static float project_f32(const orc_params *P, const float *Fc, int l, int px, int py) {
+  if (P->dim == 1) return 0.5f * (Fc[2 * px] + Fc[2 * px + 1]);
+  const int64_t n = side(l + 1);
+  const float a00 = Fc[2 * px + n * (2 * py)], a10 = Fc[2 * px + 1 + n * (2 * py)];
+  const float a01 = Fc[2 * px + n * (2 * py + 1)], a11 = Fc[2 * px + 1 + n * (2 * py + 1)];
+  return 0.25f * (((a00 + a10) + a01) + a11);
+}
+
+int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf_values, uint8_t *tnew,
+                     double *D_out) {
+  const int64_t total = orc_total_cells(P);
+  float *v = malloc(sizeof(float) * (size_t)(P->q * total));
+  double *D = D_out ? D_out : malloc(sizeof(double) * (size_t)total);
+  if (!v || !D) { free(v); if (!D_out) free(D); return -1; }
+  memcpy(v, leaf_values, sizeof(float) * (size_t)(P->q * total));
+  for (int l = P->jmax - 1; l >= P->jmin; --l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_internal(P, tree, l, c)) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = project_f32(P, valf_at(P, v, l + 1, h), l, x, y);
+    }
+  for (int l = P->jmin + 1; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (tree_at(P, tree, l)[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = predict_f32(P, valf_at(P, v, l - 1, h), l, x, y);
+    }
+  for (int64_t i = 0; i < total; ++i) D[i] = -1.0;
+  for (int l = P->jmin + 1; l <= P->jmax; ++l) {
+    const uint8_t *tp = tree_at(P, tree, l - 1), *tc = tree_at(P, tree, l);
+    double *Dp = D + orc_level_offset(P, l - 1);
+    for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
+      int px, py;
+      cell_coords(P, l - 1, p, &px, &py);
+      if (!tp[p] || !tc[child_index(P, l - 1, px, py, 0)]) continue;
+      float dmax = 0.0f;
+      for (int h = 0; h < P->q; ++h)
+        for (int sigma = 0; sigma < nchildren(P); ++sigma) {
+          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
+          const float dd = valf_at(P, v, l, h)[cell_index(P, l, cx, cy)] - predict_f32(P, valf_at(P, v, l - 1, h), l, cx, cy);
+          if (fabsf(dd) > dmax) dmax = fabsf(dd);
+        }
+      Dp[p] = (double)dmax;
+    }
+  }
+  double eps_l[64], ref_l[64];
+  thresholds(P, eps_l, ref_l);
+  for (int l = 0; l <= P->jmax; ++l) {
+    eps_l[l] = (double)(float)eps_l[l];
+    ref_l[l] = (double)(float)ref_l[l];
+  }
+  const int rc = adapt_tree_thr(P, tree, D, eps_l, ref_l, tnew);
+  free(v);
+  if (!D_out) free(D);
+  return rc;
+}
+
+/* One step of Algorithm 1 on a given new mesh (the adaptation is replaced by
+ * `tnew`, which must be a graded complete tree whose cells all have their
+ * parent in `tree`): transfer, transport, collide. */
+int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, double *values) {
+  const int64_t total = orc_total_cells(P);
+  double *vnew = calloc((size_t)(P->q * total), sizeof(double));
+  if (!vnew) return -1;
+  orc_reconstruct(P, tree, values);
+  orc_transfer(P, tree, values, tnew, vnew);
+  orc_reconstruct(P, tnew, vnew);
+  orc_transport(P, tnew, vnew, values, 0);
+  orc_collide(P, tnew, values);
+  memcpy(tree, tnew, (size_t)total);
+  free(vnew);
+  return 0;
 }

@@ -78,6 +78,15 @@ int orc_transport(const orc_params *P, const uint8_t *tree, const double *values
 int orc_collide(const orc_params *P, const uint8_t *tree, double *values);
 void orc_collide_cell(const orc_params *P, double *f);
 
+/* Mesh decision in single precision: reconstruction and details of the float
+ * leaf values evaluated in float (same expressions and order), thresholds
+ * rounded to float; optionally returns the float details (as double). */
+int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf_values, uint8_t *tnew,
+                     double *D_out);
+
+/* One step on a given new mesh (transfer, transport, collide). */
+int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, double *values);
+
 /* Uniform reference scheme on level J only: values layout [h][N_J^d]. */
 int orc_uniform_step(const orc_params *P, double *fJ);
 

@@ -167,3 +167,30 @@ def test_enlargement_keeps_upwind_neighbours_and_refines():
                         assert t_new[(y - ey) % n, (x - ex) % n]
                     if l < o.jmax and Dp[y >> 1, x >> 1] >= np.ldexp(epsl, 2) * 2.0:
                         assert o.tree_level(tnew, l + 1)[2 * y, 2 * x]
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax", [("D1Q3", 2, 8), ("D2Q9", 2, 6)])
+def test_float_decision_matches_double_on_exact_data(scheme, jmin, jmax):
+    """With leaf values that are small dyadic rationals, every projection,
+    prediction and detail is exact in float and double, so the single-precision
+    mesh decision must equal the double one."""
+    cfg = _cfg(scheme, jmin, jmax, 2.0 ** -6)
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(5)
+    tree = o.adapt_tree(np.ones(o.total, np.uint8), 10.0 ** rng.uniform(-4, 0, o.total))
+    _, v = o.new_state()
+    v[:] = rng.integers(-64, 64, v.size) / 64.0
+    assert np.array_equal(o.new_tree_f32(tree, v.astype(np.float32)), o.new_tree_from_state(tree, v))
+
+
+def test_step_frozen_equals_step_on_own_mesh():
+    cfg = _cfg("D2Q9", 2, 6, 1e-3)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 3, "jump"))
+    o.step(tree, v, 2)
+    tnew = o.new_tree_from_state(tree, v)
+    t1, v1 = tree.copy(), v.copy()
+    o.step(t1, v1)
+    t2, v2 = tree.copy(), v.copy()
+    o.step_frozen(t2, tnew, v2)
+    assert np.array_equal(t1, t2) and np.array_equal(v1, v2)
