@@ -73,6 +73,12 @@ def lib():
             f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
         for name, args in [("orc_new_tree_f32", [P, u8, dp, u8, dp]), ("orc_step_frozen", [P, u8, u8, dp])]:
             f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
+        for name, args in [("orc_reconstruct_T", [P, u8, dp]), ("orc_transport_T", [P, u8, dp, dp]),
+                           ("orc_transfer_T", [P, u8, dp, dp]), ("orc_collide_T", [P, u8, dp, dp, dp, dp]),
+                           ("orc_init_T", [P, dp, dp, dp]), ("orc_adjoint_step", [P, u8, u8, dp, dp, dp, dp]),
+                           ("orc_predict_stencil", [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp])]:
+            f = getattr(L, name); f.argtypes = args; f.restype = ctypes.c_int
+        L.orc_equilibrium_jacobian.argtypes = [P, dp, dp]; L.orc_equilibrium_jacobian.restype = None
         L.orc_predict.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_predict.restype = ctypes.c_double
         L.orc_collide_cell.argtypes = [P, dp]; L.orc_collide_cell.restype = None
@@ -243,6 +249,77 @@ class Oracle:
     def finest(self, tree, values):
         """Reconstruction f^hat-hat on the finest level, shape (q, N_J[, N_J])."""
         return self.values_level(self.reconstruct(tree, values), self.jmax).copy()
+
+    # ---- adjoint on frozen meshes ----
+    def predict_stencil(self, l, cx, cy=0):
+        idx = np.zeros(9, np.int64)
+        w = np.zeros(9, np.float64)
+        k = self.L.orc_predict_stencil(ctypes.byref(self.p), l, cx, cy, _ptr(idx), _ptr(w))
+        return idx[:k], w[:k]
+
+    def reconstruct_T(self, tree, g):
+        g = np.array(g, dtype=np.float64)
+        self._chk(self.L.orc_reconstruct_T(ctypes.byref(self.p), _ptr(tree), _ptr(g)))
+        return g
+
+    def transport_T(self, tree, ob):
+        gs = np.zeros(self.q * self.total, np.float64)
+        self._chk(self.L.orc_transport_T(ctypes.byref(self.p), _ptr(tree), _ptr(np.ascontiguousarray(ob)), _ptr(gs)))
+        return gs
+
+    def transfer_T(self, tnew, gnew):
+        gold = np.zeros(self.q * self.total, np.float64)
+        self._chk(self.L.orc_transfer_T(ctypes.byref(self.p), _ptr(tnew), _ptr(np.ascontiguousarray(gnew)), _ptr(gold)))
+        return gold
+
+    def collide_T(self, tree, h, abar):
+        hb = np.zeros(self.q * self.total, np.float64)
+        sb = np.zeros(9, np.float64)
+        self._chk(self.L.orc_collide_T(ctypes.byref(self.p), _ptr(tree), _ptr(np.ascontiguousarray(h)),
+                                       _ptr(np.ascontiguousarray(abar)), _ptr(hb), _ptr(sb)))
+        return hb, sb
+
+    def equilibrium_jacobian(self, m):
+        Je = np.zeros(self.q * self.q, np.float64)
+        self.L.orc_equilibrium_jacobian(ctypes.byref(self.p), _ptr(np.array(m, dtype=np.float64)), _ptr(Je))
+        return Je.reshape(self.q, self.q)
+
+    def init_T(self, m0, abar):
+        nc = 3 if self.q == 9 else 1
+        mb = np.zeros(nc * self.ncells(self.jmax), np.float64)
+        self._chk(self.L.orc_init_T(ctypes.byref(self.p), _ptr(np.ascontiguousarray(m0, dtype=np.float64)),
+                                    _ptr(np.ascontiguousarray(abar)), _ptr(mb)))
+        return mb.reshape(nc, -1)
+
+    def adjoint_step(self, told, tnew, vold, anew):
+        aold = np.zeros(self.q * self.total, np.float64)
+        sb = np.zeros(9, np.float64)
+        self._chk(self.L.orc_adjoint_step(ctypes.byref(self.p), _ptr(told), _ptr(tnew),
+                                          _ptr(np.ascontiguousarray(vold)), _ptr(np.ascontiguousarray(anew)),
+                                          _ptr(aold), _ptr(sb)))
+        return aold, sb
+
+    def run_frozen(self, m0, trees):
+        """Forward on the mesh sequence trees[0..N] (trees[0] = the full initial
+        mesh); returns the list of states (tree, values) at steps 0..N."""
+        t, v = self.init(m0)
+        assert np.array_equal(t, trees[0])
+        states = [(t.copy(), v.copy())]
+        for tn in trees[1:]:
+            self.step_frozen(t, tn, v)
+            states.append((t.copy(), v.copy()))
+        return states
+
+    def gradient_frozen(self, m0, trees, abar_final):
+        """Adjoint of the frozen-mesh run: (dJ/dm0 [nc][N_J^d], dJ/ds [9]) for a
+        functional with dJ/d(final leaf values) = abar_final."""
+        states = self.run_frozen(m0, trees)
+        a = np.array(abar_final, dtype=np.float64)
+        sbar = np.zeros(9)
+        for n in range(len(trees) - 1, 0, -1):
+            a, sb = self.adjoint_step(states[n - 1][0], states[n][0], states[n - 1][1], a)
+            sbar += sb
+        return self.init_T(m0, a), sbar
 
     @staticmethod
     def _chk(rc):

@@ -693,3 +693,273 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
   free(vnew);
   return 0;
 }
+
+/* ---- Adjoint on frozen meshes: transposes of the linear maps of one step and
+ *      of the linearised collision. Each scatter-adds into its output in a fixed
+ *      loop order. ---- */
+
+/* Stencil of the prediction of child (cx, cy) at level l: the parent-level cells
+ * (indices into level l-1) and weights such that the prediction equals
+ * sum_k w[k] F[idx[k]]. Returns the number of terms (3 in 1D, 9 in 2D). */
+int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w) {
+  const int n = side(l - 1);
+  const int px = cx >> 1;
+  const double sx = (cx & 1) ? -1.0 : 1.0;
+  if (P->dim == 1) {
+    idx[0] = px; w[0] = 1.0;
+    idx[1] = wrapi(px + 1, n); w[1] = sx * C1;
+    idx[2] = wrapi(px - 1, n); w[2] = -sx * C1;
+    return 3;
+  }
+  const int py = cy >> 1;
+  const double sy = (cy & 1) ? -1.0 : 1.0, c2 = sx * sy * C1 * C1;
+  int k = 0;
+#define PUT(a, b, ww) do { idx[k] = cell_index_wrapped(P, l - 1, (a), (b)); w[k] = (ww); ++k; } while (0)
+  PUT(px, py, 1.0);
+  PUT(px + 1, py, sx * C1);
+  PUT(px - 1, py, -sx * C1);
+  PUT(px, py + 1, sy * C1);
+  PUT(px, py - 1, -sy * C1);
+  PUT(px + 1, py + 1, c2);
+  PUT(px - 1, py + 1, -c2);
+  PUT(px + 1, py - 1, -c2);
+  PUT(px - 1, py - 1, c2);
+#undef PUT
+  return k;
+}
+
+/* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
+ * the leaf entries hold the adjoint of the leaf values and all others are 0. */
+int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
+  int64_t idx[9];
+  double w[9];
+  for (int l = P->jmax; l >= P->jmin + 1; --l) {  /* predictions, finest first */
+    const uint8_t *t = tree_at(P, tree, l);
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (t[c]) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      const int nk = orc_predict_stencil(P, l, x, y, idx, w);
+      for (int h = 0; h < P->q; ++h) {
+        double *gl = val_at(P, g, l, h), *gp = val_at(P, g, l - 1, h);
+        for (int k = 0; k < nk; ++k) gp[idx[k]] += w[k] * gl[c];
+        gl[c] = 0.0;
+      }
+    }
+  }
+  const double inv = 1.0 / nchildren(P);
+  for (int l = P->jmin; l <= P->jmax - 1; ++l)  /* projections, coarsest first */
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_internal(P, tree, l, c)) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      for (int h = 0; h < P->q; ++h) {
+        double *gl = val_at(P, g, l, h), *gc = val_at(P, g, l + 1, h);
+        for (int sigma = 0; sigma < nchildren(P); ++sigma) gc[child_index(P, l, x, y, sigma)] += inv * gl[c];
+        gl[c] = 0.0;
+      }
+    }
+  return 0;
+}
+
+/* Transpose of orc_transport (E/A form): adds into the dense `gs` the adjoint of
+ * the reconstruction F* from the leaf adjoints `ob` of the transported values. */
+int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs) {
+  const int J = P->jmax, d = P->dim;
+  int eta[2 * MAXQ];
+  orc_velocities(P, eta);
+  for (int l = P->jmin; l <= J; ++l) {
+    const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tree, l, c)) continue;
+      int x, y;
+      cell_coords(P, l, c, &x, &y);
+      const int bx0 = x * w, by0 = y * wy;
+      for (int h = 0; h < P->q; ++h) {
+        const int ex = eta[2 * h], ey = eta[2 * h + 1];
+        const double a = val_at(P, ob, l, h)[c];
+        double *GJ = val_at(P, gs, J, h);
+        if (ex == 0 && ey == 0) {
+          val_at(P, gs, l, h)[c] += a;
+        } else if (n == 0) {
+          GJ[cell_index_wrapped(P, J, x - ex, y - ey)] += a;
+        } else {
+          val_at(P, gs, l, h)[c] += a;
+          const double sa = ldexp(a, -d * n);
+          for (int ky = by0; ky < by0 + wy; ++ky)
+            for (int kx = bx0; kx < bx0 + w; ++kx) {
+              const int jx = kx - ex, jy = ky - ey;
+              if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy))
+                GJ[cell_index_wrapped(P, J, jx, jy)] += sa;
+              const int ix = kx + ex, iy = ky + ey;
+              if (!(ix >= bx0 && ix < bx0 + w && iy >= by0 && iy < by0 + wy)) GJ[cell_index(P, J, kx, ky)] -= sa;
+            }
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+/* Transpose of orc_transfer: the new leaf value is the old dense reconstruction
+ * at the same cell, so its adjoint adds there. */
+int orc_transfer_T(const orc_params *P, const uint8_t *tnew, const double *gnew, double *gold) {
+  for (int l = P->jmin; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tnew, l, c)) continue;
+      for (int h = 0; h < P->q; ++h) val_at(P, gold, l, h)[c] += val_at(P, gnew, l, h)[c];
+    }
+  return 0;
+}
+
+/* Jacobian d m_eq / d m (q x q, row-major); only the conserved columns are non-zero. */
+void orc_equilibrium_jacobian(const orc_params *P, const double *m, double *Je) {
+  const int q = P->q;
+  const double L = P->lambda;
+  memset(Je, 0, sizeof(double) * q * q);
+  if (P->scheme == 1) {
+    Je[0] = 1.0;
+    Je[1 * q + 0] = P->eq_param;
+  } else if (P->scheme == 2) {
+    Je[0] = 1.0;
+    Je[1 * q + 0] = m[0];
+    Je[2 * q + 0] = P->eq_param * L * L;
+  } else {
+    const double rho = m[0], qx = m[1], qy = m[2], cs2 = L * L / 3.0;
+    const double q2 = qx * qx + qy * qy, r2 = rho * rho;
+    Je[0 * q + 0] = 1.0;
+    Je[1 * q + 1] = 1.0;
+    Je[2 * q + 2] = 1.0;
+    Je[3 * q + 0] = 3.0 * (-2.0 * cs2 - q2 / r2);
+    Je[3 * q + 1] = 6.0 * qx / rho;
+    Je[3 * q + 2] = 6.0 * qy / rho;
+    Je[4 * q + 1] = -3.0 * cs2;
+    Je[5 * q + 2] = -3.0 * cs2;
+    Je[6 * q + 0] = 9.0 * (cs2 * cs2 + cs2 * q2 / r2);
+    Je[6 * q + 1] = -18.0 * cs2 * qx / rho;
+    Je[6 * q + 2] = -18.0 * cs2 * qy / rho;
+    Je[7 * q + 0] = -(qx * qx - qy * qy) / r2;
+    Je[7 * q + 1] = 2.0 * qx / rho;
+    Je[7 * q + 2] = -2.0 * qy / rho;
+    Je[8 * q + 0] = -qx * qy / r2;
+    Je[8 * q + 1] = qy / rho;
+    Je[8 * q + 2] = qx / rho;
+  }
+}
+
+/* Adjoint of the collision at one cell: f is the pre-collision state, a the
+ * adjoint of the post-collision state; returns the adjoint of f in fb and adds
+ * the derivative with respect to each relaxation rate into sb. */
+static void collide_T_cell(const orc_params *P, const double *M, const double *Minv, const double *f, const double *a,
+                           double *fb, double *sb) {
+  const int q = P->q;
+  double m[MAXQ] = {0}, meq[MAXQ] = {0}, b[MAXQ], cvec[MAXQ], Je[MAXQ * MAXQ];
+  for (int i = 0; i < q; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < q; ++j) acc += M[i * q + j] * f[j];
+    m[i] = acc;
+  }
+  orc_equilibrium(P, m, meq);
+  orc_equilibrium_jacobian(P, m, Je);
+  for (int k = 0; k < q; ++k) { /* b = M^{-T} a */
+    double acc = 0.0;
+    for (int j = 0; j < q; ++j) acc += Minv[j * q + k] * a[j];
+    b[k] = acc;
+  }
+  for (int i = 0; i < q; ++i) {
+    double acc = (1.0 - P->s[i]) * b[i];
+    for (int k = 0; k < q; ++k) acc += Je[k * q + i] * P->s[k] * b[k];
+    cvec[i] = acc;
+  }
+  for (int j = 0; j < q; ++j) { /* fb = M^T c */
+    double acc = 0.0;
+    for (int i = 0; i < q; ++i) acc += M[i * q + j] * cvec[i];
+    fb[j] = acc;
+  }
+  for (int k = 0; k < q; ++k) sb[k] += b[k] * (meq[k] - m[k]);
+}
+
+int orc_collide_T(const orc_params *P, const uint8_t *tree, const double *h, const double *abar, double *hbar,
+                  double *sbar) {
+  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ], f[MAXQ], a[MAXQ], fb[MAXQ];
+  orc_moment_matrix(P, M);
+  if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  for (int l = P->jmin; l <= P->jmax; ++l)
+    for (int64_t c = 0; c < ncells(P, l); ++c) {
+      if (!is_leaf(P, tree, l, c)) continue;
+      for (int k = 0; k < P->q; ++k) {
+        f[k] = val_at(P, h, l, k)[c];
+        a[k] = val_at(P, abar, l, k)[c];
+      }
+      collide_T_cell(P, M, Minv, f, a, fb, sbar);
+      for (int k = 0; k < P->q; ++k) val_at(P, hbar, l, k)[c] = fb[k];
+    }
+  return 0;
+}
+
+/* Adjoint of the initial datum f = M^{-1} m_eq(m0) on the finest level: from the
+ * adjoint abar of the finest-level values, the adjoint of m0 ([nc][N_J^d]). */
+int orc_init_T(const orc_params *P, const double *m0, const double *abar, double *mbar) {
+  const int q = P->q, J = P->jmax, nc = P->scheme == 3 ? 3 : 1;
+  const int64_t NJ = ncells(P, J);
+  double Minv[MAXQ * MAXQ], m[MAXQ], Je[MAXQ * MAXQ], b[MAXQ];
+  if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  for (int64_t c = 0; c < NJ; ++c) {
+    for (int i = 0; i < q; ++i) m[i] = i < nc ? m0[(int64_t)i * NJ + c] : 0.0;
+    orc_equilibrium_jacobian(P, m, Je);
+    for (int k = 0; k < q; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < q; ++j) acc += Minv[j * q + k] * val_at(P, abar, J, j)[c];
+      b[k] = acc;
+    }
+    for (int j = 0; j < nc; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < q; ++k) acc += Je[k * q + j] * b[k];
+      mbar[(int64_t)j * NJ + c] = acc;
+    }
+  }
+  return 0;
+}
+
+/* Pre-collision values h of one frozen-mesh step (transfer, reconstruction,
+ * transport), written at the leaves of tnew. */
+static int step_precollision(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
+                             double *h) {
+  const int64_t total = orc_total_cells(P);
+  double *G = malloc(sizeof(double) * (size_t)(P->q * total));
+  double *g = calloc((size_t)(P->q * total), sizeof(double));
+  if (!G || !g) { free(G); free(g); return -1; }
+  memcpy(G, vold, sizeof(double) * (size_t)(P->q * total));
+  orc_reconstruct(P, told, G);
+  orc_transfer(P, told, G, tnew, g);
+  orc_reconstruct(P, tnew, g);
+  orc_transport(P, tnew, g, h, 0);
+  free(G);
+  free(g);
+  return 0;
+}
+
+/* One adjoint step: given the leaf values vold of `told` before the step and the
+ * adjoint anew of the leaf values of `tnew` after it, the adjoint aold of vold;
+ * adds d/ds into sbar. */
+int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
+                     const double *anew, double *aold, double *sbar) {
+  const int64_t total = orc_total_cells(P), n = P->q * total;
+  double *h = calloc((size_t)n, sizeof(double)), *hb = calloc((size_t)n, sizeof(double));
+  double *gs = calloc((size_t)n, sizeof(double));
+  int rc = -1;
+  if (!h || !hb || !gs) goto done;
+  if (step_precollision(P, told, tnew, vold, h)) goto done;
+  orc_collide_T(P, tnew, h, anew, hb, sbar);
+  orc_transport_T(P, tnew, hb, gs);
+  orc_reconstruct_T(P, tnew, gs);  /* gs: adjoint of the transferred leaf values */
+  memset(aold, 0, sizeof(double) * (size_t)n);
+  orc_transfer_T(P, tnew, gs, aold);
+  orc_reconstruct_T(P, told, aold);
+  rc = 0;
+done:
+  free(h);
+  free(hb);
+  free(gs);
+  return rc;
+}

@@ -87,6 +87,19 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
 /* One step on a given new mesh (transfer, transport, collide). */
 int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, double *values);
 
+/* Adjoint on frozen meshes (transposes of the step's linear maps and of the
+ * linearised collision; each adds into its output in a fixed order). */
+int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w);
+int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g);
+int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs);
+int orc_transfer_T(const orc_params *P, const uint8_t *tnew, const double *gnew, double *gold);
+void orc_equilibrium_jacobian(const orc_params *P, const double *m, double *Je);
+int orc_collide_T(const orc_params *P, const uint8_t *tree, const double *h, const double *abar, double *hbar,
+                  double *sbar);
+int orc_init_T(const orc_params *P, const double *m0, const double *abar, double *mbar);
+int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
+                     const double *anew, double *aold, double *sbar);
+
 /* Uniform reference scheme on level J only: values layout [h][N_J^d]. */
 int orc_uniform_step(const orc_params *P, double *fJ);
 
