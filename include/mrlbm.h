@@ -159,6 +159,31 @@ int mrlbm_profile(mrlbm_ctx *ctx, int enable);
 /* Read the counters (synchronous). */
 int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
 
+/* ---- Adjoint on frozen meshes (contexts with batch = 1) ----
+ * The gradient of a functional J of the final leaf values with respect to the
+ * initial conserved moments and the relaxation rates, for the run of Algorithm 1
+ * whose meshes are held fixed (the adjoint of collision + MR transport +
+ * transfer on each recorded mesh; no derivative through the thresholding).
+ * Checkpoints every `ckpt_every` steps; each segment is recomputed forward with
+ * a tape of its meshes and pre-collision populations, then swept backwards. */
+
+/* Bytes of device workspace the adjoint of an `nsteps` run needs. */
+int mrlbm_adjoint_workspace_size(const mrlbm_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes);
+
+/* Run `nsteps` steps from the current state (normally just after
+ * mrlbm_init_equilibrium), storing checkpoints in `adj_workspace` (device,
+ * caller-owned, kept until mrlbm_adjoint). Asynchronous.
+ * Errors: MRLBM_ERR_CAPACITY if the workspace is too small. */
+int mrlbm_forward_record(mrlbm_ctx *ctx, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every);
+
+/* Backward sweep of the recorded run. `abar_final` (device, values layout of the
+ * final state; only complete-leaf entries are read) is dJ/d(final leaf values);
+ * writes dJ/d(initial conserved moments) to `mbar0` (device, [nc][N_J^d], context
+ * precision; meaningful when the run started from mrlbm_init_equilibrium) and
+ * dJ/ds_k (k = 0..q-1, summed in double) to the host array `sbar`. Synchronous.
+ * Leaves the context state unspecified (re-initialise or set it before stepping). */
+int mrlbm_adjoint(mrlbm_ctx *ctx, const void *abar_final, void *mbar0, double *sbar);
+
 /* Destroy the context (the workspace is the caller's to free). */
 int mrlbm_destroy(mrlbm_ctx *ctx);
 

@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     k_transport_collide_pop(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                             const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                             const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                            unsigned long long *__restrict__ counters) {
+                            unsigned long long *__restrict__ counters, T *__restrict__ tape) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q;
   constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
@@ -651,6 +651,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const int nn = n > 0 ? n - 1 : 0;
       fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
                                                   Ct + ((long long)nn * Q + h) * CS, nbr);
+      if (tape) tape[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     }
     __syncthreads();
     if (h == 0 && valid) {
@@ -674,7 +675,7 @@ __global__ void __launch_bounds__(BLK)
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                             unsigned long long *__restrict__ counters) {
+                             unsigned long long *__restrict__ counters, T *__restrict__ tape) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q;
   constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
@@ -709,6 +710,9 @@ __global__ void __launch_bounds__(BLK)
     for (int h = 0; h < Q; ++h)
       f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fs + ol + h * nl, Fs + of + h * nf, cl,
                                            Wt + ((long long)nn * Q + h) * WS, Ct + ((long long)nn * Q + h) * CS, nbr);
+    if (tape)
+#pragma unroll
+      for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
     collide<SCHEME, T>(f, In.sc);
 #pragma unroll
     for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];

@@ -12,6 +12,7 @@
 #include <utility>
 #include <vector>
 
+#include "mr_adjoint.h"
 #include "mr_kernels.h"
 #include "mrlbm.h"
 
@@ -259,6 +260,88 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.bytes = o + 256;  // slack for aligning the base pointer
 }
 
+// Moment matrix M of a scheme (rows scaled by powers of lambda) and its inverse
+// (Gauss-Jordan with partial pivoting), for the adjoint of the collision.
+void moment_mats(int scheme, double lam, double *M, double *Minv) {
+  const int q = scheme_q(scheme);
+  const double L = lam, L2 = L * L, L3 = L2 * L, L4 = L2 * L2;
+  std::memset(M, 0, sizeof(double) * 81);
+  if (scheme == MRLBM_D1Q2) {
+    const double m[4] = {1, 1, L, -L};
+    std::memcpy(M, m, sizeof m);
+  } else if (scheme == MRLBM_D1Q3) {
+    const double m[9] = {1, 1, 1, 0, L, -L, 0, L2, L2};
+    std::memcpy(M, m, sizeof m);
+  } else {
+    const double m[81] = {1, 1, 1, 1, 1, 1, 1, 1, 1,
+                          0, L, 0, -L, 0, L, -L, -L, L,
+                          0, 0, L, 0, -L, L, L, -L, -L,
+                          -4 * L2, -L2, -L2, -L2, -L2, 2 * L2, 2 * L2, 2 * L2, 2 * L2,
+                          0, -2 * L3, 0, 2 * L3, 0, L3, -L3, -L3, L3,
+                          0, 0, -2 * L3, 0, 2 * L3, L3, L3, -L3, -L3,
+                          4 * L4, -2 * L4, -2 * L4, -2 * L4, -2 * L4, L4, L4, L4, L4,
+                          0, L2, -L2, L2, -L2, 0, 0, 0, 0,
+                          0, 0, 0, 0, 0, L2, -L2, L2, -L2};
+    std::memcpy(M, m, sizeof m);
+  }
+  double A[9][18];
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < 2 * q; ++j) A[i][j] = j < q ? M[i * q + j] : (j - q == i ? 1.0 : 0.0);
+  for (int col = 0; col < q; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < q; ++r)
+      if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+    for (int j = 0; j < 2 * q; ++j) std::swap(A[col][j], A[piv][j]);
+    const double dd = A[col][col];
+    for (int j = 0; j < 2 * q; ++j) A[col][j] /= dd;
+    for (int r = 0; r < q; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      for (int j = 0; j < 2 * q; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) Minv[i * q + j] = A[i][q + j];
+}
+
+// Layout of the adjoint workspace: one checkpoint (codes and populations) every
+// K steps, and for one segment of K steps the tape (each step's new mesh and
+// pre-collision populations), the mesh the segment starts from, and four
+// adjoint buffers.
+struct AdjLayout {
+  int nck;
+  size_t code_b, F_b, lists_b, lvl_b;
+  size_t ck_code, ck_F, tape_code, tape_lists, tape_lvl, tape_h, st_code, st_lists, st_lvl, A, Hb, Gs, Go, spart, bytes;
+};
+constexpr int ADJ_GRID = 512;
+
+AdjLayout adj_layout(const Plan &P, int nsteps, int K) {
+  AdjLayout L;
+  L.nck = (nsteps + K - 1) / K;
+  L.code_b = align256(P.ctotal);
+  L.F_b = align256(P.rs * P.q * P.ctotal);
+  L.lists_b = align256(sizeof(uint32_t) * NCAT * P.ctotal);
+  L.lvl_b = align256(sizeof(int) * P.B * NCAT * LVL_STRIDE);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  L.ck_code = take(L.code_b * std::max(1, L.nck));
+  L.ck_F = take(L.F_b * std::max(1, L.nck));
+  L.tape_code = take(L.code_b * K);
+  L.tape_lists = take(L.lists_b * K);
+  L.tape_lvl = take(L.lvl_b * K);
+  L.tape_h = take(L.F_b * K);
+  L.st_code = take(L.code_b);
+  L.st_lists = take(L.lists_b);
+  L.st_lvl = take(L.lvl_b);
+  L.A = take(L.F_b);
+  L.Hb = take(L.F_b);
+  L.Gs = take(L.F_b);
+  L.Go = take(L.F_b);
+  L.spart = take(sizeof(double) * 9 * ADJ_GRID);
+  L.bytes = o + 256;
+  return L;
+}
+
 unsigned grid_cap(long long n, unsigned cap) {
   if (n < 1) n = 1;
   return (unsigned)(n > cap ? cap : n);
@@ -289,6 +372,9 @@ struct mrlbm_ctx {
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
   std::vector<char> has_state;
   int transport_variant;  // 0: by size, 1: one thread per leaf, 2: one wavefront per population
+  // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
+  char *adj_ws;
+  int adj_nsteps, adj_K;
   bool profiling;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
@@ -402,7 +488,7 @@ struct Engine {
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
-  static int transport(mrlbm_ctx *c) {
+  static int transport(mrlbm_ctx *c, T *tape = nullptr) {
     const Plan &P = c->P;
     const int m = c->mcur;
     T *Fc = (T *)c->F[c->cur];
@@ -416,10 +502,10 @@ struct Engine {
     if (per_leaf)
       k_transport_collide_leaf<DIM, SCHEME, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, LIST_GRID_ALL), BLK, 0,
                                                  c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
-                                                              (const T *)c->W, (const T *)c->C, c->cnt);
+                                                              (const T *)c->W, (const T *)c->C, c->cnt, tape);
     else
       k_transport_collide_pop<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
-          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt);
+          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt, tape);
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -450,6 +536,128 @@ struct Engine {
         I(c), i, (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal, c->lvl[c->mcur], cells,
         (T *)vals);
     return MRLBM_OK;
+  }
+
+  // ---------------------------------------------------------------- adjoint
+  struct Mesh {
+    const uint8_t *code;
+    const uint32_t *lists;
+    const int *lvl;
+  };
+
+  static void copy_mesh_out(mrlbm_ctx *c, int m, uint8_t *code, uint32_t *lists, int *lvl) {
+    const Plan &P = c->P;
+    (void)hipMemcpyAsync(code, c->code[m], P.ctotal, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(lists, c->lists[m], sizeof(uint32_t) * NCAT * P.ctotal, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(lvl, c->lvl[m], sizeof(int) * P.B * NCAT * LVL_STRIDE, hipMemcpyDeviceToDevice, c->stream);
+  }
+
+  static void zero(mrlbm_ctx *c, void *p, size_t bytes) {
+    const long long n4 = (long long)(bytes / 4);
+    k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>((uint32_t *)p, n4, 0u);
+  }
+
+  static int record(mrlbm_ctx *c, int nsteps, int K) {
+    const AdjLayout L = adj_layout(c->P, nsteps, K);
+    char *w = c->adj_ws;
+    for (int n = 0; n < nsteps; ++n) {
+      if (n % K == 0) {
+        const int k = n / K;
+        (void)hipMemcpyAsync(w + L.ck_code + k * L.code_b, c->code[c->mcur], c->P.ctotal, hipMemcpyDeviceToDevice,
+                             c->stream);
+        (void)hipMemcpyAsync(w + L.ck_F + k * L.F_b, c->F[c->cur], c->P.rs * c->P.q * c->P.ctotal,
+                             hipMemcpyDeviceToDevice, c->stream);
+      }
+      int rc = adapt(c);
+      if (!rc) rc = transport(c);
+      if (rc) return rc;
+    }
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  // Reconstruction transpose on mesh `ms` in the dense adjoint G: ghost
+  // predictions pushed up from the finest level, then projections pushed down.
+  static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms) {
+    const Plan &P = c->P;
+    for (int l = P.maxJ; l >= P.jmin + 1; --l)
+      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, ms.lists + (size_t)CAT_GHOST * P.ctotal,
+                                                              ms.lvl, l);
+    for (int l = P.jmin; l <= P.maxJ - 1; ++l)
+      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G,
+                                                                ms.lists + (size_t)CAT_INTERNAL * P.ctotal, ms.lvl, l);
+  }
+
+  static int adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sbar) {
+    const Plan &P = c->P;
+    const int nsteps = c->adj_nsteps, K = c->adj_K;
+    const AdjLayout L = adj_layout(P, nsteps, K);
+    char *w = c->adj_ws;
+    T *A = (T *)(w + L.A), *Hb = (T *)(w + L.Hb), *Gs = (T *)(w + L.Gs), *Go = (T *)(w + L.Go);
+    double *spart = (double *)(w + L.spart);
+    MomentMats<T> mm;
+    {
+      double M[81], Minv[81];
+      moment_mats(c->p[0].scheme, c->p[0].lambda, M, Minv);
+      for (int k = 0; k < 81; ++k) {
+        mm.M[k] = (T)M[k];
+        mm.Minv[k] = (T)Minv[k];
+      }
+    }
+    zero(c, spart, sizeof(double) * 9 * ADJ_GRID);
+    (void)hipMemcpyAsync(A, abar_final, L.F_b <= P.rs * P.q * P.ctotal ? L.F_b : P.rs * P.q * P.ctotal,
+                         hipMemcpyDeviceToDevice, c->stream);
+    const size_t fbytes = P.rs * P.q * P.ctotal;
+    for (int seg = L.nck - 1; seg >= 0; --seg) {
+      const int n0 = seg * K, n1 = std::min(n0 + K, nsteps), steps = n1 - n0;
+      // restore the checkpoint and rebuild its lists
+      (void)hipMemcpyAsync(c->code[c->mcur], w + L.ck_code + seg * L.code_b, P.ctotal, hipMemcpyDeviceToDevice,
+                           c->stream);
+      (void)hipMemcpyAsync(c->F[c->cur], w + L.ck_F + seg * L.F_b, fbytes, hipMemcpyDeviceToDevice, c->stream);
+      compact(c, c->mcur);
+      copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code), (uint32_t *)(w + L.st_lists), (int *)(w + L.st_lvl));
+      // recompute the segment, taping each step's new mesh and pre-collision values
+      for (int j = 0; j < steps; ++j) {
+        int rc = adapt(c);
+        if (!rc) rc = transport(c, (T *)(w + L.tape_h + j * L.F_b));
+        if (rc) return rc;
+        copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.tape_code + j * L.code_b),
+                      (uint32_t *)(w + L.tape_lists + j * L.lists_b), (int *)(w + L.tape_lvl + j * L.lvl_b));
+      }
+      // reverse sweep over the segment
+      for (int j = steps - 1; j >= 0; --j) {
+        const Mesh mn{(const uint8_t *)(w + L.tape_code + j * L.code_b),
+                      (const uint32_t *)(w + L.tape_lists + j * L.lists_b), (const int *)(w + L.tape_lvl + j * L.lvl_b)};
+        const Mesh mo = j > 0 ? Mesh{(const uint8_t *)(w + L.tape_code + (j - 1) * L.code_b),
+                                     (const uint32_t *)(w + L.tape_lists + (j - 1) * L.lists_b),
+                                     (const int *)(w + L.tape_lvl + (j - 1) * L.lvl_b)}
+                              : Mesh{(const uint8_t *)(w + L.st_code), (const uint32_t *)(w + L.st_lists),
+                                     (const int *)(w + L.st_lvl)};
+        const uint32_t *leaves_n = mn.lists + (size_t)CAT_LEAF * P.ctotal;
+        zero(c, Gs, fbytes);
+        zero(c, Go, fbytes);
+        k_adj_collide<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(
+            c->bt, I(c), mm, (const T *)(w + L.tape_h + j * L.F_b), A, Hb, leaves_n, mn.lvl, spart);
+        k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
+                                                                         (const T *)c->W, (const T *)c->C);
+        reconstruct_T(c, Gs, mn);
+        k_adj_transfer<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Gs, Go, mo.code, leaves_n, mn.lvl);
+        reconstruct_T(c, Go, mo);
+        std::swap(A, Go);
+      }
+    }
+    // the recorded run started from the full finest mesh of checkpoint 0
+    const long long nf = 1ll << (DIM * P.inst[0].jmax);
+    k_adj_init<DIM, SCHEME, T><<<grid_cap((nf + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        I(c), mm, (const T *)(w + L.ck_F), A, (T *)mbar0);
+    std::vector<double> part(9 * ADJ_GRID);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(part.data(), spart, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 9; ++k) {
+      double acc = 0.0;
+      for (int b = 0; b < ADJ_GRID; ++b) acc += part[b * 9 + k];
+      sbar[k] = acc;
+    }
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
   static int upload_inst(mrlbm_ctx *c) {
@@ -503,6 +711,12 @@ struct ExportOp {
 };
 template <int D, int S, typename T>
 struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::upload_inst(c); } };
+template <int D, int S, typename T>
+struct RecordOp { static int run(mrlbm_ctx *c, int n, int K) { return Engine<D, S, T>::record(c, n, K); } };
+template <int D, int S, typename T>
+struct AdjointOp {
+  static int run(mrlbm_ctx *c, const void *a, void *mb, double *sb) { return Engine<D, S, T>::adjoint(c, a, mb, sb); }
+};
 
 // Host check of a 0/1 tree of instance i: level jmin complete, sibling groups
 // complete, every tree cell's parent and prediction stencil present.
@@ -604,6 +818,9 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->has_state.assign(P.B, 0);
   c->profiling = false;
   c->ev_used = 0;
+  c->adj_ws = nullptr;
+  c->adj_nsteps = 0;
+  c->adj_K = 0;
   {
     const char *v = std::getenv("MRLBM_TRANSPORT");
     c->transport_variant = v && !std::strcmp(v, "leaf") ? 1 : v && !std::strcmp(v, "pop") ? 2 : 0;
@@ -782,6 +999,28 @@ int mrlbm_read_counters(mrlbm_ctx *c, mrlbm_counters *out) {
     else out->adapt_ms += ms;
   }
   return MRLBM_OK;
+}
+
+int mrlbm_adjoint_workspace_size(const mrlbm_ctx *c, int nsteps, int ckpt_every, size_t *bytes) {
+  if (!c || !bytes || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
+  *bytes = adj_layout(c->P, nsteps, ckpt_every).bytes;
+  return MRLBM_OK;
+}
+
+int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every) {
+  if (!c || !adj_workspace || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
+  if (!c->all_ready()) return MRLBM_ERR_STATE;
+  if (bytes < adj_layout(c->P, nsteps, ckpt_every).bytes) return MRLBM_ERR_CAPACITY;
+  c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);
+  c->adj_nsteps = nsteps;
+  c->adj_K = ckpt_every;
+  return dispatch<RecordOp>(c, nsteps, ckpt_every);
+}
+
+int mrlbm_adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sbar) {
+  if (!c || !abar_final || !mbar0 || !sbar || c->P.B != 1) return MRLBM_ERR_INVALID;
+  if (!c->adj_ws || c->adj_nsteps < 1) return MRLBM_ERR_STATE;
+  return dispatch<AdjointOp>(c, abar_final, mbar0, sbar);
 }
 
 int mrlbm_destroy(mrlbm_ctx *c) {

@@ -22,7 +22,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-fini
 EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mrlbm_adapt",
            "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
-           "mrlbm_profile", "mrlbm_read_counters"]
+           "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
+           "mrlbm_adjoint"]
 
 
 class MrlbmError(RuntimeError):
@@ -150,7 +151,10 @@ class Batch:
     # ---- time stepping
     def init_equilibrium(self, i: int, m0):
         t = self.torch
-        m = t.as_tensor(np.ascontiguousarray(m0), dtype=self.dtype).to(self.device).contiguous()
+        if isinstance(m0, t.Tensor):
+            m = m0.detach().to(device=self.device, dtype=self.dtype).contiguous()
+        else:
+            m = t.as_tensor(np.ascontiguousarray(m0), dtype=self.dtype).to(self.device).contiguous()
         assert m.numel() == self.nc * (1 << (self.dim * int(self.cfgs[i]["jmax"])))
         self._keep.append(m)  # kept alive until the asynchronous kernel has read it
         _check("mrlbm_init_equilibrium", lib().mrlbm_init_equilibrium(self._ctx, int(i), ctypes.c_void_p(m.data_ptr())))
@@ -211,6 +215,37 @@ class Batch:
         _check("mrlbm_leaves", lib().mrlbm_leaves(self._ctx, int(i), ctypes.c_void_p(cells.data_ptr()),
                                                   ctypes.c_void_p(vals.data_ptr()), n, ctypes.byref(count)))
         return cells[:n], vals[:n]
+
+
+    # ---- adjoint on frozen meshes (batch of one)
+    def forward_record(self, nsteps: int, ckpt_every: int):
+        """Run ``nsteps`` steps, keeping a checkpoint every ``ckpt_every`` steps in
+        a device workspace held by this object until :meth:`adjoint`."""
+        nbytes = ctypes.c_size_t(0)
+        _check("mrlbm_adjoint_workspace_size",
+               lib().mrlbm_adjoint_workspace_size(self._ctx, int(nsteps), int(ckpt_every), ctypes.byref(nbytes)))
+        self.adj_workspace = self.torch.empty(int(nbytes.value), dtype=self.torch.uint8, device=self.device)
+        _check("mrlbm_forward_record",
+               lib().mrlbm_forward_record(self._ctx, ctypes.c_void_p(self.adj_workspace.data_ptr()),
+                                          int(nbytes.value), int(nsteps), int(ckpt_every)))
+
+    def adjoint(self, abar_final):
+        """Backward sweep of the recorded run. ``abar_final``: dJ/d(final leaf
+        values), a device tensor in the values layout. Returns (dJ/dm0 device
+        tensor [nc][N_J^d], dJ/ds numpy [q])."""
+        t = self.torch
+        a = abar_final.to(device=self.device, dtype=self.dtype).contiguous()
+        assert a.numel() == self.q * self.total_cells[0]
+        mbar = t.empty((self.nc, 1 << (self.dim * int(self.cfgs[0]["jmax"]))), dtype=self.dtype, device=self.device)
+        sbar = (ctypes.c_double * 9)()
+        _check("mrlbm_adjoint", lib().mrlbm_adjoint(self._ctx, ctypes.c_void_p(a.data_ptr()),
+                                                    ctypes.c_void_p(mbar.data_ptr()), sbar))
+        return mbar, np.array(sbar[:self.q])
+
+    def state_tensor(self, i: int = 0):
+        """(tree uint8, values) of instance i as device tensors (values layout)."""
+        tree, values = Batch.get_state(self, i)
+        return (self.torch.from_numpy(tree).to(self.device), self.torch.from_numpy(values).to(self.device))
 
 
 class Sim(Batch):

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 from paper_2103_02903_amd import workloads as W
+from adjoint_helpers import ke_functional as _ke_functional
 
 
 def _cfg(scheme, jmin, jmax, eps):
@@ -104,42 +105,6 @@ def test_equilibrium_jacobian_and_collision_adjoint_vs_differences(scheme):
         cp["s"][k] += h; cm["s"][k] -= h
         fd = (np.dot(oracle.Oracle(cp).collide(tree, H), a) - np.dot(oracle.Oracle(cm).collide(tree, H), a)) / (2 * h)
         assert abs(fd - sb[k]) <= 1e-7 * (1 + abs(fd))
-
-
-def _ke_functional(o, tree, values, region=(0.25, 0.75)):
-    """J = sum over leaves whose centre lies in the region (each axis) of
-    |C|/|C_J| * |q|^2 / (2 rho) (D2Q9) or of |C|/|C_J| * u^2 / 2 (1D); returns
-    (J, dJ/dvalues)."""
-    J = 0.0
-    g = np.zeros_like(values)
-    M = o.moment_matrix()
-    for l in range(o.jmin, o.jmax + 1):
-        mask = o.leaf_mask(tree, l)
-        n = 1 << l
-        cen = (np.arange(n) + 0.5) / n
-        inside = (cen >= region[0]) & (cen < region[1])
-        if o.dim == 2:
-            mask = mask & inside[:, None] & inside[None, :]
-        else:
-            mask = mask & inside
-        vol = float(1 << (o.dim * (o.jmax - l)))
-        vl = o.values_level(values, l)
-        gl = o.values_level(g, l)
-        f = vl[:, mask]
-        m = M @ f
-        if o.q == 9:
-            rho, q2 = m[0], m[1] ** 2 + m[2] ** 2
-            J += vol * float(np.sum(0.5 * q2 / rho))
-            dm = np.zeros_like(m)
-            dm[0] = -0.5 * q2 / rho ** 2
-            dm[1] = m[1] / rho
-            dm[2] = m[2] / rho
-        else:
-            J += vol * float(np.sum(0.5 * m[0] ** 2))
-            dm = np.zeros_like(m)
-            dm[0] = m[0]
-        gl[:, mask] = vol * (M.T @ dm)
-    return J, g
 
 
 @pytest.mark.parametrize("scheme,jmin,jmax,steps", [("D1Q3", 2, 7, 12), ("D2Q9", 2, 5, 8)])
