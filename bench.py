@@ -1,12 +1,16 @@
 """Benchmark of the MR-LBM hot path on one MI355X.
 
 A step is one full pass of Algorithm 1 (mesh adaptation + transfer, MR
-transport, collision) over the whole synthetic state. Prints one JSON line:
-leaf updates per second over the timed steps, the roofline of the dominant
-kernel (transport + collision, HBM-bound) measured with HIP events on the
-library's stream, and the FP64 oracle timed on the host on a bounded sample.
+transport, collision) over the whole synthetic state, replayed from a HIP
+graph. Prints one JSON line: leaf updates per second of the plain FP64 path on
+the 1024^2 double shear layer over the timed steps; the roofline of the
+dominant kernel (transport + collision, HBM-bound), timed with HIP events on
+the library's stream inside the timed region; the FP32, batched and adjoint
+forms measured on the same GPU next to it; and the FP64 oracle timed on the
+host on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision 8|4]
+  python bench.py --copy-calibration     (plain copy kernel of known size only)
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "leaf updates/s + HBM GB/s (% peak) at 1 GPU; FP32/batched/adjoint vs plain FP64"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 KERNEL_SOURCES = ["paper_2103_02903_amd/csrc/mr_kernels.h", "paper_2103_02903_amd/csrc/mr_device.h"]
+COPY_BYTES = 1 << 30
 
 
 def workload(name: str):
@@ -37,8 +42,13 @@ def workload(name: str):
     elif name == "d2q9_shear_batch96":
         items = W.shear_layer_batch(96)
         desc = "96 independent D2Q9 MRT double shear layers, levels 3..J with J drawn in {7,8,9,10}, " \
-               "eps drawn in {1e-2,1e-3,1e-4}, Re uniform in [1e3,3e4], seeded perturbations; one launch " \
-               "sequence per step for all instances"
+               "eps drawn in {1e-2,1e-3,1e-4}, Re uniform in [1e3,3e4], seeded perturbations; one graph " \
+               "replay per step for all instances"
+        prec = 4
+    elif name == "d2q9_vortex_256":
+        items = [W.random_vortex_d2q9()]
+        desc = "D2Q9 MRT, periodic unit square, levels 3..8 (256^2 finest), eps=1e-3, seeded smooth " \
+               "solenoidal velocity from 16 Fourier modes"
         prec = 4
     elif name == "d1q3_burgers_16384":
         items = [W.burgers_d1q3()]
@@ -99,22 +109,224 @@ def cpu_baseline(cfg, tree, values, seconds: float):
                        "region" % (steps, dt))
 
 
+def copy_bandwidth(nbytes: int = COPY_BYTES, reps: int = 5):
+    """GB/s (read + write) of the library's plain copy kernel."""
+    import torch
+
+    from paper_2103_02903_amd import mrlbm
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    stream = torch.cuda.current_stream()
+    mrlbm.copy(dst, src, nbytes, stream)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        mrlbm.copy(dst, src, nbytes, stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    return dict(bytes_per_launch=2 * nbytes, avg_launch_ms=ms, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
+
+
+def timed_run(items, precision, steps, warmup, keep_state_of=None):
+    """Warm up, then time `steps` graph-replayed steps with the transport kernel
+    between HIP events. Returns (result dict, sim, state of instance
+    `keep_state_of` at the start of the timed region or None)."""
+    import torch
+
+    from paper_2103_02903_amd import mrlbm
+
+    sim = mrlbm.Batch([c for c, _ in items], precision=precision)
+    for i, (_, m0) in enumerate(items):
+        sim.init_equilibrium(i, m0)
+    sim.step(warmup)
+    sim.synchronize()
+    state0 = sim.get_state(keep_state_of) if keep_state_of is not None else None
+    sim.profile(True)
+    stream = sim.stream
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    sim.step(steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    elapsed_ms = t_start.elapsed_time(t_end)
+    cnt = sim.counters()
+    sim.profile(False)
+    q, rs = sim.q, precision
+    leaf_updates = int(cnt["leaf_updates"])
+    launches = max(1, int(cnt["timed_launches"]))
+    avg_ms = cnt["transport_ms"] / launches
+    bytes_per_leaf = 2 * q * rs  # read q populations, write q (neighbour reads are cache reuse)
+    bytes_per_launch = leaf_updates * bytes_per_leaf / max(1, int(cnt["transport_launches"]))
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    stats = [sim.stats(i) for i in range(sim.B)]
+    finest = sum(1 << (sim.dim * int(c["jmax"])) for c, _ in items)
+    leaves_now = sum(int(st["leaves"].sum()) for st in stats)
+    res = dict(value=leaf_updates / (elapsed_ms * 1e-3), ms_per_step=elapsed_ms / steps, steps=steps,
+               warmup=warmup, leaf_updates=leaf_updates, transport_avg_launch_ms=avg_ms,
+               transport_bytes_per_launch=bytes_per_launch, transport_gbs=achieved,
+               transport_frac=achieved / HBM_PEAK_GBS,
+               transport_leaf_updates_per_s=leaf_updates / (cnt["transport_ms"] * 1e-3),
+               mean_leaves_per_step=leaf_updates / max(1, steps),
+               compression_rate_final=1.0 - leaves_now / finest,
+               compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
+               mass_final=sum(st["mass"] for st in stats))
+    return res, sim, state0
+
+
+def phase_breakdown(sim, steps):
+    """Per-phase ms/step from kernel-by-kernel launches between HIP events
+    (diagnostic; the graph-replayed timing above is the measurement)."""
+    os.environ["MRLBM_GRAPH"] = "0"
+    from paper_2103_02903_amd import mrlbm
+
+    eager = mrlbm.Batch(sim.cfgs, precision=sim.precision)
+    os.environ.pop("MRLBM_GRAPH")
+    for i in range(sim.B):
+        t, v = sim.get_state(i)
+        eager.set_state(i, t, v)
+    eager.profile(True)
+    eager.step(steps)
+    cnt = eager.counters()
+    eager.close()
+    return {"adapt": cnt["adapt_ms"] / steps, "reconstruct": cnt["reconstruct_ms"] / steps,
+            "transport_collide": cnt["transport_ms"] / steps}
+
+
+def ke_gradient(sim, region=(0.25, 0.75)):
+    """Kinetic energy sum over leaves centred in region^2 of |C|/|C_J| |q|^2/(2 rho)
+    (D2Q9, lambda = 1) and its gradient in the library's values layout."""
+    import torch
+
+    cells, vals = sim.leaves()
+    cfg = sim.cfgs[0]
+    jmin, J = int(cfg["jmin"]), int(cfg["jmax"])
+    lv = (cells >> 26).long()
+    c = (cells & ((1 << 26) - 1)).long()
+    n = torch.ones_like(lv) << lv
+    x, y = c & (n - 1), c >> lv
+    cx, cy = (x.double() + 0.5) / n.double(), (y.double() + 0.5) / n.double()
+    inside = ((cx >= region[0]) & (cx < region[1]) & (cy >= region[0]) & (cy < region[1])).double()
+    vol = (torch.ones_like(lv) << (2 * (J - lv))).double() * inside
+    ex = torch.tensor([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=torch.float64, device=vals.device)
+    ey = torch.tensor([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=torch.float64, device=vals.device)
+    f = vals.double()
+    rho, qx, qy = f.sum(1), f @ ex, f @ ey
+    q2 = qx * qx + qy * qy
+    Jval = float(torch.sum(vol * 0.5 * q2 / rho))
+    g = vol[:, None] * (-0.5 * (q2 / (rho * rho))[:, None] + (qx[:, None] * ex + qy[:, None] * ey) / rho[:, None])
+    loff = [0] * (J + 2)
+    for l in range(jmin, J + 1):
+        loff[l + 1] = loff[l] + (1 << (2 * l))
+    loff_t = torch.tensor(loff, dtype=torch.long, device=vals.device)
+    idx = 9 * loff_t[lv][:, None] + torch.arange(9, device=vals.device)[None, :] * (n * n)[:, None] + c[:, None]
+    abar = torch.zeros(9 * loff[J + 1], dtype=torch.float64, device=vals.device)
+    abar[idx.reshape(-1)] = g.reshape(-1)
+    return Jval, abar
+
+
+def adjoint_run(nsteps: int, ckpt: int, precision: int):
+    """Forward steps alone, then a recorded forward + checkpointed adjoint, of the
+    256^2 vortex workload. Returns timings and the gradient."""
+    import torch
+
+    from paper_2103_02903_amd import mrlbm
+
+    (cfg, m0), = workload("d2q9_vortex_256")[0]
+    sim = mrlbm.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(nsteps)
+    sim.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.init_equilibrium(m0)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_record(nsteps, ckpt)
+    sim.synchronize()
+    t_rec = time.perf_counter() - t0
+    Jval, abar = ke_gradient(sim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mbar, sbar = sim.adjoint(abar)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    sim.profile(True)  # leaf updates of one plain forward run for the rate
+    sim.init_equilibrium(m0)
+    sim.step(nsteps)
+    leaf_updates = int(sim.counters()["leaf_updates"])
+    sim.close()
+    return dict(t_forward=t_fwd, t_record=t_rec, t_adjoint=t_adj, J=Jval, mbar=mbar.double(), sbar=sbar,
+                leaf_updates=leaf_updates)
+
+
+def variants(args, head):
+    """FP32 on the same workload, the 96-instance batch, and the adjoint, each
+    next to the plain FP64 path on this GPU."""
+    import numpy as np
+    import torch
+
+    out = {}
+    items, _, _ = workload(args.workload)
+    r32, s32, _ = timed_run(items, 4, args.steps, args.warmup)
+    s32.close()
+    r32["vs_fp64"] = r32["value"] / head["value"]
+    r32["accuracy"] = ("mesh decided in FP32; FP32 fields agree with the FP64 oracle's one-step replay to 1e-5 "
+                       "relative (GPU tests); final mass relative difference to the FP64 run %.2e"
+                       % (abs(r32["mass_final"] - head["mass_final"]) / abs(head["mass_final"])))
+    out["fp32_same_workload"] = r32
+    bitems, bdesc, _ = workload("d2q9_shear_batch96")
+    rb, sb, _ = timed_run(bitems, 4, args.batch_steps, args.batch_warmup)
+    sb.close()
+    rb["vs_fp64"] = rb["value"] / head["value"]
+    rb["workload"] = bdesc
+    out["batched_fp32"] = rb
+    a32 = adjoint_run(args.adjoint_steps, args.adjoint_ckpt, 4)
+    a64 = adjoint_run(args.adjoint_steps, args.adjoint_ckpt, 8)
+    for name, a in (("adjoint_fp32", a32), ("adjoint_fp64", a64)):
+        grad_ms = (a["t_record"] + a["t_adjoint"]) * 1e3
+        out[name] = dict(
+            workload=workload("d2q9_vortex_256")[1] + "; %d steps, checkpoint every %d, gradient of the kinetic "
+                     "energy in [1/4,3/4]^2 w.r.t. the initial moments and the relaxation rates" %
+                     (args.adjoint_steps, args.adjoint_ckpt),
+            value=a["leaf_updates"] / ((a["t_record"] + a["t_adjoint"])),
+            unit="forward leaf updates/s of the gradient computation (record + adjoint)",
+            gradient_ms=grad_ms, forward_ms=a["t_forward"] * 1e3,
+            gradient_over_forward=grad_ms / (a["t_forward"] * 1e3), J=a["J"],
+            dJ_ds2=float(a["sbar"][7] + a["sbar"][8]))
+    rel = float(torch.max(torch.abs(a32["mbar"] - a64["mbar"])) / torch.max(torch.abs(a64["mbar"])))
+    out["adjoint_fp32"]["accuracy"] = ("max |dJ/dm0 (FP32) - dJ/dm0 (FP64)| / max |dJ/dm0 (FP64)| = %.2e, each "
+                                       "precision on the meshes it chose itself" % rel)
+    out["adjoint_fp32"]["vs_fp64"] = out["adjoint_fp32"]["value"] / out["adjoint_fp64"]["value"]
+    del np
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="d2q9_shear_1024")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 4, 8], help="0: the workload's default")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-warmup", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=800)
+    ap.add_argument("--adjoint-ckpt", type=int, default=50)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
-              "sharding); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the design notes describe how "
+              "it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-
-    import torch
 
     from paper_2103_02903_amd import mrlbm
 
@@ -122,78 +334,59 @@ def main():
         from paper_2103_02903_amd import build as hip_build
 
         hip_build.build(force=False)
+    if args.copy_calibration:
+        print(json.dumps({"copy_kernel": "k_copy_u4", **copy_bandwidth()}))
+        return
     items, desc, prec = workload(args.workload)
     precision = args.precision or prec
-    sim = mrlbm.Batch([c for c, _ in items], precision=precision)
-    for i, (_, m0) in enumerate(items):
-        sim.init_equilibrium(i, m0)
-    sim.step(args.warmup)
-    sim.synchronize()
     # the CPU baseline steps the largest instance from its state at the start of the timed region
     big = max(range(len(items)), key=lambda i: items[i][0]["jmax"])
-    state0 = None if args.no_cpu_baseline else sim.get_state(big)
-
-    sim.profile(True)
-    stream = sim.stream
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    sim.step(args.steps)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    elapsed_ms = t_start.elapsed_time(t_end)
-    cnt = sim.counters()
-    stats = [sim.stats(i) for i in range(sim.B)]
-
-    q, rs = sim.q, precision
-    leaf_updates = int(cnt["leaf_updates"])
-    value = leaf_updates / (elapsed_ms * 1e-3)
-    bytes_per_leaf = 2 * q * rs  # read q populations, write q (neighbours are cache reuse)
-    launches = max(1, int(cnt["timed_launches"]))
-    avg_ms = cnt["transport_ms"] / launches
-    bytes_per_launch = leaf_updates * bytes_per_leaf / max(1, int(cnt["transport_launches"]))
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    finest = sum(1 << (sim.dim * int(c["jmax"])) for c, _ in items)
-    leaves_now = sum(int(st["leaves"].sum()) for st in stats)
+    head, sim, state0 = timed_run(items, precision, args.steps, args.warmup,
+                                  None if args.no_cpu_baseline else big)
+    phases = phase_breakdown(sim, min(args.steps, 100))
+    sim.close()
+    copy = copy_bandwidth()
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "leaf updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed_ms / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if precision == 8 else "f32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "precision": "fp%d" % (8 * precision),
-                   "instances": sim.B},
+                   "instances": len(items)},
         "roofline": {
             "kernel": "k_transport_collide",
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": head["transport_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": head["transport_frac"],
             "traffic": measured_traffic(args.workload, precision),
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": head["transport_bytes_per_launch"],
+            "avg_launch_ms": head["transport_avg_launch_ms"],
         },
-        "mean_leaves_per_step": leaf_updates / max(1, args.steps),
-        "compression_rate_final": 1.0 - leaves_now / finest,
-        "compression_rate_mean": 1.0 - leaf_updates / max(1, args.steps) / finest,
-        "phase_ms_per_step": {"adapt": cnt["adapt_ms"] / args.steps, "reconstruct": cnt["reconstruct_ms"] / args.steps,
-                              "transport_collide": cnt["transport_ms"] / args.steps},
-        "transport_kernel_leaf_updates_per_s": leaf_updates / (cnt["transport_ms"] * 1e-3),
-        "mass_final": sum(st["mass"] for st in stats),
+        "copy_reference": {"kernel": "k_copy_u4", "gbs": copy["gbs"], "frac": copy["gbs"] / HBM_PEAK_GBS},
+        "mean_leaves_per_step": head["mean_leaves_per_step"],
+        "compression_rate_final": head["compression_rate_final"],
+        "compression_rate_mean": head["compression_rate_mean"],
+        "transport_kernel_leaf_updates_per_s": head["transport_leaf_updates_per_s"],
+        "phase_ms_per_step_eager": phases,
+        "mass_final": head["mass_final"],
     }
+    if not args.no_variants and args.workload == "d2q9_shear_1024":
+        out["variants"] = variants(args, head)
     if state0 is not None:
         out["cpu_baseline"] = cpu_baseline(items[big][0], state0[0], state0[1], args.cpu_seconds)
-        if sim.B > 1:
+        if len(items) > 1:
             out["cpu_baseline"]["sample"] += " (instance %d of %d, levels %d..%d)" % (
-                big, sim.B, items[big][0]["jmin"], items[big][0]["jmax"])
+                big, len(items), items[big][0]["jmin"], items[big][0]["jmax"])
     print(json.dumps(out))
 
 

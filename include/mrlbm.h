@@ -107,7 +107,10 @@ int mrlbm_adapt(mrlbm_ctx *ctx);
 int mrlbm_transport_collide(mrlbm_ctx *ctx);
 
 /* `nsteps` full time steps of Algorithm 1 (adapt, transport, collide).
- * Asynchronous; nsteps >= 0. */
+ * Asynchronous; nsteps >= 0. Each step is replayed from a HIP graph captured
+ * on the context's first step in that buffer state (on a private stream, then
+ * launched on the context stream); MRLBM_GRAPH=0 in the environment at
+ * mrlbm_create launches the kernels one by one instead. Results are identical. */
 int mrlbm_step(mrlbm_ctx *ctx, int nsteps);
 
 /* Copy the current tree and values of one instance to host buffers (layouts
@@ -183,6 +186,11 @@ int mrlbm_forward_record(mrlbm_ctx *ctx, void *adj_workspace, size_t bytes, int 
  * dJ/ds_k (k = 0..q-1, summed in double) to the host array `sbar`. Synchronous.
  * Leaves the context state unspecified (re-initialise or set it before stepping). */
 int mrlbm_adjoint(mrlbm_ctx *ctx, const void *abar_final, void *mbar0, double *sbar);
+
+/* Plain device copy of `bytes` (a multiple of 16, both pointers 16-byte
+ * aligned) on `stream`: the reference kernel for bandwidth and for the scale
+ * of hardware traffic counters. Asynchronous. */
+int mrlbm_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Destroy the context (the workspace is the caller's to free). */
 int mrlbm_destroy(mrlbm_ctx *ctx);

@@ -377,6 +377,11 @@ __global__ void __launch_bounds__(BLK) k_full_tree(const Inst<T> *__restrict__ I
   }
 }
 
+// Plain 16-byte copy (reference kernel for bandwidth and counter calibration).
+__global__ void __launch_bounds__(BLK) k_copy_u4(uint4 *__restrict__ dst, const uint4 *__restrict__ src, long long n) {
+  for (long long i = blockIdx.x * (long long)BLK + threadIdx.x; i < n; i += (long long)gridDim.x * BLK) dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(BLK) k_fill_u32(uint32_t *__restrict__ p, long long n, uint32_t v) {
   for (long long i = blockIdx.x * (long long)BLK + threadIdx.x; i < n; i += (long long)gridDim.x * BLK) p[i] = v;
 }

@@ -375,6 +375,11 @@ struct mrlbm_ctx {
   // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
   char *adj_ws;
   int adj_nsteps, adj_K;
+  // HIP graphs of one step, captured on a private stream: [transport inside the
+  // graph (0) or launched after it with timing events (1)][2 * cur + mcur]
+  bool use_graph;
+  hipStream_t cap_stream;
+  hipGraphExec_t graph[2][4];
   bool profiling;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
@@ -489,13 +494,19 @@ struct Engine {
   }
 
   static int transport(mrlbm_ctx *c, T *tape = nullptr) {
+    phase_mark(c, PH_RECON, true);
+    reconstruct(c, (T *)c->F[c->cur], c->mcur);
+    phase_mark(c, PH_RECON, false);
+    return transport_kernel(c, tape);
+  }
+
+  // The transport + collision kernel alone (the current mesh's reconstruction
+  // must be in F[cur]).
+  static int transport_kernel(mrlbm_ctx *c, T *tape = nullptr) {
     const Plan &P = c->P;
     const int m = c->mcur;
     T *Fc = (T *)c->F[c->cur];
     T *Fn = (T *)c->F[1 - c->cur];
-    phase_mark(c, PH_RECON, true);
-    reconstruct(c, Fc, m);
-    phase_mark(c, PH_RECON, false);
     phase_mark(c, PH_TRANSPORT, true);
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
     const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
@@ -509,6 +520,42 @@ struct Engine {
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  // One full step replayed from a HIP graph, one graph per assignment of the
+  // double buffers (a step swaps the mesh buffers and swaps F twice). With
+  // profiling on, the graph ends after the reconstruction and the transport
+  // kernel is launched between timing events.
+  static int step_graph(mrlbm_ctx *c) {
+    const int timed = c->profiling ? 1 : 0, par = c->mcur;
+    hipGraphExec_t &g = c->graph[timed][2 * c->cur + par];
+    if (!g) {
+      const int cur0 = c->cur;
+      hipStream_t user = c->stream;
+      const bool prof = c->profiling;
+      c->stream = c->cap_stream;
+      c->profiling = false;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+      int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
+      if (rc == MRLBM_OK) reconstruct(c, (T *)c->F[c->cur], c->mcur);
+      if (rc == MRLBM_OK && !timed) rc = transport_kernel(c);
+      if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
+      c->stream = user;
+      c->profiling = prof;
+      c->mcur = par;
+      c->cur = cur0;
+      if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != MRLBM_OK) return rc;
+      if (e != hipSuccess) { g = nullptr; return MRLBM_ERR_HIP; }
+    }
+    if (hipGraphLaunch(g, c->stream) != hipSuccess) return MRLBM_ERR_HIP;
+    c->mcur = 1 - par;  // the adaptation's swaps
+    c->cur = 1 - c->cur;
+    if (timed) return transport_kernel(c);
+    c->cur = 1 - c->cur;  // the transport's swap
+    return MRLBM_OK;
   }
 
   static int init(mrlbm_ctx *c, int i, const void *mom) {
@@ -568,8 +615,13 @@ struct Engine {
         (void)hipMemcpyAsync(w + L.ck_F + k * L.F_b, c->F[c->cur], c->P.rs * c->P.q * c->P.ctotal,
                              hipMemcpyDeviceToDevice, c->stream);
       }
-      int rc = adapt(c);
-      if (!rc) rc = transport(c);
+      int rc;
+      if (c->use_graph) {
+        rc = step_graph(c);
+      } else {
+        rc = adapt(c);
+        if (!rc) rc = transport(c);
+      }
       if (rc) return rc;
     }
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -700,6 +752,8 @@ struct AdaptOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::adapt(c)
 template <int D, int S, typename T>
 struct TransportOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::transport(c); } };
 template <int D, int S, typename T>
+struct StepGraphOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::step_graph(c); } };
+template <int D, int S, typename T>
 struct InitOp { static int run(mrlbm_ctx *c, int i, const void *m) { return Engine<D, S, T>::init(c, i, m); } };
 template <int D, int S, typename T>
 struct ClassifyOp { static int run(mrlbm_ctx *c, int m) { Engine<D, S, T>::classify(c, m); return MRLBM_OK; } };
@@ -822,6 +876,17 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->adj_nsteps = 0;
   c->adj_K = 0;
   {
+    const char *v = std::getenv("MRLBM_GRAPH");
+    c->use_graph = !(v && !std::strcmp(v, "0"));
+  }
+  c->cap_stream = nullptr;
+  for (auto &row : c->graph)
+    for (auto &g : row) g = nullptr;
+  if (c->use_graph && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return MRLBM_ERR_HIP;
+  }
+  {
     const char *v = std::getenv("MRLBM_TRANSPORT");
     c->transport_variant = v && !std::strcmp(v, "leaf") ? 1 : v && !std::strcmp(v, "pop") ? 2 : 0;
   }
@@ -879,9 +944,13 @@ int mrlbm_step(mrlbm_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MRLBM_ERR_INVALID;
   if (!c->all_ready()) return MRLBM_ERR_STATE;
   for (int s = 0; s < nsteps; ++s) {
-    int rc = dispatch<AdaptOp>(c);
-    if (rc) return rc;
-    rc = dispatch<TransportOp>(c);
+    int rc;
+    if (c->use_graph) {
+      rc = dispatch<StepGraphOp>(c);
+    } else {
+      rc = dispatch<AdaptOp>(c);
+      if (!rc) rc = dispatch<TransportOp>(c);
+    }
     if (rc) return rc;
   }
   return MRLBM_OK;
@@ -1024,10 +1093,24 @@ int mrlbm_adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sba
 }
 
 int mrlbm_destroy(mrlbm_ctx *c) {
-  if (c)
-    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (!c) return MRLBM_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto &row : c->graph)
+    for (auto g : row)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return MRLBM_OK;
+}
+
+int mrlbm_copy(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return MRLBM_ERR_INVALID;
+  const long long n = (long long)(bytes / 16);
+  if (n == 0) return MRLBM_OK;
+  k_copy_u4<<<grid_cap((n + BLK - 1) / BLK, 8192), BLK, 0, (hipStream_t)stream>>>((uint4 *)dst, (const uint4 *)src,
+                                                                                  n);
+  return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
 }
 
 const char *mrlbm_status_string(int s) {

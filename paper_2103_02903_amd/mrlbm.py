@@ -23,7 +23,7 @@ EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mr
            "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
            "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
-           "mrlbm_adjoint"]
+           "mrlbm_adjoint", "mrlbm_copy"]
 
 
 class MrlbmError(RuntimeError):
@@ -88,6 +88,12 @@ def lib() -> ctypes.CDLL:
 def _check(fn: str, rc: int):
     if rc != 0:
         raise MrlbmError(fn, rc)
+
+
+def copy(dst, src, nbytes: int, stream):
+    """Device copy with the library's plain copy kernel (bandwidth reference)."""
+    _check("mrlbm_copy", lib().mrlbm_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                          int(nbytes), ctypes.c_void_p(stream.cuda_stream)))
 
 
 def transport_tables(scheme: str, n: int):
