@@ -108,7 +108,7 @@ __device__ __forceinline__ void equilibrium_moments(const T *m, const SchemeC<T>
 // wavefront (segments of one category over all levels, or of one level).
 #define MRLBM_CHUNK_LOOP(s, B)                                                                   \
   const int wave_ = threadIdx.x >> 6, lane_ = threadIdx.x & 63;                                 \
-  for (int ch = blockIdx.x * (BLK / 64) + wave_; ch < (s).pre[(B)]; ch += gridDim.x * (BLK / 64)) { \
+  MRLBM_FOR_CHUNKS(ch, (s).pre[(B)], BLK / 64, wave_) {                                            \
     const int i = upper_index((s).pre, (B), ch);                                                \
     const int item = (ch - (s).pre[i]) * CHUNK + lane_;                                         \
     if (item >= (s).cnt[i]) continue;

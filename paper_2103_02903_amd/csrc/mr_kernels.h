@@ -18,8 +18,9 @@ namespace mrlbm {
 constexpr int BLK = 256;
 constexpr int MAXB = 256;  // instances per batch
 constexpr int CHUNK = 64;  // list items per chunk (one per lane)
-constexpr int CITER = 4;   // cells per thread of an all-level dense pass
-constexpr int CCHUNK = BLK * CITER;
+constexpr int CPT = 16;    // consecutive cells per thread of an all-level dense pass
+constexpr int CCHUNK = BLK * CPT;
+constexpr int GCHUNK = BLK * 4;  // cells per block of the ghost classification
 
 // ---------------------------------------------------------------- list segments
 // Per-instance list segments of one category: of one level (l >= 0) or of all
@@ -69,6 +70,32 @@ __device__ __forceinline__ void load_segments(SegLDS &s, const Inst<T> *__restri
   __syncthreads();
 }
 
+// Chunk schedule of a list kernel. The hardware deals the blocks of a launch
+// round-robin to the 8 XCDs, each with its own L2. Each XCD takes a contiguous
+// eighth of the chunks, walked in order, so that list neighbours, whose
+// stencils overlap, are read through the same L2. `per_block` chunks per block
+// and round; `sub` is this wavefront's slot among them. Grids that are not a
+// multiple of 8 fall back to the plain interleaved order.
+#ifndef MRLBM_XCD
+#define MRLBM_XCD 1
+#endif
+constexpr int NXCD = 8;
+struct ChunkSched {
+  int ch, end, stride;
+};
+__device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int sub) {
+  const int G = (int)gridDim.x;
+  if (MRLBM_XCD && G % NXCD == 0) {
+    const int x = (int)blockIdx.x % NXCD, slot = (int)blockIdx.x / NXCD;
+    const int lo = (int)((long long)total * x / NXCD), hi = (int)((long long)total * (x + 1) / NXCD);
+    return {lo + slot * per_block + sub, hi, (G / NXCD) * per_block};
+  }
+  return {(int)blockIdx.x * per_block + sub, total, G * per_block};
+}
+#define MRLBM_FOR_CHUNKS(ch, total, per_block, sub) \
+  for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
+    if (const int ch = cs_.ch; true)
+
 // ---------------------------------------------------------------- reconstruction
 // Projection P_nabla on the internal cells of level l (section "Projection and
 // prediction operators"), children read at level l+1 of the same buffer.
@@ -79,7 +106,7 @@ __global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__r
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -97,7 +124,7 @@ __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__res
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_GHOST, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -121,7 +148,7 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
   __shared__ T dm[Q][64];
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, -1);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     const bool valid = item < s.cnt[i];
@@ -180,6 +207,61 @@ __device__ __forceinline__ void chunk_block(const uint32_t *__restrict__ binfo, 
   base = (long long)(w >> 13) * CCHUNK;
 }
 
+// ---------------------------------------------------------------- 16-cell runs
+// Sixteen consecutive byte flags or codes of one level as four little-endian
+// words. Runs start at multiples of 16 cells; `vec` (uniform per block) says
+// that the level is 16-byte aligned and holds at least 16 cells, so a run is
+// one 16-byte access. Otherwise bytes at or beyond nl read as 0.
+struct Run16 {
+  uint32_t w[4];
+};
+__device__ __forceinline__ Run16 ld16(const uint8_t *__restrict__ p, long long c0, long long nl, bool vec) {
+  Run16 r;
+  if (vec) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p + c0);
+    r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.w[k] = 0;
+    for (int t = 0; t < 16; ++t)
+      if (c0 + t < nl) r.w[t >> 2] |= (uint32_t)p[c0 + t] << (8 * (t & 3));
+  }
+  return r;
+}
+__device__ __forceinline__ void st16(uint8_t *__restrict__ p, long long c0, long long nl, bool vec, const Run16 &r) {
+  if (vec) {
+    *reinterpret_cast<uint4 *>(p + c0) = make_uint4(r.w[0], r.w[1], r.w[2], r.w[3]);
+  } else {
+    for (int t = 0; t < 16; ++t)
+      if (c0 + t < nl) p[c0 + t] = (uint8_t)(r.w[t >> 2] >> (8 * (t & 3)));
+  }
+}
+// out[t] = in[t + 1], in[16] = next (a byte).
+__device__ __forceinline__ Run16 run_next(const Run16 &a, uint32_t next) {
+  Run16 r;
+  r.w[0] = (a.w[0] >> 8) | (a.w[1] << 24);
+  r.w[1] = (a.w[1] >> 8) | (a.w[2] << 24);
+  r.w[2] = (a.w[2] >> 8) | (a.w[3] << 24);
+  r.w[3] = (a.w[3] >> 8) | (next << 24);
+  return r;
+}
+// out[t] = in[t - 1], in[-1] = prev (a byte).
+__device__ __forceinline__ Run16 run_prev(const Run16 &a, uint32_t prev) {
+  Run16 r;
+  r.w[0] = (a.w[0] << 8) | prev;
+  r.w[1] = (a.w[1] << 8) | (a.w[0] >> 24);
+  r.w[2] = (a.w[2] << 8) | (a.w[1] >> 24);
+  r.w[3] = (a.w[3] << 8) | (a.w[2] >> 24);
+  return r;
+}
+// Bytes 0, 2, 4, 6 of the eight bytes (lo, hi) packed into one word.
+__device__ __forceinline__ uint32_t even_bytes(uint32_t lo, uint32_t hi) {
+  return (lo & 0xffu) | ((lo >> 8) & 0xff00u) | ((hi & 0xffu) << 16) | ((hi << 8) & 0xff000000u);
+}
+__device__ __forceinline__ bool level_vec(const uint8_t *p, long long nl) {
+  return nl >= 16 && (((uintptr_t)p) & 15u) == 0;
+}
+
 // Ancestor closure of the thresholded set: the group of the parent of every kept
 // cell of level l is kept. One thread per cell g of level l-2 (its 4^d
 // grandchildren are read).
@@ -209,38 +291,62 @@ __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__res
 // H_eps (section "Construction of the time adaptive mesh"): a cell of level l is
 // in the enlarged set if it is kept, if it is k - eta^h for a kept k (eq.
 // AdditionNeigh), or if its parent belongs to a group flagged for refinement.
-// Level jmin is always complete. One thread per cell of every instance.
+// Level jmin is always complete. Each thread takes 16 consecutive cells of a
+// row: the shifted runs of the rows y + eta_y, ORed (rows of at least 16
+// cells), else cell by cell.
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__restrict__ I,
                                                  const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ keep,
                                                  const uint8_t *__restrict__ refg, uint8_t *__restrict__ tnew) {
+  using V = Vel<SCHEME>;
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
   const Inst<T> &In = I[i];
   const long long nl = ncells_d(DIM, l);
+  const long long c0 = base + CPT * threadIdx.x;
+  if (c0 >= nl) return;
   const uint8_t *kl = keep + In.loff[l];
   const uint8_t *rg = l >= In.jmin + 2 ? refg + In.loff[l - 2] : nullptr;
   uint8_t *tl = tnew + In.loff[l];
+  const bool vec = level_vec(kl, nl) && level_vec(tl, nl) && l >= 4;
+  Run16 v;
+  if (l == In.jmin) {
 #pragma unroll
-  for (int it = 0; it < CITER; ++it) {
-    const long long c = base + it * BLK + threadIdx.x;
-    if (c >= nl) continue;
-    uint8_t v = 1;
-    if (l > In.jmin) {
+    for (int k = 0; k < 4; ++k) v.w[k] = 0x01010101u;
+  } else if (vec) {  // rows (2D) or the level (1D) hold at least 16 cells
+    int x0, y;
+    coords<DIM>(l, (uint32_t)c0, x0, y);
+    v = ld16(kl + cidx<DIM>(l, 0, y), x0, nl, true);  // the kept cells themselves
+#pragma unroll
+    for (int h = 0; h < V::Q; ++h) {
+      const int ex = V::ex(h), ey = V::ey(h);
+      if (ex == 0 && ey == 0) continue;
+      const uint8_t *row = kl + cidx<DIM>(l, 0, wrapl(y + ey, l));
+      const Run16 a = ld16(row, x0, nl, true);
+      const Run16 t = ex == 0 ? a : ex > 0 ? run_next(a, row[wrapl(x0 + 16, l)]) : run_prev(a, row[wrapl(x0 - 1, l)]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v.w[k] |= t.w[k];
+    }
+    if (rg) {  // 16 cells have 4 grandparents (x >> 2)
+      const uint8_t *g = rg + cidx<DIM>(l - 2, x0 >> 2, y >> 2);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v.w[k] |= (uint32_t)g[k] * 0x01010101u;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v.w[k] = 0;
+    for (int t = 0; t < 16 && c0 + t < nl; ++t) {
+      const long long c = c0 + t;
       int x, y;
       coords<DIM>(l, (uint32_t)c, x, y);
-      v = kl[c];
-#pragma unroll
-      for (int h = 0; h < Vel<SCHEME>::Q; ++h) {
-        const int ex = Vel<SCHEME>::ex(h), ey = Vel<SCHEME>::ey(h);
-        if (ex == 0 && ey == 0) continue;
-        v |= kl[cidx<DIM>(l, wrapl(x + ex, l), wrapl(y + ey, l))];
-      }
-      if (rg) v |= rg[cidx<DIM>(l - 2, x >> 2, y >> 2)];
+      uint32_t b = kl[c];
+      for (int h = 0; h < V::Q; ++h) b |= kl[cidx<DIM>(l, wrapl(x + V::ex(h), l), wrapl(y + V::ey(h), l))];
+      if (rg) b |= rg[cidx<DIM>(l - 2, x >> 2, y >> 2)];
+      v.w[t >> 2] |= (b ? 1u : 0u) << (8 * (t & 3));
     }
-    tl[c] = v ? 1 : 0;
   }
+  st16(tl, c0, nl, vec, v);
 }
 
 // Grading G, level l: every sibling group of level l with one member gets all
@@ -273,7 +379,9 @@ __global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restri
   if (box) tp[cell] = 1;
 }
 
-// Codes of the tree cells of a 0/1 membership array: leaf or internal.
+// Codes of the tree cells of a 0/1 membership array: leaf, or internal when
+// its first child is in the tree. Sixteen consecutive cells per thread; their
+// first children are the even bytes of 32 cells of the finer row.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo,
@@ -283,24 +391,37 @@ __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *
   chunk_block(binfo, i, l, base);
   const Inst<T> &In = I[i];
   const long long nl = ncells_d(DIM, l);
+  const long long c0 = base + CPT * threadIdx.x;
+  if (c0 >= nl) return;
   const uint8_t *tl = tnew + In.loff[l];
   const uint8_t *tf = l < In.jmax ? tnew + In.loff[l + 1] : nullptr;
   uint8_t *cl = code + In.loff[l];
-#pragma unroll
-  for (int it = 0; it < CITER; ++it) {
-    const long long c = base + it * BLK + threadIdx.x;
-    if (c >= nl) continue;
-    uint8_t v = C_NONE;
-    if (tl[c]) {
-      v = C_LEAF;
-      if (tf) {
+  const bool vec = level_vec(tl, nl) && level_vec(cl, nl) && (!tf || level_vec(tf, 2 * nl)) && l >= 4;
+  const Run16 t = ld16(tl, c0, nl, vec);
+  uint32_t ch[4] = {0, 0, 0, 0};
+  if (tf) {
+    if (vec) {
+      int x0, y;
+      coords<DIM>(l, (uint32_t)c0, x0, y);
+      const uint8_t *row = tf + cidx<DIM>(l + 1, 2 * x0, 2 * y);
+      const Run16 a = ld16(row, 0, 16, true), b = ld16(row, 16, 16, true);
+      ch[0] = even_bytes(a.w[0], a.w[1]);
+      ch[1] = even_bytes(a.w[2], a.w[3]);
+      ch[2] = even_bytes(b.w[0], b.w[1]);
+      ch[3] = even_bytes(b.w[2], b.w[3]);
+    } else {
+      for (int k = 0; k < 16 && c0 + k < nl; ++k) {
         int x, y;
-        coords<DIM>(l, (uint32_t)c, x, y);
-        if (tf[cidx<DIM>(l + 1, 2 * x, 2 * y)]) v = C_INTERNAL;
+        coords<DIM>(l, (uint32_t)(c0 + k), x, y);
+        ch[k >> 2] |= (uint32_t)tf[cidx<DIM>(l + 1, 2 * x, 2 * y)] << (8 * (k & 3));
       }
     }
-    cl[c] = v;
   }
+  // per byte (0/1 flags): in tree -> bit 1; in tree without a first child -> bit 0
+  Run16 v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v.w[k] = (t.w[k] << 1) | (t.w[k] & ~ch[k]);
+  st16(cl, c0, nl, vec, v);
 }
 
 // Four consecutive codes starting at p (byte loads if p is not 4-byte aligned).
@@ -395,62 +516,86 @@ __device__ __forceinline__ int cat_of(uint8_t v) {
 }
 
 
+// Category counts (leaf, internal, ghost) of four codes in a word: leaf = 3,
+// internal = 2, ghost = 1.
+__device__ __forceinline__ void count_codes(uint32_t w, int *n) {
+  const uint32_t lo = w & 0x01010101u, hi = (w >> 1) & 0x01010101u;
+  n[CAT_LEAF] += __popc(lo & hi);
+  n[CAT_INTERNAL] += __popc(hi & ~lo);
+  n[CAT_GHOST] += __popc(lo & ~hi);
+}
+
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_count(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                        int *__restrict__ bcnt, int nblocks) {
-  __shared__ int cnt[NCAT];
+  __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
   const long long nl = ncells_d(DIM, l);
-  if (threadIdx.x < NCAT) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const long long c0 = base + 4 * threadIdx.x;
-  int mine[NCAT] = {0, 0, 0};
+  const uint8_t *cl = code + I[i].loff[l];
+  const long long c0 = base + CPT * threadIdx.x;
+  int n[NCAT] = {0, 0, 0};
   if (c0 < nl) {
-    const uint32_t w = load4(code + I[i].loff[l] + c0);
-    const int valid = nl - c0 >= 4 ? 4 : (int)(nl - c0);
-    for (int t = 0; t < valid; ++t) {
-      const int k = cat_of((uint8_t)(w >> (8 * t)));
-      if (k >= 0) mine[k]++;
-    }
+    const Run16 r = ld16(cl, c0, nl, level_vec(cl, nl));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) count_codes(r.w[k], n);
   }
-  for (int k = 0; k < NCAT; ++k)
-    if (mine[k]) atomicAdd(&cnt[k], mine[k]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NCAT; ++k) {
+    int v = n[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[k][wave] = v;
+  }
   __syncthreads();
-  if (threadIdx.x < NCAT) bcnt[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < NCAT) {
+    int v = 0;
+    for (int w = 0; w < BLK / 64; ++w) v += wsum[threadIdx.x][w];
+    bcnt[threadIdx.x * nblocks + blockIdx.x] = v;
+  }
 }
 
 // One block per instance: exclusive scan of its block counts (list positions
 // start at the instance's first cell), then its per-level list offsets.
+// Wavefront scans by shuffles, then a scan of the wavefront totals.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *__restrict__ I,
                                                        const int *__restrict__ cbp, const int *__restrict__ bcnt,
                                                        int *__restrict__ boff, int *__restrict__ lvl, int nblocks) {
-  __shared__ int buf[1024];
+  __shared__ int wtot[16];
+  __shared__ int carry_s;
   const int i = blockIdx.x;
   const Inst<T> &In = I[i];
   const int b0 = cbp[i], b1 = cbp[i + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < NCAT; ++k) {
     int carry = (int)In.cbase;
     for (int base = b0; base < b1; base += 1024) {
       const int b = base + threadIdx.x;
       const int v = b < b1 ? bcnt[k * nblocks + b] : 0;
-      buf[threadIdx.x] = v;
-      __syncthreads();
-      for (int off = 1; off < 1024; off <<= 1) {
-        const int t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-        __syncthreads();
-        buf[threadIdx.x] += t;
-        __syncthreads();
+      int incl = v;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
       }
-      if (b < b1) boff[k * nblocks + b] = carry + buf[threadIdx.x] - v;
-      const int tot = buf[1023];
+      if (lane == 63) wtot[wave] = incl;
       __syncthreads();
-      carry += tot;
+      if (wave == 0) {
+        int wv = lane < 16 ? wtot[lane] : 0, wi = wv;
+        for (int off = 1; off < 16; off <<= 1) {
+          const int t = __shfl_up(wi, off, 64);
+          if (lane >= off) wi += t;
+        }
+        if (lane < 16) wtot[lane] = wi - wv;  // exclusive prefix of the wavefront totals
+        if (lane == 15) carry_s = wi;
+      }
+      __syncthreads();
+      if (b < b1) boff[k * nblocks + b] = carry + wtot[wave] + incl - v;
+      carry += carry_s;
+      __syncthreads();
     }
-    __syncthreads();
     int *L = lvl + (i * NCAT + k) * LVL_STRIDE;
     for (int l = threadIdx.x; l < LVL_STRIDE; l += blockDim.x) {
       int v;
@@ -473,21 +618,17 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
   long long base;
   chunk_block(binfo, i, l, base);
   const long long nl = ncells_d(DIM, l);
+  const uint8_t *cl = code + I[i].loff[l];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long c0 = base + 4 * threadIdx.x;
-  uint32_t w = 0;
-  int valid = 0;
-  if (c0 < nl) {
-    w = load4(code + I[i].loff[l] + c0);
-    valid = nl - c0 >= 4 ? 4 : (int)(nl - c0);
-  }
-  int cnt[NCAT] = {0, 0, 0}, incl[NCAT];
-  for (int t = 0; t < valid; ++t) {
-    const int k = cat_of((uint8_t)(w >> (8 * t)));
-    if (k >= 0) cnt[k]++;
-  }
+  const long long c0 = base + CPT * threadIdx.x;
+  Run16 r = {{0, 0, 0, 0}};
+  if (c0 < nl) r = ld16(cl, c0, nl, level_vec(cl, nl));
+  int n[NCAT] = {0, 0, 0}, incl[NCAT];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) count_codes(r.w[k], n);
+#pragma unroll
   for (int k = 0; k < NCAT; ++k) {  // inclusive scan over the wavefront
-    int v = cnt[k];
+    int v = n[k];
     for (int off = 1; off < 64; off <<= 1) {
       const int u = __shfl_up(v, off, 64);
       if (lane >= off) v += u;
@@ -496,15 +637,18 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     if (lane == 63) wsum[k][wave] = v;
   }
   __syncthreads();
+  if (!(r.w[0] | r.w[1] | r.w[2] | r.w[3])) return;
   int pos[NCAT];
+#pragma unroll
   for (int k = 0; k < NCAT; ++k) {
     int before = 0;
     for (int ww = 0; ww < wave; ++ww) before += wsum[k][ww];
-    pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - cnt[k];
+    pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - n[k];
   }
-  for (int t = 0; t < valid; ++t) {
-    const int k = cat_of((uint8_t)(w >> (8 * t)));
-    if (k >= 0) lists[k * bt.ctotal + pos[k]++] = ((uint32_t)l << LEVEL_SHIFT) | (uint32_t)(c0 + t);
+  const uint32_t tag = (uint32_t)l << LEVEL_SHIFT;
+  for (int t = 0; t < 16; ++t) {
+    const int k = cat_of((uint8_t)(r.w[t >> 2] >> (8 * (t & 3))));
+    if (k >= 0) lists[k * bt.ctotal + pos[k]++] = tag | (uint32_t)(c0 + t);
   }
 }
 
@@ -520,7 +664,7 @@ __global__ void __launch_bounds__(64 * Q) k_transfer(Batch bt, const Inst<T> *__
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -635,7 +779,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     atomicAdd(&counters[1], 1ull);
   }
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x; ch < s.pre[bt.B]; ch += gridDim.x) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     const bool valid = item < s.cnt[i];
@@ -673,6 +817,36 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
   }
 }
 
+// One leaf of the per-leaf variant: transport of every population, optional
+// tape of the pre-collision values, collision, store.
+template <int DIM, int SCHEME, typename T>
+__device__ __forceinline__ void leaf_update(const Inst<T> &In, int l, uint32_t c, const T *__restrict__ Fs,
+                                            T *__restrict__ Fo, const uint8_t *__restrict__ code,
+                                            const T *__restrict__ Wt, const T *__restrict__ Ct, T *__restrict__ tape) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q;
+  constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const int J = In.jmax, n = J - l;
+  const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
+  const uint8_t *cl = code + In.loff[l];
+  const unsigned nbr = n > 0 ? refined_neighbours<DIM>(cl, l, x, y) : 0u;
+  const long long of = n > 0 ? (long long)Q * In.loff[l + 1] : ol, nf = ncells_d(DIM, l + 1);
+  const int nn = n > 0 ? n - 1 : 0;
+  T f[Q];
+#pragma unroll
+  for (int h = 0; h < Q; ++h)
+    f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fs + ol + h * nl, Fs + of + h * nf, cl,
+                                         Wt + ((long long)nn * Q + h) * WS, Ct + ((long long)nn * Q + h) * CS, nbr);
+  if (tape)
+#pragma unroll
+    for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
+  collide<SCHEME, T>(f, In.sc);
+#pragma unroll
+  for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
+}
+
 // Variant for large leaf sets: one thread per leaf, all populations in
 // registers, no barriers; every wavefront takes a chunk of 64 leaves.
 template <int DIM, int SCHEME, typename T>
@@ -681,9 +855,6 @@ __global__ void __launch_bounds__(BLK)
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
                              unsigned long long *__restrict__ counters, T *__restrict__ tape) {
-  using V = Vel<SCHEME>;
-  constexpr int Q = V::Q;
-  constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
   constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
@@ -694,7 +865,7 @@ __global__ void __launch_bounds__(BLK)
     atomicAdd(&counters[1], 1ull);
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ch = blockIdx.x * WPB + wave; ch < s.pre[bt.B]; ch += gridDim.x * WPB) {
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -702,25 +873,7 @@ __global__ void __launch_bounds__(BLK)
     const uint32_t e = leaves[s.beg[i] + item];
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    int x, y;
-    coords<DIM>(l, c, x, y);
-    const int J = In.jmax, n = J - l;
-    const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
-    const uint8_t *cl = code + In.loff[l];
-    const unsigned nbr = n > 0 ? refined_neighbours<DIM>(cl, l, x, y) : 0u;
-    const long long of = n > 0 ? (long long)Q * In.loff[l + 1] : ol, nf = ncells_d(DIM, l + 1);
-    const int nn = n > 0 ? n - 1 : 0;
-    T f[Q];
-#pragma unroll
-    for (int h = 0; h < Q; ++h)
-      f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fs + ol + h * nl, Fs + of + h * nf, cl,
-                                           Wt + ((long long)nn * Q + h) * WS, Ct + ((long long)nn * Q + h) * CS, nbr);
-    if (tape)
-#pragma unroll
-      for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
-    collide<SCHEME, T>(f, In.sc);
-#pragma unroll
-    for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
+    leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);
   }
 }
 

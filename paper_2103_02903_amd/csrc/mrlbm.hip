@@ -134,7 +134,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Cells per block of the dense per-level passes: ghost classification (off 0)
 // takes 4 cells per thread, grading (1) and ancestor closure (2) one.
-long long dense_cells(int off) { return off == 0 ? (long long)CCHUNK : (long long)BLK; }
+long long dense_cells(int off) { return off == 0 ? (long long)GCHUNK : (long long)BLK; }
 
 // Static description of a batch: instance descriptors (double-precision
 // thresholds; converted to the working precision on upload), block tables, and
@@ -346,6 +346,8 @@ unsigned grid_cap(long long n, unsigned cap) {
   if (n < 1) n = 1;
   return (unsigned)(n > cap ? cap : n);
 }
+// Grid of a list kernel: a multiple of the 8 XCDs (see chunk_sched).
+unsigned list_grid(long long chunks, unsigned cap) { return (grid_cap(chunks, cap) + NXCD - 1) / NXCD * NXCD; }
 
 }  // namespace
 
@@ -428,9 +430,9 @@ struct Engine {
     long long n = 0;
     for (int i = 0; i < c->P.B; ++i)
       if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (DIM * l)) + CHUNK - 1) / CHUNK;
-    return grid_cap(n, LIST_GRID_LEVEL);
+    return list_grid(n, LIST_GRID_LEVEL);
   }
-  static unsigned chunks_all(mrlbm_ctx *c) { return grid_cap((c->P.ctotal + CHUNK - 1) / CHUNK, LIST_GRID_ALL); }
+  static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, LIST_GRID_ALL); }
 
   static void compact(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
@@ -511,7 +513,7 @@ struct Engine {
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
     const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
     if (per_leaf)
-      k_transport_collide_leaf<DIM, SCHEME, T><<<grid_cap((P.ctotal + BLK - 1) / BLK, LIST_GRID_ALL), BLK, 0,
+      k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, LIST_GRID_ALL), BLK, 0,
                                                  c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
                                                               (const T *)c->W, (const T *)c->C, c->cnt, tape);
     else
