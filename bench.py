@@ -158,6 +158,12 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None):
     stats = [sim.stats(i) for i in range(sim.B)]
     finest = sum(1 << (sim.dim * int(c["jmax"])) for c, _ in items)
     leaves_now = sum(int(st["leaves"].sum()) for st in stats)
+    by_n = {}
+    for (c, _), st in zip(items, stats):
+        J = int(c["jmax"])
+        for l, k in enumerate(st["leaves"]):
+            if k:
+                by_n[J - l] = by_n.get(J - l, 0) + int(k)
     res = dict(value=leaf_updates / (elapsed_ms * 1e-3), ms_per_step=elapsed_ms / steps, steps=steps,
                warmup=warmup, leaf_updates=leaf_updates, transport_avg_launch_ms=avg_ms,
                transport_bytes_per_launch=bytes_per_launch, transport_gbs=achieved,
@@ -166,7 +172,8 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None):
                mean_leaves_per_step=leaf_updates / max(1, steps),
                compression_rate_final=1.0 - leaves_now / finest,
                compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
-               mass_final=sum(st["mass"] for st in stats))
+               mass_final=sum(st["mass"] for st in stats),
+               final_leaves_by_levels_above_finest={str(k): by_n[k] for k in sorted(by_n)})
     return res, sim, state0
 
 
@@ -378,6 +385,7 @@ def main():
         "transport_kernel_leaf_updates_per_s": head["transport_leaf_updates_per_s"],
         "phase_ms_per_step_eager": phases,
         "mass_final": head["mass_final"],
+        "final_leaves_by_levels_above_finest": head["final_leaves_by_levels_above_finest"],
     }
     if not args.no_variants and args.workload == "d2q9_shear_batch96" and precision == 4:
         out["variants"] = variants(args, head)

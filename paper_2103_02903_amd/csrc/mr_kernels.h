@@ -266,14 +266,10 @@ __device__ __forceinline__ bool level_vec(const uint8_t *p, long long nl) {
 // cell of level l is kept. One thread per cell g of level l-2 (its 4^d
 // grandchildren are read).
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
-                                                  const uint32_t *__restrict__ info, int l) {
-  int i;
-  const long long cell = dense_block(info, i);
+__device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__restrict__ keep, int l, long long cell) {
   const int lg = l - 2;
-  if (cell >= ncells_d(DIM, lg)) return;
-  const uint8_t *kl = keep + I[i].loff[l];
-  uint8_t *kp = keep + I[i].loff[l - 1];
+  const uint8_t *kl = keep + In.loff[l];
+  uint8_t *kp = keep + In.loff[l - 1];
   int x, y;
   coords<DIM>(lg, (uint32_t)cell, x, y);
   bool any = false;
@@ -286,6 +282,14 @@ __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__res
   if (any)
     for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
       for (int dx = 0; dx < 2; ++dx) kp[cidx<DIM>(l - 1, 2 * x + dx, 2 * y + dy)] = 1;
+}
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
+                                                  const uint32_t *__restrict__ info, int l) {
+  int i;
+  const long long cell = dense_block(info, i);
+  if (cell >= ncells_d(DIM, l - 2)) return;
+  ancestor_cell<DIM, T>(I[i], keep, l, cell);
 }
 
 // H_eps (section "Construction of the time adaptive mesh"): a cell of level l is
@@ -353,14 +357,10 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
 // of them, and every cell of level l-1 whose 3^d box holds a parent of a level-l
 // tree cell joins the tree. One thread per cell of level l-1.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
-                                               const uint32_t *__restrict__ info, int l) {
-  int i;
-  const long long cell = dense_block(info, i);
+__device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restrict__ tnew, int l, long long cell) {
   const int lp = l - 1;
-  if (cell >= ncells_d(DIM, lp)) return;
-  uint8_t *tl = tnew + I[i].loff[l];
-  uint8_t *tp = tnew + I[i].loff[lp];
+  uint8_t *tl = tnew + In.loff[l];
+  uint8_t *tp = tnew + In.loff[lp];
   int x, y;
   coords<DIM>(lp, (uint32_t)cell, x, y);
   bool own = false, box = false;
@@ -377,6 +377,14 @@ __global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restri
     for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
       for (int dx = 0; dx < 2; ++dx) tl[cidx<DIM>(l, 2 * x + dx, 2 * y + dy)] = 1;
   if (box) tp[cell] = 1;
+}
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
+                                               const uint32_t *__restrict__ info, int l) {
+  int i;
+  const long long cell = dense_block(info, i);
+  if (cell >= ncells_d(DIM, l - 1)) return;
+  grade_cell<DIM, T>(I[i], tnew, l, cell);
 }
 
 // Codes of the tree cells of a 0/1 membership array: leaf, or internal when
@@ -443,14 +451,8 @@ __device__ __forceinline__ uint32_t byte_eq_mask(uint32_t w, uint32_t v) {
 // l+1 (prediction of that ghost). Each thread classifies 4 consecutive cells of
 // a row (level l >= 2) from aligned 4-cell words of the rows around them.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> *__restrict__ I,
-                                                        uint8_t *__restrict__ code, const uint32_t *__restrict__ info,
-                                                        int l) {
-  const uint32_t w = info[blockIdx.x];
-  const int i = (int)(w & 0xffu);
-  const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
-  if (c0 >= ncells_d(DIM, l)) return;
-  uint8_t *cl = code + I[i].loff[l];
+__device__ __forceinline__ void ghost_run4(const Inst<T> &In, uint8_t *__restrict__ code, int l, long long c0) {
+  uint8_t *cl = code + In.loff[l];
   const uint32_t own = load4(cl + c0);
   if (byte_eq_mask(own, C_NONE) == 0) return;
   int x0, y;
@@ -466,8 +468,8 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> 
   }
   // ghosts of level l+1: columns 2x0-4 .. 2x0+11 (four words) of rows 2y-2 .. 2y+3
   uint32_t ghostm = 0;
-  if (l < I[i].jmax) {
-    const uint8_t *cf = code + I[i].loff[l + 1];
+  if (l < In.jmax) {
+    const uint8_t *cf = code + In.loff[l + 1];
     const int lf = l + 1, nwf = 2 * nw;
     for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 3 : 0); ++b) {
       const uint8_t *row = cf + (DIM == 2 ? ((long long)wrapl(2 * y + b, lf) << lf) : 0);
@@ -484,6 +486,103 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> 
     const bool need = ((leafm >> (t + 2)) & 0x1fu) || ((ghostm >> (2 * t + 2)) & 0x3fu);
     if (need) cl[c0 + t] = C_GHOST;
   }
+}
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> *__restrict__ I,
+                                                        uint8_t *__restrict__ code, const uint32_t *__restrict__ info,
+                                                        int l) {
+  const uint32_t w = info[blockIdx.x];
+  const int i = (int)(w & 0xffu);
+  const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
+  if (c0 >= ncells_d(DIM, l)) return;
+  ghost_run4<DIM, T>(I[i], code, l, c0);
+}
+
+// Byte flags (0/1) of the codes equal to C_LEAF, C_GHOST and C_NONE in a word.
+__device__ __forceinline__ uint32_t leaf_flags(uint32_t w) { return w & (w >> 1) & 0x01010101u; }
+__device__ __forceinline__ uint32_t ghost_flags(uint32_t w) { return w & ~(w >> 1) & 0x01010101u; }
+__device__ __forceinline__ uint32_t none_flags(uint32_t w) { return ~(w | (w >> 1)) & 0x01010101u; }
+
+// Same classification as k_classify_ghost for 16 consecutive cells of a row
+// per thread (levels whose rows hold at least 16 cells and whose code arrays
+// are 16-byte aligned). Leaves of level l in the 5-wide window of each cell:
+// the OR of the leaf flags of rows y-2..y+2, dilated by two bytes each way.
+// Ghosts of level l+1 in columns 2x-2..2x+3 of rows 2y-2..2y+3: the OR of
+// those six rows, folded into column pairs (pair t covers columns 2t, 2t+1),
+// dilated by one pair each way.
+template <int DIM, typename T>
+__device__ __forceinline__ void ghost_run16(const Inst<T> &In, uint8_t *__restrict__ code, int l, long long c0) {
+  const long long nl = ncells_d(DIM, l);
+  uint8_t *cl = code + In.loff[l];
+  const Run16 own = ld16(cl, c0, nl, true);
+  Run16 none;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) none.w[k] = none_flags(own.w[k]);
+  if (!(none.w[0] | none.w[1] | none.w[2] | none.w[3])) return;
+  int x0, y;
+  coords<DIM>(l, (uint32_t)c0, x0, y);
+  // leaves of level l: OR of the rows, edge bytes x0-2, x0-1, x0+16, x0+17
+  Run16 lf = {{0, 0, 0, 0}};
+  uint32_t em2 = 0, em1 = 0, ep0 = 0, ep1 = 0;
+  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b) {
+    const uint8_t *row = cl + cidx<DIM>(l, 0, wrapl(y + b, l));
+    const Run16 a = ld16(row, x0, nl, true);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lf.w[k] |= leaf_flags(a.w[k]);
+    em2 |= leaf_flags(row[wrapl(x0 - 2, l)]);
+    em1 |= leaf_flags(row[wrapl(x0 - 1, l)]);
+    ep0 |= leaf_flags(row[wrapl(x0 + 16, l)]);
+    ep1 |= leaf_flags(row[wrapl(x0 + 17, l)]);
+  }
+  const Run16 n1 = run_next(lf, ep0), n2 = run_next(n1, ep1);
+  const Run16 p1 = run_prev(lf, em1), p2 = run_prev(p1, em2);
+  Run16 need;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) need.w[k] = lf.w[k] | n1.w[k] | n2.w[k] | p1.w[k] | p2.w[k];
+  if (l < In.jmax) {  // ghosts of level l+1
+    const int lf1 = l + 1;
+    const uint8_t *cf = code + In.loff[lf1];
+    Run16 ga = {{0, 0, 0, 0}}, gb = {{0, 0, 0, 0}};
+    uint32_t pm = 0, pp = 0;
+    for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 3 : 0); ++b) {
+      const uint8_t *row = cf + cidx<DIM>(lf1, 0, wrapl(2 * y + b, lf1));
+      const Run16 a = ld16(row, 2 * x0, 2 * nl, true), c = ld16(row, 2 * x0 + 16, 2 * nl, true);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ga.w[k] |= ghost_flags(a.w[k]);
+        gb.w[k] |= ghost_flags(c.w[k]);
+      }
+      pm |= ghost_flags(row[wrapl(2 * x0 - 2, lf1)]) | ghost_flags(row[wrapl(2 * x0 - 1, lf1)]);
+      pp |= ghost_flags(row[wrapl(2 * x0 + 32, lf1)]) | ghost_flags(row[wrapl(2 * x0 + 33, lf1)]);
+    }
+    Run16 pr;  // pair flags of the 16 cells
+    pr.w[0] = even_bytes(ga.w[0] | (ga.w[0] >> 8), ga.w[1] | (ga.w[1] >> 8));
+    pr.w[1] = even_bytes(ga.w[2] | (ga.w[2] >> 8), ga.w[3] | (ga.w[3] >> 8));
+    pr.w[2] = even_bytes(gb.w[0] | (gb.w[0] >> 8), gb.w[1] | (gb.w[1] >> 8));
+    pr.w[3] = even_bytes(gb.w[2] | (gb.w[2] >> 8), gb.w[3] | (gb.w[3] >> 8));
+    const Run16 pn = run_next(pr, pp), pq = run_prev(pr, pm);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) need.w[k] |= pr.w[k] | pn.w[k] | pq.w[k];
+  }
+  Run16 out;
+  bool changed = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t g = need.w[k] & none.w[k];  // NONE (0) -> GHOST (1)
+    out.w[k] = own.w[k] | g;
+    changed |= g != 0;
+  }
+  if (changed) st16(cl, c0, nl, true, out);
+}
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_classify_ghost16(Batch bt, const Inst<T> *__restrict__ I,
+                                                          uint8_t *__restrict__ code,
+                                                          const uint32_t *__restrict__ info, int l) {
+  const uint32_t wi = info[blockIdx.x];
+  const int i = (int)(wi & 0xffu);
+  const long long c0 = ((long long)(wi >> 8) * BLK + threadIdx.x) * CPT;
+  if (c0 >= ncells_d(DIM, l)) return;
+  ghost_run16<DIM, T>(I[i], code, l, c0);
 }
 
 // Codes of the initial full finest mesh of instance i: internal below jmax,

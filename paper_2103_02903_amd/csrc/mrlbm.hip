@@ -132,9 +132,15 @@ void transport_tables(int scheme, int n, double *W, double *C) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Cells per block of the dense per-level passes: ghost classification (off 0)
-// takes 4 cells per thread, grading (1) and ancestor closure (2) one.
-long long dense_cells(int off) { return off == 0 ? (long long)GCHUNK : (long long)BLK; }
+// Dense per-level passes: cells per block, and the levels they cover
+// (jmin <= L <= jmax - margin): ghost classification with 4 cells per thread
+// (0) or 16 (3), grading (1, level l-1 of l) and ancestor closure (2, level
+// l-2 of l) with one.
+constexpr int NDENSE = 4;
+long long dense_cells(int off) {
+  return off == 0 ? (long long)GCHUNK : off == 3 ? (long long)CCHUNK : (long long)BLK;
+}
+int dense_margin(int off) { return off == 1 ? 1 : off == 2 ? 2 : 0; }
 
 // Static description of a batch: instance descriptors (double-precision
 // thresholds; converted to the working precision on upload), block tables, and
@@ -146,10 +152,11 @@ struct Plan {
   std::vector<Inst<double>> inst;
   std::vector<long long> cb;   // [B + 1] first cell of each instance
   std::vector<int> cbp;        // [B + 1] first compaction block of each instance
-  std::vector<int> dtab;       // [3][LVL_STRIDE][B + 1] dense-level block prefixes
+  std::vector<int> dtab;       // [NDENSE][LVL_STRIDE][B + 1] dense-level block prefixes
   std::vector<uint32_t> binfo; // [nblocks] instance | level << 8 | chunk << 13 of all-level passes
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
-  std::vector<long long> dstart;  // [3][LVL_STRIDE] first entry of each (off, L) row in dinfo
+  std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
+  bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
   size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_bcnt, off_boff, off_W,
       off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
@@ -212,28 +219,36 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.nblocks = blocks;
   P.nmax = P.maxJ - P.jmin;
   // dense passes over level L of every instance where jmin <= L <= jmax - off
-  P.dtab.assign((size_t)3 * LVL_STRIDE * (B + 1), 0);
-  for (int off = 0; off < 3; ++off)
+  P.dtab.assign((size_t)NDENSE * LVL_STRIDE * (B + 1), 0);
+  for (int off = 0; off < NDENSE; ++off)
     for (int L = 0; L < LVL_STRIDE; ++L) {
       int *row = &P.dtab[((size_t)off * LVL_STRIDE + L) * (B + 1)];
       int acc = 0;
       for (int i = 0; i < B; ++i) {
         row[i] = acc;
-        if (L >= P.jmin && L <= P.inst[i].jmax - off) acc += (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
+        if (L >= P.jmin && L <= P.inst[i].jmax - dense_margin(off))
+          acc += (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
       }
       row[B] = acc;
     }
   P.dinfo.clear();
-  P.dstart.assign((size_t)3 * LVL_STRIDE, 0);
-  for (int off = 0; off < 3; ++off)
+  P.dstart.assign((size_t)NDENSE * LVL_STRIDE, 0);
+  for (int off = 0; off < NDENSE; ++off)
     for (int L = 0; L < LVL_STRIDE; ++L) {
       P.dstart[(size_t)off * LVL_STRIDE + L] = (long long)P.dinfo.size();
       for (int i = 0; i < B; ++i)
-        if (L >= P.jmin && L <= P.inst[i].jmax - off) {
+        if (L >= P.jmin && L <= P.inst[i].jmax - dense_margin(off)) {
           const int nb = (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
           for (int k = 0; k < nb; ++k) P.dinfo.push_back((uint32_t)i | ((uint32_t)k << 8));
         }
     }
+  for (int L = 0; L < LVL_STRIDE; ++L) {
+    bool ok = L >= 4;
+    for (int i = 0; i < B && ok; ++i)
+      if (L >= P.inst[i].jmin && L <= P.inst[i].jmax)
+        ok = P.inst[i].loff[L] % 16 == 0 && (L == P.inst[i].jmax || P.inst[i].loff[L + 1] % 16 == 0);
+    P.ghost16[L] = ok;
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   for (int k = 0; k < 2; ++k) P.off_F[k] = take(P.rs * P.q * P.ctotal);
@@ -447,9 +462,17 @@ struct Engine {
     const Plan &P = c->P;
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m]);
     for (int l = P.maxJ; l > P.jmin; --l) {
-      const int nb = P.dtab_total(0, l);
-      if (nb) k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l);
+      if (P.ghost16[l]) {
+        const int nb = P.dtab_total(3, l);
+        if (nb)
+          k_classify_ghost16<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 3, l), l);
+      } else {
+        const int nb = P.dtab_total(0, l);
+        if (nb)
+          k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l);
+      }
     }
+
     compact(c, m);
   }
 
@@ -481,11 +504,13 @@ struct Engine {
       const int nb = P.dtab_total(2, l - 2);
       if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);
     }
+
     k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
     for (int l = P.maxJ; l >= P.jmin + 1; --l) {
       const int nb = P.dtab_total(1, l - 1);
       if (nb) k_grade<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dinfo_row(c->dinfo, 1, l - 1), l);
     }
+
     classify(c, mn);
     k_transfer<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(c->bt, I(c), Fc, Fn, c->code[mo],
                                                                c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn]);
