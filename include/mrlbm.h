@@ -187,6 +187,30 @@ int mrlbm_forward_record(mrlbm_ctx *ctx, void *adj_workspace, size_t bytes, int 
  * Leaves the context state unspecified (re-initialise or set it before stepping). */
 int mrlbm_adjoint(mrlbm_ctx *ctx, const void *abar_final, void *mbar0, double *sbar);
 
+/* ---- Launch schedule and its autotuner ----
+ * The list kernels (projection, prediction, details, transfer, transport) run
+ * a capped number of blocks that stride over the chunks of 64 list items; the
+ * transport has a per-leaf and a per-population variant. The autotuner times
+ * every schedule of a small grid on the context's current state (steps that
+ * leave the state unchanged, replayed from HIP graphs between HIP events),
+ * keeps the fastest, and caches it for the process per (device architecture,
+ * scheme, precision, floor(log2(leaves))). Schedules do not change results. */
+typedef struct {
+  int transport_variant; /* 1: one thread per leaf, 2: one wavefront per population */
+  int list_grid_all;     /* block cap of the all-level list kernels (8..65536) */
+  int list_grid_level;   /* block cap of the per-level list kernels (8..65536) */
+  int from_cache;        /* set by mrlbm_autotune: 1 if taken from the cache */
+  double ms_per_step;    /* set by mrlbm_autotune: timed cost of the schedule (0 if cached) */
+} mrlbm_tuning;
+
+/* Time the candidate schedules with `reps` steps each and adopt the fastest.
+ * Synchronous; the state and the leaf counters are unchanged. Needs graph
+ * stepping (not MRLBM_GRAPH=0). Errors: MRLBM_ERR_STATE before initialisation. */
+int mrlbm_autotune(mrlbm_ctx *ctx, int reps, mrlbm_tuning *chosen);
+/* Adopt a schedule / read the current one. */
+int mrlbm_set_tuning(mrlbm_ctx *ctx, const mrlbm_tuning *t);
+int mrlbm_get_tuning(const mrlbm_ctx *ctx, mrlbm_tuning *out);
+
 /* Plain device copy of `bytes` (a multiple of 16, both pointers 16-byte
  * aligned) on `stream`: the reference kernel for bandwidth and for the scale
  * of hardware traffic counters. Asynchronous. */

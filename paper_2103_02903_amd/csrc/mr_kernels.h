@@ -92,9 +92,9 @@ __device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int 
   }
   return {(int)blockIdx.x * per_block + sub, total, G * per_block};
 }
-#define MRLBM_FOR_CHUNKS(ch, total, per_block, sub) \
+#define MRLBM_FOR_CHUNKS(var_, total, per_block, sub) \
   for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
-    if (const int ch = cs_.ch; true)
+    if (const int var_ = cs_.ch; true)
 
 // ---------------------------------------------------------------- reconstruction
 // Projection P_nabla on the internal cells of level l (section "Projection and

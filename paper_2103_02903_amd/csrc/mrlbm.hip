@@ -10,6 +10,10 @@
 #include <cstring>
 #include <new>
 #include <utility>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "mr_adjoint.h"
@@ -389,6 +393,7 @@ struct mrlbm_ctx {
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
   std::vector<char> has_state;
   int transport_variant;  // 0: by size, 1: one thread per leaf, 2: one wavefront per population
+  unsigned grid_all, grid_level;  // block caps of the all-level and per-level list kernels
   // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
   char *adj_ws;
   int adj_nsteps, adj_K;
@@ -430,6 +435,16 @@ void phase_mark(mrlbm_ctx *c, int phase, bool begin) {
 }
 
 constexpr unsigned LIST_GRID_LEVEL = 1024, LIST_GRID_ALL = 4096, DENSE_GRID = 4096;
+
+// Invalidate the captured step graphs (after a change of the launch schedule).
+void drop_graphs(mrlbm_ctx *c) {
+  for (auto &row : c->graph)
+    for (auto &g : row)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
 // Above this many cells (all instances and levels) the transport runs one
 // thread per leaf; below, one wavefront per population (more parallelism for
 // small leaf sets). Both variants compute bit-identical results.
@@ -445,9 +460,9 @@ struct Engine {
     long long n = 0;
     for (int i = 0; i < c->P.B; ++i)
       if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (DIM * l)) + CHUNK - 1) / CHUNK;
-    return list_grid(n, LIST_GRID_LEVEL);
+    return list_grid(n, c->grid_level);
   }
-  static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, LIST_GRID_ALL); }
+  static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, c->grid_all); }
 
   static void compact(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
@@ -538,7 +553,7 @@ struct Engine {
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
     const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
     if (per_leaf)
-      k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, LIST_GRID_ALL), BLK, 0,
+      k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0,
                                                  c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
                                                               (const T *)c->W, (const T *)c->C, c->cnt, tape);
     else
@@ -739,6 +754,50 @@ struct Engine {
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
+  // ------------------------------------------------------------- autotuning
+  // A step that leaves the state as it was: the adaptation writes only the next
+  // mesh and value buffers (its reconstruction of the current buffer recomputes
+  // the values already there), and the transport runs on the current mesh into
+  // the other value buffer. Captured once per schedule and replayed `reps`
+  // times between HIP events.
+  static int time_dry_steps(mrlbm_ctx *c, int reps, float *ms) {
+    const int cur0 = c->cur, m0 = c->mcur;
+    hipStream_t user = c->stream;
+    const bool prof = c->profiling;
+    c->stream = c->cap_stream;
+    c->profiling = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
+    c->cur = cur0;
+    c->mcur = m0;
+    if (rc == MRLBM_OK) rc = transport(c);
+    c->cur = cur0;
+    if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
+    c->stream = user;
+    c->profiling = prof;
+    if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != MRLBM_OK) return rc;
+    if (e != hipSuccess) return MRLBM_ERR_HIP;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess) return MRLBM_ERR_HIP;
+    *ms /= (float)reps;
+    return MRLBM_OK;
+  }
+
   static int upload_inst(mrlbm_ctx *c) {
     std::vector<Inst<T>> v(c->P.B);
     for (int i = 0; i < c->P.B; ++i) {
@@ -778,6 +837,8 @@ template <int D, int S, typename T>
 struct AdaptOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::adapt(c); } };
 template <int D, int S, typename T>
 struct TransportOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::transport(c); } };
+template <int D, int S, typename T>
+struct DryOp { static int run(mrlbm_ctx *c, int reps, float *ms) { return Engine<D, S, T>::time_dry_steps(c, reps, ms); } };
 template <int D, int S, typename T>
 struct StepGraphOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::step_graph(c); } };
 template <int D, int S, typename T>
@@ -916,6 +977,8 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   {
     const char *v = std::getenv("MRLBM_TRANSPORT");
     c->transport_variant = v && !std::strcmp(v, "leaf") ? 1 : v && !std::strcmp(v, "pop") ? 2 : 0;
+    c->grid_all = LIST_GRID_ALL;
+    c->grid_level = LIST_GRID_LEVEL;
   }
   // transport weight tables, rounded once to the working precision
   const int q = P.q, d = P.dim, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
@@ -1117,6 +1180,119 @@ int mrlbm_adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sba
   if (!c || !abar_final || !mbar0 || !sbar || c->P.B != 1) return MRLBM_ERR_INVALID;
   if (!c->adj_ws || c->adj_nsteps < 1) return MRLBM_ERR_STATE;
   return dispatch<AdjointOp>(c, abar_final, mbar0, sbar);
+}
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+struct TuneKey {
+  std::string arch;
+  int scheme, precision, bucket;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(arch, scheme, precision, bucket) < std::tie(o.arch, o.scheme, o.precision, o.bucket);
+  }
+};
+std::mutex tune_mutex;
+std::map<TuneKey, mrlbm_tuning> tune_cache;
+
+int apply_tuning(mrlbm_ctx *c, const mrlbm_tuning &t) {
+  if ((t.transport_variant != 1 && t.transport_variant != 2) || t.list_grid_all < 8 || t.list_grid_all > 65536 ||
+      t.list_grid_level < 8 || t.list_grid_level > 65536)
+    return MRLBM_ERR_INVALID;
+  if (c->transport_variant != t.transport_variant || c->grid_all != (unsigned)t.list_grid_all ||
+      c->grid_level != (unsigned)t.list_grid_level) {
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+  }
+  c->transport_variant = t.transport_variant;
+  c->grid_all = (unsigned)t.list_grid_all;
+  c->grid_level = (unsigned)t.list_grid_level;
+  return MRLBM_OK;
+}
+
+int leaf_total(mrlbm_ctx *c, long long *n) {
+  std::vector<int> lvl((size_t)c->P.B * NCAT * LVL_STRIDE);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(lvl.data(), c->lvl[c->mcur], sizeof(int) * lvl.size(), hipMemcpyDeviceToHost));
+  long long t = 0;
+  for (int i = 0; i < c->P.B; ++i) {
+    const int *L = &lvl[((size_t)i * NCAT + CAT_LEAF) * LVL_STRIDE];
+    t += L[c->P.inst[i].jmax + 1] - L[c->P.inst[i].jmin];
+  }
+  *n = t;
+  return MRLBM_OK;
+}
+}  // namespace
+
+int mrlbm_get_tuning(const mrlbm_ctx *c, mrlbm_tuning *out) {
+  if (!c || !out) return MRLBM_ERR_INVALID;
+  std::memset(out, 0, sizeof *out);
+  out->transport_variant = c->transport_variant ? c->transport_variant
+                                                 : (c->P.ctotal >= LEAF_KERNEL_CELLS ? 1 : 2);
+  out->list_grid_all = (int)c->grid_all;
+  out->list_grid_level = (int)c->grid_level;
+  return MRLBM_OK;
+}
+
+int mrlbm_set_tuning(mrlbm_ctx *c, const mrlbm_tuning *t) {
+  if (!c || !t) return MRLBM_ERR_INVALID;
+  return apply_tuning(c, *t);
+}
+
+int mrlbm_autotune(mrlbm_ctx *c, int reps, mrlbm_tuning *out) {
+  if (!c || !out || reps < 1) return MRLBM_ERR_INVALID;
+  if (!c->all_ready() || !c->use_graph) return MRLBM_ERR_STATE;
+  long long leaves = 0;
+  int rc = leaf_total(c, &leaves);
+  if (rc) return rc;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int bucket = 0;
+  while ((2ll << bucket) <= leaves) ++bucket;  // floor(log2(leaves))
+  const TuneKey key{prop.gcnArchName, c->p[0].scheme, c->p[0].precision, bucket};
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex);
+    auto it = tune_cache.find(key);
+    if (it != tune_cache.end()) {
+      *out = it->second;
+      out->from_cache = 1;
+      return apply_tuning(c, *out);
+    }
+  }
+  // leaf counts are device-side; the timed steps must not disturb them
+  unsigned long long cnt[4];
+  HIPCHK(hipMemcpy(cnt, c->cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  mrlbm_tuning best{};
+  best.ms_per_step = 1e30;
+  const int variants[2] = {1, 2};
+  const int all_caps[4] = {1024, 2048, 4096, 8192};
+  const int level_caps[3] = {256, 1024, 4096};
+  for (int v : variants)
+    for (int ga : all_caps)
+      for (int gl : level_caps) {
+        mrlbm_tuning t{};
+        t.transport_variant = v;
+        t.list_grid_all = ga;
+        t.list_grid_level = gl;
+        rc = apply_tuning(c, t);
+        float ms = 0.f;
+        if (!rc) rc = dispatch<DryOp>(c, reps, &ms);
+        if (rc) return rc;
+        if (ms < best.ms_per_step) {
+          best = t;
+          best.ms_per_step = ms;
+        }
+      }
+  HIPCHK(hipMemcpy(c->cnt, cnt, sizeof cnt, hipMemcpyHostToDevice));
+  rc = apply_tuning(c, best);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex);
+    tune_cache[key] = best;
+  }
+  *out = best;
+  return MRLBM_OK;
 }
 
 int mrlbm_destroy(mrlbm_ctx *c) {

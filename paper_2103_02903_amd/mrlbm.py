@@ -23,7 +23,7 @@ EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mr
            "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
            "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
-           "mrlbm_adjoint", "mrlbm_copy"]
+           "mrlbm_adjoint", "mrlbm_copy", "mrlbm_autotune", "mrlbm_set_tuning", "mrlbm_get_tuning"]
 
 
 class MrlbmError(RuntimeError):
@@ -51,6 +51,14 @@ class Counters(ctypes.Structure):
                 ("adapt_ms", ctypes.c_double), ("timed_launches", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("transport_variant", ctypes.c_int), ("list_grid_all", ctypes.c_int),
+                ("list_grid_level", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -74,6 +82,13 @@ def lib() -> ctypes.CDLL:
             "mrlbm_leaves": [vp, ci, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
             "mrlbm_destroy": [vp], "mrlbm_transport_tables": [ctypes.c_int, ctypes.c_int, vp, vp],
             "mrlbm_profile": [vp, ctypes.c_int], "mrlbm_read_counters": [vp, ctypes.POINTER(Counters)],
+            "mrlbm_adjoint_workspace_size": [vp, ci, ci, ctypes.POINTER(ctypes.c_size_t)],
+            "mrlbm_forward_record": [vp, vp, ctypes.c_size_t, ci, ci],
+            "mrlbm_adjoint": [vp, vp, vp, ctypes.POINTER(ctypes.c_double)],
+            "mrlbm_copy": [vp, vp, ctypes.c_size_t, vp],
+            "mrlbm_autotune": [vp, ci, ctypes.POINTER(Tuning)],
+            "mrlbm_set_tuning": [vp, ctypes.POINTER(Tuning)],
+            "mrlbm_get_tuning": [vp, ctypes.POINTER(Tuning)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -222,6 +237,23 @@ class Batch:
                                                   ctypes.c_void_p(vals.data_ptr()), n, ctypes.byref(count)))
         return cells[:n], vals[:n]
 
+
+    # ---- launch schedule
+    def autotune(self, reps: int = 5) -> dict:
+        """Time the candidate launch schedules on the current state (unchanged)
+        and adopt the fastest; returns the chosen schedule."""
+        t = Tuning()
+        _check("mrlbm_autotune", lib().mrlbm_autotune(self._ctx, int(reps), ctypes.byref(t)))
+        return t.as_dict()
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check("mrlbm_get_tuning", lib().mrlbm_get_tuning(self._ctx, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, transport_variant: int, list_grid_all: int, list_grid_level: int):
+        t = Tuning(int(transport_variant), int(list_grid_all), int(list_grid_level), 0, 0.0)
+        _check("mrlbm_set_tuning", lib().mrlbm_set_tuning(self._ctx, ctypes.byref(t)))
 
     # ---- adjoint on frozen meshes (batch of one)
     def forward_record(self, nsteps: int, ckpt_every: int):

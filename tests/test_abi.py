@@ -21,6 +21,8 @@ def test_library_exports_every_declared_function():
     L = mrlbm.lib()
     for name in decl:
         assert hasattr(L, name)
+        # every entry point is bound with its exact C signature (no default int marshalling)
+        assert getattr(L, name).argtypes is not None, name
 
 
 def test_status_strings():

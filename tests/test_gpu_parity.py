@@ -304,3 +304,48 @@ def _leaf_entries(o, tree):
         for h in range(o.q):
             m[off + h * o.ncells(l): off + (h + 1) * o.ncells(l)] = lm
     return m
+
+
+def test_autotune_keeps_state_and_results(mr):
+    """The autotuner leaves the state and the leaf counters unchanged, the
+    schedule it picks computes the same bits, and a second context with the
+    same key takes the schedule from the cache."""
+    items = W.shear_layer_batch(4, jmax_choices=(6, 7))
+    cfgs = [c for c, _ in items]
+
+    def fresh():
+        b = mr.Batch(cfgs, precision=4)
+        for i, (_, m0) in enumerate(items):
+            b.init_equilibrium(i, m0)
+        b.step(5)
+        return b
+
+    ref = fresh()
+    ref.step(6)
+    want = [ref.get_state(i) for i in range(ref.B)]
+    ref.close()
+
+    b = fresh()
+    before = [b.get_state(i) for i in range(b.B)]
+    b.profile(True)
+    b.step(1)
+    n1 = b.counters()["leaf_updates"]
+    t = b.autotune(reps=2)
+    assert t["transport_variant"] in (1, 2) and t["ms_per_step"] > 0 and t["from_cache"] == 0
+    assert b.counters()["leaf_updates"] == n1
+    assert b.tuning()["list_grid_all"] == t["list_grid_all"]
+    b.step(5)
+    got = [b.get_state(i) for i in range(b.B)]
+    for cfg, sa, sb in zip(cfgs, want, got):
+        leaves = _leaf_entries(oracle.Oracle(cfg), sa[0])
+        assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1][leaves], sb[1][leaves])
+    del before
+
+    c2 = fresh()
+    t2 = c2.autotune(reps=2)
+    assert t2["from_cache"] == 1 and t2["list_grid_all"] == t["list_grid_all"]
+    c2.set_tuning(2, 1024, 256)
+    assert c2.tuning()["transport_variant"] == 2
+    c2.step(2)
+    c2.close()
+    b.close()
