@@ -63,9 +63,9 @@ def workload(name: str):
     return items, desc, prec
 
 
-def measured_traffic(workload_name: str, precision: int):
+def measured_traffic(workload_name: str, precision: int, kernel: str):
     """HBM bytes per transport launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
+    if it was taken on the current kernel source and transport variant (else None)."""
     path = os.path.join(ROOT, "profiles", "transport_collide_%s_fp%d_counters.json" % (workload_name, 8 * precision))
     if not os.path.exists(path):
         return None
@@ -73,7 +73,7 @@ def measured_traffic(workload_name: str, precision: int):
         d = json.load(f)
     from paper_2103_02903_amd.profiling import kernel_source_hash
 
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or not d.get("kernel", "").startswith(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -123,10 +123,14 @@ def copy_bandwidth(nbytes: int = COPY_BYTES, reps: int = 5):
     return dict(bytes_per_launch=2 * nbytes, avg_launch_ms=ms, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
-def timed_run(items, precision, steps, warmup, keep_state_of=None):
-    """Warm up, then time `steps` graph-replayed steps with the transport kernel
-    between HIP events. Returns (result dict, sim, state of instance
-    `keep_state_of` at the start of the timed region or None)."""
+def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, schedule=None, markers=False):
+    """Warm up, pick the launch schedule with the library's autotuner, then time
+    `steps` graph-replayed steps with the transport kernel between HIP events.
+    Returns (result dict, sim, state of instance `keep_state_of` at the start of
+    the timed region or None). `schedule` (transport variant, all-level cap,
+    per-level cap) replaces the autotuner; `markers` brackets the timed region
+    with two 256-byte launches of the copy kernel, which profiles use to find
+    the timed dispatches."""
     import torch
 
     from paper_2103_02903_amd import mrlbm
@@ -136,14 +140,27 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None):
         sim.init_equilibrium(i, m0)
     sim.step(warmup)
     sim.synchronize()
+    if schedule is not None:
+        sim.set_tuning(*schedule)
+        tuning = sim.tuning()
+    else:
+        tuning = sim.autotune(reps=5) if tune else sim.tuning()
+    mark = None
+    if markers:
+        mark = (torch.zeros(256, dtype=torch.uint8, device=sim.device),
+                torch.zeros(256, dtype=torch.uint8, device=sim.device))
     state0 = sim.get_state(keep_state_of) if keep_state_of is not None else None
     sim.profile(True)
     stream = sim.stream
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    if mark is not None:
+        mrlbm.copy(mark[1], mark[0], 256, stream)
     t_start.record(stream)
     sim.step(steps)
     t_end.record(stream)
+    if mark is not None:
+        mrlbm.copy(mark[1], mark[0], 256, stream)
     torch.cuda.synchronize()
     elapsed_ms = t_start.elapsed_time(t_end)
     cnt = sim.counters()
@@ -173,6 +190,8 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None):
                compression_rate_final=1.0 - leaves_now / finest,
                compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
                mass_final=sum(st["mass"] for st in stats),
+               tuning=tuning,
+               transport_kernel="k_transport_collide_%s" % ("leaf" if tuning["transport_variant"] == 1 else "pop"),
                final_leaves_by_levels_above_finest={str(k): by_n[k] for k in sorted(by_n)})
     return res, sim, state0
 
@@ -185,6 +204,8 @@ def phase_breakdown(sim, steps):
 
     eager = mrlbm.Batch(sim.cfgs, precision=sim.precision)
     os.environ.pop("MRLBM_GRAPH")
+    t = sim.tuning()
+    eager.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"])
     for i in range(sim.B):
         t, v = sim.get_state(i)
         eager.set_state(i, t, v)
@@ -326,6 +347,7 @@ def main():
     ap.add_argument("--single-warmup", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=800)
     ap.add_argument("--adjoint-ckpt", type=int, default=50)
+    ap.add_argument("--schedule", default="", help="transport variant,all-level cap,per-level cap (skips autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
     args = ap.parse_args()
@@ -347,8 +369,9 @@ def main():
     precision = args.precision or prec
     # the CPU baseline steps the largest instance from its state at the start of the timed region
     big = max(range(len(items)), key=lambda i: items[i][0]["jmax"])
+    schedule = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
     head, sim, state0 = timed_run(items, precision, args.steps, args.warmup,
-                                  None if args.no_cpu_baseline else big)
+                                  None if args.no_cpu_baseline else big, schedule=schedule, markers=True)
     phases = phase_breakdown(sim, min(args.steps, 100))
     sim.close()
     copy = copy_bandwidth()
@@ -368,13 +391,13 @@ def main():
         "config": {"workload": desc, "name": args.workload, "precision": "fp%d" % (8 * precision),
                    "instances": len(items)},
         "roofline": {
-            "kernel": "k_transport_collide",
+            "kernel": head["transport_kernel"],
             "bound": "hbm",
             "achieved": head["transport_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["transport_frac"],
-            "traffic": measured_traffic(args.workload, precision),
+            "traffic": measured_traffic(args.workload, precision, head["transport_kernel"]),
             "algorithmic_bytes_per_launch": head["transport_bytes_per_launch"],
             "avg_launch_ms": head["transport_avg_launch_ms"],
         },
@@ -385,6 +408,7 @@ def main():
         "transport_kernel_leaf_updates_per_s": head["transport_leaf_updates_per_s"],
         "phase_ms_per_step_eager": phases,
         "mass_final": head["mass_final"],
+        "launch_schedule": head["tuning"],
         "final_leaves_by_levels_above_finest": head["final_leaves_by_levels_above_finest"],
     }
     if not args.no_variants and args.workload == "d2q9_shear_batch96" and precision == 4:

@@ -67,7 +67,7 @@ def read_trace(path: str):
 
 
 def read_counters(path: str, counter: str):
-    """Per dispatch, in start order: (kernel name, counter value summed over rows)."""
+    """Per dispatch, in start order: (kernel name, start ns, counter value summed over rows)."""
     acc = {}
     with open(path, newline="") as f:
         for r in csv.DictReader(f):
@@ -77,11 +77,18 @@ def read_counters(path: str, counter: str):
             if key not in acc:
                 acc[key] = [r["Kernel_Name"], int(r["Start_Timestamp"]), 0.0]
             acc[key][2] += float(r["Counter_Value"])
-    out = sorted(acc.values(), key=lambda t: t[1])
-    return [(n, v) for n, _, v in out]
+    return sorted((tuple(v) for v in acc.values()), key=lambda t: t[1])
 
 
-def select(seq, patterns, skip: int, take: int):
+def select(seq, patterns, skip: int, take: int, window=""):
+    """Dispatches of the kernels matching all patterns, optionally only those
+    starting between the first two dispatches of the kernel named `window`;
+    then `skip` of them are dropped and at most `take` kept."""
+    if window:
+        marks = [x[1] for x in seq if window in x[0]]
+        if len(marks) < 2:
+            raise SystemExit("fewer than two %s markers" % window)
+        seq = [x for x in seq if marks[0] < x[1] < marks[1]]
     hits = [x for x in seq if _matches(x[0], patterns)]
     hits = hits[skip:]
     return hits[:take] if take > 0 else hits
@@ -106,39 +113,40 @@ def stats_summary(args) -> str:
         lines.append("%-58s %8d %12.1f %10.2f %10.2f %10.2f %6.1f" % (name[:58], c, t / 1e3, t / c / 1e3, mn / 1e3,
                                                                      mx / 1e3, 100.0 * t / total))
     if args.match:
-        sel = select(rows, args.match, args.skip, args.take)
+        sel = select(rows, args.match, args.skip, args.take, args.window)
         if sel:
             durs = [e - s for _, s, e in sel]
+            where = ("between the two %s markers" % args.window) if args.window else (
+                "dispatches %d..%d" % (args.skip + 1, args.skip + len(sel)))
             lines += ["",
-                      "timed region: dispatches %d..%d of the kernels matching %s (%s)" % (
-                          args.skip + 1, args.skip + len(sel), " & ".join(repr(p) for p in args.match),
-                          short_name(sel[0][0])),
+                      "timed region: %s, kernels matching %s (%s)" % (
+                          where, " & ".join(repr(p) for p in args.match), short_name(sel[0][0])),
                       "  dispatches %d, average %.3f us, min %.3f us, max %.3f us" % (
                           len(durs), sum(durs) / len(durs) / 1e3, min(durs) / 1e3, max(durs) / 1e3)]
     return "\n".join(lines) + "\n"
 
 
 def counters_summary(args) -> dict:
-    fetch = select(read_counters(args.fetch, "FETCH_SIZE"), args.match, args.skip, args.take)
-    write = select(read_counters(args.write, "WRITE_SIZE"), args.match, args.skip, args.take)
+    fetch = select(read_counters(args.fetch, "FETCH_SIZE"), args.match, args.skip, args.take, args.window)
+    write = select(read_counters(args.write, "WRITE_SIZE"), args.match, args.skip, args.take, args.window)
     cf = select(read_counters(args.copy_fetch, "FETCH_SIZE"), [COPY_KERNEL], 1, 0)  # first launch warms up
     cw = select(read_counters(args.copy_write, "WRITE_SIZE"), [COPY_KERNEL], 1, 0)
     if not fetch or not write or not cf or not cw:
         raise SystemExit("no matching dispatches in the counter files")
-    copy_kib_f = sum(v for _, v in cf) / len(cf)
-    copy_kib_w = sum(v for _, v in cw) / len(cw)
+    copy_kib_f = sum(v for _, _, v in cf) / len(cf)
+    copy_kib_w = sum(v for _, _, v in cw) / len(cw)
     # bytes per counter KiB, from the copy kernel of known size
     sf = args.copy_bytes / copy_kib_f
     sw = args.copy_bytes / copy_kib_w
-    kib_f = sum(v for _, v in fetch) / len(fetch)
-    kib_w = sum(v for _, v in write) / len(write)
+    kib_f = sum(v for _, _, v in fetch) / len(fetch)
+    kib_w = sum(v for _, _, v in write) / len(write)
     return {
         "kernel": short_name(fetch[0][0]),
         "workload": args.workload,
         "precision_bytes": args.precision,
         "kernel_source_hash": kernel_source_hash(),
         "commands": args.command,
-        "dispatches": {"fetch": len(fetch), "write": len(write), "skip": args.skip},
+        "dispatches": {"fetch": len(fetch), "write": len(write), "skip": args.skip, "window": args.window},
         "copy_calibration": {"kernel": COPY_KERNEL, "bytes_each_way": args.copy_bytes,
                              "fetch_kib": copy_kib_f, "write_kib": copy_kib_w,
                              "bytes_per_fetch_kib": sf, "bytes_per_write_kib": sw},
@@ -166,6 +174,7 @@ def main():
         p.add_argument("--match", action="append", default=[])
         p.add_argument("--skip", type=int, default=0)
         p.add_argument("--take", type=int, default=0)
+        p.add_argument("--window", default="", help="kernel whose first two dispatches bound the selection")
         p.add_argument("--command", action="append", default=[])
         p.add_argument("--out", required=True)
     args = ap.parse_args()
