@@ -935,9 +935,16 @@ __device__ __forceinline__ void leaf_update(const Inst<T> &In, int l, uint32_t c
   const int nn = n > 0 ? n - 1 : 0;
   T f[Q];
 #pragma unroll
-  for (int h = 0; h < Q; ++h)
-    f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fs + ol + h * nl, Fs + of + h * nf, cl,
+  for (int h = 0; h < Q; ++h) {
+    // The stencil offsets of every population are the same; computed once they
+    // would stay live across all nine (too many registers for 4 waves per SIMD).
+    // Hiding the coordinates behind an empty asm makes each population
+    // recompute its offsets right before its loads.
+    int xh = x, yh = y;
+    asm volatile("" : "+v"(xh), "+v"(yh));
+    f[h] = transport_pop<DIM, SCHEME, T>(h, l, J, c, xh, yh, Fs + ol + h * nl, Fs + of + h * nf, cl,
                                          Wt + ((long long)nn * Q + h) * WS, Ct + ((long long)nn * Q + h) * CS, nbr);
+  }
   if (tape)
 #pragma unroll
     for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
@@ -947,9 +954,10 @@ __device__ __forceinline__ void leaf_update(const Inst<T> &In, int l, uint32_t c
 }
 
 // Variant for large leaf sets: one thread per leaf, all populations in
-// registers, no barriers; every wavefront takes a chunk of 64 leaves.
+// registers, no barriers; every wavefront takes a chunk of 64 leaves. Register
+// budget for 4 waves per SIMD (latency hiding of the stencil loads).
 template <int DIM, int SCHEME, typename T>
-__global__ void __launch_bounds__(BLK)
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
