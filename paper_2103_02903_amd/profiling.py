@@ -96,6 +96,11 @@ def select(seq, patterns, skip: int, take: int, window=""):
 
 def stats_summary(args) -> str:
     rows = read_trace(args.trace)
+    if args.table_window:  # the table covers only the timed region
+        marks = [r[1] for r in rows if args.window in r[0]]
+        if len(marks) < 2:
+            raise SystemExit("fewer than two %s markers" % args.window)
+        rows = [r for r in rows if marks[0] < r[1] < marks[1]]
     agg = defaultdict(lambda: [0, 0, float("inf"), 0])
     for n, s, e in rows:
         a = agg[short_name(n)]
@@ -105,13 +110,19 @@ def stats_summary(args) -> str:
         a[2] = min(a[2], d)
         a[3] = max(a[3], d)
     total = sum(a[1] for a in agg.values()) or 1
+    per = args.per_step if args.table_window and args.per_step > 0 else 0
     lines = ["# rocprofv3 kernel trace summary: %s" % args.title,
              "command: %s" % args.command,
              "",
-             "%-58s %8s %12s %10s %10s %10s %6s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us", "%")]
+             "%-58s %8s %12s %10s %10s %10s %6s%s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us", "%",
+                                                    " %12s" % "us_per_step" if per else "")]
     for name, (c, t, mn, mx) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
-        lines.append("%-58s %8d %12.1f %10.2f %10.2f %10.2f %6.1f" % (name[:58], c, t / 1e3, t / c / 1e3, mn / 1e3,
-                                                                     mx / 1e3, 100.0 * t / total))
+        lines.append("%-58s %8d %12.1f %10.2f %10.2f %10.2f %6.1f%s" % (
+            name[:58], c, t / 1e3, t / c / 1e3, mn / 1e3, mx / 1e3, 100.0 * t / total,
+            " %12.2f" % (t / 1e3 / per) if per else ""))
+    if per:
+        lines.append("%-58s %8s %12.1f %10s %10s %10s %6s %12.2f" % ("sum of kernel durations", "", total / 1e3, "", "",
+                                                                    "", "", total / 1e3 / per))
     if args.match:
         sel = select(rows, args.match, args.skip, args.take, args.window)
         if sel:
@@ -164,6 +175,8 @@ def main():
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
     s.add_argument("--title", default="")
+    s.add_argument("--table-window", action="store_true", help="table only over the --window markers")
+    s.add_argument("--per-step", type=int, default=0, help="steps in the window (adds a per-step column)")
     c = sub.add_parser("counters")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         c.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
