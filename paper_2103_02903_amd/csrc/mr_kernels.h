@@ -529,10 +529,13 @@ __device__ __forceinline__ void ghost_run16(const Inst<T> &In, uint8_t *__restri
     const Run16 a = ld16(row, x0, nl, true);
 #pragma unroll
     for (int k = 0; k < 4; ++k) lf.w[k] |= leaf_flags(a.w[k]);
-    em2 |= leaf_flags(row[wrapl(x0 - 2, l)]);
-    em1 |= leaf_flags(row[wrapl(x0 - 1, l)]);
-    ep0 |= leaf_flags(row[wrapl(x0 + 16, l)]);
-    ep1 |= leaf_flags(row[wrapl(x0 + 17, l)]);
+    // the 4-cell words left and right of the run (rows hold a multiple of 16 cells)
+    const uint32_t wl = leaf_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(x0 - 4, l)));
+    const uint32_t wr = leaf_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(x0 + 16, l)));
+    em2 |= (wl >> 16) & 0xffu;
+    em1 |= wl >> 24;
+    ep0 |= wr & 0xffu;
+    ep1 |= (wr >> 8) & 0xffu;
   }
   const Run16 n1 = run_next(lf, ep0), n2 = run_next(n1, ep1);
   const Run16 p1 = run_prev(lf, em1), p2 = run_prev(p1, em2);
@@ -552,8 +555,10 @@ __device__ __forceinline__ void ghost_run16(const Inst<T> &In, uint8_t *__restri
         ga.w[k] |= ghost_flags(a.w[k]);
         gb.w[k] |= ghost_flags(c.w[k]);
       }
-      pm |= ghost_flags(row[wrapl(2 * x0 - 2, lf1)]) | ghost_flags(row[wrapl(2 * x0 - 1, lf1)]);
-      pp |= ghost_flags(row[wrapl(2 * x0 + 32, lf1)]) | ghost_flags(row[wrapl(2 * x0 + 33, lf1)]);
+      const uint32_t wl = ghost_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(2 * x0 - 4, lf1)));
+      const uint32_t wr = ghost_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(2 * x0 + 32, lf1)));
+      pm |= ((wl >> 16) | (wl >> 24)) & 0xffu;  // columns 2x0-2, 2x0-1
+      pp |= (wr | (wr >> 8)) & 0xffu;           // columns 2x0+32, 2x0+33
     }
     Run16 pr;  // pair flags of the 16 cells
     pr.w[0] = even_bytes(ga.w[0] | (ga.w[0] >> 8), ga.w[1] | (ga.w[1] >> 8));
