@@ -273,7 +273,10 @@ __device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__rest
   int x, y;
   coords<DIM>(lg, (uint32_t)cell, x, y);
   bool any = false;
-  if (DIM == 1) {
+  if ((((uintptr_t)kl) & 3u) == 0) {  // each grandchild row is one aligned 4-byte word
+    for (int b = 0; b < (DIM == 2 ? 4 : 1); ++b)
+      any |= *reinterpret_cast<const uint32_t *>(kl + cidx<DIM>(l, 4 * x, 4 * y + b)) != 0;
+  } else if (DIM == 1) {
     for (int a = 0; a < 4; ++a) any |= kl[4 * x + a] != 0;
   } else {
     for (int b = 0; b < 4; ++b)
@@ -364,15 +367,29 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   int x, y;
   coords<DIM>(lp, (uint32_t)cell, x, y);
   bool own = false, box = false;
-  for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
-    for (int a = -1; a <= 1; ++a) {
-      const int px = wrapl(x + a, lp), py = DIM == 2 ? wrapl(y + b, lp) : 0;
-      bool any = false;
-      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-        for (int dx = 0; dx < 2; ++dx) any |= tl[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] != 0;
-      box |= any;
-      if (a == 0 && b == 0) own = any;
-    }
+  if ((((uintptr_t)tl) & 3u) == 0) {
+    // children columns 2x-2 .. 2x+3 of a row: two aligned words (rows of level
+    // l >= 2 hold a multiple of 4 cells); pairs -1, 0, +1 at bytes sh .. sh+5
+    const int wa = wrapl(2 * x - 2, l) & ~3, wb = wrapl(wa + 4, l), sh = 8 * ((2 * x - 2) & 3);
+    for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy) {
+        const uint8_t *row = tl + cidx<DIM>(l, 0, DIM == 2 ? wrapl(2 * (y + b) + dy, l) : 0);
+        const unsigned long long v = ((unsigned long long)*reinterpret_cast<const uint32_t *>(row + wb) << 32 |
+                                      *reinterpret_cast<const uint32_t *>(row + wa)) >> sh;
+        box |= (v & 0xffffffffffffull) != 0;
+        if (b == 0) own |= ((v >> 16) & 0xffffu) != 0;
+      }
+  } else {
+    for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
+      for (int a = -1; a <= 1; ++a) {
+        const int px = wrapl(x + a, lp), py = DIM == 2 ? wrapl(y + b, lp) : 0;
+        bool any = false;
+        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+          for (int dx = 0; dx < 2; ++dx) any |= tl[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] != 0;
+        box |= any;
+        if (a == 0 && b == 0) own = any;
+      }
+  }
   if (own)
     for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
       for (int dx = 0; dx < 2; ++dx) tl[cidx<DIM>(l, 2 * x + dx, 2 * y + dy)] = 1;
