@@ -331,14 +331,21 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
       if (ex == 0 && ey == 0) continue;
       const uint8_t *row = kl + cidx<DIM>(l, 0, wrapl(y + ey, l));
       const Run16 a = ld16(row, x0, nl, true);
-      const Run16 t = ex == 0 ? a : ex > 0 ? run_next(a, row[wrapl(x0 + 16, l)]) : run_prev(a, row[wrapl(x0 - 1, l)]);
+      // the cell beyond the run: byte 0 of the word after it, or byte 3 of the word before
+      const Run16 t =
+          ex == 0 ? a
+          : ex > 0 ? run_next(a, *reinterpret_cast<const uint32_t *>(row + wrapl(x0 + 16, l)) & 0xffu)
+                   : run_prev(a, *reinterpret_cast<const uint32_t *>(row + wrapl(x0 - 4, l)) >> 24);
 #pragma unroll
       for (int k = 0; k < 4; ++k) v.w[k] |= t.w[k];
     }
-    if (rg) {  // 16 cells have 4 grandparents (x >> 2)
+    if (rg) {  // 16 cells have 4 grandparents (x >> 2), one 4-byte word when aligned
       const uint8_t *g = rg + cidx<DIM>(l - 2, x0 >> 2, y >> 2);
+      const uint32_t gw = (((uintptr_t)g) & 3u) == 0 ? *reinterpret_cast<const uint32_t *>(g)
+                                                     : (uint32_t)g[0] | (uint32_t)g[1] << 8 |
+                                                           (uint32_t)g[2] << 16 | (uint32_t)g[3] << 24;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v.w[k] |= (uint32_t)g[k] * 0x01010101u;
+      for (int k = 0; k < 4; ++k) v.w[k] |= ((gw >> (8 * k)) & 0xffu) * 0x01010101u;
     }
   } else {
 #pragma unroll
@@ -867,6 +874,20 @@ __device__ __forceinline__ T transport_pop(int h, int l, int J, uint32_t c, int 
 template <int DIM>
 __device__ __forceinline__ unsigned refined_neighbours(const uint8_t *__restrict__ cl, int l, int x, int y) {
   unsigned nbr = 0;
+  if (l >= 2 && (((uintptr_t)cl) & 3u) == 0) {  // columns x-1..x+1 of each row from two aligned words
+    const int wa = wrapl(x - 1, l) & ~3, wb = wrapl(wa + 4, l), sh = 8 * ((x - 1) & 3);
+    for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b) {
+      const uint8_t *row = cl + cidx<DIM>(l, 0, DIM == 2 ? wrapl(y + b, l) : 0);
+      const unsigned long long v = ((unsigned long long)*reinterpret_cast<const uint32_t *>(row + wb) << 32 |
+                                    *reinterpret_cast<const uint32_t *>(row + wa)) >> sh;
+      for (int a = -1; a <= 1; ++a) {
+        if (a == 0 && b == 0) continue;
+        if (((v >> (8 * (a + 1))) & 0xffu) == C_INTERNAL) nbr |= 1u << bit;
+        ++bit;
+      }
+    }
+    return nbr;
+  }
   for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
     for (int a = -1; a <= 1; ++a) {
       if (a == 0 && b == 0) continue;
