@@ -999,15 +999,25 @@ __device__ __forceinline__ void leaf_update(const Inst<T> &In, int l, uint32_t c
 // Variant for large leaf sets: one thread per leaf, all populations in
 // registers, no barriers; every wavefront takes a chunk of 64 leaves. Register
 // budget for 4 waves per SIMD (latency hiding of the stencil loads).
-template <int DIM, int SCHEME, typename T>
+template <int DIM, int SCHEME, typename T, bool LDSW>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                             unsigned long long *__restrict__ counters, T *__restrict__ tape) {
+                             unsigned long long *__restrict__ counters, T *__restrict__ tape, int nw, int nc) {
   constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
-  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
+  // LDSW: the weight tables (nw + nc values, all n) are staged in LDS, so the
+  // per-leaf weight reads go to the LDS and not to the vector memory path
+  // that the stencil loads saturate.
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T *sW = reinterpret_cast<T *>(dyn_lds), *sC = sW + nw;
+  if (LDSW) {
+    for (int k = threadIdx.x; k < nw; k += BLK) sW[k] = Wt[k];
+    for (int k = threadIdx.x; k < nc; k += BLK) sC[k] = Ct[k];
+  }
+  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);  // (its barrier also publishes the tables)
+  const T *W = LDSW ? sW : Wt, *C = LDSW ? sC : Ct;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     unsigned long long tot = 0;
     for (int i = 0; i < bt.B; ++i) tot += (unsigned long long)s.cnt[i];
@@ -1023,7 +1033,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     const uint32_t e = leaves[s.beg[i] + item];
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);
+    leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, W, C, tape);
   }
 }
 
