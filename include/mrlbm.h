@@ -115,7 +115,9 @@ int mrlbm_step(mrlbm_ctx *ctx, int nsteps);
 
 /* Copy the current tree and values of one instance to host buffers (layouts
  * above; `values` holds q * total_cells reals of the context precision).
- * Synchronous. */
+ * Only the complete leaves carry the state; the other cells hold scratch
+ * (reconstruction values or stale data) that depends only on the sequence of
+ * calls since mrlbm_create. Synchronous. */
 int mrlbm_get_state(mrlbm_ctx *ctx, int instance, uint8_t *tree, void *values);
 
 /* Replace the current state by a host-side tree (must be a graded complete

@@ -781,32 +781,33 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
 }
 
 // ---------------------------------------------------------------- transfer
-// Data of the new complete leaves from the old reconstruction: copy (old leaf),
-// projection (merged cell: old internal), prediction (created cell; an old
-// ghost already holds it).
+// Data of the new complete leaves from the old reconstruction, in place: the
+// value of a new leaf is the old reconstruction's value at that cell. An old
+// leaf keeps its value, a merged cell (old internal) already holds its
+// projection and an old ghost its prediction, so only cells outside the old
+// mesh are written, with the prediction from level l-1. Their parent stencils
+// lie in the old mesh (the old tree is graded and refines by one level), so no
+// cell read here is written here. One thread per new leaf.
 template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(64 * Q) k_transfer(Batch bt, const Inst<T> *__restrict__ I,
-                                                     const T *__restrict__ Fold, T *__restrict__ Fnew,
-                                                     const uint8_t *__restrict__ code_old,
-                                                     const uint32_t *__restrict__ leaves, const int *__restrict__ lvl) {
+__global__ void __launch_bounds__(BLK) k_transfer(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                  const uint8_t *__restrict__ code_old,
+                                                  const uint32_t *__restrict__ leaves, const int *__restrict__ lvl) {
+  constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
-  const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
     const uint32_t e = leaves[s.beg[i] + item];
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    const long long o = foff(I[i], DIM, Q, l, h) + c;
-    if (code_old[I[i].loff[l] + c] != C_NONE) {
-      Fnew[o] = Fold[o];
-    } else {
-      int x, y;
-      coords<DIM>(l, c, x, y);
-      Fnew[o] = predict<DIM, T>(Fold + foff(I[i], DIM, Q, l - 1, h), l, x, y);
-    }
+    if (code_old[I[i].loff[l] + c] != C_NONE) continue;
+    int x, y;
+    coords<DIM>(l, c, x, y);
+    for (int h = 0; h < Q; ++h)
+      F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y);
   }
 }
 

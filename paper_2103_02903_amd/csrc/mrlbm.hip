@@ -507,7 +507,6 @@ struct Engine {
     const Plan &P = c->P;
     const int mo = c->mcur, mn = 1 - c->mcur;
     T *Fc = (T *)c->F[c->cur];
-    T *Fn = (T *)c->F[1 - c->cur];
     phase_mark(c, PH_ADAPT, true);
     reconstruct(c, Fc, mo);
     {  // keep and refg are adjacent, 256-byte aligned byte arrays: clear both
@@ -528,11 +527,10 @@ struct Engine {
     }
 
     classify(c, mn);
-    k_transfer<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(c->bt, I(c), Fc, Fn, c->code[mo],
-                                                               c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn]);
+    k_transfer<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
+        c->bt, I(c), Fc, c->code[mo], c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn]);
     phase_mark(c, PH_ADAPT, false);
     c->mcur = mn;
-    c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
@@ -577,7 +575,7 @@ struct Engine {
   }
 
   // One full step replayed from a HIP graph, one graph per assignment of the
-  // double buffers (a step swaps the mesh buffers and swaps F twice). With
+  // double buffers (a step swaps the mesh buffers and, in the transport, F). With
   // profiling on, the graph ends after the reconstruction and the transport
   // kernel is launched between timing events.
   static int step_graph(mrlbm_ctx *c) {
@@ -605,8 +603,7 @@ struct Engine {
       if (e != hipSuccess) { g = nullptr; return MRLBM_ERR_HIP; }
     }
     if (hipGraphLaunch(g, c->stream) != hipSuccess) return MRLBM_ERR_HIP;
-    c->mcur = 1 - par;  // the adaptation's swaps
-    c->cur = 1 - c->cur;
+    c->mcur = 1 - par;  // the adaptation's swap
     if (timed) return transport_kernel(c);
     c->cur = 1 - c->cur;  // the transport's swap
     return MRLBM_OK;
@@ -767,11 +764,12 @@ struct Engine {
   }
 
   // ------------------------------------------------------------- autotuning
-  // A step that leaves the state as it was: the adaptation writes only the next
-  // mesh and value buffers (its reconstruction of the current buffer recomputes
-  // the values already there), and the transport runs on the current mesh into
-  // the other value buffer. Captured once per schedule and replayed `reps`
-  // times between HIP events.
+  // A step that leaves the state as it was: the adaptation writes the next mesh
+  // buffers and, in the current value buffer, recomputes the values already
+  // there (its reconstruction) or writes cells outside the current mesh (its
+  // transfer); the transport then runs on the current mesh into the other value
+  // buffer. Captured once per schedule and replayed `reps` times between HIP
+  // events.
   static int time_dry_steps(mrlbm_ctx *c, int reps, float *ms) {
     const int cur0 = c->cur, m0 = c->mcur;
     hipStream_t user = c->stream;
@@ -782,7 +780,6 @@ struct Engine {
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
     int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
-    c->cur = cur0;
     c->mcur = m0;
     if (rc == MRLBM_OK) rc = transport(c);
     c->cur = cur0;
@@ -1020,6 +1017,9 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
     e = hipMemcpy(c->dinfo, P.dinfo.data(), sizeof(uint32_t) * P.dinfo.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
+  // Value buffers start at zero: cells outside the mesh hold scratch that then
+  // depends only on the sequence of calls.
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
   if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) { delete c; return MRLBM_ERR_HIP; }
   *out = c;
   return MRLBM_OK;
