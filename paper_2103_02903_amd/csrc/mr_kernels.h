@@ -526,6 +526,7 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> 
 __device__ __forceinline__ uint32_t leaf_flags(uint32_t w) { return w & (w >> 1) & 0x01010101u; }
 __device__ __forceinline__ uint32_t ghost_flags(uint32_t w) { return w & ~(w >> 1) & 0x01010101u; }
 __device__ __forceinline__ uint32_t none_flags(uint32_t w) { return ~(w | (w >> 1)) & 0x01010101u; }
+__device__ __forceinline__ uint32_t internal_flags(uint32_t w) { return (w >> 1) & ~w & 0x01010101u; }
 
 // Same classification as k_classify_ghost for 16 consecutive cells of a row
 // per thread (levels whose rows hold at least 16 cells and whose code arrays
@@ -545,6 +546,29 @@ __device__ __forceinline__ void ghost_run16(const Inst<T> &In, uint8_t *__restri
   if (!(none.w[0] | none.w[1] | none.w[2] | none.w[3])) return;
   int x0, y;
   coords<DIM>(l, (uint32_t)c0, x0, y);
+  {
+    // Necessary condition: a ghost of level l has an internal cell of level l-1
+    // within one cell of its parent. (A leaf at distance <= 2 has an internal
+    // parent within one cell of the ghost's parent; a ghost of level l+1 that
+    // needs it has, by induction, an internal cell of level l within one cell
+    // of its parent, and that cell's parent is internal.) The parents of the
+    // run are columns x0/2 .. x0/2+7 of level l-1: test columns x0/2-1 ..
+    // x0/2+8 of rows y/2-1 .. y/2+1 from four aligned words per row.
+    const int lp = l - 1;
+    const uint8_t *cp = code + In.loff[lp];
+    if ((((uintptr_t)cp) & 3u) == 0) {
+      const int px = x0 >> 1;  // a multiple of 8; rows of level l-1 hold at least 8 cells
+      uint32_t any = 0;
+      for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b) {
+        const uint8_t *row = cp + cidx<DIM>(lp, 0, DIM == 2 ? wrapl((y >> 1) + b, lp) : 0);
+        any |= internal_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(px - 4, lp))) & 0x01000000u;
+        any |= internal_flags(*reinterpret_cast<const uint32_t *>(row + px));
+        any |= internal_flags(*reinterpret_cast<const uint32_t *>(row + px + 4));
+        any |= internal_flags(*reinterpret_cast<const uint32_t *>(row + wrapl(px + 8, lp))) & 0x1u;
+      }
+      if (!any) return;
+    }
+  }
   // leaves of level l: OR of the rows, edge bytes x0-2, x0-1, x0+16, x0+17
   Run16 lf = {{0, 0, 0, 0}};
   uint32_t em2 = 0, em1 = 0, ep0 = 0, ep1 = 0;

@@ -1,0 +1,70 @@
+"""Host-side ghost sets of a complete tree, written from their definition, for
+checking the GPU classification.
+
+A cell of level l > jmin outside the tree is a ghost if a leaf of level l lies
+in its 5^d box (the transport and transfer stencils of that leaf) or if it lies
+in the 3^d box of the parent of a ghost of level l+1 (the prediction stencil of
+that ghost, section "Projection and prediction operators"). The sets are built
+from the finest level down; all boxes wrap periodically.
+"""
+import numpy as np
+
+
+def _dilate(m: np.ndarray, r: int) -> np.ndarray:
+    out = m.copy()
+    axes = tuple(range(m.ndim))
+    for off in np.ndindex(*([2 * r + 1] * m.ndim)):
+        sh = tuple(o - r for o in off)
+        if any(sh):
+            out |= np.roll(m, sh, axis=axes)
+    return out
+
+
+def _parents(m: np.ndarray) -> np.ndarray:
+    """Cells of the coarser level with at least one child in m."""
+    if m.ndim == 1:
+        return m[0::2] | m[1::2]
+    return m[0::2, 0::2] | m[1::2, 0::2] | m[0::2, 1::2] | m[1::2, 1::2]
+
+
+def _children(m: np.ndarray) -> np.ndarray:
+    """Children (one level finer) of the cells in m."""
+    out = m
+    for ax in range(m.ndim):
+        out = np.repeat(out, 2, axis=ax)
+    return out
+
+
+def tree_sets(o, tree):
+    """Per level: (tree mask, leaf mask, internal mask)."""
+    T = {l: o.tree_level(tree, l).astype(bool) for l in range(o.jmin, o.jmax + 1)}
+    S, I = {}, {}
+    for l in T:
+        S[l] = o.leaf_mask(tree, l)
+        I[l] = T[l] & ~S[l]
+    return T, S, I
+
+
+def ghost_sets(o, tree):
+    """Per level l > jmin: the ghost mask (level jmin holds every cell in the tree)."""
+    T, S, _ = tree_sets(o, tree)
+    G = {}
+    for l in range(o.jmax, o.jmin, -1):
+        need = _dilate(S[l], 2)
+        if l < o.jmax:
+            need |= _dilate(_parents(G[l + 1]), 1)
+        G[l] = need & ~T[l]
+    return G
+
+
+def ghost_near_internal(o, tree):
+    """Levels where some ghost has no internal cell of the coarser level within
+    one cell of its parent (empty if the property holds everywhere)."""
+    _, _, I = tree_sets(o, tree)
+    G = ghost_sets(o, tree)
+    bad = []
+    for l, g in G.items():
+        allowed = _children(_dilate(I[l - 1], 1))
+        if np.any(g & ~allowed):
+            bad.append(l)
+    return bad

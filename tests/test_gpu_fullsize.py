@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from adjoint_helpers import ke_functional
+from ghost_sets import ghost_sets
 from paper_2103_02903_amd import workloads as W
 
 from test_gpu_parity import TOL64, leaf_err
@@ -64,6 +65,9 @@ def test_batch96_fp32_step_replay(mr):
         assert np.array_equal(tg2, tnew), "FP32 mesh of instance %d differs" % i
         e = leaf_err(o, t_o, vg2, v_o)
         assert e <= TOL32, "FP32 field error %g on instance %d" % (e, i)
+        G = ghost_sets(o, tg2)
+        want = np.array([int(G[l].sum()) if l in G else 0 for l in range(o.jmax + 1)])
+        assert np.array_equal(b.stats(i)["ghosts"], want), "ghost counts of instance %d" % i
     b.close()
 
 

@@ -229,6 +229,32 @@ def test_batch_replay_each_instance(mr, scheme):
             assert leaf_err(o, t_o, vg, v_o) <= TOL64
 
 
+@pytest.mark.parametrize("scheme,precision", [("D1Q3", 8), ("D2Q9", 4), ("D2Q9", 8)])
+def test_ghost_sets_match_definition(mr, scheme, precision):
+    """Per-level ghost counts of the GPU classification (16-cell runs and
+    4-cell runs) equal the ghost sets built on the host from their definition,
+    on the meshes of several steps of uneven instances."""
+    from ghost_sets import ghost_sets
+
+    items = _batch_cfgs(scheme)
+    bat = mr.Batch([c for c, _ in items], precision=precision)
+    for i, (_, m0) in enumerate(items):
+        bat.init_equilibrium(i, m0)
+    oracles = [oracle.Oracle(c) for c, _ in items]
+    seen = 0
+    for k in range(5):
+        bat.step(2)
+        for i, o in enumerate(oracles):
+            tree, _ = bat.get_state(i)
+            G = ghost_sets(o, tree)
+            want = np.array([int(G[l].sum()) if l in G else 0 for l in range(o.jmax + 1)])
+            got = bat.stats(i)["ghosts"]
+            assert np.array_equal(got, want), "instance %d after %d steps: %s vs %s" % (i, 2 * k + 2, got, want)
+            seen += int(want.sum())
+    assert seen > 0
+    bat.close()
+
+
 def test_batch_instance_equals_single_run(mr):
     """An instance advanced inside a batch is bit-identical to the same instance
     advanced alone."""

@@ -194,3 +194,44 @@ def test_step_frozen_equals_step_on_own_mesh():
     t2, v2 = tree.copy(), v.copy()
     o.step_frozen(t2, tnew, v2)
     assert np.array_equal(t1, t2) and np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,eps,kind", [("D1Q3", 2, 10, 1e-4, "jump"), ("D2Q9", 3, 7, 1e-3, "smooth"),
+                                                       ("D2Q9", 2, 6, 1e-3, "jump")])
+def test_ghosts_lie_next_to_coarser_internal_cells(scheme, jmin, jmax, eps, kind):
+    """Every ghost of level l has an internal cell of level l-1 within one cell
+    of its parent, on adapted meshes and on random graded trees. The GPU ghost
+    classification skips runs of cells that fail this necessary condition."""
+    from ghost_sets import ghost_near_internal, ghost_sets
+
+    cfg = _cfg(scheme, jmin, jmax, eps)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 3, kind))
+    n_ghosts = 0
+    for _ in range(4):
+        o.step(tree, v)
+        assert ghost_near_internal(o, tree) == []
+        n_ghosts += sum(int(g.sum()) for g in ghost_sets(o, tree).values())
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        t = _random_graded_tree(o, rng)
+        assert o.check_tree(t) == 0
+        assert ghost_near_internal(o, t) == []
+        n_ghosts += sum(int(g.sum()) for g in ghost_sets(o, t).values())
+    assert n_ghosts > 0
+
+
+def test_ghost_condition_check_catches_a_violation():
+    """The check itself: a ghost planted away from every internal cell fails it."""
+    from ghost_sets import _children, _dilate, tree_sets
+
+    cfg = _cfg("D2Q9", 2, 5, 1e-3)
+    o = oracle.Oracle(cfg)
+    tree = np.zeros(o.total, np.uint8)
+    tree[o.level_offset(2):o.level_offset(2) + o.ncells(2)] = 1  # uniform coarsest mesh
+    assert o.check_tree(tree) == 0
+    _, _, I = tree_sets(o, tree)
+    assert not I[2].any()
+    g = np.zeros((8, 8), bool)
+    g[3, 3] = True
+    assert np.any(g & ~_children(_dilate(I[2], 1)))
