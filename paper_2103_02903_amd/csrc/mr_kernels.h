@@ -83,8 +83,9 @@ constexpr int NXCD = 8;
 struct ChunkSched {
   int ch, end, stride;
 };
-__device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int sub) {
-  const int G = (int)gridDim.x;
+// The list work may occupy the first G blocks of a launch that also carries
+// other work (G a multiple of 8 keeps the XCD mapping).
+__device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int sub, int G) {
   if (MRLBM_XCD && G % NXCD == 0) {
     const int x = (int)blockIdx.x % NXCD, slot = (int)blockIdx.x / NXCD;
     const int lo = (int)((long long)total * x / NXCD), hi = (int)((long long)total * (x + 1) / NXCD);
@@ -92,21 +93,23 @@ __device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int 
   }
   return {(int)blockIdx.x * per_block + sub, total, G * per_block};
 }
-#define MRLBM_FOR_CHUNKS(var_, total, per_block, sub) \
-  for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
+#define MRLBM_FOR_CHUNKS_G(var_, total, per_block, sub, G) \
+  for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub), (G)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
     if (const int var_ = cs_.ch; true)
+#define MRLBM_FOR_CHUNKS(var_, total, per_block, sub) MRLBM_FOR_CHUNKS_G(var_, total, per_block, sub, (int)gridDim.x)
 
 // ---------------------------------------------------------------- reconstruction
 // Projection P_nabla on the internal cells of level l (section "Projection and
-// prediction operators"), children read at level l+1 of the same buffer.
+// prediction operators"), children read at level l+1 of the same buffer. The
+// first G blocks; wavefront h < Q takes population h.
 template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                    const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                    int l) {
-  __shared__ SegLDS s;
+__device__ __forceinline__ void project_level(SegLDS &s, const Batch &bt, const Inst<T> *__restrict__ I,
+                                              T *__restrict__ F, const uint32_t *__restrict__ lst,
+                                              const int *__restrict__ lvl, int l, int G) {
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
+  if (h >= Q) return;
+  MRLBM_FOR_CHUNKS_G(ch, s.pre[bt.B], 1, 0, G) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -116,15 +119,24 @@ __global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__r
     F[foff(I[i], DIM, Q, l, h) + c] = project<DIM, T>(F + foff(I[i], DIM, Q, l + 1, h), l + 1, x, y);
   }
 }
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                    const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                    int l) {
+  __shared__ SegLDS s;
+  project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x);
+}
 
 // Zero-detail prediction P_delta on the ghost cells of level l, from level l-1.
+// The first G blocks; wavefront h < Q takes population h.
 template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                  const uint32_t *__restrict__ lst, const int *__restrict__ lvl, int l) {
-  __shared__ SegLDS s;
+__device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const Inst<T> *__restrict__ I,
+                                            T *__restrict__ F, const uint32_t *__restrict__ lst,
+                                            const int *__restrict__ lvl, int l, int G) {
   load_segments(s, I, lvl, bt.B, CAT_GHOST, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], 1, 0) {
+  if (h >= Q) return;
+  MRLBM_FOR_CHUNKS_G(ch, s.pre[bt.B], 1, 0, G) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -133,6 +145,12 @@ __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__res
     coords<DIM>(l, c, x, y);
     F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y);
   }
+}
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                  const uint32_t *__restrict__ lst, const int *__restrict__ lvl, int l) {
+  __shared__ SegLDS s;
+  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------- mesh adaptation
@@ -402,22 +420,43 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
       for (int dx = 0; dx < 2; ++dx) tl[cidx<DIM>(l, 2 * x + dx, 2 * y + dy)] = 1;
   if (box) tp[cell] = 1;
 }
-template <int DIM, typename T>
-__global__ void __launch_bounds__(BLK) k_grade(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
-                                               const uint32_t *__restrict__ info, int l) {
-  int i;
-  const long long cell = dense_block(info, i);
-  if (cell >= ncells_d(DIM, l - 1)) return;
-  grade_cell<DIM, T>(I[i], tnew, l, cell);
+
+// ---------------------------------------------------------------- fused launches
+// Two independent chains of a step share launches: each launch runs one link of
+// each, in disjoint blocks that touch disjoint data. Blocks hold wavefronts for
+// the Q populations of the list work and at least BLK threads for the dense work.
+template <int Q>
+constexpr int fused_block() { return 64 * Q > BLK ? 64 * Q : BLK; }
+
+// Grading of level lg (blocks G.., one cell of level lg-1 per thread, block
+// table ginfo) beside the ghost predictions of level lh on the old mesh (the
+// first G blocks). The first writes the membership array, the second the values.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(fused_block<Q>())
+    k_grade_ghost(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
+                  const uint32_t *__restrict__ ginfo, int lg, T *__restrict__ F, const uint32_t *__restrict__ lst,
+                  const int *__restrict__ lvl, int lh, int G) {
+  if ((int)blockIdx.x >= G) {
+    const uint32_t w = ginfo[blockIdx.x - G];
+    const int i = (int)(w & 0xffu);
+    const long long cell = (long long)(w >> 8) * fused_block<Q>() + threadIdx.x;
+    if (cell < ncells_d(DIM, lg - 1)) grade_cell<DIM, T>(I[i], tnew, lg, cell);
+    return;
+  }
+  __shared__ SegLDS s;
+  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, lh, G);
 }
 
 // Codes of the tree cells of a 0/1 membership array: leaf, or internal when
 // its first child is in the tree. Sixteen consecutive cells per thread; their
-// first children are the even bytes of 32 cells of the finer row.
+// first children are the even bytes of 32 cells of the finer row. The same
+// cells of the two flag arrays `clear0`, `clear1` (indexed like the codes) are
+// zeroed, ready for the next adaptation.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo,
-                                                       const uint8_t *__restrict__ tnew, uint8_t *__restrict__ code) {
+                                                       const uint8_t *__restrict__ tnew, uint8_t *__restrict__ code,
+                                                       uint8_t *__restrict__ clear0, uint8_t *__restrict__ clear1) {
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
@@ -454,6 +493,10 @@ __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *
 #pragma unroll
   for (int k = 0; k < 4; ++k) v.w[k] = (t.w[k] << 1) | (t.w[k] & ~ch[k]);
   st16(cl, c0, nl, vec, v);
+  const Run16 z = {{0, 0, 0, 0}};
+  uint8_t *k0 = clear0 + In.loff[l], *k1 = clear1 + In.loff[l];
+  st16(k0, c0, nl, level_vec(k0, nl) && l >= 4, z);
+  st16(k1, c0, nl, level_vec(k1, nl) && l >= 4, z);
 }
 
 // Four consecutive codes starting at p (byte loads if p is not 4-byte aligned).

@@ -138,11 +138,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Dense per-level passes: cells per block, and the levels they cover
 // (jmin <= L <= jmax - margin): ghost classification with 4 cells per thread
-// (0) or 16 (3), grading (1, level l-1 of l) and ancestor closure (2, level
-// l-2 of l) with one.
+// (0) or 16 (3), grading (1, level l-1 of l; one cell per thread of the fused
+// block of q populations) and ancestor closure (2, level l-2 of l) with one.
 constexpr int NDENSE = 4;
-long long dense_cells(int off) {
-  return off == 0 ? (long long)GCHUNK : off == 3 ? (long long)CCHUNK : (long long)BLK;
+long long dense_cells(int off, int q) {
+  return off == 0 ? (long long)GCHUNK : off == 3 ? (long long)CCHUNK : off == 1 ? (long long)std::max(64 * q, BLK)
+                                                                                  : (long long)BLK;
 }
 int dense_margin(int off) { return off == 1 ? 1 : off == 2 ? 2 : 0; }
 
@@ -231,7 +232,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
       for (int i = 0; i < B; ++i) {
         row[i] = acc;
         if (L >= P.jmin && L <= P.inst[i].jmax - dense_margin(off))
-          acc += (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
+          acc += (int)(((1ll << (P.dim * L)) + dense_cells(off, P.q) - 1) / dense_cells(off, P.q));
       }
       row[B] = acc;
     }
@@ -242,7 +243,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
       P.dstart[(size_t)off * LVL_STRIDE + L] = (long long)P.dinfo.size();
       for (int i = 0; i < B; ++i)
         if (L >= P.jmin && L <= P.inst[i].jmax - dense_margin(off)) {
-          const int nb = (int)(((1ll << (P.dim * L)) + dense_cells(off) - 1) / dense_cells(off));
+          const int nb = (int)(((1ll << (P.dim * L)) + dense_cells(off, P.q) - 1) / dense_cells(off, P.q));
           for (int k = 0; k < nb; ++k) P.dinfo.push_back((uint32_t)i | ((uint32_t)k << 8));
         }
     }
@@ -455,6 +456,7 @@ template <int DIM, int SCHEME, typename T>
 struct Engine {
   static constexpr int Q = Vel<SCHEME>::Q;
   static constexpr unsigned QB = 64 * Q;
+  static constexpr unsigned FB = fused_block<Q>();
 
   static const Inst<T> *I(mrlbm_ctx *c) { return (const Inst<T> *)c->inst; }
   static unsigned chunks_level(mrlbm_ctx *c, int l) {  // capacity of the per-level lists in chunks
@@ -476,7 +478,8 @@ struct Engine {
   // Codes (leaf / internal / ghost) of the membership array tnew into code[m].
   static void classify(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
-    k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m]);
+    k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
+                                                              c->refg);
     for (int l = P.maxJ; l > P.jmin; --l) {
       if (P.ghost16[l]) {
         const int nb = P.dtab_total(3, l);
@@ -507,12 +510,14 @@ struct Engine {
     const Plan &P = c->P;
     const int mo = c->mcur, mn = 1 - c->mcur;
     T *Fc = (T *)c->F[c->cur];
+    const uint32_t *li = c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal;
+    const uint32_t *lg = c->lists[mo] + (size_t)CAT_GHOST * P.ctotal;
     phase_mark(c, PH_ADAPT, true);
-    reconstruct(c, Fc, mo);
-    {  // keep and refg are adjacent, 256-byte aligned byte arrays: clear both
-      const long long n4 = (long long)(2 * align256((size_t)P.ctotal) / 4);
-      k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>((uint32_t *)c->keep, n4, 0u);
-    }
+    // Projections of the old mesh (the details read tree cells only). The keep
+    // and refine flags are zero here: the tree classification of the previous
+    // adaptation, or the creation, cleared them.
+    for (int l = P.maxJ - 1; l >= P.jmin; --l)
+      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), Fc, li, c->lvl[mo], l);
     k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
         c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
     for (int l = P.maxJ; l >= P.jmin + 2; --l) {
@@ -521,9 +526,13 @@ struct Engine {
     }
 
     k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
-    for (int l = P.maxJ; l >= P.jmin + 1; --l) {
-      const int nb = P.dtab_total(1, l - 1);
-      if (nb) k_grade<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dinfo_row(c->dinfo, 1, l - 1), l);
+    // Grading (levels maxJ .. jmin+1) beside the old mesh's ghost predictions
+    // (levels jmin+1 .. maxJ), which only the transfer reads.
+    for (int k = 0; k < P.maxJ - P.jmin; ++k) {
+      const int l = P.maxJ - k, lh = P.jmin + 1 + k;
+      const unsigned nb = (unsigned)P.dtab_total(1, l - 1), G = chunks_level(c, lh);
+      k_grade_ghost<DIM, Q, T><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dinfo_row(c->dinfo, 1, l - 1), l,
+                                                             Fc, lg, c->lvl[mo], lh, (int)G);
     }
 
     classify(c, mn);
@@ -1017,6 +1026,8 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
     e = hipMemcpy(c->dinfo, P.dinfo.data(), sizeof(uint32_t) * P.dinfo.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
+  if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
+  if (e == hipSuccess) e = hipMemset(c->refg, 0, P.ctotal);
   // Value buffers start at zero: cells outside the mesh hold scratch that then
   // depends only on the sequence of calls.
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
