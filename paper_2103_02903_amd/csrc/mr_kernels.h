@@ -887,6 +887,29 @@ __global__ void __launch_bounds__(BLK) k_transfer(Batch bt, const Inst<T> *__res
 // further, its children's details weighted by C[n][h]. Finest leaves stream by
 // the plain shift f(k - eta).
 //
+// Neighbours refined one level further (bit k of nbr over the 3^d - 1
+// neighbours, x fastest): their children's details weighted by Cw, added to acc.
+template <int DIM, typename T>
+__device__ __forceinline__ T detail_correction(T acc, int l, int x, int y, const T *__restrict__ Fl,
+                                               const T *__restrict__ Ff, const T *__restrict__ Cw, unsigned nbr) {
+  for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if (a == 0 && b == 0) continue;
+      const int k = bit++;
+      if (!(nbr & (1u << k))) continue;
+      const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
+      ParentStencil<DIM, T> st;
+      st.load(Fl, l, px, py);
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
+          const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
+          acc = fma(Cw[y2 * 6 + y1], d, acc);
+        }
+    }
+  return acc;
+}
+
 // Population h of the leaf (l, c): Fl / Ff point at population h of levels l and
 // l+1, cl at the codes of level l, W / Cw at the weights of (n, h).
 template <int DIM, int SCHEME, typename T>
@@ -917,23 +940,7 @@ __device__ __forceinline__ T transport_pop(int h, int l, int J, uint32_t c, int 
       for (int a = -2; a <= 2; ++a) acc = fma(W[(b + 2) * 5 + a + 2], Fl[row + wrapl(x + a, l)], acc);
     }
   }
-  if (nbr) {  // neighbours refined one level further: their children's details
-    for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
-      for (int a = -1; a <= 1; ++a) {
-        if (a == 0 && b == 0) continue;
-        const int k = bit++;
-        if (!(nbr & (1u << k))) continue;
-        const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
-        ParentStencil<DIM, T> st;
-        st.load(Fl, l, px, py);
-        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
-            const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
-            const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
-            acc = fma(Cw[y2 * 6 + y1], d, acc);
-          }
-      }
-  }
+  if (nbr) acc = detail_correction<DIM, T>(acc, l, x, y, Fl, Ff, Cw, nbr);
   return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
 }
 
@@ -1064,9 +1071,126 @@ __device__ __forceinline__ void leaf_update(const Inst<T> &In, int l, uint32_t c
   for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
 }
 
+// The detail correction as a call: it concerns few leaves, and inlined its
+// addressing would compete for registers with the stencil loads of every leaf.
+template <int DIM, typename T>
+__device__ __attribute__((noinline)) T detail_correction_call(T acc, int l, int x, int y, const T *__restrict__ Fl,
+                                                              const T *__restrict__ Ff, const T *__restrict__ Cw,
+                                                              unsigned nbr) {
+  return detail_correction<DIM, T>(acc, l, x, y, Fl, Ff, Cw, nbr);
+}
+
+// Buffer resource of n values at a wavefront-uniform base (raw buffer, no
+// stride; the third word is the CDNA data-format word), and a load at a 32-bit
+// byte offset from it: one scalar descriptor per array and one VGPR per
+// address. Offsets at or beyond n values would read 0; every offset used here
+// is a wrapped cell index of the array's level.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const T *base, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * (long long)sizeof(T)), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T ld_off(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+
+// leaf_update for a wavefront whose leaves all lie on level l of instance In
+// (l, In uniform): the population arrays of level l are uniform buffers, the
+// 5^d stencil is a sum of a row and a column byte offset computed once per
+// leaf, and the weights of (n, h) are uniform scalar loads. Same operations in
+// the same order as transport_pop.
+template <int DIM, int SCHEME, typename T>
+__device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint32_t c, const T *__restrict__ Fs,
+                                                  T *__restrict__ Fo, const uint8_t *__restrict__ code,
+                                                  const T *__restrict__ Wt, const T *__restrict__ Ct,
+                                                  T *__restrict__ tape) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q;
+  constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const int J = In.jmax, n = J - l;
+  const long long nl = ncells_d(DIM, l);
+  const T *Fl0 = Fs + (long long)Q * In.loff[l];
+  T f[Q];
+  if (n == 0) {
+#pragma unroll
+    for (int h = 0; h < Q; ++h) {
+      const uint32_t cs = (uint32_t)cidx<DIM>(l, wrapl(x - V::ex(h), l), wrapl(y - V::ey(h), l));
+      f[h] = ld_off<T>(pop_rsrc(Fl0 + h * nl, nl), cs * (uint32_t)sizeof(T));
+    }
+  } else {
+    const uint8_t *cl = code + In.loff[l];
+    const unsigned nbr = refined_neighbours<DIM>(cl, l, x, y);
+    const T *Ff0 = Fs + (long long)Q * In.loff[l + 1];
+    const long long nf = ncells_d(DIM, l + 1);
+    const int nn = n - 1;
+    const T scale = (T)ldexp(1.0, -DIM * n);
+    uint32_t rowb[5], colb[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      rowb[k] = DIM == 2 ? ((uint32_t)wrapl(y + k - 2, l) << l) * (uint32_t)sizeof(T) : 0u;
+      colb[k] = (uint32_t)wrapl(x + k - 2, l) * (uint32_t)sizeof(T);
+    }
+    const uint32_t own = c * (uint32_t)sizeof(T);
+    // Stencil sums of every population first, with no call in between, so that
+    // the loads of several populations can be in flight together; then the
+    // detail corrections (leaves next to finer cells only), then the update.
+    T acc[Q], fc[Q];
+#pragma unroll
+    for (int h = 0; h < Q; ++h) {
+      const int ex = V::ex(h), ey = V::ey(h);
+      const __amdgpu_buffer_rsrc_t base = pop_rsrc(Fl0 + h * nl, nl);
+      const_ptr<T> W = (const_ptr<T>)(Wt + ((long long)nn * Q + h) * WS);
+      fc[h] = ld_off<T>(base, own);
+      T a_h = T(0);
+      if (ex == 0 && ey == 0) {
+      } else if (DIM == 1) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) a_h = fma(W[a], ld_off<T>(base, colb[a]), a_h);
+      } else if (ey == 0) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) a_h = fma(W[10 + a], ld_off<T>(base, rowb[2] + colb[a]), a_h);
+      } else if (ex == 0) {
+#pragma unroll
+        for (int b = 0; b < 5; ++b) a_h = fma(W[b * 5 + 2], ld_off<T>(base, rowb[b] + colb[2]), a_h);
+      } else {
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+#pragma unroll
+          for (int a = 0; a < 5; ++a) a_h = fma(W[b * 5 + a], ld_off<T>(base, rowb[b] + colb[a]), a_h);
+      }
+      acc[h] = a_h;
+    }
+    if (nbr) {
+#pragma unroll
+      for (int h = 0; h < Q; ++h)
+        if (V::ex(h) != 0 || V::ey(h) != 0)
+          acc[h] = detail_correction_call<DIM, T>(acc[h], l, x, y, Fl0 + h * nl, Ff0 + h * nf,
+                                                  Ct + ((long long)nn * Q + h) * CS, nbr);
+    }
+#pragma unroll
+    for (int h = 0; h < Q; ++h) f[h] = (V::ex(h) == 0 && V::ey(h) == 0) ? fc[h] : fma(scale, acc[h], fc[h]);
+  }
+  const long long ol = (long long)Q * In.loff[l];
+  if (tape)
+#pragma unroll
+    for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
+  collide<SCHEME, T>(f, In.sc);
+#pragma unroll
+  for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
+}
+
 // Variant for large leaf sets: one thread per leaf, all populations in
 // registers, no barriers; every wavefront takes a chunk of 64 leaves. Register
-// budget for 4 waves per SIMD (latency hiding of the stencil loads).
+// budget for 4 waves per SIMD (latency hiding of the stencil loads). A chunk
+// whose leaves share one level (all but those that straddle a level boundary)
+// takes leaf_update_level.
 template <int DIM, int SCHEME, typename T, bool LDSW>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
@@ -1094,14 +1218,20 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
-    const int i = upper_index(s.pre, bt.B, ch);
+    const int i = __builtin_amdgcn_readfirstlane(upper_index(s.pre, bt.B, ch));
     const int item = (ch - s.pre[i]) * CHUNK + lane;
-    if (item >= s.cnt[i]) continue;
-    const Inst<T> &In = I[i];
-    const uint32_t e = leaves[s.beg[i] + item];
+    const bool valid = item < s.cnt[i];  // lane 0 always is
+    const uint32_t e = valid ? leaves[s.beg[i] + item] : 0u;
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, W, C, tape);
+    const int l0 = __builtin_amdgcn_readfirstlane(l);
+    const bool one_level = __ballot(valid && l != l0) == 0;
+    if (!valid) continue;
+    const Inst<T> &In = I[i];
+    if (one_level)
+      leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape);
+    else
+      leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, W, C, tape);
   }
 }
 
