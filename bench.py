@@ -125,7 +125,8 @@ def copy_bandwidth(nbytes: int = COPY_BYTES, reps: int = 5):
 
 def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, schedule=None, markers=False):
     """Warm up, pick the launch schedule with the library's autotuner, then time
-    `steps` graph-replayed steps with the transport kernel between HIP events.
+    `steps` graph-replayed steps; HIP events inside the step graph bracket the
+    transport kernel of every 8th of them.
     Returns (result dict, sim, state of instance `keep_state_of` at the start of
     the timed region or None). `schedule` (transport variant, all-level cap,
     per-level cap) replaces the autotuner; `markers` brackets the timed region
@@ -185,7 +186,8 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, sc
                warmup=warmup, leaf_updates=leaf_updates, transport_avg_launch_ms=avg_ms,
                transport_bytes_per_launch=bytes_per_launch, transport_gbs=achieved,
                transport_frac=achieved / HBM_PEAK_GBS,
-               transport_leaf_updates_per_s=leaf_updates / (cnt["transport_ms"] * 1e-3),
+               transport_leaf_updates_per_s=bytes_per_launch / bytes_per_leaf / (avg_ms * 1e-3),
+               transport_launches=int(cnt["transport_launches"]), timed_launches=int(cnt["timed_launches"]),
                mean_leaves_per_step=leaf_updates / max(1, steps),
                compression_rate_final=1.0 - leaves_now / finest,
                compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
@@ -400,6 +402,8 @@ def main():
             "traffic": measured_traffic(args.workload, precision, head["transport_kernel"]),
             "algorithmic_bytes_per_launch": head["transport_bytes_per_launch"],
             "avg_launch_ms": head["transport_avg_launch_ms"],
+            "launches": head["transport_launches"],
+            "event_timed_launches": head["timed_launches"],
         },
         "copy_reference": {"kernel": "k_copy_u4", "gbs": copy["gbs"], "frac": copy["gbs"] / HBM_PEAK_GBS},
         "mean_leaves_per_step": head["mean_leaves_per_step"],

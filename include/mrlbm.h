@@ -146,19 +146,25 @@ int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int
 int mrlbm_leaves(mrlbm_ctx *ctx, int instance, uint32_t *cells, void *values, int64_t capacity,
                  int64_t *count);
 
-/* Counters of the work done since the last mrlbm_profile call (all instances). */
+/* Counters of the work done since the last mrlbm_profile call (all instances).
+ * With profiling on, graph-replayed steps (mrlbm_step) bracket the transport
+ * kernel of every 8th step, starting with the first, with HIP events inside the
+ * step graph; eager steps (MRLBM_GRAPH=0, mrlbm_adapt / mrlbm_transport_collide)
+ * time every phase of every step. transport_ms / timed_launches is the average
+ * duration of the kernel over the timed launches. */
 typedef struct {
   uint64_t leaf_updates;       /* complete leaves transported and collided, summed over launches */
   uint64_t transport_launches; /* launches of the transport-collision kernel */
-  double transport_ms;         /* HIP-event time of the transport-collision kernel alone */
-  double reconstruct_ms;       /* HIP-event time of the reconstructions before transport */
-  double adapt_ms;             /* HIP-event time of the mesh adaptation and transfer */
+  double transport_ms;         /* HIP-event time of the transport-collision kernel alone (timed launches) */
+  double reconstruct_ms;       /* HIP-event time of the reconstructions before transport (eager steps) */
+  double adapt_ms;             /* HIP-event time of the mesh adaptation and transfer (eager steps) */
   uint64_t timed_launches;     /* transport launches covered by the event timings */
 } mrlbm_counters;
 
-/* Reset the counters and switch per-phase HIP-event timing on (enable = 1) or
- * off (0). Leaf updates are always counted (on the device, by the transport
- * kernel). Timing records events on the context stream around each phase. */
+/* Reset the counters and switch HIP-event timing on (enable = 1) or off (0).
+ * Leaf updates are always counted (on the device, by the transport kernel).
+ * Timing records events on the context stream (see mrlbm_counters for which
+ * launches are timed). */
 int mrlbm_profile(mrlbm_ctx *ctx, int enable);
 
 /* Read the counters (synchronous). */

@@ -398,12 +398,18 @@ struct mrlbm_ctx {
   // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
   char *adj_ws;
   int adj_nsteps, adj_K;
-  // HIP graphs of one step, captured on a private stream: [transport inside the
-  // graph (0) or launched after it with timing events (1)][2 * cur + mcur]
+  // HIP graphs of one step, captured on a private stream: [plain (0) or with
+  // event-record nodes around the transport kernel (1)][2 * cur + mcur]. The
+  // timed graphs keep their source graph and event nodes, whose events are
+  // pointed at fresh pool events before each launch.
   bool use_graph;
   hipStream_t cap_stream;
   hipGraphExec_t graph[2][4];
+  hipGraph_t timed_src[4];
+  hipGraphNode_t timed_ev[4][2];
+  hipEvent_t ev_placeholder;
   bool profiling;
+  unsigned long long graph_steps;  // graph-replayed steps since profiling was switched on
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
   std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of the first of two events)
@@ -445,11 +451,49 @@ void drop_graphs(mrlbm_ctx *c) {
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
+  for (auto &g : c->timed_src)
+    if (g) {
+      (void)hipGraphDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Event-record nodes e0 -> (last kernel node) -> e1 in a captured linear graph
+// whose last node is the transport kernel; returns the two nodes.
+hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, hipGraphNode_t *n1) {
+  size_t n = 0;
+  hipError_t e = hipGraphGetNodes(g, nullptr, &n);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipErrorInvalidValue;
+  std::vector<hipGraphNode_t> nodes(n);
+  if ((e = hipGraphGetNodes(g, nodes.data(), &n)) != hipSuccess) return e;
+  hipGraphNode_t sink = nullptr;
+  for (hipGraphNode_t nd : nodes) {
+    size_t k = 0;
+    if ((e = hipGraphNodeGetDependentNodes(nd, nullptr, &k)) != hipSuccess) return e;
+    if (k == 0) {
+      if (sink) return hipErrorInvalidValue;  // not a chain
+      sink = nd;
+    }
+  }
+  hipGraphNodeType type;
+  if (!sink || (e = hipGraphNodeGetType(sink, &type)) != hipSuccess) return sink ? e : hipErrorInvalidValue;
+  if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;
+  size_t nd = 0;
+  if ((e = hipGraphNodeGetDependencies(sink, nullptr, &nd)) != hipSuccess) return e;
+  std::vector<hipGraphNode_t> deps(nd);
+  if (nd && (e = hipGraphNodeGetDependencies(sink, deps.data(), &nd)) != hipSuccess) return e;
+  for (hipGraphNode_t d : deps)
+    if ((e = hipGraphRemoveDependencies(g, &d, &sink, 1)) != hipSuccess) return e;
+  if ((e = hipGraphAddEventRecordNode(n0, g, deps.data(), nd, ev)) != hipSuccess) return e;
+  if ((e = hipGraphAddDependencies(g, n0, &sink, 1)) != hipSuccess) return e;
+  return hipGraphAddEventRecordNode(n1, g, &sink, 1, ev);
 }
 // Above this many cells (all instances and levels) the transport runs one
 // thread per leaf; below, one wavefront per population (more parallelism for
 // small leaf sets). Both variants compute bit-identical results.
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
+constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch
 constexpr size_t LEAF_LDS_MAX = 40 << 10;  // bytes of weight tables staged per block
 
 template <int DIM, int SCHEME, typename T>
@@ -585,11 +629,14 @@ struct Engine {
 
   // One full step replayed from a HIP graph, one graph per assignment of the
   // double buffers (a step swaps the mesh buffers and, in the transport, F). With
-  // profiling on, the graph ends after the reconstruction and the transport
-  // kernel is launched between timing events.
+  // profiling on, every TIMING_PERIOD-th step replays a graph in which
+  // event-record nodes bracket the transport kernel; before each such launch
+  // they are pointed at two fresh events. (Each event record drains the queue,
+  // some microseconds, so timing every step would slow the steps it measures.)
   static int step_graph(mrlbm_ctx *c) {
-    const int timed = c->profiling ? 1 : 0, par = c->mcur;
-    hipGraphExec_t &g = c->graph[timed][2 * c->cur + par];
+    const int timed = c->profiling && (c->graph_steps++ % TIMING_PERIOD == 0) ? 1 : 0;
+    const int par = c->mcur, key = 2 * c->cur + par;
+    hipGraphExec_t &g = c->graph[timed][key];
     if (!g) {
       const int cur0 = c->cur;
       hipStream_t user = c->stream;
@@ -600,20 +647,38 @@ struct Engine {
       hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
       int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
       if (rc == MRLBM_OK) reconstruct(c, (T *)c->F[c->cur], c->mcur);
-      if (rc == MRLBM_OK && !timed) rc = transport_kernel(c);
+      if (rc == MRLBM_OK) rc = transport_kernel(c);
       if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
       c->stream = user;
       c->profiling = prof;
       c->mcur = par;
       c->cur = cur0;
+      if (rc == MRLBM_OK && e == hipSuccess && timed)
+        e = bracket_last_kernel(graph, c->ev_placeholder, &c->timed_ev[key][0], &c->timed_ev[key][1]);
       if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+      if (rc == MRLBM_OK && e == hipSuccess && timed) {
+        c->timed_src[key] = graph;  // the event nodes belong to it
+        graph = nullptr;
+      }
       if (graph) (void)hipGraphDestroy(graph);
       if (rc != MRLBM_OK) return rc;
       if (e != hipSuccess) { g = nullptr; return MRLBM_ERR_HIP; }
     }
+    if (timed) {
+      for (int k = 0; k < 2; ++k) {
+        if (c->ev_used + k == c->ev_pool.size()) {
+          hipEvent_t ev;
+          if (hipEventCreate(&ev) != hipSuccess) return MRLBM_ERR_HIP;
+          c->ev_pool.push_back(ev);
+        }
+        if (hipGraphExecEventRecordNodeSetEvent(g, c->timed_ev[key][k], c->ev_pool[c->ev_used + k]) != hipSuccess)
+          return MRLBM_ERR_HIP;
+      }
+      c->ev_marks.push_back({PH_TRANSPORT, c->ev_used});
+      c->ev_used += 2;
+    }
     if (hipGraphLaunch(g, c->stream) != hipSuccess) return MRLBM_ERR_HIP;
-    c->mcur = 1 - par;  // the adaptation's swap
-    if (timed) return transport_kernel(c);
+    c->mcur = 1 - par;    // the adaptation's swap
     c->cur = 1 - c->cur;  // the transport's swap
     return MRLBM_OK;
   }
@@ -977,6 +1042,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->mcur = 0;
   c->has_state.assign(P.B, 0);
   c->profiling = false;
+  c->graph_steps = 0;
   c->ev_used = 0;
   c->adj_ws = nullptr;
   c->adj_nsteps = 0;
@@ -988,8 +1054,14 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->cap_stream = nullptr;
   for (auto &row : c->graph)
     for (auto &g : row) g = nullptr;
-  if (c->use_graph && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  for (auto &g : c->timed_src) g = nullptr;
+  c->ev_placeholder = nullptr;
+  if (hipEventCreate(&c->ev_placeholder) != hipSuccess) {
     delete c;
+    return MRLBM_ERR_HIP;
+  }
+  if (c->use_graph && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)mrlbm_destroy(c);
     return MRLBM_ERR_HIP;
   }
   {
@@ -1031,7 +1103,10 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   // Value buffers start at zero: cells outside the mesh hold scratch that then
   // depends only on the sequence of calls.
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
-  if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) { delete c; return MRLBM_ERR_HIP; }
+  if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) {
+    (void)mrlbm_destroy(c);
+    return MRLBM_ERR_HIP;
+  }
   *out = c;
   return MRLBM_OK;
 }
@@ -1159,6 +1234,7 @@ int mrlbm_profile(mrlbm_ctx *c, int enable) {
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long)));
   c->profiling = enable != 0;
+  c->graph_steps = 0;
   c->ev_used = 0;
   c->ev_marks.clear();
   return MRLBM_OK;
@@ -1321,10 +1397,9 @@ int mrlbm_autotune(mrlbm_ctx *c, int reps, mrlbm_tuning *out) {
 int mrlbm_destroy(mrlbm_ctx *c) {
   if (!c) return MRLBM_OK;
   (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
-  for (auto &row : c->graph)
-    for (auto g : row)
-      if (g) (void)hipGraphExecDestroy(g);
+  if (c->ev_placeholder) (void)hipEventDestroy(c->ev_placeholder);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return MRLBM_OK;

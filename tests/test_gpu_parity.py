@@ -320,6 +320,32 @@ def test_graph_steps_match_eager_launches(mr, monkeypatch):
             assert np.array_equal(sa[1][leaves], sb[1][leaves])
 
 
+def test_profiled_graph_steps_time_every_eighth_transport(mr):
+    """With profiling on, graph-replayed steps count every transport launch and
+    bracket the kernel of steps 0, 8, 16, ... with HIP events; the timed steps
+    compute the same results as untimed ones."""
+    items = _batch_cfgs("D2Q9")
+    cfgs = [c for c, _ in items]
+    states = {}
+    for prof in (False, True):
+        b = mr.Batch(cfgs, precision=4)
+        for i, (_, m0) in enumerate(items):
+            b.init_equilibrium(i, m0)
+        b.step(2)
+        b.profile(prof)
+        b.step(17)
+        cnt = b.counters()
+        b.profile(False)
+        if prof:
+            assert cnt["transport_launches"] == 17 and cnt["timed_launches"] == 3
+            assert 0.0 < cnt["transport_ms"] < 1e3
+        states[prof] = [b.get_state(i) for i in range(b.B)]
+        b.close()
+    for cfg, sa, sb in zip(cfgs, states[False], states[True]):
+        leaves = _leaf_entries(oracle.Oracle(cfg), sa[0])
+        assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1][leaves], sb[1][leaves])
+
+
 def _leaf_entries(o, tree):
     """Boolean mask of the complete-leaf entries of a values array (the other
     entries hold reconstruction scratch, which the state does not define)."""
