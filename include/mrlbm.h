@@ -131,9 +131,10 @@ int mrlbm_set_state(mrlbm_ctx *ctx, int instance, const uint8_t *tree, const voi
 int mrlbm_sizes(const mrlbm_ctx *ctx, int instance, int64_t *total_cells, int *q);
 
 /* Diagnostics of one instance (synchronous): mass = sum over complete
- * leaves of |C_l| / |C_J| * sum_h f^h, accumulated in double with a fixed
- * order; per-level counts of complete leaves, internal tree cells and ghost
- * cells ([jmax + 1] each, any of them may be NULL).
+ * leaves of |C_l| / |C_J| * sum_h f^h, accumulated in double with
+ * compensated (Neumaier) summation in a fixed order, in either precision;
+ * per-level counts of complete leaves, internal tree cells and ghost cells
+ * ([jmax + 1] each, any of them may be NULL).
  * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite. */
 int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int64_t *internal,
                 int64_t *ghosts);

@@ -1252,38 +1252,54 @@ __global__ void __launch_bounds__(BLK) k_init_equilibrium(const Inst<T> *__restr
 
 constexpr int RED_BLOCKS = 64;
 
+// Compensated summation (Neumaier's variant of Kahan's): s + c carries the
+// rounding error of every addition into s. Needs unfused, unreassociated
+// double arithmetic (the library is built with -ffp-contract=off).
+__device__ __forceinline__ void neumaier_add(double &s, double &c, double t) {
+  const double u = s + t;
+  c += fabs(s) >= fabs(t) ? (s - u) + t : (t - u) + s;
+  s = u;
+}
+
 // Mass partial sums of instance blockIdx.y (fixed grid and order, so the result
 // is reproducible) and a non-finite flag.
 template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(BLK) k_mass_partial(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ F,
                                                       const uint32_t *__restrict__ leaves, const int *__restrict__ lvl,
                                                       double *__restrict__ part, int *__restrict__ bad) {
-  __shared__ double red[BLK];
+  __shared__ double red_s[BLK], red_c[BLK];
   const int i = blockIdx.y;
   const Inst<T> &In = I[i];
   const int *L = lvl + (i * NCAT + CAT_LEAF) * LVL_STRIDE;
   const int beg = L[In.jmin], n = L[In.jmax + 1] - beg;
-  double acc = 0.0;
+  double acc = 0.0, comp = 0.0;
   int nonfinite = 0;
   for (int k = blockIdx.x * BLK + threadIdx.x; k < n; k += gridDim.x * BLK) {
     const uint32_t e = leaves[beg + k];
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    double sum = 0.0;
     for (int h = 0; h < Q; ++h) {
       const double v = (double)F[foff(In, DIM, Q, l, h) + c];
       nonfinite |= !isfinite(v);
-      sum += v;
+      neumaier_add(acc, comp, ldexp(v, DIM * (In.jmax - l)));  // the volume factor is exact
     }
-    acc += ldexp(sum, DIM * (In.jmax - l));
   }
-  red[threadIdx.x] = acc;
+  red_s[threadIdx.x] = acc;
+  red_c[threadIdx.x] = comp;
   __syncthreads();
   for (int off = BLK / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    if (threadIdx.x < off) {
+      double s2 = red_s[threadIdx.x], c2 = red_c[threadIdx.x] + red_c[threadIdx.x + off];
+      neumaier_add(s2, c2, red_s[threadIdx.x + off]);
+      red_s[threadIdx.x] = s2;
+      red_c[threadIdx.x] = c2;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[i * RED_BLOCKS + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    part[2 * (i * RED_BLOCKS + blockIdx.x)] = red_s[0];
+    part[2 * (i * RED_BLOCKS + blockIdx.x) + 1] = red_c[0];
+  }
   if (nonfinite) atomicOr(bad, 1);
 }
 

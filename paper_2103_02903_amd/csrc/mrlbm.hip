@@ -268,7 +268,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
   P.off_W = take(P.rs * std::max(1, P.nmax) * P.q * ws);
   P.off_C = take(P.rs * std::max(1, P.nmax) * P.q * cs);
-  P.off_red = take(sizeof(double) * RED_BLOCKS * B);
+  P.off_red = take(sizeof(double) * 2 * RED_BLOCKS * B);
   P.off_bad = take(sizeof(int) * 4);
   P.off_cnt = take(sizeof(unsigned long long) * 4);
   P.off_inst = take(std::max(sizeof(Inst<double>), sizeof(Inst<float>)) * B);
@@ -1190,14 +1190,19 @@ int mrlbm_stats(mrlbm_ctx *c, int instance, double *mass, int64_t *leaves, int64
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemset(c->bad, 0, sizeof(int)));
     dispatch<MassOp>(c);
-    std::vector<double> part(RED_BLOCKS * c->P.B);
+    std::vector<double> part(2 * RED_BLOCKS * c->P.B);
     int bad = 0;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(part.data(), c->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost));
-    double s = 0.0;
-    for (int k = 0; k < RED_BLOCKS; ++k) s += part[instance * RED_BLOCKS + k];
-    *mass = s;
+    // compensated sum of the per-block (sum, compensation) pairs, fixed order
+    double s = 0.0, e = 0.0;
+    for (int k = 0; k < 2 * RED_BLOCKS; ++k) {
+      const double t = part[2 * instance * RED_BLOCKS + k], u = s + t;
+      e += std::fabs(s) >= std::fabs(t) ? (s - u) + t : (t - u) + s;
+      s = u;
+    }
+    *mass = s + e;
     if (bad) rc = MRLBM_ERR_NONFINITE;
   }
   int lvl[NCAT * LVL_STRIDE];
