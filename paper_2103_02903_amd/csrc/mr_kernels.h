@@ -1099,16 +1099,42 @@ __device__ __forceinline__ T ld_off(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 template <typename T>
 using const_ptr = const __attribute__((address_space(4))) T *;
 
+// Row buffers of one wavefront: 68 columns (64 leaves and two on each side)
+// per staged row; one row for each x-axis velocity and five for each diagonal
+// one, at consecutive slots in population order.
+constexpr int ROWBUF = 68;
+template <int SCHEME>
+__host__ __device__ constexpr int row_slot(int h) {
+  int r = 0;
+  for (int k = 0; k < h; ++k)
+    if (Vel<SCHEME>::ex(k) != 0) r += Vel<SCHEME>::ey(k) == 0 ? 1 : 5;
+  return r;
+}
+template <int SCHEME>
+__host__ __device__ constexpr int row_slots() { return row_slot<SCHEME>(Vel<SCHEME>::Q); }
+
+// Order LDS accesses of the lanes of one wavefront: the compiler may not move
+// memory operations across it, and the LDS executes a wavefront's operations
+// in order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // leaf_update for a wavefront whose leaves all lie on level l of instance In
 // (l, In uniform): the population arrays of level l are uniform buffers, the
 // 5^d stencil is a sum of a row and a column byte offset computed once per
-// leaf, and the weights of (n, h) are uniform scalar loads. Same operations in
-// the same order as transport_pop.
+// leaf, and the weights of (n, h) are uniform scalar loads. With `row` (2D,
+// uniform: the 64 leaves are the consecutive cells x0..x0+63 of one row, lane
+// k at x0 + k, above the finest level), the rows of the stencils of the x-axis
+// and diagonal velocities are staged once per wavefront in `rowbuf` (68
+// columns each, coalesced) and the 5 or 25 values of each leaf are read from
+// there. Same operations in the same order as transport_pop.
 template <int DIM, int SCHEME, typename T>
 __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint32_t c, const T *__restrict__ Fs,
                                                   T *__restrict__ Fo, const uint8_t *__restrict__ code,
                                                   const T *__restrict__ Wt, const T *__restrict__ Ct,
-                                                  T *__restrict__ tape) {
+                                                  T *__restrict__ tape, bool row, T (*rowbuf)[ROWBUF]) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q;
   constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
@@ -1142,11 +1168,57 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
     // the loads of several populations can be in flight together; then the
     // detail corrections (leaves next to finer cells only), then the update.
     T acc[Q], fc[Q];
+    const int lane = threadIdx.x & 63;
+    if (DIM == 2 && row) {
+      // Stage the stencil rows of every x-axis and diagonal velocity at once:
+      // all loads first (one memory latency for the chunk), then the LDS writes.
+      const uint32_t cst0 = (uint32_t)wrapl(x - 2, l) * (uint32_t)sizeof(T);   // column x0 - 2 + lane
+      const uint32_t cst1 = (uint32_t)wrapl(x + 62, l) * (uint32_t)sizeof(T);  // x0 + 62 + lane (lanes 0..3)
+      constexpr int NR = row_slots<SCHEME>();
+      T v0[NR], v1[NR];
+#pragma unroll
+      for (int h = 0; h < Q; ++h) {
+        if (V::ex(h) == 0) continue;
+        const __amdgpu_buffer_rsrc_t base = pop_rsrc(Fl0 + h * nl, nl);
+        const int rs = row_slot<SCHEME>(h);
+        const int b0 = V::ey(h) == 0 ? 2 : 0, b1 = V::ey(h) == 0 ? 2 : 4;
+#pragma unroll
+        for (int b = b0; b <= b1; ++b) {
+          v0[rs + b - b0] = ld_off<T>(base, rowb[b] + cst0);
+          v1[rs + b - b0] = lane < 4 ? ld_off<T>(base, rowb[b] + cst1) : T(0);
+        }
+      }
+      wave_lds_sync();  // the previous chunk's reads of the buffer come first
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        rowbuf[r][lane] = v0[r];
+        if (lane < 4) rowbuf[r][64 + lane] = v1[r];
+      }
+      wave_lds_sync();
+    }
 #pragma unroll
     for (int h = 0; h < Q; ++h) {
       const int ex = V::ex(h), ey = V::ey(h);
       const __amdgpu_buffer_rsrc_t base = pop_rsrc(Fl0 + h * nl, nl);
       const_ptr<T> W = (const_ptr<T>)(Wt + ((long long)nn * Q + h) * WS);
+      if (DIM == 2 && row && ex != 0) {
+        // from the staged rows: row y at slot rs (x-axis velocity) or rows
+        // y-2 .. y+2 at slots rs .. rs+4 (diagonal)
+        const int rs = row_slot<SCHEME>(h);
+        fc[h] = rowbuf[ey == 0 ? rs : rs + 2][lane + 2];
+        T a_h = T(0);
+        if (ey == 0) {
+#pragma unroll
+          for (int a = 0; a < 5; ++a) a_h = fma(W[10 + a], rowbuf[rs][lane + a], a_h);
+        } else {
+#pragma unroll
+          for (int b = 0; b < 5; ++b)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) a_h = fma(W[b * 5 + a], rowbuf[rs + b][lane + a], a_h);
+        }
+        acc[h] = a_h;
+        continue;
+      }
       fc[h] = ld_off<T>(base, own);
       T a_h = T(0);
       if (ex == 0 && ey == 0) {
@@ -1190,26 +1262,17 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
 // registers, no barriers; every wavefront takes a chunk of 64 leaves. Register
 // budget for 4 waves per SIMD (latency hiding of the stencil loads). A chunk
 // whose leaves share one level (all but those that straddle a level boundary)
-// takes leaf_update_level.
-template <int DIM, int SCHEME, typename T, bool LDSW>
+// takes leaf_update_level, in row mode when its leaves are one row segment.
+template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                             unsigned long long *__restrict__ counters, T *__restrict__ tape, int nw, int nc) {
+                             unsigned long long *__restrict__ counters, T *__restrict__ tape) {
   constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
-  // LDSW: the weight tables (nw + nc values, all n) are staged in LDS, so the
-  // per-leaf weight reads go to the LDS and not to the vector memory path
-  // that the stencil loads saturate.
-  extern __shared__ __align__(16) unsigned char dyn_lds[];
-  T *sW = reinterpret_cast<T *>(dyn_lds), *sC = sW + nw;
-  if (LDSW) {
-    for (int k = threadIdx.x; k < nw; k += BLK) sW[k] = Wt[k];
-    for (int k = threadIdx.x; k < nc; k += BLK) sC[k] = Ct[k];
-  }
-  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);  // (its barrier also publishes the tables)
-  const T *W = LDSW ? sW : Wt, *C = LDSW ? sC : Ct;
+  __shared__ T rowbuf[WPB][DIM == 2 ? row_slots<SCHEME>() : 1][ROWBUF];
+  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     unsigned long long tot = 0;
     for (int i = 0; i < bt.B; ++i) tot += (unsigned long long)s.cnt[i];
@@ -1226,12 +1289,16 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
     const uint32_t c = e & CELL_MASK;
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
+    // row mode: 64 consecutive cells of one row of a level above the finest
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(c);
+    const bool row = DIM == 2 && one_level && l0 < I[i].jmax && __ballot(valid && c == c0 + (uint32_t)lane) == ~0ull &&
+                     (c0 & ((1u << l0) - 1)) + 63u < (1u << l0);
     if (!valid) continue;
     const Inst<T> &In = I[i];
     if (one_level)
-      leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape);
+      leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);
     else
-      leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, W, C, tape);
+      leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);
   }
 }
 

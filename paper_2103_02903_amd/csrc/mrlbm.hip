@@ -494,7 +494,6 @@ hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, 
 // small leaf sets). Both variants compute bit-identical results.
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
 constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch
-constexpr size_t LEAF_LDS_MAX = 40 << 10;  // bytes of weight tables staged per block
 
 template <int DIM, int SCHEME, typename T>
 struct Engine {
@@ -605,20 +604,9 @@ struct Engine {
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
     const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
     if (per_leaf)
-    {
-      // weight tables in LDS if they fit beside the list segments
-      const int nn = std::max(1, P.nmax), ws = DIM == 2 ? 25 : 5, cs = DIM == 2 ? 36 : 6;
-      const int nw = nn * Q * ws, nc = nn * Q * cs;
-      const size_t lds = sizeof(T) * (size_t)(nw + nc);
-      const bool fit = lds <= LEAF_LDS_MAX;
-      const unsigned g = list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all);
-      if (fit)
-        k_transport_collide_leaf<DIM, SCHEME, T, true><<<g, BLK, lds, c->stream>>>(
-            c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt, tape, nw, nc);
-      else
-        k_transport_collide_leaf<DIM, SCHEME, T, false><<<g, BLK, 0, c->stream>>>(
-            c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt, tape, 0, 0);
-    }
+      k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0,
+                                                 c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
+                                                              (const T *)c->W, (const T *)c->C, c->cnt, tape);
     else
       k_transport_collide_pop<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt, tape);
