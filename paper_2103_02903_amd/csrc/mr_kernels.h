@@ -1264,7 +1264,7 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
 // whose leaves share one level (all but those that straddle a level boundary)
 // takes leaf_update_level, in row mode when its leaves are one row segment.
 template <int DIM, int SCHEME, typename T>
-__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
