@@ -199,13 +199,15 @@ int mrlbm_adjoint(mrlbm_ctx *ctx, const void *abar_final, void *mbar0, double *s
 /* ---- Launch schedule and its autotuner ----
  * The list kernels (projection, prediction, details, transfer, transport) run
  * a capped number of blocks that stride over the chunks of 64 list items; the
- * transport has a per-leaf and a per-population variant. The autotuner times
+ * transport and the details have a per-item variant (one thread per leaf or
+ * internal parent, all populations in it) and a per-population variant (one
+ * wavefront per population), chosen together. The autotuner times
  * every schedule of a small grid on the context's current state (steps that
  * leave the state unchanged, replayed from HIP graphs between HIP events),
  * keeps the fastest, and caches it for the process per (device architecture,
  * scheme, precision, floor(log2(leaves))). Schedules do not change results. */
 typedef struct {
-  int transport_variant; /* 1: one thread per leaf, 2: one wavefront per population */
+  int transport_variant; /* transport and details: 1 one thread per item, 2 one wavefront per population */
   int list_grid_all;     /* block cap of the all-level list kernels (8..65536) */
   int list_grid_level;   /* block cap of the per-level list kernels (8..65536) */
   int from_cache;        /* set by mrlbm_autotune: 1 if taken from the cache */

@@ -208,6 +208,52 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
   }
 }
 
+// The same per internal parent, one thread per parent and all populations in
+// that thread: no block barriers, and the loads of every population can be in
+// flight together. Same arithmetic and decisions as k_details.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *__restrict__ I,
+                                                      const T *__restrict__ F, const uint32_t *__restrict__ lst,
+                                                      const int *__restrict__ lvl, uint8_t *__restrict__ keep,
+                                                      uint8_t *__restrict__ refg) {
+  constexpr int WPB = BLK / 64;
+  __shared__ SegLDS s;
+  load_segments(s, I, lvl, bt.B, CAT_INTERNAL, -1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
+    const int i = upper_index(s.pre, bt.B, ch);
+    const int item = (ch - s.pre[i]) * CHUNK + lane;
+    if (item >= s.cnt[i]) continue;
+    const Inst<T> &In = I[i];
+    const uint32_t e = lst[s.beg[i] + item];
+    const int lp = (int)(e >> LEVEL_SHIFT), l = lp + 1;
+    const uint32_t p = e & CELL_MASK;
+    int px, py;
+    coords<DIM>(lp, p, px, py);
+    T D = T(0);
+#pragma unroll
+    for (int h = 0; h < Q; ++h) {
+      ParentStencil<DIM, T> st;
+      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py);
+      const T *C = F + foff(In, DIM, Q, l, h);
+      T dmax = T(0);
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const T d = C[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
+          const T a = d < T(0) ? -d : d;
+          dmax = a > dmax ? a : dmax;
+        }
+      D = h == 0 ? dmax : (dmax > D ? dmax : D);
+    }
+    if (D >= In.eps_l[l]) {
+      uint8_t *k = keep + In.loff[l];
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) k[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] = 1;
+    }
+    if (l > In.jmin && l < In.jmax && D >= In.ref_l[l]) refg[In.loff[lp] + p] = 1;
+  }
+}
+
 // Block -> (instance, first cell) of a dense pass over one level per instance:
 // one static info word per block, instance | (chunk << 8).
 __device__ __forceinline__ long long dense_block(const uint32_t *__restrict__ info, int &i) {

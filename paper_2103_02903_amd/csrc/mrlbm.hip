@@ -489,9 +489,9 @@ hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, 
   if ((e = hipGraphAddDependencies(g, n0, &sink, 1)) != hipSuccess) return e;
   return hipGraphAddEventRecordNode(n1, g, &sink, 1, ev);
 }
-// Above this many cells (all instances and levels) the transport runs one
-// thread per leaf; below, one wavefront per population (more parallelism for
-// small leaf sets). Both variants compute bit-identical results.
+// Above this many cells (all instances and levels) the transport and the
+// details run one thread per item; below, one wavefront per population (more
+// parallelism for small sets). Both variants compute bit-identical results.
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
 constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch
 
@@ -509,6 +509,12 @@ struct Engine {
     return list_grid(n, c->grid_level);
   }
   static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, c->grid_all); }
+  // One thread per item and all populations in it (large sets), or one
+  // wavefront per population (small sets: nine times the threads): for the
+  // transport and the details.
+  static bool per_leaf(const mrlbm_ctx *c) {
+    return c->transport_variant == 1 || (c->transport_variant == 0 && c->P.ctotal >= LEAF_KERNEL_CELLS);
+  }
 
   static void compact(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
@@ -561,8 +567,12 @@ struct Engine {
     // adaptation, or the creation, cleared them.
     for (int l = P.maxJ - 1; l >= P.jmin; --l)
       k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), Fc, li, c->lvl[mo], l);
-    k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
-        c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
+    if (per_leaf(c))
+      k_details_leaf<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
+          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
+    else
+      k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
+          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
     for (int l = P.maxJ; l >= P.jmin + 2; --l) {
       const int nb = P.dtab_total(2, l - 2);
       if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);
@@ -602,8 +612,7 @@ struct Engine {
     T *Fn = (T *)c->F[1 - c->cur];
     phase_mark(c, PH_TRANSPORT, true);
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
-    const bool per_leaf = c->transport_variant == 1 || (c->transport_variant == 0 && P.ctotal >= LEAF_KERNEL_CELLS);
-    if (per_leaf)
+    if (per_leaf(c))
       k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0,
                                                  c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
                                                               (const T *)c->W, (const T *)c->C, c->cnt, tape);

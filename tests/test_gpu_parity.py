@@ -296,7 +296,8 @@ def test_batch_instance_equals_single_run(mr):
 
 
 def test_transport_variants_bit_identical(mr, monkeypatch):
-    """The per-leaf and per-population transport kernels compute the same bits."""
+    """The per-item and per-population variants of the transport and details
+    kernels compute the same meshes and the same bits."""
     cfg, m0 = W.shear_layer_d2q9(jmin=3, jmax=8, eps=1e-4, re=1000.0, width=1.0 / 40)
     out = {}
     for v in ("leaf", "pop"):
