@@ -330,10 +330,10 @@ __device__ __forceinline__ bool level_vec(const uint8_t *p, long long nl) {
 // cell of level l is kept. One thread per cell g of level l-2 (its 4^d
 // grandchildren are read).
 template <int DIM, typename T>
-__device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__restrict__ keep, int l, long long cell) {
+__device__ __forceinline__ bool ancestor_any(const Inst<T> &In, const uint8_t *__restrict__ keep, int l,
+                                             long long cell) {
   const int lg = l - 2;
   const uint8_t *kl = keep + In.loff[l];
-  uint8_t *kp = keep + In.loff[l - 1];
   int x, y;
   coords<DIM>(lg, (uint32_t)cell, x, y);
   bool any = false;
@@ -346,9 +346,19 @@ __device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__rest
     for (int b = 0; b < 4; ++b)
       for (int a = 0; a < 4; ++a) any |= kl[cidx<2>(l, 4 * x + a, 4 * y + b)] != 0;
   }
-  if (any)
-    for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-      for (int dx = 0; dx < 2; ++dx) kp[cidx<DIM>(l - 1, 2 * x + dx, 2 * y + dy)] = 1;
+  return any;
+}
+template <int DIM, typename T>
+__device__ __forceinline__ void ancestor_mark(const Inst<T> &In, uint8_t *__restrict__ keep, int l, long long cell) {
+  uint8_t *kp = keep + In.loff[l - 1];
+  int x, y;
+  coords<DIM>(l - 2, (uint32_t)cell, x, y);
+  for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+    for (int dx = 0; dx < 2; ++dx) kp[cidx<DIM>(l - 1, 2 * x + dx, 2 * y + dy)] = 1;
+}
+template <int DIM, typename T>
+__device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__restrict__ keep, int l, long long cell) {
+  if (ancestor_any<DIM, T>(In, keep, l, cell)) ancestor_mark<DIM, T>(In, keep, l, cell);
 }
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
@@ -465,6 +475,89 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
     for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
       for (int dx = 0; dx < 2; ++dx) tl[cidx<DIM>(l, 2 * x + dx, 2 * y + dy)] = 1;
   if (box) tp[cell] = 1;
+}
+
+// ---------------------------------------------------------------- coarse levels
+// The levels of an instance with at most COARSE_CELLS cells are walked by one
+// block of CBLK threads per instance, level after level with block barriers,
+// in a single launch (a per-level launch costs a few microseconds whatever its
+// work). Each level runs the same per-cell operations as the per-level kernels;
+// the finer levels keep one launch per level.
+constexpr int CBLK = 1024;
+constexpr long long COARSE_CELLS = 1024;
+
+// Ghost classification of levels min(lc, jmax) .. jmin+1, finest first; bit L
+// of v16 selects the 16-cell form for level L.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(CBLK) k_classify_ghost_coarse(const Inst<T> *__restrict__ I,
+                                                                uint8_t *__restrict__ code, int lc,
+                                                                unsigned long long v16) {
+  const Inst<T> &In = I[blockIdx.x];
+  for (int l = lc < In.jmax ? lc : In.jmax; l > In.jmin; --l) {
+    const long long nl = ncells_d(DIM, l);
+    if ((v16 >> l) & 1ull) {
+      for (long long c0 = (long long)threadIdx.x * CPT; c0 < nl; c0 += (long long)CBLK * CPT)
+        ghost_run16<DIM, T>(In, code, l, c0);
+    } else {
+      for (long long c0 = (long long)threadIdx.x * 4; c0 < nl; c0 += (long long)CBLK * 4)
+        ghost_run4<DIM, T>(In, code, l, c0);
+    }
+    __syncthreads();
+  }
+}
+
+// Ancestor closure for l = min(lc + 2, jmax) .. jmin+2 (cells of level l-2).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(CBLK) k_ancestor_coarse(const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
+                                                          int lc) {
+  const Inst<T> &In = I[blockIdx.x];
+  for (int l = lc + 2 < In.jmax ? lc + 2 : In.jmax; l >= In.jmin + 2; --l) {
+    const long long n = ncells_d(DIM, l - 2);
+    for (long long cell = threadIdx.x; cell < n; cell += CBLK) ancestor_cell<DIM, T>(In, keep, l, cell);
+    __syncthreads();
+  }
+}
+
+// Projection of the internal cells of levels min(lc, jmax-1) .. jmin.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                         const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                         int lc) {
+  const int i = blockIdx.x;
+  const Inst<T> &In = I[i];
+  const int *L = lvl + (i * NCAT + CAT_INTERNAL) * LVL_STRIDE;
+  for (int l = lc < In.jmax - 1 ? lc : In.jmax - 1; l >= In.jmin; --l) {
+    const int b = L[l], n = L[l + 1] - b;
+    for (int k = threadIdx.x; k < n * Q; k += CBLK) {  // population-major: lanes on consecutive items
+      const int h = k / n, item = k - h * n;
+      const uint32_t c = lst[b + item] & CELL_MASK;
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      F[foff(In, DIM, Q, l, h) + c] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
+    }
+    __syncthreads();
+  }
+}
+
+// Ghost predictions of levels jmin+1 .. min(lc, jmax), coarsest first.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                       const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                       int lc) {
+  const int i = blockIdx.x;
+  const Inst<T> &In = I[i];
+  const int *L = lvl + (i * NCAT + CAT_GHOST) * LVL_STRIDE;
+  for (int l = In.jmin + 1; l <= (lc < In.jmax ? lc : In.jmax); ++l) {
+    const int b = L[l], n = L[l + 1] - b;
+    for (int k = threadIdx.x; k < n * Q; k += CBLK) {
+      const int h = k / n, item = k - h * n;
+      const uint32_t c = lst[b + item] & CELL_MASK;
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- fused launches

@@ -509,6 +509,13 @@ struct Engine {
     return list_grid(n, c->grid_level);
   }
   static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, c->grid_all); }
+  // Finest level that the one-block-per-instance kernels walk: at most
+  // COARSE_CELLS cells per instance.
+  static int coarse_cap() {
+    int lc = 0;
+    while ((1ll << (DIM * (lc + 1))) <= COARSE_CELLS) ++lc;
+    return lc;
+  }
   // One thread per item and all populations in it (large sets), or one
   // wavefront per population (small sets: nine times the threads): for the
   // transport and the details.
@@ -529,7 +536,8 @@ struct Engine {
     const Plan &P = c->P;
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
                                                               c->refg);
-    for (int l = P.maxJ; l > P.jmin; --l) {
+    const int lc = coarse_cap();
+    for (int l = P.maxJ; l > std::max(P.jmin, lc); --l) {
       if (P.ghost16[l]) {
         const int nb = P.dtab_total(3, l);
         if (nb)
@@ -540,8 +548,24 @@ struct Engine {
           k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l);
       }
     }
+    if (lc > P.jmin) {
+      unsigned long long v16 = 0;
+      for (int l = 0; l <= lc; ++l)
+        if (P.ghost16[l]) v16 |= 1ull << l;
+      k_classify_ghost_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->code[m], lc, v16);
+    }
 
     compact(c, m);
+  }
+
+  // Projections of the internal cells of a mesh: levels above the coarse cap
+  // one launch each (fine to coarse), then the coarse levels in one launch.
+  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl) {
+    const Plan &P = c->P;
+    const int lc = coarse_cap();
+    for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l)
+      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
+    if (lc >= P.jmin) k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc);
   }
 
   // Reconstruction on mesh m inside F: projections upward, ghost predictions downward.
@@ -549,9 +573,10 @@ struct Engine {
     const Plan &P = c->P;
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
-    for (int l = P.maxJ - 1; l >= P.jmin; --l)
-      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, c->lvl[m], l);
-    for (int l = P.jmin + 1; l <= P.maxJ; ++l)
+    const int lc = coarse_cap();
+    project_all(c, F, li, c->lvl[m]);
+    if (lc > P.jmin) k_ghost_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, lg, c->lvl[m], lc);
+    for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
       k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
   }
 
@@ -565,18 +590,19 @@ struct Engine {
     // Projections of the old mesh (the details read tree cells only). The keep
     // and refine flags are zero here: the tree classification of the previous
     // adaptation, or the creation, cleared them.
-    for (int l = P.maxJ - 1; l >= P.jmin; --l)
-      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), Fc, li, c->lvl[mo], l);
+    project_all(c, Fc, li, c->lvl[mo]);
     if (per_leaf(c))
       k_details_leaf<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
     else
       k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
-    for (int l = P.maxJ; l >= P.jmin + 2; --l) {
+    const int lc = coarse_cap();
+    for (int l = P.maxJ; l >= std::max(P.jmin + 2, lc + 3); --l) {
       const int nb = P.dtab_total(2, l - 2);
       if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);
     }
+    if (lc + 2 >= P.jmin + 2) k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
 
     k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
     // Grading (levels maxJ .. jmin+1) beside the old mesh's ghost predictions
