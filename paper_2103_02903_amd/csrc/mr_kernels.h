@@ -942,11 +942,17 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
   }
 }
 
-template <int DIM, typename T>
+// With F (the adaptation: code holds the new mesh, code_old the old one), the
+// same pass also performs the transfer to the new leaves in place (Algorithm
+// 1): a run with leaves reads the same 16 old codes, and its leaves that were
+// outside the old mesh are predicted from level l-1; every other new leaf
+// already holds its value in F (see the adaptation).
+template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T> *__restrict__ I,
                                                          const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                          const int *__restrict__ boff, uint32_t *__restrict__ lists,
-                                                         int nblocks) {
+                                                         int nblocks, const uint8_t *__restrict__ code_old,
+                                                         T *__restrict__ F) {
   __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
@@ -955,8 +961,9 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
   const uint8_t *cl = code + I[i].loff[l];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long c0 = base + CPT * threadIdx.x;
+  const bool vec = level_vec(cl, nl);
   Run16 r = {{0, 0, 0, 0}};
-  if (c0 < nl) r = ld16(cl, c0, nl, level_vec(cl, nl));
+  if (c0 < nl) r = ld16(cl, c0, nl, vec);
   int n[NCAT] = {0, 0, 0}, incl[NCAT];
 #pragma unroll
   for (int k = 0; k < 4; ++k) count_codes(r.w[k], n);
@@ -984,36 +991,23 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     const int k = cat_of((uint8_t)(r.w[t >> 2] >> (8 * (t & 3))));
     if (k >= 0) lists[k * bt.ctotal + pos[k]++] = tag | (uint32_t)(c0 + t);
   }
-}
-
-// ---------------------------------------------------------------- transfer
-// Data of the new complete leaves from the old reconstruction, in place: the
-// value of a new leaf is the old reconstruction's value at that cell. An old
-// leaf keeps its value, a merged cell (old internal) already holds its
-// projection and an old ghost its prediction, so only cells outside the old
-// mesh are written, with the prediction from level l-1. Their parent stencils
-// lie in the old mesh (the old tree is graded and refines by one level), so no
-// cell read here is written here. One thread per new leaf.
-template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(BLK) k_transfer(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                  const uint8_t *__restrict__ code_old,
-                                                  const uint32_t *__restrict__ leaves, const int *__restrict__ lvl) {
-  constexpr int WPB = BLK / 64;
-  __shared__ SegLDS s;
-  load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
-    const int i = upper_index(s.pre, bt.B, ch);
-    const int item = (ch - s.pre[i]) * CHUNK + lane;
-    if (item >= s.cnt[i]) continue;
-    const uint32_t e = leaves[s.beg[i] + item];
-    const int l = (int)(e >> LEVEL_SHIFT);
-    const uint32_t c = e & CELL_MASK;
-    if (code_old[I[i].loff[l] + c] != C_NONE) continue;
-    int x, y;
-    coords<DIM>(l, c, x, y);
-    for (int h = 0; h < Q; ++h)
-      F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y);
+  if (F && n[CAT_LEAF]) {
+    const uint8_t *co = code_old + I[i].loff[l];
+    const Run16 o = ld16(co, c0, nl, level_vec(co, nl));
+    uint32_t created[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) created[k] = leaf_flags(r.w[k]) & none_flags(o.w[k]);
+    if (created[0] | created[1] | created[2] | created[3]) {
+      const Inst<T> &In = I[i];
+      for (int t = 0; t < 16; ++t) {
+        if (!((created[t >> 2] >> (8 * (t & 3))) & 1u)) continue;
+        const long long c = c0 + t;
+        int x, y;
+        coords<DIM>(l, (uint32_t)c, x, y);
+        for (int h = 0; h < Q; ++h)
+          F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+      }
+    }
   }
 }
 

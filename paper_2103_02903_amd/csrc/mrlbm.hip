@@ -523,16 +523,19 @@ struct Engine {
     return c->transport_variant == 1 || (c->transport_variant == 0 && c->P.ctotal >= LEAF_KERNEL_CELLS);
   }
 
-  static void compact(mrlbm_ctx *c, int m) {
+  // Lists of mesh m. With F, also the transfer from the mesh in code_old into
+  // the new leaves of mesh m, in place in F (the adaptation).
+  static void compact(mrlbm_ctx *c, int m, const uint8_t *code_old = nullptr, T *F = nullptr) {
     const Plan &P = c->P;
     k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks);
     k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks);
-    k_compact_scatter<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
-                                                                c->lists[m], P.nblocks);
+    k_compact_scatter<DIM, Q, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
+                                                                   c->lists[m], P.nblocks, code_old, F);
   }
 
-  // Codes (leaf / internal / ghost) of the membership array tnew into code[m].
-  static void classify(mrlbm_ctx *c, int m) {
+  // Codes (leaf / internal / ghost) of the membership array tnew into code[m],
+  // then its lists (and, with F, the transfer from the mesh in code_old).
+  static void classify(mrlbm_ctx *c, int m, const uint8_t *code_old = nullptr, T *F = nullptr) {
     const Plan &P = c->P;
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
                                                               c->refg);
@@ -555,7 +558,7 @@ struct Engine {
       k_classify_ghost_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->code[m], lc, v16);
     }
 
-    compact(c, m);
+    compact(c, m, code_old, F);
   }
 
   // Projections of the internal cells of a mesh: levels above the coarse cap
@@ -614,9 +617,13 @@ struct Engine {
                                                              Fc, lg, c->lvl[mo], lh, (int)G);
     }
 
-    classify(c, mn);
-    k_transfer<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
-        c->bt, I(c), Fc, c->code[mo], c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn]);
+    // new codes and lists, with the transfer in place: a new leaf's value is
+    // the old reconstruction's value at that cell, which F already holds for
+    // old leaves, merged cells (their projection) and old ghosts (their
+    // prediction); only cells outside the old mesh are predicted from level
+    // l-1, whose parent stencils lie in the old mesh (the old tree is graded
+    // and refines by one level), so nothing read there is written there.
+    classify(c, mn, c->code[mo], Fc);
     phase_mark(c, PH_ADAPT, false);
     c->mcur = mn;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
