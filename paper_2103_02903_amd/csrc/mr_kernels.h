@@ -528,12 +528,15 @@ __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restri
   const int *L = lvl + (i * NCAT + CAT_INTERNAL) * LVL_STRIDE;
   for (int l = lc < In.jmax - 1 ? lc : In.jmax - 1; l >= In.jmin; --l) {
     const int b = L[l], n = L[l + 1] - b;
-    for (int k = threadIdx.x; k < n * Q; k += CBLK) {  // population-major: lanes on consecutive items
-      const int h = k / n, item = k - h * n;
+    for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
       const uint32_t c = lst[b + item] & CELL_MASK;
       int x, y;
       coords<DIM>(l, c, x, y);
-      F[foff(In, DIM, Q, l, h) + c] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
+      T v[Q];
+#pragma unroll
+      for (int h = 0; h < Q; ++h) v[h] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
+#pragma unroll
+      for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
     }
     __syncthreads();
   }
@@ -549,12 +552,25 @@ __global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict
   const int *L = lvl + (i * NCAT + CAT_GHOST) * LVL_STRIDE;
   for (int l = In.jmin + 1; l <= (lc < In.jmax ? lc : In.jmax); ++l) {
     const int b = L[l], n = L[l + 1] - b;
-    for (int k = threadIdx.x; k < n * Q; k += CBLK) {
-      const int h = k / n, item = k - h * n;
-      const uint32_t c = lst[b + item] & CELL_MASK;
-      int x, y;
-      coords<DIM>(l, c, x, y);
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+    if constexpr (sizeof(T) == 4) {
+      for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
+        const uint32_t c = lst[b + item] & CELL_MASK;
+        int x, y;
+        coords<DIM>(l, c, x, y);
+        T v[Q];
+#pragma unroll
+        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+#pragma unroll
+        for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
+      }
+    } else {  // (double: the nine populations' stencils would not fit 128 VGPRs)
+      for (int k = threadIdx.x; k < n * Q; k += CBLK) {  // population-major: lanes on consecutive items
+        const int h = k / n, item = k - h * n;
+        const uint32_t c = lst[b + item] & CELL_MASK;
+        int x, y;
+        coords<DIM>(l, c, x, y);
+        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+      }
     }
     __syncthreads();
   }

@@ -77,7 +77,10 @@ def replay(mr, cfg, m0, nsteps, check_every=1, precision=8):
 
 @pytest.mark.parametrize("scheme,jmin,jmax,eps,seed", [
     ("D1Q2", 2, 10, 1e-4, 0), ("D1Q3", 2, 10, 1e-4, 1), ("D1Q3", 1, 9, 1e-3, 2),
-    ("D2Q9", 2, 6, 1e-3, 3), ("D2Q9", 3, 7, 1e-4, 4), ("D2Q9", 1, 5, 1e-2, 5)])
+    ("D2Q9", 2, 6, 1e-3, 3), ("D2Q9", 3, 7, 1e-4, 4), ("D2Q9", 1, 5, 1e-2, 5),
+    # coarsest level at and above the largest level the one-block-per-instance
+    # kernels walk (2D: 5, 1D: 10): those kernels then cover one level or none
+    ("D2Q9", 5, 8, 1e-3, 6), ("D2Q9", 6, 8, 1e-3, 7), ("D1Q3", 10, 13, 1e-3, 8), ("D1Q3", 11, 13, 1e-3, 9)])
 def test_step_replay_random_fields(mr, scheme, jmin, jmax, eps, seed):
     cfg = _cfg(scheme, jmin, jmax, eps)
     m0 = W.random_field(cfg, seed, "jump")
