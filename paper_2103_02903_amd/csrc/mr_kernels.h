@@ -478,13 +478,13 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
 }
 
 // ---------------------------------------------------------------- coarse levels
-// The levels of an instance with at most COARSE_CELLS cells are walked by one
-// block of CBLK threads per instance, level after level with block barriers,
-// in a single launch (a per-level launch costs a few microseconds whatever its
-// work). Each level runs the same per-cell operations as the per-level kernels;
-// the finer levels keep one launch per level.
+// The coarse levels of an instance (up to level lc, chosen by the host) are
+// walked by one block of CBLK threads per instance, level after level with
+// block barriers, in a single launch (a per-level launch costs a few
+// microseconds whatever its work). Each level runs the same per-cell
+// operations as the per-level kernels; the finer levels keep one launch per
+// level.
 constexpr int CBLK = 1024;
-constexpr long long COARSE_CELLS = 1024;
 
 // Ghost classification of levels min(lc, jmax) .. jmin+1, finest first; bit L
 // of v16 selects the 16-cell form for level L.

@@ -509,11 +509,14 @@ struct Engine {
     return list_grid(n, c->grid_level);
   }
   static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, c->grid_all); }
-  // Finest level that the one-block-per-instance kernels walk: at most
-  // COARSE_CELLS cells per instance.
-  static int coarse_cap() {
+  // Finest level that the one-block-per-instance kernels walk: levels of at
+  // most 4096 cells when the batch has 32 instances or more (one block each),
+  // else of at most 1024 (with few blocks a larger level is better spread over
+  // one launch of many blocks).
+  static int coarse_cap(const mrlbm_ctx *c) {
+    const long long cells = c->P.B >= 32 ? 4096 : 1024;
     int lc = 0;
-    while ((1ll << (DIM * (lc + 1))) <= COARSE_CELLS) ++lc;
+    while ((1ll << (DIM * (lc + 1))) <= cells) ++lc;
     return lc;
   }
   // One thread per item and all populations in it (large sets), or one
@@ -539,7 +542,7 @@ struct Engine {
     const Plan &P = c->P;
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
                                                               c->refg);
-    const int lc = coarse_cap();
+    const int lc = coarse_cap(c);
     for (int l = P.maxJ; l > std::max(P.jmin, lc); --l) {
       if (P.ghost16[l]) {
         const int nb = P.dtab_total(3, l);
@@ -565,7 +568,7 @@ struct Engine {
   // one launch each (fine to coarse), then the coarse levels in one launch.
   static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl) {
     const Plan &P = c->P;
-    const int lc = coarse_cap();
+    const int lc = coarse_cap(c);
     for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l)
       k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
     if (lc >= P.jmin) k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc);
@@ -576,7 +579,7 @@ struct Engine {
     const Plan &P = c->P;
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
-    const int lc = coarse_cap();
+    const int lc = coarse_cap(c);
     project_all(c, F, li, c->lvl[m]);
     if (lc > P.jmin) k_ghost_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, lg, c->lvl[m], lc);
     for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
@@ -600,7 +603,7 @@ struct Engine {
     else
       k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
-    const int lc = coarse_cap();
+    const int lc = coarse_cap(c);
     for (int l = P.maxJ; l >= std::max(P.jmin + 2, lc + 3); --l) {
       const int nb = P.dtab_total(2, l - 2);
       if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);

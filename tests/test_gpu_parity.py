@@ -281,6 +281,34 @@ def test_ghost_sets_match_definition(mr, scheme, precision):
     bat.close()
 
 
+@pytest.mark.parametrize("jmin", [3, 6, 7])
+def test_batch32_replay_coarse_levels(mr, jmin):
+    """Batches of 32 instances (the one-block-per-instance kernels then walk
+    the 2D levels up to 6) with coarsest level below, at and above that level
+    and uneven finest levels: every instance's step replayed on the oracle
+    (mesh bit-exact, fields within 1e-12)."""
+    items = []
+    for k in range(32):
+        jmax = max(jmin + 1, [7, 8][k % 2])
+        cfg = _cfg("D2Q9", jmin, jmax, [1e-3, 1e-2][(k // 2) % 2])
+        items.append((cfg, W.random_field(cfg, 100 + k, "jump" if k % 3 else "smooth")))
+    bat = mr.Batch([c for c, _ in items])
+    for i, (_, m0) in enumerate(items):
+        bat.init_equilibrium(i, m0)
+    bat.step(3)
+    oracles = [oracle.Oracle(c) for c, _ in items]
+    for k in range(2):
+        pre = [bat.get_state(i) for i in range(len(items))]
+        bat.step(1)
+        for i, o in enumerate(oracles):
+            t_o, v_o = pre[i][0].copy(), pre[i][1].copy()
+            o.step(t_o, v_o)
+            tg, vg = bat.get_state(i)
+            assert np.array_equal(tg, t_o), "instance %d mesh differs at replay %d" % (i, k)
+            assert leaf_err(o, t_o, vg, v_o) <= TOL64
+    bat.close()
+
+
 def test_batch_instance_equals_single_run(mr):
     """An instance advanced inside a batch is bit-identical to the same instance
     advanced alone."""
