@@ -994,36 +994,57 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     if (lane == 63) wsum[k][wave] = v;
   }
   __syncthreads();
-  if (!(r.w[0] | r.w[1] | r.w[2] | r.w[3])) return;
-  int pos[NCAT];
+  if (r.w[0] | r.w[1] | r.w[2] | r.w[3]) {
+    int pos[NCAT];
 #pragma unroll
-  for (int k = 0; k < NCAT; ++k) {
-    int before = 0;
-    for (int ww = 0; ww < wave; ++ww) before += wsum[k][ww];
-    pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - n[k];
+    for (int k = 0; k < NCAT; ++k) {
+      int before = 0;
+      for (int ww = 0; ww < wave; ++ww) before += wsum[k][ww];
+      pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - n[k];
+    }
+    const uint32_t tag = (uint32_t)l << LEVEL_SHIFT;
+    for (int t = 0; t < 16; ++t) {
+      const int k = cat_of((uint8_t)(r.w[t >> 2] >> (8 * (t & 3))));
+      if (k >= 0) lists[k * bt.ctotal + pos[k]++] = tag | (uint32_t)(c0 + t);
+    }
   }
-  const uint32_t tag = (uint32_t)l << LEVEL_SHIFT;
-  for (int t = 0; t < 16; ++t) {
-    const int k = cat_of((uint8_t)(r.w[t >> 2] >> (8 * (t & 3))));
-    if (k >= 0) lists[k * bt.ctotal + pos[k]++] = tag | (uint32_t)(c0 + t);
-  }
-  if (F && n[CAT_LEAF]) {
+  if (!F) return;  // uniform: the adaptation's transfer follows
+  // The cells of the block created by the adaptation (new leaves outside the
+  // old mesh) are gathered in LDS and predicted one per thread.
+  __shared__ uint16_t xq[CCHUNK];
+  __shared__ int xtot[BLK / 64 + 1];
+  uint32_t created[4] = {0, 0, 0, 0};
+  if (n[CAT_LEAF]) {
     const uint8_t *co = code_old + I[i].loff[l];
     const Run16 o = ld16(co, c0, nl, level_vec(co, nl));
-    uint32_t created[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) created[k] = leaf_flags(r.w[k]) & none_flags(o.w[k]);
-    if (created[0] | created[1] | created[2] | created[3]) {
-      const Inst<T> &In = I[i];
-      for (int t = 0; t < 16; ++t) {
-        if (!((created[t >> 2] >> (8 * (t & 3))) & 1u)) continue;
-        const long long c = c0 + t;
-        int x, y;
-        coords<DIM>(l, (uint32_t)c, x, y);
-        for (int h = 0; h < Q; ++h)
-          F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
-      }
-    }
+  }
+  const int nc = __popc(created[0]) + __popc(created[1]) + __popc(created[2]) + __popc(created[3]);
+  int inc = nc;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) xtot[wave] = inc;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int ww = 0; ww < BLK / 64; ++ww) {
+    if (ww < wave) before += xtot[ww];
+    total += xtot[ww];
+  }
+  if (total == 0) return;  // uniform
+  int at = before + inc - nc;
+  for (int t = 0; t < 16; ++t)
+    if ((created[t >> 2] >> (8 * (t & 3))) & 1u) xq[at++] = (uint16_t)(CPT * threadIdx.x + t);
+  __syncthreads();
+  const Inst<T> &In = I[i];
+  for (int k = threadIdx.x; k < total; k += BLK) {
+    const long long c = base + xq[k];
+    int x, y;
+    coords<DIM>(l, (uint32_t)c, x, y);
+    for (int h = 0; h < Q; ++h)
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
   }
 }
 
