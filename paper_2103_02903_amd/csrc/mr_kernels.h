@@ -542,18 +542,19 @@ __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restri
   }
 }
 
-// Ghost predictions of levels jmin+1 .. min(lc, jmax), coarsest first.
+// Ghost predictions of levels jmin+1 .. min(lc, jmax) of instance i, coarsest
+// first, by the whole block.
 template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                       const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                       int lc) {
-  const int i = blockIdx.x;
+__device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                  const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                  int lc, int i) {
+  const int nt = (int)blockDim.x;
   const Inst<T> &In = I[i];
   const int *L = lvl + (i * NCAT + CAT_GHOST) * LVL_STRIDE;
   for (int l = In.jmin + 1; l <= (lc < In.jmax ? lc : In.jmax); ++l) {
     const int b = L[l], n = L[l + 1] - b;
     if constexpr (sizeof(T) == 4) {
-      for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
+      for (int item = threadIdx.x; item < n; item += nt) {  // all populations per thread, loads before stores
         const uint32_t c = lst[b + item] & CELL_MASK;
         int x, y;
         coords<DIM>(l, c, x, y);
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict
         for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
       }
     } else {  // (double: the nine populations' stencils would not fit 128 VGPRs)
-      for (int k = threadIdx.x; k < n * Q; k += CBLK) {  // population-major: lanes on consecutive items
+      for (int k = threadIdx.x; k < n * Q; k += nt) {  // population-major: lanes on consecutive items
         const int h = k / n, item = k - h * n;
         const uint32_t c = lst[b + item] & CELL_MASK;
         int x, y;
@@ -575,6 +576,12 @@ __global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict
     __syncthreads();
   }
 }
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                       const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                       int lc) {
+  ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x);
+}
 
 // ---------------------------------------------------------------- fused launches
 // Two independent chains of a step share launches: each launch runs one link of
@@ -583,19 +590,35 @@ __global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict
 template <int Q>
 constexpr int fused_block() { return 64 * Q > BLK ? 64 * Q : BLK; }
 
-// Grading of level lg (blocks G.., one cell of level lg-1 per thread, block
-// table ginfo) beside the ghost predictions of level lh on the old mesh (the
-// first G blocks). The first writes the membership array, the second the values.
-template <int DIM, int Q, typename T>
+// Grading beside the ghost predictions of the old mesh. Grading (blocks G..):
+// of level lg, one cell of level lg-1 per thread (block table ginfo), or with
+// GC the coarse levels min(lc+1, jmax) .. jmin+1, one block per instance.
+// Ghosts (the first G blocks): of level lh, or with HC the coarse levels
+// jmin+1 .. min(lc, jmax), one block per instance. The first writes the
+// membership array, the second the values.
+template <int DIM, int Q, typename T, bool GC, bool HC>
 __global__ void __launch_bounds__(fused_block<Q>())
     k_grade_ghost(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
                   const uint32_t *__restrict__ ginfo, int lg, T *__restrict__ F, const uint32_t *__restrict__ lst,
-                  const int *__restrict__ lvl, int lh, int G) {
+                  const int *__restrict__ lvl, int lh, int G, int lc) {
   if ((int)blockIdx.x >= G) {
+    if (GC) {
+      const Inst<T> &In = I[blockIdx.x - G];
+      for (int l = lc + 1 < In.jmax ? lc + 1 : In.jmax; l > In.jmin; --l) {
+        const long long n = ncells_d(DIM, l - 1);
+        for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T>(In, tnew, l, cell);
+        __syncthreads();
+      }
+      return;
+    }
     const uint32_t w = ginfo[blockIdx.x - G];
     const int i = (int)(w & 0xffu);
     const long long cell = (long long)(w >> 8) * fused_block<Q>() + threadIdx.x;
     if (cell < ncells_d(DIM, lg - 1)) grade_cell<DIM, T>(I[i], tnew, lg, cell);
+    return;
+  }
+  if (HC) {
+    ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x);
     return;
   }
   __shared__ SegLDS s;

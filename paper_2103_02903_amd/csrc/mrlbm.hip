@@ -612,12 +612,35 @@ struct Engine {
 
     k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
     // Grading (levels maxJ .. jmin+1) beside the old mesh's ghost predictions
-    // (levels jmin+1 .. maxJ), which only the transfer reads.
-    for (int k = 0; k < P.maxJ - P.jmin; ++k) {
-      const int l = P.maxJ - k, lh = P.jmin + 1 + k;
-      const unsigned nb = (unsigned)P.dtab_total(1, l - 1), G = chunks_level(c, lh);
-      k_grade_ghost<DIM, Q, T><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, P.dinfo_row(c->dinfo, 1, l - 1), l,
-                                                             Fc, lg, c->lvl[mo], lh, (int)G);
+    // (levels jmin+1 .. maxJ), which only the transfer reads: one link of each
+    // chain per launch. The coarse levels of each chain are one link (one
+    // block per instance); 0 marks a launch without that chain.
+    {
+      const int lc = coarse_cap(c);
+      std::vector<int> gl, hl;  // levels, or -1 for the coarse link
+      for (int l = P.maxJ; l >= std::max(P.jmin + 1, lc + 2); --l) gl.push_back(l);
+      if (lc >= P.jmin) gl.push_back(-1);
+      if (lc > P.jmin) hl.push_back(-1);
+      for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l) hl.push_back(l);
+      for (size_t k = 0; k < std::max(gl.size(), hl.size()); ++k) {
+        const int g = k < gl.size() ? gl[k] : 0, h = k < hl.size() ? hl[k] : 0;
+        const unsigned nb = g == 0 ? 0u : g < 0 ? (unsigned)P.B : (unsigned)P.dtab_total(1, g - 1);
+        const unsigned G = h == 0 ? 0u : h < 0 ? (unsigned)P.B : chunks_level(c, h);
+        const uint32_t *gi = g > 0 ? P.dinfo_row(c->dinfo, 1, g - 1) : c->dinfo;
+        if (G + nb == 0) continue;
+        if (g < 0 && h < 0)
+          k_grade_ghost<DIM, Q, T, true, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
+                                                                            c->lvl[mo], h, (int)G, lc);
+        else if (g < 0)
+          k_grade_ghost<DIM, Q, T, true, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
+                                                                             c->lvl[mo], h, (int)G, lc);
+        else if (h < 0)
+          k_grade_ghost<DIM, Q, T, false, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
+                                                                             c->lvl[mo], h, (int)G, lc);
+        else
+          k_grade_ghost<DIM, Q, T, false, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
+                                                                              c->lvl[mo], h, (int)G, lc);
+      }
     }
 
     // new codes and lists, with the transfer in place: a new leaf's value is
