@@ -518,30 +518,6 @@ __global__ void __launch_bounds__(CBLK) k_ancestor_coarse(const Inst<T> *__restr
   }
 }
 
-// Projection of the internal cells of levels min(lc, jmax-1) .. jmin.
-template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                         const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                         int lc) {
-  const int i = blockIdx.x;
-  const Inst<T> &In = I[i];
-  const int *L = lvl + (i * NCAT + CAT_INTERNAL) * LVL_STRIDE;
-  for (int l = lc < In.jmax - 1 ? lc : In.jmax - 1; l >= In.jmin; --l) {
-    const int b = L[l], n = L[l + 1] - b;
-    for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
-      const uint32_t c = lst[b + item] & CELL_MASK;
-      int x, y;
-      coords<DIM>(l, c, x, y);
-      T v[Q];
-#pragma unroll
-      for (int h = 0; h < Q; ++h) v[h] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
-#pragma unroll
-      for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
-    }
-    __syncthreads();
-  }
-}
-
 // Ghost predictions of levels jmin+1 .. min(lc, jmax) of instance i, coarsest
 // first, by the whole block.
 template <int DIM, int Q, typename T>
@@ -576,11 +552,31 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
     __syncthreads();
   }
 }
+// Projection of the internal cells of levels min(lc, jmax-1) .. jmin; with
+// lg, then the ghost predictions of levels jmin+1 .. min(lc, jmax) (same block,
+// after the projections they read).
 template <int DIM, int Q, typename T>
-__global__ void __launch_bounds__(CBLK) k_ghost_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
-                                                       const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                       int lc) {
-  ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x);
+__global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                         const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                         int lc, const uint32_t *__restrict__ lg) {
+  const int i = blockIdx.x;
+  const Inst<T> &In = I[i];
+  const int *L = lvl + (i * NCAT + CAT_INTERNAL) * LVL_STRIDE;
+  for (int l = lc < In.jmax - 1 ? lc : In.jmax - 1; l >= In.jmin; --l) {
+    const int b = L[l], n = L[l + 1] - b;
+    for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
+      const uint32_t c = lst[b + item] & CELL_MASK;
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      T v[Q];
+#pragma unroll
+      for (int h = 0; h < Q; ++h) v[h] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
+#pragma unroll
+      for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
+    }
+    __syncthreads();
+  }
+  if (lg) ghost_coarse_walk<DIM, Q, T>(I, F, lg, lvl, lc, i);
 }
 
 // ---------------------------------------------------------------- fused launches

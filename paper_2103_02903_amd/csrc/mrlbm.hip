@@ -565,13 +565,15 @@ struct Engine {
   }
 
   // Projections of the internal cells of a mesh: levels above the coarse cap
-  // one launch each (fine to coarse), then the coarse levels in one launch.
-  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl) {
+  // one launch each (fine to coarse), then the coarse levels in one launch,
+  // followed there by the coarse ghost predictions when lg is given.
+  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl, const uint32_t *lg = nullptr) {
     const Plan &P = c->P;
     const int lc = coarse_cap(c);
     for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l)
       k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
-    if (lc >= P.jmin) k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc);
+    if (lc >= P.jmin)
+      k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc, lc > P.jmin ? lg : nullptr);
   }
 
   // Reconstruction on mesh m inside F: projections upward, ghost predictions downward.
@@ -580,8 +582,7 @@ struct Engine {
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
     const int lc = coarse_cap(c);
-    project_all(c, F, li, c->lvl[m]);
-    if (lc > P.jmin) k_ghost_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, lg, c->lvl[m], lc);
+    project_all(c, F, li, c->lvl[m], lg);
     for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
       k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
   }
