@@ -354,8 +354,8 @@ def main():
                     help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the design notes describe how "
-              "it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single GPU (instances of a batch are "
+              "independent; a multi-GPU run would give each GPU its own batch); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from paper_2103_02903_amd import mrlbm
