@@ -624,8 +624,11 @@ __global__ void __launch_bounds__(fused_block<Q>())
 // Codes of the tree cells of a 0/1 membership array: leaf, or internal when
 // its first child is in the tree. Sixteen consecutive cells per thread; their
 // first children are the even bytes of 32 cells of the finer row. The same
-// cells of the two flag arrays `clear0`, `clear1` (indexed like the codes) are
-// zeroed, ready for the next adaptation.
+// cells of the two flag arrays `clear0`, `clear1` (indexed like the codes:
+// the keep and refine flags) are zeroed, ready for the next adaptation, where
+// the run holds a tree cell: a kept cell belongs to the new tree, and so does
+// a cell flagged for refinement (its grandchildren join the tree, and with
+// them their ancestors), so flags outside the tree are already zero.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo,
@@ -667,10 +670,12 @@ __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *
 #pragma unroll
   for (int k = 0; k < 4; ++k) v.w[k] = (t.w[k] << 1) | (t.w[k] & ~ch[k]);
   st16(cl, c0, nl, vec, v);
-  const Run16 z = {{0, 0, 0, 0}};
-  uint8_t *k0 = clear0 + In.loff[l], *k1 = clear1 + In.loff[l];
-  st16(k0, c0, nl, level_vec(k0, nl) && l >= 4, z);
-  st16(k1, c0, nl, level_vec(k1, nl) && l >= 4, z);
+  if (t.w[0] | t.w[1] | t.w[2] | t.w[3]) {
+    const Run16 z = {{0, 0, 0, 0}};
+    uint8_t *k0 = clear0 + In.loff[l], *k1 = clear1 + In.loff[l];
+    st16(k0, c0, nl, level_vec(k0, nl) && l >= 4, z);
+    st16(k1, c0, nl, level_vec(k1, nl) && l >= 4, z);
+  }
 }
 
 // Four consecutive codes starting at p (byte loads if p is not 4-byte aligned).

@@ -235,3 +235,42 @@ def test_ghost_condition_check_catches_a_violation():
     g = np.zeros((8, 8), bool)
     g[3, 3] = True
     assert np.any(g & ~_children(_dilate(I[2], 1)))
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,eps,kind", [("D1Q3", 2, 10, 1e-4, "jump"), ("D2Q9", 3, 7, 1e-3, "smooth"),
+                                                       ("D2Q9", 2, 6, 1e-3, "jump")])
+def test_kept_and_refined_cells_belong_to_the_new_tree(scheme, jmin, jmax, eps, kind):
+    """Every cell kept by the thresholding (with the sibling groups of its
+    ancestors) and every parent flagged for refinement is a cell of the new
+    tree: the GPU zeroes these flags only where the new tree has cells."""
+    cfg = _cfg(scheme, jmin, jmax, eps)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 4, kind))
+    d, mu = o.dim, float(cfg.get("mu_bar", 0.0))
+    checked = 0
+    for _ in range(5):
+        D = o.details(tree, o.reconstruct(tree, v))
+        tnew = o.adapt_tree(tree, D)
+        for l in range(jmin + 1, jmax + 1):
+            eps_l = np.ldexp(eps, d * (l - jmax))
+            ref_l = np.ldexp(eps_l, d) * 2.0 ** mu
+            Dp = o.tree_level(D, l - 1) if d == 2 else D[o.level_offset(l - 1):o.level_offset(l - 1) + o.ncells(l - 1)]
+            told_l = o.tree_level(tree, l).astype(bool)
+            kept_groups = Dp >= eps_l  # parents whose children are kept
+            kept = told_l & (np.repeat(np.repeat(kept_groups, 2, 0), 2, 1) if d == 2 else np.repeat(kept_groups, 2))
+            tn_l = o.tree_level(tnew, l).astype(bool)
+            assert not np.any(kept & ~tn_l), "kept cell outside the new tree at level %d" % l
+            # the sibling group of a kept cell's parent (ancestor closure)
+            if l - 1 > jmin:
+                par = (kept.reshape(kept.shape[0] // 2, 2, kept.shape[1] // 2, 2).any(axis=(1, 3)) if d == 2
+                       else kept.reshape(-1, 2).any(axis=1))
+                grp = (par.reshape(par.shape[0] // 2, 2, par.shape[1] // 2, 2).any(axis=(1, 3)) if d == 2
+                       else par.reshape(-1, 2).any(axis=1))
+                sib = np.repeat(np.repeat(grp, 2, 0), 2, 1) if d == 2 else np.repeat(grp, 2)
+                assert not np.any(sib & ~o.tree_level(tnew, l - 1).astype(bool))
+            if jmin < l < jmax:
+                refined = (Dp >= ref_l) & (Dp >= 0)
+                assert not np.any(refined & ~o.tree_level(tnew, l - 1).astype(bool))
+            checked += int(kept.sum())
+        o.step(tree, v)
+    assert checked > 0
