@@ -103,7 +103,12 @@ int mrlbm_init_equilibrium(mrlbm_ctx *ctx, int instance, const void *moments);
 int mrlbm_adapt(mrlbm_ctx *ctx);
 
 /* Transport and collision on the current complete leaves, without adaptation
- * (the mesh is frozen for this call). Asynchronous. */
+ * (the mesh is frozen for this call), after the reconstruction of the current
+ * mesh. Right after mrlbm_adapt that reconstruction recomputes only the
+ * projections above cells the adaptation changed (the others are still exact
+ * in the context's buffers); otherwise, and after mrlbm_set_state or
+ * mrlbm_init_equilibrium, all of them. Same results either way.
+ * Asynchronous. */
 int mrlbm_transport_collide(mrlbm_ctx *ctx);
 
 /* `nsteps` full time steps of Algorithm 1 (adapt, transport, collide).

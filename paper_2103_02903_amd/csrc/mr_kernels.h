@@ -127,6 +127,56 @@ __global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__r
   project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x);
 }
 
+// Projection of internal cell c of level l in the reconstruction that follows
+// an adaptation. F then holds the old mesh's projections, computed at the start
+// of the adaptation; since then only cells outside the old tree were written
+// (old ghosts, and the transfer into cells the adaptation added). Each value
+// that changed carries a mark byte: the new leaves outside the old tree (set by
+// the compaction) and, level by level, the internal cells with a marked child.
+// An unmarked internal cell with unmarked children belonged to the old mesh
+// with the same children, so its old projection is the exact result and it is
+// skipped. A parent consumes (zeroes) its children's marks; a stray mark only
+// costs a recomputation.
+template <int DIM, int Q, typename T>
+__device__ __forceinline__ void project_marked(const Inst<T> &In, T *__restrict__ F, uint8_t *__restrict__ mark,
+                                               int l, uint32_t c) {
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  uint8_t *mc = mark + In.loff[l + 1];
+  const long long r0 = DIM == 1 ? 2ll * x : cidx<2>(l + 1, 2 * x, 2 * y);
+  const long long r1 = DIM == 1 ? r0 : cidx<2>(l + 1, 2 * x, 2 * y + 1);
+  if (!(mc[r0] | mc[r0 + 1] | mc[r1] | mc[r1 + 1])) return;
+  T v[Q];
+#pragma unroll
+  for (int h = 0; h < Q; ++h) v[h] = project<DIM, T>(F + foff(In, DIM, Q, l + 1, h), l + 1, x, y);
+#pragma unroll
+  for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
+  mc[r0] = 0;
+  mc[r0 + 1] = 0;
+  if (DIM == 2) {
+    mc[r1] = 0;
+    mc[r1 + 1] = 0;
+  }
+  if (l > In.jmin) mark[In.loff[l] + c] = 1;
+}
+// project_marked on the internal cells of level l, one cell (all populations)
+// per thread.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(BLK) k_project_marked(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                        const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                        int l, uint8_t *__restrict__ mark) {
+  constexpr int WPB = BLK / 64;
+  __shared__ SegLDS s;
+  load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  MRLBM_FOR_CHUNKS(ch, s.pre[bt.B], WPB, wave) {
+    const int i = upper_index(s.pre, bt.B, ch);
+    const int item = (ch - s.pre[i]) * CHUNK + lane;
+    if (item >= s.cnt[i]) continue;
+    project_marked<DIM, Q, T>(I[i], F, mark, l, lst[s.beg[i] + item] & CELL_MASK);
+  }
+}
+
 // Zero-detail prediction P_delta on the ghost cells of level l, from level l-1.
 // The first G blocks; wavefront h < Q takes population h.
 template <int DIM, int Q, typename T>
@@ -552,13 +602,15 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
     __syncthreads();
   }
 }
-// Projection of the internal cells of levels min(lc, jmax-1) .. jmin; with
-// lg, then the ghost predictions of levels jmin+1 .. min(lc, jmax) (same block,
-// after the projections they read).
+// Projection of the internal cells of levels min(lc, jmax-1) .. jmin (with
+// mark, only the marked ones: project_marked); with lg, then the ghost
+// predictions of levels jmin+1 .. min(lc, jmax) (same block, after the
+// projections they read).
 template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                          const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                         int lc, const uint32_t *__restrict__ lg) {
+                                                         int lc, const uint32_t *__restrict__ lg,
+                                                         uint8_t *__restrict__ mark) {
   const int i = blockIdx.x;
   const Inst<T> &In = I[i];
   const int *L = lvl + (i * NCAT + CAT_INTERNAL) * LVL_STRIDE;
@@ -566,6 +618,10 @@ __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restri
     const int b = L[l], n = L[l + 1] - b;
     for (int item = threadIdx.x; item < n; item += CBLK) {  // all populations per thread, loads before stores
       const uint32_t c = lst[b + item] & CELL_MASK;
+      if (mark) {
+        project_marked<DIM, Q, T>(In, F, mark, l, c);
+        continue;
+      }
       int x, y;
       coords<DIM>(l, c, x, y);
       T v[Q];
@@ -992,7 +1048,7 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
                                                          const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                          const int *__restrict__ boff, uint32_t *__restrict__ lists,
                                                          int nblocks, const uint8_t *__restrict__ code_old,
-                                                         T *__restrict__ F) {
+                                                         T *__restrict__ F, uint8_t *__restrict__ mark) {
   __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
@@ -1034,15 +1090,25 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
   }
   if (!F) return;  // uniform: the adaptation's transfer follows
   // The cells of the block created by the adaptation (new leaves outside the
-  // old mesh) are gathered in LDS and predicted one per thread.
+  // old mesh) are gathered in LDS and predicted one per thread. New leaves
+  // outside the old tree (these and former ghosts) get a mark for the
+  // reconstruction that follows (project_marked).
   __shared__ uint16_t xq[CCHUNK];
   __shared__ int xtot[BLK / 64 + 1];
   uint32_t created[4] = {0, 0, 0, 0};
   if (n[CAT_LEAF]) {
     const uint8_t *co = code_old + I[i].loff[l];
     const Run16 o = ld16(co, c0, nl, level_vec(co, nl));
+    Run16 fresh;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) created[k] = leaf_flags(r.w[k]) & none_flags(o.w[k]);
+    for (int k = 0; k < 4; ++k) {
+      created[k] = leaf_flags(r.w[k]) & none_flags(o.w[k]);
+      fresh.w[k] = leaf_flags(r.w[k]) & ~(o.w[k] >> 1) & 0x01010101u;
+    }
+    if (fresh.w[0] | fresh.w[1] | fresh.w[2] | fresh.w[3]) {
+      uint8_t *ml = mark + I[i].loff[l];
+      st16(ml, c0, nl, level_vec(ml, nl), fresh);
+    }
   }
   const int nc = __popc(created[0]) + __popc(created[1]) + __popc(created[2]) + __popc(created[3]);
   int inc = nc;

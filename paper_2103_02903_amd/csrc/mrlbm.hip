@@ -162,7 +162,7 @@ struct Plan {
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
-  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_bcnt, off_boff, off_W,
+  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_bcnt, off_boff, off_W,
       off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
@@ -263,6 +263,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_keep = take(P.ctotal);
   P.off_refg = take(P.ctotal);
   P.off_tnew = take(P.ctotal);
+  P.off_mark = take(P.ctotal);
   P.off_bcnt = take(sizeof(int) * NCAT * P.nblocks);
   P.off_boff = take(sizeof(int) * NCAT * P.nblocks);
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
@@ -381,6 +382,8 @@ struct mrlbm_ctx {
   uint32_t *lists[2];
   int *lvl[2];
   uint8_t *keep, *refg, *tnew;
+  uint8_t *mark;      // change marks of the reconstruction after an adaptation
+  bool recon_reuse;   // the next reconstruction follows an adaptation
   int *bcnt, *boff;
   void *W, *C;
   double *red;
@@ -502,12 +505,13 @@ struct Engine {
   static constexpr unsigned FB = fused_block<Q>();
 
   static const Inst<T> *I(mrlbm_ctx *c) { return (const Inst<T> *)c->inst; }
-  static unsigned chunks_level(mrlbm_ctx *c, int l) {  // capacity of the per-level lists in chunks
+  static long long level_chunks(mrlbm_ctx *c, int l) {  // capacity of the per-level lists in chunks
     long long n = 0;
     for (int i = 0; i < c->P.B; ++i)
       if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (DIM * l)) + CHUNK - 1) / CHUNK;
-    return list_grid(n, c->grid_level);
+    return n;
   }
+  static unsigned chunks_level(mrlbm_ctx *c, int l) { return list_grid(level_chunks(c, l), c->grid_level); }
   static unsigned chunks_all(mrlbm_ctx *c) { return list_grid((c->P.ctotal + CHUNK - 1) / CHUNK, c->grid_all); }
   // Finest level that the one-block-per-instance kernels walk: levels of at
   // most 4096 cells when the batch has 32 instances or more (one block each),
@@ -533,7 +537,7 @@ struct Engine {
     k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks);
     k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks);
     k_compact_scatter<DIM, Q, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
-                                                                   c->lists[m], P.nblocks, code_old, F);
+                                                                   c->lists[m], P.nblocks, code_old, F, c->mark);
   }
 
   // Codes (leaf / internal / ghost) of the membership array tnew into code[m],
@@ -566,23 +570,33 @@ struct Engine {
 
   // Projections of the internal cells of a mesh: levels above the coarse cap
   // one launch each (fine to coarse), then the coarse levels in one launch,
-  // followed there by the coarse ghost predictions when lg is given.
-  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl, const uint32_t *lg = nullptr) {
+  // followed there by the coarse ghost predictions when lg is given. With
+  // mark, only the cells whose subtree changed (k_project_marked).
+  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl, const uint32_t *lg = nullptr,
+                          uint8_t *mark = nullptr) {
     const Plan &P = c->P;
     const int lc = coarse_cap(c);
-    for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l)
-      k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
+    for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l) {
+      if (mark)
+        k_project_marked<DIM, Q, T><<<list_grid((level_chunks(c, l) + BLK / 64 - 1) / (BLK / 64), c->grid_level), BLK,
+                                      0, c->stream>>>(c->bt, I(c), F, li, lvl, l, mark);
+      else
+        k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
+    }
     if (lc >= P.jmin)
-      k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc, lc > P.jmin ? lg : nullptr);
+      k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc, lc > P.jmin ? lg : nullptr,
+                                                               mark);
   }
 
-  // Reconstruction on mesh m inside F: projections upward, ghost predictions downward.
+  // Reconstruction on mesh m inside F: projections upward, ghost predictions
+  // downward. Right after an adaptation, only the projections that changed.
   static void reconstruct(mrlbm_ctx *c, T *F, int m) {
     const Plan &P = c->P;
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
     const int lc = coarse_cap(c);
-    project_all(c, F, li, c->lvl[m], lg);
+    project_all(c, F, li, c->lvl[m], lg, c->recon_reuse ? c->mark : nullptr);
+    c->recon_reuse = false;
     for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
       k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
   }
@@ -653,7 +667,11 @@ struct Engine {
     classify(c, mn, c->code[mo], Fc);
     phase_mark(c, PH_ADAPT, false);
     c->mcur = mn;
-    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+    if (hipPeekAtLastError() != hipSuccess) return MRLBM_ERR_HIP;
+    // F holds the old mesh's projections and the transfer: the next
+    // reconstruction recomputes only what the marks name.
+    c->recon_reuse = true;
+    return MRLBM_OK;
   }
 
   static int transport(mrlbm_ctx *c, T *tape = nullptr) {
@@ -750,6 +768,7 @@ struct Engine {
                                                                                                   c->code[c->mcur]);
     compact(c, c->mcur);
     c->has_state[i] = 1;
+    c->recon_reuse = false;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
@@ -1082,6 +1101,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->keep = (uint8_t *)(b + P.off_keep);
   c->refg = (uint8_t *)(b + P.off_refg);
   c->tnew = (uint8_t *)(b + P.off_tnew);
+  c->mark = (uint8_t *)(b + P.off_mark);
   c->bcnt = (int *)(b + P.off_bcnt);
   c->boff = (int *)(b + P.off_boff);
   c->W = b + P.off_W;
@@ -1157,6 +1177,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->refg, 0, P.ctotal);
+  if (e == hipSuccess) e = hipMemset(c->mark, 0, P.ctotal);
   // Value buffers start at zero: cells outside the mesh hold scratch that then
   // depends only on the sequence of calls.
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
@@ -1224,6 +1245,7 @@ int mrlbm_set_state(mrlbm_ctx *c, int instance, const uint8_t *tree, const void 
   HIPCHK(hipMemcpy(c->tnew + I.cbase, tree, I.total, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((char *)c->F[c->cur] + c->P.rs * c->P.q * I.cbase, values, c->P.rs * c->P.q * I.total,
                    hipMemcpyHostToDevice));
+  c->recon_reuse = false;  // the new values need a full reconstruction
   int rc = dispatch<ClassifyOp>(c, c->mcur);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));

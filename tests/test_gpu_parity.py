@@ -375,6 +375,34 @@ def test_graph_steps_match_eager_launches(mr, monkeypatch):
             assert np.array_equal(sa[1][leaves], sb[1][leaves])
 
 
+def test_reconstruction_after_adaptation_equals_full_one(mr):
+    """Right after an adaptation the reconstruction recomputes only the
+    projections above cells the adaptation changed. Handing the adapted state
+    back through set_state, which forces the full reconstruction, must give the
+    same bits in every cell, step after step."""
+    items = W.shear_layer_batch(3, jmax_choices=(6, 7))
+    cfgs = [c for c, _ in items]
+    for prec in (8, 4):
+        runs = []
+        for full in (False, True):
+            b = mr.Batch(cfgs, precision=prec)
+            for i, (_, m) in enumerate(items):
+                b.init_equilibrium(i, m)
+            b.step(5)
+            for _ in range(4):
+                b.adapt()
+                if full:
+                    for i in range(b.B):
+                        b.set_state(i, *b.get_state(i))
+                b.transport_collide()
+            runs.append([b.get_state(i) for i in range(b.B)])
+            b.close()
+        for i, ((ta, va), (tb, vb)) in enumerate(zip(*runs)):
+            print("precision", prec, "instance", i, flush=True)
+            assert np.array_equal(ta, tb)
+            assert np.array_equal(va, vb)
+
+
 def test_profiled_graph_steps_time_every_eighth_transport(mr):
     """With profiling on, graph-replayed steps count every transport launch and
     bracket the kernel of steps 0, 8, 16, ... with HIP events; the timed steps

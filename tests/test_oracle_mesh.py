@@ -274,3 +274,72 @@ def test_kept_and_refined_cells_belong_to_the_new_tree(scheme, jmin, jmax, eps, 
             checked += int(kept.sum())
         o.step(tree, v)
     assert checked > 0
+
+
+def _change_marks(o, told, tnew, propagate=True):
+    """Marks of the reconstruction that follows an adaptation: the new leaves
+    outside the old tree and (with propagate) every internal cell of the new
+    tree with a marked child, finest level first."""
+    from ghost_sets import _parents, tree_sets
+
+    To, _, Io = tree_sets(o, told)
+    _, Sn, In = tree_sets(o, tnew)
+    M = {l: Sn[l] & ~To[l] for l in Sn}
+    if propagate:
+        for l in range(o.jmax - 1, o.jmin - 1, -1):
+            M[l] = M[l] | (In[l] & _parents(M[l + 1]))
+    return M, Io, In
+
+
+def _unmarked_violations(o, told, dense_old, tnew, dense_new, M, Io, In):
+    """Unmarked internal cells of the new tree that were not internal before
+    or whose projection changed (bitwise), and the number of unmarked ones."""
+    bad, n = 0, 0
+    for l in range(o.jmin, o.jmax):
+        keep = In[l] & ~M[l]
+        n += int(keep.sum())
+        bad += int(np.sum(keep & ~Io[l]))
+        a, b = o.values_level(dense_old, l)[:, keep], o.values_level(dense_new, l)[:, keep]
+        bad += int(np.sum(np.any(a != b, axis=0)))
+    return bad, n
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,eps,kind", [("D1Q3", 2, 10, 1e-4, "jump"), ("D2Q9", 3, 7, 1e-3, "jump"),
+                                                       ("D2Q9", 2, 6, 1e-3, "jump")])
+def test_unmarked_projections_survive_the_adaptation(scheme, jmin, jmax, eps, kind):
+    """The reconstruction after an adaptation recomputes only the projections
+    of marked cells (new leaves outside the old tree, then internal cells with
+    a marked child): every unmarked internal cell of the new tree was internal
+    in the old one and its reconstructed value is bit for bit the old one."""
+    cfg = _cfg(scheme, jmin, jmax, eps)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 6, kind))
+    skipped = marked = 0
+    for _ in range(5):
+        o.step(tree, v)
+        dense_old = o.reconstruct(tree, v)
+        tnew = o.adapt_tree(tree, o.details(tree, dense_old))
+        dense_new = o.reconstruct(tnew, o.transfer(tree, dense_old, tnew))
+        M, Io, In = _change_marks(o, tree, tnew)
+        bad, n = _unmarked_violations(o, tree, dense_old, tnew, dense_new, M, Io, In)
+        assert bad == 0
+        skipped += n
+        marked += sum(int(m.sum()) for m in M.values())
+    assert skipped > 0 and marked > 0
+
+
+def test_change_marks_need_the_upward_pass():
+    """The check has teeth: marking only the new leaves, without the upward
+    pass, leaves changed projections unmarked."""
+    cfg = _cfg("D2Q9", 2, 6, 1e-3)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(W.random_field(cfg, 6, "jump"))
+    found = 0
+    for _ in range(5):
+        o.step(tree, v)
+        dense_old = o.reconstruct(tree, v)
+        tnew = o.adapt_tree(tree, o.details(tree, dense_old))
+        dense_new = o.reconstruct(tnew, o.transfer(tree, dense_old, tnew))
+        M, Io, In = _change_marks(o, tree, tnew, propagate=False)
+        found += _unmarked_violations(o, tree, dense_old, tnew, dense_new, M, Io, In)[0]
+    assert found > 0
