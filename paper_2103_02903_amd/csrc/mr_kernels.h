@@ -22,6 +22,24 @@ constexpr int CPT = 16;    // consecutive cells per thread of an all-level dense
 constexpr int CCHUNK = BLK * CPT;
 constexpr int GCHUNK = BLK * 4;  // cells per block of the ghost classification
 
+// Mesh activity of instance i: act[ACT*i] and act[ACT*i+1] hold the finest
+// tree level of the last two meshes the compaction built (the current mesh's
+// first), act[ACT*i+2] the finest level the current adaptation's refinement
+// reaches (0 if none). A new tree is at most as fine as the old one or its
+// refinement, and the code buffer the adaptation rewrites holds the mesh before
+// the current one, so above active_top every code, membership and flag byte
+// the dense passes of an adaptation read or write is zero, and stays zero:
+// those passes skip such levels (by induction over the steps, from a state
+// where every level is active, as after set_state).
+constexpr int ACT = 4;
+constexpr int ACT_ALL = 64;  // an entry above every level: all levels active
+template <typename T>
+__device__ __forceinline__ int active_top(const int *__restrict__ act, const Inst<T> &In, int i) {
+  const int a0 = act[ACT * i], a1 = act[ACT * i + 1], r = act[ACT * i + 2];
+  const int a = a0 > a1 ? (a0 > r ? a0 : r) : (a1 > r ? a1 : r);
+  return a < In.jmax ? a : In.jmax;
+}
+
 // ---------------------------------------------------------------- list segments
 // Per-instance list segments of one category: of one level (l >= 0) or of all
 // levels (l < 0), with the exclusive prefix of their chunk counts.
@@ -211,7 +229,8 @@ __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__res
 template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ F,
                                                     const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
-                                                    uint8_t *__restrict__ keep, uint8_t *__restrict__ refg) {
+                                                    uint8_t *__restrict__ keep, uint8_t *__restrict__ refg,
+                                                    int *__restrict__ act) {
   __shared__ SegLDS s;
   __shared__ T dm[Q][64];
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, -1);
@@ -252,7 +271,11 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
         for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
           for (int dx = 0; dx < 2; ++dx) k[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] = 1;
       }
-      if (l > I[i].jmin && l < I[i].jmax && D >= I[i].ref_l[l]) refg[I[i].loff[lp] + p] = 1;
+      if (l > I[i].jmin && l < I[i].jmax && D >= I[i].ref_l[l]) {
+        refg[I[i].loff[lp] + p] = 1;
+        // its grandchildren join the tree: recorded when finer than the mesh
+        if (l + 1 > act[ACT * i]) atomicMax(act + ACT * i + 2, l + 1);
+      }
     }
     __syncthreads();
   }
@@ -265,7 +288,7 @@ template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *__restrict__ I,
                                                       const T *__restrict__ F, const uint32_t *__restrict__ lst,
                                                       const int *__restrict__ lvl, uint8_t *__restrict__ keep,
-                                                      uint8_t *__restrict__ refg) {
+                                                      uint8_t *__restrict__ refg, int *__restrict__ act) {
   constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, -1);
@@ -300,7 +323,11 @@ __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *_
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
         for (int dx = 0; dx < 2; ++dx) k[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] = 1;
     }
-    if (l > In.jmin && l < In.jmax && D >= In.ref_l[l]) refg[In.loff[lp] + p] = 1;
+    if (l > In.jmin && l < In.jmax && D >= In.ref_l[l]) {
+      refg[In.loff[lp] + p] = 1;
+      // its grandchildren join the tree: recorded when finer than the mesh
+      if (l + 1 > act[ACT * i]) atomicMax(act + ACT * i + 2, l + 1);
+    }
   }
 }
 
@@ -320,6 +347,7 @@ __device__ __forceinline__ void chunk_block(const uint32_t *__restrict__ binfo, 
   l = (int)((w >> 8) & 0x1fu);
   base = (long long)(w >> 13) * CCHUNK;
 }
+
 
 // ---------------------------------------------------------------- 16-cell runs
 // Sixteen consecutive byte flags or codes of one level as four little-endian
@@ -412,10 +440,11 @@ __device__ __forceinline__ void ancestor_cell(const Inst<T> &In, uint8_t *__rest
 }
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ keep,
-                                                  const uint32_t *__restrict__ info, int l) {
+                                                  const uint32_t *__restrict__ info, int l,
+                                                  const int *__restrict__ act) {
   int i;
   const long long cell = dense_block(info, i);
-  if (cell >= ncells_d(DIM, l - 2)) return;
+  if (cell >= ncells_d(DIM, l - 2) || l > active_top(act, I[i], i)) return;
   ancestor_cell<DIM, T>(I[i], keep, l, cell);
 }
 
@@ -428,11 +457,13 @@ __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__res
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__restrict__ I,
                                                  const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ keep,
-                                                 const uint8_t *__restrict__ refg, uint8_t *__restrict__ tnew) {
+                                                 const uint8_t *__restrict__ refg, uint8_t *__restrict__ tnew,
+                                                 const int *__restrict__ act) {
   using V = Vel<SCHEME>;
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
+  if (l > active_top(act, I[i], i)) return;
   const Inst<T> &In = I[i];
   const long long nl = ncells_d(DIM, l);
   const long long c0 = base + CPT * threadIdx.x;
@@ -652,7 +683,7 @@ template <int DIM, int Q, typename T, bool GC, bool HC>
 __global__ void __launch_bounds__(fused_block<Q>())
     k_grade_ghost(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
                   const uint32_t *__restrict__ ginfo, int lg, T *__restrict__ F, const uint32_t *__restrict__ lst,
-                  const int *__restrict__ lvl, int lh, int G, int lc) {
+                  const int *__restrict__ lvl, int lh, int G, int lc, const int *__restrict__ act) {
   if ((int)blockIdx.x >= G) {
     if (GC) {
       const Inst<T> &In = I[blockIdx.x - G];
@@ -666,7 +697,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
     const uint32_t w = ginfo[blockIdx.x - G];
     const int i = (int)(w & 0xffu);
     const long long cell = (long long)(w >> 8) * fused_block<Q>() + threadIdx.x;
-    if (cell < ncells_d(DIM, lg - 1)) grade_cell<DIM, T>(I[i], tnew, lg, cell);
+    if (cell < ncells_d(DIM, lg - 1) && lg <= active_top(act, I[i], i)) grade_cell<DIM, T>(I[i], tnew, lg, cell);
     return;
   }
   if (HC) {
@@ -689,10 +720,12 @@ template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_tree(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo,
                                                        const uint8_t *__restrict__ tnew, uint8_t *__restrict__ code,
-                                                       uint8_t *__restrict__ clear0, uint8_t *__restrict__ clear1) {
+                                                       uint8_t *__restrict__ clear0, uint8_t *__restrict__ clear1,
+                                                       const int *__restrict__ act) {
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
+  if (l > active_top(act, I[i], i)) return;
   const Inst<T> &In = I[i];
   const long long nl = ncells_d(DIM, l);
   const long long c0 = base + CPT * threadIdx.x;
@@ -792,11 +825,11 @@ __device__ __forceinline__ void ghost_run4(const Inst<T> &In, uint8_t *__restric
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> *__restrict__ I,
                                                         uint8_t *__restrict__ code, const uint32_t *__restrict__ info,
-                                                        int l) {
+                                                        int l, const int *__restrict__ act) {
   const uint32_t w = info[blockIdx.x];
   const int i = (int)(w & 0xffu);
   const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
-  if (c0 >= ncells_d(DIM, l)) return;
+  if (c0 >= ncells_d(DIM, l) || l > active_top(act, I[i], i)) return;
   ghost_run4<DIM, T>(I[i], code, l, c0);
 }
 
@@ -908,11 +941,12 @@ __device__ __forceinline__ void ghost_run16(const Inst<T> &In, uint8_t *__restri
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_classify_ghost16(Batch bt, const Inst<T> *__restrict__ I,
                                                           uint8_t *__restrict__ code,
-                                                          const uint32_t *__restrict__ info, int l) {
+                                                          const uint32_t *__restrict__ info, int l,
+                                                          const int *__restrict__ act) {
   const uint32_t wi = info[blockIdx.x];
   const int i = (int)(wi & 0xffu);
   const long long c0 = ((long long)(wi >> 8) * BLK + threadIdx.x) * CPT;
-  if (c0 >= ncells_d(DIM, l)) return;
+  if (c0 >= ncells_d(DIM, l) || l > active_top(act, I[i], i)) return;
   ghost_run16<DIM, T>(I[i], code, l, c0);
 }
 
@@ -958,11 +992,15 @@ __device__ __forceinline__ void count_codes(uint32_t w, int *n) {
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_count(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
-                                                       int *__restrict__ bcnt, int nblocks) {
+                                                       int *__restrict__ bcnt, int nblocks, const int *__restrict__ act) {
   __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
+  if (l > active_top(act, I[i], i)) {  // uniform: an inactive level holds no codes
+    if (threadIdx.x < NCAT) bcnt[threadIdx.x * nblocks + blockIdx.x] = 0;
+    return;
+  }
   const long long nl = ncells_d(DIM, l);
   const uint8_t *cl = code + I[i].loff[l];
   const long long c0 = base + CPT * threadIdx.x;
@@ -993,7 +1031,8 @@ __global__ void __launch_bounds__(BLK) k_compact_count(Batch bt, const Inst<T> *
 template <typename T>
 __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *__restrict__ I,
                                                        const int *__restrict__ cbp, const int *__restrict__ bcnt,
-                                                       int *__restrict__ boff, int *__restrict__ lvl, int nblocks) {
+                                                       int *__restrict__ boff, int *__restrict__ lvl, int nblocks,
+                                                       int *__restrict__ act) {
   __shared__ int wtot[16];
   __shared__ int carry_s;
   const int i = blockIdx.x;
@@ -1036,6 +1075,15 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0) {  // activity: this mesh's finest tree level becomes the newest entry
+    const int *L = lvl + (i * NCAT + CAT_LEAF) * LVL_STRIDE;
+    int fin = In.jmin;
+    for (int l = In.jmin; l <= In.jmax; ++l)
+      if (L[l + 1] > L[l]) fin = l;
+    act[ACT * i + 1] = act[ACT * i];
+    act[ACT * i] = fin;
+    act[ACT * i + 2] = 0;
+  }
 }
 
 // With F (the adaptation: code holds the new mesh, code_old the old one), the
@@ -1048,11 +1096,13 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
                                                          const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                          const int *__restrict__ boff, uint32_t *__restrict__ lists,
                                                          int nblocks, const uint8_t *__restrict__ code_old,
-                                                         T *__restrict__ F, uint8_t *__restrict__ mark) {
+                                                         T *__restrict__ F, uint8_t *__restrict__ mark,
+                                                         const int *__restrict__ act) {
   __shared__ int wsum[NCAT][BLK / 64];
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
+  if (l > active_top(act, I[i], i)) return;  // uniform: no codes, no counts
   const long long nl = ncells_d(DIM, l);
   const uint8_t *cl = code + I[i].loff[l];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -162,7 +162,7 @@ struct Plan {
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
-  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_bcnt, off_boff, off_W,
+  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_bcnt, off_boff, off_W,
       off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
@@ -264,6 +264,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_refg = take(P.ctotal);
   P.off_tnew = take(P.ctotal);
   P.off_mark = take(P.ctotal);
+  P.off_act = take(sizeof(int) * ACT * B);
   P.off_bcnt = take(sizeof(int) * NCAT * P.nblocks);
   P.off_boff = take(sizeof(int) * NCAT * P.nblocks);
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
@@ -383,6 +384,7 @@ struct mrlbm_ctx {
   int *lvl[2];
   uint8_t *keep, *refg, *tnew;
   uint8_t *mark;      // change marks of the reconstruction after an adaptation
+  int *act;           // mesh activity per instance (see active_top)
   bool recon_reuse;   // the next reconstruction follows an adaptation
   int *bcnt, *boff;
   void *W, *C;
@@ -424,6 +426,12 @@ struct mrlbm_ctx {
 };
 
 namespace {
+
+// Every level active until the compaction has built two meshes (after the
+// mesh or the buffers were set from outside the step sequence).
+void activity_reset(mrlbm_ctx *c) {
+  k_fill_u32<<<1, BLK, 0, c->stream>>>((uint32_t *)c->act, (long long)ACT * c->P.B, (uint32_t)ACT_ALL);
+}
 
 #define HIPCHK(x)                                \
   do {                                           \
@@ -534,10 +542,13 @@ struct Engine {
   // the new leaves of mesh m, in place in F (the adaptation).
   static void compact(mrlbm_ctx *c, int m, const uint8_t *code_old = nullptr, T *F = nullptr) {
     const Plan &P = c->P;
-    k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks);
-    k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks);
+    k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks,
+                                                               c->act);
+    k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks,
+                                                   c->act);
     k_compact_scatter<DIM, Q, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
-                                                                   c->lists[m], P.nblocks, code_old, F, c->mark);
+                                                                   c->lists[m], P.nblocks, code_old, F, c->mark,
+                                                                   c->act);
   }
 
   // Codes (leaf / internal / ghost) of the membership array tnew into code[m],
@@ -545,17 +556,19 @@ struct Engine {
   static void classify(mrlbm_ctx *c, int m, const uint8_t *code_old = nullptr, T *F = nullptr) {
     const Plan &P = c->P;
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
-                                                              c->refg);
+                                                              c->refg, c->act);
     const int lc = coarse_cap(c);
     for (int l = P.maxJ; l > std::max(P.jmin, lc); --l) {
       if (P.ghost16[l]) {
         const int nb = P.dtab_total(3, l);
         if (nb)
-          k_classify_ghost16<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 3, l), l);
+          k_classify_ghost16<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 3, l), l,
+                                                                c->act);
       } else {
         const int nb = P.dtab_total(0, l);
         if (nb)
-          k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l);
+          k_classify_ghost<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l), l,
+                                                              c->act);
       }
     }
     if (lc > P.jmin) {
@@ -614,18 +627,20 @@ struct Engine {
     project_all(c, Fc, li, c->lvl[mo]);
     if (per_leaf(c))
       k_details_leaf<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
-          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
+          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
     else
       k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
-          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg);
+          c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
     const int lc = coarse_cap(c);
     for (int l = P.maxJ; l >= std::max(P.jmin + 2, lc + 3); --l) {
       const int nb = P.dtab_total(2, l - 2);
-      if (nb) k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l);
+      if (nb)
+        k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l, c->act);
     }
     if (lc + 2 >= P.jmin + 2) k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
 
-    k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew);
+    k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew,
+                                                                c->act);
     // Grading (levels maxJ .. jmin+1) beside the old mesh's ghost predictions
     // (levels jmin+1 .. maxJ), which only the transfer reads: one link of each
     // chain per launch. The coarse levels of each chain are one link (one
@@ -645,16 +660,16 @@ struct Engine {
         if (G + nb == 0) continue;
         if (g < 0 && h < 0)
           k_grade_ghost<DIM, Q, T, true, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                            c->lvl[mo], h, (int)G, lc);
+                                                                            c->lvl[mo], h, (int)G, lc, c->act);
         else if (g < 0)
           k_grade_ghost<DIM, Q, T, true, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                             c->lvl[mo], h, (int)G, lc);
+                                                                             c->lvl[mo], h, (int)G, lc, c->act);
         else if (h < 0)
           k_grade_ghost<DIM, Q, T, false, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                             c->lvl[mo], h, (int)G, lc);
+                                                                             c->lvl[mo], h, (int)G, lc, c->act);
         else
           k_grade_ghost<DIM, Q, T, false, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                              c->lvl[mo], h, (int)G, lc);
+                                                                              c->lvl[mo], h, (int)G, lc, c->act);
       }
     }
 
@@ -766,6 +781,7 @@ struct Engine {
         I(c), i, F, (const T *)mom);
     k_full_tree<T><<<grid_cap((P.inst[i].total + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(I(c), i,
                                                                                                   c->code[c->mcur]);
+    activity_reset(c);
     compact(c, c->mcur);
     c->has_state[i] = 1;
     c->recon_reuse = false;
@@ -866,6 +882,7 @@ struct Engine {
       (void)hipMemcpyAsync(c->code[c->mcur], w + L.ck_code + seg * L.code_b, P.ctotal, hipMemcpyDeviceToDevice,
                            c->stream);
       (void)hipMemcpyAsync(c->F[c->cur], w + L.ck_F + seg * L.F_b, fbytes, hipMemcpyDeviceToDevice, c->stream);
+      activity_reset(c);  // the other code buffer and tnew hold later meshes
       compact(c, c->mcur);
       copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code), (uint32_t *)(w + L.st_lists), (int *)(w + L.st_lvl));
       // recompute the segment, taping each step's new mesh and pre-collision values
@@ -929,6 +946,9 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    // each replay repeats the same adaptation: every level active, as the
+    // activity history would not match the replayed meshes
+    if (e == hipSuccess) activity_reset(c);
     int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
     c->mcur = m0;
     if (rc == MRLBM_OK) rc = transport(c);
@@ -952,6 +972,7 @@ struct Engine {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     (void)hipGraphExecDestroy(exec);
+    activity_reset(c);  // the replays left the history of their own meshes
     if (e != hipSuccess) return MRLBM_ERR_HIP;
     *ms /= (float)reps;
     return MRLBM_OK;
@@ -1102,6 +1123,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->refg = (uint8_t *)(b + P.off_refg);
   c->tnew = (uint8_t *)(b + P.off_tnew);
   c->mark = (uint8_t *)(b + P.off_mark);
+  c->act = (int *)(b + P.off_act);
   c->bcnt = (int *)(b + P.off_bcnt);
   c->boff = (int *)(b + P.off_boff);
   c->W = b + P.off_W;
@@ -1178,6 +1200,10 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->refg, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->mark, 0, P.ctotal);
+  if (e == hipSuccess) {  // every level active until two meshes were built
+    const std::vector<int> all(ACT * P.B, ACT_ALL);
+    e = hipMemcpy(c->act, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice);
+  }
   // Value buffers start at zero: cells outside the mesh hold scratch that then
   // depends only on the sequence of calls.
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
@@ -1246,6 +1272,7 @@ int mrlbm_set_state(mrlbm_ctx *c, int instance, const uint8_t *tree, const void 
   HIPCHK(hipMemcpy((char *)c->F[c->cur] + c->P.rs * c->P.q * I.cbase, values, c->P.rs * c->P.q * I.total,
                    hipMemcpyHostToDevice));
   c->recon_reuse = false;  // the new values need a full reconstruction
+  activity_reset(c);
   int rc = dispatch<ClassifyOp>(c, c->mcur);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));

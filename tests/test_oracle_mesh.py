@@ -343,3 +343,92 @@ def test_change_marks_need_the_upward_pass():
         M, Io, In = _change_marks(o, tree, tnew, propagate=False)
         found += _unmarked_violations(o, tree, dense_old, tnew, dense_new, M, Io, In)[0]
     assert found > 0
+
+
+def _codes(o, tree):
+    """Dense codes of a mesh per level: 3 leaf, 2 internal, 1 ghost, 0 none."""
+    from ghost_sets import ghost_sets, tree_sets
+
+    _, S, I = tree_sets(o, tree)
+    G = ghost_sets(o, tree)
+    return {l: (3 * S[l] + 2 * I[l] + (G[l] if l in G else 0)).astype(np.uint8) for l in S}
+
+
+def _finest(o, tree):
+    return max(l for l in range(o.jmin, o.jmax + 1) if o.tree_level(tree, l).any())
+
+
+def _refine_reach(o, cfg, tree, values):
+    """Finest level the refinement flags of the next adaptation reach (the
+    grandchildren of flagged parents), 0 if there are none."""
+    D = o.details(tree, o.reconstruct(tree, values))
+    d, mu, eps = o.dim, float(cfg.get("mu_bar", 0.0)), float(cfg["eps"])
+    reach = 0
+    for l in range(o.jmin + 1, o.jmax):
+        ref_l = np.ldexp(np.ldexp(eps, d * (l - o.jmax)), d) * 2.0 ** mu
+        Dp = o.tree_level(D, l - 1) if d == 2 else D[o.level_offset(l - 1):o.level_offset(l - 1) + o.ncells(l - 1)]
+        inner = o.tree_level(tree, l - 1).astype(bool) & ~o.leaf_mask(tree, l - 1)
+        if np.any(inner & (Dp >= ref_l)):
+            reach = max(reach, l + 1)
+    return reach
+
+
+def _activity_run(o, cfg, tree, v, steps, keep_history=True, use_reach=True):
+    """Replays the GPU's level skipping on the two code buffers and the
+    membership array: each adaptation writes only levels up to
+    max(finest of the old mesh, refinement reach, finest of the mesh before),
+    starting from all levels active. Returns the number of (step, level)
+    pairs where a buffer then differs from the true mesh, and of skipped ones."""
+    code = [_codes(o, tree), {l: np.zeros_like(c) for l, c in _codes(o, tree).items()}]
+    tnew = {l: np.zeros_like(c) for l, c in code[0].items()}
+    hist = [o.jmax, 64]  # the compaction of the initial mesh, after a reset
+    cur, bad, skipped = 0, 0, 0
+    for _ in range(steps):
+        reach = _refine_reach(o, cfg, tree, v) if use_reach else 0
+        top = min(o.jmax, max(hist[0], reach, hist[1] if keep_history else 0))
+        o.step(tree, v)
+        want, memb = _codes(o, tree), {l: o.tree_level(tree, l).astype(np.uint8) for l in code[0]}
+        for l in want:
+            if l <= top:
+                code[1 - cur][l] = want[l].copy()
+                tnew[l] = memb[l].copy()
+            else:
+                skipped += 1
+            bad += int(not np.array_equal(code[1 - cur][l], want[l])) + int(not np.array_equal(tnew[l], memb[l]))
+        cur = 1 - cur
+        hist = [_finest(o, tree), hist[0]]
+    return bad, skipped
+
+
+def _activity_case(name):
+    if name == "burgers":  # a shock forms: the mesh refines into new levels
+        cfg, m0 = W.burgers_d1q3(jmin=2, jmax=9, eps=3e-3, mu_bar=1.0, nmodes=3)
+        return cfg, m0, 150
+    scheme, jmin, jmax, eps, seed = {"d1q2": ("D1Q2", 2, 10, 1e-3, 3), "d2q9": ("D2Q9", 2, 7, 1e-2, 1)}[name]
+    cfg = _cfg(scheme, jmin, jmax, eps)
+    return cfg, W.random_field(cfg, seed, "smooth"), 12
+
+
+@pytest.mark.parametrize("name", ["burgers", "d1q2", "d2q9"])
+def test_dense_passes_may_skip_inactive_levels(name):
+    """Levels above max(finest level of the old mesh, reach of its refinement
+    flags, finest level of the mesh before) hold only zeros in the code buffer
+    an adaptation rewrites and in the membership array: writing only the levels
+    below keeps both equal to the true meshes, step after step."""
+    cfg, m0, steps = _activity_case(name)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(m0)
+    bad, skipped = _activity_run(o, cfg, tree, v, steps)
+    assert bad == 0 and skipped > 0
+
+
+@pytest.mark.parametrize("name,keep_history,use_reach", [("d2q9", False, True), ("burgers", True, False)])
+def test_level_skipping_needs_both_terms(name, keep_history, use_reach):
+    """The check has teeth: without the mesh before the old one (coarsening
+    leaves its codes in the buffer being rewritten), or without the reach of
+    the refinement (new levels), some buffer goes stale."""
+    cfg, m0, steps = _activity_case(name)
+    o = oracle.Oracle(cfg)
+    tree, v = o.init(m0)
+    bad, _ = _activity_run(o, cfg, tree, v, steps, keep_history, use_reach)
+    assert bad > 0
