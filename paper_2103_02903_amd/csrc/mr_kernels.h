@@ -1033,48 +1033,59 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
                                                        const int *__restrict__ cbp, const int *__restrict__ bcnt,
                                                        int *__restrict__ boff, int *__restrict__ lvl, int nblocks,
                                                        int *__restrict__ act) {
-  __shared__ int wtot[16];
-  __shared__ int carry_s;
+  __shared__ int wtot[NCAT][16];
+  __shared__ int carry_s[NCAT];
   const int i = blockIdx.x;
   const Inst<T> &In = I[i];
   const int b0 = cbp[i], b1 = cbp[i + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < NCAT; ++k) {
-    int carry = (int)In.cbase;
-    for (int base = b0; base < b1; base += 1024) {
-      const int b = base + threadIdx.x;
-      const int v = b < b1 ? bcnt[k * nblocks + b] : 0;
-      int incl = v;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
-      }
-      if (lane == 63) wtot[wave] = incl;
-      __syncthreads();
-      if (wave == 0) {
-        int wv = lane < 16 ? wtot[lane] : 0, wi = wv;
-        for (int off = 1; off < 16; off <<= 1) {
-          const int t = __shfl_up(wi, off, 64);
-          if (lane >= off) wi += t;
-        }
-        if (lane < 16) wtot[lane] = wi - wv;  // exclusive prefix of the wavefront totals
-        if (lane == 15) carry_s = wi;
-      }
-      __syncthreads();
-      if (b < b1) boff[k * nblocks + b] = carry + wtot[wave] + incl - v;
-      carry += carry_s;
-      __syncthreads();
+  int carry = (int)In.cbase;  // the same start for the three categories
+  int car[NCAT] = {carry, carry, carry};
+  for (int base = b0; base < b1; base += 1024) {  // the three categories side by side
+    const int b = base + threadIdx.x;
+    int v[NCAT], incl[NCAT];
+#pragma unroll
+    for (int k = 0; k < NCAT; ++k) {
+      v[k] = b < b1 ? bcnt[k * nblocks + b] : 0;
+      incl[k] = v[k];
     }
-    int *L = lvl + (i * NCAT + k) * LVL_STRIDE;
-    for (int l = threadIdx.x; l < LVL_STRIDE; l += blockDim.x) {
-      int v;
-      if (l < In.jmin) v = (int)In.cbase;
-      else if (l > In.jmax) v = carry;
-      else v = boff[k * nblocks + In.bstart[l]];
-      L[l] = v;
+#pragma unroll
+    for (int k = 0; k < NCAT; ++k)
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl[k], off, 64);
+        if (lane >= off) incl[k] += t;
+      }
+    if (lane == 63)
+#pragma unroll
+      for (int k = 0; k < NCAT; ++k) wtot[k][wave] = incl[k];
+    __syncthreads();
+    if (wave < NCAT) {  // wavefront k scans the wavefront totals of category k
+      const int k = wave;
+      int wv = lane < 16 ? wtot[k][lane] : 0, wi = wv;
+      for (int off = 1; off < 16; off <<= 1) {
+        const int t = __shfl_up(wi, off, 64);
+        if (lane >= off) wi += t;
+      }
+      if (lane < 16) wtot[k][lane] = wi - wv;  // exclusive prefix of the wavefront totals
+      if (lane == 15) carry_s[k] = wi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NCAT; ++k) {
+      if (b < b1) boff[k * nblocks + b] = car[k] + wtot[k][wave] + incl[k] - v[k];
+      car[k] += carry_s[k];
     }
     __syncthreads();
   }
+  for (int t = threadIdx.x; t < NCAT * LVL_STRIDE; t += blockDim.x) {
+    const int k = t / LVL_STRIDE, l = t - k * LVL_STRIDE;
+    int v;
+    if (l < In.jmin) v = (int)In.cbase;
+    else if (l > In.jmax) v = car[k];
+    else v = boff[k * nblocks + In.bstart[l]];
+    lvl[(i * NCAT + k) * LVL_STRIDE + l] = v;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {  // activity: this mesh's finest tree level becomes the newest entry
     const int *L = lvl + (i * NCAT + CAT_LEAF) * LVL_STRIDE;
     int fin = In.jmin;
@@ -1124,26 +1135,41 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     if (lane == 63) wsum[k][wave] = v;
   }
   __syncthreads();
-  if (r.w[0] | r.w[1] | r.w[2] | r.w[3]) {
-    int pos[NCAT];
+  // The block's cells of each category, in cell order, gathered in LDS (as
+  // offsets in the block), then written out as one contiguous, coalesced range
+  // per category.
+  __shared__ uint16_t ent[NCAT][CCHUNK];
+  int tot[NCAT];
 #pragma unroll
-    for (int k = 0; k < NCAT; ++k) {
-      int before = 0;
-      for (int ww = 0; ww < wave; ++ww) before += wsum[k][ww];
-      pos[k] = boff[k * nblocks + blockIdx.x] + before + incl[k] - n[k];
+  for (int k = 0; k < NCAT; ++k) {
+    int before = 0, all = 0;
+    for (int ww = 0; ww < BLK / 64; ++ww) {
+      if (ww < wave) before += wsum[k][ww];
+      all += wsum[k][ww];
     }
-    const uint32_t tag = (uint32_t)l << LEVEL_SHIFT;
+    tot[k] = all;
+    incl[k] = before + incl[k] - n[k];  // first slot of this thread
+  }
+  if (r.w[0] | r.w[1] | r.w[2] | r.w[3]) {
     for (int t = 0; t < 16; ++t) {
       const int k = cat_of((uint8_t)(r.w[t >> 2] >> (8 * (t & 3))));
-      if (k >= 0) lists[k * bt.ctotal + pos[k]++] = tag | (uint32_t)(c0 + t);
+      if (k >= 0) ent[k][incl[k]++] = (uint16_t)(CPT * threadIdx.x + t);
     }
+  }
+  __syncthreads();
+  const uint32_t tag = (uint32_t)l << LEVEL_SHIFT;
+#pragma unroll
+  for (int k = 0; k < NCAT; ++k) {
+    if (!tot[k]) continue;
+    uint32_t *out = lists + (size_t)k * bt.ctotal + boff[k * nblocks + blockIdx.x];
+    for (int j = threadIdx.x; j < tot[k]; j += BLK) out[j] = tag | (uint32_t)(base + ent[k][j]);
   }
   if (!F) return;  // uniform: the adaptation's transfer follows
   // The cells of the block created by the adaptation (new leaves outside the
   // old mesh) are gathered in LDS and predicted one per thread. New leaves
   // outside the old tree (these and former ghosts) get a mark for the
   // reconstruction that follows (project_marked).
-  __shared__ uint16_t xq[CCHUNK];
+  uint16_t *xq = ent[0];  // free again after the barrier below
   __shared__ int xtot[BLK / 64 + 1];
   uint32_t created[4] = {0, 0, 0, 0};
   if (n[CAT_LEAF]) {
