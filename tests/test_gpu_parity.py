@@ -326,6 +326,44 @@ def test_batch_instance_equals_single_run(mr):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][leaves], b[1][leaves])
 
 
+def test_set_state_to_a_finer_mesh_midrun(mr):
+    """After some steps (the dense passes then skip the levels no mesh
+    reaches), one instance of a batch is set to its full finest mesh. Every
+    level must be processed again: the batch instance stays bit-identical to
+    the same state advanced in a fresh context, and the others to a batch run
+    without the change."""
+    items = _batch_cfgs("D2Q9")
+    cfgs = [c for c, _ in items]
+    runs = []
+    for change in (True, False):
+        bat = mr.Batch(cfgs)
+        for i, (_, m0) in enumerate(items):
+            bat.init_equilibrium(i, m0)
+        bat.step(20)
+        if change:
+            o = oracle.Oracle(cfgs[0])
+            t0, v0 = o.init(items[0][1])
+            bat.set_state(0, t0, v0)
+        bat.step(12)
+        runs.append([bat.get_state(i) for i in range(bat.B)])
+        bat.close()
+    sim = mr.Sim(cfgs[0])
+    o = oracle.Oracle(cfgs[0])
+    sim.init_equilibrium(items[0][1])  # any state, then replaced
+    sim.set_state(*o.init(items[0][1]))
+    sim.step(12)
+    a, b = runs[0][0], sim.get_state()
+    print("instance 0 leaves", int(o.leaf_counts(a[0]).sum()), flush=True)
+    leaves = _leaf_entries(o, a[0])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][leaves], b[1][leaves])
+    for i in range(1, len(cfgs)):
+        (ta, va), (tb, vb) = runs[0][i], runs[1][i]
+        assert np.array_equal(ta, tb)
+        assert np.array_equal(va[_leaf_entries(oracle.Oracle(cfgs[i]), ta)],
+                              vb[_leaf_entries(oracle.Oracle(cfgs[i]), tb)])
+    sim.close()
+
+
 def test_transport_variants_bit_identical(mr, monkeypatch):
     """The per-item and per-population variants of the transport and details
     kernels compute the same meshes and the same bits."""
