@@ -675,7 +675,7 @@ constexpr int fused_block() { return 64 * Q > BLK ? 64 * Q : BLK; }
 
 // Grading beside the ghost predictions of the old mesh. Grading (blocks G..):
 // of level lg, one cell of level lg-1 per thread (block table ginfo), or with
-// GC the coarse levels min(lc+1, jmax) .. jmin+1, one block per instance.
+// GC the coarse levels min(lc, jmax) .. jmin+1, one block per instance.
 // Ghosts (the first G blocks): of level lh, or with HC the coarse levels
 // jmin+1 .. min(lc, jmax), one block per instance. The first writes the
 // membership array, the second the values.
@@ -687,7 +687,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
   if ((int)blockIdx.x >= G) {
     if (GC) {
       const Inst<T> &In = I[blockIdx.x - G];
-      for (int l = lc + 1 < In.jmax ? lc + 1 : In.jmax; l > In.jmin; --l) {
+      for (int l = lc < In.jmax ? lc : In.jmax; l > In.jmin; --l) {
         const long long n = ncells_d(DIM, l - 1);
         for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T>(In, tnew, l, cell);
         __syncthreads();

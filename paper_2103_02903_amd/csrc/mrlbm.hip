@@ -648,8 +648,8 @@ struct Engine {
     {
       const int lc = coarse_cap(c);
       std::vector<int> gl, hl;  // levels, or -1 for the coarse link
-      for (int l = P.maxJ; l >= std::max(P.jmin + 1, lc + 2); --l) gl.push_back(l);
-      if (lc >= P.jmin) gl.push_back(-1);
+      for (int l = P.maxJ; l >= std::max(P.jmin + 1, lc + 1); --l) gl.push_back(l);
+      if (lc > P.jmin) gl.push_back(-1);
       if (lc > P.jmin) hl.push_back(-1);
       for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l) hl.push_back(l);
       for (size_t k = 0; k < std::max(gl.size(), hl.size()); ++k) {
