@@ -103,17 +103,22 @@ struct ChunkSched {
 };
 // The list work may occupy the first G blocks of a launch that also carries
 // other work (G a multiple of 8 keeps the XCD mapping).
-__device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int sub, int G) {
+// b is the block's index among the G (blockIdx.x unless the launch carries
+// two parts; the second starts at a multiple of 8 blocks, so b and blockIdx.x
+// agree modulo 8).
+__device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int sub, int G, int b) {
   if (MRLBM_XCD && G % NXCD == 0) {
-    const int x = (int)blockIdx.x % NXCD, slot = (int)blockIdx.x / NXCD;
+    const int x = b % NXCD, slot = b / NXCD;
     const int lo = (int)((long long)total * x / NXCD), hi = (int)((long long)total * (x + 1) / NXCD);
     return {lo + slot * per_block + sub, hi, (G / NXCD) * per_block};
   }
-  return {(int)blockIdx.x * per_block + sub, total, G * per_block};
+  return {b * per_block + sub, total, G * per_block};
 }
-#define MRLBM_FOR_CHUNKS_G(var_, total, per_block, sub, G) \
-  for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub), (G)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
+#define MRLBM_FOR_CHUNKS_GB(var_, total, per_block, sub, G, b) \
+  for (ChunkSched cs_ = chunk_sched((total), (per_block), (sub), (G), (b)); cs_.ch < cs_.end; cs_.ch += cs_.stride) \
     if (const int var_ = cs_.ch; true)
+#define MRLBM_FOR_CHUNKS_G(var_, total, per_block, sub, G) \
+  MRLBM_FOR_CHUNKS_GB(var_, total, per_block, sub, G, (int)blockIdx.x)
 #define MRLBM_FOR_CHUNKS(var_, total, per_block, sub) MRLBM_FOR_CHUNKS_G(var_, total, per_block, sub, (int)gridDim.x)
 
 // ---------------------------------------------------------------- reconstruction
@@ -123,11 +128,11 @@ __device__ __forceinline__ ChunkSched chunk_sched(int total, int per_block, int 
 template <int DIM, int Q, typename T>
 __device__ __forceinline__ void project_level(SegLDS &s, const Batch &bt, const Inst<T> *__restrict__ I,
                                               T *__restrict__ F, const uint32_t *__restrict__ lst,
-                                              const int *__restrict__ lvl, int l, int G) {
+                                              const int *__restrict__ lvl, int l, int G, int b) {
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (h >= Q) return;
-  MRLBM_FOR_CHUNKS_G(ch, s.pre[bt.B], 1, 0, G) {
+  MRLBM_FOR_CHUNKS_GB(ch, s.pre[bt.B], 1, 0, G, b) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -142,7 +147,7 @@ __global__ void __launch_bounds__(64 * Q) k_project(Batch bt, const Inst<T> *__r
                                                     const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
                                                     int l) {
   __shared__ SegLDS s;
-  project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x);
+  project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x, (int)blockIdx.x);
 }
 
 // Projection of internal cell c of level l in the reconstruction that follows
@@ -200,11 +205,11 @@ __global__ void __launch_bounds__(BLK) k_project_marked(Batch bt, const Inst<T> 
 template <int DIM, int Q, typename T>
 __device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const Inst<T> *__restrict__ I,
                                             T *__restrict__ F, const uint32_t *__restrict__ lst,
-                                            const int *__restrict__ lvl, int l, int G) {
+                                            const int *__restrict__ lvl, int l, int G, int b) {
   load_segments(s, I, lvl, bt.B, CAT_GHOST, l);
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (h >= Q) return;
-  MRLBM_FOR_CHUNKS_G(ch, s.pre[bt.B], 1, 0, G) {
+  MRLBM_FOR_CHUNKS_GB(ch, s.pre[bt.B], 1, 0, G, b) {
     const int i = upper_index(s.pre, bt.B, ch);
     const int item = (ch - s.pre[i]) * CHUNK + lane;
     if (item >= s.cnt[i]) continue;
@@ -218,7 +223,76 @@ template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                   const uint32_t *__restrict__ lst, const int *__restrict__ lvl, int l) {
   __shared__ SegLDS s;
-  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x);
+  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- paired links
+// Two consecutive links of a per-level chain (the second reads what the first
+// writes) in one launch: the first takes blocks 0..G0-1, the second the next
+// G1. The finest links of the chains are often empty, and a launch costs about
+// as much as a nearly empty level; sharing one saves it. The order between the
+// links is needed only when both have work (both sides tell from the list
+// lengths, which the compaction summarises per mesh in ne[cat][level]): then
+// every block of the first publishes its writes (device-scope
+// release) and counts itself in sync[0], and every block of the second waits
+// for the count (bounded) and acquires. Blocks are dispatched in increasing
+// order on each XCD, so a waiting block never holds back one it waits for.
+// The last block of the second link clears the counters (sync[1] counts them).
+__device__ __forceinline__ void pair_wait(unsigned *__restrict__ sync, unsigned G0) {
+  if (threadIdx.x == 0) {
+    for (unsigned spin = 0; spin < (1u << 20); ++spin) {  // about 50 ms
+      if (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G0) break;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+__device__ __forceinline__ void pair_signal(unsigned *__restrict__ sync) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(sync, 1u);
+  }
+}
+__device__ __forceinline__ void pair_leave(unsigned *__restrict__ sync, unsigned G1) {
+  __syncthreads();
+  if (threadIdx.x == 0 && atomicAdd(sync + 1, 1u) == G1 - 1u) {  // every block has passed its wait
+    sync[0] = 0u;
+    sync[1] = 0u;
+  }
+}
+// KIND 0: projections (levels l0 then l0-1 = l1), 2: marked projections, 1:
+// ghost predictions (levels l0 then l0+1 = l1).
+template <int DIM, int Q, typename T, int KIND>
+__global__ void __launch_bounds__(64 * Q) k_pair(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
+                                                 const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
+                                                 int l0, int l1, int G0, int G1, unsigned *__restrict__ sync,
+                                                 uint8_t *__restrict__ mark, const int *__restrict__ ne) {
+  __shared__ SegLDS s;
+  const int cat = KIND == 1 ? CAT_GHOST : CAT_INTERNAL;
+  const bool second = (int)blockIdx.x >= G0;
+  const bool ordered = ne[cat * LVL_STRIDE + l0] && ne[cat * LVL_STRIDE + l1];
+  if (second && ordered) pair_wait(sync, (unsigned)G0);
+  const int l = second ? l1 : l0, G = second ? G1 : G0, b = second ? (int)blockIdx.x - G0 : (int)blockIdx.x;
+  if constexpr (KIND == 0) {
+    project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, G, b);
+  } else if constexpr (KIND == 1) {
+    ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, G, b);
+  } else {  // one internal cell (all populations) per thread, Q chunks per block
+    load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    MRLBM_FOR_CHUNKS_GB(ch, s.pre[bt.B], Q, wave, G, b) {
+      const int i = upper_index(s.pre, bt.B, ch);
+      const int item = (ch - s.pre[i]) * CHUNK + lane;
+      if (item >= s.cnt[i]) continue;
+      project_marked<DIM, Q, T>(I[i], F, mark, l, lst[s.beg[i] + item] & CELL_MASK);
+    }
+  }
+  if (ordered) {
+    if (second) pair_leave(sync, (unsigned)G1);
+    else pair_signal(sync);
+  }
 }
 
 // ---------------------------------------------------------------- mesh adaptation
@@ -705,7 +779,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
     return;
   }
   __shared__ SegLDS s;
-  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, lh, G);
+  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, lh, G, (int)blockIdx.x);
 }
 
 // Codes of the tree cells of a 0/1 membership array: leaf, or internal when
@@ -992,8 +1066,11 @@ __device__ __forceinline__ void count_codes(uint32_t w, int *n) {
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BLK) k_compact_count(Batch bt, const Inst<T> *__restrict__ I,
                                                        const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
-                                                       int *__restrict__ bcnt, int nblocks, const int *__restrict__ act) {
+                                                       int *__restrict__ bcnt, int nblocks, const int *__restrict__ act,
+                                                       int *__restrict__ ne) {
   __shared__ int wsum[NCAT][BLK / 64];
+  if (blockIdx.x == 0)  // the nonempty flags of this mesh's lists, set by the scan that follows
+    for (int t = threadIdx.x; t < NCAT * LVL_STRIDE; t += blockDim.x) ne[t] = 0;
   int i, l;
   long long base;
   chunk_block(binfo, i, l, base);
@@ -1032,7 +1109,7 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *__restrict__ I,
                                                        const int *__restrict__ cbp, const int *__restrict__ bcnt,
                                                        int *__restrict__ boff, int *__restrict__ lvl, int nblocks,
-                                                       int *__restrict__ act) {
+                                                       int *__restrict__ act, int *__restrict__ ne) {
   __shared__ int wtot[NCAT][16];
   __shared__ int carry_s[NCAT];
   const int i = blockIdx.x;
@@ -1086,6 +1163,10 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
     lvl[(i * NCAT + k) * LVL_STRIDE + l] = v;
   }
   __syncthreads();
+  for (int t = threadIdx.x; t < NCAT * LVL_STRIDE - 1; t += blockDim.x) {  // lists with items at (category, level)
+    const int *L = lvl + (i * NCAT + t / LVL_STRIDE) * LVL_STRIDE + t % LVL_STRIDE;
+    if (t % LVL_STRIDE < LVL_STRIDE - 1 && L[1] > L[0]) ne[t] = 1;
+  }
   if (threadIdx.x == 0) {  // activity: this mesh's finest tree level becomes the newest entry
     const int *L = lvl + (i * NCAT + CAT_LEAF) * LVL_STRIDE;
     int fin = In.jmin;

@@ -162,7 +162,7 @@ struct Plan {
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
-  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_bcnt, off_boff, off_W,
+  size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_sync, off_ne[2], off_bcnt, off_boff, off_W,
       off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
@@ -265,6 +265,8 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_tnew = take(P.ctotal);
   P.off_mark = take(P.ctotal);
   P.off_act = take(sizeof(int) * ACT * B);
+  P.off_sync = take(sizeof(unsigned) * 2);
+  for (int k = 0; k < 2; ++k) P.off_ne[k] = take(sizeof(int) * NCAT * LVL_STRIDE);
   P.off_bcnt = take(sizeof(int) * NCAT * P.nblocks);
   P.off_boff = take(sizeof(int) * NCAT * P.nblocks);
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
@@ -385,6 +387,8 @@ struct mrlbm_ctx {
   uint8_t *keep, *refg, *tnew;
   uint8_t *mark;      // change marks of the reconstruction after an adaptation
   int *act;           // mesh activity per instance (see active_top)
+  unsigned *sync;     // counters of the paired links (zero between launches)
+  int *ne[2];         // per mesh: lists with items at [category][level] (0/1)
   bool recon_reuse;   // the next reconstruction follows an adaptation
   int *bcnt, *boff;
   void *W, *C;
@@ -543,9 +547,9 @@ struct Engine {
   static void compact(mrlbm_ctx *c, int m, const uint8_t *code_old = nullptr, T *F = nullptr) {
     const Plan &P = c->P;
     k_compact_count<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks,
-                                                               c->act);
+                                                               c->act, c->ne[m]);
     k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks,
-                                                   c->act);
+                                                   c->act, c->ne[m]);
     k_compact_scatter<DIM, Q, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
                                                                    c->lists[m], P.nblocks, code_old, F, c->mark,
                                                                    c->act);
@@ -585,11 +589,25 @@ struct Engine {
   // one launch each (fine to coarse), then the coarse levels in one launch,
   // followed there by the coarse ghost predictions when lg is given. With
   // mark, only the cells whose subtree changed (k_project_marked).
-  static void project_all(mrlbm_ctx *c, T *F, const uint32_t *li, const int *lvl, const uint32_t *lg = nullptr,
-                          uint8_t *mark = nullptr) {
+  static void project_all(mrlbm_ctx *c, int m, T *F, const uint32_t *li, const int *lvl,
+                          const uint32_t *lg = nullptr, uint8_t *mark = nullptr) {
     const Plan &P = c->P;
     const int lc = coarse_cap(c);
-    for (int l = P.maxJ - 1; l > std::max(P.jmin - 1, lc); --l) {
+    int l = P.maxJ - 1;
+    if (l - 1 > std::max(P.jmin - 1, lc)) {  // the two finest levels share a launch
+      if (mark) {
+        const unsigned g0 = list_grid((level_chunks(c, l) + Q - 1) / Q, c->grid_level);
+        const unsigned g1 = list_grid((level_chunks(c, l - 1) + Q - 1) / Q, c->grid_level);
+        k_pair<DIM, Q, T, 2><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
+                                                           c->sync, mark, c->ne[m]);
+      } else {
+        const unsigned g0 = chunks_level(c, l), g1 = chunks_level(c, l - 1);
+        k_pair<DIM, Q, T, 0><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
+                                                           c->sync, nullptr, c->ne[m]);
+      }
+      l -= 2;
+    }
+    for (; l > std::max(P.jmin - 1, lc); --l) {
       if (mark)
         k_project_marked<DIM, Q, T><<<list_grid((level_chunks(c, l) + BLK / 64 - 1) / (BLK / 64), c->grid_level), BLK,
                                       0, c->stream>>>(c->bt, I(c), F, li, lvl, l, mark);
@@ -608,10 +626,17 @@ struct Engine {
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
     const int lc = coarse_cap(c);
-    project_all(c, F, li, c->lvl[m], lg, c->recon_reuse ? c->mark : nullptr);
+    project_all(c, m, F, li, c->lvl[m], lg, c->recon_reuse ? c->mark : nullptr);
     c->recon_reuse = false;
-    for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
+    const int l0 = std::max(P.jmin, lc) + 1;
+    const int last = P.maxJ - 1 >= l0 ? P.maxJ - 1 : P.maxJ + 1;  // first of the shared pair
+    for (int l = l0; l <= P.maxJ && l < last; ++l)
       k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
+    if (last <= P.maxJ) {  // the two finest levels share a launch
+      const unsigned g0 = chunks_level(c, last), g1 = chunks_level(c, last + 1);
+      k_pair<DIM, Q, T, 1><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], last, last + 1, (int)g0,
+                                                         (int)g1, c->sync, nullptr, c->ne[m]);
+    }
   }
 
   static int adapt(mrlbm_ctx *c) {
@@ -624,7 +649,7 @@ struct Engine {
     // Projections of the old mesh (the details read tree cells only). The keep
     // and refine flags are zero here: the tree classification of the previous
     // adaptation, or the creation, cleared them.
-    project_all(c, Fc, li, c->lvl[mo]);
+    project_all(c, mo, Fc, li, c->lvl[mo]);
     if (per_leaf(c))
       k_details_leaf<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
@@ -1124,6 +1149,8 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->tnew = (uint8_t *)(b + P.off_tnew);
   c->mark = (uint8_t *)(b + P.off_mark);
   c->act = (int *)(b + P.off_act);
+  c->sync = (unsigned *)(b + P.off_sync);
+  for (int k = 0; k < 2; ++k) c->ne[k] = (int *)(b + P.off_ne[k]);
   c->bcnt = (int *)(b + P.off_bcnt);
   c->boff = (int *)(b + P.off_boff);
   c->W = b + P.off_W;
@@ -1200,6 +1227,8 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->refg, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->mark, 0, P.ctotal);
+  if (e == hipSuccess) e = hipMemset(c->sync, 0, sizeof(unsigned) * 2);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->ne[k], 0, sizeof(int) * NCAT * LVL_STRIDE);
   if (e == hipSuccess) {  // every level active until two meshes were built
     const std::vector<int> all(ACT * P.B, ACT_ALL);
     e = hipMemcpy(c->act, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice);
