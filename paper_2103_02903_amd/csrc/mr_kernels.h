@@ -1024,6 +1024,28 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost16(Batch bt, const Inst<T
   ghost_run16<DIM, T>(I[i], code, l, c0);
 }
 
+// The same pairing for the ancestor closure: levels l0 then l0-1 (blocks
+// from the dense tables info0, info1), ordered when flag is nonzero (the
+// finest link has kept cells).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_ancestor_pair(Batch bt, const Inst<T> *__restrict__ I,
+                                                       uint8_t *__restrict__ keep, const uint32_t *__restrict__ info0,
+                                                       const uint32_t *__restrict__ info1, int l0, int l1, int G0,
+                                                       int G1, const int *__restrict__ act,
+                                                       const int *__restrict__ flag, unsigned *__restrict__ sync) {
+  const bool second = (int)blockIdx.x >= G0;
+  const bool ordered = *flag != 0;
+  if (second && ordered) pair_wait(sync, (unsigned)G0);
+  const uint32_t w = second ? info1[blockIdx.x - G0] : info0[blockIdx.x];
+  const int i = (int)(w & 0xffu), l = second ? l1 : l0;
+  const long long cell = (long long)(w >> 8) * BLK + threadIdx.x;
+  if (l <= active_top(act, I[i], i) && cell < ncells_d(DIM, l - 2)) ancestor_cell<DIM, T>(I[i], keep, l, cell);
+  if (ordered) {
+    if (second) pair_leave(sync, (unsigned)G1);
+    else pair_signal(sync);
+  }
+}
+
 // Codes of the initial full finest mesh of instance i: internal below jmax,
 // leaf on jmax.
 template <typename T>

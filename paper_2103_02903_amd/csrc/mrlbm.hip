@@ -657,7 +657,18 @@ struct Engine {
       k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
     const int lc = coarse_cap(c);
-    for (int l = P.maxJ; l >= std::max(P.jmin + 2, lc + 3); --l) {
+    int la = P.maxJ;
+    const int la_end = std::max(P.jmin + 2, lc + 3);
+    if (la - 1 >= la_end && P.dtab_total(2, la - 2) && P.dtab_total(2, la - 3)) {
+      // the two finest links in one launch, ordered when the finest has kept
+      // cells (children of internal cells one level up in the old mesh)
+      const int nb0 = P.dtab_total(2, la - 2), nb1 = P.dtab_total(2, la - 3);
+      k_ancestor_pair<DIM, T><<<nb0 + nb1, BLK, 0, c->stream>>>(
+          c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, la - 2), P.dinfo_row(c->dinfo, 2, la - 3), la, la - 1, nb0,
+          nb1, c->act, c->ne[mo] + CAT_INTERNAL * LVL_STRIDE + (la - 1), c->sync);
+      la -= 2;
+    }
+    for (int l = la; l >= la_end; --l) {
       const int nb = P.dtab_total(2, l - 2);
       if (nb)
         k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l, c->act);
