@@ -740,6 +740,26 @@ __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restri
   if (lg) ghost_coarse_walk<DIM, Q, T>(I, F, lg, lvl, lc, i);
 }
 
+// The coarse ancestor closure (blocks 0..B-1) beside the coarse link of the
+// old mesh's ghost predictions (blocks B..2B-1), which reads only the old
+// mesh's reconstruction: two walks of one block per instance in one launch.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(CBLK) k_ancestor_ghost_coarse(const Inst<T> *__restrict__ I,
+                                                                uint8_t *__restrict__ keep, int lc, int B,
+                                                                T *__restrict__ F, const uint32_t *__restrict__ lst,
+                                                                const int *__restrict__ lvl) {
+  if ((int)blockIdx.x >= B) {
+    ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x - B);
+    return;
+  }
+  const Inst<T> &In = I[blockIdx.x];
+  for (int l = lc + 2 < In.jmax ? lc + 2 : In.jmax; l >= In.jmin + 2; --l) {
+    const long long n = ncells_d(DIM, l - 2);
+    for (long long cell = threadIdx.x; cell < n; cell += CBLK) ancestor_cell<DIM, T>(In, keep, l, cell);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- fused launches
 // Two independent chains of a step share launches: each launch runs one link of
 // each, in disjoint blocks that touch disjoint data. Blocks hold wavefronts for

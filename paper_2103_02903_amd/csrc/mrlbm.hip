@@ -673,20 +673,26 @@ struct Engine {
       if (nb)
         k_ancestor<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->keep, P.dinfo_row(c->dinfo, 2, l - 2), l, c->act);
     }
-    if (lc + 2 >= P.jmin + 2) k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
+    // the coarse ancestor closure; beside it the coarse link of the old mesh's
+    // ghost predictions (which only the transfer reads), whose finer links
+    // ride in the grading launches below
+    if (lc > P.jmin)
+      k_ancestor_ghost_coarse<DIM, Q, T><<<2 * P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc, P.B, Fc, lg,
+                                                                         c->lvl[mo]);
+    else if (lc + 2 >= P.jmin + 2)
+      k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
 
     k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew,
                                                                 c->act);
-    // Grading (levels maxJ .. jmin+1) beside the old mesh's ghost predictions
-    // (levels jmin+1 .. maxJ), which only the transfer reads: one link of each
-    // chain per launch. The coarse levels of each chain are one link (one
-    // block per instance); 0 marks a launch without that chain.
+    // Grading (levels maxJ .. jmin+1) beside the finer links of the old mesh's
+    // ghost predictions (levels above the coarse cap, coarse to fine): one link
+    // of each chain per launch. The coarse levels of the grading are one link
+    // (one block per instance); 0 marks a launch without that chain.
     {
       const int lc = coarse_cap(c);
       std::vector<int> gl, hl;  // levels, or -1 for the coarse link
       for (int l = P.maxJ; l >= std::max(P.jmin + 1, lc + 1); --l) gl.push_back(l);
       if (lc > P.jmin) gl.push_back(-1);
-      if (lc > P.jmin) hl.push_back(-1);
       for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l) hl.push_back(l);
       for (size_t k = 0; k < std::max(gl.size(), hl.size()); ++k) {
         const int g = k < gl.size() ? gl[k] : 0, h = k < hl.size() ? hl[k] : 0;
