@@ -201,13 +201,11 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, sc
 def phase_breakdown(sim, steps):
     """Per-phase ms/step from kernel-by-kernel launches between HIP events
     (diagnostic; the graph-replayed timing above is the measurement)."""
-    os.environ["MRLBM_GRAPH"] = "0"
     from paper_2103_02903_amd import mrlbm
 
     eager = mrlbm.Batch(sim.cfgs, precision=sim.precision)
-    os.environ.pop("MRLBM_GRAPH")
     t = sim.tuning()
-    eager.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"])
+    eager.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"], graph=0)
     for i in range(sim.B):
         t, v = sim.get_state(i)
         eager.set_state(i, t, v)

@@ -34,7 +34,12 @@
  *
  * Errors: every function returns a status (0 = OK, < 0 = error, see below);
  * no exception or abort crosses the boundary. After an error the context stays
- * valid for mrlbm_destroy.
+ * valid for mrlbm_destroy. Device-side failures are sticky flags in the
+ * workspace, reported by the next call that synchronises the stream
+ * (mrlbm_get_state, mrlbm_get_mesh, mrlbm_stats, mrlbm_leaves, mrlbm_fields):
+ * MRLBM_ERR_SYNC if a wait between the two halves of a paired launch ran out
+ * of its spin budget (the launch then finished without the ordering, so every
+ * later result of the context is invalid until it is destroyed).
  */
 #ifndef MRLBM_H
 #define MRLBM_H
@@ -52,6 +57,7 @@ extern "C" {
 #define MRLBM_ERR_NONFINITE (-3) /* a leaf value is NaN or infinite */
 #define MRLBM_ERR_HIP (-4)       /* a HIP runtime call failed */
 #define MRLBM_ERR_STATE (-5)     /* call out of order (e.g. step before init) */
+#define MRLBM_ERR_SYNC (-6)      /* a device-side wait gave up: the context's results are invalid (sticky) */
 
 #define MRLBM_D1Q2 1 /* linear advection, eta = (+1, -1), m_eq = (u, V u) */
 #define MRLBM_D1Q3 2 /* Burgers, eta = (0, +1, -1), m_eq = (u, u^2/2, alpha lambda^2 u) */
@@ -83,11 +89,10 @@ int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes);
 /* Create a context inside `workspace` (device memory, >= mrlbm_workspace_size
  * bytes, 256-byte aligned) that enqueues its work on `stream` (a hipStream_t,
  * NULL = the default stream). Uploads the parameter-dependent tables; does not
- * set an initial state. The environment variable MRLBM_TRANSPORT=leaf|pop, read
- * here, forces one of the two transport kernels (one thread per leaf, or one
- * wavefront per population; they give bit-identical results), which are
- * otherwise chosen by problem size. Errors: MRLBM_ERR_INVALID,
- * MRLBM_ERR_CAPACITY, MRLBM_ERR_HIP. */
+ * set an initial state. The launch schedule starts at its default (graph
+ * replay, transport kernel chosen by problem size); mrlbm_set_tuning and
+ * mrlbm_autotune change it. Reads no environment variable.
+ * Errors: MRLBM_ERR_INVALID, MRLBM_ERR_CAPACITY, MRLBM_ERR_HIP. */
 int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream,
                  mrlbm_ctx **out);
 
@@ -114,15 +119,35 @@ int mrlbm_transport_collide(mrlbm_ctx *ctx);
 /* `nsteps` full time steps of Algorithm 1 (adapt, transport, collide).
  * Asynchronous; nsteps >= 0. Each step is replayed from a HIP graph captured
  * on the context's first step in that buffer state (on a private stream, then
- * launched on the context stream); MRLBM_GRAPH=0 in the environment at
- * mrlbm_create launches the kernels one by one instead. Results are identical. */
+ * launched on the context stream); with mrlbm_tuning.graph = 0 the kernels are
+ * launched one by one instead. Results are identical. */
 int mrlbm_step(mrlbm_ctx *ctx, int nsteps);
 
+/* One time step with the mesh adaptation replaced by given meshes (frozen /
+ * replay mode, e.g. to repeat a recorded run's mesh sequence for finite
+ * differences): `trees` (host) holds the membership bytes of the new complete
+ * tree of every instance, concatenated in instance order, each in the tree
+ * layout above. The step then transfers the leaf data to the new leaves
+ * (section "Construction of the time adaptive mesh": copy, projection on
+ * merged cells, prediction on created ones), transports and collides, as
+ * mrlbm_step does after its adaptation. Each tree must be graded and complete
+ * (as for mrlbm_set_state) and may refine the current tree by at most one
+ * level (every new cell outside the current tree has its parent in it), as
+ * an adaptation does. Synchronises the stream for the host checks, then
+ * enqueues the step. Errors: MRLBM_ERR_INVALID (a tree fails the checks;
+ * nothing is changed), MRLBM_ERR_STATE before initialisation. */
+int mrlbm_step_frozen(mrlbm_ctx *ctx, const uint8_t *trees);
+
+/* The current complete tree of one instance (membership bytes, tree layout
+ * above) into a host buffer of mrlbm_sizes' total_cells bytes. Synchronous. */
+int mrlbm_get_mesh(mrlbm_ctx *ctx, int instance, uint8_t *tree);
+
 /* Copy the current tree and values of one instance to host buffers (layouts
- * above; `values` holds q * total_cells reals of the context precision).
- * Only the complete leaves carry the state; the other cells hold scratch
- * (reconstruction values or stale data) that depends only on the sequence of
- * calls since mrlbm_create. Synchronous. */
+ * above; `values` holds q * total_cells reals of the context precision): the
+ * state of Algorithm 1 after the last collision. Only the complete leaves carry
+ * the state; the other cells hold scratch (reconstruction values or stale data)
+ * that depends only on the sequence of calls since mrlbm_create. Synchronous;
+ * for device-side access to the leaves alone see mrlbm_fields. */
 int mrlbm_get_state(mrlbm_ctx *ctx, int instance, uint8_t *tree, void *values);
 
 /* Replace the current state by a host-side tree (must be a graded complete
@@ -136,15 +161,23 @@ int mrlbm_set_state(mrlbm_ctx *ctx, int instance, const uint8_t *tree, const voi
 int mrlbm_sizes(const mrlbm_ctx *ctx, int instance, int64_t *total_cells, int *q);
 
 /* Diagnostics of one instance (synchronous): mass = sum over complete
- * leaves of |C_l| / |C_J| * sum_h f^h, accumulated in double with
- * compensated (Neumaier) summation in a fixed order, in either precision;
- * per-level counts of complete leaves, internal tree cells and ghost cells
- * ([jmax + 1] each, any of them may be NULL).
- * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite. */
+ * leaves of |C_l| / |C_J| * sum_h f^h, the first conserved moment integrated
+ * over the domain in units of finest cells (the quantity the adapted scheme
+ * conserves: eq. (AdaptiveAdvectionPhase) telescopes over the leaves, which
+ * partition the domain), accumulated in double with compensated (Neumaier)
+ * summation in a fixed order, in either precision; per-level counts of
+ * complete leaves (the set S(Lambda) of section "Tree structure and grading"; their sum
+ * over levels divided by N_J^d is the mesh occupation rate of the numerical
+ * experiments), internal tree cells and ghost cells ([jmax + 1] each, any of
+ * them may be NULL).
+ * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite; MRLBM_ERR_SYNC
+ * (takes precedence) if the sticky wait flag is set. */
 int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int64_t *internal,
                 int64_t *ghosts);
 
-/* Export of the complete leaves of one instance to device buffers, in the order (level, cell):
+/* Export of the complete leaves of one instance (the set S(Lambda) of section
+ * "Tree structure and grading", which carries the solution of Algorithm 1) to device
+ * buffers, in the order (level, cell):
  * `cells` receives (level << 26) | cell as uint32 and `values` receives q reals
  * per leaf ([leaf][h], context precision). `capacity` is the number of leaves
  * the buffers hold; *count receives the number of leaves. Synchronous.
@@ -152,11 +185,36 @@ int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int
 int mrlbm_leaves(mrlbm_ctx *ctx, int instance, uint32_t *cells, void *values, int64_t capacity,
                  int64_t *count);
 
+/* Fields of one instance into a device buffer `out` of `out_bytes` bytes;
+ * *n_written receives the number of elements (also when the buffer is too
+ * small, so a first call with out = NULL, out_bytes = 0 sizes it):
+ *   MRLBM_FIELD_LEAF_TABLE  uint32 [n]: (level << 26) | cell of every complete
+ *                           leaf, in the order (level, cell);
+ *   MRLBM_FIELD_POPULATIONS real [n][q]: the leaf populations, same order;
+ *   MRLBM_FIELD_MOMENTS     real [n][q]: m = M f on every leaf, same order (M
+ *                           of the scheme, section "Lattice Boltzmann schemes
+ *                           on volumes"; D2Q9: the matrix of the Navier-Stokes
+ *                           section, rows scaled by powers of lambda);
+ *   MRLBM_FIELD_FINEST      real [q][N_J^d]: the reconstruction of every
+ *                           population on the finest level (the double-hat
+ *                           operator of section "Mesh coarsening": projection
+ *                           up the tree, then zero-detail prediction down to J
+ *                           on every cell outside it).
+ * real is the context precision. MRLBM_FIELD_FINEST rewrites reconstruction
+ * scratch of the context (never a leaf). Synchronous.
+ * Errors: MRLBM_ERR_CAPACITY (nothing written), MRLBM_ERR_INVALID,
+ * MRLBM_ERR_STATE before initialisation, MRLBM_ERR_SYNC. */
+#define MRLBM_FIELD_LEAF_TABLE 1
+#define MRLBM_FIELD_POPULATIONS 2
+#define MRLBM_FIELD_MOMENTS 3
+#define MRLBM_FIELD_FINEST 4
+int mrlbm_fields(mrlbm_ctx *ctx, int instance, int what, void *out, size_t out_bytes, int64_t *n_written);
+
 /* Counters of the work done since the last mrlbm_profile call (all instances).
  * With profiling on, graph-replayed steps (mrlbm_step) bracket the transport
  * kernel of every 8th step, starting with the first, with HIP events inside the
- * step graph; eager steps (MRLBM_GRAPH=0, mrlbm_adapt / mrlbm_transport_collide)
- * time every phase of every step. transport_ms / timed_launches is the average
+ * step graph; eager steps (tuning graph = 0, mrlbm_adapt /
+ * mrlbm_transport_collide) time every phase of every step. transport_ms / timed_launches is the average
  * duration of the kernel over the timed launches. */
 typedef struct {
   uint64_t leaf_updates;       /* complete leaves transported and collided, summed over launches */
@@ -215,13 +273,15 @@ typedef struct {
   int transport_variant; /* transport and details: 1 one thread per item, 2 one wavefront per population */
   int list_grid_all;     /* block cap of the all-level list kernels (8..65536) */
   int list_grid_level;   /* block cap of the per-level list kernels (8..65536) */
+  int graph;             /* 1: steps replayed from HIP graphs (default); 0: kernels launched one by one */
   int from_cache;        /* set by mrlbm_autotune: 1 if taken from the cache */
   double ms_per_step;    /* set by mrlbm_autotune: timed cost of the schedule (0 if cached) */
 } mrlbm_tuning;
 
 /* Time the candidate schedules with `reps` steps each and adopt the fastest.
  * Synchronous; the state and the leaf counters are unchanged. Needs graph
- * stepping (not MRLBM_GRAPH=0). Errors: MRLBM_ERR_STATE before initialisation. */
+ * stepping (tuning graph = 1). Errors: MRLBM_ERR_STATE before initialisation
+ * or without graph stepping. */
 int mrlbm_autotune(mrlbm_ctx *ctx, int reps, mrlbm_tuning *chosen);
 /* Adopt a schedule / read the current one. */
 int mrlbm_set_tuning(mrlbm_ctx *ctx, const mrlbm_tuning *t);
@@ -231,6 +291,14 @@ int mrlbm_get_tuning(const mrlbm_ctx *ctx, mrlbm_tuning *out);
  * aligned) on `stream`: the reference kernel for bandwidth and for the scale
  * of hardware traffic counters. Asynchronous. */
 int mrlbm_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Test hook of the paired launches' bounded wait: sets its spin budget
+ * (0 = the default, about 50 ms) and overwrites the counter the waits poll
+ * with `count`. A large negative count makes every ordered wait give up after
+ * `budget` spins, so that the failure path (MRLBM_ERR_SYNC) can be exercised
+ * while every kernel still runs to its end. For tests only: the context's
+ * results are invalid afterwards. Synchronous. */
+int mrlbm_debug_pair_wait(mrlbm_ctx *ctx, uint32_t budget, int32_t count);
 
 /* Destroy the context (the workspace is the caller's to free). */
 int mrlbm_destroy(mrlbm_ctx *ctx);

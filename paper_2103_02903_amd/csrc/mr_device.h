@@ -233,6 +233,21 @@ __device__ __forceinline__ void collide(T *f, const SchemeC<T> &sc) {
   }
 }
 
+// Moments m = M f of one cell (the same bases as the collision below).
+template <int SCHEME, typename T>
+__device__ __forceinline__ void moments(const T *f, T *m, T L) {
+  if constexpr (SCHEME == 1) {
+    m[0] = f[0] + f[1];
+    m[1] = L * (f[0] - f[1]);
+  } else if constexpr (SCHEME == 2) {
+    m[0] = f[0] + f[1] + f[2];
+    m[1] = L * (f[1] - f[2]);
+    m[2] = (L * L) * (f[1] + f[2]);
+  } else {
+    d2q9_moments(f, m, L);
+  }
+}
+
 // f = M^{-1} m_eq(m) from the conserved moments (initial datum of Algorithm 1).
 template <int SCHEME, typename T>
 __device__ __forceinline__ void equilibrium_populations(const T *mc, T *f, const SchemeC<T> &sc) {

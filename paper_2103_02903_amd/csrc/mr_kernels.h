@@ -233,15 +233,28 @@ __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__res
 // as much as a nearly empty level; sharing one saves it. The order between the
 // links is needed only when both have work (both sides tell from the list
 // lengths, which the compaction summarises per mesh in ne[cat][level]): then
-// every block of the first publishes its writes (device-scope
-// release) and counts itself in sync[0], and every block of the second waits
-// for the count (bounded) and acquires. Blocks are dispatched in increasing
-// order on each XCD, so a waiting block never holds back one it waits for.
-// The last block of the second link clears the counters (sync[1] counts them).
+// every block of the first publishes its writes (device-scope release) and
+// counts itself in sync[0], and every block of the second waits for the count
+// and acquires. Blocks are dispatched in increasing order on each XCD, so a
+// waiting block never holds back one it waits for.
+//
+// sync[] (device memory of the context): [0] first-link blocks counted and not
+// yet consumed (read as a signed int), [1] second-link blocks that have left,
+// [2] the spin budget of one wait, [3] a sticky flag. The last block of the
+// second link consumes the launch's G0 counts by subtraction, not by a reset,
+// so a first-link block that counts itself late (after a wait gave up) still
+// leaves the counter balanced for the next launch. A wait that exhausts its
+// budget sets sync[3], which the host reports as MRLBM_ERR_SYNC; the step's
+// results are then invalid, but every block still runs to its end.
 __device__ __forceinline__ void pair_wait(unsigned *__restrict__ sync, unsigned G0) {
   if (threadIdx.x == 0) {
-    for (unsigned spin = 0; spin < (1u << 20); ++spin) {  // about 50 ms
-      if (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G0) break;
+    const unsigned budget = __hip_atomic_load(sync + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (unsigned spin = 0;; ++spin) {
+      if ((int)__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (int)G0) break;
+      if (spin >= budget) {
+        atomicOr(sync + 3, 1u);
+        break;
+      }
       __builtin_amdgcn_s_sleep(2);
     }
     __threadfence();
@@ -255,11 +268,11 @@ __device__ __forceinline__ void pair_signal(unsigned *__restrict__ sync) {
     atomicAdd(sync, 1u);
   }
 }
-__device__ __forceinline__ void pair_leave(unsigned *__restrict__ sync, unsigned G1) {
+__device__ __forceinline__ void pair_leave(unsigned *__restrict__ sync, unsigned G0, unsigned G1) {
   __syncthreads();
   if (threadIdx.x == 0 && atomicAdd(sync + 1, 1u) == G1 - 1u) {  // every block has passed its wait
-    sync[0] = 0u;
-    sync[1] = 0u;
+    atomicSub(sync, G0);
+    __hip_atomic_store(sync + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 // KIND 0: projections (levels l0 then l0-1 = l1), 2: marked projections, 1:
@@ -290,7 +303,7 @@ __global__ void __launch_bounds__(64 * Q) k_pair(Batch bt, const Inst<T> *__rest
     }
   }
   if (ordered) {
-    if (second) pair_leave(sync, (unsigned)G1);
+    if (second) pair_leave(sync, (unsigned)G0, (unsigned)G1);
     else pair_signal(sync);
   }
 }
@@ -1061,7 +1074,7 @@ __global__ void __launch_bounds__(BLK) k_ancestor_pair(Batch bt, const Inst<T> *
   const long long cell = (long long)(w >> 8) * BLK + threadIdx.x;
   if (l <= active_top(act, I[i], i) && cell < ncells_d(DIM, l - 2)) ancestor_cell<DIM, T>(I[i], keep, l, cell);
   if (ordered) {
-    if (second) pair_leave(sync, (unsigned)G1);
+    if (second) pair_leave(sync, (unsigned)G0, (unsigned)G1);
     else pair_signal(sync);
   }
 }
@@ -1840,8 +1853,56 @@ __global__ void __launch_bounds__(BLK) k_export(const Inst<T> *__restrict__ I, i
     const uint32_t e = leaves[beg + k];
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    cells[k] = e;
-    for (int h = 0; h < Q; ++h) vals[(long long)k * Q + h] = F[foff(In, DIM, Q, l, h) + c];
+    if (cells) cells[k] = e;
+    if (vals)
+      for (int h = 0; h < Q; ++h) vals[(long long)k * Q + h] = F[foff(In, DIM, Q, l, h) + c];
+  }
+}
+
+// Moments m = M f of every complete leaf of instance i, [leaf][k] in the order
+// (level, cell) of the leaf list (the moment bases of the collision: section
+// "Lattice Boltzmann schemes on volumes", and the D2Q9 matrix of the
+// incompressible Navier-Stokes section).
+template <int DIM, int SCHEME, typename T>
+__global__ void __launch_bounds__(BLK) k_moments(const Inst<T> *__restrict__ I, int i, const T *__restrict__ F,
+                                                 const uint32_t *__restrict__ leaves, const int *__restrict__ lvl,
+                                                 T *__restrict__ out) {
+  constexpr int Q = Vel<SCHEME>::Q;
+  const Inst<T> &In = I[i];
+  const int *L = lvl + (i * NCAT + CAT_LEAF) * LVL_STRIDE;
+  const int beg = L[In.jmin], n = L[In.jmax + 1] - beg;
+  for (int k = blockIdx.x * BLK + threadIdx.x; k < n; k += gridDim.x * BLK) {
+    const uint32_t e = leaves[beg + k];
+    const int l = (int)(e >> LEVEL_SHIFT);
+    const uint32_t c = e & CELL_MASK;
+    T f[Q], m[Q];
+#pragma unroll
+    for (int h = 0; h < Q; ++h) f[h] = F[foff(In, DIM, Q, l, h) + c];
+    moments<SCHEME, T>(f, m, In.sc.lam);
+#pragma unroll
+    for (int h = 0; h < Q; ++h) out[(long long)k * Q + h] = m[h];
+  }
+}
+
+// Reconstruction of level l of instance i on every cell outside the complete
+// tree (ghost or not): the zero-detail prediction from level l-1, which holds
+// the reconstruction of that level. Applied for l = jmin+1 .. J in order after
+// the reconstruction of the tree, it gives the double-hat reconstruction on
+// the finest level (section "Mesh coarsening"). Ghosts get the value they
+// already hold (same expression); values of tree cells are not touched.
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(BLK) k_predict_outside(const Inst<T> *__restrict__ I, int i, T *__restrict__ F,
+                                                         const uint8_t *__restrict__ code, int l) {
+  const Inst<T> &In = I[i];
+  const long long n = ncells_d(DIM, l);
+  const uint8_t *cl = code + In.loff[l];
+  for (long long c = blockIdx.x * (long long)BLK + threadIdx.x; c < n; c += (long long)gridDim.x * BLK) {
+    if (cl[c] >= C_INTERNAL) continue;
+    int x, y;
+    coords<DIM>(l, (uint32_t)c, x, y);
+#pragma unroll
+    for (int h = 0; h < Q; ++h)
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
   }
 }
 

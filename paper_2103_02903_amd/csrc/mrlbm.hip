@@ -265,7 +265,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_tnew = take(P.ctotal);
   P.off_mark = take(P.ctotal);
   P.off_act = take(sizeof(int) * ACT * B);
-  P.off_sync = take(sizeof(unsigned) * 2);
+  P.off_sync = take(sizeof(unsigned) * 4);
   for (int k = 0; k < 2; ++k) P.off_ne[k] = take(sizeof(int) * NCAT * LVL_STRIDE);
   P.off_bcnt = take(sizeof(int) * NCAT * P.nblocks);
   P.off_boff = take(sizeof(int) * NCAT * P.nblocks);
@@ -387,7 +387,7 @@ struct mrlbm_ctx {
   uint8_t *keep, *refg, *tnew;
   uint8_t *mark;      // change marks of the reconstruction after an adaptation
   int *act;           // mesh activity per instance (see active_top)
-  unsigned *sync;     // counters of the paired links (zero between launches)
+  unsigned *sync;     // paired links: counter, leave count, spin budget, sticky timeout flag
   int *ne[2];         // per mesh: lists with items at [category][level] (0/1)
   bool recon_reuse;   // the next reconstruction follows an adaptation
   int *bcnt, *boff;
@@ -457,6 +457,16 @@ void phase_mark(mrlbm_ctx *c, int phase, bool begin) {
 }
 
 constexpr unsigned LIST_GRID_LEVEL = 1024, LIST_GRID_ALL = 4096, DENSE_GRID = 4096;
+constexpr unsigned PAIR_WAIT_BUDGET = 1u << 20;  // spins of a paired-link wait (about 50 ms)
+
+// Sticky device-side failure of the context: a paired-link wait that gave up
+// (sync[3]). Synchronises the context stream.
+int sync_status(mrlbm_ctx *c) {
+  unsigned flag = 0;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(&flag, c->sync + 3, sizeof flag, hipMemcpyDeviceToHost));
+  return flag ? MRLBM_ERR_SYNC : MRLBM_OK;
+}
 
 // Invalidate the captured step graphs (after a change of the launch schedule).
 void drop_graphs(mrlbm_ctx *c) {
@@ -844,6 +854,55 @@ struct Engine {
     return MRLBM_OK;
   }
 
+  // Leaf table, populations or moments of instance i (device outputs, either
+  // of cells / vals may be null for the first two).
+  static int leaf_fields(mrlbm_ctx *c, int i, int what, void *out) {
+    const long long n = c->P.inst[i].total;
+    const unsigned g = grid_cap((n + BLK - 1) / BLK, DENSE_GRID);
+    const uint32_t *lf = c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal;
+    if (what == MRLBM_FIELD_MOMENTS)
+      k_moments<DIM, SCHEME, T><<<g, BLK, 0, c->stream>>>(I(c), i, (const T *)c->F[c->cur], lf, c->lvl[c->mcur],
+                                                           (T *)out);
+    else
+      k_export<DIM, Q, T><<<g, BLK, 0, c->stream>>>(I(c), i, (const T *)c->F[c->cur], lf, c->lvl[c->mcur],
+                                                    what == MRLBM_FIELD_LEAF_TABLE ? (uint32_t *)out : nullptr,
+                                                    what == MRLBM_FIELD_POPULATIONS ? (T *)out : nullptr);
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  // The double-hat reconstruction of instance i on its finest level, [h][N_J^d]
+  // into out: the reconstruction of the current mesh (projections, ghost
+  // predictions), then the predictions of every other cell outside the tree,
+  // level by level down to J, in F (cells outside the tree hold scratch).
+  static int finest(mrlbm_ctx *c, int i, void *out) {
+    const Inst<double> &In = c->P.inst[i];
+    T *F = (T *)c->F[c->cur];
+    reconstruct(c, F, c->mcur);
+    for (int l = In.jmin + 1; l <= In.jmax; ++l)
+      k_predict_outside<DIM, Q, T><<<grid_cap(((1ll << (DIM * l)) + BLK - 1) / BLK, DENSE_GRID), BLK, 0,
+                                     c->stream>>>(I(c), i, F, c->code[c->mcur], l);
+    const size_t bytes = sizeof(T) * Q * ((size_t)1 << (DIM * In.jmax));
+    HIPCHK(hipMemcpyAsync(out, F + (size_t)Q * In.loff[In.jmax], bytes, hipMemcpyDeviceToDevice, c->stream));
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  // One step on given new trees (membership bytes of every instance, host):
+  // the adaptation is replaced by the given mesh; the transfer, transport and
+  // collision are those of a normal step.
+  static int frozen(mrlbm_ctx *c, const uint8_t *trees) {
+    const Plan &P = c->P;
+    const int mo = c->mcur, mn = 1 - mo;
+    T *Fc = (T *)c->F[c->cur];
+    reconstruct(c, Fc, mo);  // the old mesh's projections and ghosts feed the transfer
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->tnew, trees, P.ctotal, hipMemcpyHostToDevice));
+    activity_reset(c);
+    classify(c, mn, c->code[mo], Fc);
+    c->mcur = mn;
+    c->recon_reuse = false;
+    return transport(c);
+  }
+
   // ---------------------------------------------------------------- adjoint
   struct Mesh {
     const uint8_t *code;
@@ -1074,6 +1133,14 @@ struct ExportOp {
   static int run(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) { return Engine<D, S, T>::exportl(c, i, cells, vals); }
 };
 template <int D, int S, typename T>
+struct LeafFieldsOp {
+  static int run(mrlbm_ctx *c, int i, int what, void *out) { return Engine<D, S, T>::leaf_fields(c, i, what, out); }
+};
+template <int D, int S, typename T>
+struct FinestOp { static int run(mrlbm_ctx *c, int i, void *out) { return Engine<D, S, T>::finest(c, i, out); } };
+template <int D, int S, typename T>
+struct FrozenOp { static int run(mrlbm_ctx *c, const uint8_t *t) { return Engine<D, S, T>::frozen(c, t); } };
+template <int D, int S, typename T>
 struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::upload_inst(c); } };
 template <int D, int S, typename T>
 struct RecordOp { static int run(mrlbm_ctx *c, int n, int K) { return Engine<D, S, T>::record(c, n, K); } };
@@ -1109,6 +1176,25 @@ bool tree_is_graded(const mrlbm_ctx *c, int inst, const uint8_t *t) {
             if (!at(l - 1, pi)) return false;
           }
       }
+  }
+  return true;
+}
+
+// Host check that every cell of the new tree t outside the old tree `old`
+// (membership bytes of instance inst) has its parent in the old tree: the
+// adaptation refines by at most one level per step, which the in-place
+// transfer relies on (a created cell is predicted from its parent's level).
+bool refines_by_one(const mrlbm_ctx *c, int inst, const uint8_t *old, const uint8_t *t) {
+  const Inst<double> &I = c->P.inst[inst];
+  const int d = c->P.dim;
+  for (int l = I.jmin + 1; l <= I.jmax; ++l) {
+    const long long n = 1ll << (d * l), o = I.loff[l] - I.cbase, op = I.loff[l - 1] - I.cbase;
+    for (long long k = 0; k < n; ++k) {
+      if (!t[o + k] || old[o + k]) continue;
+      const long long x = d == 2 ? (k & ((1ll << l) - 1)) : k, y = d == 2 ? (k >> l) : 0;
+      const long long pk = d == 2 ? (x >> 1) + ((y >> 1) << (l - 1)) : (x >> 1);
+      if (!old[op + pk]) return false;
+    }
   }
   return true;
 }
@@ -1190,10 +1276,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->adj_ws = nullptr;
   c->adj_nsteps = 0;
   c->adj_K = 0;
-  {
-    const char *v = std::getenv("MRLBM_GRAPH");
-    c->use_graph = !(v && !std::strcmp(v, "0"));
-  }
+  c->use_graph = true;
   c->cap_stream = nullptr;
   for (auto &row : c->graph)
     for (auto &g : row) g = nullptr;
@@ -1203,16 +1286,13 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
     delete c;
     return MRLBM_ERR_HIP;
   }
-  if (c->use_graph && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)mrlbm_destroy(c);
     return MRLBM_ERR_HIP;
   }
-  {
-    const char *v = std::getenv("MRLBM_TRANSPORT");
-    c->transport_variant = v && !std::strcmp(v, "leaf") ? 1 : v && !std::strcmp(v, "pop") ? 2 : 0;
-    c->grid_all = LIST_GRID_ALL;
-    c->grid_level = LIST_GRID_LEVEL;
-  }
+  c->transport_variant = 0;
+  c->grid_all = LIST_GRID_ALL;
+  c->grid_level = LIST_GRID_LEVEL;
   // transport weight tables, rounded once to the working precision
   const int q = P.q, d = P.dim, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
   const int nn = std::max(1, P.nmax);
@@ -1244,7 +1324,10 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->refg, 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->mark, 0, P.ctotal);
-  if (e == hipSuccess) e = hipMemset(c->sync, 0, sizeof(unsigned) * 2);
+  if (e == hipSuccess) {
+    const unsigned sync0[4] = {0u, 0u, PAIR_WAIT_BUDGET, 0u};
+    e = hipMemcpy(c->sync, sync0, sizeof sync0, hipMemcpyHostToDevice);
+  }
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->ne[k], 0, sizeof(int) * NCAT * LVL_STRIDE);
   if (e == hipSuccess) {  // every level active until two meshes were built
     const std::vector<int> all(ACT * P.B, ACT_ALL);
@@ -1303,7 +1386,7 @@ int mrlbm_get_state(mrlbm_ctx *c, int instance, uint8_t *tree, void *values) {
   for (long long k = 0; k < I.total; ++k) tree[k] = tree[k] >= C_INTERNAL ? 1 : 0;
   HIPCHK(hipMemcpy(values, (char *)c->F[c->cur] + c->P.rs * c->P.q * I.cbase, c->P.rs * c->P.q * I.total,
                    hipMemcpyDeviceToHost));
-  return MRLBM_OK;
+  return sync_status(c);
 }
 
 int mrlbm_set_state(mrlbm_ctx *c, int instance, const uint8_t *tree, const void *values) {
@@ -1357,6 +1440,10 @@ int mrlbm_stats(mrlbm_ctx *c, int instance, double *mass, int64_t *leaves, int64
     *mass = s + e;
     if (bad) rc = MRLBM_ERR_NONFINITE;
   }
+  {
+    const int st = sync_status(c);
+    if (st) rc = st;
+  }
   int lvl[NCAT * LVL_STRIDE];
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur] + instance * NCAT * LVL_STRIDE, sizeof lvl, hipMemcpyDeviceToHost));
@@ -1382,7 +1469,69 @@ int mrlbm_leaves(mrlbm_ctx *c, int instance, uint32_t *cells, void *values, int6
   if (capacity < n) return MRLBM_ERR_CAPACITY;
   if (!cells || !values) return MRLBM_ERR_INVALID;
   dispatch<ExportOp>(c, instance, cells, values);
+  return sync_status(c);
+}
+
+int mrlbm_fields(mrlbm_ctx *c, int instance, int what, void *out, size_t out_bytes, int64_t *n_written) {
+  if (bad_instance(c, instance) || !n_written) return MRLBM_ERR_INVALID;
+  if (what < MRLBM_FIELD_LEAF_TABLE || what > MRLBM_FIELD_FINEST) return MRLBM_ERR_INVALID;
+  if (!c->has_state[instance]) return MRLBM_ERR_STATE;
+  const Inst<double> &I = c->P.inst[instance];
+  size_t need = 0;
+  if (what == MRLBM_FIELD_FINEST) {
+    *n_written = (int64_t)c->P.q << (c->P.dim * I.jmax);
+    need = c->P.rs * (size_t)*n_written;
+  } else {
+    int lvl[LVL_STRIDE];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(lvl, c->lvl[c->mcur] + (instance * NCAT + CAT_LEAF) * LVL_STRIDE, sizeof lvl,
+                     hipMemcpyDeviceToHost));
+    const int64_t n = lvl[I.jmax + 1] - lvl[I.jmin];
+    *n_written = what == MRLBM_FIELD_LEAF_TABLE ? n : n * c->P.q;
+    need = (what == MRLBM_FIELD_LEAF_TABLE ? sizeof(uint32_t) : c->P.rs) * (size_t)*n_written;
+  }
+  if (out_bytes < need) return MRLBM_ERR_CAPACITY;
+  if (!out && need) return MRLBM_ERR_INVALID;
+  if (need) {
+    const int rc = what == MRLBM_FIELD_FINEST ? dispatch<FinestOp>(c, instance, out)
+                                              : dispatch<LeafFieldsOp>(c, instance, what, out);
+    if (rc) return rc;
+  }
+  return sync_status(c);
+}
+
+int mrlbm_get_mesh(mrlbm_ctx *c, int instance, uint8_t *tree) {
+  if (bad_instance(c, instance) || !tree) return MRLBM_ERR_INVALID;
+  if (!c->has_state[instance]) return MRLBM_ERR_STATE;
+  const Inst<double> &I = c->P.inst[instance];
   HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(tree, c->code[c->mcur] + I.cbase, I.total, hipMemcpyDeviceToHost));
+  for (long long k = 0; k < I.total; ++k) tree[k] = tree[k] >= C_INTERNAL ? 1 : 0;
+  return sync_status(c);
+}
+
+int mrlbm_step_frozen(mrlbm_ctx *c, const uint8_t *trees) {
+  if (!c || !trees) return MRLBM_ERR_INVALID;
+  if (!c->all_ready()) return MRLBM_ERR_STATE;
+  const Plan &P = c->P;
+  std::vector<uint8_t> old(P.ctotal);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(old.data(), c->code[c->mcur], P.ctotal, hipMemcpyDeviceToHost));
+  for (auto &v : old) v = v >= C_INTERNAL ? 1 : 0;
+  for (int i = 0; i < P.B; ++i) {
+    const uint8_t *t = trees + P.inst[i].cbase;
+    if (!tree_is_graded(c, i, t) || !refines_by_one(c, i, old.data() + P.inst[i].cbase, t))
+      return MRLBM_ERR_INVALID;
+  }
+  return dispatch<FrozenOp>(c, trees);
+}
+
+int mrlbm_debug_pair_wait(mrlbm_ctx *c, uint32_t budget, int32_t count) {
+  if (!c) return MRLBM_ERR_INVALID;
+  const unsigned v[2] = {(unsigned)count, budget ? budget : PAIR_WAIT_BUDGET};
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->sync, &v[0], sizeof(unsigned), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->sync + 2, &v[1], sizeof(unsigned), hipMemcpyHostToDevice));
   return MRLBM_OK;
 }
 
@@ -1452,13 +1601,14 @@ std::map<TuneKey, mrlbm_tuning> tune_cache;
 
 int apply_tuning(mrlbm_ctx *c, const mrlbm_tuning &t) {
   if ((t.transport_variant != 1 && t.transport_variant != 2) || t.list_grid_all < 8 || t.list_grid_all > 65536 ||
-      t.list_grid_level < 8 || t.list_grid_level > 65536)
+      t.list_grid_level < 8 || t.list_grid_level > 65536 || (t.graph != 0 && t.graph != 1))
     return MRLBM_ERR_INVALID;
   if (c->transport_variant != t.transport_variant || c->grid_all != (unsigned)t.list_grid_all ||
-      c->grid_level != (unsigned)t.list_grid_level) {
+      c->grid_level != (unsigned)t.list_grid_level || c->use_graph != (t.graph == 1)) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
   }
+  c->use_graph = t.graph == 1;
   c->transport_variant = t.transport_variant;
   c->grid_all = (unsigned)t.list_grid_all;
   c->grid_level = (unsigned)t.list_grid_level;
@@ -1486,6 +1636,7 @@ int mrlbm_get_tuning(const mrlbm_ctx *c, mrlbm_tuning *out) {
                                                  : (c->P.ctotal >= LEAF_KERNEL_CELLS ? 1 : 2);
   out->list_grid_all = (int)c->grid_all;
   out->list_grid_level = (int)c->grid_level;
+  out->graph = c->use_graph ? 1 : 0;
   return MRLBM_OK;
 }
 
@@ -1531,6 +1682,7 @@ int mrlbm_autotune(mrlbm_ctx *c, int reps, mrlbm_tuning *out) {
         t.transport_variant = v;
         t.list_grid_all = ga;
         t.list_grid_level = gl;
+        t.graph = 1;
         rc = apply_tuning(c, t);
         float ms = 0.f;
         if (!rc) rc = dispatch<DryOp>(c, reps, &ms);
@@ -1579,6 +1731,7 @@ const char *mrlbm_status_string(int s) {
     case MRLBM_ERR_NONFINITE: return "non-finite leaf value";
     case MRLBM_ERR_HIP: return "HIP runtime error";
     case MRLBM_ERR_STATE: return "call out of order";
+    case MRLBM_ERR_SYNC: return "device-side wait gave up";
     default: return "unknown status";
   }
 }

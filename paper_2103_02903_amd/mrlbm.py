@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(_PKG, "libmrlbm.so")
 
 SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-finite leaf value",
-          -4: "HIP runtime error", -5: "call out of order"}
+          -4: "HIP runtime error", -5: "call out of order", -6: "device-side wait gave up"}
+FIELDS = {"leaf_table": 1, "populations": 2, "moments": 3, "finest": 4}
 EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mrlbm_adapt",
            "mrlbm_transport_collide", "mrlbm_step", "mrlbm_get_state", "mrlbm_set_state", "mrlbm_sizes",
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
            "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
-           "mrlbm_adjoint", "mrlbm_copy", "mrlbm_autotune", "mrlbm_set_tuning", "mrlbm_get_tuning"]
+           "mrlbm_adjoint", "mrlbm_copy", "mrlbm_autotune", "mrlbm_set_tuning", "mrlbm_get_tuning",
+           "mrlbm_fields", "mrlbm_get_mesh", "mrlbm_step_frozen", "mrlbm_debug_pair_wait"]
 
 
 class MrlbmError(RuntimeError):
@@ -53,7 +55,8 @@ class Counters(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("transport_variant", ctypes.c_int), ("list_grid_all", ctypes.c_int),
-                ("list_grid_level", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
+                ("list_grid_level", ctypes.c_int), ("graph", ctypes.c_int), ("from_cache", ctypes.c_int),
+                ("ms_per_step", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +92,9 @@ def lib() -> ctypes.CDLL:
             "mrlbm_autotune": [vp, ci, ctypes.POINTER(Tuning)],
             "mrlbm_set_tuning": [vp, ctypes.POINTER(Tuning)],
             "mrlbm_get_tuning": [vp, ctypes.POINTER(Tuning)],
+            "mrlbm_fields": [vp, ci, ci, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)],
+            "mrlbm_get_mesh": [vp, ci, vp], "mrlbm_step_frozen": [vp, vp],
+            "mrlbm_debug_pair_wait": [vp, ctypes.c_uint32, ctypes.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -223,6 +229,48 @@ class Batch:
                                                 internal.ctypes.data, ghosts.ctypes.data))
         return dict(mass=float(mass.value), leaves=leaves, internal=internal, ghosts=ghosts)
 
+    def fields(self, i: int, what: str):
+        """One of the C-ABI's field outputs as a device tensor: "leaf_table"
+        (int32 (level << 26) | cell per leaf), "populations" / "moments" ([n][q]
+        per leaf, order (level, cell)), "finest" ([q][N_J^d] double-hat
+        reconstruction on the finest level)."""
+        t = self.torch
+        code = FIELDS[what]
+        n = ctypes.c_int64(0)
+        rc = lib().mrlbm_fields(self._ctx, int(i), code, None, 0, ctypes.byref(n))
+        if rc not in (0, -2):
+            _check("mrlbm_fields", rc)
+        count = int(n.value)
+        dtype = t.int32 if what == "leaf_table" else self.dtype
+        out = t.empty(max(count, 1), dtype=dtype, device=self.device)
+        _check("mrlbm_fields", lib().mrlbm_fields(self._ctx, int(i), code, ctypes.c_void_p(out.data_ptr()),
+                                                  out.element_size() * out.numel(), ctypes.byref(n)))
+        out = out[:count]
+        if what in ("populations", "moments"):
+            return out.view(-1, self.q)
+        if what == "finest":
+            return out.view(self.q, -1)
+        return out
+
+    def get_mesh(self, i: int):
+        tree = np.zeros(self.total_cells[i], np.uint8)
+        _check("mrlbm_get_mesh", lib().mrlbm_get_mesh(self._ctx, int(i), tree.ctypes.data))
+        return tree
+
+    def step_frozen(self, trees):
+        """One step on given new meshes: ``trees`` is one membership array per
+        instance (or one array for a batch of one)."""
+        if isinstance(trees, np.ndarray):
+            trees = [trees]
+        assert len(trees) == self.B
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(t, np.uint8).ravel() for t in trees]))
+        assert flat.size == sum(self.total_cells)
+        _check("mrlbm_step_frozen", lib().mrlbm_step_frozen(self._ctx, flat.ctypes.data))
+
+    def debug_pair_wait(self, budget: int, count: int):
+        """Test hook of the paired launches' bounded wait (see include/mrlbm.h)."""
+        _check("mrlbm_debug_pair_wait", lib().mrlbm_debug_pair_wait(self._ctx, int(budget), int(count)))
+
     def leaves(self, i: int):
         """(cells int32 tensor of (level << 26) | cell, values [n][q] tensor) on the device."""
         t = self.torch
@@ -251,8 +299,8 @@ class Batch:
         _check("mrlbm_get_tuning", lib().mrlbm_get_tuning(self._ctx, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, transport_variant: int, list_grid_all: int, list_grid_level: int):
-        t = Tuning(int(transport_variant), int(list_grid_all), int(list_grid_level), 0, 0.0)
+    def set_tuning(self, transport_variant: int, list_grid_all: int, list_grid_level: int, graph: int = 1):
+        t = Tuning(int(transport_variant), int(list_grid_all), int(list_grid_level), int(graph), 0, 0.0)
         _check("mrlbm_set_tuning", lib().mrlbm_set_tuning(self._ctx, ctypes.byref(t)))
 
     # ---- adjoint on frozen meshes (batch of one)
@@ -308,3 +356,9 @@ class Sim(Batch):
 
     def leaves(self):
         return super().leaves(0)
+
+    def fields(self, what: str):
+        return super().fields(0, what)
+
+    def get_mesh(self):
+        return super().get_mesh(0)

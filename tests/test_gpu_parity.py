@@ -364,15 +364,16 @@ def test_set_state_to_a_finer_mesh_midrun(mr):
     sim.close()
 
 
-def test_transport_variants_bit_identical(mr, monkeypatch):
+def test_transport_variants_bit_identical(mr):
     """The per-item and per-population variants of the transport and details
     kernels compute the same meshes and the same bits."""
     cfg, m0 = W.shear_layer_d2q9(jmin=3, jmax=8, eps=1e-4, re=1000.0, width=1.0 / 40)
     out = {}
     for v in ("leaf", "pop"):
-        monkeypatch.setenv("MRLBM_TRANSPORT", v)
         for prec in (8, 4):
             sim = mr.Sim(cfg, precision=prec)
+            t = sim.tuning()
+            sim.set_tuning(1 if v == "leaf" else 2, t["list_grid_all"], t["list_grid_level"])
             sim.init_equilibrium(m0)
             sim.step(12)
             out[(v, prec)] = sim.get_state()
@@ -382,7 +383,7 @@ def test_transport_variants_bit_identical(mr, monkeypatch):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][leaves], b[1][leaves])
 
 
-def test_graph_steps_match_eager_launches(mr, monkeypatch):
+def test_graph_steps_match_eager_launches(mr):
     """Steps replayed from HIP graphs (plain and with the timed transport launched
     outside the graph) compute the same bits as kernel-by-kernel launches, also
     after single adapt / transport calls change the buffer assignment."""
@@ -390,9 +391,11 @@ def test_graph_steps_match_eager_launches(mr, monkeypatch):
     m0s = [it[1] for it in W.shear_layer_batch(3, jmax_choices=(6, 7))]
     out = {}
     for mode in ("0", "1"):
-        monkeypatch.setenv("MRLBM_GRAPH", mode)
         for prec in (8, 4):
             b = mr.Batch(cfgs, precision=prec)
+            t = b.tuning()
+            b.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"], graph=int(mode))
+            assert b.tuning()["graph"] == int(mode)
             for i, m in enumerate(m0s):
                 b.init_equilibrium(i, m)
             b.step(3)
