@@ -78,28 +78,52 @@ def measured_traffic(workload_name: str, precision: int, kernel: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, tree, values, seconds: float):
-    """The FP64 oracle (single thread) stepping from the GPU's state for about
-    `seconds` of host time; leaf updates per second of that sample."""
+    """The FP64 oracle stepping from the GPU's state, timed on the host: with
+    all the threads OpenMP gets here (its parallel per-cell loops; the value
+    reported) and single-threaded, each for about `seconds` of host time."""
     import numpy as np
 
     import oracle
 
     o = oracle.Oracle(cfg)
-    tree = tree.copy()
-    values = values.astype(np.float64)
-    updates, steps = 0, 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(tree, values)
-        updates += int(o.leaf_counts(tree).sum())
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=updates / dt, unit="leaf updates/s", cores=1, kind="oracle",
-                sample="%d oracle steps (%.1f s, single thread) from the GPU state at the start of the timed "
-                       "region" % (steps, dt))
+    n_all = oracle.threads()
+
+    def run(nthreads, secs):
+        oracle.threads(nthreads)
+        t, v = tree.copy(), values.astype(np.float64)
+        updates, steps = 0, 0
+        t0 = time.perf_counter()
+        while True:
+            o.step(t, v)
+            updates += int(o.leaf_counts(t).sum())
+            steps += 1
+            if time.perf_counter() - t0 >= secs:
+                break
+        return updates / (time.perf_counter() - t0), steps, time.perf_counter() - t0
+
+    rate_all, steps_all, dt_all = run(n_all, seconds)
+    rate_one, steps_one, dt_one = run(1, seconds)
+    oracle.threads(n_all)
+    host = dict(cpu_model=_cpu_model(), nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)),
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+    return dict(value=rate_all, unit="leaf updates/s", cores=n_all, kind="oracle",
+                sample="%d oracle steps (%.1f s, %d threads) from the GPU state at the start of the measured "
+                       "window" % (steps_all, dt_all, n_all),
+                single_thread=dict(value=rate_one, cores=1,
+                                   sample="%d oracle steps (%.1f s, one thread), same start" % (steps_one, dt_one)),
+                host=host)
 
 
 def copy_bandwidth(nbytes: int = COPY_BYTES, reps: int = 5):
@@ -124,14 +148,18 @@ def copy_bandwidth(nbytes: int = COPY_BYTES, reps: int = 5):
 
 
 def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, schedule=None, markers=False):
-    """Warm up, pick the launch schedule with the library's autotuner, then time
-    `steps` graph-replayed steps; HIP events inside the step graph bracket the
-    transport kernel of every 8th of them.
+    """Warm up, pick the launch schedule with the library's autotuner, then run
+    two windows of `steps` graph-replayed steps each:
+      A (the measurement of `value` and ms_per_step): no timing inside the steps;
+      B (the roofline): HIP events inside every step graph bracket the transport
+        kernel, on the library's stream, so every launch of the window is timed
+        (each bracket costs the step a few microseconds, which is why A is kept
+        free of them).
     Returns (result dict, sim, state of instance `keep_state_of` at the start of
-    the timed region or None). `schedule` (transport variant, all-level cap,
-    per-level cap) replaces the autotuner; `markers` brackets the timed region
-    with two 256-byte launches of the copy kernel, which profiles use to find
-    the timed dispatches."""
+    window A or None). `schedule` (transport variant, all-level cap, per-level
+    cap) replaces the autotuner; `markers` puts a 256-byte launch of the copy
+    kernel before A, between A and B and after B, which profiles use to find
+    the dispatches of each window."""
     import torch
 
     from paper_2103_02903_amd import mrlbm
@@ -151,29 +179,42 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, sc
         mark = (torch.zeros(256, dtype=torch.uint8, device=sim.device),
                 torch.zeros(256, dtype=torch.uint8, device=sim.device))
     state0 = sim.get_state(keep_state_of) if keep_state_of is not None else None
-    sim.profile(True)
     stream = sim.stream
+
+    def marker():
+        if mark is not None:
+            mrlbm.copy(mark[1], mark[0], 256, stream)
+
+    # window A
+    sim.profile(0)  # counters reset, no timing events
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    if mark is not None:
-        mrlbm.copy(mark[1], mark[0], 256, stream)
+    marker()
     t_start.record(stream)
     sim.step(steps)
     t_end.record(stream)
-    if mark is not None:
-        mrlbm.copy(mark[1], mark[0], 256, stream)
+    marker()
     torch.cuda.synchronize()
     elapsed_ms = t_start.elapsed_time(t_end)
+    cnt_a = sim.counters()
+    leaf_updates = int(cnt_a["leaf_updates"])
+    stats = [sim.stats(i) for i in range(sim.B)]
+    # window B
+    sim.profile(2)
+    sim.step(steps)
+    marker()
+    torch.cuda.synchronize()
     cnt = sim.counters()
-    sim.profile(False)
-    q, rs = sim.q, precision
-    leaf_updates = int(cnt["leaf_updates"])
+    sim.profile(0)
+    q, rs, d = sim.q, precision, sim.dim
     launches = max(1, int(cnt["timed_launches"]))
     avg_ms = cnt["transport_ms"] / launches
     bytes_per_leaf = 2 * q * rs  # read q populations, write q (neighbour reads are cache reuse)
-    bytes_per_launch = leaf_updates * bytes_per_leaf / max(1, int(cnt["transport_launches"]))
+    bytes_per_launch = int(cnt["leaf_updates"]) * bytes_per_leaf / max(1, int(cnt["transport_launches"]))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    stats = [sim.stats(i) for i in range(sim.B)]
+    # whole step: the minimum fused step moves (2 + 2^d / (2^d - 1)) q s bytes per leaf
+    step_bytes_per_leaf = (2.0 + 2.0 ** d / (2.0 ** d - 1.0)) * q * rs
+    step_gbs = step_bytes_per_leaf * leaf_updates / (elapsed_ms * 1e-3) / 1e9
     finest = sum(1 << (sim.dim * int(c["jmax"])) for c, _ in items)
     leaves_now = sum(int(st["leaves"].sum()) for st in stats)
     by_n = {}
@@ -188,6 +229,7 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, sc
                transport_frac=achieved / HBM_PEAK_GBS,
                transport_leaf_updates_per_s=bytes_per_launch / bytes_per_leaf / (avg_ms * 1e-3),
                transport_launches=int(cnt["transport_launches"]), timed_launches=int(cnt["timed_launches"]),
+               step_bytes_per_leaf=step_bytes_per_leaf, step_gbs=step_gbs, step_frac=step_gbs / HBM_PEAK_GBS,
                mean_leaves_per_step=leaf_updates / max(1, steps),
                compression_rate_final=1.0 - leaves_now / finest,
                compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
@@ -217,7 +259,7 @@ def phase_breakdown(sim, steps):
             "transport_collide": cnt["transport_ms"] / steps}
 
 
-def ke_gradient(sim, region=(0.25, 0.75)):
+def ke_gradient(sim, region=(0.375, 0.625)):
     """Kinetic energy sum over leaves centred in region^2 of |C|/|C_J| |q|^2/(2 rho)
     (D2Q9, lambda = 1) and its gradient in the library's values layout."""
     import torch
@@ -281,8 +323,45 @@ def adjoint_run(nsteps: int, ckpt: int, precision: int):
     sim.step(nsteps)
     leaf_updates = int(sim.counters()["leaf_updates"])
     sim.close()
+    from paper_2103_02903_amd import workloads as W
+
+    da = W.vortex_amplitude_gradient(cfg, mbar.double().cpu().numpy())
     return dict(t_forward=t_fwd, t_record=t_rec, t_adjoint=t_adj, J=Jval, mbar=mbar.double(), sbar=sbar,
-                leaf_updates=leaf_updates)
+                dJda=da.tolist(), leaf_updates=leaf_updates)
+
+
+def finest_moments(sim, i):
+    """Conserved moments (first nc rows of M f) of the finest-level reconstruction
+    of instance i, float64 numpy [nc][N_J^d]."""
+    f = sim.fields(i, "finest").double()
+    if sim.q == 9:
+        import torch
+
+        ex = torch.tensor([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=torch.float64, device=f.device)
+        ey = torch.tensor([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=torch.float64, device=f.device)
+        lam = float(sim.cfgs[i].get("lam", 1.0))
+        m = torch.stack([f.sum(0), lam * (ex @ f), lam * (ey @ f)])
+    else:
+        m = f.sum(0)[None]
+    return m.cpu().numpy()
+
+
+def field_errors(a, b, names):
+    out = {}
+    for k, n in enumerate(names):
+        d = abs(a[k] - b[k])
+        out[n] = dict(l1_rel=float(d.sum() / abs(b[k]).sum()), linf=float(d.max()))
+    return out
+
+
+def sample_instances(items):
+    """One instance of each finest level of a batch (the first one)."""
+    seen, out = set(), []
+    for i, (c, _) in enumerate(items):
+        if c["jmax"] not in seen:
+            seen.add(c["jmax"])
+            out.append(i)
+    return out
 
 
 def variants(args, head):
@@ -293,24 +372,33 @@ def variants(args, head):
     out = {}
     items, desc, _ = workload("d2q9_shear_batch96")
     r64, s64, _ = timed_run(items, 8, args.steps, args.warmup)
+    fin64 = {i: finest_moments(s64, i) for i in head.get("finest_check", {})}
     s64.close()
     r64["workload"] = desc
     r64["fp32_vs_fp64"] = head["value"] / r64["value"]
-    r64["accuracy"] = ("FP32 run's total mass relative to this FP64 run's: %.2e (each precision decides its own "
-                       "meshes; per-field FP32 errors against the FP64 oracle are checked by one-step replays in "
-                       "the GPU tests)" % (abs(head["mass_final"] - r64["mass_final"]) / abs(r64["mass_final"])))
+    r64["accuracy"] = dict(
+        mass_rel=abs(head["mass_final"] - r64["mass_final"]) / abs(r64["mass_final"]),
+        per_field_fp32_vs_fp64={"instance %d (J=%d)" % (i, items[i][0]["jmax"]):
+                                field_errors(head["finest_check"][i], fin64[i], ("rho", "q_x", "q_y"))
+                                for i in fin64},
+        basis="finest-level reconstruction of the FP32 batch (the measured run) and of this FP64 batch after the "
+              "same steps, one instance of each finest level; each precision decides its own meshes")
     out["batched_fp64"] = r64
     items, desc, _ = workload("d2q9_shear_1024")
-    single = {}
+    single, fin = {}, {}
     for prec in (8, 4):
         r, sm, _ = timed_run(items, prec, args.single_steps, args.single_warmup)
+        fin[prec] = finest_moments(sm, 0)
         sm.close()
         r["workload"] = desc
         single[prec] = r
     single[8]["batched_fp32_vs_this"] = head["value"] / single[8]["value"]
     single[4]["fp32_vs_fp64"] = single[4]["value"] / single[8]["value"]
-    single[4]["accuracy"] = "final mass relative difference to the FP64 run %.2e" % (
-        abs(single[4]["mass_final"] - single[8]["mass_final"]) / abs(single[8]["mass_final"]))
+    single[4]["accuracy"] = dict(
+        per_field_fp32_vs_fp64=field_errors(fin[4], fin[8], ("rho", "q_x", "q_y")),
+        mass_rel=abs(single[4]["mass_final"] - single[8]["mass_final"]) / abs(single[8]["mass_final"]),
+        basis="finest-level reconstruction of both runs after the same steps; each precision decides its own "
+              "meshes; the FP64 path is the one the GPU tests replay against the FP64 oracle")
     out["single_fp64"] = single[8]
     out["single_fp32"] = single[4]
     a32 = adjoint_run(args.adjoint_steps, args.adjoint_ckpt, 4)
@@ -319,13 +407,14 @@ def variants(args, head):
         grad_ms = (a["t_record"] + a["t_adjoint"]) * 1e3
         out[name] = dict(
             workload=workload("d2q9_vortex_256")[1] + "; %d steps, checkpoint every %d, gradient of the kinetic "
-                     "energy in [1/4,3/4]^2 w.r.t. the initial moments and the relaxation rates" %
+                     "energy in [3/8,5/8]^2 w.r.t. the initial moments, the relaxation rates and the 16 mode "
+                     "amplitudes" %
                      (args.adjoint_steps, args.adjoint_ckpt),
             value=a["leaf_updates"] / ((a["t_record"] + a["t_adjoint"])),
             unit="forward leaf updates/s of the gradient computation (record + adjoint)",
             gradient_ms=grad_ms, forward_ms=a["t_forward"] * 1e3,
             gradient_over_forward=grad_ms / (a["t_forward"] * 1e3), J=a["J"],
-            dJ_ds2=float(a["sbar"][7] + a["sbar"][8]))
+            dJ_ds2=float(a["sbar"][7] + a["sbar"][8]), dJ_da=a["dJda"])
     rel = float(torch.max(torch.abs(a32["mbar"] - a64["mbar"])) / torch.max(torch.abs(a64["mbar"])))
     out["adjoint_fp32"]["accuracy"] = ("max |dJ/dm0 (FP32) - dJ/dm0 (FP64)| / max |dJ/dm0 (FP64)| = %.2e, each "
                                        "precision on the meshes it chose itself" % rel)
@@ -340,7 +429,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="d2q9_shear_batch96")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 4, 8], help="0: the workload's default")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--single-steps", type=int, default=1000)
@@ -372,6 +461,8 @@ def main():
     schedule = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
     head, sim, state0 = timed_run(items, precision, args.steps, args.warmup,
                                   None if args.no_cpu_baseline else big, schedule=schedule, markers=True)
+    check = sample_instances(items)
+    head["finest_check"] = {i: finest_moments(sim, i) for i in check}
     phases = phase_breakdown(sim, min(args.steps, 100))
     sim.close()
     copy = copy_bandwidth()
@@ -402,6 +493,12 @@ def main():
             "avg_launch_ms": head["transport_avg_launch_ms"],
             "launches": head["transport_launches"],
             "event_timed_launches": head["timed_launches"],
+            "window": "second window of --steps graph steps after the measured one, every transport launch "
+                      "bracketed by HIP events in the step graph",
+            "step": {"bytes_per_leaf": head["step_bytes_per_leaf"], "achieved": head["step_gbs"],
+                     "frac": head["step_frac"], "unit": "GB/s",
+                     "basis": "minimum fused step (2 + 2^d/(2^d-1)) q s bytes per leaf update, times the leaf "
+                              "updates of the measured window, over its wall time"},
         },
         "copy_reference": {"kernel": "k_copy_u4", "gbs": copy["gbs"], "frac": copy["gbs"] / HBM_PEAK_GBS},
         "mean_leaves_per_step": head["mean_leaves_per_step"],
@@ -420,6 +517,7 @@ def main():
         if len(items) > 1:
             out["cpu_baseline"]["sample"] += " (instance %d of %d, levels %d..%d)" % (
                 big, len(items), items[big][0]["jmin"], items[big][0]["jmax"])
+    head.pop("finest_check", None)
     print(json.dumps(out))
 
 

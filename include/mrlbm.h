@@ -212,8 +212,8 @@ int mrlbm_fields(mrlbm_ctx *ctx, int instance, int what, void *out, size_t out_b
 
 /* Counters of the work done since the last mrlbm_profile call (all instances).
  * With profiling on, graph-replayed steps (mrlbm_step) bracket the transport
- * kernel of every 8th step, starting with the first, with HIP events inside the
- * step graph; eager steps (tuning graph = 0, mrlbm_adapt /
+ * kernel of every 8th step (profile mode 1) or of every step (mode 2), starting
+ * with the first, with HIP events inside the step graph; eager steps (tuning graph = 0, mrlbm_adapt /
  * mrlbm_transport_collide) time every phase of every step. transport_ms / timed_launches is the average
  * duration of the kernel over the timed launches. */
 typedef struct {
@@ -225,10 +225,13 @@ typedef struct {
   uint64_t timed_launches;     /* transport launches covered by the event timings */
 } mrlbm_counters;
 
-/* Reset the counters and switch HIP-event timing on (enable = 1) or off (0).
- * Leaf updates are always counted (on the device, by the transport kernel).
- * Timing records events on the context stream (see mrlbm_counters for which
- * launches are timed). */
+/* Reset the counters and switch HIP-event timing off (enable = 0), on with
+ * the transport kernel of every 8th graph-replayed step bracketed (1), or on
+ * with that kernel of every graph-replayed step bracketed (2). Leaf updates are
+ * always counted (on the device, by the transport kernel). Timing records
+ * events on the context stream (see mrlbm_counters for which launches are
+ * timed); each bracketing event costs the step a few microseconds.
+ * Errors: MRLBM_ERR_INVALID for another value of enable. */
 int mrlbm_profile(mrlbm_ctx *ctx, int enable);
 
 /* Read the counters (synchronous). */

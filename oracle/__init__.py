@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
              "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -62,6 +62,7 @@ def lib():
         u8 = ctypes.c_void_p
         dp = ctypes.c_void_p
         L.orc_total_cells.argtypes = [P]; L.orc_total_cells.restype = ctypes.c_int64
+        L.orc_threads.argtypes = [ctypes.c_int]; L.orc_threads.restype = ctypes.c_int
         L.orc_level_offset.argtypes = [P, ctypes.c_int]; L.orc_level_offset.restype = ctypes.c_int64
         for name, args in [("orc_init", [P, dp, u8, dp]), ("orc_reconstruct", [P, u8, dp]),
                            ("orc_details", [P, u8, dp, dp]), ("orc_adapt_tree", [P, u8, dp, u8]),
@@ -88,6 +89,12 @@ def lib():
         L.orc_mass.argtypes = [P, u8, dp]; L.orc_mass.restype = ctypes.c_double
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Host threads of the oracle's parallel per-cell loops (n > 0 sets them);
+    returns the count in use. Results do not depend on it."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):

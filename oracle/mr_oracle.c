@@ -6,6 +6,11 @@
  * baseline of the benchmark; never by the GPU library, with which it shares
  * no code. Build with -ffp-contract=off and without fast-math: the prediction,
  * projection and detail expressions below are evaluated in the order written.
+ * Loops whose iterations write disjoint cells from read-only inputs carry an
+ * OpenMP pragma (a build with -fopenmp spreads them over the host cores), and
+ * the scatters of the adjoint run one population per thread, each in its
+ * serial order; no reduction is parallel, so every result is independent of
+ * the thread count, bit for bit.
  *
  * Readings of the paper taken here (each is listed with its justification in
  * the design notes of the repository):
@@ -25,10 +30,18 @@
 #include "mr_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define MAXQ 9
+
+/* Host threads of the parallel loops: sets the count when n > 0; returns the
+ * count the next parallel loop uses. */
+int orc_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 
 /* ---- Level geometry (section "Nested lattices"): N_l = 2^l cells per axis ---- */
 
@@ -235,6 +248,7 @@ static double project(const orc_params *P, const double *Fc, int l, int px, int 
 int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values) {
   /* Upward: internal tree cells hold the projection of their children. */
   for (int l = P->jmax - 1; l >= P->jmin; --l) {
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_internal(P, tree, l, c)) continue;
       int x, y;
@@ -246,6 +260,7 @@ int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values) {
   /* Downward: cells outside the tree receive the zero-detail prediction. */
   for (int l = P->jmin + 1; l <= P->jmax; ++l) {
     const uint8_t *t = tree_at(P, tree, l);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (t[c]) continue;
       int x, y;
@@ -266,6 +281,7 @@ int orc_details(const orc_params *P, const uint8_t *tree, const double *values, 
   for (int l = P->jmin + 1; l <= P->jmax; ++l) {
     const uint8_t *tp = tree_at(P, tree, l - 1), *tc = tree_at(P, tree, l);
     double *Dp = D + orc_level_offset(P, l - 1);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
       int px, py;
       cell_coords(P, l - 1, p, &px, &py);
@@ -395,6 +411,7 @@ int orc_transfer(const orc_params *P, const uint8_t *told, const double *vold, c
                  double *vnew) {
   (void)told; /* the dense reconstruction already holds copy, projection and prediction values */
   for (int l = P->jmin; l <= P->jmax; ++l)
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_leaf(P, tnew, l, c)) continue;
       for (int h = 0; h < P->q; ++h) val_at(P, vnew, l, h)[c] = val_at(P, vold, l, h)[c];
@@ -412,6 +429,7 @@ int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, do
   orc_velocities(P, eta);
   for (int l = P->jmin; l <= J; ++l) {
     const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_leaf(P, tree, l, c)) continue;
       int x, y;
@@ -457,11 +475,13 @@ int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, do
 }
 
 int orc_collide(const orc_params *P, const uint8_t *tree, double *values) {
-  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ], f[MAXQ];
+  double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ];
   orc_moment_matrix(P, M);
   if (orc_moment_matrix_inverse(P, Minv)) return -1;
   for (int l = P->jmin; l <= P->jmax; ++l)
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
+      double f[MAXQ];
       if (!is_leaf(P, tree, l, c)) continue;
       for (int h = 0; h < P->q; ++h) f[h] = val_at(P, values, l, h)[c];
       collide_with(P, M, Minv, f);
@@ -634,6 +654,7 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
   if (!v || !D) { free(v); if (!D_out) free(D); return -1; }
   memcpy(v, leaf_values, sizeof(float) * (size_t)(P->q * total));
   for (int l = P->jmax - 1; l >= P->jmin; --l)
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_internal(P, tree, l, c)) continue;
       int x, y;
@@ -641,6 +662,7 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
       for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = project_f32(P, valf_at(P, v, l + 1, h), l, x, y);
     }
   for (int l = P->jmin + 1; l <= P->jmax; ++l)
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (tree_at(P, tree, l)[c]) continue;
       int x, y;
@@ -651,6 +673,7 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
   for (int l = P->jmin + 1; l <= P->jmax; ++l) {
     const uint8_t *tp = tree_at(P, tree, l - 1), *tc = tree_at(P, tree, l);
     double *Dp = D + orc_level_offset(P, l - 1);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
       int px, py;
       cell_coords(P, l - 1, p, &px, &py);
@@ -731,34 +754,36 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
 /* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
  * the leaf entries hold the adjoint of the leaf values and all others are 0. */
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
-  int64_t idx[9];
-  double w[9];
-  for (int l = P->jmax; l >= P->jmin + 1; --l) {  /* predictions, finest first */
-    const uint8_t *t = tree_at(P, tree, l);
-    for (int64_t c = 0; c < ncells(P, l); ++c) {
-      if (t[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      const int nk = orc_predict_stencil(P, l, x, y, idx, w);
-      for (int h = 0; h < P->q; ++h) {
-        double *gl = val_at(P, g, l, h), *gp = val_at(P, g, l - 1, h);
+  const double inv = 1.0 / nchildren(P);
+  /* Each population is its own linear map: the populations run in parallel,
+   * each with the loop order below. */
+#pragma omp parallel for schedule(static, 1)
+  for (int h = 0; h < P->q; ++h) {
+    int64_t idx[9];
+    double w[9];
+    for (int l = P->jmax; l >= P->jmin + 1; --l) { /* predictions, finest first */
+      const uint8_t *t = tree_at(P, tree, l);
+      double *gl = val_at(P, g, l, h), *gp = val_at(P, g, l - 1, h);
+      for (int64_t c = 0; c < ncells(P, l); ++c) {
+        if (t[c]) continue;
+        int x, y;
+        cell_coords(P, l, c, &x, &y);
+        const int nk = orc_predict_stencil(P, l, x, y, idx, w);
         for (int k = 0; k < nk; ++k) gp[idx[k]] += w[k] * gl[c];
         gl[c] = 0.0;
       }
     }
-  }
-  const double inv = 1.0 / nchildren(P);
-  for (int l = P->jmin; l <= P->jmax - 1; ++l)  /* projections, coarsest first */
-    for (int64_t c = 0; c < ncells(P, l); ++c) {
-      if (!is_internal(P, tree, l, c)) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      for (int h = 0; h < P->q; ++h) {
-        double *gl = val_at(P, g, l, h), *gc = val_at(P, g, l + 1, h);
+    for (int l = P->jmin; l <= P->jmax - 1; ++l) { /* projections, coarsest first */
+      double *gl = val_at(P, g, l, h), *gc = val_at(P, g, l + 1, h);
+      for (int64_t c = 0; c < ncells(P, l); ++c) {
+        if (!is_internal(P, tree, l, c)) continue;
+        int x, y;
+        cell_coords(P, l, c, &x, &y);
         for (int sigma = 0; sigma < nchildren(P); ++sigma) gc[child_index(P, l, x, y, sigma)] += inv * gl[c];
         gl[c] = 0.0;
       }
     }
+  }
   return 0;
 }
 
@@ -768,17 +793,19 @@ int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, 
   const int J = P->jmax, d = P->dim;
   int eta[2 * MAXQ];
   orc_velocities(P, eta);
-  for (int l = P->jmin; l <= J; ++l) {
-    const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
-    for (int64_t c = 0; c < ncells(P, l); ++c) {
-      if (!is_leaf(P, tree, l, c)) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      const int bx0 = x * w, by0 = y * wy;
-      for (int h = 0; h < P->q; ++h) {
-        const int ex = eta[2 * h], ey = eta[2 * h + 1];
+  /* populations in parallel, each with the loop order below */
+#pragma omp parallel for schedule(static, 1)
+  for (int h = 0; h < P->q; ++h) {
+    const int ex = eta[2 * h], ey = eta[2 * h + 1];
+    double *GJ = val_at(P, gs, J, h);
+    for (int l = P->jmin; l <= J; ++l) {
+      const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
+      for (int64_t c = 0; c < ncells(P, l); ++c) {
+        if (!is_leaf(P, tree, l, c)) continue;
+        int x, y;
+        cell_coords(P, l, c, &x, &y);
+        const int bx0 = x * w, by0 = y * wy;
         const double a = val_at(P, ob, l, h)[c];
-        double *GJ = val_at(P, gs, J, h);
         if (ex == 0 && ey == 0) {
           val_at(P, gs, l, h)[c] += a;
         } else if (n == 0) {
@@ -805,6 +832,7 @@ int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, 
  * at the same cell, so its adjoint adds there. */
 int orc_transfer_T(const orc_params *P, const uint8_t *tnew, const double *gnew, double *gold) {
   for (int l = P->jmin; l <= P->jmax; ++l)
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_leaf(P, tnew, l, c)) continue;
       for (int h = 0; h < P->q; ++h) val_at(P, gold, l, h)[c] += val_at(P, gnew, l, h)[c];

@@ -110,6 +110,10 @@ void orc_equilibrium(const orc_params *P, const double *m, double *meq);
 /* Logical velocities eta^h, layout [q][2] (y component 0 in 1D). */
 void orc_velocities(const orc_params *P, int *eta);
 
+/* Host threads of the oracle's parallel per-cell loops (results do not depend
+ * on it): sets the count when n > 0, returns the count in use. */
+int orc_threads(int n);
+
 /* Diagnostics. */
 int orc_leaf_counts(const orc_params *P, const uint8_t *tree, int64_t *counts /* [J+1] */);
 double orc_mass(const orc_params *P, const uint8_t *tree, const double *values);

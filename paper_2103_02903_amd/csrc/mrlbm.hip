@@ -418,7 +418,8 @@ struct mrlbm_ctx {
   hipGraphNode_t timed_ev[4][2];
   hipEvent_t ev_placeholder;
   bool profiling;
-  unsigned long long graph_steps;  // graph-replayed steps since profiling was switched on
+  unsigned long long timing_period;  // graph steps per event-timed transport launch (1 or 8)
+  unsigned long long graph_steps;    // graph-replayed steps since profiling was switched on
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
   std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of the first of two events)
@@ -518,7 +519,7 @@ hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, 
 // details run one thread per item; below, one wavefront per population (more
 // parallelism for small sets). Both variants compute bit-identical results.
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
-constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch
+constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch (profile mode 1)
 
 template <int DIM, int SCHEME, typename T>
 struct Engine {
@@ -776,7 +777,7 @@ struct Engine {
   // they are pointed at two fresh events. (Each event record drains the queue,
   // some microseconds, so timing every step would slow the steps it measures.)
   static int step_graph(mrlbm_ctx *c) {
-    const int timed = c->profiling && (c->graph_steps++ % TIMING_PERIOD == 0) ? 1 : 0;
+    const int timed = c->profiling && (c->graph_steps++ % c->timing_period == 0) ? 1 : 0;
     const int par = c->mcur, key = 2 * c->cur + par;
     hipGraphExec_t &g = c->graph[timed][key];
     if (!g) {
@@ -1271,6 +1272,7 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->mcur = 0;
   c->has_state.assign(P.B, 0);
   c->profiling = false;
+  c->timing_period = TIMING_PERIOD;
   c->graph_steps = 0;
   c->ev_used = 0;
   c->adj_ws = nullptr;
@@ -1539,7 +1541,9 @@ int mrlbm_profile(mrlbm_ctx *c, int enable) {
   if (!c) return MRLBM_ERR_INVALID;
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long)));
+  if (enable < 0 || enable > 2) return MRLBM_ERR_INVALID;
   c->profiling = enable != 0;
+  c->timing_period = enable == 2 ? 1 : TIMING_PERIOD;
   c->graph_steps = 0;
   c->ev_used = 0;
   c->ev_marks.clear();

@@ -200,8 +200,10 @@ class Batch:
         self._keep.clear()
 
     # ---- measurement
-    def profile(self, enable: bool = True):
-        _check("mrlbm_profile", lib().mrlbm_profile(self._ctx, int(bool(enable))))
+    def profile(self, enable=True):
+        """Reset the counters; timing off (False / 0), every 8th transport launch
+        of graph steps event-timed (True / 1) or every one (2)."""
+        _check("mrlbm_profile", lib().mrlbm_profile(self._ctx, int(enable)))
 
     def counters(self) -> dict:
         c = Counters()

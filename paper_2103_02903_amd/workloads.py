@@ -116,21 +116,49 @@ def random_vortex_d2q9(jmin=3, jmax=8, eps=1e-3, mu_bar=1.0, u0=0.05, s1=1.5, s2
     ks = [(kx, ky) for ky in range(1, kmax + 1) for kx in range(1, kmax + 1)]
     amp = np.array([rng.normal() / (kx * kx + ky * ky) for kx, ky in ks])
     phs = rng.uniform(0.0, 2.0 * np.pi, len(ks))
-    xc = cell_centres(jmax)
-    X, Y = np.meshgrid(xc, xc, indexing="xy")
-    ux = np.zeros_like(X)
-    uy = np.zeros_like(X)
-    for (kx, ky), a, p in zip(ks, amp, phs):
-        c = np.cos(2.0 * np.pi * (kx * X + ky * Y) + p) * 2.0 * np.pi * a
-        ux += c * ky      # d psi / dy
-        uy -= c * kx      # -d psi / dx
-    scale = u0 / max(np.max(np.abs(ux)), np.max(np.abs(uy)))
-    ux *= scale
-    uy *= scale
-    rho = np.ones_like(ux)
-    m0 = np.stack([rho.ravel(), ux.ravel(), uy.ravel()])
     cfg.update(modes=ks, amplitudes=amp.tolist(), phases=phs.tolist(), u0=float(u0))
-    return cfg, np.ascontiguousarray(m0)
+    return cfg, vortex_moments(cfg, amp)
+
+
+def vortex_mode_fields(cfg: dict):
+    """Velocity of each mode of `random_vortex_d2q9` at unit amplitude, before the
+    max-norm scaling: arrays gx, gy of shape [modes][N_J^2] (cell index x + N_J y)."""
+    xc = cell_centres(cfg["jmax"])
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    gx, gy = [], []
+    for (kx, ky), p in zip(cfg["modes"], cfg["phases"]):
+        c = np.cos(2.0 * np.pi * (kx * X + ky * Y) + p) * 2.0 * np.pi
+        gx.append((c * ky).ravel())      # d psi / dy
+        gy.append((-c * kx).ravel())     # -d psi / dx
+    return np.array(gx), np.array(gy)
+
+
+def vortex_moments(cfg: dict, amplitudes) -> np.ndarray:
+    """Initial moments (rho = 1, q = u) of the vortex workload for the given mode
+    amplitudes: u = u0 * g / max(|g_x|_inf, |g_y|_inf), g = sum_k a_k g_k."""
+    gx, gy = vortex_mode_fields(cfg)
+    a = np.asarray(amplitudes, np.float64)
+    ux, uy = a @ gx, a @ gy
+    scale = cfg["u0"] / max(np.max(np.abs(ux)), np.max(np.abs(uy)))
+    m0 = np.stack([np.ones_like(ux), ux * scale, uy * scale])
+    return np.ascontiguousarray(m0)
+
+
+def vortex_amplitude_gradient(cfg: dict, mbar) -> np.ndarray:
+    """dJ/da_k of the 16 mode amplitudes of the vortex workload from dJ/dm0
+    ([3][N_J^2]): the transpose of the input map a -> m0 of vortex_moments,
+    u = u0 g / S with g = sum_k a_k g_k and S the max norm of g over both
+    components, differentiated at the cell that attains it."""
+    gx, gy = vortex_mode_fields(cfg)
+    a = np.asarray(cfg["amplitudes"], np.float64)
+    ux, uy = a @ gx, a @ gy
+    comp, vals = (gx, ux) if np.max(np.abs(ux)) >= np.max(np.abs(uy)) else (gy, uy)
+    j = int(np.argmax(np.abs(vals)))
+    S = abs(vals[j])
+    dS = np.sign(vals[j]) * comp[:, j]
+    s = cfg["u0"] / S
+    mb = np.asarray(mbar, np.float64).reshape(3, -1)
+    return s * (gx @ mb[1] + gy @ mb[2]) - (s / S) * dS * float(mb[1] @ ux + mb[2] @ uy)
 
 
 def random_field(cfg: dict, seed: int, kind: str = "smooth") -> np.ndarray:

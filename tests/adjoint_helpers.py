@@ -38,3 +38,16 @@ def ke_functional(o, tree, values, region=(0.25, 0.75)):
             dm[0] = m[0]
         gl[:, mask] = vol * (M.T @ dm)
     return J, g
+
+
+def final_frozen(o, m0, trees):
+    """Final leaf values of the oracle run from m0 on the mesh sequence trees
+    (trees[0] the full initial mesh), without keeping the intermediate states."""
+    t, v = o.init(m0)
+    assert np.array_equal(t, trees[0])
+    for tn in trees[1:]:
+        o.step_frozen(t, tn, v)
+    return t, v
+
+
+from paper_2103_02903_amd.workloads import vortex_amplitude_gradient  # noqa: E402,F401
