@@ -96,6 +96,28 @@ int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes);
 int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream,
                  mrlbm_ctx **out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same context as
+ * mrlbm_create, with its workspace in a device array of the library itself,
+ * MRLBM_STATIC_WORKSPACE_BYTES (16 MiB) on every GPU the library runs on, held
+ * until the process ends. Enough for a D1Q2 or D1Q3 instance up to level 14 or
+ * a D2Q9 instance up to level 8 in either precision; mrlbm_workspace_size tells
+ * whether a configuration fits. The context runs on the current device; every
+ * kernel of it uses that device's array, so at most one static context may be
+ * alive per device at a time (a second create fails with MRLBM_ERR_STATE until
+ * the first is destroyed; two contexts sharing the array would race). The array
+ * keeps the last context's contents: creation clears what must start at zero,
+ * as mrlbm_create does for a fresh workspace. Neither this call nor any later
+ * call on the context allocates device memory: its steps launch the kernels
+ * one by one (mrlbm_set_tuning with graph = 1 and mrlbm_autotune return
+ * MRLBM_ERR_STATE), and everything else behaves as for mrlbm_create, with
+ * identical results. The adjoint still takes the caller's adjoint workspace.
+ * Errors: MRLBM_ERR_INVALID, MRLBM_ERR_CAPACITY (the workspace would exceed
+ * MRLBM_STATIC_WORKSPACE_BYTES), MRLBM_ERR_STATE (a static context is alive on
+ * this device), MRLBM_ERR_HIP. */
+#define MRLBM_STATIC_WORKSPACE_BYTES (16u << 20)
+int mrlbm_create_static(const mrlbm_params *p, int batch, void *stream, mrlbm_ctx **out);
+
 /* Initial state of Algorithm 1 for one instance: the full finest mesh with
  * f = M^{-1} m_eq(m0) on every finest cell. `moments` is a device buffer in the
  * context precision, layout [nc][N_J^d] (see above). Every instance must be

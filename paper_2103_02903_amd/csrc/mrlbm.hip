@@ -412,6 +412,7 @@ struct mrlbm_ctx {
   // timed graphs keep their source graph and event nodes, whose events are
   // pointed at fresh pool events before each launch.
   bool use_graph;
+  int static_dev;  // device whose static workspace the context uses, or -1 (caller's workspace)
   hipStream_t cap_stream;
   hipGraphExec_t graph[2][4];
   hipGraph_t timed_src[4];
@@ -1211,6 +1212,23 @@ bool bad_instance(const mrlbm_ctx *c, int i) { return !c || i < 0 || i >= c->P.B
 
 // ====================================================================== C-ABI
 
+namespace {
+// Workspace of the contexts made by mrlbm_create_static: one per GPU, held
+// from the library's load on that GPU until the process ends. Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t STATIC_WS_BYTES = (size_t)MRLBM_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex static_mutex;
+void *static_ptr[STATIC_MAX_DEVICES];     // device address of `scratch` on each device (null until looked up)
+bool static_busy[STATIC_MAX_DEVICES];     // a live static context uses that device's array
+
+int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream, int static_dev,
+               mrlbm_ctx **out);
+}  // namespace
+
 extern "C" {
 
 int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes) {
@@ -1223,8 +1241,40 @@ int mrlbm_workspace_size(const mrlbm_params *p, int batch, size_t *bytes) {
   return MRLBM_OK;
 }
 
+
 int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream, mrlbm_ctx **out) {
   if (!out || !workspace) return MRLBM_ERR_INVALID;
+  return create_ctx(p, batch, workspace, ws_bytes, stream, -1, out);
+}
+
+int mrlbm_create_static(const mrlbm_params *p, int batch, void *stream, mrlbm_ctx **out) {
+  if (!out) return MRLBM_ERR_INVALID;
+  *out = nullptr;
+  int rc = validate(p, batch);
+  if (rc) return rc;
+  Plan P;
+  make_plan(p, batch, P);
+  if (P.bytes > STATIC_WS_BYTES) return MRLBM_ERR_CAPACITY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MRLBM_ERR_HIP;
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return MRLBM_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(static_mutex);
+  if (static_busy[dev]) return MRLBM_ERR_STATE;
+  if (!static_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MRLBM_ERR_HIP;
+    static_ptr[dev] = ptr;
+  }
+  rc = create_ctx(p, batch, static_ptr[dev], STATIC_WS_BYTES, stream, dev, out);
+  if (rc == MRLBM_OK) static_busy[dev] = true;
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_bytes, void *stream, int static_dev,
+               mrlbm_ctx **out) {
   *out = nullptr;
   const int rc = validate(p, batch);
   if (rc) return rc;
@@ -1233,7 +1283,11 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->p.assign(p, p + batch);
   make_plan(p, batch, c->P);
   const Plan &P = c->P;
-  if (ws_bytes < P.bytes) { delete c; return MRLBM_ERR_CAPACITY; }
+  c->static_dev = static_dev;
+  if (ws_bytes < P.bytes) {
+    delete c;
+    return MRLBM_ERR_CAPACITY;
+  }
   c->bt.B = P.B;
   c->bt.dim = P.dim;
   c->bt.q = P.q;
@@ -1278,19 +1332,21 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   c->adj_ws = nullptr;
   c->adj_nsteps = 0;
   c->adj_K = 0;
-  c->use_graph = true;
+  c->use_graph = static_dev < 0;  // a static context creates no capture stream: kernels launched one by one
   c->cap_stream = nullptr;
   for (auto &row : c->graph)
     for (auto &g : row) g = nullptr;
   for (auto &g : c->timed_src) g = nullptr;
   c->ev_placeholder = nullptr;
-  if (hipEventCreate(&c->ev_placeholder) != hipSuccess) {
-    delete c;
-    return MRLBM_ERR_HIP;
-  }
-  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    (void)mrlbm_destroy(c);
-    return MRLBM_ERR_HIP;
+  if (static_dev < 0) {
+    if (hipEventCreate(&c->ev_placeholder) != hipSuccess) {
+      delete c;
+      return MRLBM_ERR_HIP;
+    }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)mrlbm_destroy(c);
+      return MRLBM_ERR_HIP;
+    }
   }
   c->transport_variant = 0;
   c->grid_all = LIST_GRID_ALL;
@@ -1339,12 +1395,16 @@ int mrlbm_create(const mrlbm_params *p, int batch, void *workspace, size_t ws_by
   // depends only on the sequence of calls.
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->F[k], 0, P.rs * P.q * P.ctotal);
   if (e != hipSuccess || dispatch<UploadOp>(c) != MRLBM_OK) {
+    c->static_dev = -1;  // the caller of a static create still holds the array's lock and flag
     (void)mrlbm_destroy(c);
     return MRLBM_ERR_HIP;
   }
   *out = c;
   return MRLBM_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int mrlbm_init_equilibrium(mrlbm_ctx *c, int instance, const void *moments) {
   if (bad_instance(c, instance) || !moments) return MRLBM_ERR_INVALID;
@@ -1607,6 +1667,7 @@ int apply_tuning(mrlbm_ctx *c, const mrlbm_tuning &t) {
   if ((t.transport_variant != 1 && t.transport_variant != 2) || t.list_grid_all < 8 || t.list_grid_all > 65536 ||
       t.list_grid_level < 8 || t.list_grid_level > 65536 || (t.graph != 0 && t.graph != 1))
     return MRLBM_ERR_INVALID;
+  if (t.graph == 1 && !c->cap_stream) return MRLBM_ERR_STATE;  // static context: no capture stream
   if (c->transport_variant != t.transport_variant || c->grid_all != (unsigned)t.list_grid_all ||
       c->grid_level != (unsigned)t.list_grid_level || c->use_graph != (t.graph == 1)) {
     (void)hipStreamSynchronize(c->stream);
@@ -1714,6 +1775,10 @@ int mrlbm_destroy(mrlbm_ctx *c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev_placeholder) (void)hipEventDestroy(c->ev_placeholder);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(static_mutex);
+    static_busy[c->static_dev] = false;
+  }
   delete c;
   return MRLBM_OK;
 }

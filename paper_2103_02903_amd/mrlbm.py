@@ -25,7 +25,7 @@ EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mr
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
            "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
            "mrlbm_adjoint", "mrlbm_copy", "mrlbm_autotune", "mrlbm_set_tuning", "mrlbm_get_tuning",
-           "mrlbm_fields", "mrlbm_get_mesh", "mrlbm_step_frozen", "mrlbm_debug_pair_wait"]
+           "mrlbm_fields", "mrlbm_get_mesh", "mrlbm_step_frozen", "mrlbm_debug_pair_wait", "mrlbm_create_static"]
 
 
 class MrlbmError(RuntimeError):
@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "mrlbm_workspace_size": [P, ci, ctypes.POINTER(ctypes.c_size_t)],
             "mrlbm_create": [P, ci, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+            "mrlbm_create_static": [P, ci, vp, ctypes.POINTER(vp)],
             "mrlbm_init_equilibrium": [vp, ci, vp], "mrlbm_adapt": [vp], "mrlbm_transport_collide": [vp],
             "mrlbm_step": [vp, ci], "mrlbm_get_state": [vp, ci, vp, vp], "mrlbm_set_state": [vp, ci, vp, vp],
             "mrlbm_sizes": [vp, ci, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
@@ -132,7 +133,7 @@ class Batch:
     ``cfgs`` are parameter dictionaries of ``workloads`` sharing the scheme and
     jmin; ``precision`` is 8 (FP64) or 4 (FP32)."""
 
-    def __init__(self, cfgs, precision: int = 8, device: str = "cuda:0"):
+    def __init__(self, cfgs, precision: int = 8, device: str = "cuda:0", static: bool = False):
         import torch
 
         self.torch = torch
@@ -148,13 +149,18 @@ class Batch:
         nbytes = ctypes.c_size_t(0)
         _check("mrlbm_workspace_size", L.mrlbm_workspace_size(self._p, self.B, ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
-        with torch.cuda.device(self.device):
-            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p(0)
-        _check("mrlbm_create", L.mrlbm_create(self._p, self.B, ctypes.c_void_p(self.workspace.data_ptr()),
-                                              self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream),
-                                              ctypes.byref(ctx)))
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            if static:  # the library's own per-device workspace (mrlbm_create_static)
+                self.workspace = None
+                _check("mrlbm_create_static", L.mrlbm_create_static(
+                    self._p, self.B, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+            else:
+                self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+                _check("mrlbm_create", L.mrlbm_create(self._p, self.B, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                      self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                                      ctypes.byref(ctx)))
         self._ctx = ctx
         self.total_cells = []
         for i in range(self.B):
@@ -339,8 +345,8 @@ class Batch:
 class Sim(Batch):
     """A single MR-LBM instance (a batch of one)."""
 
-    def __init__(self, cfg: dict, precision: int = 8, device: str = "cuda:0"):
-        super().__init__([cfg], precision, device)
+    def __init__(self, cfg: dict, precision: int = 8, device: str = "cuda:0", static: bool = False):
+        super().__init__([cfg], precision, device, static)
         self.cfg = self.cfgs[0]
         self.jmin, self.jmax = int(cfg["jmin"]), int(cfg["jmax"])
 
