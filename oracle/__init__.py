@@ -46,7 +46,8 @@ class _Params(ctypes.Structure):
                 ("jmin", ctypes.c_int), ("jmax", ctypes.c_int), ("pad_", ctypes.c_int),
                 ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double),
-                ("s", ctypes.c_double * 9)]
+                ("s", ctypes.c_double * 9), ("bc", ctypes.c_int * 4), ("bc_eval", ctypes.c_int),
+                ("pad2_", ctypes.c_int)]
 
 
 _lib = None
@@ -108,9 +109,11 @@ class Oracle:
     def __init__(self, cfg: dict):
         scheme_id, dim, q = SCHEMES[cfg["scheme"]]
         s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        bc = [int(v) for v in cfg.get("bc", (0, 0, 0, 0))]
         self.p = _Params(dim, q, scheme_id, int(cfg["jmin"]), int(cfg["jmax"]), 0,
                          float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)),
-                         float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s))
+                         float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s),
+                         (ctypes.c_int * 4)(*bc), int(cfg.get("bc_eval", 0)), 0)
         self.dim, self.q, self.jmin, self.jmax = dim, q, int(cfg["jmin"]), int(cfg["jmax"])
         self.L = lib()
         self.total = int(self.L.orc_total_cells(ctypes.byref(self.p)))

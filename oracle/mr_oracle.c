@@ -25,7 +25,18 @@
  *  - Collision is written m + S (m_eq - m), equal to (I - S) m + S m_eq.
  *  - D2Q9: diagonal logical velocities are (+-1, +-1) as the rows of M imply;
  *    the equilibrium uses |q|^2 and c_s^4 rho where the printed text is garbled.
- *  - All index arithmetic is periodic.
+ *  - Boundaries (section "Boundary conditions"): an axis is periodic, or has a
+ *    wall at both ends. At a wall the prediction, the details and the
+ *    reconstruction see each level extended by even reflection across the wall
+ *    (the paper does not say how its stencils are completed there; reflection
+ *    commutes with the symmetric prediction stencil, so the reconstruction of
+ *    a level is that of the mirrored periodic problem). The set operations of
+ *    the mesh (neighbour addition, grading box) ignore cells beyond a wall. In
+ *    the transport, a finest cell of E beyond a wall takes the side's
+ *    condition (copy, bounce back, anti bounce back, eq. refBoundaryConditions)
+ *    evaluated either on the leaf itself or on the reconstruction, as eq.
+ *    AdvectionOnBoundary allows; a cell beyond two walls (a corner) takes the
+ *    condition of the x wall.
  */
 #include "mr_oracle.h"
 
@@ -49,6 +60,24 @@ static int side(int l) { return 1 << l; }
 static int64_t ncells(const orc_params *P, int l) { return (int64_t)1 << (P->dim * l); }
 static int wrapi(int i, int n) { i %= n; return i < 0 ? i + n : i; }
 
+/* Walls: axis a (0 = x, 1 = y) has walls when either of its sides is not periodic. */
+static int wall_axis(const orc_params *P, int a) { return P->bc[2 * a] != 0 || P->bc[2 * a + 1] != 0; }
+static int has_walls(const orc_params *P) { return wall_axis(P, 0) || (P->dim == 2 && wall_axis(P, 1)); }
+/* Index i (|overflow| < n) along axis a for the MR operators: periodic wrap, or
+ * even reflection across a wall (cell -1 is cell 0, cell n is cell n-1). */
+static int mr_axis(const orc_params *P, int a, int i, int n) {
+  if (!wall_axis(P, a)) return wrapi(i, n);
+  return i < 0 ? -1 - i : i >= n ? 2 * n - 1 - i : i;
+}
+/* Side of the domain beyond which index (x, y) of level l lies (0 x-, 1 x+,
+ * 2 y-, 3 y+; x first), or -1 if inside or only beyond periodic sides. */
+static int beyond_wall(const orc_params *P, int l, int x, int y) {
+  const int n = 1 << l;
+  if (wall_axis(P, 0) && (x < 0 || x >= n)) return x < 0 ? 0 : 1;
+  if (P->dim == 2 && wall_axis(P, 1) && (y < 0 || y >= n)) return y < 0 ? 2 : 3;
+  return -1;
+}
+
 int64_t orc_level_offset(const orc_params *P, int l) {
   int64_t off = 0;
   for (int m = P->jmin; m < l; ++m) off += ncells(P, m);
@@ -69,6 +98,16 @@ static int64_t cell_index(const orc_params *P, int l, int x, int y) {
 static int64_t cell_index_wrapped(const orc_params *P, int l, int x, int y) {
   int n = side(l);
   return P->dim == 1 ? wrapi(x, n) : (int64_t)wrapi(x, n) + (int64_t)n * wrapi(y, n);
+}
+/* Cell (x, y) of level l as the MR operators read it (wrap or reflection). */
+static int64_t cell_index_mr(const orc_params *P, int l, int x, int y) {
+  int n = side(l);
+  return P->dim == 1 ? mr_axis(P, 0, x, n) : (int64_t)mr_axis(P, 0, x, n) + (int64_t)n * mr_axis(P, 1, y, n);
+}
+/* Cell (x, y) of level l for the set operations: wrapped on periodic axes, -1
+ * beyond a wall. */
+static int64_t cell_index_set(const orc_params *P, int l, int x, int y) {
+  return beyond_wall(P, l, x, y) >= 0 ? -1 : cell_index_wrapped(P, l, x, y);
 }
 static void cell_coords(const orc_params *P, int l, int64_t c, int *x, int *y) {
   if (P->dim == 1) { *x = (int)c; *y = 0; }
@@ -219,12 +258,12 @@ double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy)
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
   if (P->dim == 1) {
-    const double Q = C1 * (Fp[wrapi(px + 1, n)] - Fp[wrapi(px - 1, n)]);
+    const double Q = C1 * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
     return Fp[px] + sx * Q;
   }
   const int py = cy >> 1;
   const double sy = (cy & 1) ? -1.0 : 1.0;
-#define AT(a, b) Fp[(int64_t)wrapi((a), n) + (int64_t)n * wrapi((b), n)]
+#define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
   const double Qx = C1 * (AT(px + 1, py) - AT(px - 1, py));
   const double Qy = C1 * (AT(px, py + 1) - AT(px, py - 1));
   const double Qxy =
@@ -374,8 +413,10 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
       int x, y;
       cell_coords(P, l, c, &x, &y);
       tn[c] = 1;
-      for (int h = 0; h < P->q; ++h)
-        tn[cell_index_wrapped(P, l, x - eta[2 * h], y - eta[2 * h + 1])] = 1;
+      for (int h = 0; h < P->q; ++h) {
+        const int64_t nb = cell_index_set(P, l, x - eta[2 * h], y - eta[2 * h + 1]);
+        if (nb >= 0) tn[nb] = 1;
+      }
       if (l > jmin && l < J) {
         const double Dg = D[orc_level_offset(P, l - 1) + cell_index(P, l - 1, x >> 1, y >> 1)];
         if (Dg >= refine_thr) mark_group(P, tree_at(P, tnew, l + 1), l + 1, x, y);
@@ -397,7 +438,10 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
       cell_coords(P, l, c, &x, &y);
       const int px = x >> 1, py = y >> 1;
       for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
-        for (int ax = -1; ax <= 1; ++ax) tp[cell_index_wrapped(P, l - 1, px + ax, py + ay)] = 1;
+        for (int ax = -1; ax <= 1; ++ax) {
+          const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
+          if (nb >= 0) tp[nb] = 1;
+        }
     }
   }
   memset(tree_at(P, tnew, jmin), 1, (size_t)ncells(P, jmin));
@@ -422,11 +466,44 @@ int orc_transfer(const orc_params *P, const uint8_t *told, const double *vold, c
 /* ---- MR transport (eq. AdaptiveAdvectionPhase with the sets E and A built
  *      from the cell splitting B, eq. CellSplitting) ---- */
 
+/* Index of the velocity opposite to h (eta^{h+} = -eta^h). */
+static int opposite(const orc_params *P, const int *eta, int h) {
+  for (int k = 0; k < P->q; ++k)
+    if (eta[2 * k] == -eta[2 * h] && eta[2 * k + 1] == -eta[2 * h + 1]) return k;
+  return h;
+}
+
+/* Boundary sides valid: each 0..3; an axis periodic on both sides or walled on
+ * both; 1D has no y sides; the reconstruction evaluation flag is 0 or 1. */
+static int bad_bc(const orc_params *P) {
+  for (int k = 0; k < 4; ++k)
+    if (P->bc[k] < 0 || P->bc[k] > 3) return 1;
+  for (int a = 0; a < 2; ++a)
+    if ((P->bc[2 * a] == 0) != (P->bc[2 * a + 1] == 0)) return 1;
+  if (P->dim == 1 && (P->bc[2] || P->bc[3])) return 1;
+  return P->bc_eval != 0 && P->bc_eval != 1;
+}
+
+/* Population h entering the domain from the finest cell beyond wall `side`
+ * whose image under eta^h is the finest cell (ix, iy) of the leaf (l, c), eq.
+ * AdvectionOnBoundary with eq. refBoundaryConditions: the side's condition on
+ * population h (copy) or on its opposite hd (bounce back; anti bounce back with
+ * the sign changed), evaluated on the leaf (bc_eval 0) or on the
+ * reconstruction at (ix, iy) (bc_eval 1). */
+static double wall_value(const orc_params *P, const double *vs, int side, int h, int hd, int l, int64_t c, int ix,
+                         int iy) {
+  const int kind = P->bc[side];
+  const int g = kind == 1 ? h : hd;
+  const double v = P->bc_eval ? val_at(P, vs, P->jmax, g)[cell_index(P, P->jmax, ix, iy)] : val_at(P, vs, l, g)[c];
+  return kind == 3 ? -v : v;
+}
+
 int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, double *out,
                   int definition_form) {
   const int J = P->jmax, d = P->dim;
   int eta[2 * MAXQ];
   orc_velocities(P, eta);
+  if (bad_bc(P)) return -1;
   for (int l = P->jmin; l <= J; ++l) {
     const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
 #pragma omp parallel for schedule(dynamic, 256)
@@ -436,27 +513,33 @@ int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, do
       cell_coords(P, l, c, &x, &y);
       const int bx0 = x * w, by0 = y * wy; /* B = [bx0, bx0+w) x [by0, by0+wy) */
       for (int h = 0; h < P->q; ++h) {
-        const int ex = eta[2 * h], ey = eta[2 * h + 1];
+        const int ex = eta[2 * h], ey = eta[2 * h + 1], hd = opposite(P, eta, h);
         const double *FJ = val_at(P, vs, J, h);
         const double fl = val_at(P, vs, l, h)[c];
         double res;
         if (ex == 0 && ey == 0) {
           res = fl;
         } else if (n == 0) {
-          res = FJ[cell_index_wrapped(P, J, x - ex, y - ey)];
+          const int sd = beyond_wall(P, J, x - ex, y - ey);
+          res = sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, x, y) : FJ[cell_index_wrapped(P, J, x - ex, y - ey)];
         } else if (definition_form) {
           double s = 0.0;
           for (int ky = by0; ky < by0 + wy; ++ky)
-            for (int kx = bx0; kx < bx0 + w; ++kx) s += FJ[cell_index_wrapped(P, J, kx - ex, ky - ey)];
+            for (int kx = bx0; kx < bx0 + w; ++kx) {
+              const int sd = beyond_wall(P, J, kx - ex, ky - ey);
+              s += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky) : FJ[cell_index_wrapped(P, J, kx - ex, ky - ey)];
+            }
           res = ldexp(s, -d * n);
         } else {
           double sE = 0.0, sA = 0.0;
           for (int ky = by0; ky < by0 + wy; ++ky)
             for (int kx = bx0; kx < bx0 + w; ++kx) {
-              /* E = (B - eta) \ B: the cell k - eta, if it left B */
+              /* E = (B - eta) \ B: the cell k - eta, if it left B (beyond a wall: the condition) */
               const int jx = kx - ex, jy = ky - ey;
-              if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy))
-                sE += FJ[cell_index_wrapped(P, J, jx, jy)];
+              if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy)) {
+                const int sd = beyond_wall(P, J, jx, jy);
+                sE += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky) : FJ[cell_index_wrapped(P, J, jx, jy)];
+              }
             }
           for (int ky = by0; ky < by0 + wy; ++ky)
             for (int kx = bx0; kx < bx0 + w; ++kx) {
@@ -513,6 +596,7 @@ int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *value
 }
 
 int orc_step(const orc_params *P, uint8_t *tree, double *values) {
+  if (bad_bc(P)) return -1;
   const int64_t total = orc_total_cells(P);
   double *D = malloc(sizeof(double) * (size_t)total);
   double *vnew = calloc((size_t)(P->q * total), sizeof(double));
@@ -547,13 +631,20 @@ int orc_uniform_step(const orc_params *P, double *fJ) {
   orc_velocities(P, eta);
   orc_moment_matrix(P, M);
   if (orc_moment_matrix_inverse(P, Minv)) return -1;
+  if (bad_bc(P)) return -1;
   double *g = malloc(sizeof(double) * (size_t)(q * NJ));
   if (!g) return -1;
   for (int h = 0; h < q; ++h)
     for (int64_t c = 0; c < NJ; ++c) {
       int x, y;
       cell_coords(P, J, c, &x, &y);
-      g[h * NJ + c] = fJ[h * NJ + cell_index_wrapped(P, J, x - eta[2 * h], y - eta[2 * h + 1])];
+      const int sd = beyond_wall(P, J, x - eta[2 * h], y - eta[2 * h + 1]);
+      if (sd < 0) {
+        g[h * NJ + c] = fJ[h * NJ + cell_index_wrapped(P, J, x - eta[2 * h], y - eta[2 * h + 1])];
+      } else {  /* the boundary cell's own value of h (copy) or of its opposite */
+        const int kind = P->bc[sd], src = kind == 1 ? h : opposite(P, eta, h);
+        g[h * NJ + c] = kind == 3 ? -fJ[src * NJ + c] : fJ[src * NJ + c];
+      }
     }
   for (int64_t c = 0; c < NJ; ++c) {
     for (int h = 0; h < q; ++h) f[h] = g[h * NJ + c];
@@ -603,8 +694,10 @@ int orc_check_tree(const orc_params *P, const uint8_t *tree) {
       if (cnt && !tp[p]) bad |= 4;
       if (cnt)
         for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
-          for (int ax = -1; ax <= 1; ++ax)
-            if (!tp[cell_index_wrapped(P, l - 1, px + ax, py + ay)]) bad |= 8;
+          for (int ax = -1; ax <= 1; ++ax) {
+            const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
+            if (nb >= 0 && !tp[nb]) bad |= 8;
+          }
     }
   }
   return bad;
@@ -624,12 +717,12 @@ static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, in
   const float sx = (cx & 1) ? -1.0f : 1.0f;
   const float c1 = -0.125f;
   if (P->dim == 1) {
-    const float Q = c1 * (Fp[wrapi(px + 1, n)] - Fp[wrapi(px - 1, n)]);
+    const float Q = c1 * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
     return Fp[px] + sx * Q;
   }
   const int py = cy >> 1;
   const float sy = (cy & 1) ? -1.0f : 1.0f;
-#define AT(a, b) Fp[(int64_t)wrapi((a), n) + (int64_t)n * wrapi((b), n)]
+#define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
   const float Qx = c1 * (AT(px + 1, py) - AT(px - 1, py));
   const float Qy = c1 * (AT(px, py + 1) - AT(px, py - 1));
   const float Qxy =
@@ -704,6 +797,7 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
  * `tnew`, which must be a graded complete tree whose cells all have their
  * parent in `tree`): transfer, transport, collide. */
 int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, double *values) {
+  if (bad_bc(P)) return -1;
   const int64_t total = orc_total_cells(P);
   double *vnew = calloc((size_t)(P->q * total), sizeof(double));
   if (!vnew) return -1;
@@ -725,6 +819,7 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
  * (indices into level l-1) and weights such that the prediction equals
  * sum_k w[k] F[idx[k]]. Returns the number of terms (3 in 1D, 9 in 2D). */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w) {
+  if (has_walls(P)) return -1;
   const int n = side(l - 1);
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
@@ -754,6 +849,7 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
 /* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
  * the leaf entries hold the adjoint of the leaf values and all others are 0. */
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
+  if (has_walls(P)) return -1;
   const double inv = 1.0 / nchildren(P);
   /* Each population is its own linear map: the populations run in parallel,
    * each with the loop order below. */
@@ -790,6 +886,7 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
 /* Transpose of orc_transport (E/A form): adds into the dense `gs` the adjoint of
  * the reconstruction F* from the leaf adjoints `ob` of the transported values. */
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs) {
+  if (has_walls(P)) return -1;
   const int J = P->jmax, d = P->dim;
   int eta[2 * MAXQ];
   orc_velocities(P, eta);
@@ -972,6 +1069,7 @@ static int step_precollision(const orc_params *P, const uint8_t *told, const uin
  * adds d/ds into sbar. */
 int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
                      const double *anew, double *aold, double *sbar) {
+  if (has_walls(P)) return -1;
   const int64_t total = orc_total_cells(P), n = P->q * total;
   double *h = calloc((size_t)n, sizeof(double)), *hb = calloc((size_t)n, sizeof(double));
   double *gs = calloc((size_t)n, sizeof(double));

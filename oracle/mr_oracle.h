@@ -38,6 +38,15 @@ typedef struct {
   double eps;      /* threshold epsilon >= 0 */
   double mu_bar;   /* regularity guess in [0, 2*gamma+1] */
   double s[9];     /* relaxation rate of each moment (0 for conserved moments) */
+  /* Boundary of each side (section "Boundary conditions"), order x-, x+, y-, y+:
+   * 0 periodic, 1 copy, 2 bounce back, 3 anti bounce back (eq. refBoundaryConditions).
+   * An axis is periodic when both of its sides are 0, else both must be walls;
+   * 1D uses x only. */
+  int bc[4];
+  /* Evaluation of the incoming values at a wall (eq. AdvectionOnBoundary):
+   * 0 directly on the leaf (the paper's choice), 1 by the reconstruction. */
+  int bc_eval;
+  int pad2_;
 } orc_params;
 
 /* Number of cells summed over levels jmin..J, and the offset of level l. */
@@ -88,7 +97,8 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
 int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, double *values);
 
 /* Adjoint on frozen meshes (transposes of the step's linear maps and of the
- * linearised collision; each adds into its output in a fixed order). */
+ * linearised collision; each adds into its output in a fixed order). Periodic
+ * boundaries only: with a wall they return -1. */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w);
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g);
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs);
@@ -100,7 +110,9 @@ int orc_init_T(const orc_params *P, const double *m0, const double *abar, double
 int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
                      const double *anew, double *aold, double *sbar);
 
-/* Uniform reference scheme on level J only: values layout [h][N_J^d]. */
+/* Uniform reference scheme on level J only: values layout [h][N_J^d]; at a wall
+ * the incoming population of a boundary cell is set from that cell by the
+ * side's condition (eq. refBoundaryConditions). */
 int orc_uniform_step(const orc_params *P, double *fJ);
 
 /* Moment matrix M and its inverse (q*q, row-major), and equilibrium moments. */

@@ -9,7 +9,10 @@ Parameter dictionary keys:
   scheme   "D1Q2" | "D1Q3" | "D2Q9"
   jmin, jmax, eps, mu_bar, lam (lattice velocity), eq_param (V or alpha),
   s        relaxation rate of every moment (0 for conserved moments)
-  domain   (lo, hi) of the periodic box along each axis
+  domain   (lo, hi) of the box along each axis
+  bc       boundary of each side x-, x+, y-, y+ (BC_KINDS codes; default all
+           periodic); bc_eval 0 / 1: wall values taken on the leaf / on the
+           reconstruction (section "Boundary conditions")
 Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D) or 3 (rho, q_x, q_y),
 cell index x + N_J * y.
 """
@@ -20,14 +23,23 @@ import numpy as np
 SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3)}  # dim, q, conserved
 
 
+BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
+
+
 def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0, lam: float = 1.0,
-           eq_param: float = 0.0, domain=(0.0, 1.0)) -> dict:
+           eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0) -> dict:
+    """Parameter dictionary. ``bc``: None (periodic) or the kind of each side
+    x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two)."""
     dim, q, _ = SCHEME_DIMS[scheme]
     s = [float(v) for v in s]
     assert len(s) == q
+    codes = [0, 0, 0, 0]
+    if bc is not None:
+        for k, v in enumerate(bc):
+            codes[k] = BC_KINDS[v] if isinstance(v, str) else int(v)
     return dict(scheme=scheme, dim=dim, q=q, jmin=int(jmin), jmax=int(jmax), eps=float(eps),
                 mu_bar=float(mu_bar), lam=float(lam), eq_param=float(eq_param), s=s,
-                domain=tuple(domain))
+                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval))
 
 
 def cell_centres(jmax: int, domain=(0.0, 1.0)) -> np.ndarray:

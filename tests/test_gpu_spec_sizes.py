@@ -1,0 +1,188 @@
+"""The workloads at their specified sizes and step counts, against the oracle.
+
+* D2Q9 double shear layer, levels 3..10 (1024^2 finest), 5000 steps in FP64 and
+  in FP32: every 500 steps one step is replayed on the oracle from the GPU
+  state (FP64: the oracle's own step; FP32: the oracle's float mesh decision,
+  then its FP64 step from the upcast state). Meshes bit for bit; fields to
+  1e-12 (FP64) or 1e-5 (FP32) relative.
+* D1Q3 Burgers, levels 2..14, 4000 steps: the GPU runs (FP32 and FP64) against
+  the oracle's own free-running FP64 trajectory, per field (u, m1, m2) of the
+  finest-level reconstruction, each run deciding its own meshes.
+* Adjoint workload, D2Q9 levels 3..8, 800 steps, checkpoint every 50: the GPU
+  gradient of the kinetic energy in [3/8,5/8]^2 (FP32 and FP64) against the
+  oracle's frozen-mesh gradient on the GPU's own mesh sequence, for the
+  initial moments, the shear relaxation rate s2 and the 16 mode amplitudes;
+  the FP64 gradient also against central differences (h = 1e-6) of FP64 runs
+  replaying the same meshes (mrlbm_step_frozen), along three seeded
+  directions and along s2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from adjoint_helpers import ke_functional
+from paper_2103_02903_amd import workloads as W
+
+from test_gpu_parity import TOL64, leaf_err
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+REGION = (0.375, 0.625)
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_02903_amd import mrlbm
+
+    mrlbm.lib()
+    return mrlbm
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_shear_1024_5000_steps(mr, precision):
+    cfg, m0 = W.shear_layer_d2q9()
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.step(20)
+    sim.autotune(reps=2)
+    done, worst = 20, 0.0
+    while done < 5000:
+        sim.step(499 if done > 20 else 479)
+        done += 499 if done > 20 else 479
+        tg, vg = sim.get_state()
+        t_o, v_o = tg.copy(), vg.astype(np.float64)
+        if precision == 8:
+            o.step(t_o, v_o)
+        else:
+            o.step_frozen(t_o, o.new_tree_f32(tg, vg), v_o)
+        sim.step(1)
+        done += 1
+        tg2, vg2 = sim.get_state()
+        assert np.array_equal(tg2, t_o), "mesh differs at step %d" % done
+        e = leaf_err(o, t_o, vg2, v_o)
+        worst = max(worst, e)
+        print("fp%d step %d leaves %d replay error %.3e" % (8 * precision, done, int(o.leaf_counts(t_o).sum()), e),
+              flush=True)
+        assert e <= (TOL64 if precision == 8 else TOL32), "field error %g at step %d" % (e, done)
+    assert done == 5000
+    st = sim.stats()
+    mass0 = o.mass(*o.init(m0))
+    drift = abs(st["mass"] - mass0) / mass0
+    print("fp%d worst replay error %.3e, relative mass drift over 5000 steps %.3e" % (8 * precision, worst, drift))
+    # round-off of the per-step sums: about 3e-16 per step measured in FP64
+    assert drift <= (1e-11 if precision == 8 else 1e-4)
+    sim.close()
+
+
+def _finest_moments(o, tree, values):
+    f = o.finest(tree, values.astype(np.float64)).reshape(o.q, -1)
+    return o.moment_matrix() @ f
+
+
+def test_burgers_16384_4000_steps_vs_oracle_run(mr):
+    cfg, m0 = W.burgers_d1q3()
+    o = oracle.Oracle(cfg)
+    t_o, v_o = o.init(m0)
+    o.step(t_o, v_o, 4000)
+    ref = _finest_moments(o, t_o, v_o)
+    bounds = {8: (1e-6, 1e-4), 4: (1e-3, 1e-2)}
+    for precision in (8, 4):
+        sim = mr.Sim(cfg, precision=precision)
+        sim.init_equilibrium(m0)
+        sim.step(4000)
+        tg, vg = sim.get_state()
+        got = _finest_moments(o, tg, vg)
+        for k, name in enumerate(("u", "m1", "m2")):
+            d = np.abs(got[k] - ref[k])
+            l1, linf = float(d.sum() / np.abs(ref[k]).sum()), float(d.max())
+            print("fp%d %s: l1-rel %.3e linf %.3e (leaves gpu %d oracle %d)" % (
+                8 * precision, name, l1, linf, int(o.leaf_counts(tg).sum()), int(o.leaf_counts(t_o).sum())),
+                flush=True)
+            assert l1 <= bounds[precision][0] and linf <= bounds[precision][1], (precision, name, l1, linf)
+        sim.close()
+
+
+def _mesh_sequence(mr, cfg, m0, nsteps, precision):
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    trees = [sim.get_mesh()]
+    for _ in range(nsteps):
+        sim.step(1)
+        trees.append(sim.get_mesh())
+    sim.close()
+    return trees
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) / float(np.max(np.abs(b)))
+
+
+def _frozen_J(mr, o, cfg, m0, trees):
+    """J of an FP64 GPU run from m0 that replays the mesh sequence trees[1:]."""
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    for t in trees[1:]:
+        sim.step_frozen(t)
+    tg, vg = sim.get_state()
+    sim.close()
+    assert np.array_equal(tg, trees[-1])
+    return ke_functional(o, tg, vg, REGION)[0]
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_vortex_256_adjoint_800_steps(mr, precision):
+    import torch
+
+    cfg, m0 = W.random_vortex_d2q9()
+    nsteps, K = 800, 50
+    o = oracle.Oracle(cfg)
+    trees = _mesh_sequence(mr, cfg, m0, nsteps, precision)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.forward_record(nsteps, K)
+    t_fin, v_fin = sim.get_state()
+    assert np.array_equal(t_fin, trees[-1])
+    Jval, abar = ke_functional(o, t_fin, v_fin.astype(np.float64), REGION)
+    mbar_g, sbar_g = sim.adjoint(torch.from_numpy(abar).to(sim.device))
+    sim.close()
+    mbar_g = mbar_g.double().cpu().numpy()
+    mbar_o, sbar_o = o.gradient_frozen(m0, trees, abar)
+    da_g = W.vortex_amplitude_gradient(cfg, mbar_g)
+    da_o = W.vortex_amplitude_gradient(cfg, mbar_o)
+    ds2_g, ds2_o = sbar_g[7] + sbar_g[8], sbar_o[7] + sbar_o[8]
+    r_m, r_s, r_a = _rel(mbar_g, mbar_o), abs(ds2_g - ds2_o) / abs(ds2_o), _rel(da_g, da_o)
+    print("fp%d J %.10f leaves %d; dJ/dm0 rel %.3e, dJ/ds2 %.10f vs %.10f (rel %.3e), dJ/da rel %.3e" % (
+        8 * precision, Jval, int(o.leaf_counts(t_fin).sum()), r_m, ds2_g, ds2_o, r_s, r_a), flush=True)
+    print("dJ/da (oracle):", np.array2string(da_o, precision=8, max_line_width=200), flush=True)
+    tol = 1e-9 if precision == 8 else 1e-3
+    assert r_m <= tol and r_s <= tol and r_a <= tol
+    if precision != 8:
+        return
+    # central differences of FP64 GPU runs on the same meshes
+    rng = np.random.default_rng(2103)
+    h = 1e-6
+    for k in range(3):
+        amp = rng.normal(size=len(cfg["amplitudes"]))
+        dm = W.vortex_moments(cfg, np.asarray(cfg["amplitudes"]) + amp) - m0  # a smooth direction
+        Jp = _frozen_J(mr, o, cfg, m0 + h * dm, trees)
+        Jm = _frozen_J(mr, o, cfg, m0 - h * dm, trees)
+        fd, ad = (Jp - Jm) / (2 * h), float(np.sum(mbar_g * dm))
+        print("direction %d: central difference %.10e adjoint %.10e rel %.3e" % (k, fd, ad, abs(fd - ad) / abs(fd)),
+              flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
+    s2 = cfg["s"][7]
+    Js = []
+    for sgn in (1, -1):
+        c = dict(cfg)
+        c["s"] = list(cfg["s"])
+        c["s"][7] = c["s"][8] = s2 + sgn * h
+        Js.append(_frozen_J(mr, o, c, m0, trees))
+    fd = (Js[0] - Js[1]) / (2 * h)
+    print("s2: central difference %.10e adjoint %.10e rel %.3e" % (fd, ds2_g, abs(fd - ds2_g) / abs(fd)), flush=True)
+    assert abs(fd - ds2_g) <= 1e-5 * abs(fd)
