@@ -13,11 +13,12 @@
  *      the detail correction next to finer neighbours (section "A non-recursive
  *      implementation of the reconstruction operator");
  *   3. the collision of eq. (AdaptiveCollision) on the same leaf.
- * Boundary conditions are periodic; the prediction stencil half-width is gamma = 1.
+ * Each axis is periodic or bounded by walls (section "Boundary conditions"); the
+ * prediction stencil half-width is gamma = 1.
  *
  * Data layout (shared by every host<->device exchange below):
  *   levels l = jmin..jmax are concatenated; level l holds N_l^d cells, N_l = 2^l,
- *   cell index c = x (1D) or x + N_l * y (2D), periodic in every axis;
+ *   cell index c = x (1D) or x + N_l * y (2D);
  *   tree    uint8  [level][cell]      1 = the cell belongs to the complete tree;
  *   values  real   [level][h][cell]   real = double (precision 8) or float (4);
  *                                     only complete leaves carry meaningful data.
@@ -74,7 +75,23 @@ typedef struct {
   double eps;      /* threshold epsilon >= 0 of eq. (Thresholding) */
   double mu_bar;   /* regularity guess in [0, 3] of the refinement rule */
   double s[9];     /* relaxation rate of each moment; conserved moments must be 0 */
+  /* Boundary of each side x-, x+, y-, y+ (section "Boundary conditions"):
+   * MRLBM_PERIODIC, or a wall with the condition of eq. refBoundaryConditions
+   * (MRLBM_COPY, MRLBM_BOUNCE_BACK, MRLBM_ANTI_BOUNCE_BACK). An axis is
+   * periodic on both sides or walled on both; 1D uses the x sides only. At a
+   * wall, the finest cells of the transport sets E beyond it take the side's
+   * condition evaluated directly on the leaf (eq. AdvectionOnBoundary, the
+   * paper's choice); a cell beyond two walls takes the x wall's condition. The
+   * prediction, the details and the reconstruction extend each level by even
+   * reflection across a wall, and the mesh's neighbour additions and grading
+   * boxes stop at it. The adjoint accepts periodic contexts only. */
+  int bc[4];
 } mrlbm_params;
+
+#define MRLBM_PERIODIC 0
+#define MRLBM_COPY 1
+#define MRLBM_BOUNCE_BACK 2
+#define MRLBM_ANTI_BOUNCE_BACK 3
 
 /* A context runs a batch of `batch` independent instances (1 <= batch <= 256),
  * p[0..batch-1], that share the scheme, the precision and jmin; jmax, eps,
@@ -174,7 +191,7 @@ int mrlbm_get_state(mrlbm_ctx *ctx, int instance, uint8_t *tree, void *values);
 
 /* Replace the current state by a host-side tree (must be a graded complete
  * tree: level jmin full, sibling groups complete, every tree cell's prediction
- * stencil in the tree) and leaf values. Synchronous.
+ * stencil in the tree, up to the walls) and leaf values. Synchronous.
  * Errors: MRLBM_ERR_INVALID if the tree is not graded and complete. */
 int mrlbm_set_state(mrlbm_ctx *ctx, int instance, const uint8_t *tree, const void *values);
 
@@ -265,7 +282,8 @@ int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
  * whose meshes are held fixed (the adjoint of collision + MR transport +
  * transfer on each recorded mesh; no derivative through the thresholding).
  * Checkpoints every `ckpt_every` steps; each segment is recomputed forward with
- * a tape of its meshes and pre-collision populations, then swept backwards. */
+ * a tape of its meshes and pre-collision populations, then swept backwards.
+ * Periodic boundaries only (MRLBM_ERR_INVALID with a wall). */
 
 /* Bytes of device workspace the adjoint of an `nsteps` run needs. */
 int mrlbm_adjoint_workspace_size(const mrlbm_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes);

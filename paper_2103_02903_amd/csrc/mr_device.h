@@ -42,6 +42,11 @@ struct Inst {
   T eps_l[MAXLEV + 2];         // eps_l = 2^{d (l - J)} eps, indexed by the level of the children
   T ref_l[MAXLEV + 2];         // 2^{mu_bar + d} eps_l
   SchemeC<T> sc;
+  // Boundaries (section "Boundary conditions"): bit 0 walls on the x axis, bit
+  // 1 on the y axis (else periodic); kind of each side x-, x+, y-, y+ (1 copy,
+  // 2 bounce back, 3 anti bounce back, 0 periodic).
+  int walls;
+  int bck[4];
 };
 
 // Batch-wide constants (passed by value).
@@ -56,6 +61,16 @@ __device__ __forceinline__ long long foff(const Inst<T> &I, int dim, int q, int 
   return (long long)q * I.loff[l] + (long long)h * ncells_d(dim, l);
 }
 __device__ __forceinline__ int wrapl(int x, int l) { return x & ((1 << l) - 1); }
+// Index x (|overflow| <= N_l) of level l along an axis as the MR operators read
+// it: periodic wrap, or with a wall even reflection (cell -1 reads cell 0, cell
+// N_l reads cell N_l - 1). The prediction stencil is symmetric, so reflection
+// commutes with it: the reconstruction near a wall is that of the mirrored
+// periodic problem.
+__device__ __forceinline__ int axl(int x, int l, bool wall) {
+  if (!wall) return wrapl(x, l);
+  const int n = 1 << l;
+  return x < 0 ? -1 - x : (x >= n ? 2 * n - 1 - x : x);
+}
 template <int DIM>
 __device__ __forceinline__ long long cidx(int l, int x, int y) {
   return DIM == 1 ? (long long)x : (long long)x + ((long long)y << l);
@@ -85,19 +100,21 @@ __device__ __forceinline__ int upper_index(const I *a, int n, long long v) {
 // with s = +1 for the lower child and -1 for the upper one along each axis
 // (tensor product of the 1D operator). The evaluation order is part of the
 // contract: details decide the mesh, which must not depend on rounding order.
+// `walls` (Inst::walls) selects reflection instead of wrap per axis.
 template <int DIM, typename T>
 struct ParentStencil {
   T c, qx, qy, qxy;
-  __device__ __forceinline__ void load(const T *__restrict__ P, int lp, int px, int py) {
+  __device__ __forceinline__ void load(const T *__restrict__ P, int lp, int px, int py, int walls) {
     const T c1 = T(-0.125);
+    const bool wx = walls & 1, wy = walls & 2;
     if (DIM == 1) {
       c = P[px];
-      qx = c1 * (P[wrapl(px + 1, lp)] - P[wrapl(px - 1, lp)]);
+      qx = c1 * (P[axl(px + 1, lp, wx)] - P[axl(px - 1, lp, wx)]);
       qy = T(0);
       qxy = T(0);
     } else {
-      const int xm = wrapl(px - 1, lp), xp = wrapl(px + 1, lp);
-      const int ym = wrapl(py - 1, lp), yp = wrapl(py + 1, lp);
+      const int xm = axl(px - 1, lp, wx), xp = axl(px + 1, lp, wx);
+      const int ym = axl(py - 1, lp, wy), yp = axl(py + 1, lp, wy);
       c = P[cidx<2>(lp, px, py)];
       qx = c1 * (P[cidx<2>(lp, xp, py)] - P[cidx<2>(lp, xm, py)]);
       qy = c1 * (P[cidx<2>(lp, px, yp)] - P[cidx<2>(lp, px, ym)]);
@@ -115,9 +132,9 @@ struct ParentStencil {
 };
 
 template <int DIM, typename T>
-__device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy) {
+__device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy, int walls) {
   ParentStencil<DIM, T> s;
-  s.load(P, l - 1, cx >> 1, cy >> 1);
+  s.load(P, l - 1, cx >> 1, cy >> 1, walls);
   return s.child(cx & 1, cy & 1);
 }
 

@@ -216,7 +216,7 @@ __device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const In
     const uint32_t c = lst[s.beg[i] + item] & CELL_MASK;
     int x, y;
     coords<DIM>(l, c, x, y);
-    F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y);
+    F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y, I[i].walls);
   }
 }
 template <int DIM, int Q, typename T>
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
       int px, py;
       coords<DIM>(lp, e & CELL_MASK, px, py);
       ParentStencil<DIM, T> st;
-      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py);
+      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py, I[i].walls);
       const T *C = F + foff(I[i], DIM, Q, l, h);
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
         for (int dx = 0; dx < 2; ++dx) {
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *_
 #pragma unroll
     for (int h = 0; h < Q; ++h) {
       ParentStencil<DIM, T> st;
-      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py);
+      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py, In.walls);
       const T *C = F + foff(In, DIM, Q, l, h);
       T dmax = T(0);
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
@@ -567,17 +567,22 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
     int x0, y;
     coords<DIM>(l, (uint32_t)c0, x0, y);
     v = ld16(kl + cidx<DIM>(l, 0, y), x0, nl, true);  // the kept cells themselves
+    const int N = 1 << l;
+    const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
 #pragma unroll
     for (int h = 0; h < V::Q; ++h) {
       const int ex = V::ex(h), ey = V::ey(h);
       if (ex == 0 && ey == 0) continue;
+      if (wy && (y + ey < 0 || y + ey >= N)) continue;  // beyond a wall: no cell
       const uint8_t *row = kl + cidx<DIM>(l, 0, wrapl(y + ey, l));
       const Run16 a = ld16(row, x0, nl, true);
-      // the cell beyond the run: byte 0 of the word after it, or byte 3 of the word before
+      // the cell beyond the run: byte 0 of the word after it, or byte 3 of the word
+      // before (none beyond a wall)
       const Run16 t =
           ex == 0 ? a
-          : ex > 0 ? run_next(a, *reinterpret_cast<const uint32_t *>(row + wrapl(x0 + 16, l)) & 0xffu)
-                   : run_prev(a, *reinterpret_cast<const uint32_t *>(row + wrapl(x0 - 4, l)) >> 24);
+          : ex > 0 ? run_next(a, wx && x0 + 16 >= N ? 0u
+                                     : *reinterpret_cast<const uint32_t *>(row + wrapl(x0 + 16, l)) & 0xffu)
+                   : run_prev(a, wx && x0 == 0 ? 0u : *reinterpret_cast<const uint32_t *>(row + wrapl(x0 - 4, l)) >> 24);
 #pragma unroll
       for (int k = 0; k < 4; ++k) v.w[k] |= t.w[k];
     }
@@ -597,7 +602,12 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
       int x, y;
       coords<DIM>(l, (uint32_t)c, x, y);
       uint32_t b = kl[c];
-      for (int h = 0; h < V::Q; ++h) b |= kl[cidx<DIM>(l, wrapl(x + V::ex(h), l), wrapl(y + V::ey(h), l))];
+      const int N = 1 << l;
+      for (int h = 0; h < V::Q; ++h) {
+        const int sx = x + V::ex(h), sy = y + V::ey(h);
+        if (((In.walls & 1) && (sx < 0 || sx >= N)) || (DIM == 2 && (In.walls & 2) && (sy < 0 || sy >= N))) continue;
+        b |= kl[cidx<DIM>(l, wrapl(sx, l), wrapl(sy, l))];
+      }
       if (rg) b |= rg[cidx<DIM>(l - 2, x >> 2, y >> 2)];
       v.w[t >> 2] |= (b ? 1u : 0u) << (8 * (t & 3));
     }
@@ -616,21 +626,29 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   int x, y;
   coords<DIM>(lp, (uint32_t)cell, x, y);
   bool own = false, box = false;
+  // beyond a wall there is no parent: the box is clipped there
+  const int np = 1 << lp;
+  const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
   if ((((uintptr_t)tl) & 3u) == 0) {
     // children columns 2x-2 .. 2x+3 of a row: two aligned words (rows of level
     // l >= 2 hold a multiple of 4 cells); pairs -1, 0, +1 at bytes sh .. sh+5
     const int wa = wrapl(2 * x - 2, l) & ~3, wb = wrapl(wa + 4, l), sh = 8 * ((2 * x - 2) & 3);
-    for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
+    const unsigned long long keep6 = 0xffffffffffffull & (wx && x == 0 ? ~0xffffull : ~0ull) &
+                                     (wx && x == np - 1 ? ~0xffff00000000ull : ~0ull);
+    for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b) {
+      if (wy && (y + b < 0 || y + b >= np)) continue;
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy) {
         const uint8_t *row = tl + cidx<DIM>(l, 0, DIM == 2 ? wrapl(2 * (y + b) + dy, l) : 0);
         const unsigned long long v = ((unsigned long long)*reinterpret_cast<const uint32_t *>(row + wb) << 32 |
                                       *reinterpret_cast<const uint32_t *>(row + wa)) >> sh;
-        box |= (v & 0xffffffffffffull) != 0;
+        box |= (v & keep6) != 0;
         if (b == 0) own |= ((v >> 16) & 0xffffu) != 0;
       }
+    }
   } else {
     for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
       for (int a = -1; a <= 1; ++a) {
+        if ((wx && (x + a < 0 || x + a >= np)) || (wy && (y + b < 0 || y + b >= np))) continue;
         const int px = wrapl(x + a, lp), py = DIM == 2 ? wrapl(y + b, lp) : 0;
         bool any = false;
         for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
@@ -704,7 +722,7 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         coords<DIM>(l, c, x, y);
         T v[Q];
 #pragma unroll
-        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
 #pragma unroll
         for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
       }
@@ -714,7 +732,7 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         const uint32_t c = lst[b + item] & CELL_MASK;
         int x, y;
         coords<DIM>(l, c, x, y);
-        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
       }
     }
     __syncthreads();
@@ -1346,7 +1364,7 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     int x, y;
     coords<DIM>(l, (uint32_t)c, x, y);
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
   }
 }
 
@@ -1371,7 +1389,7 @@ __device__ __forceinline__ T detail_correction(T acc, int l, int x, int y, const
       if (!(nbr & (1u << k))) continue;
       const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
       ParentStencil<DIM, T> st;
-      st.load(Fl, l, px, py);
+      st.load(Fl, l, px, py, 0);  // leaves of the periodic paths only (walls: transport_wall)
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
         for (int dx = 0; dx < 2; ++dx) {
           const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
@@ -1444,6 +1462,135 @@ __device__ __forceinline__ unsigned refined_neighbours(const uint8_t *__restrict
   return nbr;
 }
 
+// ---------------------------------------------------------------- walls
+// Tables of the leaves next to a wall (section "Boundary conditions"), per
+// n - 1 and wall case wc = cx + 3 cy (per axis 0: the leaf touches no wall of
+// that axis, 1: the lower one, 2: the upper one): W and C as for the periodic
+// leaves with the finest cells of E beyond the walls left out, and the number
+// of those cells beyond the x wall and (x inside) beyond the y wall. Those
+// cells take the side's condition evaluated on the leaf itself (eq.
+// AdvectionOnBoundary, direct evaluation).
+template <typename T>
+struct WallTabs {
+  const T *W;  // [nmax][9][q][WS]
+  const T *C;  // [nmax][9][q][CS]
+  const T *N;  // [nmax][9][q][2]
+};
+
+template <int SCHEME>
+__host__ __device__ constexpr int opposite_vel(int h) {
+  for (int k = 0; k < Vel<SCHEME>::Q; ++k)
+    if (Vel<SCHEME>::ex(k) == -Vel<SCHEME>::ex(h) && Vel<SCHEME>::ey(k) == -Vel<SCHEME>::ey(h)) return k;
+  return h;
+}
+
+// Population h entering a leaf from beyond a wall of `kind` (eq.
+// refBoundaryConditions), evaluated on the leaf: its own value of h (copy) or
+// of the opposite velocity (bounce back; anti bounce back with the sign changed).
+template <int SCHEME, typename T>
+__device__ __forceinline__ T wall_value(int kind, int h, const T *__restrict__ Fl0, long long nl, uint32_t c) {
+  const T v = Fl0[(long long)(kind == 1 ? h : opposite_vel<SCHEME>(h)) * nl + c];
+  return kind == 3 ? -v : v;
+}
+
+// A leaf whose 5^d transport box reaches beyond a wall (it lies within two
+// cells of it): the box is read with reflection, which reproduces the
+// reconstruction of the mirrored problem.
+template <int DIM, typename T>
+__device__ __forceinline__ bool near_wall(const Inst<T> &In, int l, int x, int y) {
+  const int n = 1 << l;
+  return ((In.walls & 1) && (x < 2 || x > n - 3)) || (DIM == 2 && (In.walls & 2) && (y < 2 || y > n - 3));
+}
+
+// Population h of a leaf of an instance with walls (any position): the same
+// sums as transport_pop, with every index reflected at a wall, the neighbours
+// beyond a wall mirrored (a refined mirrored neighbour contributes the details
+// of the mirrored children), the tables of the leaf's wall case, and the
+// incoming values from beyond the walls. Fl0 / Ff0 point at population 0 of
+// levels l and l+1, cl at the codes of level l.
+template <int DIM, int SCHEME, typename T>
+__device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
+                                                      const T *__restrict__ Fl0, const T *__restrict__ Ff0,
+                                                      const uint8_t *__restrict__ cl, const T *__restrict__ Wt,
+                                                      const T *__restrict__ Ct, WallTabs<T> wt) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q, WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  const int ex = V::ex(h), ey = V::ey(h), J = In.jmax, n = J - l, N = 1 << l;
+  const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
+  const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
+  const T *Fl = Fl0 + (long long)h * nl;
+  if (ex == 0 && ey == 0) return Fl[c];
+  if (n == 0) {  // the plain shift, or the condition of the wall the source lies beyond
+    const int sx = x - ex, sy = y - ey;
+    int side = -1;
+    if (wx && (sx < 0 || sx >= N)) side = sx < 0 ? 0 : 1;
+    else if (wy && (sy < 0 || sy >= N)) side = sy < 0 ? 2 : 3;
+    if (side >= 0) return wall_value<SCHEME, T>(In.bck[side], h, Fl0, nl, c);
+    return Fl[cidx<DIM>(l, wrapl(sx, l), wrapl(sy, l))];
+  }
+  const int cx = wx ? (x == 0 ? 1 : (x == N - 1 ? 2 : 0)) : 0;
+  const int cy = wy ? (y == 0 ? 1 : (y == N - 1 ? 2 : 0)) : 0;
+  const int wc = cx + 3 * cy, nn = n - 1;
+  const T *W = wc ? wt.W + (((long long)nn * 9 + wc) * Q + h) * WS : Wt + ((long long)nn * Q + h) * WS;
+  const T *Cw = wc ? wt.C + (((long long)nn * 9 + wc) * Q + h) * CS : Ct + ((long long)nn * Q + h) * CS;
+  T acc = T(0);
+  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b) {
+    const long long row = DIM == 2 ? ((long long)axl(y + b, l, wy) << l) : 0;
+    for (int a = -2; a <= 2; ++a)
+      acc = fma(W[DIM == 2 ? (b + 2) * 5 + a + 2 : a + 2], Fl[row + axl(x + a, l, wx)], acc);
+  }
+  // neighbours refined one level further, mirrored beyond a wall
+  const T *Ff = Ff0 + (long long)h * nf;
+  for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if (a == 0 && b == 0) continue;
+      const int vx = x + a, vy = y + b;
+      const bool mx = wx && (vx < 0 || vx >= N), my = wy && (vy < 0 || vy >= N);
+      const int px = axl(vx, l, wx), py = DIM == 2 ? axl(vy, l, wy) : 0;
+      if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
+      ParentStencil<DIM, T> st;
+      st.load(Fl, l, px, py, In.walls);
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int rx = mx ? 1 - dx : dx, ry = my ? 1 - dy : dy;  // the real child the virtual one mirrors
+          const T d = Ff[cidx<DIM>(l + 1, 2 * px + rx, 2 * py + ry)] - st.child(rx, ry);
+          const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
+          acc = fma(Cw[y2 * 6 + y1], d, acc);
+        }
+    }
+  if (wc) {  // the finest cells of E beyond the walls
+    const T *Nw = wt.N + (((long long)nn * 9 + wc) * Q + h) * 2;
+    if (cx && Nw[0] != T(0)) acc = fma(Nw[0], wall_value<SCHEME, T>(In.bck[cx - 1], h, Fl0, nl, c), acc);
+    if (cy && Nw[1] != T(0)) acc = fma(Nw[1], wall_value<SCHEME, T>(In.bck[1 + cy], h, Fl0, nl, c), acc);
+  }
+  return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
+}
+
+// One leaf of an instance with walls, every population by transport_wall, then
+// the tape, the collision and the store as in leaf_update.
+template <int DIM, int SCHEME, typename T>
+__device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, int l, uint32_t c,
+                                                           const T *__restrict__ Fs, T *__restrict__ Fo,
+                                                           const uint8_t *__restrict__ code, const T *__restrict__ Wt,
+                                                           const T *__restrict__ Ct, WallTabs<T> wt,
+                                                           T *__restrict__ tape) {
+  constexpr int Q = Vel<SCHEME>::Q;
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
+  const T *Ff0 = l < In.jmax ? Fs + (long long)Q * In.loff[l + 1] : Fs;
+  T f[Q];
+#pragma unroll
+  for (int h = 0; h < Q; ++h)
+    f[h] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], Wt, Ct, wt);
+  if (tape)
+#pragma unroll
+    for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
+  collide<SCHEME, T>(f, In.sc);
+#pragma unroll
+  for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
+}
+
 // Variant for small leaf sets: wavefront h transports population h of 64 leaves
 // (nine times the parallelism), the collision of each leaf then runs in
 // wavefront 0 through LDS.
@@ -1452,7 +1599,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     k_transport_collide_pop(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                             const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                             const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                            unsigned long long *__restrict__ counters, T *__restrict__ tape) {
+                            WallTabs<T> wt, unsigned long long *__restrict__ counters, T *__restrict__ tape) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q;
   constexpr int WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
@@ -1487,8 +1634,12 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
-                                                  Ct + ((long long)nn * Q + h) * CS, nbr);
+      if (I[i].walls && near_wall<DIM>(I[i], l, x, y))
+        fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
+                                                     n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, Wt, Ct, wt);
+      else
+        fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
+                                                    Ct + ((long long)nn * Q + h) * CS, nbr);
       if (tape) tape[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     }
     __syncthreads();
@@ -1740,7 +1891,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
-                             unsigned long long *__restrict__ counters, T *__restrict__ tape) {
+                             WallTabs<T> wt, unsigned long long *__restrict__ counters, T *__restrict__ tape) {
   constexpr int WPB = BLK / 64;
   __shared__ SegLDS s;
   __shared__ T rowbuf[WPB][DIM == 2 ? row_slots<SCHEME>() : 1][ROWBUF];
@@ -1761,13 +1912,19 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint32_t c = e & CELL_MASK;
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
+    // leaves whose transport box reaches beyond a wall take the wall path
+    int x, y;
+    coords<DIM>(l, c, x, y);
+    const bool wall = valid && I[i].walls && near_wall<DIM>(I[i], l, x, y);
     // row mode: 64 consecutive cells of one row of a level above the finest
     const uint32_t c0 = __builtin_amdgcn_readfirstlane(c);
     const bool row = DIM == 2 && one_level && l0 < I[i].jmax && __ballot(valid && c == c0 + (uint32_t)lane) == ~0ull &&
-                     (c0 & ((1u << l0) - 1)) + 63u < (1u << l0);
+                     (c0 & ((1u << l0) - 1)) + 63u < (1u << l0) && __ballot(wall) == 0;
     if (!valid) continue;
     const Inst<T> &In = I[i];
-    if (one_level)
+    if (wall)
+      leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, wt, tape);
+    else if (one_level)
       leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);
     else
       leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);
@@ -1902,7 +2059,7 @@ __global__ void __launch_bounds__(BLK) k_predict_outside(const Inst<T> *__restri
     coords<DIM>(l, (uint32_t)c, x, y);
 #pragma unroll
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y);
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
   }
 }
 

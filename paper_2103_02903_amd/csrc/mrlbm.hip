@@ -51,8 +51,14 @@ int validate_one(const mrlbm_params *p) {
     if (!std::isfinite(p->s[i])) return MRLBM_ERR_INVALID;
     if (conserved(p->scheme, i) && p->s[i] != 0.0) return MRLBM_ERR_INVALID;
   }
+  for (int k = 0; k < 4; ++k)
+    if (p->bc[k] < MRLBM_PERIODIC || p->bc[k] > MRLBM_ANTI_BOUNCE_BACK) return MRLBM_ERR_INVALID;
+  for (int a = 0; a < 2; ++a)  // an axis is periodic on both sides or walled on both
+    if ((p->bc[2 * a] == MRLBM_PERIODIC) != (p->bc[2 * a + 1] == MRLBM_PERIODIC)) return MRLBM_ERR_INVALID;
+  if (dim == 1 && (p->bc[2] != MRLBM_PERIODIC || p->bc[3] != MRLBM_PERIODIC)) return MRLBM_ERR_INVALID;
   return MRLBM_OK;
 }
+int walls_of(const mrlbm_params *p) { return (p->bc[0] ? 1 : 0) | (p->bc[2] ? 2 : 0); }
 
 int validate(const mrlbm_params *p, int batch) {
   if (!p || batch < 1 || batch > MAXB) return MRLBM_ERR_INVALID;
@@ -88,15 +94,19 @@ void predict_down(std::vector<double> &v, long long &lo, int n) {
 
 // Sum over the finest cells [-e, 2^n - e) (the leaf's finest cells shifted by
 // -e) of the reconstruction of a unit impulse at cell `a` of level J - m
-// (the leaf covers [0, 2^n) finest cells, n >= m).
-double impulse_sum(int n, int m, int e, int a) {
+// (the leaf covers [0, 2^n) finest cells, n >= m). A leaf touching a wall
+// (wall = 1: the lower one, at finest cell 0; 2: the upper one, at 2^n) sums
+// only the cells on its side of it.
+double impulse_sum(int n, int m, int e, int a, int wall = 0) {
   const long long pad = 8;
   std::vector<double> v(2 * pad + 1, 0.0);
   long long lo = -pad;
   v[a - lo] = 1.0;
   predict_down(v, lo, m);
   double s = 0.0;
-  const long long b0 = -e, b1 = (1ll << n) - e;
+  long long b0 = -e, b1 = (1ll << n) - e;
+  if (wall == 1) b0 = std::max(b0, 0ll);
+  if (wall == 2) b1 = std::min(b1, 1ll << n);
   for (long long i = b0; i < b1; ++i) {
     const long long k = i - lo;
     if (k >= 0 && k < (long long)v.size()) s += v[k];
@@ -105,21 +115,34 @@ double impulse_sum(int n, int m, int e, int a) {
 }
 
 // W[h][25] and C[h][36] of a leaf n >= 1 levels above the finest (see header).
-void transport_tables(int scheme, int n, double *W, double *C) {
+// With a wall case (per axis 0 none, 1 the leaf touches the lower wall, 2 the
+// upper one) the sums over E leave out the finest cells beyond the walls
+// (E minus those cells is still a box: (B - eta) clipped to the domain), and
+// N[h][2] receives how many of those cells lie beyond the x wall and, with x
+// inside, beyond the y wall.
+void transport_tables(int scheme, int n, double *W, double *C, int wx = 0, int wy = 0, double *N = nullptr) {
   const int q = scheme_q(scheme), dim = scheme_dim(scheme);
   for (int h = 0; h < q; ++h) {
     int ex, ey;
     scheme_eta(scheme, h, ex, ey);
     double Sx[5], Sy[5], Tx[6], Ty[6];
     for (int a = -2; a <= 2; ++a) {
-      Sx[a + 2] = impulse_sum(n, n, ex, a);
-      Sy[a + 2] = dim == 2 ? impulse_sum(n, n, ey, a) : (a == 0 ? 1.0 : 0.0);
+      Sx[a + 2] = impulse_sum(n, n, ex, a, wx);
+      Sy[a + 2] = dim == 2 ? impulse_sum(n, n, ey, a, wy) : (a == 0 ? 1.0 : 0.0);
     }
     // detail impulses live one level below the leaf, on cells 2k + y, y in [-2, 3];
     // the leaf's range is then [0, 2) cells of that level = [0, 2^n) finest cells
     for (int y = -2; y <= 3; ++y) {
-      Tx[y + 2] = impulse_sum(n, n - 1, ex, y);
-      Ty[y + 2] = dim == 2 ? impulse_sum(n, n - 1, ey, y) : (y == 0 ? 1.0 : 0.0);
+      Tx[y + 2] = impulse_sum(n, n - 1, ex, y, wx);
+      Ty[y + 2] = dim == 2 ? impulse_sum(n, n - 1, ey, y, wy) : (y == 0 ? 1.0 : 0.0);
+    }
+    if (N) {  // positions of [-e, 2^n - e) beyond the touched wall, per axis
+      const double w = std::ldexp(1.0, n);
+      const double ox = (wx == 1 && ex > 0) || (wx == 2 && ex < 0) ? 1.0 : 0.0;
+      const double oy = dim == 2 && ((wy == 1 && ey > 0) || (wy == 2 && ey < 0)) ? 1.0 : 0.0;
+      N[2 * h] = ox * (dim == 2 ? w : 1.0);
+      N[2 * h + 1] = (w - ox) * oy;
+      if (ex == 0 && ey == 0) N[2 * h] = N[2 * h + 1] = 0.0;
     }
     const double full = std::ldexp(1.0, dim * n);
     const bool rest = ex == 0 && ey == 0;
@@ -163,7 +186,7 @@ struct Plan {
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
   size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_sync, off_ne[2], off_bcnt, off_boff, off_W,
-      off_C, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
+      off_C, off_Wb, off_Cb, off_Nb, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
     return dev + dstart[(size_t)off * LVL_STRIDE + L];
@@ -211,6 +234,8 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
     I.sc.inv_lam = 1.0 / p[i].lambda;
     I.sc.eq = p[i].eq_param;
     for (int k = 0; k < 9; ++k) I.sc.s[k] = p[i].s[k];
+    I.walls = walls_of(&p[i]);
+    for (int k = 0; k < 4; ++k) I.bck[k] = p[i].bc[k];
   }
   P.cb[B] = cells;
   P.cbp[B] = blocks;
@@ -272,6 +297,10 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
   P.off_W = take(P.rs * std::max(1, P.nmax) * P.q * ws);
   P.off_C = take(P.rs * std::max(1, P.nmax) * P.q * cs);
+  // tables of the leaves touching a wall: [n - 1][wall case 0..8][h][.]
+  P.off_Wb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * ws);
+  P.off_Cb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * cs);
+  P.off_Nb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * 2);
   P.off_red = take(sizeof(double) * 2 * RED_BLOCKS * B);
   P.off_bad = take(sizeof(int) * 4);
   P.off_cnt = take(sizeof(unsigned long long) * 4);
@@ -392,6 +421,7 @@ struct mrlbm_ctx {
   bool recon_reuse;   // the next reconstruction follows an adaptation
   int *bcnt, *boff;
   void *W, *C;
+  void *Wb, *Cb, *Nb;  // transport tables of the leaves touching a wall
   double *red;
   int *bad;
   unsigned long long *cnt;  // device counters: leaf updates, transport launches
@@ -529,6 +559,7 @@ struct Engine {
   static constexpr unsigned FB = fused_block<Q>();
 
   static const Inst<T> *I(mrlbm_ctx *c) { return (const Inst<T> *)c->inst; }
+  static WallTabs<T> wall_tabs(mrlbm_ctx *c) { return WallTabs<T>{(const T *)c->Wb, (const T *)c->Cb, (const T *)c->Nb}; }
   static long long level_chunks(mrlbm_ctx *c, int l) {  // capacity of the per-level lists in chunks
     long long n = 0;
     for (int i = 0; i < c->P.B; ++i)
@@ -762,10 +793,11 @@ struct Engine {
     if (per_leaf(c))
       k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0,
                                                  c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
-                                                              (const T *)c->W, (const T *)c->C, c->cnt, tape);
+                                                              (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt,
+                                                              tape);
     else
       k_transport_collide_pop<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
-          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt, tape);
+          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -1101,6 +1133,8 @@ struct Engine {
       d.sc.inv_lam = (T)s.sc.inv_lam;
       d.sc.eq = (T)s.sc.eq;
       for (int k = 0; k < 9; ++k) d.sc.s[k] = (T)s.sc.s[k];
+      d.walls = s.walls;
+      for (int k = 0; k < 4; ++k) d.bck[k] = s.bck[k];
     }
     HIPCHK(hipMemcpy(c->inst, v.data(), sizeof(Inst<T>) * v.size(), hipMemcpyHostToDevice));
     return MRLBM_OK;
@@ -1173,6 +1207,8 @@ bool tree_is_graded(const mrlbm_ctx *c, int inst, const uint8_t *t) {
         if (cnt != (1 << d)) return false;
         for (int b = (d == 2 ? -1 : 0); b <= (d == 2 ? 1 : 0); ++b)
           for (int a = -1; a <= 1; ++a) {
+            if (((I.walls & 1) && (px + a < 0 || px + a >= np)) || ((I.walls & 2) && (py + b < 0 || py + b >= np)))
+              continue;  // no cell beyond a wall
             const int x = (px + a) & (np - 1), y = (py + b) & (np - 1);
             const long long pi = d == 2 ? (long long)x + ((long long)y << (l - 1)) : x;
             if (!at(l - 1, pi)) return false;
@@ -1313,6 +1349,9 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   c->boff = (int *)(b + P.off_boff);
   c->W = b + P.off_W;
   c->C = b + P.off_C;
+  c->Wb = b + P.off_Wb;
+  c->Cb = b + P.off_Cb;
+  c->Nb = b + P.off_Nb;
   c->red = (double *)(b + P.off_red);
   c->bad = (int *)(b + P.off_bad);
   c->cnt = (unsigned long long *)(b + P.off_cnt);
@@ -1362,15 +1401,35 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
       for (int k = 0; k < cs; ++k) C[((size_t)(n - 1) * q + h) * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
     }
   }
-  hipError_t e;
-  if (P.rs == 8) {
-    e = hipMemcpy(c->W, W.data(), W.size() * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->C, C.data(), C.size() * 8, hipMemcpyHostToDevice);
-  } else {
-    std::vector<float> Wf(W.begin(), W.end()), Cf(C.begin(), C.end());
-    e = hipMemcpy(c->W, Wf.data(), Wf.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->C, Cf.data(), Cf.size() * 4, hipMemcpyHostToDevice);
-  }
+  // the same per wall case (index wx + 3 wy); case 0 repeats the periodic tables
+  std::vector<double> Wb((size_t)nn * 9 * q * ws, 0.0), Cb((size_t)nn * 9 * q * cs, 0.0), Nb((size_t)nn * 9 * q * 2, 0.0);
+  std::vector<double> n2(q * 2);
+  for (int n = 1; n <= P.nmax; ++n)
+    for (int wc = 0; wc < (d == 2 ? 9 : 3); ++wc) {
+      transport_tables(p[0].scheme, n, w25.data(), c36.data(), wc % 3, wc / 3, n2.data());
+      for (int h = 0; h < q; ++h) {
+        const size_t r = ((size_t)(n - 1) * 9 + wc) * q + h;
+        for (int k = 0; k < ws; ++k) Wb[r * ws + k] = d == 2 ? w25[h * 25 + k] : w25[h * 25 + 10 + k];
+        for (int k = 0; k < cs; ++k) Cb[r * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
+        Nb[r * 2] = n2[2 * h];
+        Nb[r * 2 + 1] = n2[2 * h + 1];
+      }
+    }
+  hipError_t e = hipSuccess;
+  auto put = [&](void *dst, const std::vector<double> &v) {
+    if (e != hipSuccess) return;
+    if (P.rs == 8) {
+      e = hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    } else {
+      const std::vector<float> f(v.begin(), v.end());
+      e = hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+  };
+  put(c->W, W);
+  put(c->C, C);
+  put(c->Wb, Wb);
+  put(c->Cb, Cb);
+  put(c->Nb, Nb);
   if (e == hipSuccess) e = hipMemcpy(c->cb, P.cb.data(), sizeof(long long) * P.cb.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->cbp, P.cbp.data(), sizeof(int) * P.cbp.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dtab, P.dtab.data(), sizeof(int) * P.dtab.size(), hipMemcpyHostToDevice);
@@ -1637,6 +1696,7 @@ int mrlbm_adjoint_workspace_size(const mrlbm_ctx *c, int nsteps, int ckpt_every,
 
 int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every) {
   if (!c || !adj_workspace || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
+  if (c->P.inst[0].walls) return MRLBM_ERR_INVALID;  // the adjoint covers periodic boundaries
   if (!c->all_ready()) return MRLBM_ERR_STATE;
   if (bytes < adj_layout(c->P, nsteps, ckpt_every).bytes) return MRLBM_ERR_CAPACITY;
   c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);

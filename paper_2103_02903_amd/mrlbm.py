@@ -37,14 +37,18 @@ class MrlbmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
-                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 9)]
+                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 9),
+                ("bc", ctypes.c_int * 4)]
 
     @classmethod
     def from_cfg(cls, cfg: dict, precision: int = 8) -> "Params":
         s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        if int(cfg.get("bc_eval", 0)) != 0:
+            raise ValueError("the library evaluates wall values on the leaf (bc_eval = 0) only")
+        bc = [int(v) for v in cfg.get("bc", (0, 0, 0, 0))]
         return cls(SCHEME_IDS[cfg["scheme"]], int(cfg["jmin"]), int(cfg["jmax"]), int(precision),
                    float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)), float(cfg["eps"]),
-                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s))
+                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s), (ctypes.c_int * 4)(*bc))
 
 
 class Counters(ctypes.Structure):

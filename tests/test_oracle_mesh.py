@@ -79,7 +79,11 @@ def _brute_adapt(o, cfg, told, D):
             return [(2 * c[0] + s,) for s in (0, 1)]
         return [(2 * c[0] + sx, 2 * c[1] + sy) for sy in (0, 1) for sx in (0, 1)]
 
-    def wrap(l, c):
+    walls = [cfg.get("bc", (0, 0, 0, 0))[2 * a] != 0 for a in range(d)]
+
+    def wrap(l, c):  # periodic axes wrap; beyond a wall the cell does not exist (None)
+        if any(walls[a] and not 0 <= c[a] < N(l) for a in range(d)):
+            return None
         return tuple(v % N(l) for v in c)
 
     def D_of(l, c):  # metric of the group of (l, c), stored at the parent's slot
@@ -104,7 +108,9 @@ def _brute_adapt(o, cfg, told, D):
     H = set(K)
     for (l, c) in K:
         for e in eta:
-            H.add((l, wrap(l, tuple(ci - ei for ci, ei in zip(c, e)))))
+            nb = wrap(l, tuple(ci - ei for ci, ei in zip(c, e)))
+            if nb is not None:
+                H.add((l, nb))
         if jmin < l < J and D_of(l, c) >= np.ldexp(eps_l(l), d) * 2.0 ** cfg["mu_bar"]:
             for ch in children(c):
                 H.add((l + 1, ch))
@@ -122,7 +128,7 @@ def _brute_adapt(o, cfg, told, D):
             else:
                 need += [(l - 1, wrap(l - 1, (p[0] + a, p[1] + b))) for b in rng_ for a in rng_]
             for item in need:
-                if item not in H:
+                if item[1] is not None and item not in H:
                     H.add(item)
                     changed = True
     H |= {(jmin, c) for c in cells(jmin)}
@@ -135,8 +141,11 @@ def _brute_adapt(o, cfg, told, D):
 @pytest.mark.parametrize("scheme,jmin,jmax,mu_bar,seed", [("D1Q2", 2, 6, 0.0, 0), ("D1Q3", 1, 6, 1.0, 1),
                                                           ("D1Q3", 2, 6, 2.0, 2), ("D2Q9", 1, 4, 1.0, 3),
                                                           ("D2Q9", 2, 4, 0.0, 4)])
-def test_adapt_equals_brute_force_fixed_point(scheme, jmin, jmax, mu_bar, seed):
+@pytest.mark.parametrize("walls", [False, True])
+def test_adapt_equals_brute_force_fixed_point(scheme, jmin, jmax, mu_bar, seed, walls):
     cfg = _cfg(scheme, jmin, jmax, 1e-2, mu_bar)
+    if walls:  # the set operations ignore cells beyond a wall
+        cfg = dict(cfg, bc=(2, 1, 3, 2) if cfg["dim"] == 2 else (1, 2, 0, 0))
     o = oracle.Oracle(cfg)
     rng = np.random.default_rng(seed)
     for trial in range(4):
