@@ -4,7 +4,7 @@
   in FP32: every 500 steps one step is replayed on the oracle from the GPU
   state (FP64: the oracle's own step; FP32: the oracle's float mesh decision,
   then its FP64 step from the upcast state). Meshes bit for bit; fields to
-  1e-12 (FP64) or 1e-5 (FP32) relative.
+  1e-12 (FP64) or 2e-6 (FP32) relative (measured: 5e-16 and 1.6e-7).
 * D1Q3 Burgers, levels 2..14, 4000 steps: the GPU runs (FP32 and FP64) against
   the oracle's own free-running FP64 trajectory, per field (u, m1, m2) of the
   finest-level reconstruction, each run deciding its own meshes.
@@ -27,7 +27,7 @@ from test_gpu_parity import TOL64, leaf_err
 
 pytestmark = pytest.mark.gpu
 
-TOL32 = 1e-5
+TOL32 = 2e-6  # measured 1.6e-7 worst over the ten replays
 REGION = (0.375, 0.625)
 
 
@@ -75,8 +75,8 @@ def test_shear_1024_5000_steps(mr, precision):
     mass0 = o.mass(*o.init(m0))
     drift = abs(st["mass"] - mass0) / mass0
     print("fp%d worst replay error %.3e, relative mass drift over 5000 steps %.3e" % (8 * precision, worst, drift))
-    # round-off of the per-step sums: about 3e-16 per step measured in FP64
-    assert drift <= (1e-11 if precision == 8 else 1e-4)
+    # measured 1.6e-12 (FP64: round-off of the per-step sums) and 3.4e-5 (FP32)
+    assert drift <= (1e-11 if precision == 8 else 3e-4)
     sim.close()
 
 
@@ -91,7 +91,9 @@ def test_burgers_16384_4000_steps_vs_oracle_run(mr):
     t_o, v_o = o.init(m0)
     o.step(t_o, v_o, 4000)
     ref = _finest_moments(o, t_o, v_o)
-    bounds = {8: (1e-6, 1e-4), 4: (1e-3, 1e-2)}
+    # measured: FP64 l1-rel <= 6.4e-15, linf <= 3.5e-13 (the same mesh as the
+    # oracle's); FP32 l1-rel <= 7.3e-5, linf <= 1.2e-4 (its own mesh)
+    bounds = {8: (1e-13, 5e-12), 4: (7e-4, 1.2e-3)}
     for precision in (8, 4):
         sim = mr.Sim(cfg, precision=precision)
         sim.init_equilibrium(m0)
@@ -160,7 +162,9 @@ def test_vortex_256_adjoint_800_steps(mr, precision):
     print("fp%d J %.10f leaves %d; dJ/dm0 rel %.3e, dJ/ds2 %.10f vs %.10f (rel %.3e), dJ/da rel %.3e" % (
         8 * precision, Jval, int(o.leaf_counts(t_fin).sum()), r_m, ds2_g, ds2_o, r_s, r_a), flush=True)
     print("dJ/da (oracle):", np.array2string(da_o, precision=8, max_line_width=200), flush=True)
-    tol = 1e-9 if precision == 8 else 1e-3
+    # measured (FP64 / FP32): dJ/dm0 7.8e-15 / 2.5e-5, dJ/ds2 3.1e-14 / 9.4e-6,
+    # dJ/da 4.2e-15 / 2.2e-5
+    tol = 3e-13 if precision == 8 else 2.5e-4
     assert r_m <= tol and r_s <= tol and r_a <= tol
     if precision != 8:
         return
@@ -175,7 +179,7 @@ def test_vortex_256_adjoint_800_steps(mr, precision):
         fd, ad = (Jp - Jm) / (2 * h), float(np.sum(mbar_g * dm))
         print("direction %d: central difference %.10e adjoint %.10e rel %.3e" % (k, fd, ad, abs(fd - ad) / abs(fd)),
               flush=True)
-        assert abs(fd - ad) <= 1e-5 * abs(fd)
+        assert abs(fd - ad) <= 1e-7 * abs(fd)  # measured <= 1.2e-8 (the differences' rounding)
     s2 = cfg["s"][7]
     Js = []
     for sgn in (1, -1):
@@ -185,4 +189,4 @@ def test_vortex_256_adjoint_800_steps(mr, precision):
         Js.append(_frozen_J(mr, o, c, m0, trees))
     fd = (Js[0] - Js[1]) / (2 * h)
     print("s2: central difference %.10e adjoint %.10e rel %.3e" % (fd, ds2_g, abs(fd - ds2_g) / abs(fd)), flush=True)
-    assert abs(fd - ds2_g) <= 1e-5 * abs(fd)
+    assert abs(fd - ds2_g) <= 1e-7 * abs(fd)  # measured 3.2e-9
