@@ -47,8 +47,14 @@ def test_workspace_size_and_parameter_validation():
     assert _wsize(eps=-1.0)[0] == -1
     assert _wsize(mu_bar=4.0)[0] == -1
     assert _wsize(s=[0.1] + [0.0] * 8)[0] == -1   # a conserved moment must not relax
+    assert _wsize(bc=(2, 2, 3, 1))[0] == 0        # walls on both axes
+    assert _wsize(bc=(0, 0, 1, 1))[0] == 0        # periodic in x, walls in y
+    assert _wsize(bc=(1, 0, 0, 0))[0] == -1       # an axis is periodic on both sides or on none
+    assert _wsize(bc=(4, 4, 0, 0))[0] == -1       # unknown condition
     p = mrlbm.Params.from_cfg(W.params("D1Q2", 2, 5, 1e-3, [0, 1.9]), 16)
     n = ctypes.c_size_t(0)
+    assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == -1
+    p = mrlbm.Params.from_cfg(W.params("D1Q2", 2, 5, 1e-3, [0, 1.9], bc=(1, 1, 1, 1)), 8)  # 1D has no y walls
     assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == -1
 
 

@@ -1,0 +1,114 @@
+"""Walls on the GPU (section "Boundary conditions"), through the C-ABI, against
+the oracle.
+
+One-step replays as in test_gpu_parity: from the GPU state before a step, the
+oracle's step (FP64; FP32: the oracle's float mesh decision and its FP64 step
+from the upcast state) must give the GPU's mesh bit for bit and its leaf values
+within 1e-12 (FP64) or 1e-5 (FP32) relative. The library evaluates the wall
+values on the leaf (the paper's choice), the oracle's bc_eval 0. With jmin = J
+the GPU run is the oracle's uniform scheme with the same conditions, bit for
+bit, and the finest-level reconstruction (even reflection at the walls) equals
+the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02903_amd import workloads as W
+
+from test_gpu_parity import TOL64, leaf_err
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+K = W.BC_KINDS
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_02903_amd import mrlbm
+
+    mrlbm.lib()
+    return mrlbm
+
+
+def _cfg(scheme, jmin, jmax, eps, bc, mu_bar=1.0):
+    s = {"D1Q2": [0, 1.9], "D1Q3": [0, 1.5, 1.5], "D2Q9": W.d2q9_s(1.5, 1.8)}[scheme]
+    return W.params(scheme, jmin, jmax, eps, s, mu_bar=mu_bar, eq_param=0.5 if scheme == "D1Q3" else 1.0, bc=bc)
+
+
+CASES = [
+    # scheme, jmin, jmax, eps, sides x-, x+, y-, y+, seed, steps
+    ("D1Q2", 2, 10, 1e-4, ("copy", "copy"), 1, 24),
+    ("D1Q3", 2, 11, 1e-4, ("bounce_back", "anti_bounce_back"), 2, 24),
+    ("D1Q3", 3, 9, 1e-3, ("anti_bounce_back", "copy"), 3, 16),
+    ("D2Q9", 2, 7, 1e-3, ("bounce_back",) * 4, 4, 12),
+    ("D2Q9", 3, 7, 1e-4, ("copy", "bounce_back", "anti_bounce_back", "bounce_back"), 5, 10),
+    ("D2Q9", 2, 6, 1e-3, ("periodic", "periodic", "bounce_back", "bounce_back"), 6, 12),
+    ("D2Q9", 3, 8, 1e-3, ("bounce_back", "bounce_back", "periodic", "periodic"), 7, 8),
+]
+
+
+@pytest.mark.parametrize("scheme,jmin,jmax,eps,sides,seed,steps", CASES)
+@pytest.mark.parametrize("precision", [8, 4])
+def test_walls_step_replay(mr, scheme, jmin, jmax, eps, sides, seed, steps, precision):
+    cfg = _cfg(scheme, jmin, jmax, eps, sides)
+    print("walls", scheme, jmin, jmax, sides, "precision", precision, flush=True)
+    o = oracle.Oracle(cfg)
+    m0 = W.random_field(cfg, seed, "jump")
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    levels = set()
+    for k in range(steps):
+        tg, vg = sim.get_state()
+        t_o, v_o = tg.copy(), vg.astype(np.float64)
+        if precision == 8:
+            o.step(t_o, v_o)
+        else:
+            o.step_frozen(t_o, o.new_tree_f32(tg, vg), v_o)
+        sim.step(1)
+        tg2, vg2 = sim.get_state()
+        assert np.array_equal(tg2, t_o), "mesh differs at step %d" % (k + 1)
+        assert o.check_tree(tg2) == 0
+        e = leaf_err(o, t_o, vg2, v_o)
+        assert e <= (TOL64 if precision == 8 else TOL32), "field error %g at step %d" % (e, k + 1)
+        levels |= {l for l, c in enumerate(o.leaf_counts(tg2)) if c}
+    assert len(levels) >= 2
+    if precision == 8:  # finest-level reconstruction with the reflection at the walls
+        fin = sim.fields("finest").cpu().numpy()
+        tg, vg = sim.get_state()
+        assert np.array_equal(fin, o.finest(tg, vg).reshape(o.q, -1))
+    sim.close()
+
+
+@pytest.mark.parametrize("scheme,J", [("D1Q3", 8), ("D2Q9", 5)])
+@pytest.mark.parametrize("kind", ["copy", "bounce_back", "anti_bounce_back"])
+def test_walls_uniform_limit_is_bitwise(mr, scheme, J, kind):
+    sides = (kind, kind) if scheme != "D2Q9" else (kind, "copy", kind, "bounce_back")
+    cfg = _cfg(scheme, J, J, 1e-3, sides)
+    o = oracle.Oracle(cfg)
+    m0 = W.random_field(cfg, 9, "jump")
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    t, v = o.init(m0)
+    fJ = o.values_level(v, J).reshape(o.q, -1).copy().ravel()
+    for _ in range(20):
+        sim.step(1)
+        o.uniform_step(fJ)
+    _, vg = sim.get_state()
+    assert np.array_equal(o.values_level(vg, J).reshape(-1), fJ)
+    sim.close()
+
+
+def test_walls_reject_adjoint(mr):
+    cfg = _cfg("D2Q9", 2, 5, 1e-3, ("bounce_back",) * 4)
+    sim = mr.Sim(cfg)
+    sim.init_equilibrium(W.random_field(cfg, 1))
+    with pytest.raises(mr.MrlbmError) as e:
+        sim.forward_record(4, 2)
+    assert e.value.status == -1
+    sim.close()
