@@ -104,7 +104,10 @@ def test_d1q2_advection_config_1000_steps(mr):
 
 
 def test_uniform_limits_match_oracle_uniform(mr):
-    """jmin = J and eps = 0: the adaptive GPU path reduces to the uniform scheme."""
+    """jmin = J and eps = 0: the adaptive GPU path reduces to the uniform scheme,
+    bit for bit in 1D. In D2Q9 the GPU's collision applies M^-1 in the closed
+    form M^T diag(1/|row|^2) of the orthogonal moment basis and the oracle a
+    Gauss-Jordan inverse: equal in exact arithmetic, a few roundings apart."""
     for scheme, J in [("D1Q2", 8), ("D1Q3", 8), ("D2Q9", 5)]:
         for cfg in (_cfg(scheme, J, J, 1e-3), _cfg(scheme, 2, J, 0.0)):
             o = oracle.Oracle(cfg)
@@ -118,7 +121,10 @@ def test_uniform_limits_match_oracle_uniform(mr):
             tg, vg = sim.get_state()
             assert tg.all()
             g = o.values_level(vg, J).reshape(o.q, -1)
-            assert np.max(np.abs(g - fJ)) <= 1e-13
+            if scheme == "D2Q9":
+                assert np.max(np.abs(g - fJ)) <= 1e-13
+            else:
+                assert np.array_equal(g, fJ)
 
 
 def test_d1q2_courant_one_exact_shift_on_gpu(mr):
