@@ -26,7 +26,7 @@ _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liborc.so")
 _SRC = os.path.join(_HERE, "mr_oracle.c")
 
-SCHEMES = {"D1Q2": (1, 1, 2), "D1Q3": (2, 1, 3), "D2Q9": (3, 2, 9)}  # id, dim, q
+SCHEMES = {"D1Q2": (1, 1, 2), "D1Q3": (2, 1, 3), "D2Q9": (3, 2, 9), "D2Q4E": (4, 2, 16)}  # id, dim, q
 
 
 def build(force: bool = True) -> str:
@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
                 ("jmin", ctypes.c_int), ("jmax", ctypes.c_int), ("pad_", ctypes.c_int),
                 ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double),
-                ("s", ctypes.c_double * 9), ("bc", ctypes.c_int * 4), ("bc_eval", ctypes.c_int),
+                ("s", ctypes.c_double * 16), ("bc", ctypes.c_int * 4), ("bc_eval", ctypes.c_int),
                 ("pad2_", ctypes.c_int)]
 
 
@@ -108,11 +108,11 @@ class Oracle:
 
     def __init__(self, cfg: dict):
         scheme_id, dim, q = SCHEMES[cfg["scheme"]]
-        s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        s = list(cfg["s"]) + [0.0] * (16 - len(cfg["s"]))
         bc = [int(v) for v in cfg.get("bc", (0, 0, 0, 0))]
         self.p = _Params(dim, q, scheme_id, int(cfg["jmin"]), int(cfg["jmax"]), 0,
                          float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)),
-                         float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s),
+                         float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s),
                          (ctypes.c_int * 4)(*bc), int(cfg.get("bc_eval", 0)), 0)
         self.dim, self.q, self.jmin, self.jmax = dim, q, int(cfg["jmin"]), int(cfg["jmax"])
         self.L = lib()
@@ -284,7 +284,7 @@ class Oracle:
 
     def collide_T(self, tree, h, abar):
         hb = np.zeros(self.q * self.total, np.float64)
-        sb = np.zeros(9, np.float64)
+        sb = np.zeros(16, np.float64)
         self._chk(self.L.orc_collide_T(ctypes.byref(self.p), _ptr(tree), _ptr(np.ascontiguousarray(h)),
                                        _ptr(np.ascontiguousarray(abar)), _ptr(hb), _ptr(sb)))
         return hb, sb

@@ -45,7 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define MAXQ 9
+#define MAXQ 16
 
 /* Host threads of the parallel loops: sets the count when n > 0; returns the
  * count the next parallel loop uses. */
@@ -138,6 +138,12 @@ void orc_velocities(const orc_params *P, int *eta) {
   static const int d1q3[3][2] = {{0, 0}, {1, 0}, {-1, 0}};
   static const int d2q9[9][2] = {{0, 0},  {1, 0},  {0, 1},   {-1, 0}, {0, -1},
                                  {1, 1},  {-1, 1}, {-1, -1}, {1, -1}};
+  /* D2Q4: lambda (cos(k pi / 2), sin(k pi / 2)), k = 0..3, for every variable */
+  static const int d2q4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  if (P->scheme == 4) {
+    for (int h = 0; h < P->q; ++h) { eta[2 * h] = d2q4[h & 3][0]; eta[2 * h + 1] = d2q4[h & 3][1]; }
+    return;
+  }
   const int(*t)[2] = P->scheme == 1 ? d1q2 : P->scheme == 2 ? d1q3 : d2q9;
   for (int h = 0; h < P->q; ++h) { eta[2 * h] = t[h][0]; eta[2 * h + 1] = t[h][1]; }
 }
@@ -151,6 +157,13 @@ void orc_moment_matrix(const orc_params *P, double *M) {
   } else if (P->scheme == 2) {
     const double m[3][3] = {{1, 1, 1}, {0, L, -L}, {0, L2, L2}};
     memcpy(M, m, sizeof m);
+  } else if (P->scheme == 4) {
+    /* section "Systems of hyperbolic conservation laws": the same D2Q4 matrix
+     * for each of the four variables (block diagonal) */
+    const double m[4][4] = {{1, 1, 1, 1}, {L, 0, -L, 0}, {0, L, 0, -L}, {L2, -L2, L2, -L2}};
+    for (int i = 0; i < 4; ++i)
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) M[(4 * i + r) * 16 + 4 * i + c] = m[r][c];
   } else {
     const double m[9][9] = {
         {1, 1, 1, 1, 1, 1, 1, 1, 1},
@@ -204,6 +217,21 @@ void orc_equilibrium(const orc_params *P, const double *m, double *meq) {
     meq[0] = m[0];
     meq[1] = 0.5 * m[0] * m[0];
     meq[2] = P->eq_param * L * L * m[0];
+  } else if (P->scheme == 4) {
+    /* Euler system: conserved u = (rho, rho u, rho v, E), pressure from
+     * E = p / (gamma - 1) + rho (u^2 + v^2) / 2; variable i relaxes its first
+     * moments towards the fluxes Phi_x,i(u), Phi_y,i(u) and its last one to 0 */
+    const double rho = m[0], mx = m[4], my = m[8], E = m[12];
+    const double u = mx / rho, v = my / rho;
+    const double p = (P->eq_param - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    const double fx[4] = {mx, mx * u + p, mx * v, u * (E + p)};
+    const double fy[4] = {my, my * u, my * v + p, v * (E + p)};
+    for (int i = 0; i < 4; ++i) {
+      meq[4 * i] = m[4 * i];
+      meq[4 * i + 1] = fx[i];
+      meq[4 * i + 2] = fy[i];
+      meq[4 * i + 3] = 0.0;
+    }
   } else {
     const double rho = m[0], qx = m[1], qy = m[2];
     const double cs2 = L * L / 3.0;
@@ -577,14 +605,16 @@ int orc_collide(const orc_params *P, const uint8_t *tree, double *values) {
 
 int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *values) {
   const int J = P->jmax, q = P->q;
-  const int nc = P->scheme == 3 ? 3 : 1;
+  const int nc = P->scheme == 3 ? 3 : P->scheme == 4 ? 4 : 1;
+  const int stride = P->scheme == 4 ? 4 : 1; /* moment index of conserved variable k: stride * k */
   const int64_t NJ = ncells(P, J);
   double Minv[MAXQ * MAXQ], m[MAXQ], meq[MAXQ];
   if (orc_moment_matrix_inverse(P, Minv)) return -1;
   memset(tree, 1, (size_t)orc_total_cells(P));
   memset(values, 0, sizeof(double) * (size_t)(q * orc_total_cells(P)));
   for (int64_t c = 0; c < NJ; ++c) {
-    for (int i = 0; i < q; ++i) m[i] = i < nc ? m0[(int64_t)i * NJ + c] : 0.0;
+    for (int i = 0; i < q; ++i) m[i] = 0.0;
+    for (int k = 0; k < nc; ++k) m[stride * k] = m0[(int64_t)k * NJ + c];
     orc_equilibrium(P, m, meq);
     for (int i = 0; i < q; ++i) {
       double acc = 0.0;
@@ -819,7 +849,7 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
  * (indices into level l-1) and weights such that the prediction equals
  * sum_k w[k] F[idx[k]]. Returns the number of terms (3 in 1D, 9 in 2D). */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w) {
-  if (has_walls(P)) return -1;
+  if (has_walls(P) || P->scheme == 4) return -1;
   const int n = side(l - 1);
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
@@ -849,7 +879,7 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
 /* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
  * the leaf entries hold the adjoint of the leaf values and all others are 0. */
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
-  if (has_walls(P)) return -1;
+  if (has_walls(P) || P->scheme == 4) return -1;
   const double inv = 1.0 / nchildren(P);
   /* Each population is its own linear map: the populations run in parallel,
    * each with the loop order below. */
@@ -886,7 +916,7 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
 /* Transpose of orc_transport (E/A form): adds into the dense `gs` the adjoint of
  * the reconstruction F* from the leaf adjoints `ob` of the transported values. */
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs) {
-  if (has_walls(P)) return -1;
+  if (has_walls(P) || P->scheme == 4) return -1;
   const int J = P->jmax, d = P->dim;
   int eta[2 * MAXQ];
   orc_velocities(P, eta);
@@ -942,6 +972,7 @@ void orc_equilibrium_jacobian(const orc_params *P, const double *m, double *Je) 
   const int q = P->q;
   const double L = P->lambda;
   memset(Je, 0, sizeof(double) * q * q);
+  if (P->scheme == 4) return; /* the adjoint covers schemes 1..3 (its entry points refuse 4) */
   if (P->scheme == 1) {
     Je[0] = 1.0;
     Je[1 * q + 0] = P->eq_param;
@@ -1025,6 +1056,7 @@ int orc_collide_T(const orc_params *P, const uint8_t *tree, const double *h, con
 /* Adjoint of the initial datum f = M^{-1} m_eq(m0) on the finest level: from the
  * adjoint abar of the finest-level values, the adjoint of m0 ([nc][N_J^d]). */
 int orc_init_T(const orc_params *P, const double *m0, const double *abar, double *mbar) {
+  if (P->scheme == 4) return -1;
   const int q = P->q, J = P->jmax, nc = P->scheme == 3 ? 3 : 1;
   const int64_t NJ = ncells(P, J);
   double Minv[MAXQ * MAXQ], m[MAXQ], Je[MAXQ * MAXQ], b[MAXQ];
@@ -1069,7 +1101,7 @@ static int step_precollision(const orc_params *P, const uint8_t *told, const uin
  * adds d/ds into sbar. */
 int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
                      const double *anew, double *aold, double *sbar) {
-  if (has_walls(P)) return -1;
+  if (has_walls(P) || P->scheme == 4) return -1;
   const int64_t total = orc_total_cells(P), n = P->q * total;
   double *h = calloc((size_t)n, sizeof(double)), *hb = calloc((size_t)n, sizeof(double));
   double *gs = calloc((size_t)n, sizeof(double));

@@ -16,6 +16,8 @@
  * Flat array layouts shared with the Python wrapper:
  *   tree   uint8  [level jmin..J][cell]        1 = cell is in the complete tree
  *   values double [level jmin..J][h][cell]     cell index = x (1D), x + N_l*y (2D)
+ *   (vectorial D2Q4: population h = 4 i + k is velocity k of the scheme of
+ *   conserved variable i; moment 4 i + j is moment j of that scheme)
  *   detail double [level jmin..J][cell]        D(parent) stored at the parent's slot
  */
 #ifndef MR_ORACLE_H
@@ -29,15 +31,17 @@ extern "C" {
 
 typedef struct {
   int dim;        /* 1 or 2 */
-  int q;          /* 2 (D1Q2), 3 (D1Q3), 9 (D2Q9) */
-  int scheme;     /* 1 = D1Q2 advection, 2 = D1Q3 Burgers, 3 = D2Q9 Lallemand-Luo MRT */
+  int q;          /* 2 (D1Q2), 3 (D1Q3), 9 (D2Q9), 16 (four D2Q4) */
+  int scheme;     /* 1 = D1Q2 advection, 2 = D1Q3 Burgers, 3 = D2Q9 Lallemand-Luo MRT,
+                     4 = vectorial D2Q4 for the Euler system (four D2Q4 schemes,
+                     one per conserved variable rho, rho u, rho v, E) */
   int jmin, jmax; /* coarsest and finest level */
   int pad_;
   double lambda;   /* lattice velocity, Delta x / Delta t */
-  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: unused */
+  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: unused; Euler: gamma_gas */
   double eps;      /* threshold epsilon >= 0 */
   double mu_bar;   /* regularity guess in [0, 2*gamma+1] */
-  double s[9];     /* relaxation rate of each moment (0 for conserved moments) */
+  double s[16];    /* relaxation rate of each moment (0 for conserved moments) */
   /* Boundary of each side (section "Boundary conditions"), order x-, x+, y-, y+:
    * 0 periodic, 1 copy, 2 bounce back, 3 anti bounce back (eq. refBoundaryConditions).
    * An axis is periodic when both of its sides are 0, else both must be walls;
@@ -55,7 +59,8 @@ int64_t orc_level_offset(const orc_params *P, int l);
 
 /* Initial datum at equilibrium on the full finest mesh (Algorithm 1):
  * m0 holds the conserved moments at the finest cells, layout [nc][N_J^d]
- * (nc = 1 for D1Q2/D1Q3, 3 for D2Q9: rho, q_x, q_y). */
+ * (nc = 1 for D1Q2/D1Q3, 3 for D2Q9: rho, q_x, q_y; 4 for the Euler system:
+ * rho, rho u, rho v, E). */
 int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *values);
 
 /* Reconstruction on every cell of every level: projection upward on internal

@@ -13,14 +13,14 @@ Parameter dictionary keys:
   bc       boundary of each side x-, x+, y-, y+ (BC_KINDS codes; default all
            periodic); bc_eval 0 / 1: wall values taken on the leaf / on the
            reconstruction (section "Boundary conditions")
-Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D) or 3 (rho, q_x, q_y),
-cell index x + N_J * y.
+Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D), 3 (rho, q_x, q_y)
+or 4 (the Euler system: rho, rho u, rho v, E), cell index x + N_J * y.
 """
 from __future__ import annotations
 
 import numpy as np
 
-SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3)}  # dim, q, conserved
+SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3), "D2Q4E": (2, 16, 4)}  # dim, q, conserved
 
 
 BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
@@ -118,6 +118,37 @@ def shear_layer_batch(n=96, jmin=3, seed=0, jmax_choices=(7, 8, 9, 10), eps_choi
         eps = float(rng.choice(eps_choices))
         out.append(shear_layer_d2q9(jmin=jmin, jmax=jmax, eps=eps, re=re, seed=seed + 1000 + i))
     return out
+
+
+def euler_s(sq=(1.9, 1.75, 1.75, 1.75), sxy=(1.0, 1.0, 1.0, 1.0)) -> list:
+    """Relaxation vector of the vectorial D2Q4 scheme: per variable i the rates
+    (0, s_i^q, s_i^q, s_i^xy) of its moments."""
+    out = []
+    for i in range(4):
+        out += [0.0, float(sq[i]), float(sq[i]), float(sxy[i])]
+    return out
+
+
+def riemann_d2q4e(jmin=2, jmax=8, eps=1e-3, mu_bar=0.0, lam=5.0, gamma=1.4, seed=0, bc="copy"):
+    """Euler system on [0, 1]^2 with the vectorial D2Q4 scheme (lambda = 5,
+    s^q = 1.9 for rho and 1.75 for the others, s^xy = 1) and copy walls: a
+    two-dimensional Riemann problem whose four quadrant states (x and y below
+    or above 1/2) are drawn from a seeded generator, rho in [0.5, 1.5], u and v
+    in [-0.5, 0.5], p in [0.2, 1.5] (a synthetic stand-in for the paper's
+    configurations, whose states it does not print)."""
+    cfg = params("D2Q4E", jmin, jmax, eps, euler_s(), mu_bar=mu_bar, lam=lam, eq_param=gamma,
+                 domain=(0.0, 1.0), bc=(bc,) * 4)
+    rng = np.random.default_rng(seed)
+    st = [(rng.uniform(0.5, 1.5), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), rng.uniform(0.2, 1.5))
+          for _ in range(4)]  # quadrants LL, LR, UL, UR
+    cfg.update(quadrant_states=st, gamma=float(gamma))
+    xc = cell_centres(jmax)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    q = (X > 0.5).astype(int) + 2 * (Y > 0.5).astype(int)
+    rho, u, v, p = (np.choose(q, [s[k] for s in st]) for k in range(4))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    m0 = np.stack([rho.ravel(), (rho * u).ravel(), (rho * v).ravel(), E.ravel()])
+    return cfg, np.ascontiguousarray(m0)
 
 
 def random_vortex_d2q9(jmin=3, jmax=8, eps=1e-3, mu_bar=1.0, u0=0.05, s1=1.5, s2=1.8, seed=0, kmax=4):
