@@ -24,7 +24,8 @@
  *                                     only complete leaves carry meaningful data.
  *   moments real   [nc][N_J^d]        conserved moments on the finest level:
  *                                     nc = 1 (u) for D1Q2 / D1Q3,
- *                                     nc = 3 (rho, q_x, q_y) for D2Q9.
+ *                                     nc = 3 (rho, q_x, q_y) for D2Q9,
+ *                                     nc = 4 (rho, rho u, rho v, E) for the Euler scheme.
  *
  * Ownership: the caller allocates the workspace (size from
  * mrlbm_workspace_size) on the device, and owns every input and output buffer.
@@ -63,18 +64,26 @@ extern "C" {
 #define MRLBM_D1Q2 1 /* linear advection, eta = (+1, -1), m_eq = (u, V u) */
 #define MRLBM_D1Q3 2 /* Burgers, eta = (0, +1, -1), m_eq = (u, u^2/2, alpha lambda^2 u) */
 #define MRLBM_D2Q9 3 /* Lallemand-Luo MRT of the von Karman section of the paper */
+/* Vectorial D2Q4 scheme of the Euler system (section "Systems of hyperbolic
+ * conservation laws"): four D2Q4 schemes, one per conserved variable rho,
+ * rho u, rho v, E; velocities lambda (1, 0), (0, 1), (-1, 0), (0, -1); moments
+ * of variable i: u_i, lambda (f0 - f2), lambda (f1 - f3), lambda^2 (f0 - f1 +
+ * f2 - f3), with equilibria u_i, Phi_x,i(u), Phi_y,i(u), 0 and the pressure
+ * law p = (gamma_gas - 1) (E - rho (u^2 + v^2) / 2). Population 4 i + k is
+ * velocity k of variable i, and so is moment 4 i + k. */
+#define MRLBM_D2Q4_EULER 4
 
 typedef struct mrlbm_ctx mrlbm_ctx;
 
 typedef struct {
-  int scheme;      /* MRLBM_D1Q2, MRLBM_D1Q3 or MRLBM_D2Q9 */
+  int scheme;      /* MRLBM_D1Q2, MRLBM_D1Q3, MRLBM_D2Q9 or MRLBM_D2Q4_EULER */
   int jmin, jmax;  /* coarsest and finest level: 1 <= jmin <= jmax, jmax <= 13 (2D) / 25 (1D) */
   int precision;   /* 8: populations, details and weights in double; 4: in float */
   double lambda;   /* lattice velocity dx/dt (> 0) */
-  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: ignored */
+  double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: ignored; Euler: gamma_gas > 1 */
   double eps;      /* threshold epsilon >= 0 of eq. (Thresholding) */
   double mu_bar;   /* regularity guess in [0, 3] of the refinement rule */
-  double s[9];     /* relaxation rate of each moment; conserved moments must be 0 */
+  double s[16];    /* relaxation rate of each moment (q of them); conserved moments must be 0 */
   /* Boundary of each side x-, x+, y-, y+ (section "Boundary conditions"):
    * MRLBM_PERIODIC, or a wall with the condition of eq. refBoundaryConditions
    * (MRLBM_COPY, MRLBM_BOUNCE_BACK, MRLBM_ANTI_BOUNCE_BACK). An axis is
@@ -283,7 +292,8 @@ int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
  * transfer on each recorded mesh; no derivative through the thresholding).
  * Checkpoints every `ckpt_every` steps; each segment is recomputed forward with
  * a tape of its meshes and pre-collision populations, then swept backwards.
- * Periodic boundaries only (MRLBM_ERR_INVALID with a wall). */
+ * Periodic boundaries and the schemes D1Q2, D1Q3 and D2Q9 only
+ * (MRLBM_ERR_INVALID with a wall or the Euler scheme). */
 
 /* Bytes of device workspace the adjoint of an `nsteps` run needs. */
 int mrlbm_adjoint_workspace_size(const mrlbm_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes);

@@ -25,8 +25,8 @@ enum { CAT_LEAF = 0, CAT_INTERNAL = 1, CAT_GHOST = 2, NCAT = 3 };
 
 template <typename T>
 struct SchemeC {
-  T lam, inv_lam, eq;  // lattice velocity, its inverse, V (D1Q2) or alpha (D1Q3)
-  T s[9];
+  T lam, inv_lam, eq;  // lattice velocity, its inverse, V (D1Q2), alpha (D1Q3) or gamma_gas (Euler)
+  T s[16];
 };
 
 // One simulation of a batch. Per-cell arrays (codes, flags, lists) of all
@@ -163,6 +163,12 @@ struct Vel<2> {  // D1Q3
   __host__ __device__ static constexpr int ey(int) { return 0; }
 };
 template <>
+struct Vel<4> {  // Euler system: four D2Q4 schemes, population 4 i + k is velocity k of variable i
+  static constexpr int Q = 16, DIM = 2, NC = 4;
+  __host__ __device__ static constexpr int ex(int h) { return (h & 3) == 0 ? 1 : ((h & 3) == 2 ? -1 : 0); }
+  __host__ __device__ static constexpr int ey(int h) { return (h & 3) == 1 ? 1 : ((h & 3) == 3 ? -1 : 0); }
+};
+template <>
 struct Vel<3> {  // D2Q9: rest, four axis velocities, four diagonals
   static constexpr int Q = 9, DIM = 2, NC = 3;
   __host__ __device__ static constexpr int ex(int h) {
@@ -219,6 +225,36 @@ __device__ __forceinline__ void d2q9_populations(const T *m, T *f, T il) {
   f[8] = a0 + a1 - a2 + T(2) * a3 + a4 - a5 + a6 - a8;
 }
 
+// Vectorial D2Q4 scheme of the Euler system (section "Systems of hyperbolic
+// conservation laws"): variable i (rho, rho u, rho v, E) has its own D2Q4 scheme
+// with moments m0 = sum f, m1 = lambda (f0 - f2), m2 = lambda (f1 - f3),
+// m3 = lambda^2 (f0 - f1 + f2 - f3), relaxed towards (u_i, Phi_x,i(u),
+// Phi_y,i(u), 0); the fluxes couple the four. M^{-1} in the closed form of the
+// orthogonal rows: f0 = m0/4 + m1/(2 lambda) + m3/(4 lambda^2), f2 with -m1,
+// f1 = m0/4 + m2/(2 lambda) - m3/(4 lambda^2), f3 with -m2.
+template <typename T>
+__device__ __forceinline__ void euler_fluxes(const T *u, T gam, T *fx, T *fy) {
+  const T rho = u[0], mx = u[1], my = u[2], E = u[3];
+  const T ir = T(1) / rho, vx = mx * ir, vy = my * ir;
+  const T p = (gam - T(1)) * (E - T(0.5) * rho * (vx * vx + vy * vy));
+  fx[0] = mx;
+  fx[1] = mx * vx + p;
+  fx[2] = mx * vy;
+  fx[3] = vx * (E + p);
+  fy[0] = my;
+  fy[1] = my * vx;
+  fy[2] = my * vy + p;
+  fy[3] = vy * (E + p);
+}
+template <typename T>
+__device__ __forceinline__ void d2q4_populations(T m0, T m1, T m2, T m3, T il, T *f) {
+  const T a = T(0.25) * m0, b = T(0.5) * il * m1, c = T(0.5) * il * m2, d = T(0.25) * (il * il) * m3;
+  f[0] = (a + b) + d;
+  f[1] = (a + c) - d;
+  f[2] = (a - b) + d;
+  f[3] = (a - c) - d;
+}
+
 // Collision in moment space: f^* = M^{-1} (m + S (m_eq(m) - m)), m = M f; the
 // conserved moments (s = 0) are passed through untouched.
 template <int SCHEME, typename T>
@@ -240,6 +276,24 @@ __device__ __forceinline__ void collide(T *f, const SchemeC<T> &sc) {
     f[0] = m0 - a;
     f[1] = T(0.5) * (a + b);
     f[2] = T(0.5) * (a - b);
+  } else if constexpr (SCHEME == 4) {
+    T u[4], m1[4], m2[4], m3[4], fx[4], fy[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T *g = f + 4 * i;
+      u[i] = ((g[0] + g[1]) + g[2]) + g[3];
+      m1[i] = sc.lam * (g[0] - g[2]);
+      m2[i] = sc.lam * (g[1] - g[3]);
+      m3[i] = (sc.lam * sc.lam) * ((g[0] - g[1]) + (g[2] - g[3]));
+    }
+    euler_fluxes(u, sc.eq, fx, fy);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T a = m1[i] + sc.s[4 * i + 1] * (fx[i] - m1[i]);
+      const T b = m2[i] + sc.s[4 * i + 2] * (fy[i] - m2[i]);
+      const T c = m3[i] + sc.s[4 * i + 3] * (T(0) - m3[i]);
+      d2q4_populations(u[i], a, b, c, sc.inv_lam, f + 4 * i);
+    }
   } else {
     T m[9], e[9];
     d2q9_moments(f, m, sc.lam);
@@ -260,6 +314,15 @@ __device__ __forceinline__ void moments(const T *f, T *m, T L) {
     m[0] = f[0] + f[1] + f[2];
     m[1] = L * (f[1] - f[2]);
     m[2] = (L * L) * (f[1] + f[2]);
+  } else if constexpr (SCHEME == 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T *g = f + 4 * i;
+      m[4 * i] = ((g[0] + g[1]) + g[2]) + g[3];
+      m[4 * i + 1] = L * (g[0] - g[2]);
+      m[4 * i + 2] = L * (g[1] - g[3]);
+      m[4 * i + 3] = (L * L) * ((g[0] - g[1]) + (g[2] - g[3]));
+    }
   } else {
     d2q9_moments(f, m, L);
   }
@@ -279,6 +342,11 @@ __device__ __forceinline__ void equilibrium_populations(const T *mc, T *f, const
     f[0] = u - a;
     f[1] = T(0.5) * (a + b);
     f[2] = T(0.5) * (a - b);
+  } else if constexpr (SCHEME == 4) {
+    T fx[4], fy[4];
+    euler_fluxes(mc, sc.eq, fx, fy);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d2q4_populations(mc[i], fx[i], fy[i], T(0), sc.inv_lam, f + 4 * i);
   } else {
     T m[9];
     m[0] = mc[0];

@@ -1939,7 +1939,7 @@ __global__ void __launch_bounds__(BLK) k_init_equilibrium(const Inst<T> *__restr
   const Inst<T> &In = I[i];
   const long long n = ncells_d(DIM, In.jmax);
   for (long long c = blockIdx.x * (long long)BLK + threadIdx.x; c < n; c += (long long)gridDim.x * BLK) {
-    T mc[3], f[V::Q];
+    T mc[V::NC], f[V::Q];
     for (int k = 0; k < V::NC; ++k) mc[k] = mom[k * n + c];
     equilibrium_populations<SCHEME, T>(mc, f, In.sc);
     for (int h = 0; h < V::Q; ++h) F[foff(In, DIM, V::Q, In.jmax, h) + c] = f[h];

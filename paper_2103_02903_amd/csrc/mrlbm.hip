@@ -24,22 +24,28 @@ using namespace mrlbm;
 
 namespace {
 
-int scheme_dim(int s) { return s == MRLBM_D2Q9 ? 2 : 1; }
-int scheme_q(int s) { return s == MRLBM_D1Q2 ? 2 : s == MRLBM_D1Q3 ? 3 : 9; }
+int scheme_dim(int s) { return s == MRLBM_D2Q9 || s == MRLBM_D2Q4_EULER ? 2 : 1; }
+int scheme_q(int s) { return s == MRLBM_D1Q2 ? 2 : s == MRLBM_D1Q3 ? 3 : s == MRLBM_D2Q9 ? 9 : 16; }
 void scheme_eta(int s, int h, int &ex, int &ey) {
   static const int d1q2[2] = {1, -1};
   static const int d1q3[3] = {0, 1, -1};
   static const int d2q9x[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   static const int d2q9y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static const int d2q4x[4] = {1, 0, -1, 0};
+  static const int d2q4y[4] = {0, 1, 0, -1};
   if (s == MRLBM_D1Q2) { ex = d1q2[h]; ey = 0; }
   else if (s == MRLBM_D1Q3) { ex = d1q3[h]; ey = 0; }
-  else { ex = d2q9x[h]; ey = d2q9y[h]; }
+  else if (s == MRLBM_D2Q9) { ex = d2q9x[h]; ey = d2q9y[h]; }
+  else { ex = d2q4x[h & 3]; ey = d2q4y[h & 3]; }
 }
-bool conserved(int s, int i) { return s == MRLBM_D2Q9 ? i < 3 : i == 0; }
+bool conserved(int s, int i) {
+  return s == MRLBM_D2Q9 ? i < 3 : s == MRLBM_D2Q4_EULER ? (i & 3) == 0 : i == 0;
+}
 
 int validate_one(const mrlbm_params *p) {
   if (!p) return MRLBM_ERR_INVALID;
-  if (p->scheme < MRLBM_D1Q2 || p->scheme > MRLBM_D2Q9) return MRLBM_ERR_INVALID;
+  if (p->scheme < MRLBM_D1Q2 || p->scheme > MRLBM_D2Q4_EULER) return MRLBM_ERR_INVALID;
+  if (p->scheme == MRLBM_D2Q4_EULER && !(p->eq_param > 1.0)) return MRLBM_ERR_INVALID;  // gamma_gas
   const int dim = scheme_dim(p->scheme);
   const int maxj = dim == 2 ? 13 : 25;
   if (p->jmin < 1 || p->jmax < p->jmin || p->jmax > maxj) return MRLBM_ERR_INVALID;
@@ -233,7 +239,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
     I.sc.lam = p[i].lambda;
     I.sc.inv_lam = 1.0 / p[i].lambda;
     I.sc.eq = p[i].eq_param;
-    for (int k = 0; k < 9; ++k) I.sc.s[k] = p[i].s[k];
+    for (int k = 0; k < 16; ++k) I.sc.s[k] = p[i].s[k];
     I.walls = walls_of(&p[i]);
     for (int k = 0; k < 4; ++k) I.bck[k] = p[i].bc[k];
   }
@@ -1132,7 +1138,7 @@ struct Engine {
       d.sc.lam = (T)s.sc.lam;
       d.sc.inv_lam = (T)s.sc.inv_lam;
       d.sc.eq = (T)s.sc.eq;
-      for (int k = 0; k < 9; ++k) d.sc.s[k] = (T)s.sc.s[k];
+      for (int k = 0; k < 16; ++k) d.sc.s[k] = (T)s.sc.s[k];
       d.walls = s.walls;
       for (int k = 0; k < 4; ++k) d.bck[k] = s.bck[k];
     }
@@ -1147,6 +1153,7 @@ int dispatch(mrlbm_ctx *c, A... a) {
   switch (c->p[0].scheme) {
     case MRLBM_D1Q2: return dbl ? Op<1, 1, double>::run(c, a...) : Op<1, 1, float>::run(c, a...);
     case MRLBM_D1Q3: return dbl ? Op<1, 2, double>::run(c, a...) : Op<1, 2, float>::run(c, a...);
+    case MRLBM_D2Q4_EULER: return dbl ? Op<2, 4, double>::run(c, a...) : Op<2, 4, float>::run(c, a...);
     default: return dbl ? Op<2, 3, double>::run(c, a...) : Op<2, 3, float>::run(c, a...);
   }
 }
@@ -1183,6 +1190,10 @@ struct RecordOp { static int run(mrlbm_ctx *c, int n, int K) { return Engine<D, 
 template <int D, int S, typename T>
 struct AdjointOp {
   static int run(mrlbm_ctx *c, const void *a, void *mb, double *sb) { return Engine<D, S, T>::adjoint(c, a, mb, sb); }
+};
+template <typename T>
+struct AdjointOp<2, 4, T> {  // the adjoint covers the schemes with one to three conserved moments
+  static int run(mrlbm_ctx *, const void *, void *, double *) { return MRLBM_ERR_INVALID; }
 };
 
 // Host check of a 0/1 tree of instance i: level jmin complete, sibling groups
@@ -1697,6 +1708,7 @@ int mrlbm_adjoint_workspace_size(const mrlbm_ctx *c, int nsteps, int ckpt_every,
 int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every) {
   if (!c || !adj_workspace || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
   if (c->P.inst[0].walls) return MRLBM_ERR_INVALID;  // the adjoint covers periodic boundaries
+  if (c->p[0].scheme == MRLBM_D2Q4_EULER) return MRLBM_ERR_INVALID;
   if (!c->all_ready()) return MRLBM_ERR_STATE;
   if (bytes < adj_layout(c->P, nsteps, ckpt_every).bytes) return MRLBM_ERR_CAPACITY;
   c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);
@@ -1866,7 +1878,7 @@ const char *mrlbm_status_string(int s) {
 }
 
 int mrlbm_transport_tables(int scheme, int n, double *W, double *C) {
-  if (scheme < MRLBM_D1Q2 || scheme > MRLBM_D2Q9 || n < 1 || n > 25 || !W || !C) return MRLBM_ERR_INVALID;
+  if (scheme < MRLBM_D1Q2 || scheme > MRLBM_D2Q4_EULER || n < 1 || n > 25 || !W || !C) return MRLBM_ERR_INVALID;
   if (scheme_dim(scheme) == 2 && n > 13) return MRLBM_ERR_INVALID;
   transport_tables(scheme, n, W, C);
   return MRLBM_OK;

@@ -16,7 +16,7 @@ from .workloads import SCHEME_DIMS
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmrlbm.so")
 
-SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3}
+SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3, "D2Q4E": 4}
 STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-finite leaf value",
           -4: "HIP runtime error", -5: "call out of order", -6: "device-side wait gave up"}
 FIELDS = {"leaf_table": 1, "populations": 2, "moments": 3, "finest": 4}
@@ -37,18 +37,18 @@ class MrlbmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
-                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 9),
+                ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 16),
                 ("bc", ctypes.c_int * 4)]
 
     @classmethod
     def from_cfg(cls, cfg: dict, precision: int = 8) -> "Params":
-        s = list(cfg["s"]) + [0.0] * (9 - len(cfg["s"]))
+        s = list(cfg["s"]) + [0.0] * (16 - len(cfg["s"]))
         if int(cfg.get("bc_eval", 0)) != 0:
             raise ValueError("the library evaluates wall values on the leaf (bc_eval = 0) only")
         bc = [int(v) for v in cfg.get("bc", (0, 0, 0, 0))]
         return cls(SCHEME_IDS[cfg["scheme"]], int(cfg["jmin"]), int(cfg["jmax"]), int(precision),
                    float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)), float(cfg["eps"]),
-                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 9)(*s), (ctypes.c_int * 4)(*bc))
+                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s), (ctypes.c_int * 4)(*bc))
 
 
 class Counters(ctypes.Structure):
