@@ -436,7 +436,8 @@ def main():
     ap.add_argument("--single-warmup", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=800)
     ap.add_argument("--adjoint-ckpt", type=int, default=50)
-    ap.add_argument("--schedule", default="", help="transport variant,all-level cap,per-level cap (skips autotuning)")
+    ap.add_argument("--schedule", default="",
+                    help="transport variant,all-level cap,per-level cap[,graph 1|0] (skips autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
     args = ap.parse_args()
