@@ -71,6 +71,12 @@ __device__ __forceinline__ int axl(int x, int l, bool wall) {
   const int n = 1 << l;
   return x < 0 ? -1 - x : (x >= n ? 2 * n - 1 - x : x);
 }
+// The same for a neighbour at distance 1 (x in [-1, N_l]), where reflection is
+// a clamp: no branch, one select.
+__device__ __forceinline__ int axl1(int x, int l, bool wall) {
+  const int w = wrapl(x, l), c = min(max(x, 0), (1 << l) - 1);
+  return wall ? c : w;
+}
 template <int DIM>
 __device__ __forceinline__ long long cidx(int l, int x, int y) {
   return DIM == 1 ? (long long)x : (long long)x + ((long long)y << l);
@@ -109,12 +115,12 @@ struct ParentStencil {
     const bool wx = walls & 1, wy = walls & 2;
     if (DIM == 1) {
       c = P[px];
-      qx = c1 * (P[axl(px + 1, lp, wx)] - P[axl(px - 1, lp, wx)]);
+      qx = c1 * (P[axl1(px + 1, lp, wx)] - P[axl1(px - 1, lp, wx)]);
       qy = T(0);
       qxy = T(0);
     } else {
-      const int xm = axl(px - 1, lp, wx), xp = axl(px + 1, lp, wx);
-      const int ym = axl(py - 1, lp, wy), yp = axl(py + 1, lp, wy);
+      const int xm = axl1(px - 1, lp, wx), xp = axl1(px + 1, lp, wx);
+      const int ym = axl1(py - 1, lp, wy), yp = axl1(py + 1, lp, wy);
       c = P[cidx<2>(lp, px, py)];
       qx = c1 * (P[cidx<2>(lp, xp, py)] - P[cidx<2>(lp, xm, py)]);
       qy = c1 * (P[cidx<2>(lp, px, yp)] - P[cidx<2>(lp, px, ym)]);

@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(BLK) k_ancestor(Batch bt, const Inst<T> *__res
 // Level jmin is always complete. Each thread takes 16 consecutive cells of a
 // row: the shifted runs of the rows y + eta_y, ORed (rows of at least 16
 // cells), else cell by cell.
-template <int DIM, int SCHEME, typename T>
+template <int DIM, int SCHEME, typename T, bool WALLS>
 __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__restrict__ I,
                                                  const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ keep,
                                                  const uint8_t *__restrict__ refg, uint8_t *__restrict__ tnew,
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
     coords<DIM>(l, (uint32_t)c0, x0, y);
     v = ld16(kl + cidx<DIM>(l, 0, y), x0, nl, true);  // the kept cells themselves
     const int N = 1 << l;
-    const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
+    const bool wx = WALLS && (In.walls & 1), wy = WALLS && DIM == 2 && (In.walls & 2);
 #pragma unroll
     for (int h = 0; h < V::Q; ++h) {
       const int ex = V::ex(h), ey = V::ey(h);
@@ -605,7 +605,8 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
       const int N = 1 << l;
       for (int h = 0; h < V::Q; ++h) {
         const int sx = x + V::ex(h), sy = y + V::ey(h);
-        if (((In.walls & 1) && (sx < 0 || sx >= N)) || (DIM == 2 && (In.walls & 2) && (sy < 0 || sy >= N))) continue;
+        if (WALLS && (((In.walls & 1) && (sx < 0 || sx >= N)) || (DIM == 2 && (In.walls & 2) && (sy < 0 || sy >= N))))
+          continue;
         b |= kl[cidx<DIM>(l, wrapl(sx, l), wrapl(sy, l))];
       }
       if (rg) b |= rg[cidx<DIM>(l - 2, x >> 2, y >> 2)];
@@ -618,7 +619,7 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
 // Grading G, level l: every sibling group of level l with one member gets all
 // of them, and every cell of level l-1 whose 3^d box holds a parent of a level-l
 // tree cell joins the tree. One thread per cell of level l-1.
-template <int DIM, typename T>
+template <int DIM, typename T, bool WALLS>
 __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restrict__ tnew, int l, long long cell) {
   const int lp = l - 1;
   uint8_t *tl = tnew + In.loff[l];
@@ -628,15 +629,15 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   bool own = false, box = false;
   // beyond a wall there is no parent: the box is clipped there
   const int np = 1 << lp;
-  const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
+  const bool wx = WALLS && (In.walls & 1), wy = WALLS && DIM == 2 && (In.walls & 2);
   if ((((uintptr_t)tl) & 3u) == 0) {
     // children columns 2x-2 .. 2x+3 of a row: two aligned words (rows of level
     // l >= 2 hold a multiple of 4 cells); pairs -1, 0, +1 at bytes sh .. sh+5
     const int wa = wrapl(2 * x - 2, l) & ~3, wb = wrapl(wa + 4, l), sh = 8 * ((2 * x - 2) & 3);
-    const unsigned long long keep6 = 0xffffffffffffull & (wx && x == 0 ? ~0xffffull : ~0ull) &
-                                     (wx && x == np - 1 ? ~0xffff00000000ull : ~0ull);
+    unsigned long long keep6 = 0xffffffffffffull;
+    if (WALLS) keep6 &= (wx && x == 0 ? ~0xffffull : ~0ull) & (wx && x == np - 1 ? ~0xffff00000000ull : ~0ull);
     for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b) {
-      if (wy && (y + b < 0 || y + b >= np)) continue;
+      if (WALLS && wy && (y + b < 0 || y + b >= np)) continue;
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy) {
         const uint8_t *row = tl + cidx<DIM>(l, 0, DIM == 2 ? wrapl(2 * (y + b) + dy, l) : 0);
         const unsigned long long v = ((unsigned long long)*reinterpret_cast<const uint32_t *>(row + wb) << 32 |
@@ -648,7 +649,7 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   } else {
     for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
       for (int a = -1; a <= 1; ++a) {
-        if ((wx && (x + a < 0 || x + a >= np)) || (wy && (y + b < 0 || y + b >= np))) continue;
+        if (WALLS && ((wx && (x + a < 0 || x + a >= np)) || (wy && (y + b < 0 || y + b >= np)))) continue;
         const int px = wrapl(x + a, lp), py = DIM == 2 ? wrapl(y + b, lp) : 0;
         bool any = false;
         for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
@@ -804,7 +805,7 @@ constexpr int fused_block() { return 64 * Q > BLK ? 64 * Q : BLK; }
 // Ghosts (the first G blocks): of level lh, or with HC the coarse levels
 // jmin+1 .. min(lc, jmax), one block per instance. The first writes the
 // membership array, the second the values.
-template <int DIM, int Q, typename T, bool GC, bool HC>
+template <int DIM, int Q, typename T, bool GC, bool HC, bool WALLS>
 __global__ void __launch_bounds__(fused_block<Q>())
     k_grade_ghost(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
                   const uint32_t *__restrict__ ginfo, int lg, T *__restrict__ F, const uint32_t *__restrict__ lst,
@@ -814,7 +815,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
       const Inst<T> &In = I[blockIdx.x - G];
       for (int l = lc < In.jmax ? lc : In.jmax; l > In.jmin; --l) {
         const long long n = ncells_d(DIM, l - 1);
-        for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T>(In, tnew, l, cell);
+        for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T, WALLS>(In, tnew, l, cell);
         __syncthreads();
       }
       return;
@@ -822,7 +823,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
     const uint32_t w = ginfo[blockIdx.x - G];
     const int i = (int)(w & 0xffu);
     const long long cell = (long long)(w >> 8) * fused_block<Q>() + threadIdx.x;
-    if (cell < ncells_d(DIM, lg - 1) && lg <= active_top(act, I[i], i)) grade_cell<DIM, T>(I[i], tnew, lg, cell);
+    if (cell < ncells_d(DIM, lg - 1) && lg <= active_top(act, I[i], i)) grade_cell<DIM, T, WALLS>(I[i], tnew, lg, cell);
     return;
   }
   if (HC) {
@@ -1594,7 +1595,7 @@ __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, in
 // Variant for small leaf sets: wavefront h transports population h of 64 leaves
 // (nine times the parallelism), the collision of each leaf then runs in
 // wavefront 0 through LDS.
-template <int DIM, int SCHEME, typename T>
+template <int DIM, int SCHEME, typename T, bool WALLS>
 __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     k_transport_collide_pop(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                             const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
@@ -1634,7 +1635,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      if (I[i].walls && near_wall<DIM>(I[i], l, x, y))
+      if (WALLS && I[i].walls && near_wall<DIM>(I[i], l, x, y))
         fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
                                                      n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, Wt, Ct, wt);
       else
@@ -1886,7 +1887,7 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
 // budget for 4 waves per SIMD (latency hiding of the stencil loads). A chunk
 // whose leaves share one level (all but those that straddle a level boundary)
 // takes leaf_update_level, in row mode when its leaves are one row segment.
-template <int DIM, int SCHEME, typename T>
+template <int DIM, int SCHEME, typename T, bool WALLS>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
@@ -1912,17 +1913,21 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint32_t c = e & CELL_MASK;
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
-    // leaves whose transport box reaches beyond a wall take the wall path
-    int x, y;
-    coords<DIM>(l, c, x, y);
-    const bool wall = valid && I[i].walls && near_wall<DIM>(I[i], l, x, y);
+    // leaves whose transport box reaches beyond a wall take the wall path (a
+    // variant of the kernel launched only for batches with walls)
+    bool wall = false;
+    if constexpr (WALLS) {
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      wall = valid && I[i].walls && near_wall<DIM>(I[i], l, x, y);
+    }
     // row mode: 64 consecutive cells of one row of a level above the finest
     const uint32_t c0 = __builtin_amdgcn_readfirstlane(c);
     const bool row = DIM == 2 && one_level && l0 < I[i].jmax && __ballot(valid && c == c0 + (uint32_t)lane) == ~0ull &&
                      (c0 & ((1u << l0) - 1)) + 63u < (1u << l0) && __ballot(wall) == 0;
     if (!valid) continue;
     const Inst<T> &In = I[i];
-    if (wall)
+    if (WALLS && wall)
       leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, wt, tape);
     else if (one_level)
       leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);

@@ -181,6 +181,7 @@ int dense_margin(int off) { return off == 1 ? 1 : off == 2 ? 2 : 0; }
 // the workspace layout.
 struct Plan {
   int B, dim, q, jmin, maxJ, nmax, nblocks;
+  bool any_walls;  // some instance has walls: the launches take the kernel variants that handle them
   size_t rs;
   long long ctotal;
   std::vector<Inst<double>> inst;
@@ -207,6 +208,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.maxJ = 0;
   P.rs = p[0].precision == 8 ? 8 : 4;
   P.inst.assign(B, Inst<double>());
+  P.any_walls = false;
   P.cb.assign(B + 1, 0);
   P.cbp.assign(B + 1, 0);
   long long cells = 0;
@@ -241,6 +243,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
     I.sc.eq = p[i].eq_param;
     for (int k = 0; k < 16; ++k) I.sc.s[k] = p[i].s[k];
     I.walls = walls_of(&p[i]);
+    if (I.walls) P.any_walls = true;
     for (int k = 0; k < 4; ++k) I.bck[k] = p[i].bc[k];
   }
   P.cb[B] = cells;
@@ -482,12 +485,17 @@ void activity_reset(mrlbm_ctx *c) {
 
 enum { PH_TRANSPORT = 0, PH_RECON = 1, PH_ADAPT = 2 };
 
+// Timing events: no system-scope fence when they are recorded (no cache
+// writeback and invalidation around the timed kernel, which would slow it
+// down); they are read only after the stream has been synchronised.
+hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 // Start (begin = true) or end a timed phase: two events on the context stream.
 void phase_mark(mrlbm_ctx *c, int phase, bool begin) {
   if (!c->profiling) return;
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (timing_event(&e) != hipSuccess) return;
     c->ev_pool.push_back(e);
   }
   if (begin) c->ev_marks.push_back({phase, c->ev_used});
@@ -731,7 +739,8 @@ struct Engine {
     else if (lc + 2 >= P.jmin + 2)
       k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
 
-    k_enlarge<DIM, SCHEME, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew,
+    auto enlarge = P.any_walls ? k_enlarge<DIM, SCHEME, T, true> : k_enlarge<DIM, SCHEME, T, false>;
+    enlarge<<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->keep, c->refg, c->tnew,
                                                                 c->act);
     // Grading (levels maxJ .. jmin+1) beside the finer links of the old mesh's
     // ghost predictions (levels above the coarse cap, coarse to fine): one link
@@ -749,18 +758,12 @@ struct Engine {
         const unsigned G = h == 0 ? 0u : h < 0 ? (unsigned)P.B : chunks_level(c, h);
         const uint32_t *gi = g > 0 ? P.dinfo_row(c->dinfo, 1, g - 1) : c->dinfo;
         if (G + nb == 0) continue;
-        if (g < 0 && h < 0)
-          k_grade_ghost<DIM, Q, T, true, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                            c->lvl[mo], h, (int)G, lc, c->act);
-        else if (g < 0)
-          k_grade_ghost<DIM, Q, T, true, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                             c->lvl[mo], h, (int)G, lc, c->act);
-        else if (h < 0)
-          k_grade_ghost<DIM, Q, T, false, true><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                             c->lvl[mo], h, (int)G, lc, c->act);
-        else
-          k_grade_ghost<DIM, Q, T, false, false><<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg,
-                                                                              c->lvl[mo], h, (int)G, lc, c->act);
+        const bool w = P.any_walls;
+        auto kern = g < 0 && h < 0 ? (w ? k_grade_ghost<DIM, Q, T, true, true, true> : k_grade_ghost<DIM, Q, T, true, true, false>)
+                    : g < 0        ? (w ? k_grade_ghost<DIM, Q, T, true, false, true> : k_grade_ghost<DIM, Q, T, true, false, false>)
+                    : h < 0        ? (w ? k_grade_ghost<DIM, Q, T, false, true, true> : k_grade_ghost<DIM, Q, T, false, true, false>)
+                                   : (w ? k_grade_ghost<DIM, Q, T, false, false, true> : k_grade_ghost<DIM, Q, T, false, false, false>);
+        kern<<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg, c->lvl[mo], h, (int)G, lc, c->act);
       }
     }
 
@@ -796,14 +799,17 @@ struct Engine {
     T *Fn = (T *)c->F[1 - c->cur];
     phase_mark(c, PH_TRANSPORT, true);
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
-    if (per_leaf(c))
-      k_transport_collide_leaf<DIM, SCHEME, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0,
-                                                 c->stream>>>(c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m],
-                                                              (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt,
-                                                              tape);
-    else
-      k_transport_collide_pop<DIM, SCHEME, T><<<chunks_all(c), QB, 0, c->stream>>>(
+    if (per_leaf(c)) {
+      auto kern = P.any_walls ? k_transport_collide_leaf<DIM, SCHEME, T, true>
+                              : k_transport_collide_leaf<DIM, SCHEME, T, false>;
+      kern<<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
+    } else {
+      auto kern = P.any_walls ? k_transport_collide_pop<DIM, SCHEME, T, true>
+                              : k_transport_collide_pop<DIM, SCHEME, T, false>;
+      kern<<<chunks_all(c), QB, 0, c->stream>>>(
+          c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
+    }
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -850,7 +856,7 @@ struct Engine {
       for (int k = 0; k < 2; ++k) {
         if (c->ev_used + k == c->ev_pool.size()) {
           hipEvent_t ev;
-          if (hipEventCreate(&ev) != hipSuccess) return MRLBM_ERR_HIP;
+          if (timing_event(&ev) != hipSuccess) return MRLBM_ERR_HIP;
           c->ev_pool.push_back(ev);
         }
         if (hipGraphExecEventRecordNodeSetEvent(g, c->timed_ev[key][k], c->ev_pool[c->ev_used + k]) != hipSuccess)
@@ -1102,8 +1108,8 @@ struct Engine {
     if (rc != MRLBM_OK) return rc;
     if (e != hipSuccess) return MRLBM_ERR_HIP;
     hipEvent_t a = nullptr, b = nullptr;
-    e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
+    e = timing_event(&a);
+    if (e == hipSuccess) e = timing_event(&b);
     if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(a, c->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, c->stream);
@@ -1389,7 +1395,7 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   for (auto &g : c->timed_src) g = nullptr;
   c->ev_placeholder = nullptr;
   if (static_dev < 0) {
-    if (hipEventCreate(&c->ev_placeholder) != hipSuccess) {
+    if (timing_event(&c->ev_placeholder) != hipSuccess) {
       delete c;
       return MRLBM_ERR_HIP;
     }
