@@ -80,27 +80,27 @@ def read_counters(path: str, counter: str):
     return sorted((tuple(v) for v in acc.values()), key=lambda t: t[1])
 
 
-def select(seq, patterns, skip: int, take: int, window=""):
+def select(seq, patterns, skip: int, take: int, window="", index: int = 0):
     """Dispatches of the kernels matching all patterns, optionally only those
-    starting between the first two dispatches of the kernel named `window`;
-    then `skip` of them are dropped and at most `take` kept."""
+    starting between dispatches `index` and `index` + 1 of the kernel named
+    `window`; then `skip` of them are dropped and at most `take` kept."""
     if window:
         marks = [x[1] for x in seq if window in x[0]]
-        if len(marks) < 2:
-            raise SystemExit("fewer than two %s markers" % window)
-        seq = [x for x in seq if marks[0] < x[1] < marks[1]]
+        if len(marks) < index + 2:
+            raise SystemExit("fewer than %d %s markers" % (index + 2, window))
+        seq = [x for x in seq if marks[index] < x[1] < marks[index + 1]]
     hits = [x for x in seq if _matches(x[0], patterns)]
     hits = hits[skip:]
     return hits[:take] if take > 0 else hits
 
 
 def stats_summary(args) -> str:
-    rows = read_trace(args.trace)
+    rows = all_rows = read_trace(args.trace)
     if args.table_window:  # the table covers only the timed region
         marks = [r[1] for r in rows if args.window in r[0]]
-        if len(marks) < 2:
-            raise SystemExit("fewer than two %s markers" % args.window)
-        rows = [r for r in rows if marks[0] < r[1] < marks[1]]
+        if len(marks) < args.window_index + 2:
+            raise SystemExit("fewer than %d %s markers" % (args.window_index + 2, args.window))
+        rows = [r for r in rows if marks[args.window_index] < r[1] < marks[args.window_index + 1]]
     agg = defaultdict(lambda: [0, 0, float("inf"), 0])
     for n, s, e in rows:
         a = agg[short_name(n)]
@@ -124,10 +124,11 @@ def stats_summary(args) -> str:
         lines.append("%-58s %8s %12.1f %10s %10s %10s %6s %12.2f" % ("sum of kernel durations", "", total / 1e3, "", "",
                                                                     "", "", total / 1e3 / per))
     if args.match:
-        sel = select(rows, args.match, args.skip, args.take, args.window)
+        sel = select(all_rows, args.match, args.skip, args.take, args.window, args.window_index)
         if sel:
             durs = [e - s for _, s, e in sel]
-            where = ("between the two %s markers" % args.window) if args.window else (
+            where = ("between %s markers %d and %d" % (args.window, args.window_index + 1, args.window_index + 2)) \
+                if args.window else (
                 "dispatches %d..%d" % (args.skip + 1, args.skip + len(sel)))
             lines += ["",
                       "timed region: %s, kernels matching %s (%s)" % (
@@ -138,8 +139,10 @@ def stats_summary(args) -> str:
 
 
 def counters_summary(args) -> dict:
-    fetch = select(read_counters(args.fetch, "FETCH_SIZE"), args.match, args.skip, args.take, args.window)
-    write = select(read_counters(args.write, "WRITE_SIZE"), args.match, args.skip, args.take, args.window)
+    fetch = select(read_counters(args.fetch, "FETCH_SIZE"), args.match, args.skip, args.take, args.window,
+                   args.window_index)
+    write = select(read_counters(args.write, "WRITE_SIZE"), args.match, args.skip, args.take, args.window,
+                   args.window_index)
     cf = select(read_counters(args.copy_fetch, "FETCH_SIZE"), [COPY_KERNEL], 1, 0)  # first launch warms up
     cw = select(read_counters(args.copy_write, "WRITE_SIZE"), [COPY_KERNEL], 1, 0)
     if not fetch or not write or not cf or not cw:
@@ -187,7 +190,9 @@ def main():
         p.add_argument("--match", action="append", default=[])
         p.add_argument("--skip", type=int, default=0)
         p.add_argument("--take", type=int, default=0)
-        p.add_argument("--window", default="", help="kernel whose first two dispatches bound the selection")
+        p.add_argument("--window", default="", help="kernel whose dispatches bound the selection")
+        p.add_argument("--window-index", type=int, default=0,
+                       help="the selection lies between dispatches INDEX and INDEX + 1 of the window kernel")
         p.add_argument("--command", action="append", default=[])
         p.add_argument("--out", required=True)
     args = ap.parse_args()
