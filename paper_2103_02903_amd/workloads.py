@@ -27,9 +27,11 @@ BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
 
 
 def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0, lam: float = 1.0,
-           eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0) -> dict:
+           eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0, gamma: int = 1,
+           metric: str = "linf") -> dict:
     """Parameter dictionary. ``bc``: None (periodic) or the kind of each side
-    x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two)."""
+    x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two). ``gamma``:
+    prediction stencil half-width 1..3; ``metric``: "linf" or "l2" sibling metric."""
     dim, q, _ = SCHEME_DIMS[scheme]
     s = [float(v) for v in s]
     assert len(s) == q
@@ -39,7 +41,7 @@ def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0
             codes[k] = BC_KINDS[v] if isinstance(v, str) else int(v)
     return dict(scheme=scheme, dim=dim, q=q, jmin=int(jmin), jmax=int(jmax), eps=float(eps),
                 mu_bar=float(mu_bar), lam=float(lam), eq_param=float(eq_param), s=s,
-                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval))
+                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval), gamma=int(gamma), metric=metric)
 
 
 def cell_centres(jmax: int, domain=(0.0, 1.0)) -> np.ndarray:
