@@ -14,7 +14,7 @@
  *      implementation of the reconstruction operator");
  *   3. the collision of eq. (AdaptiveCollision) on the same leaf.
  * Each axis is periodic or bounded by walls (section "Boundary conditions"); the
- * prediction stencil half-width is gamma = 1.
+ * prediction stencil half-width is gamma = 1, 2 or 3 (Table 1).
  *
  * Data layout (shared by every host<->device exchange below):
  *   levels l = jmin..jmax are concatenated; level l holds N_l^d cells, N_l = 2^l,
@@ -82,7 +82,7 @@ typedef struct {
   double lambda;   /* lattice velocity dx/dt (> 0) */
   double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: ignored; Euler: gamma_gas > 1 */
   double eps;      /* threshold epsilon >= 0 of eq. (Thresholding) */
-  double mu_bar;   /* regularity guess in [0, 3] of the refinement rule */
+  double mu_bar;   /* regularity guess in [0, 2 gamma + 1] of the refinement rule */
   double s[16];    /* relaxation rate of each moment (q of them); conserved moments must be 0 */
   /* Boundary of each side x-, x+, y-, y+ (section "Boundary conditions"):
    * MRLBM_PERIODIC, or a wall with the condition of eq. refBoundaryConditions
@@ -95,7 +95,24 @@ typedef struct {
    * reflection across a wall, and the mesh's neighbour additions and grading
    * boxes stop at it. The adjoint accepts periodic contexts only. */
   int bc[4];
+  /* Half-width gamma of the prediction stencil (Table 1): 1, 2 or 3 (0 reads
+   * as 1), shared by the batch. It sets the grading box (+-gamma cells of the
+   * parent level), the transport box (+-2 gamma cells of the leaf's level) and
+   * the neighbours whose details correct it (+-gamma). gamma > 1 takes the
+   * general transport path for every leaf (about five times the transport's
+   * cost of gamma = 1). With a wall, 2^jmin >= 2 gamma. The adjoint accepts
+   * gamma = 1 only. */
+  int gamma;
+  /* Sibling metric of the details (section "Mesh coarsening"):
+   * MRLBM_METRIC_MAX, the max norm over the 2^d siblings, or MRLBM_METRIC_L2,
+   * the l2 form 2^{-d/2} (sum of their squares)^{1/2} of the section's
+   * footnote, which the library compares squared (2^{-d} times the sum of
+   * squares against the squared thresholds). May differ per instance. */
+  int metric;
 } mrlbm_params;
+
+#define MRLBM_METRIC_MAX 0
+#define MRLBM_METRIC_L2 1
 
 #define MRLBM_PERIODIC 0
 #define MRLBM_COPY 1
@@ -292,8 +309,8 @@ int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
  * transfer on each recorded mesh; no derivative through the thresholding).
  * Checkpoints every `ckpt_every` steps; each segment is recomputed forward with
  * a tape of its meshes and pre-collision populations, then swept backwards.
- * Periodic boundaries and the schemes D1Q2, D1Q3 and D2Q9 only
- * (MRLBM_ERR_INVALID with a wall or the Euler scheme). */
+ * Periodic boundaries, gamma = 1 and the schemes D1Q2, D1Q3 and D2Q9 only
+ * (MRLBM_ERR_INVALID with a wall, gamma > 1 or the Euler scheme). */
 
 /* Bytes of device workspace the adjoint of an `nsteps` run needs. */
 int mrlbm_adjoint_workspace_size(const mrlbm_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes);
@@ -362,12 +379,29 @@ const char *mrlbm_status_string(int status);
 /* Host-side flattened transport weights of eq. (PredictionWithMatrixNew) for a
  * leaf n = jmax - l >= 1 levels above the finest, velocity h of `scheme`:
  *   W[h][25]: weight of the leaf-level value at offset (a, b) in [-2, 2]^2,
- *             index (b + 2) * 5 + (a + 2) (1D: b = 0 only, W[h][a + 2]), of
- *             sum_E f^hat-hat - sum_A f^hat-hat;
+ *             index (b + 2) * 5 + (a + 2), of sum_E f^hat-hat - sum_A f^hat-hat
+ *             (1D: the same layout, with only the row b = 0 nonzero);
  *   C[h][36]: weight of the detail of the level-(l+1) cell at offset (y1, y2)
- *             in [-2, 3]^2 from 2k, index (y2 + 2) * 6 + (y1 + 2) (1D: C[h][y1 + 2]).
+ *             in [-2, 3]^2 from 2k, index (y2 + 2) * 6 + (y1 + 2) (1D: only
+ *             the row y2 = 0 nonzero).
  * Pure host computation (no device, no context). Errors: MRLBM_ERR_INVALID. */
 int mrlbm_transport_tables(int scheme, int n, double *W, double *C);
+
+/* The tables of the general transport path (walls, gamma > 1): as above for a
+ * prediction of half-width gamma (1..3, Table 1), over the boxes of half-width
+ * R = 2 gamma, for a leaf touching the walls named by wall_x, wall_y (0 none,
+ * 1 the lower wall, 2 the upper one; 1D: wall_y = 0) of section "Boundary
+ * conditions". The sums over E leave out the finest cells beyond the walls.
+ *   W[h][(2R+1)^d]: offsets (a, b) in [-R, R]^d, index (b + R)(2R+1) + (a + R)
+ *                   (1D: a + R);
+ *   C[h][(2R+2)^d]: offsets (y1, y2) in [-R, R+1]^d from 2k, index
+ *                   (y2 + R)(2R+2) + (y1 + R) (1D: y1 + R);
+ *   N[h][2]:        the number of finest cells of E beyond the x wall and,
+ *                   with x inside, beyond the y wall (their values come from the
+ *                   wall's condition, eq. AdvectionOnBoundary).
+ * Pure host computation. Errors: MRLBM_ERR_INVALID. */
+int mrlbm_transport_tables_general(int scheme, int n, int gamma, int wall_x, int wall_y, double *W, double *C,
+                                   double *N);
 
 #ifdef __cplusplus
 }

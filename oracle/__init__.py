@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
                 ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double),
                 ("s", ctypes.c_double * 16), ("bc", ctypes.c_int * 4), ("bc_eval", ctypes.c_int),
-                ("pad2_", ctypes.c_int)]
+                ("gamma", ctypes.c_int), ("metric", ctypes.c_int), ("pad3_", ctypes.c_int)]
 
 
 _lib = None
@@ -113,7 +113,8 @@ class Oracle:
         self.p = _Params(dim, q, scheme_id, int(cfg["jmin"]), int(cfg["jmax"]), 0,
                          float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)),
                          float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s),
-                         (ctypes.c_int * 4)(*bc), int(cfg.get("bc_eval", 0)), 0)
+                         (ctypes.c_int * 4)(*bc), int(cfg.get("bc_eval", 0)), int(cfg.get("gamma", 1)),
+                         {"linf": 0, "l2": 1}[cfg.get("metric", "linf")], 0)
         self.dim, self.q, self.jmin, self.jmax = dim, q, int(cfg["jmin"]), int(cfg["jmax"])
         self.L = lib()
         self.total = int(self.L.orc_total_cells(ctypes.byref(self.p)))

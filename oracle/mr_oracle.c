@@ -277,25 +277,44 @@ void orc_collide_cell(const orc_params *P, double *f) {
 
 /* Table 1, gamma = 1. */
 static const double C1 = -0.125;
+/* Table 1: the coefficients c_1 .. c_gamma of the prediction of half-width
+ * gamma = 1, 2, 3 (exact dyadic rationals). */
+static const double CG[4][3] = {{0, 0, 0}, {-0.125, 0, 0}, {-22.0 / 128, 3.0 / 128, 0},
+                                {-201.0 / 1024, 11.0 / 256, -5.0 / 1024}};
+static int gam(const orc_params *P) { return P->gamma > 0 ? P->gamma : 1; }
 
 /* Prediction of child (cx, cy) at level l from the dense data Fp of level l-1:
  * 1D:  f_parent + (-1)^dx * c1 * (f_{p+1} - f_{p-1});
  * 2D:  tensor product, f + (-1)^dx Qx + (-1)^dy Qy + (-1)^(dx+dy) Qxy. */
 double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy) {
-  const int n = side(l - 1);
+  const int n = side(l - 1), g = gam(P);
+  const double *c = CG[g];
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
   if (P->dim == 1) {
-    const double Q = C1 * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
+    /* Q = sum over alpha = 1..gamma of c_alpha (F(p + alpha) - F(p - alpha)), alpha ascending */
+    double Q = c[0] * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
+    for (int a = 2; a <= g; ++a) Q = Q + c[a - 1] * (Fp[mr_axis(P, 0, px + a, n)] - Fp[mr_axis(P, 0, px - a, n)]);
     return Fp[px] + sx * Q;
   }
   const int py = cy >> 1;
   const double sy = (cy & 1) ? -1.0 : 1.0;
 #define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
-  const double Qx = C1 * (AT(px + 1, py) - AT(px - 1, py));
-  const double Qy = C1 * (AT(px, py + 1) - AT(px, py - 1));
-  const double Qxy =
-      (C1 * C1) * (((AT(px + 1, py + 1) - AT(px - 1, py + 1)) - AT(px + 1, py - 1)) + AT(px - 1, py - 1));
+  double Qx = c[0] * (AT(px + 1, py) - AT(px - 1, py));
+  double Qy = c[0] * (AT(px, py + 1) - AT(px, py - 1));
+  for (int a = 2; a <= g; ++a) {
+    Qx = Qx + c[a - 1] * (AT(px + a, py) - AT(px - a, py));
+    Qy = Qy + c[a - 1] * (AT(px, py + a) - AT(px, py - a));
+  }
+  /* tensor-product cross term: beta (y) outer, alpha (x) inner, starting with
+   * (1, 1); each product c_alpha c_beta is exact */
+#define TERM(a, b) \
+  ((c[(a) - 1] * c[(b) - 1]) * (((AT(px + (a), py + (b)) - AT(px - (a), py + (b))) - AT(px + (a), py - (b))) + \
+                                AT(px - (a), py - (b))))
+  double Qxy = TERM(1, 1);
+  for (int b = 1; b <= g; ++b)
+    for (int a = (b == 1 ? 2 : 1); a <= g; ++a) Qxy = Qxy + TERM(a, b);
+#undef TERM
   return ((AT(px, py) + sx * Qx) + sy * Qy) + (sx * sy) * Qxy;
 #undef AT
 }
@@ -356,10 +375,16 @@ int orc_details(const orc_params *P, const uint8_t *tree, const double *values, 
       double dmax = 0.0;
       for (int h = 0; h < P->q; ++h) {
         const double *Fc = val_at(P, values, l, h), *Fp = val_at(P, values, l - 1, h);
+        double s2 = 0.0;
         for (int sigma = 0; sigma < nchildren(P); ++sigma) {
           const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
           const double d = Fc[cell_index(P, l, cx, cy)] - orc_predict(P, Fp, l, cx, cy);
-          if (fabs(d) > dmax) dmax = fabs(d);
+          if (P->metric) s2 = s2 + d * d;
+          else if (fabs(d) > dmax) dmax = fabs(d);
+        }
+        if (P->metric) {
+          s2 = ldexp(s2, -P->dim); /* square of 2^{-d/2} (sum of d^2)^{1/2} */
+          if (s2 > dmax) dmax = s2;
         }
       }
       Dp[p] = dmax;
@@ -383,6 +408,11 @@ static void thresholds(const orc_params *P, double *eps_l, double *ref_l) {
     eps_l[l] = ldexp(P->eps, P->dim * (l - P->jmax));
     ref_l[l] = ldexp(eps_l[l], P->dim) * exp2(P->mu_bar);
   }
+  if (P->metric) /* the l2 metric is kept squared: compare with squared thresholds */
+    for (int l = 0; l <= P->jmax; ++l) {
+      eps_l[l] = eps_l[l] * eps_l[l];
+      ref_l[l] = ref_l[l] * ref_l[l];
+    }
 }
 
 static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double *D, const double *eps_lv,
@@ -464,9 +494,9 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
       if (!tn[c]) continue;
       int x, y;
       cell_coords(P, l, c, &x, &y);
-      const int px = x >> 1, py = y >> 1;
-      for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
-        for (int ax = -1; ax <= 1; ++ax) {
+      const int px = x >> 1, py = y >> 1, g = gam(P);
+      for (int ay = (d == 2 ? -g : 0); ay <= (d == 2 ? g : 0); ++ay)
+        for (int ax = -g; ax <= g; ++ax) {
           const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
           if (nb >= 0) tp[nb] = 1;
         }
@@ -722,9 +752,10 @@ int orc_check_tree(const orc_params *P, const uint8_t *tree) {
       for (int sigma = 0; sigma < nchildren(P); ++sigma) cnt += t[child_index(P, l - 1, px, py, sigma)];
       if (cnt != 0 && cnt != nchildren(P)) bad |= 2;
       if (cnt && !tp[p]) bad |= 4;
+      const int g = gam(P);
       if (cnt)
-        for (int ay = (d == 2 ? -1 : 0); ay <= (d == 2 ? 1 : 0); ++ay)
-          for (int ax = -1; ax <= 1; ++ax) {
+        for (int ay = (d == 2 ? -g : 0); ay <= (d == 2 ? g : 0); ++ay)
+          for (int ax = -g; ax <= g; ++ax) {
             const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
             if (nb >= 0 && !tp[nb]) bad |= 8;
           }
@@ -742,21 +773,32 @@ static float *valf_at(const orc_params *P, const float *v, int l, int h) {
 }
 
 static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, int cy) {
-  const int n = side(l - 1);
+  const int n = side(l - 1), g = gam(P);
+  float c[3];
+  for (int a = 0; a < 3; ++a) c[a] = (float)CG[g][a]; /* exact in float */
   const int px = cx >> 1;
   const float sx = (cx & 1) ? -1.0f : 1.0f;
-  const float c1 = -0.125f;
   if (P->dim == 1) {
-    const float Q = c1 * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
+    float Q = c[0] * (Fp[mr_axis(P, 0, px + 1, n)] - Fp[mr_axis(P, 0, px - 1, n)]);
+    for (int a = 2; a <= g; ++a) Q = Q + c[a - 1] * (Fp[mr_axis(P, 0, px + a, n)] - Fp[mr_axis(P, 0, px - a, n)]);
     return Fp[px] + sx * Q;
   }
   const int py = cy >> 1;
   const float sy = (cy & 1) ? -1.0f : 1.0f;
 #define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
-  const float Qx = c1 * (AT(px + 1, py) - AT(px - 1, py));
-  const float Qy = c1 * (AT(px, py + 1) - AT(px, py - 1));
-  const float Qxy =
-      0.015625f * (((AT(px + 1, py + 1) - AT(px - 1, py + 1)) - AT(px + 1, py - 1)) + AT(px - 1, py - 1));
+  float Qx = c[0] * (AT(px + 1, py) - AT(px - 1, py));
+  float Qy = c[0] * (AT(px, py + 1) - AT(px, py - 1));
+  for (int a = 2; a <= g; ++a) {
+    Qx = Qx + c[a - 1] * (AT(px + a, py) - AT(px - a, py));
+    Qy = Qy + c[a - 1] * (AT(px, py + a) - AT(px, py - a));
+  }
+#define TERM(a, b) \
+  ((c[(a) - 1] * c[(b) - 1]) * (((AT(px + (a), py + (b)) - AT(px - (a), py + (b))) - AT(px + (a), py - (b))) + \
+                                AT(px - (a), py - (b))))
+  float Qxy = TERM(1, 1);
+  for (int b = 1; b <= g; ++b)
+    for (int a = (b == 1 ? 2 : 1); a <= g; ++a) Qxy = Qxy + TERM(a, b);
+#undef TERM
   return ((AT(px, py) + sx * Qx) + sy * Qy) + (sx * sy) * Qxy;
 #undef AT
 }
@@ -802,12 +844,19 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
       cell_coords(P, l - 1, p, &px, &py);
       if (!tp[p] || !tc[child_index(P, l - 1, px, py, 0)]) continue;
       float dmax = 0.0f;
-      for (int h = 0; h < P->q; ++h)
+      for (int h = 0; h < P->q; ++h) {
+        float s2 = 0.0f;
         for (int sigma = 0; sigma < nchildren(P); ++sigma) {
           const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
           const float dd = valf_at(P, v, l, h)[cell_index(P, l, cx, cy)] - predict_f32(P, valf_at(P, v, l - 1, h), l, cx, cy);
-          if (fabsf(dd) > dmax) dmax = fabsf(dd);
+          if (P->metric) s2 = s2 + dd * dd;
+          else if (fabsf(dd) > dmax) dmax = fabsf(dd);
         }
+        if (P->metric) {
+          s2 = ldexpf(s2, -P->dim);
+          if (s2 > dmax) dmax = s2;
+        }
+      }
       Dp[p] = (double)dmax;
     }
   }
@@ -849,7 +898,7 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
  * (indices into level l-1) and weights such that the prediction equals
  * sum_k w[k] F[idx[k]]. Returns the number of terms (3 in 1D, 9 in 2D). */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w) {
-  if (has_walls(P) || P->scheme == 4) return -1;
+  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
   const int n = side(l - 1);
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
@@ -879,7 +928,7 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
 /* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
  * the leaf entries hold the adjoint of the leaf values and all others are 0. */
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
-  if (has_walls(P) || P->scheme == 4) return -1;
+  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
   const double inv = 1.0 / nchildren(P);
   /* Each population is its own linear map: the populations run in parallel,
    * each with the loop order below. */
@@ -916,7 +965,7 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
 /* Transpose of orc_transport (E/A form): adds into the dense `gs` the adjoint of
  * the reconstruction F* from the leaf adjoints `ob` of the transported values. */
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs) {
-  if (has_walls(P) || P->scheme == 4) return -1;
+  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
   const int J = P->jmax, d = P->dim;
   int eta[2 * MAXQ];
   orc_velocities(P, eta);
@@ -1101,7 +1150,7 @@ static int step_precollision(const orc_params *P, const uint8_t *told, const uin
  * adds d/ds into sbar. */
 int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
                      const double *anew, double *aold, double *sbar) {
-  if (has_walls(P) || P->scheme == 4) return -1;
+  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
   const int64_t total = orc_total_cells(P), n = P->q * total;
   double *h = calloc((size_t)n, sizeof(double)), *hb = calloc((size_t)n, sizeof(double));
   double *gs = calloc((size_t)n, sizeof(double));

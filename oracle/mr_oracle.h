@@ -50,7 +50,13 @@ typedef struct {
   /* Evaluation of the incoming values at a wall (eq. AdvectionOnBoundary):
    * 0 directly on the leaf (the paper's choice), 1 by the reconstruction. */
   int bc_eval;
-  int pad2_;
+  /* Prediction stencil half-width gamma = 1, 2 or 3 (Table 1; the grading box
+   * grows with it), and the sibling metric of the details: 0 the max norm of
+   * section "Mesh coarsening", 1 the l2 form of its footnote,
+   * 2^{-d/2} (sum over the siblings of d^2)^{1/2}. */
+  int gamma;
+  int metric;
+  int pad3_;
 } orc_params;
 
 /* Number of cells summed over levels jmin..J, and the offset of level l. */
@@ -73,7 +79,9 @@ int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values);
 double orc_predict(const orc_params *P, const double *parent_level, int l, int cx, int cy);
 
 /* Details: for every parent p at level l-1 whose children are in the tree,
- * D[l-1][p] = max_h max_children |f - prediction|. Other slots are set to -1.
+ * D[l-1][p] = max_h max_children |f - prediction| (metric 0), or
+ * max_h 2^{-d} sum_children (f - prediction)^2, the square of the l2 form
+ * (metric 1; compared with squared thresholds). Other slots are set to -1.
  * `values` must be dense (output of orc_reconstruct). */
 int orc_details(const orc_params *P, const uint8_t *tree, const double *values, double *D);
 

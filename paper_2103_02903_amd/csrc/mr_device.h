@@ -47,6 +47,12 @@ struct Inst {
   // 2 bounce back, 3 anti bounce back, 0 periodic).
   int walls;
   int bck[4];
+  // Prediction stencil half-width gamma (1..3, Table 1; the same for the whole
+  // batch) and the sibling metric of the details: 0 the max norm, 1 the l2
+  // form 2^{-d/2} (sum d^2)^{1/2}, kept squared (eps_l and ref_l are then the
+  // squared thresholds).
+  int gamma;
+  int metric;
 };
 
 // Batch-wide constants (passed by value).
@@ -98,6 +104,14 @@ __device__ __forceinline__ int upper_index(const I *a, int n, long long v) {
 }
 
 // ---------------------------------------------------------------- MR operators
+// Table 1: the coefficients c_1 .. c_gamma of the prediction of half-width
+// gamma (exact dyadic rationals, exact in float as well).
+__host__ __device__ constexpr double table1(int g, int a) {
+  return g == 1 ? -0.125
+         : g == 2 ? (a == 1 ? -22.0 / 128 : 3.0 / 128)
+                  : (a == 1 ? -201.0 / 1024 : (a == 2 ? 11.0 / 256 : -5.0 / 1024));
+}
+
 // Prediction (gamma = 1, c_1 = -1/8): with P the data of level l-1 around the
 // parent (px, py) of a child,
 //   1D: child = P(p) + s_x Qx,                      Qx = c_1 (P(p+1) - P(p-1)),
@@ -106,11 +120,41 @@ __device__ __forceinline__ int upper_index(const I *a, int n, long long v) {
 // with s = +1 for the lower child and -1 for the upper one along each axis
 // (tensor product of the 1D operator). The evaluation order is part of the
 // contract: details decide the mesh, which must not depend on rounding order.
-// `walls` (Inst::walls) selects reflection instead of wrap per axis.
+// `walls` (Inst::walls) selects reflection instead of wrap per axis. With
+// gamma > 1 (Table 1): Qx = c_1 (P(+1) - P(-1)), then + c_a (P(+a) - P(-a)) for
+// a = 2..gamma; Qy alike; Qxy the sum of c_a c_b (((P(+a,+b) - P(-a,+b)) -
+// P(+a,-b)) + P(-a,-b)) starting with (a, b) = (1, 1), then b = 1, a = 2..gamma,
+// then b = 2..gamma, a = 1..gamma.
 template <int DIM, typename T>
 struct ParentStencil {
   T c, qx, qy, qxy;
-  __device__ __forceinline__ void load(const T *__restrict__ P, int lp, int px, int py, int walls) {
+  __device__ __noinline__ void load_wide(const T *__restrict__ P, int lp, int px, int py, int walls, int g) {
+    const bool wx = walls & 1, wy = walls & 2;
+    auto at = [&](int a, int b) -> T {
+      return DIM == 1 ? P[axl(px + a, lp, wx)] : P[cidx<2>(lp, axl(px + a, lp, wx), axl(py + b, lp, wy))];
+    };
+    c = at(0, 0);
+    qx = T(table1(g, 1)) * (at(1, 0) - at(-1, 0));
+    for (int a = 2; a <= g; ++a) qx = qx + T(table1(g, a)) * (at(a, 0) - at(-a, 0));
+    if (DIM == 1) {
+      qy = T(0);
+      qxy = T(0);
+      return;
+    }
+    qy = T(table1(g, 1)) * (at(0, 1) - at(0, -1));
+    for (int b = 2; b <= g; ++b) qy = qy + T(table1(g, b)) * (at(0, b) - at(0, -b));
+    auto term = [&](int a, int b) -> T {
+      return T(table1(g, a) * table1(g, b)) * (((at(a, b) - at(-a, b)) - at(a, -b)) + at(-a, -b));
+    };
+    qxy = term(1, 1);
+    for (int b = 1; b <= g; ++b)
+      for (int a = (b == 1 ? 2 : 1); a <= g; ++a) qxy = qxy + term(a, b);
+  }
+  __device__ __forceinline__ void load(const T *__restrict__ P, int lp, int px, int py, int walls, int g = 1) {
+    if (g > 1) {
+      load_wide(P, lp, px, py, walls, g);
+      return;
+    }
     const T c1 = T(-0.125);
     const bool wx = walls & 1, wy = walls & 2;
     if (DIM == 1) {
@@ -138,9 +182,9 @@ struct ParentStencil {
 };
 
 template <int DIM, typename T>
-__device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy, int walls) {
+__device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy, int walls, int g) {
   ParentStencil<DIM, T> s;
-  s.load(P, l - 1, cx >> 1, cy >> 1, walls);
+  s.load(P, l - 1, cx >> 1, cy >> 1, walls, g);
   return s.child(cx & 1, cy & 1);
 }
 

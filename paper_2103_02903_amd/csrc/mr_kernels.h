@@ -216,7 +216,7 @@ __device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const In
     const uint32_t c = lst[s.beg[i] + item] & CELL_MASK;
     int x, y;
     coords<DIM>(l, c, x, y);
-    F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y, I[i].walls);
+    F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y, I[i].walls, I[i].gamma);
   }
 }
 template <int DIM, int Q, typename T>
@@ -309,10 +309,32 @@ __global__ void __launch_bounds__(64 * Q) k_pair(Batch bt, const Inst<T> *__rest
 }
 
 // ---------------------------------------------------------------- mesh adaptation
-// Details and the sibling l-infinity metric over all populations (section "Mesh
+// The sibling metric of one population's details d = f(child) - prediction,
+// children in the order (0,0), (1,0), (0,1), (1,1): the max of |d| (metric 0),
+// or the square of the l2 form of the footnote in section "Mesh coarsening",
+// 2^{-d} (((d00^2 + d10^2) + d01^2) + d11^2) (metric 1).
+template <int DIM, typename T>
+__device__ __forceinline__ T sibling_metric(const ParentStencil<DIM, T> &st, const T *__restrict__ C, int l, int px,
+                                            int py, int metric) {
+  T m = T(0);
+  for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const T d = C[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
+      if (metric) {
+        m = m + d * d;
+      } else {
+        const T a = d < T(0) ? -d : d;
+        m = a > m ? a : m;
+      }
+    }
+  return metric ? (T)ldexp(m, -DIM) : m;
+}
+
+// Details and the sibling metric over all populations (section "Mesh
 // coarsening"), per internal cell p (level l-1) of the old tree: keep the
 // children (T_eps, eq. Thresholding) if the metric reaches eps_l, flag the group
-// for refinement (H_eps) if it reaches 2^{mu_bar + d} eps_l.
+// for refinement (H_eps) if it reaches 2^{mu_bar + d} eps_l (both squared for
+// the l2 metric).
 template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ F,
                                                     const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
@@ -334,14 +356,8 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
       int px, py;
       coords<DIM>(lp, e & CELL_MASK, px, py);
       ParentStencil<DIM, T> st;
-      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py, I[i].walls);
-      const T *C = F + foff(I[i], DIM, Q, l, h);
-      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-        for (int dx = 0; dx < 2; ++dx) {
-          const T d = C[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
-          const T a = d < T(0) ? -d : d;
-          dmax = a > dmax ? a : dmax;
-        }
+      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py, I[i].walls, I[i].gamma);
+      dmax = sibling_metric<DIM, T>(st, F + foff(I[i], DIM, Q, l, h), l, px, py, I[i].metric);
     }
     dm[h][lane] = dmax;
     __syncthreads();
@@ -394,15 +410,8 @@ __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *_
 #pragma unroll
     for (int h = 0; h < Q; ++h) {
       ParentStencil<DIM, T> st;
-      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py, In.walls);
-      const T *C = F + foff(In, DIM, Q, l, h);
-      T dmax = T(0);
-      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-        for (int dx = 0; dx < 2; ++dx) {
-          const T d = C[cidx<DIM>(l, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
-          const T a = d < T(0) ? -d : d;
-          dmax = a > dmax ? a : dmax;
-        }
+      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py, In.walls, In.gamma);
+      const T dmax = sibling_metric<DIM, T>(st, F + foff(In, DIM, Q, l, h), l, px, py, In.metric);
       D = h == 0 ? dmax : (dmax > D ? dmax : D);
     }
     if (D >= In.eps_l[l]) {
@@ -630,7 +639,8 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   // beyond a wall there is no parent: the box is clipped there
   const int np = 1 << lp;
   const bool wx = WALLS && (In.walls & 1), wy = WALLS && DIM == 2 && (In.walls & 2);
-  if ((((uintptr_t)tl) & 3u) == 0) {
+  const int g = In.gamma;
+  if (g == 1 && (((uintptr_t)tl) & 3u) == 0) {
     // children columns 2x-2 .. 2x+3 of a row: two aligned words (rows of level
     // l >= 2 hold a multiple of 4 cells); pairs -1, 0, +1 at bytes sh .. sh+5
     const int wa = wrapl(2 * x - 2, l) & ~3, wb = wrapl(wa + 4, l), sh = 8 * ((2 * x - 2) & 3);
@@ -647,8 +657,9 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
       }
     }
   } else {
-    for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
-      for (int a = -1; a <= 1; ++a) {
+    // box of half-width gamma around the cell (a parent of level l-1)
+    for (int b = (DIM == 2 ? -g : 0); b <= (DIM == 2 ? g : 0); ++b)
+      for (int a = -g; a <= g; ++a) {
         if (WALLS && ((wx && (x + a < 0 || x + a >= np)) || (wy && (y + b < 0 || y + b >= np)))) continue;
         const int px = wrapl(x + a, lp), py = DIM == 2 ? wrapl(y + b, lp) : 0;
         bool any = false;
@@ -723,7 +734,7 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         coords<DIM>(l, c, x, y);
         T v[Q];
 #pragma unroll
-        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
+        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
 #pragma unroll
         for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
       }
@@ -733,7 +744,7 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         const uint32_t c = lst[b + item] & CELL_MASK;
         int x, y;
         coords<DIM>(l, c, x, y);
-        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
+        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
       }
     }
     __syncthreads();
@@ -957,6 +968,45 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> 
   const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
   if (c0 >= ncells_d(DIM, l) || l > active_top(act, I[i], i)) return;
   ghost_run4<DIM, T>(I[i], code, l, c0);
+}
+
+// The same classification for a prediction of half-width gamma > 1: a cell
+// outside the tree is a ghost if a leaf of its level lies within 2 gamma of it
+// (the transport box of that leaf) or if a ghost of level l+1 has its parent
+// within gamma of it (the prediction of that ghost). Four consecutive cells per
+// thread, plain loops (boxes wrap periodically; with walls this marks a
+// superset of the cells read, whose reads stay inside the domain).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLK) k_classify_ghost_wide(Batch bt, const Inst<T> *__restrict__ I,
+                                                             uint8_t *__restrict__ code,
+                                                             const uint32_t *__restrict__ info, int l,
+                                                             const int *__restrict__ act) {
+  const uint32_t w = info[blockIdx.x];
+  const int i = (int)(w & 0xffu);
+  const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
+  const Inst<T> &In = I[i];
+  const long long nl = ncells_d(DIM, l);
+  if (c0 >= nl || l > active_top(act, In, i)) return;
+  const int g = In.gamma, R = 2 * g;
+  uint8_t *cl = code + In.loff[l];
+  const uint8_t *cf = l < In.jmax ? code + In.loff[l + 1] : nullptr;
+  for (long long c = c0; c < c0 + 4 && c < nl; ++c) {
+    if (cl[c] != C_NONE) continue;
+    int x, y;
+    coords<DIM>(l, (uint32_t)c, x, y);
+    bool need = false;
+    for (int b = (DIM == 2 ? -R : 0); b <= (DIM == 2 ? R : 0) && !need; ++b)
+      for (int a = -R; a <= R && !need; ++a)
+        need = cl[cidx<DIM>(l, wrapl(x + a, l), wrapl(y + b, l))] == C_LEAF;
+    if (cf)
+      for (int b = (DIM == 2 ? -g : 0); b <= (DIM == 2 ? g : 0) && !need; ++b)
+        for (int a = -g; a <= g && !need; ++a) {
+          const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
+          for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+            for (int dx = 0; dx < 2; ++dx) need |= cf[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] == C_GHOST;
+        }
+    if (need) cl[c] = C_GHOST;
+  }
 }
 
 // Byte flags (0/1) of the codes equal to C_LEAF, C_GHOST and C_NONE in a word.
@@ -1365,7 +1415,7 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     int x, y;
     coords<DIM>(l, (uint32_t)c, x, y);
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
   }
 }
 
@@ -1463,18 +1513,20 @@ __device__ __forceinline__ unsigned refined_neighbours(const uint8_t *__restrict
   return nbr;
 }
 
-// ---------------------------------------------------------------- walls
-// Tables of the leaves next to a wall (section "Boundary conditions"), per
-// n - 1 and wall case wc = cx + 3 cy (per axis 0: the leaf touches no wall of
-// that axis, 1: the lower one, 2: the upper one): W and C as for the periodic
-// leaves with the finest cells of E beyond the walls left out, and the number
-// of those cells beyond the x wall and (x inside) beyond the y wall. Those
-// cells take the side's condition evaluated on the leaf itself (eq.
-// AdvectionOnBoundary, direct evaluation).
+// ---------------------------------------------------------------- walls, wide stencils
+// Tables of the general transport path, per n - 1 and wall case wc = cx + 3 cy
+// (per axis 0: the leaf touches no wall of that axis, 1: the lower one, 2: the
+// upper one): W over the leaf-level box of half-width R = 2 gamma ((2R+1)^d
+// entries) and C over the children offsets -R .. R+1 from 2k ((2R+2)^d), as
+// for the periodic leaves but with the finest cells of E beyond the walls left
+// out, and the number of those cells beyond the x wall and (x inside) beyond
+// the y wall. Those cells take the side's condition evaluated on the leaf
+// itself (section "Boundary conditions", eq. AdvectionOnBoundary, direct
+// evaluation). Case 0 holds the periodic tables of the batch's gamma.
 template <typename T>
 struct WallTabs {
-  const T *W;  // [nmax][9][q][WS]
-  const T *C;  // [nmax][9][q][CS]
+  const T *W;  // [nmax][9][q][(2R+1)^d]
+  const T *C;  // [nmax][9][q][(2R+2)^d]
   const T *N;  // [nmax][9][q][2]
 };
 
@@ -1494,28 +1546,29 @@ __device__ __forceinline__ T wall_value(int kind, int h, const T *__restrict__ F
   return kind == 3 ? -v : v;
 }
 
-// A leaf whose 5^d transport box reaches beyond a wall (it lies within two
-// cells of it): the box is read with reflection, which reproduces the
-// reconstruction of the mirrored problem.
+// A leaf whose transport box (half-width 2 gamma) reaches beyond a wall: the
+// box is read with reflection, which reproduces the reconstruction of the
+// mirrored problem.
 template <int DIM, typename T>
 __device__ __forceinline__ bool near_wall(const Inst<T> &In, int l, int x, int y) {
-  const int n = 1 << l;
-  return ((In.walls & 1) && (x < 2 || x > n - 3)) || (DIM == 2 && (In.walls & 2) && (y < 2 || y > n - 3));
+  const int n = 1 << l, R = 2 * In.gamma;
+  return ((In.walls & 1) && (x < R || x > n - 1 - R)) || (DIM == 2 && (In.walls & 2) && (y < R || y > n - 1 - R));
 }
 
-// Population h of a leaf of an instance with walls (any position): the same
-// sums as transport_pop, with every index reflected at a wall, the neighbours
-// beyond a wall mirrored (a refined mirrored neighbour contributes the details
-// of the mirrored children), the tables of the leaf's wall case, and the
-// incoming values from beyond the walls. Fl0 / Ff0 point at population 0 of
+// Population h of a leaf by the general path (walls at any position, or a
+// prediction of half-width gamma > 1): the sums of transport_pop over the box
+// of half-width R = 2 gamma with every index reflected at a wall, detail
+// corrections from the neighbours within gamma that are refined one level
+// further (beyond a wall mirrored: a refined mirrored neighbour contributes the
+// details of the mirrored children), the tables of the leaf's wall case, and
+// the incoming values from beyond the walls. Fl0 / Ff0 point at population 0 of
 // levels l and l+1, cl at the codes of level l.
 template <int DIM, int SCHEME, typename T>
 __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
                                                       const T *__restrict__ Fl0, const T *__restrict__ Ff0,
-                                                      const uint8_t *__restrict__ cl, const T *__restrict__ Wt,
-                                                      const T *__restrict__ Ct, WallTabs<T> wt) {
+                                                      const uint8_t *__restrict__ cl, WallTabs<T> wt) {
   using V = Vel<SCHEME>;
-  constexpr int Q = V::Q, WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  constexpr int Q = V::Q;
   const int ex = V::ex(h), ey = V::ey(h), J = In.jmax, n = J - l, N = 1 << l;
   const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
   const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
@@ -1531,32 +1584,33 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
   }
   const int cx = wx ? (x == 0 ? 1 : (x == N - 1 ? 2 : 0)) : 0;
   const int cy = wy ? (y == 0 ? 1 : (y == N - 1 ? 2 : 0)) : 0;
-  const int wc = cx + 3 * cy, nn = n - 1;
-  const T *W = wc ? wt.W + (((long long)nn * 9 + wc) * Q + h) * WS : Wt + ((long long)nn * Q + h) * WS;
-  const T *Cw = wc ? wt.C + (((long long)nn * 9 + wc) * Q + h) * CS : Ct + ((long long)nn * Q + h) * CS;
+  const int wc = cx + 3 * cy, nn = n - 1, g = In.gamma, R = 2 * g, WW = 2 * R + 1, CW = 2 * R + 2;
+  const int WSg = DIM == 2 ? WW * WW : WW, CSg = DIM == 2 ? CW * CW : CW;
+  const T *W = wt.W + (((long long)nn * 9 + wc) * Q + h) * WSg;
+  const T *Cw = wt.C + (((long long)nn * 9 + wc) * Q + h) * CSg;
   T acc = T(0);
-  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b) {
+  for (int b = (DIM == 2 ? -R : 0); b <= (DIM == 2 ? R : 0); ++b) {
     const long long row = DIM == 2 ? ((long long)axl(y + b, l, wy) << l) : 0;
-    for (int a = -2; a <= 2; ++a)
-      acc = fma(W[DIM == 2 ? (b + 2) * 5 + a + 2 : a + 2], Fl[row + axl(x + a, l, wx)], acc);
+    for (int a = -R; a <= R; ++a)
+      acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + axl(x + a, l, wx)], acc);
   }
   // neighbours refined one level further, mirrored beyond a wall
   const T *Ff = Ff0 + (long long)h * nf;
-  for (int b = (DIM == 2 ? -1 : 0); b <= (DIM == 2 ? 1 : 0); ++b)
-    for (int a = -1; a <= 1; ++a) {
+  for (int b = (DIM == 2 ? -g : 0); b <= (DIM == 2 ? g : 0); ++b)
+    for (int a = -g; a <= g; ++a) {
       if (a == 0 && b == 0) continue;
       const int vx = x + a, vy = y + b;
       const bool mx = wx && (vx < 0 || vx >= N), my = wy && (vy < 0 || vy >= N);
       const int px = axl(vx, l, wx), py = DIM == 2 ? axl(vy, l, wy) : 0;
       if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
       ParentStencil<DIM, T> st;
-      st.load(Fl, l, px, py, In.walls);
+      st.load(Fl, l, px, py, In.walls, In.gamma);
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
         for (int dx = 0; dx < 2; ++dx) {
           const int rx = mx ? 1 - dx : dx, ry = my ? 1 - dy : dy;  // the real child the virtual one mirrors
           const T d = Ff[cidx<DIM>(l + 1, 2 * px + rx, 2 * py + ry)] - st.child(rx, ry);
-          const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
-          acc = fma(Cw[y2 * 6 + y1], d, acc);
+          const int y1 = 2 * a + dx + R, y2 = DIM == 2 ? 2 * b + dy + R : 0;
+          acc = fma(Cw[y2 * CW + y1], d, acc);
         }
     }
   if (wc) {  // the finest cells of E beyond the walls
@@ -1572,8 +1626,7 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
 template <int DIM, int SCHEME, typename T>
 __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, int l, uint32_t c,
                                                            const T *__restrict__ Fs, T *__restrict__ Fo,
-                                                           const uint8_t *__restrict__ code, const T *__restrict__ Wt,
-                                                           const T *__restrict__ Ct, WallTabs<T> wt,
+                                                           const uint8_t *__restrict__ code, WallTabs<T> wt,
                                                            T *__restrict__ tape) {
   constexpr int Q = Vel<SCHEME>::Q;
   int x, y;
@@ -1583,7 +1636,7 @@ __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, in
   T f[Q];
 #pragma unroll
   for (int h = 0; h < Q; ++h)
-    f[h] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], Wt, Ct, wt);
+    f[h] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
   if (tape)
 #pragma unroll
     for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
@@ -1595,7 +1648,7 @@ __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, in
 // Variant for small leaf sets: wavefront h transports population h of 64 leaves
 // (nine times the parallelism), the collision of each leaf then runs in
 // wavefront 0 through LDS.
-template <int DIM, int SCHEME, typename T, bool WALLS>
+template <int DIM, int SCHEME, typename T, int MODE>
 __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     k_transport_collide_pop(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                             const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
@@ -1635,9 +1688,9 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      if (WALLS && I[i].walls && near_wall<DIM>(I[i], l, x, y))
+      if (MODE == 2 || (MODE == 1 && I[i].walls && near_wall<DIM>(I[i], l, x, y)))
         fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
-                                                     n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, Wt, Ct, wt);
+                                                     n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
       else
         fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
                                                     Ct + ((long long)nn * Q + h) * CS, nbr);
@@ -1887,7 +1940,7 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
 // budget for 4 waves per SIMD (latency hiding of the stencil loads). A chunk
 // whose leaves share one level (all but those that straddle a level boundary)
 // takes leaf_update_level, in row mode when its leaves are one row segment.
-template <int DIM, int SCHEME, typename T, bool WALLS>
+template <int DIM, int SCHEME, typename T, int MODE>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
@@ -1913,10 +1966,10 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint32_t c = e & CELL_MASK;
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
-    // leaves whose transport box reaches beyond a wall take the wall path (a
-    // variant of the kernel launched only for batches with walls)
-    bool wall = false;
-    if constexpr (WALLS) {
+    // MODE 0: periodic, gamma = 1 (no general path); 1: leaves whose transport
+    // box reaches beyond a wall take the general path; 2 (gamma > 1): every leaf
+    bool wall = MODE == 2 && valid;
+    if constexpr (MODE == 1) {
       int x, y;
       coords<DIM>(l, c, x, y);
       wall = valid && I[i].walls && near_wall<DIM>(I[i], l, x, y);
@@ -1927,8 +1980,8 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
                      (c0 & ((1u << l0) - 1)) + 63u < (1u << l0) && __ballot(wall) == 0;
     if (!valid) continue;
     const Inst<T> &In = I[i];
-    if (WALLS && wall)
-      leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, wt, tape);
+    if (MODE != 0 && wall)
+      leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, wt, tape);
     else if (one_level)
       leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);
     else
@@ -2064,7 +2117,7 @@ __global__ void __launch_bounds__(BLK) k_predict_outside(const Inst<T> *__restri
     coords<DIM>(l, (uint32_t)c, x, y);
 #pragma unroll
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls);
+      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
   }
 }
 

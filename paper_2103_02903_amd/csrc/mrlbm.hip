@@ -52,7 +52,9 @@ int validate_one(const mrlbm_params *p) {
   if (p->precision != 4 && p->precision != 8) return MRLBM_ERR_INVALID;
   if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return MRLBM_ERR_INVALID;
   if (!(p->eps >= 0.0)) return MRLBM_ERR_INVALID;
-  if (!(p->mu_bar >= 0.0 && p->mu_bar <= 3.0)) return MRLBM_ERR_INVALID;
+  const int g = p->gamma == 0 ? 1 : p->gamma;
+  if (g < 1 || g > 3 || (p->metric != MRLBM_METRIC_MAX && p->metric != MRLBM_METRIC_L2)) return MRLBM_ERR_INVALID;
+  if (!(p->mu_bar >= 0.0 && p->mu_bar <= 2 * g + 1)) return MRLBM_ERR_INVALID;
   for (int i = 0; i < scheme_q(p->scheme); ++i) {
     if (!std::isfinite(p->s[i])) return MRLBM_ERR_INVALID;
     if (conserved(p->scheme, i) && p->s[i] != 0.0) return MRLBM_ERR_INVALID;
@@ -62,9 +64,13 @@ int validate_one(const mrlbm_params *p) {
   for (int a = 0; a < 2; ++a)  // an axis is periodic on both sides or walled on both
     if ((p->bc[2 * a] == MRLBM_PERIODIC) != (p->bc[2 * a + 1] == MRLBM_PERIODIC)) return MRLBM_ERR_INVALID;
   if (dim == 1 && (p->bc[2] != MRLBM_PERIODIC || p->bc[3] != MRLBM_PERIODIC)) return MRLBM_ERR_INVALID;
+  // one reflection at a wall covers the widest read (2 gamma cells) of the coarsest level
+  if (p->bc[0] != MRLBM_PERIODIC || p->bc[2] != MRLBM_PERIODIC)
+    if ((1 << p->jmin) < 2 * g) return MRLBM_ERR_INVALID;
   return MRLBM_OK;
 }
 int walls_of(const mrlbm_params *p) { return (p->bc[0] ? 1 : 0) | (p->bc[2] ? 2 : 0); }
+int gamma_of(const mrlbm_params *p) { return p->gamma == 0 ? 1 : p->gamma; }
 
 int validate(const mrlbm_params *p, int batch) {
   if (!p || batch < 1 || batch > MAXB) return MRLBM_ERR_INVALID;
@@ -72,7 +78,8 @@ int validate(const mrlbm_params *p, int batch) {
   for (int i = 0; i < batch; ++i) {
     const int rc = validate_one(&p[i]);
     if (rc) return rc;
-    if (p[i].scheme != p[0].scheme || p[i].precision != p[0].precision || p[i].jmin != p[0].jmin)
+    if (p[i].scheme != p[0].scheme || p[i].precision != p[0].precision || p[i].jmin != p[0].jmin ||
+        gamma_of(&p[i]) != gamma_of(&p[0]))
       return MRLBM_ERR_INVALID;
     for (int l = p[i].jmin; l <= p[i].jmax; ++l) cells += 1ll << (scheme_dim(p[i].scheme) * l);
   }
@@ -81,66 +88,93 @@ int validate(const mrlbm_params *p, int batch) {
 }
 
 // ---------------------------------------------------------------- transport weights
-// Reconstruction of an impulse placed on one cell of a coarse level, n levels
-// down, by repeated 1D prediction (gamma = 1). `v` covers indices [lo, lo+size).
-void predict_down(std::vector<double> &v, long long &lo, int n) {
-  for (int k = 0; k < n; ++k) {
-    const long long sz = (long long)v.size();
-    std::vector<double> w(2 * sz, 0.0);
-    auto at = [&](long long i) { return (i < 0 || i >= sz) ? 0.0 : v[i]; };
-    for (long long i = 0; i < sz; ++i) {
-      const double q = -0.125 * (at(i + 1) - at(i - 1));
-      w[2 * i] = v[i] + q;
-      w[2 * i + 1] = v[i] - q;
+// Coefficients c_1 .. c_gamma of the prediction of half-width gamma (Table 1).
+double table1_coef(int g, int a) {
+  static const double c[4][3] = {{0, 0, 0}, {-0.125, 0, 0}, {-22.0 / 128, 3.0 / 128, 0},
+                                 {-201.0 / 1024, 11.0 / 256, -5.0 / 1024}};
+  return c[g][a - 1];
+}
+
+// Value at finest index i of the reconstruction, m levels down, of a unit
+// impulse on cell a of a coarse level, by repeated 1D prediction of half-width
+// g: each level is computed on the window of cells that the levels below read.
+long long floor_half(long long j) { return j >= 0 ? j / 2 : -((1 - j) / 2); }
+double impulse_value(int g, int m, int a, long long i) {
+  std::vector<long long> lo(m + 1), hi(m + 1);
+  lo[m] = hi[m] = i;
+  for (int k = m; k > 0; --k) {
+    lo[k - 1] = floor_half(lo[k]) - g;
+    hi[k - 1] = floor_half(hi[k]) + g;
+  }
+  std::vector<double> v((size_t)(hi[0] - lo[0] + 1));
+  for (long long k = lo[0]; k <= hi[0]; ++k) v[(size_t)(k - lo[0])] = k == a ? 1.0 : 0.0;
+  for (int k = 1; k <= m; ++k) {
+    std::vector<double> w((size_t)(hi[k] - lo[k] + 1));
+    const long long pl = lo[k - 1];
+    auto at = [&](long long t) { return v[(size_t)(t - pl)]; };
+    for (long long j = lo[k]; j <= hi[k]; ++j) {
+      const long long p = floor_half(j);
+      double q = table1_coef(g, 1) * (at(p + 1) - at(p - 1));
+      for (int b = 2; b <= g; ++b) q = q + table1_coef(g, b) * (at(p + b) - at(p - b));
+      w[(size_t)(j - lo[k])] = (j & 1) ? at(p) - q : at(p) + q;
     }
     v.swap(w);
-    lo *= 2;
   }
+  return v[0];
 }
 
-// Sum over the finest cells [-e, 2^n - e) (the leaf's finest cells shifted by
-// -e) of the reconstruction of a unit impulse at cell `a` of level J - m
-// (the leaf covers [0, 2^n) finest cells, n >= m). A leaf touching a wall
-// (wall = 1: the lower one, at finest cell 0; 2: the upper one, at 2^n) sums
-// only the cells on its side of it.
-double impulse_sum(int n, int m, int e, int a, int wall = 0) {
-  const long long pad = 8;
-  std::vector<double> v(2 * pad + 1, 0.0);
-  long long lo = -pad;
-  v[a - lo] = 1.0;
-  predict_down(v, lo, m);
-  double s = 0.0;
-  long long b0 = -e, b1 = (1ll << n) - e;
-  if (wall == 1) b0 = std::max(b0, 0ll);
-  if (wall == 2) b1 = std::min(b1, 1ll << n);
-  for (long long i = b0; i < b1; ++i) {
-    const long long k = i - lo;
-    if (k >= 0 && k < (long long)v.size()) s += v[k];
+// Sums of the reconstruction of a unit impulse at cell `a` of level J - m over
+// ranges of finest cells. The prediction keeps the sum of each pair of children
+// equal to twice their parent, so a whole block of 2^m finest cells under a
+// coarse cell k sums to 2^m [k == a]; a range that differs from whole blocks by
+// a cell at either end adds or takes that cell's value.
+struct ImpulseSums {
+  int g;
+  explicit ImpulseSums(int gamma) : g(gamma) {}
+  // Sum over the finest cells [-e, 2^n - e) (the leaf's finest cells shifted by
+  // -e, |e| <= 1; the leaf covers [0, 2^n) finest cells, n >= m). A leaf
+  // touching a wall (wall = 1: the lower one, at finest cell 0; 2: the upper
+  // one, at 2^n) sums only the cells on its side of it.
+  double sum(int n, int m, int e, int a, int wall = 0) {
+    const long long N = 1ll << n;
+    long long b0 = -e, b1 = N - e;
+    if (wall == 1) b0 = std::max(b0, 0ll);
+    if (wall == 2) b1 = std::min(b1, N);
+    double s = (a >= 0 && a < (1ll << (n - m))) ? std::ldexp(1.0, m) : 0.0;
+    for (long long i = b0; i < 0; ++i) s += impulse_value(g, m, a, i);
+    for (long long i = 0; i < b0; ++i) s -= impulse_value(g, m, a, i);
+    for (long long i = N; i < b1; ++i) s += impulse_value(g, m, a, i);
+    for (long long i = b1; i < N; ++i) s -= impulse_value(g, m, a, i);
+    return s;
   }
-  return s;
-}
+};
 
-// W[h][25] and C[h][36] of a leaf n >= 1 levels above the finest (see header).
-// With a wall case (per axis 0 none, 1 the leaf touches the lower wall, 2 the
-// upper one) the sums over E leave out the finest cells beyond the walls
-// (E minus those cells is still a box: (B - eta) clipped to the domain), and
-// N[h][2] receives how many of those cells lie beyond the x wall and, with x
-// inside, beyond the y wall.
-void transport_tables(int scheme, int n, double *W, double *C, int wx = 0, int wy = 0, double *N = nullptr) {
-  const int q = scheme_q(scheme), dim = scheme_dim(scheme);
+// W[h][(2R+1)^2] and C[h][(2R+2)^2], R = 2 gamma, of a leaf n >= 1 levels
+// above the finest (see header; a 1D scheme uses the middle rows). With a wall
+// case (per axis 0 none, 1 the leaf touches the lower wall, 2 the upper one)
+// the sums over E leave out the finest cells beyond the walls (E minus those
+// cells is still a box: (B - eta) clipped to the domain), and N[h][2] receives
+// how many of those cells lie beyond the x wall and, with x inside, beyond the
+// y wall.
+void transport_tables(int scheme, int n, double *W, double *C, int wx = 0, int wy = 0, double *N = nullptr,
+                      int g = 1, ImpulseSums *cache = nullptr) {
+  const int q = scheme_q(scheme), dim = scheme_dim(scheme), R = 2 * g, WW = 2 * R + 1, CW = 2 * R + 2;
+  ImpulseSums own(g);
+  ImpulseSums &is = cache ? *cache : own;
   for (int h = 0; h < q; ++h) {
     int ex, ey;
     scheme_eta(scheme, h, ex, ey);
-    double Sx[5], Sy[5], Tx[6], Ty[6];
-    for (int a = -2; a <= 2; ++a) {
-      Sx[a + 2] = impulse_sum(n, n, ex, a, wx);
-      Sy[a + 2] = dim == 2 ? impulse_sum(n, n, ey, a, wy) : (a == 0 ? 1.0 : 0.0);
+    double Sx[13], Sy[13], Tx[14], Ty[14];
+    for (int a = -R; a <= R; ++a) {
+      Sx[a + R] = is.sum(n, n, ex, a, wx);
+      Sy[a + R] = dim == 2 ? is.sum(n, n, ey, a, wy) : (a == 0 ? 1.0 : 0.0);
     }
-    // detail impulses live one level below the leaf, on cells 2k + y, y in [-2, 3];
-    // the leaf's range is then [0, 2) cells of that level = [0, 2^n) finest cells
-    for (int y = -2; y <= 3; ++y) {
-      Tx[y + 2] = impulse_sum(n, n - 1, ex, y, wx);
-      Ty[y + 2] = dim == 2 ? impulse_sum(n, n - 1, ey, y, wy) : (y == 0 ? 1.0 : 0.0);
+    // detail impulses live one level below the leaf, on cells 2k + y, y in
+    // [-R, R+1]; the leaf's range is then [0, 2) cells of that level = [0, 2^n)
+    // finest cells
+    for (int y = -R; y <= R + 1; ++y) {
+      Tx[y + R] = is.sum(n, n - 1, ex, y, wx);
+      Ty[y + R] = dim == 2 ? is.sum(n, n - 1, ey, y, wy) : (y == 0 ? 1.0 : 0.0);
     }
     if (N) {  // positions of [-e, 2^n - e) beyond the touched wall, per axis
       const double w = std::ldexp(1.0, n);
@@ -152,18 +186,22 @@ void transport_tables(int scheme, int n, double *W, double *C, int wx = 0, int w
     }
     const double full = std::ldexp(1.0, dim * n);
     const bool rest = ex == 0 && ey == 0;
-    for (int b = -2; b <= 2; ++b)
-      for (int a = -2; a <= 2; ++a) {
-        double w = Sx[a + 2] * Sy[b + 2];
+    for (int b = -R; b <= R; ++b)
+      for (int a = -R; a <= R; ++a) {
+        double w = Sx[a + R] * Sy[b + R];
         if (a == 0 && b == 0) w -= rest ? w : full;  // E - A form; rest velocity: 0
-        W[h * 25 + (b + 2) * 5 + (a + 2)] = w;
+        W[h * WW * WW + (b + R) * WW + (a + R)] = w;
       }
-    for (int y2 = -2; y2 <= 3; ++y2)
-      for (int y1 = -2; y1 <= 3; ++y1) C[h * 36 + (y2 + 2) * 6 + (y1 + 2)] = rest ? 0.0 : Tx[y1 + 2] * Ty[y2 + 2];
+    for (int y2 = -R; y2 <= R + 1; ++y2)
+      for (int y1 = -R; y1 <= R + 1; ++y1)
+        C[h * CW * CW + (y2 + R) * CW + (y1 + R)] = rest ? 0.0 : Tx[y1 + R] * Ty[y2 + R];
   }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+// Entries per population of the general path's tables: (4 gamma + 1)^d and (4 gamma + 2)^d.
+int wide_ws(int dim, int g) { return dim == 2 ? (4 * g + 1) * (4 * g + 1) : 4 * g + 1; }
+int wide_cs(int dim, int g) { return dim == 2 ? (4 * g + 2) * (4 * g + 2) : 4 * g + 2; }
 
 // Dense per-level passes: cells per block, and the levels they cover
 // (jmin <= L <= jmax - margin): ghost classification with 4 cells per thread
@@ -181,6 +219,7 @@ int dense_margin(int off) { return off == 1 ? 1 : off == 2 ? 2 : 0; }
 // the workspace layout.
 struct Plan {
   int B, dim, q, jmin, maxJ, nmax, nblocks;
+  int gamma;       // prediction half-width, shared by the batch (the transport tables depend on it)
   bool any_walls;  // some instance has walls: the launches take the kernel variants that handle them
   size_t rs;
   long long ctotal;
@@ -207,6 +246,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.jmin = p[0].jmin;
   P.maxJ = 0;
   P.rs = p[0].precision == 8 ? 8 : 4;
+  P.gamma = gamma_of(&p[0]);
   P.inst.assign(B, Inst<double>());
   P.any_walls = false;
   P.cb.assign(B + 1, 0);
@@ -237,7 +277,13 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
     for (int l = 0; l < LVL_STRIDE; ++l) {
       I.eps_l[l] = std::ldexp(p[i].eps, P.dim * (l - p[i].jmax));
       I.ref_l[l] = std::ldexp(I.eps_l[l], P.dim) * std::exp2(p[i].mu_bar);
+      if (p[i].metric == MRLBM_METRIC_L2) {  // the l2 metric is kept squared: squared thresholds
+        I.eps_l[l] *= I.eps_l[l];
+        I.ref_l[l] *= I.ref_l[l];
+      }
     }
+    I.gamma = P.gamma;
+    I.metric = p[i].metric;
     I.sc.lam = p[i].lambda;
     I.sc.inv_lam = 1.0 / p[i].lambda;
     I.sc.eq = p[i].eq_param;
@@ -306,9 +352,9 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   const int ws = P.dim == 2 ? 25 : 5, cs = P.dim == 2 ? 36 : 6;
   P.off_W = take(P.rs * std::max(1, P.nmax) * P.q * ws);
   P.off_C = take(P.rs * std::max(1, P.nmax) * P.q * cs);
-  // tables of the leaves touching a wall: [n - 1][wall case 0..8][h][.]
-  P.off_Wb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * ws);
-  P.off_Cb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * cs);
+  // tables of the general path (walls, gamma > 1): [n - 1][wall case 0..8][h][.]
+  P.off_Wb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * wide_ws(P.dim, P.gamma));
+  P.off_Cb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * wide_cs(P.dim, P.gamma));
   P.off_Nb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * 2);
   P.off_red = take(sizeof(double) * 2 * RED_BLOCKS * B);
   P.off_bad = take(sizeof(int) * 4);
@@ -619,6 +665,16 @@ struct Engine {
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
                                                               c->refg, c->act);
     const int lc = coarse_cap(c);
+    if (P.gamma > 1) {  // wider stencils: one plain pass per level, finest first
+      for (int l = P.maxJ; l > P.jmin; --l) {
+        const int nb = P.dtab_total(0, l);
+        if (nb)
+          k_classify_ghost_wide<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l),
+                                                                   l, c->act);
+      }
+      compact(c, m, code_old, F);
+      return;
+    }
     for (int l = P.maxJ; l > std::max(P.jmin, lc); --l) {
       if (P.ghost16[l]) {
         const int nb = P.dtab_total(3, l);
@@ -799,14 +855,19 @@ struct Engine {
     T *Fn = (T *)c->F[1 - c->cur];
     phase_mark(c, PH_TRANSPORT, true);
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
+    // kernel variant: 0 periodic with gamma = 1, 1 walls (near them the general
+    // path), 2 gamma > 1 (the general path everywhere)
+    const int mode = P.gamma > 1 ? 2 : (P.any_walls ? 1 : 0);
     if (per_leaf(c)) {
-      auto kern = P.any_walls ? k_transport_collide_leaf<DIM, SCHEME, T, true>
-                              : k_transport_collide_leaf<DIM, SCHEME, T, false>;
+      auto kern = mode == 2   ? k_transport_collide_leaf<DIM, SCHEME, T, 2>
+                  : mode == 1 ? k_transport_collide_leaf<DIM, SCHEME, T, 1>
+                              : k_transport_collide_leaf<DIM, SCHEME, T, 0>;
       kern<<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     } else {
-      auto kern = P.any_walls ? k_transport_collide_pop<DIM, SCHEME, T, true>
-                              : k_transport_collide_pop<DIM, SCHEME, T, false>;
+      auto kern = mode == 2   ? k_transport_collide_pop<DIM, SCHEME, T, 2>
+                  : mode == 1 ? k_transport_collide_pop<DIM, SCHEME, T, 1>
+                              : k_transport_collide_pop<DIM, SCHEME, T, 0>;
       kern<<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     }
@@ -1147,6 +1208,8 @@ struct Engine {
       for (int k = 0; k < 16; ++k) d.sc.s[k] = (T)s.sc.s[k];
       d.walls = s.walls;
       for (int k = 0; k < 4; ++k) d.bck[k] = s.bck[k];
+      d.gamma = s.gamma;
+      d.metric = s.metric;
     }
     HIPCHK(hipMemcpy(c->inst, v.data(), sizeof(Inst<T>) * v.size(), hipMemcpyHostToDevice));
     return MRLBM_OK;
@@ -1222,8 +1285,9 @@ bool tree_is_graded(const mrlbm_ctx *c, int inst, const uint8_t *t) {
           }
         if (cnt == 0) continue;
         if (cnt != (1 << d)) return false;
-        for (int b = (d == 2 ? -1 : 0); b <= (d == 2 ? 1 : 0); ++b)
-          for (int a = -1; a <= 1; ++a) {
+        const int g = I.gamma;  // grading box of half-width gamma
+        for (int b = (d == 2 ? -g : 0); b <= (d == 2 ? g : 0); ++b)
+          for (int a = -g; a <= g; ++a) {
             if (((I.walls & 1) && (px + a < 0 || px + a >= np)) || ((I.walls & 2) && (py + b < 0 || py + b >= np)))
               continue;  // no cell beyond a wall
             const int x = (px + a) & (np - 1), y = (py + b) & (np - 1);
@@ -1410,24 +1474,31 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   // transport weight tables, rounded once to the working precision
   const int q = P.q, d = P.dim, ws = d == 2 ? 25 : 5, cs = d == 2 ? 36 : 6;
   const int nn = std::max(1, P.nmax);
+  // (gamma = 1: the fast kernels' periodic tables; unused for gamma > 1)
   std::vector<double> W((size_t)nn * q * ws, 0.0), C((size_t)nn * q * cs, 0.0), w25(q * 25), c36(q * 36);
-  for (int n = 1; n <= P.nmax; ++n) {
-    transport_tables(p[0].scheme, n, w25.data(), c36.data());
+  ImpulseSums imp1(1);
+  for (int n = 1; n <= P.nmax && P.gamma == 1; ++n) {
+    transport_tables(p[0].scheme, n, w25.data(), c36.data(), 0, 0, nullptr, 1, &imp1);
     for (int h = 0; h < q; ++h) {
       for (int k = 0; k < ws; ++k) W[((size_t)(n - 1) * q + h) * ws + k] = d == 2 ? w25[h * 25 + k] : w25[h * 25 + 10 + k];
       for (int k = 0; k < cs; ++k) C[((size_t)(n - 1) * q + h) * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
     }
   }
-  // the same per wall case (index wx + 3 wy); case 0 repeats the periodic tables
-  std::vector<double> Wb((size_t)nn * 9 * q * ws, 0.0), Cb((size_t)nn * 9 * q * cs, 0.0), Nb((size_t)nn * 9 * q * 2, 0.0);
-  std::vector<double> n2(q * 2);
-  for (int n = 1; n <= P.nmax; ++n)
+  // the general path's tables, per wall case (index wx + 3 wy; case 0: no wall
+  // touched, the periodic tables), over the boxes of half-width 2 gamma
+  const int g = P.gamma, R = 2 * g, WW = 2 * R + 1, CW = 2 * R + 2;
+  const int wsg = wide_ws(d, g), csg = wide_cs(d, g);
+  std::vector<double> Wb((size_t)nn * 9 * q * wsg, 0.0), Cb((size_t)nn * 9 * q * csg, 0.0), Nb((size_t)nn * 9 * q * 2, 0.0);
+  std::vector<double> wg((size_t)q * WW * WW), cg((size_t)q * CW * CW), n2(q * 2);
+  ImpulseSums impg(g);
+  for (int n = 1; n <= P.nmax && (P.any_walls || g > 1); ++n)
     for (int wc = 0; wc < (d == 2 ? 9 : 3); ++wc) {
-      transport_tables(p[0].scheme, n, w25.data(), c36.data(), wc % 3, wc / 3, n2.data());
+      transport_tables(p[0].scheme, n, wg.data(), cg.data(), wc % 3, wc / 3, n2.data(), g, &impg);
       for (int h = 0; h < q; ++h) {
         const size_t r = ((size_t)(n - 1) * 9 + wc) * q + h;
-        for (int k = 0; k < ws; ++k) Wb[r * ws + k] = d == 2 ? w25[h * 25 + k] : w25[h * 25 + 10 + k];
-        for (int k = 0; k < cs; ++k) Cb[r * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
+        // a 1D scheme keeps the middle row
+        for (int k = 0; k < wsg; ++k) Wb[r * wsg + k] = wg[(size_t)h * WW * WW + (d == 2 ? k : R * WW + k)];
+        for (int k = 0; k < csg; ++k) Cb[r * csg + k] = cg[(size_t)h * CW * CW + (d == 2 ? k : R * CW + k)];
         Nb[r * 2] = n2[2 * h];
         Nb[r * 2 + 1] = n2[2 * h + 1];
       }
@@ -1714,7 +1785,7 @@ int mrlbm_adjoint_workspace_size(const mrlbm_ctx *c, int nsteps, int ckpt_every,
 int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every) {
   if (!c || !adj_workspace || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
   if (c->P.inst[0].walls) return MRLBM_ERR_INVALID;  // the adjoint covers periodic boundaries
-  if (c->p[0].scheme == MRLBM_D2Q4_EULER) return MRLBM_ERR_INVALID;
+  if (c->p[0].scheme == MRLBM_D2Q4_EULER || c->P.gamma > 1) return MRLBM_ERR_INVALID;
   if (!c->all_ready()) return MRLBM_ERR_STATE;
   if (bytes < adj_layout(c->P, nsteps, ckpt_every).bytes) return MRLBM_ERR_CAPACITY;
   c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);
@@ -1887,6 +1958,23 @@ int mrlbm_transport_tables(int scheme, int n, double *W, double *C) {
   if (scheme < MRLBM_D1Q2 || scheme > MRLBM_D2Q4_EULER || n < 1 || n > 25 || !W || !C) return MRLBM_ERR_INVALID;
   if (scheme_dim(scheme) == 2 && n > 13) return MRLBM_ERR_INVALID;
   transport_tables(scheme, n, W, C);
+  return MRLBM_OK;
+}
+
+int mrlbm_transport_tables_general(int scheme, int n, int gamma, int wall_x, int wall_y, double *W, double *C,
+                                   double *N) {
+  if (scheme < MRLBM_D1Q2 || scheme > MRLBM_D2Q4_EULER || n < 1 || n > 25 || !W || !C || !N) return MRLBM_ERR_INVALID;
+  if (scheme_dim(scheme) == 2 && n > 13) return MRLBM_ERR_INVALID;
+  if (gamma < 1 || gamma > 3 || wall_x < 0 || wall_x > 2 || wall_y < 0 || wall_y > 2) return MRLBM_ERR_INVALID;
+  if (scheme_dim(scheme) == 1 && wall_y) return MRLBM_ERR_INVALID;
+  const int q = scheme_q(scheme), R = 2 * gamma, WW = 2 * R + 1, CW = 2 * R + 2;
+  std::vector<double> w((size_t)q * WW * WW), c((size_t)q * CW * CW);
+  transport_tables(scheme, n, w.data(), c.data(), wall_x, wall_y, N, gamma);
+  const int d = scheme_dim(scheme), ws = wide_ws(d, gamma), cs = wide_cs(d, gamma);
+  for (int h = 0; h < q; ++h) {  // a 1D scheme keeps the middle row
+    for (int k = 0; k < ws; ++k) W[(size_t)h * ws + k] = w[(size_t)h * WW * WW + (d == 2 ? k : R * WW + k)];
+    for (int k = 0; k < cs; ++k) C[(size_t)h * cs + k] = c[(size_t)h * CW * CW + (d == 2 ? k : R * CW + k)];
+  }
   return MRLBM_OK;
 }
 

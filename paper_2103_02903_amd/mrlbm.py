@@ -17,6 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmrlbm.so")
 
 SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3, "D2Q4E": 4}
+METRIC_IDS = {"linf": 0, "l2": 1}  # sibling metric of the details: max norm, or its l2 form
 STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-finite leaf value",
           -4: "HIP runtime error", -5: "call out of order", -6: "device-side wait gave up"}
 FIELDS = {"leaf_table": 1, "populations": 2, "moments": 3, "finest": 4}
@@ -25,7 +26,8 @@ EXPORTS = ["mrlbm_workspace_size", "mrlbm_create", "mrlbm_init_equilibrium", "mr
            "mrlbm_stats", "mrlbm_leaves", "mrlbm_destroy", "mrlbm_status_string", "mrlbm_transport_tables",
            "mrlbm_profile", "mrlbm_read_counters", "mrlbm_adjoint_workspace_size", "mrlbm_forward_record",
            "mrlbm_adjoint", "mrlbm_copy", "mrlbm_autotune", "mrlbm_set_tuning", "mrlbm_get_tuning",
-           "mrlbm_fields", "mrlbm_get_mesh", "mrlbm_step_frozen", "mrlbm_debug_pair_wait", "mrlbm_create_static"]
+           "mrlbm_fields", "mrlbm_get_mesh", "mrlbm_step_frozen", "mrlbm_debug_pair_wait", "mrlbm_create_static",
+           "mrlbm_transport_tables_general"]
 
 
 class MrlbmError(RuntimeError):
@@ -38,7 +40,7 @@ class Params(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 16),
-                ("bc", ctypes.c_int * 4)]
+                ("bc", ctypes.c_int * 4), ("gamma", ctypes.c_int), ("metric", ctypes.c_int)]
 
     @classmethod
     def from_cfg(cls, cfg: dict, precision: int = 8) -> "Params":
@@ -48,7 +50,8 @@ class Params(ctypes.Structure):
         bc = [int(v) for v in cfg.get("bc", (0, 0, 0, 0))]
         return cls(SCHEME_IDS[cfg["scheme"]], int(cfg["jmin"]), int(cfg["jmax"]), int(precision),
                    float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)), float(cfg["eps"]),
-                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s), (ctypes.c_int * 4)(*bc))
+                   float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s), (ctypes.c_int * 4)(*bc),
+                   int(cfg.get("gamma", 1)), METRIC_IDS[cfg.get("metric", "linf")])
 
 
 class Counters(ctypes.Structure):
@@ -89,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "mrlbm_stats": [vp, ci, ctypes.POINTER(ctypes.c_double), vp, vp, vp],
             "mrlbm_leaves": [vp, ci, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
             "mrlbm_destroy": [vp], "mrlbm_transport_tables": [ctypes.c_int, ctypes.c_int, vp, vp],
+            "mrlbm_transport_tables_general": [ci, ci, ci, ci, ci, vp, vp, vp],
             "mrlbm_profile": [vp, ctypes.c_int], "mrlbm_read_counters": [vp, ctypes.POINTER(Counters)],
             "mrlbm_adjoint_workspace_size": [vp, ci, ci, ctypes.POINTER(ctypes.c_size_t)],
             "mrlbm_forward_record": [vp, vp, ctypes.c_size_t, ci, ci],
@@ -130,6 +134,19 @@ def transport_tables(scheme: str, n: int):
     _check("mrlbm_transport_tables",
            lib().mrlbm_transport_tables(SCHEME_IDS[scheme], int(n), W.ctypes.data, C.ctypes.data))
     return W, C
+
+
+def transport_tables_general(scheme: str, n: int, gamma: int = 1, wall_x: int = 0, wall_y: int = 0):
+    """Tables of the general transport path: W[q][(4 gamma + 1)^d],
+    C[q][(4 gamma + 2)^d] and the counts N[q][2] of finest cells beyond the walls."""
+    dim, q, _ = SCHEME_DIMS[scheme]
+    W = np.zeros((q, (4 * gamma + 1) ** dim), np.float64)
+    C = np.zeros((q, (4 * gamma + 2) ** dim), np.float64)
+    N = np.zeros((q, 2), np.float64)
+    _check("mrlbm_transport_tables_general",
+           lib().mrlbm_transport_tables_general(SCHEME_IDS[scheme], int(n), int(gamma), int(wall_x), int(wall_y),
+                                                W.ctypes.data, C.ctypes.data, N.ctypes.data))
+    return W, C, N
 
 
 class Batch:

@@ -27,9 +27,11 @@ BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
 
 
 def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0, lam: float = 1.0,
-           eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0) -> dict:
+           eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0, gamma: int = 1,
+           metric: str = "linf") -> dict:
     """Parameter dictionary. ``bc``: None (periodic) or the kind of each side
-    x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two)."""
+    x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two). ``gamma``:
+    prediction stencil half-width 1..3; ``metric``: "linf" or "l2" sibling metric."""
     dim, q, _ = SCHEME_DIMS[scheme]
     s = [float(v) for v in s]
     assert len(s) == q
@@ -39,7 +41,7 @@ def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0
             codes[k] = BC_KINDS[v] if isinstance(v, str) else int(v)
     return dict(scheme=scheme, dim=dim, q=q, jmin=int(jmin), jmax=int(jmax), eps=float(eps),
                 mu_bar=float(mu_bar), lam=float(lam), eq_param=float(eq_param), s=s,
-                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval))
+                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval), gamma=int(gamma), metric=metric)
 
 
 def cell_centres(jmax: int, domain=(0.0, 1.0)) -> np.ndarray:
@@ -129,24 +131,26 @@ def euler_s(sq=(1.9, 1.75, 1.75, 1.75), sxy=(1.0, 1.0, 1.0, 1.0)) -> list:
     return out
 
 
-def riemann_d2q4e(jmin=2, jmax=8, eps=1e-3, mu_bar=0.0, lam=5.0, gamma=1.4, seed=0, bc="copy"):
+def riemann_d2q4e(jmin=2, jmax=8, eps=1e-3, mu_bar=0.0, lam=5.0, gamma_gas=1.4, seed=0, bc="copy", gamma=1,
+                  metric="linf"):
     """Euler system on [0, 1]^2 with the vectorial D2Q4 scheme (lambda = 5,
     s^q = 1.9 for rho and 1.75 for the others, s^xy = 1) and copy walls: a
     two-dimensional Riemann problem whose four quadrant states (x and y below
     or above 1/2) are drawn from a seeded generator, rho in [0.5, 1.5], u and v
     in [-0.5, 0.5], p in [0.2, 1.5] (a synthetic stand-in for the paper's
-    configurations, whose states it does not print)."""
-    cfg = params("D2Q4E", jmin, jmax, eps, euler_s(), mu_bar=mu_bar, lam=lam, eq_param=gamma,
-                 domain=(0.0, 1.0), bc=(bc,) * 4)
+    configurations, whose states it does not print). ``gamma`` and ``metric``:
+    the prediction half-width and sibling metric of the multiresolution."""
+    cfg = params("D2Q4E", jmin, jmax, eps, euler_s(), mu_bar=mu_bar, lam=lam, eq_param=gamma_gas,
+                 domain=(0.0, 1.0), bc=(bc,) * 4, gamma=gamma, metric=metric)
     rng = np.random.default_rng(seed)
     st = [(rng.uniform(0.5, 1.5), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), rng.uniform(0.2, 1.5))
           for _ in range(4)]  # quadrants LL, LR, UL, UR
-    cfg.update(quadrant_states=st, gamma=float(gamma))
+    cfg.update(quadrant_states=st, gamma_gas=float(gamma_gas))
     xc = cell_centres(jmax)
     X, Y = np.meshgrid(xc, xc, indexing="xy")
     q = (X > 0.5).astype(int) + 2 * (Y > 0.5).astype(int)
     rho, u, v, p = (np.choose(q, [s[k] for s in st]) for k in range(4))
-    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    E = p / (gamma_gas - 1.0) + 0.5 * rho * (u * u + v * v)
     m0 = np.stack([rho.ravel(), (rho * u).ravel(), (rho * v).ravel(), E.ravel()])
     return cfg, np.ascontiguousarray(m0)
 

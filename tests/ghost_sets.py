@@ -2,10 +2,12 @@
 checking the GPU classification.
 
 A cell of level l > jmin outside the tree is a ghost if a leaf of level l lies
-in its 5^d box (the transport and transfer stencils of that leaf) or if it lies
-in the 3^d box of the parent of a ghost of level l+1 (the prediction stencil of
-that ghost, section "Projection and prediction operators"). The sets are built
-from the finest level down; all boxes wrap periodically.
+in its box of half-width 2 gamma (5^d for gamma = 1: the transport and
+transfer stencils of that leaf) or if it lies in the box of half-width gamma of
+the parent of a ghost of level l+1 (the prediction stencil of that ghost,
+section "Projection and prediction operators"). The sets are built from the
+finest level down; all boxes wrap periodically (with walls this is the superset
+the library classifies).
 """
 import numpy as np
 
@@ -45,14 +47,14 @@ def tree_sets(o, tree):
     return T, S, I
 
 
-def ghost_sets(o, tree):
+def ghost_sets(o, tree, gamma=1):
     """Per level l > jmin: the ghost mask (level jmin holds every cell in the tree)."""
     T, S, _ = tree_sets(o, tree)
     G = {}
     for l in range(o.jmax, o.jmin, -1):
-        need = _dilate(S[l], 2)
+        need = _dilate(S[l], 2 * gamma)
         if l < o.jmax:
-            need |= _dilate(_parents(G[l + 1]), 1)
+            need |= _dilate(_parents(G[l + 1]), gamma)
         G[l] = need & ~T[l]
     return G
 

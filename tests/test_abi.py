@@ -51,6 +51,17 @@ def test_workspace_size_and_parameter_validation():
     assert _wsize(bc=(0, 0, 1, 1))[0] == 0        # periodic in x, walls in y
     assert _wsize(bc=(1, 0, 0, 0))[0] == -1       # an axis is periodic on both sides or on none
     assert _wsize(bc=(4, 4, 0, 0))[0] == -1       # unknown condition
+    assert _wsize(gamma=2, mu_bar=4.0)[0] == 0    # mu_bar up to 2 gamma + 1
+    assert _wsize(gamma=2, mu_bar=5.5)[0] == -1
+    assert _wsize(gamma=3, metric="l2")[0] == 0
+    assert _wsize(gamma=4)[0] == -1               # Table 1 stops at gamma = 3
+    assert _wsize(gamma=-1)[0] == -1
+    assert _wsize(jmin=2, gamma=3, bc=(1, 1, 0, 0))[0] == -1  # a wall needs 2^jmin >= 2 gamma
+    assert _wsize(jmin=3, gamma=3, bc=(1, 1, 0, 0))[0] == 0
+    assert _wsize(jmin=2, gamma=3)[0] == 0        # periodic: no such bound
+    rc1, n1 = _wsize(bc=(2, 2, 2, 2))
+    rc3, n3 = _wsize(bc=(2, 2, 2, 2), gamma=3)
+    assert rc1 == rc3 == 0 and n3 > n1            # the general path's tables over the 13^2 / 14^2 boxes
     p = mrlbm.Params.from_cfg(W.params("D1Q2", 2, 5, 1e-3, [0, 1.9]), 16)
     n = ctypes.c_size_t(0)
     assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == -1
@@ -71,6 +82,10 @@ def test_batch_validation():
     assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, c), 2, ctypes.byref(n)) == -1
     d = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8)), 8)   # other precision
     assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, d), 2, ctypes.byref(n)) == -1
+    e = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8), gamma=2), 4)  # other gamma
+    assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, e), 2, ctypes.byref(n)) == -1
+    f = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8), metric="l2"), 4)  # metric per instance
+    assert mrlbm.lib().mrlbm_workspace_size((mrlbm.Params * 2)(a, f), 2, ctypes.byref(n)) == 0
     assert mrlbm.lib().mrlbm_workspace_size(arr, 0, ctypes.byref(n)) == -1
     assert mrlbm.lib().mrlbm_workspace_size(arr, 257, ctypes.byref(n)) == -1
 
@@ -148,3 +163,72 @@ def test_transport_table_support_at_most_25_values():
             assert not grid[h][[0, 1, 3, 4]].any()
         for h in (2, 4):
             assert not grid[h][:, [0, 1, 3, 4]].any()
+
+
+def _pred_down_g(vals, m, g):
+    """Exact 1D prediction of half-width g (Table 1) of a dict {index: Fraction}, m levels down."""
+    c = {1: [Fr(-1, 8)], 2: [Fr(-22, 128), Fr(3, 128)], 3: [Fr(-201, 1024), Fr(11, 256), Fr(-5, 1024)]}[g]
+    for _ in range(m):
+        nv = {}
+        for i in range(min(vals) - g, max(vals) + g + 1):
+            q = sum(c[a - 1] * (vals.get(i + a, Fr(0)) - vals.get(i - a, Fr(0))) for a in range(1, g + 1))
+            nv[2 * i] = vals.get(i, Fr(0)) + q
+            nv[2 * i + 1] = vals.get(i, Fr(0)) - q
+        vals = nv
+    return vals
+
+
+def _exact_sum_g(n, m, e, a, g, wall):
+    v = _pred_down_g({a: Fr(1)}, m, g)
+    lo, hi = -e, (1 << n) - e
+    if wall == 1:
+        lo = max(lo, 0)
+    if wall == 2:
+        hi = min(hi, 1 << n)
+    return sum(v.get(i, Fr(0)) for i in range(lo, hi))
+
+
+@pytest.mark.parametrize("scheme,n,gamma,wx,wy", [
+    ("D1Q3", 1, 2, 0, 0), ("D1Q3", 3, 3, 0, 0), ("D1Q2", 4, 2, 1, 0), ("D1Q3", 2, 3, 2, 0),
+    ("D2Q9", 2, 2, 0, 0), ("D2Q9", 3, 3, 1, 2), ("D2Q9", 1, 1, 2, 1), ("D2Q9", 3, 2, 0, 1), ("D2Q4E", 2, 3, 1, 0)])
+def test_general_transport_tables_are_exact(scheme, n, gamma, wx, wy):
+    """The general path's tables: W and C from the exact reconstruction of
+    leaf-level and detail impulses with the prediction of half-width gamma,
+    summed over E (clipped at the walls the leaf touches) minus A, and N the
+    count of E's finest cells beyond the walls. The Table 1 coefficients are
+    dyadic, so the double tables hold the exact values up to one rounding of
+    each product (relative 2^-52)."""
+    Wt, Ct, Nt = mrlbm.transport_tables_general(scheme, n, gamma, wx, wy)
+    dim, q, _ = W.SCHEME_DIMS[scheme]
+    R = 2 * gamma
+    import oracle
+    eta = oracle.Oracle(W.params(scheme, 2, 4, 0.0, [0.0] * q,
+                                 eq_param=1.4 if scheme == "D2Q4E" else 0.0)).velocities()
+    for h in range(q):
+        ex, ey = (int(v) for v in eta[h][:2])
+        if ex == 0 and ey == 0:
+            assert not Wt[h].any() and not Ct[h].any() and not Nt[h].any()
+            continue
+        Sx = {a: _exact_sum_g(n, n, ex, a, gamma, wx) for a in range(-R, R + 1)}
+        Sy = {b: (_exact_sum_g(n, n, ey, b, gamma, wy) if dim == 2 else Fr(int(b == 0))) for b in range(-R, R + 1)}
+        Tx = {y: _exact_sum_g(n, n - 1, ex, y, gamma, wx) for y in range(-R, R + 2)}
+        Ty = {y: (_exact_sum_g(n, n - 1, ey, y, gamma, wy) if dim == 2 else Fr(int(y == 0)))
+              for y in range(-R, R + 2)}
+        WW, CW = 2 * R + 1, 2 * R + 2
+        for b in (range(-R, R + 1) if dim == 2 else [0]):
+            for a in range(-R, R + 1):
+                want = Sx[a] * Sy[b] - (Fr(2) ** (dim * n) if a == 0 and b == 0 else 0)
+                got = Wt[h, (b + R) * WW + a + R if dim == 2 else a + R]
+                assert abs(Fr(got) - want) <= abs(want) * Fr(1, 2 ** 50), (h, a, b)
+        for y2 in (range(-R, R + 2) if dim == 2 else [0]):
+            for y1 in range(-R, R + 2):
+                want = Tx[y1] * Ty[y2]
+                got = Ct[h, (y2 + R) * CW + y1 + R if dim == 2 else y1 + R]
+                assert abs(Fr(got) - want) <= abs(want) * Fr(1, 2 ** 50), (h, y1, y2)
+        # cells of E = B - eta beyond the touched walls: a full column (x) then,
+        # with x inside, the rest of a row (y)
+        w = 1 << n
+        ox = (wx == 1 and ex > 0) or (wx == 2 and ex < 0)
+        oy = dim == 2 and ((wy == 1 and ey > 0) or (wy == 2 and ey < 0))
+        assert Nt[h, 0] == (w if dim == 2 else 1) * ox
+        assert Nt[h, 1] == (w - ox) * oy

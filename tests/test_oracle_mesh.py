@@ -89,8 +89,16 @@ def _brute_adapt(o, cfg, told, D):
     def D_of(l, c):  # metric of the group of (l, c), stored at the parent's slot
         return D[idx(l - 1, parent(c))]
 
+    sq = cfg.get("metric", "linf") == "l2"  # the l2 metric is compared squared
+    g = int(cfg.get("gamma", 1))
+
     def eps_l(l):
-        return np.ldexp(cfg["eps"], d * (l - J))
+        e = np.ldexp(cfg["eps"], d * (l - J))
+        return e * e if sq else e
+
+    def ref_l(l):
+        r = np.ldexp(np.ldexp(cfg["eps"], d * (l - J)), d) * 2.0 ** cfg["mu_bar"]
+        return r * r if sq else r
 
     old = {(l, c) for l in range(jmin, J + 1) for c in cells(l) if told[idx(l, c)]}
     K = {(jmin, c) for c in cells(jmin)}
@@ -111,7 +119,7 @@ def _brute_adapt(o, cfg, told, D):
             nb = wrap(l, tuple(ci - ei for ci, ei in zip(c, e)))
             if nb is not None:
                 H.add((l, nb))
-        if jmin < l < J and D_of(l, c) >= np.ldexp(eps_l(l), d) * 2.0 ** cfg["mu_bar"]:
+        if jmin < l < J and D_of(l, c) >= ref_l(l):
             for ch in children(c):
                 H.add((l + 1, ch))
     changed = True
@@ -122,7 +130,7 @@ def _brute_adapt(o, cfg, told, D):
                 continue
             p = parent(c)
             need = [(l, s) for s in children(p)]
-            rng_ = range(-1, 2)
+            rng_ = range(-g, g + 1)
             if d == 1:
                 need += [(l - 1, wrap(l - 1, (p[0] + a,))) for a in rng_]
             else:
