@@ -52,7 +52,7 @@ CASES = [
     ("D2Q9", 3, 7, 1e-3, ("periodic",) * 4, 3, "l2", 6, 8),
     ("D2Q9", 3, 7, 1e-3, ("bounce_back",) * 4, 2, "l2", 7, 10),
     ("D2Q9", 3, 7, 1e-3, ("copy", "copy", "bounce_back", "bounce_back"), 3, "linf", 8, 8),
-    ("D2Q9", 2, 7, 1e-3, ("periodic",) * 4, 1, "l2", 9, 12),
+    ("D2Q9", 3, 7, 3e-3, ("periodic",) * 4, 1, "l2", 9, 12),
     ("D1Q3", 2, 10, 1e-4, ("copy", "bounce_back"), 1, "l2", 10, 20),
 ]
 
