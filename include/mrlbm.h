@@ -235,7 +235,8 @@ int mrlbm_sizes(const mrlbm_ctx *ctx, int instance, int64_t *total_cells, int *q
  * over levels divided by N_J^d is the mesh occupation rate of the numerical
  * experiments), internal tree cells and ghost cells ([jmax + 1] each, any of
  * them may be NULL).
- * Errors: MRLBM_ERR_NONFINITE if a leaf value is not finite; MRLBM_ERR_SYNC
+ * Errors: MRLBM_ERR_NONFINITE if a leaf value of this instance is not finite
+ * (the outputs are still written; the mass is then not finite); MRLBM_ERR_SYNC
  * (takes precedence) if the sticky wait flag is set. */
 int mrlbm_stats(mrlbm_ctx *ctx, int instance, double *mass, int64_t *leaves, int64_t *internal,
                 int64_t *ghosts);

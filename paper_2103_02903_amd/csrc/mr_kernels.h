@@ -684,6 +684,11 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
 // level.
 constexpr int CBLK = 1024;
 
+template <int DIM, typename T>
+__device__ void ghost_run4(const Inst<T> &In, uint8_t *__restrict__ code, int l, long long c0);
+template <int DIM, typename T>
+__device__ void ghost_run16(const Inst<T> &In, uint8_t *__restrict__ code, int l, long long c0);
+
 // Ghost classification of levels min(lc, jmax) .. jmin+1, finest first; bit L
 // of v16 selects the 16-cell form for level L.
 template <int DIM, typename T>
@@ -2016,7 +2021,7 @@ __device__ __forceinline__ void neumaier_add(double &s, double &c, double t) {
 }
 
 // Mass partial sums of instance blockIdx.y (fixed grid and order, so the result
-// is reproducible) and a non-finite flag.
+// is reproducible) and its non-finite flag bad[i].
 template <int DIM, int Q, typename T>
 __global__ void __launch_bounds__(BLK) k_mass_partial(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ F,
                                                       const uint32_t *__restrict__ leaves, const int *__restrict__ lvl,
@@ -2054,7 +2059,7 @@ __global__ void __launch_bounds__(BLK) k_mass_partial(Batch bt, const Inst<T> *_
     part[2 * (i * RED_BLOCKS + blockIdx.x)] = red_s[0];
     part[2 * (i * RED_BLOCKS + blockIdx.x) + 1] = red_c[0];
   }
-  if (nonfinite) atomicOr(bad, 1);
+  if (nonfinite) atomicOr(bad + i, 1);
 }
 
 template <int DIM, int Q, typename T>

@@ -357,7 +357,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_Cb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * wide_cs(P.dim, P.gamma));
   P.off_Nb = take(P.rs * std::max(1, P.nmax) * 9 * P.q * 2);
   P.off_red = take(sizeof(double) * 2 * RED_BLOCKS * B);
-  P.off_bad = take(sizeof(int) * 4);
+  P.off_bad = take(sizeof(int) * std::max(4, B));  // non-finite flag per instance
   P.off_cnt = take(sizeof(unsigned long long) * 4);
   P.off_inst = take(std::max(sizeof(Inst<double>), sizeof(Inst<float>)) * B);
   P.off_cb = take(sizeof(long long) * (B + 1));
@@ -1632,13 +1632,13 @@ int mrlbm_stats(mrlbm_ctx *c, int instance, double *mass, int64_t *leaves, int64
   int rc = MRLBM_OK;
   if (mass) {
     HIPCHK(hipStreamSynchronize(c->stream));
-    HIPCHK(hipMemset(c->bad, 0, sizeof(int)));
+    HIPCHK(hipMemset(c->bad, 0, sizeof(int) * c->P.B));
     dispatch<MassOp>(c);
     std::vector<double> part(2 * RED_BLOCKS * c->P.B);
     int bad = 0;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(part.data(), c->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&bad, c->bad + instance, sizeof bad, hipMemcpyDeviceToHost));
     // compensated sum of the per-block (sum, compensation) pairs, fixed order
     double s = 0.0, e = 0.0;
     for (int k = 0; k < 2 * RED_BLOCKS; ++k) {

@@ -178,6 +178,15 @@ def test_nonfinite_leaf_reported(mr):
         sim.stats()
     assert ei.value.status == -3
     sim.close()
+    # the flag is per instance: a batch reports it for the instance that holds the value
+    bat = mr.Batch([cfg, cfg])
+    bat.set_state(0, t, o.init(W.random_field(cfg, 3, "smooth"))[1])
+    bat.set_state(1, t, v)
+    assert bat.stats(0)["leaves"].sum() == 64 * 64
+    with pytest.raises(mr.MrlbmError) as ei:
+        bat.stats(1)
+    assert ei.value.status == -3
+    bat.close()
 
 
 def test_pair_wait_timeout_is_reported(mr):
