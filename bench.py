@@ -12,6 +12,7 @@ same GPU next to it; and the FP64 oracle timed on the host on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision 8|4]
   python bench.py --copy-calibration     (plain copy kernel of known size only)
+  python bench.py --adjoint-only 4       (the adjoint leg only, 4 or 8: for a kernel trace)
 """
 from __future__ import annotations
 
@@ -440,6 +441,8 @@ def main():
                     help="transport variant,all-level cap,per-level cap[,graph 1|0] (skips autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
+    ap.add_argument("--adjoint-only", type=int, default=0, choices=[0, 4, 8],
+                    help="only the adjoint leg in this precision (for a kernel trace of the adjoint kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single GPU (instances of a batch are "
@@ -454,6 +457,10 @@ def main():
         hip_build.build(force=False)
     if args.copy_calibration:
         print(json.dumps({"copy_kernel": "k_copy_u4", **copy_bandwidth()}))
+        return
+    if args.adjoint_only:
+        a = adjoint_run(args.adjoint_steps, args.adjoint_ckpt, args.adjoint_only)
+        print(json.dumps({k: a[k] for k in ("t_forward", "t_record", "t_adjoint", "J", "leaf_updates")}))
         return
     items, desc, prec = workload(args.workload)
     precision = args.precision or prec
