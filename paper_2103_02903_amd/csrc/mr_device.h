@@ -181,6 +181,14 @@ struct ParentStencil {
   }
 };
 
+// The prediction half-width of an instance as a kernel sees it: GAM = 1 for the
+// kernels of batches with gamma = 1 (a constant: the wide stencil code is left
+// out of them), GAM = 0 for the others (the instance's value).
+template <int GAM, typename T>
+__device__ __forceinline__ int gamma_k(const Inst<T> &In) {
+  return GAM == 1 ? 1 : In.gamma;
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ T predict(const T *__restrict__ P, int l, int cx, int cy, int walls, int g) {
   ParentStencil<DIM, T> s;

@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(BLK) k_project_marked(Batch bt, const Inst<T> 
 
 // Zero-detail prediction P_delta on the ghost cells of level l, from level l-1.
 // The first G blocks; wavefront h < Q takes population h.
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const Inst<T> *__restrict__ I,
                                             T *__restrict__ F, const uint32_t *__restrict__ lst,
                                             const int *__restrict__ lvl, int l, int G, int b) {
@@ -216,14 +216,15 @@ __device__ __forceinline__ void ghost_level(SegLDS &s, const Batch &bt, const In
     const uint32_t c = lst[s.beg[i] + item] & CELL_MASK;
     int x, y;
     coords<DIM>(l, c, x, y);
-    F[foff(I[i], DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y, I[i].walls, I[i].gamma);
+    F[foff(I[i], DIM, Q, l, h) + c] =
+        predict<DIM, T>(F + foff(I[i], DIM, Q, l - 1, h), l, x, y, I[i].walls, gamma_k<GAM>(I[i]));
   }
 }
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __global__ void __launch_bounds__(64 * Q) k_ghost(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                   const uint32_t *__restrict__ lst, const int *__restrict__ lvl, int l) {
   __shared__ SegLDS s;
-  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, (int)gridDim.x, (int)blockIdx.x);
+  ghost_level<DIM, Q, T, GAM>(s, bt, I, F, lst, lvl, l, (int)gridDim.x, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------- paired links
@@ -277,7 +278,7 @@ __device__ __forceinline__ void pair_leave(unsigned *__restrict__ sync, unsigned
 }
 // KIND 0: projections (levels l0 then l0-1 = l1), 2: marked projections, 1:
 // ghost predictions (levels l0 then l0+1 = l1).
-template <int DIM, int Q, typename T, int KIND>
+template <int DIM, int Q, typename T, int KIND, int GAM>
 __global__ void __launch_bounds__(64 * Q) k_pair(Batch bt, const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                  const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
                                                  int l0, int l1, int G0, int G1, unsigned *__restrict__ sync,
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(64 * Q) k_pair(Batch bt, const Inst<T> *__rest
   if constexpr (KIND == 0) {
     project_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, G, b);
   } else if constexpr (KIND == 1) {
-    ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, l, G, b);
+    ghost_level<DIM, Q, T, GAM>(s, bt, I, F, lst, lvl, l, G, b);
   } else {  // one internal cell (all populations) per thread, Q chunks per block
     load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -331,11 +332,12 @@ __device__ __forceinline__ T sibling_metric(const ParentStencil<DIM, T> &st, con
 }
 
 // Details and the sibling metric over all populations (section "Mesh
-// coarsening"), per internal cell p (level l-1) of the old tree: keep the
+// coarsening"), per internal cell p (level l-1) of the old tree (MET: the
+// batch's metric, 0 max or 1 l2, or 2 for each instance its own): keep the
 // children (T_eps, eq. Thresholding) if the metric reaches eps_l, flag the group
 // for refinement (H_eps) if it reaches 2^{mu_bar + d} eps_l (both squared for
 // the l2 metric).
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM, int MET>
 __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ F,
                                                     const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
                                                     uint8_t *__restrict__ keep, uint8_t *__restrict__ refg,
@@ -356,8 +358,8 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
       int px, py;
       coords<DIM>(lp, e & CELL_MASK, px, py);
       ParentStencil<DIM, T> st;
-      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py, I[i].walls, I[i].gamma);
-      dmax = sibling_metric<DIM, T>(st, F + foff(I[i], DIM, Q, l, h), l, px, py, I[i].metric);
+      st.load(F + foff(I[i], DIM, Q, lp, h), lp, px, py, I[i].walls, gamma_k<GAM>(I[i]));
+      dmax = sibling_metric<DIM, T>(st, F + foff(I[i], DIM, Q, l, h), l, px, py, MET == 2 ? I[i].metric : MET);
     }
     dm[h][lane] = dmax;
     __syncthreads();
@@ -387,7 +389,7 @@ __global__ void __launch_bounds__(64 * Q) k_details(Batch bt, const Inst<T> *__r
 // The same per internal parent, one thread per parent and all populations in
 // that thread: no block barriers, and the loads of every population can be in
 // flight together. Same arithmetic and decisions as k_details.
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM, int MET>
 __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *__restrict__ I,
                                                       const T *__restrict__ F, const uint32_t *__restrict__ lst,
                                                       const int *__restrict__ lvl, uint8_t *__restrict__ keep,
@@ -410,8 +412,8 @@ __global__ void __launch_bounds__(BLK) k_details_leaf(Batch bt, const Inst<T> *_
 #pragma unroll
     for (int h = 0; h < Q; ++h) {
       ParentStencil<DIM, T> st;
-      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py, In.walls, In.gamma);
-      const T dmax = sibling_metric<DIM, T>(st, F + foff(In, DIM, Q, l, h), l, px, py, In.metric);
+      st.load(F + foff(In, DIM, Q, lp, h), lp, px, py, In.walls, gamma_k<GAM>(In));
+      const T dmax = sibling_metric<DIM, T>(st, F + foff(In, DIM, Q, l, h), l, px, py, MET == 2 ? In.metric : MET);
       D = h == 0 ? dmax : (dmax > D ? dmax : D);
     }
     if (D >= In.eps_l[l]) {
@@ -628,7 +630,7 @@ __global__ void __launch_bounds__(BLK) k_enlarge(Batch bt, const Inst<T> *__rest
 // Grading G, level l: every sibling group of level l with one member gets all
 // of them, and every cell of level l-1 whose 3^d box holds a parent of a level-l
 // tree cell joins the tree. One thread per cell of level l-1.
-template <int DIM, typename T, bool WALLS>
+template <int DIM, typename T, bool WALLS, int GAM>
 __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restrict__ tnew, int l, long long cell) {
   const int lp = l - 1;
   uint8_t *tl = tnew + In.loff[l];
@@ -639,7 +641,7 @@ __device__ __forceinline__ void grade_cell(const Inst<T> &In, uint8_t *__restric
   // beyond a wall there is no parent: the box is clipped there
   const int np = 1 << lp;
   const bool wx = WALLS && (In.walls & 1), wy = WALLS && DIM == 2 && (In.walls & 2);
-  const int g = In.gamma;
+  const int g = gamma_k<GAM>(In);
   if (g == 1 && (((uintptr_t)tl) & 3u) == 0) {
     // children columns 2x-2 .. 2x+3 of a row: two aligned words (rows of level
     // l >= 2 hold a multiple of 4 cells); pairs -1, 0, +1 at bytes sh .. sh+5
@@ -723,7 +725,7 @@ __global__ void __launch_bounds__(CBLK) k_ancestor_coarse(const Inst<T> *__restr
 
 // Ghost predictions of levels jmin+1 .. min(lc, jmax) of instance i, coarsest
 // first, by the whole block.
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                   const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
                                                   int lc, int i) {
@@ -739,7 +741,8 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         coords<DIM>(l, c, x, y);
         T v[Q];
 #pragma unroll
-        for (int h = 0; h < Q; ++h) v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
+        for (int h = 0; h < Q; ++h)
+          v[h] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, gamma_k<GAM>(In));
 #pragma unroll
         for (int h = 0; h < Q; ++h) F[foff(In, DIM, Q, l, h) + c] = v[h];
       }
@@ -749,7 +752,8 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
         const uint32_t c = lst[b + item] & CELL_MASK;
         int x, y;
         coords<DIM>(l, c, x, y);
-        F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
+        F[foff(In, DIM, Q, l, h) + c] =
+            predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, gamma_k<GAM>(In));
       }
     }
     __syncthreads();
@@ -759,7 +763,7 @@ __device__ __forceinline__ void ghost_coarse_walk(const Inst<T> *__restrict__ I,
 // mark, only the marked ones: project_marked); with lg, then the ghost
 // predictions of levels jmin+1 .. min(lc, jmax) (same block, after the
 // projections they read).
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restrict__ I, T *__restrict__ F,
                                                          const uint32_t *__restrict__ lst, const int *__restrict__ lvl,
                                                          int lc, const uint32_t *__restrict__ lg,
@@ -785,19 +789,19 @@ __global__ void __launch_bounds__(CBLK) k_project_coarse(const Inst<T> *__restri
     }
     __syncthreads();
   }
-  if (lg) ghost_coarse_walk<DIM, Q, T>(I, F, lg, lvl, lc, i);
+  if (lg) ghost_coarse_walk<DIM, Q, T, GAM>(I, F, lg, lvl, lc, i);
 }
 
 // The coarse ancestor closure (blocks 0..B-1) beside the coarse link of the
 // old mesh's ghost predictions (blocks B..2B-1), which reads only the old
 // mesh's reconstruction: two walks of one block per instance in one launch.
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __global__ void __launch_bounds__(CBLK) k_ancestor_ghost_coarse(const Inst<T> *__restrict__ I,
                                                                 uint8_t *__restrict__ keep, int lc, int B,
                                                                 T *__restrict__ F, const uint32_t *__restrict__ lst,
                                                                 const int *__restrict__ lvl) {
   if ((int)blockIdx.x >= B) {
-    ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x - B);
+    ghost_coarse_walk<DIM, Q, T, GAM>(I, F, lst, lvl, lc, (int)blockIdx.x - B);
     return;
   }
   const Inst<T> &In = I[blockIdx.x];
@@ -821,7 +825,7 @@ constexpr int fused_block() { return 64 * Q > BLK ? 64 * Q : BLK; }
 // Ghosts (the first G blocks): of level lh, or with HC the coarse levels
 // jmin+1 .. min(lc, jmax), one block per instance. The first writes the
 // membership array, the second the values.
-template <int DIM, int Q, typename T, bool GC, bool HC, bool WALLS>
+template <int DIM, int Q, typename T, bool GC, bool HC, bool WALLS, int GAM>
 __global__ void __launch_bounds__(fused_block<Q>())
     k_grade_ghost(Batch bt, const Inst<T> *__restrict__ I, uint8_t *__restrict__ tnew,
                   const uint32_t *__restrict__ ginfo, int lg, T *__restrict__ F, const uint32_t *__restrict__ lst,
@@ -831,7 +835,7 @@ __global__ void __launch_bounds__(fused_block<Q>())
       const Inst<T> &In = I[blockIdx.x - G];
       for (int l = lc < In.jmax ? lc : In.jmax; l > In.jmin; --l) {
         const long long n = ncells_d(DIM, l - 1);
-        for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T, WALLS>(In, tnew, l, cell);
+        for (long long cell = threadIdx.x; cell < n; cell += blockDim.x) grade_cell<DIM, T, WALLS, GAM>(In, tnew, l, cell);
         __syncthreads();
       }
       return;
@@ -839,15 +843,15 @@ __global__ void __launch_bounds__(fused_block<Q>())
     const uint32_t w = ginfo[blockIdx.x - G];
     const int i = (int)(w & 0xffu);
     const long long cell = (long long)(w >> 8) * fused_block<Q>() + threadIdx.x;
-    if (cell < ncells_d(DIM, lg - 1) && lg <= active_top(act, I[i], i)) grade_cell<DIM, T, WALLS>(I[i], tnew, lg, cell);
+    if (cell < ncells_d(DIM, lg - 1) && lg <= active_top(act, I[i], i)) grade_cell<DIM, T, WALLS, GAM>(I[i], tnew, lg, cell);
     return;
   }
   if (HC) {
-    ghost_coarse_walk<DIM, Q, T>(I, F, lst, lvl, lc, (int)blockIdx.x);
+    ghost_coarse_walk<DIM, Q, T, GAM>(I, F, lst, lvl, lc, (int)blockIdx.x);
     return;
   }
   __shared__ SegLDS s;
-  ghost_level<DIM, Q, T>(s, bt, I, F, lst, lvl, lh, G, (int)blockIdx.x);
+  ghost_level<DIM, Q, T, GAM>(s, bt, I, F, lst, lvl, lh, G, (int)blockIdx.x);
 }
 
 // Codes of the tree cells of a 0/1 membership array: leaf, or internal when
@@ -1312,7 +1316,7 @@ __global__ void __launch_bounds__(1024) k_compact_scan(Batch bt, const Inst<T> *
 // 1): a run with leaves reads the same 16 old codes, and its leaves that were
 // outside the old mesh are predicted from level l-1; every other new leaf
 // already holds its value in F (see the adaptation).
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T> *__restrict__ I,
                                                          const uint32_t *__restrict__ binfo, const uint8_t *__restrict__ code,
                                                          const int *__restrict__ boff, uint32_t *__restrict__ lists,
@@ -1420,7 +1424,8 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     int x, y;
     coords<DIM>(l, (uint32_t)c, x, y);
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
+      F[foff(In, DIM, Q, l, h) + c] =
+          predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, gamma_k<GAM>(In));
   }
 }
 
@@ -2110,7 +2115,7 @@ __global__ void __launch_bounds__(BLK) k_moments(const Inst<T> *__restrict__ I, 
 // the reconstruction of the tree, it gives the double-hat reconstruction on
 // the finest level (section "Mesh coarsening"). Ghosts get the value they
 // already hold (same expression); values of tree cells are not touched.
-template <int DIM, int Q, typename T>
+template <int DIM, int Q, typename T, int GAM>
 __global__ void __launch_bounds__(BLK) k_predict_outside(const Inst<T> *__restrict__ I, int i, T *__restrict__ F,
                                                          const uint8_t *__restrict__ code, int l) {
   const Inst<T> &In = I[i];
@@ -2122,7 +2127,8 @@ __global__ void __launch_bounds__(BLK) k_predict_outside(const Inst<T> *__restri
     coords<DIM>(l, (uint32_t)c, x, y);
 #pragma unroll
     for (int h = 0; h < Q; ++h)
-      F[foff(In, DIM, Q, l, h) + c] = predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, In.gamma);
+      F[foff(In, DIM, Q, l, h) + c] =
+          predict<DIM, T>(F + foff(In, DIM, Q, l - 1, h), l, x, y, In.walls, gamma_k<GAM>(In));
   }
 }
 

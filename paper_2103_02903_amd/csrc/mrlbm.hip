@@ -220,6 +220,7 @@ int dense_margin(int off) { return off == 1 ? 1 : off == 2 ? 2 : 0; }
 struct Plan {
   int B, dim, q, jmin, maxJ, nmax, nblocks;
   int gamma;       // prediction half-width, shared by the batch (the transport tables depend on it)
+  int metric_mode; // sibling metric of every instance (0 max, 1 l2), or 2 if they differ
   bool any_walls;  // some instance has walls: the launches take the kernel variants that handle them
   size_t rs;
   long long ctotal;
@@ -247,6 +248,9 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.maxJ = 0;
   P.rs = p[0].precision == 8 ? 8 : 4;
   P.gamma = gamma_of(&p[0]);
+  P.metric_mode = p[0].metric;
+  for (int i = 1; i < B; ++i)
+    if (p[i].metric != p[0].metric) P.metric_mode = 2;
   P.inst.assign(B, Inst<double>());
   P.any_walls = false;
   P.cb.assign(B + 1, 0);
@@ -612,7 +616,9 @@ hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, 
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
 constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch (profile mode 1)
 
-template <int DIM, int SCHEME, typename T>
+// GAM = 1: a batch with gamma = 1 (the kernels that predict take it as a
+// constant); GAM = 0: gamma > 1, read per instance.
+template <int DIM, int SCHEME, typename T, int GAM>
 struct Engine {
   static constexpr int Q = Vel<SCHEME>::Q;
   static constexpr unsigned QB = 64 * Q;
@@ -653,7 +659,7 @@ struct Engine {
                                                                c->act, c->ne[m]);
     k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks,
                                                    c->act, c->ne[m]);
-    k_compact_scatter<DIM, Q, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
+    k_compact_scatter<DIM, Q, T, GAM><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
                                                                    c->lists[m], P.nblocks, code_old, F, c->mark,
                                                                    c->act);
   }
@@ -711,11 +717,11 @@ struct Engine {
       if (mark) {
         const unsigned g0 = list_grid((level_chunks(c, l) + Q - 1) / Q, c->grid_level);
         const unsigned g1 = list_grid((level_chunks(c, l - 1) + Q - 1) / Q, c->grid_level);
-        k_pair<DIM, Q, T, 2><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
+        k_pair<DIM, Q, T, 2, GAM><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
                                                            c->sync, mark, c->ne[m]);
       } else {
         const unsigned g0 = chunks_level(c, l), g1 = chunks_level(c, l - 1);
-        k_pair<DIM, Q, T, 0><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
+        k_pair<DIM, Q, T, 0, GAM><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l, l - 1, (int)g0, (int)g1,
                                                            c->sync, nullptr, c->ne[m]);
       }
       l -= 2;
@@ -728,7 +734,7 @@ struct Engine {
         k_project<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, li, lvl, l);
     }
     if (lc >= P.jmin)
-      k_project_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc, lc > P.jmin ? lg : nullptr,
+      k_project_coarse<DIM, Q, T, GAM><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, lvl, lc, lc > P.jmin ? lg : nullptr,
                                                                mark);
   }
 
@@ -744,10 +750,10 @@ struct Engine {
     const int l0 = std::max(P.jmin, lc) + 1;
     const int last = P.maxJ - 1 >= l0 ? P.maxJ - 1 : P.maxJ + 1;  // first of the shared pair
     for (int l = l0; l <= P.maxJ && l < last; ++l)
-      k_ghost<DIM, Q, T><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
+      k_ghost<DIM, Q, T, GAM><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
     if (last <= P.maxJ) {  // the two finest levels share a launch
       const unsigned g0 = chunks_level(c, last), g1 = chunks_level(c, last + 1);
-      k_pair<DIM, Q, T, 1><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], last, last + 1, (int)g0,
+      k_pair<DIM, Q, T, 1, GAM><<<g0 + g1, QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], last, last + 1, (int)g0,
                                                          (int)g1, c->sync, nullptr, c->ne[m]);
     }
   }
@@ -763,12 +769,20 @@ struct Engine {
     // and refine flags are zero here: the tree classification of the previous
     // adaptation, or the creation, cleared them.
     project_all(c, mo, Fc, li, c->lvl[mo]);
-    if (per_leaf(c))
-      k_details_leaf<DIM, Q, T><<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
+    // the sibling metric as a constant when the batch shares it
+    if (per_leaf(c)) {
+      auto kern = P.metric_mode == 0   ? k_details_leaf<DIM, Q, T, GAM, 0>
+                  : P.metric_mode == 1 ? k_details_leaf<DIM, Q, T, GAM, 1>
+                                       : k_details_leaf<DIM, Q, T, GAM, 2>;
+      kern<<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
-    else
-      k_details<DIM, Q, T><<<chunks_all(c), QB, 0, c->stream>>>(
+    } else {
+      auto kern = P.metric_mode == 0   ? k_details<DIM, Q, T, GAM, 0>
+                  : P.metric_mode == 1 ? k_details<DIM, Q, T, GAM, 1>
+                                       : k_details<DIM, Q, T, GAM, 2>;
+      kern<<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal, c->lvl[mo], c->keep, c->refg, c->act);
+    }
     const int lc = coarse_cap(c);
     int la = P.maxJ;
     const int la_end = std::max(P.jmin + 2, lc + 3);
@@ -790,7 +804,7 @@ struct Engine {
     // ghost predictions (which only the transfer reads), whose finer links
     // ride in the grading launches below
     if (lc > P.jmin)
-      k_ancestor_ghost_coarse<DIM, Q, T><<<2 * P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc, P.B, Fc, lg,
+      k_ancestor_ghost_coarse<DIM, Q, T, GAM><<<2 * P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc, P.B, Fc, lg,
                                                                          c->lvl[mo]);
     else if (lc + 2 >= P.jmin + 2)
       k_ancestor_coarse<DIM, T><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, lc);
@@ -815,10 +829,10 @@ struct Engine {
         const uint32_t *gi = g > 0 ? P.dinfo_row(c->dinfo, 1, g - 1) : c->dinfo;
         if (G + nb == 0) continue;
         const bool w = P.any_walls;
-        auto kern = g < 0 && h < 0 ? (w ? k_grade_ghost<DIM, Q, T, true, true, true> : k_grade_ghost<DIM, Q, T, true, true, false>)
-                    : g < 0        ? (w ? k_grade_ghost<DIM, Q, T, true, false, true> : k_grade_ghost<DIM, Q, T, true, false, false>)
-                    : h < 0        ? (w ? k_grade_ghost<DIM, Q, T, false, true, true> : k_grade_ghost<DIM, Q, T, false, true, false>)
-                                   : (w ? k_grade_ghost<DIM, Q, T, false, false, true> : k_grade_ghost<DIM, Q, T, false, false, false>);
+        auto kern = g < 0 && h < 0 ? (w ? k_grade_ghost<DIM, Q, T, true, true, true, GAM> : k_grade_ghost<DIM, Q, T, true, true, false, GAM>)
+                    : g < 0        ? (w ? k_grade_ghost<DIM, Q, T, true, false, true, GAM> : k_grade_ghost<DIM, Q, T, true, false, false, GAM>)
+                    : h < 0        ? (w ? k_grade_ghost<DIM, Q, T, false, true, true, GAM> : k_grade_ghost<DIM, Q, T, false, true, false, GAM>)
+                                   : (w ? k_grade_ghost<DIM, Q, T, false, false, true, GAM> : k_grade_ghost<DIM, Q, T, false, false, false, GAM>);
         kern<<<G + nb, FB, 0, c->stream>>>(c->bt, I(c), c->tnew, gi, g, Fc, lg, c->lvl[mo], h, (int)G, lc, c->act);
       }
     }
@@ -986,7 +1000,7 @@ struct Engine {
     T *F = (T *)c->F[c->cur];
     reconstruct(c, F, c->mcur);
     for (int l = In.jmin + 1; l <= In.jmax; ++l)
-      k_predict_outside<DIM, Q, T><<<grid_cap(((1ll << (DIM * l)) + BLK - 1) / BLK, DENSE_GRID), BLK, 0,
+      k_predict_outside<DIM, Q, T, GAM><<<grid_cap(((1ll << (DIM * l)) + BLK - 1) / BLK, DENSE_GRID), BLK, 0,
                                      c->stream>>>(I(c), i, F, c->code[c->mcur], l);
     const size_t bytes = sizeof(T) * Q * ((size_t)1 << (DIM * In.jmax));
     HIPCHK(hipMemcpyAsync(out, F + (size_t)Q * In.loff[In.jmax], bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1216,53 +1230,62 @@ struct Engine {
   }
 };
 
-template <template <int, int, typename> class Op, typename... A>
-int dispatch(mrlbm_ctx *c, A... a) {
+template <template <int, int, typename, int> class Op, int G, typename... A>
+int dispatch_g(mrlbm_ctx *c, A... a) {
   const bool dbl = c->p[0].precision == 8;
   switch (c->p[0].scheme) {
-    case MRLBM_D1Q2: return dbl ? Op<1, 1, double>::run(c, a...) : Op<1, 1, float>::run(c, a...);
-    case MRLBM_D1Q3: return dbl ? Op<1, 2, double>::run(c, a...) : Op<1, 2, float>::run(c, a...);
-    case MRLBM_D2Q4_EULER: return dbl ? Op<2, 4, double>::run(c, a...) : Op<2, 4, float>::run(c, a...);
-    default: return dbl ? Op<2, 3, double>::run(c, a...) : Op<2, 3, float>::run(c, a...);
+    case MRLBM_D1Q2: return dbl ? Op<1, 1, double, G>::run(c, a...) : Op<1, 1, float, G>::run(c, a...);
+    case MRLBM_D1Q3: return dbl ? Op<1, 2, double, G>::run(c, a...) : Op<1, 2, float, G>::run(c, a...);
+    case MRLBM_D2Q4_EULER: return dbl ? Op<2, 4, double, G>::run(c, a...) : Op<2, 4, float, G>::run(c, a...);
+    default: return dbl ? Op<2, 3, double, G>::run(c, a...) : Op<2, 3, float, G>::run(c, a...);
   }
 }
-template <int D, int S, typename T>
-struct AdaptOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::adapt(c); } };
-template <int D, int S, typename T>
-struct TransportOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::transport(c); } };
-template <int D, int S, typename T>
-struct DryOp { static int run(mrlbm_ctx *c, int reps, float *ms) { return Engine<D, S, T>::time_dry_steps(c, reps, ms); } };
-template <int D, int S, typename T>
-struct StepGraphOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::step_graph(c); } };
-template <int D, int S, typename T>
-struct InitOp { static int run(mrlbm_ctx *c, int i, const void *m) { return Engine<D, S, T>::init(c, i, m); } };
-template <int D, int S, typename T>
-struct ClassifyOp { static int run(mrlbm_ctx *c, int m) { Engine<D, S, T>::classify(c, m); return MRLBM_OK; } };
-template <int D, int S, typename T>
-struct MassOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::mass(c); } };
-template <int D, int S, typename T>
+template <template <int, int, typename, int> class Op, typename... A>
+int dispatch(mrlbm_ctx *c, A... a) {
+  return c->P.gamma > 1 ? dispatch_g<Op, 0>(c, a...) : dispatch_g<Op, 1>(c, a...);
+}
+template <int D, int S, typename T, int G>
+struct AdaptOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::adapt(c); } };
+template <int D, int S, typename T, int G>
+struct TransportOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::transport(c); } };
+template <int D, int S, typename T, int G>
+struct DryOp { static int run(mrlbm_ctx *c, int reps, float *ms) { return Engine<D, S, T, G>::time_dry_steps(c, reps, ms); } };
+template <int D, int S, typename T, int G>
+struct StepGraphOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::step_graph(c); } };
+template <int D, int S, typename T, int G>
+struct InitOp { static int run(mrlbm_ctx *c, int i, const void *m) { return Engine<D, S, T, G>::init(c, i, m); } };
+template <int D, int S, typename T, int G>
+struct ClassifyOp { static int run(mrlbm_ctx *c, int m) { Engine<D, S, T, G>::classify(c, m); return MRLBM_OK; } };
+template <int D, int S, typename T, int G>
+struct MassOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::mass(c); } };
+template <int D, int S, typename T, int G>
 struct ExportOp {
-  static int run(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) { return Engine<D, S, T>::exportl(c, i, cells, vals); }
+  static int run(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) { return Engine<D, S, T, G>::exportl(c, i, cells, vals); }
 };
-template <int D, int S, typename T>
+template <int D, int S, typename T, int G>
 struct LeafFieldsOp {
-  static int run(mrlbm_ctx *c, int i, int what, void *out) { return Engine<D, S, T>::leaf_fields(c, i, what, out); }
+  static int run(mrlbm_ctx *c, int i, int what, void *out) { return Engine<D, S, T, G>::leaf_fields(c, i, what, out); }
 };
-template <int D, int S, typename T>
-struct FinestOp { static int run(mrlbm_ctx *c, int i, void *out) { return Engine<D, S, T>::finest(c, i, out); } };
-template <int D, int S, typename T>
-struct FrozenOp { static int run(mrlbm_ctx *c, const uint8_t *t) { return Engine<D, S, T>::frozen(c, t); } };
-template <int D, int S, typename T>
-struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T>::upload_inst(c); } };
-template <int D, int S, typename T>
-struct RecordOp { static int run(mrlbm_ctx *c, int n, int K) { return Engine<D, S, T>::record(c, n, K); } };
-template <int D, int S, typename T>
+template <int D, int S, typename T, int G>
+struct FinestOp { static int run(mrlbm_ctx *c, int i, void *out) { return Engine<D, S, T, G>::finest(c, i, out); } };
+template <int D, int S, typename T, int G>
+struct FrozenOp { static int run(mrlbm_ctx *c, const uint8_t *t) { return Engine<D, S, T, G>::frozen(c, t); } };
+template <int D, int S, typename T, int G>
+struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::upload_inst(c); } };
+// The adjoint covers gamma = 1 and the schemes with one to three conserved moments.
+template <int D, int S, typename T, int G>
+struct RecordOp {
+  static int run(mrlbm_ctx *c, int n, int K) {
+    if constexpr (G == 1 && S != MRLBM_D2Q4_EULER) return Engine<D, S, T, G>::record(c, n, K);
+    else return MRLBM_ERR_INVALID;
+  }
+};
+template <int D, int S, typename T, int G>
 struct AdjointOp {
-  static int run(mrlbm_ctx *c, const void *a, void *mb, double *sb) { return Engine<D, S, T>::adjoint(c, a, mb, sb); }
-};
-template <typename T>
-struct AdjointOp<2, 4, T> {  // the adjoint covers the schemes with one to three conserved moments
-  static int run(mrlbm_ctx *, const void *, void *, double *) { return MRLBM_ERR_INVALID; }
+  static int run(mrlbm_ctx *c, const void *a, void *mb, double *sb) {
+    if constexpr (G == 1 && S != MRLBM_D2Q4_EULER) return Engine<D, S, T, G>::adjoint(c, a, mb, sb);
+    else return MRLBM_ERR_INVALID;
+  }
 };
 
 // Host check of a 0/1 tree of instance i: level jmin complete, sibling groups
