@@ -7,12 +7,15 @@ shear layers (finest levels 7..10) advanced together in FP32. Prints one JSON
 line: leaf updates per second over the timed steps; the roofline of the
 dominant kernel (transport + collision, HBM-bound), timed with HIP events on
 the library's stream inside the timed region; the same batch in FP64, the
-single 1024^2 shear layer in FP64 and FP32, and the adjoint, measured on the
-same GPU next to it; and the FP64 oracle timed on the host on a bounded sample.
+single 1024^2 shear layer in FP64 and FP32, the adjoint, and the method's
+variants (walls, gamma = 2 and 3, the l2 metric, the Euler scheme), measured on
+the same GPU next to it; and the FP64 oracle timed on the host on a bounded
+sample.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision 8|4]
   python bench.py --copy-calibration     (plain copy kernel of known size only)
   python bench.py --adjoint-only 4       (the adjoint leg only, 4 or 8: for a kernel trace)
+  python bench.py --scope-only [NAME]    (the walls, gamma, l2 and Euler workloads only)
 """
 from __future__ import annotations
 
@@ -365,6 +368,54 @@ def sample_instances(items):
     return out
 
 
+def scope_row_workloads():
+    """The method's variants beyond the periodic D2Q9 batch, each at a size that
+    fills the GPU: (name, items, description, precision)."""
+    from paper_2103_02903_amd import workloads as W
+
+    def batch(**kw):
+        items = W.shear_layer_batch(96)
+        for c, _ in items:
+            c.update(kw)
+        return items
+
+    walled = batch(bc=(0, 0, 2, 2))
+    return [
+        ("walls_bounce_back_batch96_fp32", walled,
+         "the 96-instance shear-layer batch with bounce-back walls on the y sides (x periodic)", 4),
+        ("gamma2_batch96_fp32", batch(gamma=2, mu_bar=1.0),
+         "the 96-instance shear-layer batch with the prediction of half-width gamma = 2 (Table 1)", 4),
+        ("gamma3_batch96_fp32", batch(gamma=3, mu_bar=1.0),
+         "the 96-instance shear-layer batch with the prediction of half-width gamma = 3 (Table 1)", 4),
+        ("l2_metric_batch96_fp32", batch(metric="l2"),
+         "the 96-instance shear-layer batch with the l2 sibling metric", 4),
+        ("euler_d2q4_riemann_1024_fp32", [W.riemann_d2q4e(jmin=3, jmax=10, eps=1e-3, seed=0)],
+         "vectorial D2Q4 Euler scheme (lambda 5, copy walls), seeded two-dimensional Riemann problem, levels "
+         "3..10 (1024^2 finest), eps 1e-3", 4),
+        ("euler_d2q4_riemann_1024_fp64", [W.riemann_d2q4e(jmin=3, jmax=10, eps=1e-3, seed=0)],
+         "the same Euler run in FP64", 8),
+    ]
+
+
+def scope_rows(args, only=None):
+    """Leaf updates/s and the transport kernel's roofline fraction of each
+    workload of scope_row_workloads (windows A and B as for the headline), or
+    of the one named `only`."""
+    out = {}
+    for name, items, desc, prec in scope_row_workloads():
+        if only is not None and name != only:
+            continue
+        r, sim, _ = timed_run(items, prec, args.scope_steps, args.scope_warmup)
+        sim.close()
+        out[name] = dict(workload=desc, value=r["value"], unit="leaf updates/s", ms_per_step=r["ms_per_step"],
+                         mean_leaves_per_step=r["mean_leaves_per_step"],
+                         compression_rate_mean=r["compression_rate_mean"],
+                         transport_avg_launch_ms=r["transport_avg_launch_ms"],
+                         transport_gbs=r["transport_gbs"], transport_frac=r["transport_frac"],
+                         step_frac=r["step_frac"], launch_schedule=r["tuning"])
+    return out
+
+
 def variants(args, head):
     """The same batch in FP64, the single 1024^2 shear layer (plain FP64 and
     FP32), and the adjoint in both precisions, each measured on this GPU."""
@@ -420,6 +471,7 @@ def variants(args, head):
     out["adjoint_fp32"]["accuracy"] = ("max |dJ/dm0 (FP32) - dJ/dm0 (FP64)| / max |dJ/dm0 (FP64)| = %.2e, each "
                                        "precision on the meshes it chose itself" % rel)
     out["adjoint_fp32"]["fp32_vs_fp64"] = out["adjoint_fp32"]["value"] / out["adjoint_fp64"]["value"]
+    out["scope_rows"] = scope_rows(args)
     return out
 
 
@@ -437,8 +489,13 @@ def main():
     ap.add_argument("--single-warmup", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=800)
     ap.add_argument("--adjoint-ckpt", type=int, default=50)
+    ap.add_argument("--scope-steps", type=int, default=100)
+    ap.add_argument("--scope-warmup", type=int, default=30)
+    ap.add_argument("--scope-only", nargs="?", const="all", default="",
+                    help="only the walls, gamma, l2-metric and Euler workloads, or the one named (kernel traces)")
     ap.add_argument("--schedule", default="",
-                    help="transport variant,all-level cap,per-level cap[,graph 1|0] (skips autotuning)")
+                    help="transport variant,all-level cap,per-level cap[,graph 1|0[,pair links 0|1]] (skips "
+                         "autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel on %d bytes (counter calibration)" % COPY_BYTES)
     ap.add_argument("--adjoint-only", type=int, default=0, choices=[0, 4, 8],
@@ -457,6 +514,9 @@ def main():
         hip_build.build(force=False)
     if args.copy_calibration:
         print(json.dumps({"copy_kernel": "k_copy_u4", **copy_bandwidth()}))
+        return
+    if args.scope_only:
+        print(json.dumps(scope_rows(args, None if args.scope_only == "all" else args.scope_only)))
         return
     if args.adjoint_only:
         a = adjoint_run(args.adjoint_steps, args.adjoint_ckpt, args.adjoint_only)

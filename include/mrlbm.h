@@ -335,16 +335,23 @@ int mrlbm_adjoint(mrlbm_ctx *ctx, const void *abar_final, void *mbar0, double *s
  * a capped number of blocks that stride over the chunks of 64 list items; the
  * transport and the details have a per-item variant (one thread per leaf or
  * internal parent, all populations in it) and a per-population variant (one
- * wavefront per population), chosen together. The autotuner times
+ * wavefront per population), chosen together; the finest two links of the
+ * level chains can share a launch (pair_links). The autotuner times
  * every schedule of a small grid on the context's current state (steps that
  * leave the state unchanged, replayed from HIP graphs between HIP events),
  * keeps the fastest, and caches it for the process per (device architecture,
- * scheme, precision, floor(log2(leaves))). Schedules do not change results. */
+ * scheme, precision, floor(log2(leaves)), walls present, gamma, sibling
+ * metric). Schedules do not change results. */
 typedef struct {
   int transport_variant; /* transport and details: 1 one thread per item, 2 one wavefront per population */
   int list_grid_all;     /* block cap of the all-level list kernels (8..65536) */
   int list_grid_level;   /* block cap of the per-level list kernels (8..65536) */
   int graph;             /* 1: steps replayed from HIP graphs (default); 0: kernels launched one by one */
+  int pair_links;        /* 1: the two finest links of the projection, ghost and ancestor chains share a
+                          * launch, the second half's blocks waiting on a device counter for the first
+                          * half when both have work (one launch fewer; each waiting block then pays a
+                          * device-scope release of the first half's blocks); 0 (default): one launch
+                          * per link */
   int from_cache;        /* set by mrlbm_autotune: 1 if taken from the cache */
   double ms_per_step;    /* set by mrlbm_autotune: timed cost of the schedule (0 if cached) */
 } mrlbm_tuning;

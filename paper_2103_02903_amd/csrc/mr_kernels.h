@@ -1689,7 +1689,13 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     __syncthreads();
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    if (valid) {
+    bool todo = valid;  // MODE 1: the leaves near a wall belong to k_transport_wall_band
+    if (MODE == 1 && valid && I[i].walls) {
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      todo = !near_wall<DIM>(I[i], l, x, y);
+    }
+    if (todo) {
       int x, y;
       coords<DIM>(l, c, x, y);
       const int J = sjmax, n = J - l;
@@ -1698,7 +1704,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      if (MODE == 2 || (MODE == 1 && I[i].walls && near_wall<DIM>(I[i], l, x, y)))
+      if (MODE == 2)
         fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
                                                      n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
       else
@@ -1707,7 +1713,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       if (tape) tape[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     }
     __syncthreads();
-    if (h == 0 && valid) {
+    if (h == 0 && todo) {
       T g[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) g[k] = fl[k][lane];
@@ -1716,7 +1722,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       for (int k = 0; k < Q; ++k) fl[k][lane] = g[k];
     }
     __syncthreads();
-    if (valid) Fo[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
+    if (todo) Fo[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     __syncthreads();
   }
 }
@@ -1977,7 +1983,8 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
     // MODE 0: periodic, gamma = 1 (no general path); 1: leaves whose transport
-    // box reaches beyond a wall take the general path; 2 (gamma > 1): every leaf
+    // box reaches beyond a wall are left to k_transport_wall_band; 2 (gamma >
+    // 1): every leaf takes the general path
     bool wall = MODE == 2 && valid;
     if constexpr (MODE == 1) {
       int x, y;
@@ -1990,13 +1997,74 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
                      (c0 & ((1u << l0) - 1)) + 63u < (1u << l0) && __ballot(wall) == 0;
     if (!valid) continue;
     const Inst<T> &In = I[i];
-    if (MODE != 0 && wall)
+    if (MODE == 1 && wall) continue;  // k_transport_wall_band takes the leaves near a wall
+    if (MODE == 2 && wall)
       leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, wt, tape);
     else if (one_level)
       leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);
     else
       leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);
   }
+}
+
+// The leaves whose transport box reaches beyond a wall (batches with gamma = 1
+// and walls; the transport kernels leave them out), by the general path. Each
+// block takes 64 cells of the wall band of one level of one instance: the rows
+// within R = 2 gamma of a y wall, then the columns within R of an x wall in the
+// other rows (every cell when the level is at most 2R wide). Wavefront h
+// transports population h of the band cells that are complete leaves; the
+// collision then runs in wavefront 0 through LDS, as in the per-population
+// transport kernel. info[block] = instance | level << 8 | chunk << 13.
+constexpr int WBAND_CHUNK = 64;
+template <int DIM, int SCHEME, typename T>
+__global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
+    k_transport_wall_band(const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
+                          const uint8_t *__restrict__ code, const uint32_t *__restrict__ info, WallTabs<T> wt,
+                          T *__restrict__ tape) {
+  constexpr int Q = Vel<SCHEME>::Q;
+  __shared__ T fl[Q][64];
+  const uint32_t w = info[blockIdx.x];
+  const int i = (int)(w & 0xffu), l = (int)((w >> 8) & 0x1fu);
+  const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long k = (long long)(w >> 13) * WBAND_CHUNK + lane;
+  const Inst<T> &In = I[i];
+  const int N = 1 << l, R = 2 * In.gamma;
+  const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
+  const int rows = wy ? min(2 * R, N) : 0;                   // rows of the y band
+  const int cols = wx ? min(2 * R, N) : 0;                   // columns of the x band
+  const long long ny = DIM == 2 ? (long long)(N - rows) : 1;  // rows left to the x band
+  int x = 0, y = 0;
+  bool in = true;
+  if (k < (long long)rows * N) {
+    const int r = (int)(k / N);
+    x = (int)(k - (long long)r * N);
+    y = r < R ? r : N - rows + r;
+  } else {
+    const long long kk = k - (long long)rows * N;
+    in = kk < ny * cols;
+    const int r = in ? (int)(kk / cols) : 0, cc = in ? (int)(kk - (long long)r * cols) : 0;
+    y = DIM == 2 ? (wy ? R : 0) + r : 0;
+    x = cc < R ? cc : N - cols + cc;
+  }
+  const uint32_t c = (uint32_t)cidx<DIM>(l, x, y);
+  const bool leaf = in && code[In.loff[l] + c] == C_LEAF;
+  const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
+  if (leaf) {
+    const T *Ff0 = l < In.jmax ? Fs + (long long)Q * In.loff[l + 1] : Fs;
+    fl[h][lane] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
+    if (tape) tape[ol + h * nl + c] = fl[h][lane];
+  }
+  __syncthreads();
+  if (h == 0 && leaf) {
+    T g[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = fl[q][lane];
+    collide<SCHEME, T>(g, In.sc);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fl[q][lane] = g[q];
+  }
+  __syncthreads();
+  if (leaf) Fo[ol + h * nl + c] = fl[h][lane];
 }
 
 // ---------------------------------------------------------------- init / diagnostics

@@ -230,10 +230,11 @@ struct Plan {
   std::vector<int> dtab;       // [NDENSE][LVL_STRIDE][B + 1] dense-level block prefixes
   std::vector<uint32_t> binfo; // [nblocks] instance | level << 8 | chunk << 13 of all-level passes
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
+  std::vector<uint32_t> wband; // wall bands of the transport (gamma = 1 with walls): instance | level << 8 | chunk << 13
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
   size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_sync, off_ne[2], off_bcnt, off_boff, off_W,
-      off_C, off_Wb, off_Cb, off_Nb, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, bytes;
+      off_C, off_Wb, off_Cb, off_Nb, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, off_wband, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
     return dev + dstart[(size_t)off * LVL_STRIDE + L];
@@ -331,6 +332,21 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
           for (int k = 0; k < nb; ++k) P.dinfo.push_back((uint32_t)i | ((uint32_t)k << 8));
         }
     }
+  // cells within R = 2 gamma of a wall, per instance with walls and level: the
+  // rows of the y band, then the columns of the x band in the other rows
+  P.wband.clear();
+  for (int i = 0; i < B && P.gamma == 1; ++i) {
+    const int walls = P.inst[i].walls, R = 2 * P.gamma;
+    if (!walls) continue;
+    for (int l = P.inst[i].jmin; l <= P.inst[i].jmax; ++l) {
+      const long long N = 1ll << l;
+      const long long rows = (P.dim == 2 && (walls & 2)) ? std::min<long long>(2 * R, N) : 0;
+      const long long cols = (walls & 1) ? std::min<long long>(2 * R, N) : 0;
+      const long long n = rows * N + (P.dim == 2 ? N - rows : 1) * cols;
+      for (long long k = 0; k < (n + WBAND_CHUNK - 1) / WBAND_CHUNK; ++k)
+        P.wband.push_back((uint32_t)i | ((uint32_t)l << 8) | ((uint32_t)k << 13));
+    }
+  }
   for (int L = 0; L < LVL_STRIDE; ++L) {
     bool ok = L >= 4;
     for (int i = 0; i < B && ok; ++i)
@@ -369,6 +385,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_dtab = take(sizeof(int) * P.dtab.size());
   P.off_binfo = take(sizeof(uint32_t) * P.binfo.size());
   P.off_dinfo = take(sizeof(uint32_t) * std::max<size_t>(1, P.dinfo.size()));
+  P.off_wband = take(sizeof(uint32_t) * std::max<size_t>(1, P.wband.size()));
   P.bytes = o + 256;  // slack for aligning the base pointer
 }
 
@@ -487,11 +504,12 @@ struct mrlbm_ctx {
   void *inst;               // Inst<T>[B]
   long long *cb;
   int *cbp, *dtab;
-  uint32_t *binfo, *dinfo;
+  uint32_t *binfo, *dinfo, *wband;
   int cur;   // F[cur] holds the state
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
   std::vector<char> has_state;
   int transport_variant;  // 0: by size, 1: one thread per leaf, 2: one wavefront per population
+  bool pair_links;        // the finest two links of the level chains share a launch (tuning pair_links)
   unsigned grid_all, grid_level;  // block caps of the all-level and per-level list kernels
   // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
   char *adj_ws;
@@ -579,9 +597,9 @@ void drop_graphs(mrlbm_ctx *c) {
     }
 }
 
-// Event-record nodes e0 -> (last kernel node) -> e1 in a captured linear graph
-// whose last node is the transport kernel; returns the two nodes.
-hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, hipGraphNode_t *n1) {
+// Event-record nodes e0 -> (the last `count` kernel nodes) -> e1 in a captured
+// linear graph whose last nodes are the transport kernels; returns the two nodes.
+hipError_t bracket_last_kernels(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, hipGraphNode_t *n1, int count) {
   size_t n = 0;
   hipError_t e = hipGraphGetNodes(g, nullptr, &n);
   if (e != hipSuccess) return e;
@@ -600,14 +618,26 @@ hipError_t bracket_last_kernel(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0, 
   hipGraphNodeType type;
   if (!sink || (e = hipGraphNodeGetType(sink, &type)) != hipSuccess) return sink ? e : hipErrorInvalidValue;
   if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;
+  // walk back to the first of the last `count` kernel nodes (a chain: one dependency each)
+  hipGraphNode_t first = sink;
+  for (int k = 1; k < count; ++k) {
+    size_t np = 0;
+    if ((e = hipGraphNodeGetDependencies(first, nullptr, &np)) != hipSuccess) return e;
+    if (np != 1) return hipErrorInvalidValue;
+    hipGraphNode_t prev = nullptr;
+    if ((e = hipGraphNodeGetDependencies(first, &prev, &np)) != hipSuccess) return e;
+    first = prev;
+    if ((e = hipGraphNodeGetType(first, &type)) != hipSuccess) return e;
+    if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;
+  }
   size_t nd = 0;
-  if ((e = hipGraphNodeGetDependencies(sink, nullptr, &nd)) != hipSuccess) return e;
+  if ((e = hipGraphNodeGetDependencies(first, nullptr, &nd)) != hipSuccess) return e;
   std::vector<hipGraphNode_t> deps(nd);
-  if (nd && (e = hipGraphNodeGetDependencies(sink, deps.data(), &nd)) != hipSuccess) return e;
+  if (nd && (e = hipGraphNodeGetDependencies(first, deps.data(), &nd)) != hipSuccess) return e;
   for (hipGraphNode_t d : deps)
-    if ((e = hipGraphRemoveDependencies(g, &d, &sink, 1)) != hipSuccess) return e;
+    if ((e = hipGraphRemoveDependencies(g, &d, &first, 1)) != hipSuccess) return e;
   if ((e = hipGraphAddEventRecordNode(n0, g, deps.data(), nd, ev)) != hipSuccess) return e;
-  if ((e = hipGraphAddDependencies(g, n0, &sink, 1)) != hipSuccess) return e;
+  if ((e = hipGraphAddDependencies(g, n0, &first, 1)) != hipSuccess) return e;
   return hipGraphAddEventRecordNode(n1, g, &sink, 1, ev);
 }
 // Above this many cells (all instances and levels) the transport and the
@@ -647,6 +677,10 @@ struct Engine {
   // One thread per item and all populations in it (large sets), or one
   // wavefront per population (small sets: nine times the threads): for the
   // transport and the details.
+  // Kernel launches of the transport: one, and the wall-band kernel for gamma = 1 with walls.
+  static int transport_kernels(const mrlbm_ctx *c) {
+    return (c->P.gamma == 1 && c->P.any_walls && !c->P.wband.empty()) ? 2 : 1;
+  }
   static bool per_leaf(const mrlbm_ctx *c) {
     return c->transport_variant == 1 || (c->transport_variant == 0 && c->P.ctotal >= LEAF_KERNEL_CELLS);
   }
@@ -713,7 +747,7 @@ struct Engine {
     const Plan &P = c->P;
     const int lc = coarse_cap(c);
     int l = P.maxJ - 1;
-    if (l - 1 > std::max(P.jmin - 1, lc)) {  // the two finest levels share a launch
+    if (c->pair_links && l - 1 > std::max(P.jmin - 1, lc)) {  // the two finest levels share a launch
       if (mark) {
         const unsigned g0 = list_grid((level_chunks(c, l) + Q - 1) / Q, c->grid_level);
         const unsigned g1 = list_grid((level_chunks(c, l - 1) + Q - 1) / Q, c->grid_level);
@@ -748,7 +782,7 @@ struct Engine {
     project_all(c, m, F, li, c->lvl[m], lg, c->recon_reuse ? c->mark : nullptr);
     c->recon_reuse = false;
     const int l0 = std::max(P.jmin, lc) + 1;
-    const int last = P.maxJ - 1 >= l0 ? P.maxJ - 1 : P.maxJ + 1;  // first of the shared pair
+    const int last = c->pair_links && P.maxJ - 1 >= l0 ? P.maxJ - 1 : P.maxJ + 1;  // first of the shared pair
     for (int l = l0; l <= P.maxJ && l < last; ++l)
       k_ghost<DIM, Q, T, GAM><<<chunks_level(c, l), QB, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
     if (last <= P.maxJ) {  // the two finest levels share a launch
@@ -786,7 +820,7 @@ struct Engine {
     const int lc = coarse_cap(c);
     int la = P.maxJ;
     const int la_end = std::max(P.jmin + 2, lc + 3);
-    if (la - 1 >= la_end && P.dtab_total(2, la - 2) && P.dtab_total(2, la - 3)) {
+    if (c->pair_links && la - 1 >= la_end && P.dtab_total(2, la - 2) && P.dtab_total(2, la - 3)) {
       // the two finest links in one launch, ordered when the finest has kept
       // cells (children of internal cells one level up in the old mesh)
       const int nb0 = P.dtab_total(2, la - 2), nb1 = P.dtab_total(2, la - 3);
@@ -885,6 +919,9 @@ struct Engine {
       kern<<<chunks_all(c), QB, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     }
+    if (mode == 1 && !P.wband.empty())  // the leaves near a wall, which the kernel above left out
+      k_transport_wall_band<DIM, SCHEME, T><<<(unsigned)P.wband.size(), QB, 0, c->stream>>>(
+          I(c), Fc, Fn, c->code[m], c->wband, wall_tabs(c), tape);
     phase_mark(c, PH_TRANSPORT, false);
     c->cur = 1 - c->cur;
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
@@ -917,7 +954,8 @@ struct Engine {
       c->mcur = par;
       c->cur = cur0;
       if (rc == MRLBM_OK && e == hipSuccess && timed)
-        e = bracket_last_kernel(graph, c->ev_placeholder, &c->timed_ev[key][0], &c->timed_ev[key][1]);
+        e = bracket_last_kernels(graph, c->ev_placeholder, &c->timed_ev[key][0], &c->timed_ev[key][1],
+                                 transport_kernels(c));
       if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
       if (rc == MRLBM_OK && e == hipSuccess && timed) {
         c->timed_src[key] = graph;  // the event nodes belong to it
@@ -1465,6 +1503,7 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   c->dtab = (int *)(b + P.off_dtab);
   c->binfo = (uint32_t *)(b + P.off_binfo);
   c->dinfo = (uint32_t *)(b + P.off_dinfo);
+  c->wband = (uint32_t *)(b + P.off_wband);
   c->cur = 0;
   c->mcur = 0;
   c->has_state.assign(P.B, 0);
@@ -1492,6 +1531,7 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
     }
   }
   c->transport_variant = 0;
+  c->pair_links = false;
   c->grid_all = LIST_GRID_ALL;
   c->grid_level = LIST_GRID_LEVEL;
   // transport weight tables, rounded once to the working precision
@@ -1547,6 +1587,8 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   if (e == hipSuccess) e = hipMemcpy(c->binfo, P.binfo.data(), sizeof(uint32_t) * P.binfo.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !P.dinfo.empty())
     e = hipMemcpy(c->dinfo, P.dinfo.data(), sizeof(uint32_t) * P.dinfo.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.wband.empty())
+    e = hipMemcpy(c->wband, P.wband.data(), sizeof(uint32_t) * P.wband.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
@@ -1825,11 +1867,14 @@ int mrlbm_adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sba
 
 // ---------------------------------------------------------------- autotuner
 namespace {
+// A schedule is kept per device, scheme, precision, leaf-count octave and
+// kernel class (walls, gamma, metric: they select other kernels).
 struct TuneKey {
   std::string arch;
-  int scheme, precision, bucket;
+  int scheme, precision, bucket, walls, gamma, metric;
   bool operator<(const TuneKey &o) const {
-    return std::tie(arch, scheme, precision, bucket) < std::tie(o.arch, o.scheme, o.precision, o.bucket);
+    return std::tie(arch, scheme, precision, bucket, walls, gamma, metric) <
+           std::tie(o.arch, o.scheme, o.precision, o.bucket, o.walls, o.gamma, o.metric);
   }
 };
 std::mutex tune_mutex;
@@ -1837,11 +1882,13 @@ std::map<TuneKey, mrlbm_tuning> tune_cache;
 
 int apply_tuning(mrlbm_ctx *c, const mrlbm_tuning &t) {
   if ((t.transport_variant != 1 && t.transport_variant != 2) || t.list_grid_all < 8 || t.list_grid_all > 65536 ||
-      t.list_grid_level < 8 || t.list_grid_level > 65536 || (t.graph != 0 && t.graph != 1))
+      t.list_grid_level < 8 || t.list_grid_level > 65536 || (t.graph != 0 && t.graph != 1) ||
+      (t.pair_links != 0 && t.pair_links != 1))
     return MRLBM_ERR_INVALID;
   if (t.graph == 1 && !c->cap_stream) return MRLBM_ERR_STATE;  // static context: no capture stream
   if (c->transport_variant != t.transport_variant || c->grid_all != (unsigned)t.list_grid_all ||
-      c->grid_level != (unsigned)t.list_grid_level || c->use_graph != (t.graph == 1)) {
+      c->grid_level != (unsigned)t.list_grid_level || c->use_graph != (t.graph == 1) ||
+      c->pair_links != (t.pair_links == 1)) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
   }
@@ -1849,6 +1896,7 @@ int apply_tuning(mrlbm_ctx *c, const mrlbm_tuning &t) {
   c->transport_variant = t.transport_variant;
   c->grid_all = (unsigned)t.list_grid_all;
   c->grid_level = (unsigned)t.list_grid_level;
+  c->pair_links = t.pair_links == 1;
   return MRLBM_OK;
 }
 
@@ -1874,6 +1922,7 @@ int mrlbm_get_tuning(const mrlbm_ctx *c, mrlbm_tuning *out) {
   out->list_grid_all = (int)c->grid_all;
   out->list_grid_level = (int)c->grid_level;
   out->graph = c->use_graph ? 1 : 0;
+  out->pair_links = c->pair_links ? 1 : 0;
   return MRLBM_OK;
 }
 
@@ -1894,7 +1943,8 @@ int mrlbm_autotune(mrlbm_ctx *c, int reps, mrlbm_tuning *out) {
   HIPCHK(hipGetDeviceProperties(&prop, dev));
   int bucket = 0;
   while ((2ll << bucket) <= leaves) ++bucket;  // floor(log2(leaves))
-  const TuneKey key{prop.gcnArchName, c->p[0].scheme, c->p[0].precision, bucket};
+  const TuneKey key{prop.gcnArchName, c->p[0].scheme, c->p[0].precision, bucket,
+                    c->P.any_walls ? 1 : 0, c->P.gamma, c->P.metric_mode};
   {
     std::lock_guard<std::mutex> lock(tune_mutex);
     auto it = tune_cache.find(key);
@@ -1914,21 +1964,23 @@ int mrlbm_autotune(mrlbm_ctx *c, int reps, mrlbm_tuning *out) {
   const int level_caps[3] = {256, 1024, 4096};
   for (int v : variants)
     for (int ga : all_caps)
-      for (int gl : level_caps) {
-        mrlbm_tuning t{};
-        t.transport_variant = v;
-        t.list_grid_all = ga;
-        t.list_grid_level = gl;
-        t.graph = 1;
-        rc = apply_tuning(c, t);
-        float ms = 0.f;
-        if (!rc) rc = dispatch<DryOp>(c, reps, &ms);
-        if (rc) return rc;
-        if (ms < best.ms_per_step) {
-          best = t;
-          best.ms_per_step = ms;
+      for (int gl : level_caps)
+        for (int pl = 0; pl < 2; ++pl) {
+          mrlbm_tuning t{};
+          t.transport_variant = v;
+          t.list_grid_all = ga;
+          t.list_grid_level = gl;
+          t.graph = 1;
+          t.pair_links = pl;
+          rc = apply_tuning(c, t);
+          float ms = 0.f;
+          if (!rc) rc = dispatch<DryOp>(c, reps, &ms);
+          if (rc) return rc;
+          if (ms < best.ms_per_step) {
+            best = t;
+            best.ms_per_step = ms;
+          }
         }
-      }
   HIPCHK(hipMemcpy(c->cnt, cnt, sizeof cnt, hipMemcpyHostToDevice));
   rc = apply_tuning(c, best);
   if (rc) return rc;

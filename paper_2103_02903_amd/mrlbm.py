@@ -62,8 +62,8 @@ class Counters(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("transport_variant", ctypes.c_int), ("list_grid_all", ctypes.c_int),
-                ("list_grid_level", ctypes.c_int), ("graph", ctypes.c_int), ("from_cache", ctypes.c_int),
-                ("ms_per_step", ctypes.c_double)]
+                ("list_grid_level", ctypes.c_int), ("graph", ctypes.c_int), ("pair_links", ctypes.c_int),
+                ("from_cache", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -328,8 +328,10 @@ class Batch:
         _check("mrlbm_get_tuning", lib().mrlbm_get_tuning(self._ctx, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, transport_variant: int, list_grid_all: int, list_grid_level: int, graph: int = 1):
-        t = Tuning(int(transport_variant), int(list_grid_all), int(list_grid_level), int(graph), 0, 0.0)
+    def set_tuning(self, transport_variant: int, list_grid_all: int, list_grid_level: int, graph: int = 1,
+                   pair_links: int = 0):
+        t = Tuning(int(transport_variant), int(list_grid_all), int(list_grid_level), int(graph), int(pair_links), 0,
+                   0.0)
         _check("mrlbm_set_tuning", lib().mrlbm_set_tuning(self._ctx, ctypes.byref(t)))
 
     # ---- adjoint on frozen meshes (batch of one)

@@ -198,6 +198,8 @@ def test_pair_wait_timeout_is_reported(mr):
     m0 = W.random_field(cfg, 4, "smooth")
     sim = mr.Sim(cfg)
     sim.init_equilibrium(m0)
+    t = sim.tuning()  # the paired launches (tuning pair_links)
+    sim.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"], graph=t["graph"], pair_links=1)
     sim.step(2)
     assert sim.stats()["leaves"][8] == 256 * 256  # no flag after ordered waits that succeed
     sim.debug_pair_wait(64, -(1 << 30))

@@ -389,6 +389,31 @@ def test_transport_variants_bit_identical(mr):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][leaves], b[1][leaves])
 
 
+@pytest.mark.parametrize("prec", [8, 4])
+def test_paired_links_bit_identical(mr, prec):
+    """The finest two links of the level chains in one paired launch (tuning
+    pair_links = 1) or in one launch each: the same meshes and bits, with the
+    finest level holding cells (the pairs then wait) and with a batch whose
+    instances reach it unevenly."""
+    cfgs = [_cfg("D2Q9", 3, 8, 0.0), _cfg("D2Q9", 3, 8, 1e-3), _cfg("D2Q9", 3, 7, 1e-3)]
+    m0s = [W.random_field(c, 70 + k, "jump") for k, c in enumerate(cfgs)]
+    out = {}
+    for pl in (0, 1):
+        b = mr.Batch(cfgs, precision=prec)
+        t = b.tuning()
+        b.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"], graph=t["graph"], pair_links=pl)
+        assert b.tuning()["pair_links"] == pl
+        for i, m in enumerate(m0s):
+            b.init_equilibrium(i, m)
+        b.step(6)
+        out[pl] = [b.get_state(i) for i in range(len(cfgs))]
+        b.close()
+    for i, c in enumerate(cfgs):
+        a, p = out[0][i], out[1][i]
+        leaves = _leaf_entries(oracle.Oracle(c), a[0])
+        assert np.array_equal(a[0], p[0]) and np.array_equal(a[1][leaves], p[1][leaves])
+
+
 def test_graph_steps_match_eager_launches(mr):
     """Steps replayed from HIP graphs (plain and with the timed transport launched
     outside the graph) compute the same bits as kernel-by-kernel launches, also
