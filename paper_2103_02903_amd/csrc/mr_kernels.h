@@ -1599,9 +1599,13 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
   const T *W = wt.W + (((long long)nn * 9 + wc) * Q + h) * WSg;
   const T *Cw = wt.C + (((long long)nn * 9 + wc) * Q + h) * CSg;
   T acc = T(0);
-  for (int b = (DIM == 2 ? -R : 0); b <= (DIM == 2 ? R : 0); ++b) {
+  // an axis velocity's weights vanish off its own row (column): the sums over
+  // the other rows of the leaf's cells of a unit impulse's reconstruction
+  const int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
+  const int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+  for (int b = b0; b <= b1; ++b) {
     const long long row = DIM == 2 ? ((long long)axl(y + b, l, wy) << l) : 0;
-    for (int a = -R; a <= R; ++a)
+    for (int a = a0; a <= a1; ++a)
       acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + axl(x + a, l, wx)], acc);
   }
   // neighbours refined one level further, mirrored beyond a wall
@@ -1647,6 +1651,107 @@ __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, in
 #pragma unroll
   for (int h = 0; h < Q; ++h)
     f[h] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
+  if (tape)
+#pragma unroll
+    for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
+  collide<SCHEME, T>(f, In.sc);
+#pragma unroll
+  for (int h = 0; h < Q; ++h) Fo[ol + h * nl + c] = f[h];
+}
+
+// ParentStencil::load_wide for a half-width G known at compile time and a
+// periodic neighbourhood (the same operations in the same order).
+template <int DIM, typename T, int G>
+__device__ __forceinline__ void parent_stencil_g(ParentStencil<DIM, T> &st, const T *__restrict__ P, int lp, int px,
+                                                 int py) {
+  auto at = [&](int a, int b) -> T {
+    return DIM == 1 ? P[wrapl(px + a, lp)] : P[cidx<2>(lp, wrapl(px + a, lp), wrapl(py + b, lp))];
+  };
+  st.c = at(0, 0);
+  st.qx = T(table1(G, 1)) * (at(1, 0) - at(-1, 0));
+#pragma unroll
+  for (int a = 2; a <= G; ++a) st.qx = st.qx + T(table1(G, a)) * (at(a, 0) - at(-a, 0));
+  if (DIM == 1) {
+    st.qy = T(0);
+    st.qxy = T(0);
+    return;
+  }
+  st.qy = T(table1(G, 1)) * (at(0, 1) - at(0, -1));
+#pragma unroll
+  for (int b = 2; b <= G; ++b) st.qy = st.qy + T(table1(G, b)) * (at(0, b) - at(0, -b));
+  auto term = [&](int a, int b) -> T {
+    return T(table1(G, a) * table1(G, b)) * (((at(a, b) - at(-a, b)) - at(a, -b)) + at(-a, -b));
+  };
+  st.qxy = term(1, 1);
+#pragma unroll
+  for (int b = 1; b <= G; ++b)
+#pragma unroll
+    for (int a = (b == 1 ? 2 : 1); a <= G; ++a) st.qxy = st.qxy + term(a, b);
+}
+
+// transport_wall for a leaf whose transport box stays inside the domain (a
+// periodic instance, or a leaf farther than 2 G cells from every wall), with
+// the prediction half-width G as a compile-time constant: no reflection, the
+// tables of wall case 0, the same operations in the same order.
+template <int DIM, int SCHEME, typename T, int G>
+__device__ __attribute__((noinline)) T transport_inner_g(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
+                                               const T *__restrict__ Fl0, const T *__restrict__ Ff0,
+                                               const uint8_t *__restrict__ cl, WallTabs<T> wt) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q, R = 2 * G, WW = 2 * R + 1, CW = 2 * R + 2;
+  constexpr int WSg = DIM == 2 ? WW * WW : WW, CSg = DIM == 2 ? CW * CW : CW;
+  const int ex = V::ex(h), ey = V::ey(h), n = In.jmax - l;
+  const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
+  const T *Fl = Fl0 + (long long)h * nl;
+  if (ex == 0 && ey == 0) return Fl[c];
+  if (n == 0) return Fl[cidx<DIM>(l, wrapl(x - ex, l), wrapl(y - ey, l))];
+  const T *W = wt.W + ((long long)(n - 1) * 9 * Q + h) * WSg;
+  const T *Cw = wt.C + ((long long)(n - 1) * 9 * Q + h) * CSg;
+  T acc = T(0);
+  const int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
+  const int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+  for (int b = b0; b <= b1; ++b) {
+    const long long row = DIM == 2 ? ((long long)wrapl(y + b, l) << l) : 0;
+#pragma unroll
+    for (int a = -R; a <= R; ++a)
+      if (a >= a0 && a <= a1) acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + wrapl(x + a, l)], acc);
+  }
+  const T *Ff = Ff0 + (long long)h * nf;
+  for (int b = (DIM == 2 ? -G : 0); b <= (DIM == 2 ? G : 0); ++b)
+#pragma unroll 1
+    for (int a = -G; a <= G; ++a) {
+      if (a == 0 && b == 0) continue;
+      const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
+      if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
+      ParentStencil<DIM, T> st;
+      parent_stencil_g<DIM, T, G>(st, Fl, l, px, py);
+#pragma unroll
+      for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const T d = Ff[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] - st.child(dx, dy);
+          const int y1 = 2 * a + dx + R, y2 = DIM == 2 ? 2 * b + dy + R : 0;
+          acc = fma(Cw[y2 * CW + y1], d, acc);
+        }
+    }
+  return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
+}
+
+// One leaf by transport_inner_g, then the tape, the collision and the store.
+template <int DIM, int SCHEME, typename T, int G>
+__device__ __forceinline__ void leaf_update_inner_g(const Inst<T> &In, int l, uint32_t c,
+                                                    const T *__restrict__ Fs, T *__restrict__ Fo,
+                                                    const uint8_t *__restrict__ code, WallTabs<T> wt,
+                                                    T *__restrict__ tape) {
+  constexpr int Q = Vel<SCHEME>::Q;
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
+  const T *Ff0 = l < In.jmax ? Fs + (long long)Q * In.loff[l + 1] : Fs;
+  T f[Q];
+#pragma unroll
+  for (int h = 0; h < Q; ++h)
+    f[h] = transport_inner_g<DIM, SCHEME, T, G>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
   if (tape)
 #pragma unroll
     for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
@@ -1704,7 +1809,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      if (MODE == 2)
+      if (MODE >= 2)
         fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
                                                      n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
       else
@@ -1957,7 +2062,7 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
 // whose leaves share one level (all but those that straddle a level boundary)
 // takes leaf_update_level, in row mode when its leaves are one row segment.
 template <int DIM, int SCHEME, typename T, int MODE>
-__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(MODE >= 2 ? 2 : (sizeof(T) == 4 ? 5 : 4))))
     k_transport_collide_leaf(Batch bt, const Inst<T> *__restrict__ I, const T *__restrict__ Fs, T *__restrict__ Fo,
                              const uint8_t *__restrict__ code, const uint32_t *__restrict__ leaves,
                              const int *__restrict__ lvl, const T *__restrict__ Wt, const T *__restrict__ Ct,
@@ -1982,11 +2087,12 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint32_t c = e & CELL_MASK;
     const int l0 = __builtin_amdgcn_readfirstlane(l);
     const bool one_level = __ballot(valid && l != l0) == 0;
-    // MODE 0: periodic, gamma = 1 (no general path); 1: leaves whose transport
-    // box reaches beyond a wall are left to k_transport_wall_band; 2 (gamma >
-    // 1): every leaf takes the general path
-    bool wall = MODE == 2 && valid;
-    if constexpr (MODE == 1) {
+    // MODE 0: periodic, gamma = 1; 1 (gamma = 1 with walls): leaves whose
+    // transport box reaches beyond a wall are left to k_transport_wall_band;
+    // MODE = gamma > 1: those leaves take the general path here, the others
+    // the path of that gamma
+    bool wall = false;
+    if constexpr (MODE != 0) {
       int x, y;
       coords<DIM>(l, c, x, y);
       wall = valid && I[i].walls && near_wall<DIM>(I[i], l, x, y);
@@ -1998,9 +2104,12 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof
     if (!valid) continue;
     const Inst<T> &In = I[i];
     if (MODE == 1 && wall) continue;  // k_transport_wall_band takes the leaves near a wall
-    if (MODE == 2 && wall)
-      leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, wt, tape);
-    else if (one_level)
+    if constexpr (MODE >= 2) {
+      if (wall)
+        leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, wt, tape);
+      else
+        leaf_update_inner_g<DIM, SCHEME, T, MODE>(In, l, c, Fs, Fo, code, wt, tape);
+    } else if (one_level)
       leaf_update_level<DIM, SCHEME, T>(In, l0, c, Fs, Fo, code, Wt, Ct, tape, row, rowbuf[wave]);
     else
       leaf_update<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, Wt, Ct, tape);

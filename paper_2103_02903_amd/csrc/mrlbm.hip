@@ -903,17 +903,19 @@ struct Engine {
     T *Fn = (T *)c->F[1 - c->cur];
     phase_mark(c, PH_TRANSPORT, true);
     const uint32_t *lf = c->lists[m] + (size_t)CAT_LEAF * P.ctotal;
-    // kernel variant: 0 periodic with gamma = 1, 1 walls (near them the general
-    // path), 2 gamma > 1 (the general path everywhere)
-    const int mode = P.gamma > 1 ? 2 : (P.any_walls ? 1 : 0);
+    // kernel variant: 0 periodic with gamma = 1, 1 walls with gamma = 1 (the
+    // wall band in a kernel of its own), gamma > 1: the variant of that gamma
+    // (the general path near walls)
+    const int mode = P.gamma > 1 ? P.gamma : (P.any_walls ? 1 : 0);
     if (per_leaf(c)) {
-      auto kern = mode == 2   ? k_transport_collide_leaf<DIM, SCHEME, T, 2>
+      auto kern = mode == 3   ? k_transport_collide_leaf<DIM, SCHEME, T, 3>
+                  : mode == 2 ? k_transport_collide_leaf<DIM, SCHEME, T, 2>
                   : mode == 1 ? k_transport_collide_leaf<DIM, SCHEME, T, 1>
                               : k_transport_collide_leaf<DIM, SCHEME, T, 0>;
       kern<<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     } else {
-      auto kern = mode == 2   ? k_transport_collide_pop<DIM, SCHEME, T, 2>
+      auto kern = mode >= 2   ? k_transport_collide_pop<DIM, SCHEME, T, 2>
                   : mode == 1 ? k_transport_collide_pop<DIM, SCHEME, T, 1>
                               : k_transport_collide_pop<DIM, SCHEME, T, 0>;
       kern<<<chunks_all(c), QB, 0, c->stream>>>(
