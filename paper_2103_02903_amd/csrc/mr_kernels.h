@@ -1794,11 +1794,14 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
     __syncthreads();
     const int l = (int)(e >> LEVEL_SHIFT);
     const uint32_t c = e & CELL_MASK;
-    bool todo = valid;  // MODE 1: the leaves near a wall belong to k_transport_wall_band
-    if (MODE == 1 && valid && I[i].walls) {
+    // MODE 1: the leaves near a wall belong to k_transport_wall_band; MODE =
+    // gamma > 1: they take the general path, the others the path of that gamma
+    bool todo = valid, wall = false;
+    if (MODE != 0 && valid && I[i].walls) {
       int x, y;
       coords<DIM>(l, c, x, y);
-      todo = !near_wall<DIM>(I[i], l, x, y);
+      wall = near_wall<DIM>(I[i], l, x, y);
+      if (MODE == 1) todo = !wall;
     }
     if (todo) {
       int x, y;
@@ -1809,12 +1812,17 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const T *Fl = Fs + (long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l);
       const T *Ff = n > 0 ? Fs + (long long)Q * sloff[l + 1] + (long long)h * ncells_d(DIM, l + 1) : Fl;
       const int nn = n > 0 ? n - 1 : 0;
-      if (MODE >= 2)
-        fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
-                                                     n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
-      else
+      if constexpr (MODE >= 2) {
+        if (wall)
+          fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
+                                                       n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
+        else
+          fl[h][lane] = transport_inner_g<DIM, SCHEME, T, MODE>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
+                                                                n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
+      } else {
         fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
                                                     Ct + ((long long)nn * Q + h) * CS, nbr);
+      }
       if (tape) tape[(long long)Q * sloff[l] + (long long)h * ncells_d(DIM, l) + c] = fl[h][lane];
     }
     __syncthreads();

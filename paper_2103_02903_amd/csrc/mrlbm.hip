@@ -915,7 +915,8 @@ struct Engine {
       kern<<<list_grid((P.ctotal + BLK - 1) / BLK, c->grid_all), BLK, 0, c->stream>>>(
           c->bt, I(c), Fc, Fn, c->code[m], lf, c->lvl[m], (const T *)c->W, (const T *)c->C, wall_tabs(c), c->cnt, tape);
     } else {
-      auto kern = mode >= 2   ? k_transport_collide_pop<DIM, SCHEME, T, 2>
+      auto kern = mode == 3   ? k_transport_collide_pop<DIM, SCHEME, T, 3>
+                  : mode == 2 ? k_transport_collide_pop<DIM, SCHEME, T, 2>
                   : mode == 1 ? k_transport_collide_pop<DIM, SCHEME, T, 1>
                               : k_transport_collide_pop<DIM, SCHEME, T, 0>;
       kern<<<chunks_all(c), QB, 0, c->stream>>>(
