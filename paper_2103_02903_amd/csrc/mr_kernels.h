@@ -979,42 +979,85 @@ __global__ void __launch_bounds__(BLK) k_classify_ghost(Batch bt, const Inst<T> 
   ghost_run4<DIM, T>(I[i], code, l, c0);
 }
 
-// The same classification for a prediction of half-width gamma > 1: a cell
-// outside the tree is a ghost if a leaf of its level lies within 2 gamma of it
-// (the transport box of that leaf) or if a ghost of level l+1 has its parent
-// within gamma of it (the prediction of that ghost). Four consecutive cells per
-// thread, plain loops (boxes wrap periodically; with walls this marks a
-// superset of the cells read, whose reads stay inside the domain).
+// The same classification for a prediction of half-width gamma > 1 (a leaf of
+// level l within 2 gamma, or a ghost of level l+1 whose parent lies within
+// gamma), for a tile of TX x TY cells of level l per block, through LDS: the leaf flags of the tile with a halo of R = 2 gamma cells,
+// dilated by R along x and then along y, and the ghost flags of level l+1 under
+// the parents within gamma of the tile, folded to their parents and dilated by
+// gamma; a cell outside the tree whose dilated flags hold is a ghost. Boxes
+// wrap periodically (the superset noted above with walls). info[block] =
+// instance | tile << 8 (tiles row-major over the level).
+constexpr int GT_X = 64, GT_Y = 16, GT_R = 6;  // tile size and the largest 2 gamma
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLK) k_classify_ghost_wide(Batch bt, const Inst<T> *__restrict__ I,
+__global__ void __launch_bounds__(BLK) k_classify_ghost_tile(Batch bt, const Inst<T> *__restrict__ I,
                                                              uint8_t *__restrict__ code,
                                                              const uint32_t *__restrict__ info, int l,
                                                              const int *__restrict__ act) {
+  constexpr int TX = DIM == 2 ? GT_X : GT_X * GT_Y, TY = DIM == 2 ? GT_Y : 1;
+  constexpr int HX = TX + 2 * GT_R, HY = DIM == 2 ? TY + 2 * GT_R : 1;            // leaf flags with halo
+  constexpr int CX = 2 * (TX + GT_R), CY = DIM == 2 ? 2 * (TY + GT_R) : 1;        // children under the parents
+  constexpr int PX = TX + GT_R, PY = DIM == 2 ? TY + GT_R : 1;                    // those parents
+  __shared__ uint8_t lf[HY][HX], hx[HY][TX], cf[CY][CX], pf[PY][PX], px_[PY][TX];
   const uint32_t w = info[blockIdx.x];
   const int i = (int)(w & 0xffu);
-  const long long c0 = ((long long)(w >> 8) * BLK + threadIdx.x) * 4;
   const Inst<T> &In = I[i];
-  const long long nl = ncells_d(DIM, l);
-  if (c0 >= nl || l > active_top(act, In, i)) return;
-  const int g = In.gamma, R = 2 * g;
+  if (l > active_top(act, In, i)) return;  // (uniform over the block)
+  const int N = 1 << l, g = In.gamma, R = 2 * g;
+  const int ntx = (N + TX - 1) / TX, tile = (int)(w >> 8);
+  const int x0 = (tile % ntx) * TX, y0 = DIM == 2 ? (tile / ntx) * TY : 0;
   uint8_t *cl = code + In.loff[l];
-  const uint8_t *cf = l < In.jmax ? code + In.loff[l + 1] : nullptr;
-  for (long long c = c0; c < c0 + 4 && c < nl; ++c) {
-    if (cl[c] != C_NONE) continue;
-    int x, y;
-    coords<DIM>(l, (uint32_t)c, x, y);
-    bool need = false;
-    for (int b = (DIM == 2 ? -R : 0); b <= (DIM == 2 ? R : 0) && !need; ++b)
-      for (int a = -R; a <= R && !need; ++a)
-        need = cl[cidx<DIM>(l, wrapl(x + a, l), wrapl(y + b, l))] == C_LEAF;
-    if (cf)
-      for (int b = (DIM == 2 ? -g : 0); b <= (DIM == 2 ? g : 0) && !need; ++b)
-        for (int a = -g; a <= g && !need; ++a) {
-          const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
-          for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-            for (int dx = 0; dx < 2; ++dx) need |= cf[cidx<DIM>(l + 1, 2 * px + dx, 2 * py + dy)] == C_GHOST;
-        }
-    if (need) cl[c] = C_GHOST;
+  const bool finer = l < In.jmax;
+  const uint8_t *cfl = finer ? code + In.loff[l + 1] : nullptr;
+  const int RY = DIM == 2 ? TY + 2 * R : 1;  // rows of the leaf flags
+  // leaf flags of rows y0-R .. y0+TY-1+R, columns x0-R .. x0+TX-1+R
+  for (int k = threadIdx.x; k < RY * (TX + 2 * R); k += BLK) {
+    const int r = k / (TX + 2 * R), q = k - r * (TX + 2 * R);
+    const int x = wrapl(x0 - R + q, l), y = DIM == 2 ? wrapl(y0 - R + r, l) : 0;
+    lf[r][q] = cl[cidx<DIM>(l, x, y)] == C_LEAF;
+  }
+  // ghost flags of level l+1 under the parents x0-g .. x0+TX-1+g (rows alike)
+  if (finer)
+    for (int k = threadIdx.x; k < (DIM == 2 ? 2 * (TY + 2 * g) : 1) * 2 * (TX + 2 * g); k += BLK) {
+      const int w2 = 2 * (TX + 2 * g), r = k / w2, q = k - r * w2;
+      const int x = wrapl(2 * (x0 - g) + q, l + 1), y = DIM == 2 ? wrapl(2 * (y0 - g) + r, l + 1) : 0;
+      cf[r][q] = cfl[cidx<DIM>(l + 1, x, y)] == C_GHOST;
+    }
+  __syncthreads();
+  // dilation of the leaf flags along x, rows of the halo
+  for (int k = threadIdx.x; k < RY * TX; k += BLK) {
+    const int r = k / TX, q = k - r * TX;
+    uint8_t v = 0;
+    for (int a = 0; a <= 2 * R; ++a) v |= lf[r][q + a];
+    hx[r][q] = v;
+  }
+  // parent flags: some child is a ghost
+  if (finer)
+    for (int k = threadIdx.x; k < (DIM == 2 ? TY + 2 * g : 1) * (TX + 2 * g); k += BLK) {
+      const int r = k / (TX + 2 * g), q = k - r * (TX + 2 * g);
+      uint8_t v = cf[DIM == 2 ? 2 * r : 0][2 * q] | cf[DIM == 2 ? 2 * r : 0][2 * q + 1];
+      if (DIM == 2) v |= cf[2 * r + 1][2 * q] | cf[2 * r + 1][2 * q + 1];
+      pf[r][q] = v;
+    }
+  __syncthreads();
+  if (finer)  // dilation of the parent flags along x by gamma
+    for (int k = threadIdx.x; k < (DIM == 2 ? TY + 2 * g : 1) * TX; k += BLK) {
+      const int r = k / TX, q = k - r * TX;
+      uint8_t v = 0;
+      for (int a = 0; a <= 2 * g; ++a) v |= pf[r][q + a];
+      px_[r][q] = v;
+    }
+  __syncthreads();
+  // the tile's cells: dilation along y, then the classification
+  for (int k = threadIdx.x; k < TY * TX; k += BLK) {
+    const int r = k / TX, q = k - r * TX;
+    const int x = x0 + q, y = y0 + r;
+    if (x >= N || (DIM == 2 && y >= N)) continue;
+    uint8_t v = 0;
+    for (int b = 0; b <= (DIM == 2 ? 2 * R : 0); ++b) v |= hx[r + b][q];
+    if (finer)
+      for (int b = 0; b <= (DIM == 2 ? 2 * g : 0); ++b) v |= px_[r + b][q];
+    const long long c = cidx<DIM>(l, x, y);
+    if (v && cl[c] == C_NONE) cl[c] = C_GHOST;
   }
 }
 
@@ -1689,18 +1732,36 @@ __device__ __forceinline__ void parent_stencil_g(ParentStencil<DIM, T> &st, cons
     for (int a = (b == 1 ? 2 : 1); a <= G; ++a) st.qxy = st.qxy + term(a, b);
 }
 
+// Neighbours of (x, y) within G (periodic) that are internal cells, as bits
+// (b + G)(2G + 1) + (a + G) of offset (a, b): their codes are loaded together,
+// once per leaf.
+template <int DIM, int G>
+__device__ __forceinline__ unsigned long long refined_within_g(const uint8_t *__restrict__ cl, int l, int x, int y) {
+  constexpr int S = 2 * G + 1;
+  unsigned long long m = 0;
+#pragma unroll
+  for (int b = (DIM == 2 ? -G : 0); b <= (DIM == 2 ? G : 0); ++b)
+#pragma unroll
+    for (int a = -G; a <= G; ++a)
+      if ((a != 0 || b != 0) && cl[cidx<DIM>(l, wrapl(x + a, l), DIM == 2 ? wrapl(y + b, l) : 0)] == C_INTERNAL)
+        m |= 1ull << ((b + G) * S + (a + G));
+  return m;
+}
+
 // transport_wall for a leaf whose transport box stays inside the domain (a
 // periodic instance, or a leaf farther than 2 G cells from every wall), with
-// the prediction half-width G as a compile-time constant: no reflection, the
-// tables of wall case 0, the same operations in the same order.
-template <int DIM, int SCHEME, typename T, int G>
-__device__ __attribute__((noinline)) T transport_inner_g(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
-                                               const T *__restrict__ Fl0, const T *__restrict__ Ff0,
-                                               const uint8_t *__restrict__ cl, WallTabs<T> wt) {
+// the prediction half-width G and the population H as compile-time constants:
+// no reflection, the tables of wall case 0, the refined neighbours given as
+// bits (refined_within_g); the same operations in the same order.
+template <int DIM, int SCHEME, typename T, int G, int H>
+__device__ __attribute__((noinline)) T transport_inner_g(const Inst<T> &In, int l, uint32_t c, int x, int y,
+                                                         const T *__restrict__ Fl0, const T *__restrict__ Ff0,
+                                                         unsigned long long nbm, WallTabs<T> wt) {
   using V = Vel<SCHEME>;
-  constexpr int Q = V::Q, R = 2 * G, WW = 2 * R + 1, CW = 2 * R + 2;
+  constexpr int Q = V::Q, R = 2 * G, WW = 2 * R + 1, CW = 2 * R + 2, h = H;
   constexpr int WSg = DIM == 2 ? WW * WW : WW, CSg = DIM == 2 ? CW * CW : CW;
-  const int ex = V::ex(h), ey = V::ey(h), n = In.jmax - l;
+  constexpr int ex = V::ex(H), ey = V::ey(H);
+  const int n = In.jmax - l;
   const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
   const T *Fl = Fl0 + (long long)h * nl;
   if (ex == 0 && ey == 0) return Fl[c];
@@ -1708,21 +1769,21 @@ __device__ __attribute__((noinline)) T transport_inner_g(const Inst<T> &In, int 
   const T *W = wt.W + ((long long)(n - 1) * 9 * Q + h) * WSg;
   const T *Cw = wt.C + ((long long)(n - 1) * 9 * Q + h) * CSg;
   T acc = T(0);
-  const int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
-  const int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+  constexpr int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
+  constexpr int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+#pragma unroll
   for (int b = b0; b <= b1; ++b) {
     const long long row = DIM == 2 ? ((long long)wrapl(y + b, l) << l) : 0;
 #pragma unroll
-    for (int a = -R; a <= R; ++a)
-      if (a >= a0 && a <= a1) acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + wrapl(x + a, l)], acc);
+    for (int a = a0; a <= a1; ++a)
+      acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + wrapl(x + a, l)], acc);
   }
   const T *Ff = Ff0 + (long long)h * nf;
   for (int b = (DIM == 2 ? -G : 0); b <= (DIM == 2 ? G : 0); ++b)
 #pragma unroll 1
     for (int a = -G; a <= G; ++a) {
-      if (a == 0 && b == 0) continue;
+      if (!((nbm >> ((b + G) * (2 * G + 1) + (a + G))) & 1ull)) continue;
       const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
-      if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
       ParentStencil<DIM, T> st;
       parent_stencil_g<DIM, T, G>(st, Fl, l, px, py);
 #pragma unroll
@@ -1737,6 +1798,24 @@ __device__ __attribute__((noinline)) T transport_inner_g(const Inst<T> &In, int 
   return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
 }
 
+// Every population H of a leaf by transport_inner_g (f[H]), and population h
+// (a run-time index) by a chain of tests.
+template <int DIM, int SCHEME, typename T, int G, int H>
+__device__ __forceinline__ void inner_all(T *f, const Inst<T> &In, int l, uint32_t c, int x, int y, const T *Fl0,
+                                          const T *Ff0, unsigned long long nbm, WallTabs<T> wt) {
+  if constexpr (H < Vel<SCHEME>::Q) {
+    f[H] = transport_inner_g<DIM, SCHEME, T, G, H>(In, l, c, x, y, Fl0, Ff0, nbm, wt);
+    inner_all<DIM, SCHEME, T, G, H + 1>(f, In, l, c, x, y, Fl0, Ff0, nbm, wt);
+  }
+}
+template <int DIM, int SCHEME, typename T, int G, int H>
+__device__ __forceinline__ T inner_one(int h, const Inst<T> &In, int l, uint32_t c, int x, int y, const T *Fl0,
+                                       const T *Ff0, unsigned long long nbm, WallTabs<T> wt) {
+  if constexpr (H + 1 < Vel<SCHEME>::Q)
+    if (h != H) return inner_one<DIM, SCHEME, T, G, H + 1>(h, In, l, c, x, y, Fl0, Ff0, nbm, wt);
+  return transport_inner_g<DIM, SCHEME, T, G, H>(In, l, c, x, y, Fl0, Ff0, nbm, wt);
+}
+
 // One leaf by transport_inner_g, then the tape, the collision and the store.
 template <int DIM, int SCHEME, typename T, int G>
 __device__ __forceinline__ void leaf_update_inner_g(const Inst<T> &In, int l, uint32_t c,
@@ -1748,10 +1827,9 @@ __device__ __forceinline__ void leaf_update_inner_g(const Inst<T> &In, int l, ui
   coords<DIM>(l, c, x, y);
   const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
   const T *Ff0 = l < In.jmax ? Fs + (long long)Q * In.loff[l + 1] : Fs;
+  const unsigned long long nbm = l < In.jmax ? refined_within_g<DIM, G>(code + In.loff[l], l, x, y) : 0ull;
   T f[Q];
-#pragma unroll
-  for (int h = 0; h < Q; ++h)
-    f[h] = transport_inner_g<DIM, SCHEME, T, G>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
+  inner_all<DIM, SCHEME, T, G, 0>(f, In, l, c, x, y, Fs + ol, Ff0, nbm, wt);
   if (tape)
 #pragma unroll
     for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
@@ -1817,8 +1895,9 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
           fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
                                                        n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
         else
-          fl[h][lane] = transport_inner_g<DIM, SCHEME, T, MODE>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
-                                                                n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
+          fl[h][lane] = inner_one<DIM, SCHEME, T, MODE, 0>(
+              h, I[i], l, c, x, y, Fs + (long long)Q * sloff[l], n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs,
+              n > 0 ? refined_within_g<DIM, MODE>(cl, l, x, y) : 0ull, wt);
       } else {
         fl[h][lane] = transport_pop<DIM, SCHEME, T>(h, l, J, c, x, y, Fl, Ff, cl, Wt + ((long long)nn * Q + h) * WS,
                                                     Ct + ((long long)nn * Q + h) * CS, nbr);

@@ -231,10 +231,12 @@ struct Plan {
   std::vector<uint32_t> binfo; // [nblocks] instance | level << 8 | chunk << 13 of all-level passes
   std::vector<uint32_t> dinfo; // dense per-level passes: instance | chunk << 8, rows at dstart
   std::vector<uint32_t> wband; // wall bands of the transport (gamma = 1 with walls): instance | level << 8 | chunk << 13
+  std::vector<uint32_t> gtile; // gamma > 1: tiles of the ghost classification, instance | tile << 8, by level
+  std::vector<long long> gtile_start;  // [LVL_STRIDE + 1] first tile of each level in gtile
   std::vector<long long> dstart;  // [NDENSE][LVL_STRIDE] first entry of each (off, L) row in dinfo
   bool ghost16[LVL_STRIDE];       // level L's codes (and L+1's) are 16-byte aligned in every instance
   size_t off_F[2], off_code[2], off_lists[2], off_lvl[2], off_keep, off_refg, off_tnew, off_mark, off_act, off_sync, off_ne[2], off_bcnt, off_boff, off_W,
-      off_C, off_Wb, off_Cb, off_Nb, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, off_wband, bytes;
+      off_C, off_Wb, off_Cb, off_Nb, off_red, off_bad, off_cnt, off_inst, off_cb, off_cbp, off_dtab, off_binfo, off_dinfo, off_wband, off_gtile, bytes;
   int dtab_total(int off, int L) const { return dtab[((size_t)off * LVL_STRIDE + L) * (B + 1) + B]; }
   const uint32_t *dinfo_row(const uint32_t *dev, int off, int L) const {
     return dev + dstart[(size_t)off * LVL_STRIDE + L];
@@ -347,6 +349,19 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
         P.wband.push_back((uint32_t)i | ((uint32_t)l << 8) | ((uint32_t)k << 13));
     }
   }
+  // gamma > 1: tiles of GT_X x GT_Y cells (1D: GT_X * GT_Y) of every level above jmin
+  P.gtile.clear();
+  P.gtile_start.assign(LVL_STRIDE + 1, 0);
+  for (int l = 0; l < LVL_STRIDE; ++l) {
+    P.gtile_start[l] = (long long)P.gtile.size();
+    if (P.gamma == 1 || l <= P.jmin) continue;
+    const long long N = 1ll << l, tx = P.dim == 2 ? GT_X : GT_X * GT_Y, ty = P.dim == 2 ? GT_Y : 1;
+    const long long nt = ((N + tx - 1) / tx) * (P.dim == 2 ? (N + ty - 1) / ty : 1);
+    for (int i = 0; i < B; ++i)
+      if (l <= P.inst[i].jmax)
+        for (long long t = 0; t < nt; ++t) P.gtile.push_back((uint32_t)i | ((uint32_t)t << 8));
+  }
+  P.gtile_start[LVL_STRIDE] = (long long)P.gtile.size();
   for (int L = 0; L < LVL_STRIDE; ++L) {
     bool ok = L >= 4;
     for (int i = 0; i < B && ok; ++i)
@@ -386,6 +401,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
   P.off_binfo = take(sizeof(uint32_t) * P.binfo.size());
   P.off_dinfo = take(sizeof(uint32_t) * std::max<size_t>(1, P.dinfo.size()));
   P.off_wband = take(sizeof(uint32_t) * std::max<size_t>(1, P.wband.size()));
+  P.off_gtile = take(sizeof(uint32_t) * std::max<size_t>(1, P.gtile.size()));
   P.bytes = o + 256;  // slack for aligning the base pointer
 }
 
@@ -504,7 +520,7 @@ struct mrlbm_ctx {
   void *inst;               // Inst<T>[B]
   long long *cb;
   int *cbp, *dtab;
-  uint32_t *binfo, *dinfo, *wband;
+  uint32_t *binfo, *dinfo, *wband, *gtile;
   int cur;   // F[cur] holds the state
   int mcur;  // code/lists/lvl[mcur] describe the current mesh
   std::vector<char> has_state;
@@ -705,12 +721,12 @@ struct Engine {
     k_classify_tree<DIM, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->tnew, c->code[m], c->keep,
                                                               c->refg, c->act);
     const int lc = coarse_cap(c);
-    if (P.gamma > 1) {  // wider stencils: one plain pass per level, finest first
+    if (P.gamma > 1) {  // wider stencils: one tiled pass per level, finest first
       for (int l = P.maxJ; l > P.jmin; --l) {
-        const int nb = P.dtab_total(0, l);
+        const long long nb = P.gtile_start[l + 1] - P.gtile_start[l];
         if (nb)
-          k_classify_ghost_wide<DIM, T><<<nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m], P.dinfo_row(c->dinfo, 0, l),
-                                                                   l, c->act);
+          k_classify_ghost_tile<DIM, T><<<(unsigned)nb, BLK, 0, c->stream>>>(c->bt, I(c), c->code[m],
+                                                                          c->gtile + P.gtile_start[l], l, c->act);
       }
       compact(c, m, code_old, F);
       return;
@@ -1507,6 +1523,7 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   c->binfo = (uint32_t *)(b + P.off_binfo);
   c->dinfo = (uint32_t *)(b + P.off_dinfo);
   c->wband = (uint32_t *)(b + P.off_wband);
+  c->gtile = (uint32_t *)(b + P.off_gtile);
   c->cur = 0;
   c->mcur = 0;
   c->has_state.assign(P.B, 0);
@@ -1592,6 +1609,8 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
     e = hipMemcpy(c->dinfo, P.dinfo.data(), sizeof(uint32_t) * P.dinfo.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !P.wband.empty())
     e = hipMemcpy(c->wband, P.wband.data(), sizeof(uint32_t) * P.wband.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.gtile.empty())
+    e = hipMemcpy(c->gtile, P.gtile.data(), sizeof(uint32_t) * P.gtile.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->cnt, 0, 4 * sizeof(unsigned long long));
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(c->code[k], 0, P.ctotal);
   if (e == hipSuccess) e = hipMemset(c->keep, 0, P.ctotal);
