@@ -405,7 +405,8 @@ def scope_rows(args, only=None):
     for name, items, desc, prec in scope_row_workloads():
         if only is not None and name != only:
             continue
-        r, sim, _ = timed_run(items, prec, args.scope_steps, args.scope_warmup)
+        # (alone, the windows get the copy-kernel markers the profile summaries use)
+        r, sim, _ = timed_run(items, prec, args.scope_steps, args.scope_warmup, markers=only is not None)
         sim.close()
         out[name] = dict(workload=desc, value=r["value"], unit="leaf updates/s", ms_per_step=r["ms_per_step"],
                          mean_leaves_per_step=r["mean_leaves_per_step"],
