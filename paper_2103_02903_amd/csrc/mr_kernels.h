@@ -1616,13 +1616,14 @@ __device__ __forceinline__ bool near_wall(const Inst<T> &In, int l, int x, int y
 // details of the mirrored children), the tables of the leaf's wall case, and
 // the incoming values from beyond the walls. Fl0 / Ff0 point at population 0 of
 // levels l and l+1, cl at the codes of level l.
-template <int DIM, int SCHEME, typename T>
-__device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
-                                                      const T *__restrict__ Fl0, const T *__restrict__ Ff0,
-                                                      const uint8_t *__restrict__ cl, WallTabs<T> wt) {
+template <int DIM, int SCHEME, typename T, int G, int H>
+__device__ __attribute__((noinline)) T transport_wall_gh(const Inst<T> &In, int l, uint32_t c, int x, int y,
+                                                         const T *__restrict__ Fl0, const T *__restrict__ Ff0,
+                                                         const uint8_t *__restrict__ cl, WallTabs<T> wt) {
   using V = Vel<SCHEME>;
-  constexpr int Q = V::Q;
-  const int ex = V::ex(h), ey = V::ey(h), J = In.jmax, n = J - l, N = 1 << l;
+  constexpr int Q = V::Q, h = H;
+  constexpr int ex = V::ex(H), ey = V::ey(H);
+  const int J = In.jmax, n = J - l, N = 1 << l;
   const bool wx = In.walls & 1, wy = DIM == 2 && (In.walls & 2);
   const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
   const T *Fl = Fl0 + (long long)h * nl;
@@ -1637,23 +1638,28 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
   }
   const int cx = wx ? (x == 0 ? 1 : (x == N - 1 ? 2 : 0)) : 0;
   const int cy = wy ? (y == 0 ? 1 : (y == N - 1 ? 2 : 0)) : 0;
-  const int wc = cx + 3 * cy, nn = n - 1, g = In.gamma, R = 2 * g, WW = 2 * R + 1, CW = 2 * R + 2;
-  const int WSg = DIM == 2 ? WW * WW : WW, CSg = DIM == 2 ? CW * CW : CW;
+  constexpr int g = G, R = 2 * g, WW = 2 * R + 1, CW = 2 * R + 2;
+  constexpr int WSg = DIM == 2 ? WW * WW : WW, CSg = DIM == 2 ? CW * CW : CW;
+  const int wc = cx + 3 * cy, nn = n - 1;
   const T *W = wt.W + (((long long)nn * 9 + wc) * Q + h) * WSg;
   const T *Cw = wt.C + (((long long)nn * 9 + wc) * Q + h) * CSg;
   T acc = T(0);
   // an axis velocity's weights vanish off its own row (column): the sums over
   // the other rows of the leaf's cells of a unit impulse's reconstruction
-  const int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
-  const int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+  constexpr int b0 = DIM == 2 && ey != 0 ? -R : 0, b1 = DIM == 2 && ey != 0 ? R : 0;
+  constexpr int a0 = ex != 0 ? -R : 0, a1 = ex != 0 ? R : 0;
+  // (the rows unrolled for gamma = 1 only: the wider boxes would not fit the registers)
+#pragma unroll(G == 1 ? 5 : 1)
   for (int b = b0; b <= b1; ++b) {
     const long long row = DIM == 2 ? ((long long)axl(y + b, l, wy) << l) : 0;
+#pragma unroll
     for (int a = a0; a <= a1; ++a)
       acc = fma(W[DIM == 2 ? (b + R) * WW + a + R : a + R], Fl[row + axl(x + a, l, wx)], acc);
   }
   // neighbours refined one level further, mirrored beyond a wall
   const T *Ff = Ff0 + (long long)h * nf;
   for (int b = (DIM == 2 ? -g : 0); b <= (DIM == 2 ? g : 0); ++b)
+#pragma unroll 1
     for (int a = -g; a <= g; ++a) {
       if (a == 0 && b == 0) continue;
       const int vx = x + a, vy = y + b;
@@ -1661,7 +1667,7 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
       const int px = axl(vx, l, wx), py = DIM == 2 ? axl(vy, l, wy) : 0;
       if (cl[cidx<DIM>(l, px, py)] != C_INTERNAL) continue;
       ParentStencil<DIM, T> st;
-      st.load(Fl, l, px, py, In.walls, In.gamma);
+      st.load(Fl, l, px, py, In.walls, G);
       for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
         for (int dx = 0; dx < 2; ++dx) {
           const int rx = mx ? 1 - dx : dx, ry = my ? 1 - dy : dy;  // the real child the virtual one mirrors
@@ -1678,9 +1684,24 @@ __device__ __attribute__((noinline)) T transport_wall(const Inst<T> &In, int h, 
   return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
 }
 
+// transport_wall_gh for the instance's gamma and a run-time population h.
+template <int DIM, int SCHEME, typename T, int G, int H>
+__device__ __forceinline__ T transport_wall_h(int h, const Inst<T> &In, int l, uint32_t c, int x, int y, const T *Fl0,
+                                              const T *Ff0, const uint8_t *cl, WallTabs<T> wt) {
+  if constexpr (H + 1 < Vel<SCHEME>::Q)
+    if (h != H) return transport_wall_h<DIM, SCHEME, T, G, H + 1>(h, In, l, c, x, y, Fl0, Ff0, cl, wt);
+  return transport_wall_gh<DIM, SCHEME, T, G, H>(In, l, c, x, y, Fl0, Ff0, cl, wt);
+}
+template <int DIM, int SCHEME, typename T, int G>
+__device__ __forceinline__ T transport_wall(const Inst<T> &In, int h, int l, uint32_t c, int x, int y,
+                                            const T *__restrict__ Fl0, const T *__restrict__ Ff0,
+                                            const uint8_t *__restrict__ cl, WallTabs<T> wt) {
+  return transport_wall_h<DIM, SCHEME, T, G, 0>(h, In, l, c, x, y, Fl0, Ff0, cl, wt);
+}
+
 // One leaf of an instance with walls, every population by transport_wall, then
 // the tape, the collision and the store as in leaf_update.
-template <int DIM, int SCHEME, typename T>
+template <int DIM, int SCHEME, typename T, int G>
 __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, int l, uint32_t c,
                                                            const T *__restrict__ Fs, T *__restrict__ Fo,
                                                            const uint8_t *__restrict__ code, WallTabs<T> wt,
@@ -1693,7 +1714,7 @@ __device__ __attribute__((noinline)) void leaf_update_wall(const Inst<T> &In, in
   T f[Q];
 #pragma unroll
   for (int h = 0; h < Q; ++h)
-    f[h] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
+    f[h] = transport_wall<DIM, SCHEME, T, G>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
   if (tape)
 #pragma unroll
     for (int h = 0; h < Q; ++h) tape[ol + h * nl + c] = f[h];
@@ -1892,7 +1913,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
       const int nn = n > 0 ? n - 1 : 0;
       if constexpr (MODE >= 2) {
         if (wall)
-          fl[h][lane] = transport_wall<DIM, SCHEME, T>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
+          fl[h][lane] = transport_wall<DIM, SCHEME, T, MODE>(I[i], h, l, c, x, y, Fs + (long long)Q * sloff[l],
                                                        n > 0 ? Fs + (long long)Q * sloff[l + 1] : Fs, cl, wt);
         else
           fl[h][lane] = inner_one<DIM, SCHEME, T, MODE, 0>(
@@ -2193,7 +2214,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(MODE >
     if (MODE == 1 && wall) continue;  // k_transport_wall_band takes the leaves near a wall
     if constexpr (MODE >= 2) {
       if (wall)
-        leaf_update_wall<DIM, SCHEME, T>(In, l, c, Fs, Fo, code, wt, tape);
+        leaf_update_wall<DIM, SCHEME, T, MODE>(In, l, c, Fs, Fo, code, wt, tape);
       else
         leaf_update_inner_g<DIM, SCHEME, T, MODE>(In, l, c, Fs, Fo, code, wt, tape);
     } else if (one_level)
@@ -2247,7 +2268,7 @@ __global__ void __launch_bounds__(64 * Vel<SCHEME>::Q)
   const long long ol = (long long)Q * In.loff[l], nl = ncells_d(DIM, l);
   if (leaf) {
     const T *Ff0 = l < In.jmax ? Fs + (long long)Q * In.loff[l + 1] : Fs;
-    fl[h][lane] = transport_wall<DIM, SCHEME, T>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
+    fl[h][lane] = transport_wall<DIM, SCHEME, T, 1>(In, h, l, c, x, y, Fs + ol, Ff0, code + In.loff[l], wt);
     if (tape) tape[ol + h * nl + c] = fl[h][lane];
   }
   __syncthreads();
