@@ -9,7 +9,8 @@ arithmetic.
 The C source ``mr_oracle.c`` follows the paper (arXiv 2103.02903) operation by
 operation on dense per-level arrays; this module only marshals numpy arrays.
 
-Flat layouts (all levels jmin..J concatenated, cell index x + N_l * y):
+Flat layouts (all levels jmin..J concatenated, cell index x + N_l * y in 2D,
+x + N_l * (y + N_l * z) in 3D):
   tree   uint8   [level][cell]       1 = cell in the complete tree
   values float64 [level][h][cell]
 """
@@ -26,7 +27,8 @@ _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liborc.so")
 _SRC = os.path.join(_HERE, "mr_oracle.c")
 
-SCHEMES = {"D1Q2": (1, 1, 2), "D1Q3": (2, 1, 3), "D2Q9": (3, 2, 9), "D2Q4E": (4, 2, 16)}  # id, dim, q
+SCHEMES = {"D1Q2": (1, 1, 2), "D1Q3": (2, 1, 3), "D2Q9": (3, 2, 9), "D2Q4E": (4, 2, 16),
+           "D3Q6": (5, 3, 6)}  # id, dim, q
 
 
 def build(force: bool = True) -> str:
@@ -47,7 +49,8 @@ class _Params(ctypes.Structure):
                 ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double),
                 ("s", ctypes.c_double * 16), ("bc", ctypes.c_int * 4), ("bc_eval", ctypes.c_int),
-                ("gamma", ctypes.c_int), ("metric", ctypes.c_int), ("pad3_", ctypes.c_int)]
+                ("gamma", ctypes.c_int), ("metric", ctypes.c_int), ("pad3_", ctypes.c_int),
+                ("vel", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -83,6 +86,8 @@ def lib():
         L.orc_equilibrium_jacobian.argtypes = [P, dp, dp]; L.orc_equilibrium_jacobian.restype = None
         L.orc_predict.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_predict.restype = ctypes.c_double
+        L.orc_predict3.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_predict3.restype = ctypes.c_double
         L.orc_collide_cell.argtypes = [P, dp]; L.orc_collide_cell.restype = None
         L.orc_moment_matrix.argtypes = [P, dp]; L.orc_moment_matrix.restype = None
         L.orc_equilibrium.argtypes = [P, dp, dp]; L.orc_equilibrium.restype = None
@@ -114,7 +119,8 @@ class Oracle:
                          float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)),
                          float(cfg["eps"]), float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s),
                          (ctypes.c_int * 4)(*bc), int(cfg.get("bc_eval", 0)), int(cfg.get("gamma", 1)),
-                         {"linf": 0, "l2": 1}[cfg.get("metric", "linf")], 0)
+                         {"linf": 0, "l2": 1}[cfg.get("metric", "linf")], 0,
+                         (ctypes.c_double * 3)(*[float(v) for v in cfg.get("velocity", (0.0, 0.0, 0.0))]))
         self.dim, self.q, self.jmin, self.jmax = dim, q, int(cfg["jmin"]), int(cfg["jmax"])
         self.L = lib()
         self.total = int(self.L.orc_total_cells(ctypes.byref(self.p)))
@@ -127,14 +133,15 @@ class Oracle:
         return int(self.L.orc_level_offset(ctypes.byref(self.p), l))
 
     def tree_level(self, tree: np.ndarray, l: int) -> np.ndarray:
+        """Level l of a tree as an array indexed [y, x] (2D) or [z, y, x] (3D)."""
         o = self.level_offset(l)
         t = tree[o:o + self.ncells(l)]
-        return t.reshape((1 << l, 1 << l)) if self.dim == 2 else t
+        return t.reshape((1 << l,) * self.dim) if self.dim > 1 else t
 
     def values_level(self, values: np.ndarray, l: int) -> np.ndarray:
         o = self.q * self.level_offset(l)
         v = values[o:o + self.q * self.ncells(l)].reshape(self.q, self.ncells(l))
-        return v.reshape(self.q, 1 << l, 1 << l) if self.dim == 2 else v
+        return v.reshape((self.q,) + (1 << l,) * self.dim) if self.dim > 1 else v
 
     def new_state(self):
         return np.zeros(self.total, np.uint8), np.zeros(self.q * self.total, np.float64)
@@ -207,9 +214,9 @@ class Oracle:
         self.L.orc_collide_cell(ctypes.byref(self.p), _ptr(f))
         return f
 
-    def predict(self, parent_level: np.ndarray, l: int, cx: int, cy: int = 0) -> float:
+    def predict(self, parent_level: np.ndarray, l: int, cx: int, cy: int = 0, cz: int = 0) -> float:
         a = np.ascontiguousarray(parent_level, dtype=np.float64).ravel()
-        return float(self.L.orc_predict(ctypes.byref(self.p), _ptr(a), l, cx, cy))
+        return float(self.L.orc_predict3(ctypes.byref(self.p), _ptr(a), l, cx, cy, cz))
 
     def uniform_step(self, fJ: np.ndarray, nsteps: int = 1):
         for _ in range(nsteps):
@@ -233,9 +240,10 @@ class Oracle:
         return meq
 
     def velocities(self):
-        eta = np.zeros(2 * self.q, np.int32)
+        """Logical velocities, shape (q, 2) for d <= 2 and (q, 3) in 3D."""
+        eta = np.zeros(3 * self.q, np.int32)
         self.L.orc_velocities(ctypes.byref(self.p), _ptr(eta))
-        return eta.reshape(self.q, 2)
+        return eta.reshape(self.q, 3)[:, :max(2, self.dim)].copy()
 
     def leaf_counts(self, tree):
         c = np.zeros(self.jmax + 1, np.int64)
@@ -255,6 +263,8 @@ class Oracle:
         tc = self.tree_level(tree, l + 1).astype(bool)
         if self.dim == 1:
             return t & ~tc[0::2]
+        if self.dim == 3:
+            return t & ~tc[0::2, 0::2, 0::2]
         return t & ~tc[0::2, 0::2]
 
     def finest(self, tree, values):

@@ -17,6 +17,10 @@
  *  - 2D prediction: the cross term enters with the tensor-product sign
  *    +(-1)^{dx+dy} Q_xy (Appendix 2 builds the 2D operator as a Kronecker
  *    product of the 1D one); only this sign is exact on the monomial x*y.
+ *    3D likewise: every pair term with +(-1)^{da+db} and the triple term with
+ *    +(-1)^{dx+dy+dz} (the Kronecker product of three 1D operators; the
+ *    printed minus on the pair terms is not exact on x*y).
+ *  - 3D runs periodic boundaries only (the paper's 3D test has no wall).
  *  - The thresholded set is closed under ancestors (parent group of every kept
  *    group) before the enlargement H_eps, so that H_eps acts on a tree.
  *  - Neighbour addition shifts by eta^h in cells of the kept cell's own level.
@@ -60,7 +64,8 @@ static int side(int l) { return 1 << l; }
 static int64_t ncells(const orc_params *P, int l) { return (int64_t)1 << (P->dim * l); }
 static int wrapi(int i, int n) { i %= n; return i < 0 ? i + n : i; }
 
-/* Walls: axis a (0 = x, 1 = y) has walls when either of its sides is not periodic. */
+/* Walls: axis a (0 = x, 1 = y) has walls when either of its sides is not
+ * periodic (3D: periodic only, refused by bad_bc). */
 static int wall_axis(const orc_params *P, int a) { return P->bc[2 * a] != 0 || P->bc[2 * a + 1] != 0; }
 static int has_walls(const orc_params *P) { return wall_axis(P, 0) || (P->dim == 2 && wall_axis(P, 1)); }
 /* Index i (|overflow| < n) along axis a for the MR operators: periodic wrap, or
@@ -92,39 +97,42 @@ static uint8_t *tree_at(const orc_params *P, const uint8_t *tree, int l) {
 static double *val_at(const orc_params *P, const double *v, int l, int h) {
   return (double *)v + (int64_t)P->q * orc_level_offset(P, l) + (int64_t)h * ncells(P, l);
 }
-static int64_t cell_index(const orc_params *P, int l, int x, int y) {
-  return P->dim == 1 ? x : (int64_t)x + (int64_t)side(l) * y;
+static int64_t cell_index(const orc_params *P, int l, int x, int y, int z) {
+  const int64_t n = side(l);
+  return P->dim == 1 ? x : P->dim == 2 ? (int64_t)x + n * y : (int64_t)x + n * ((int64_t)y + n * z);
 }
-static int64_t cell_index_wrapped(const orc_params *P, int l, int x, int y) {
-  int n = side(l);
-  return P->dim == 1 ? wrapi(x, n) : (int64_t)wrapi(x, n) + (int64_t)n * wrapi(y, n);
+static int64_t cell_index_wrapped(const orc_params *P, int l, int x, int y, int z) {
+  const int n = side(l);
+  return cell_index(P, l, wrapi(x, n), P->dim >= 2 ? wrapi(y, n) : 0, P->dim == 3 ? wrapi(z, n) : 0);
 }
-/* Cell (x, y) of level l as the MR operators read it (wrap or reflection). */
+/* Cell (x, y) of level l (d <= 2) as the MR operators read it (wrap or reflection). */
 static int64_t cell_index_mr(const orc_params *P, int l, int x, int y) {
   int n = side(l);
   return P->dim == 1 ? mr_axis(P, 0, x, n) : (int64_t)mr_axis(P, 0, x, n) + (int64_t)n * mr_axis(P, 1, y, n);
 }
-/* Cell (x, y) of level l for the set operations: wrapped on periodic axes, -1
- * beyond a wall. */
-static int64_t cell_index_set(const orc_params *P, int l, int x, int y) {
-  return beyond_wall(P, l, x, y) >= 0 ? -1 : cell_index_wrapped(P, l, x, y);
+/* Cell (x, y, z) of level l for the set operations: wrapped on periodic axes,
+ * -1 beyond a wall. */
+static int64_t cell_index_set(const orc_params *P, int l, int x, int y, int z) {
+  return beyond_wall(P, l, x, y) >= 0 ? -1 : cell_index_wrapped(P, l, x, y, z);
 }
-static void cell_coords(const orc_params *P, int l, int64_t c, int *x, int *y) {
-  if (P->dim == 1) { *x = (int)c; *y = 0; }
-  else { *x = (int)(c % side(l)); *y = (int)(c / side(l)); }
+static void cell_coords(const orc_params *P, int l, int64_t c, int *x, int *y, int *z) {
+  const int64_t n = side(l);
+  *x = (int)(c % n);
+  *y = P->dim >= 2 ? (int)((c / n) % n) : 0;
+  *z = P->dim == 3 ? (int)(c / (n * n)) : 0;
 }
 static int nchildren(const orc_params *P) { return 1 << P->dim; }
-/* Child sigma of (x, y): sigma bit 0 is the x offset, bit 1 the y offset. */
-static int64_t child_index(const orc_params *P, int l, int x, int y, int sigma) {
-  int cx = 2 * x + (sigma & 1), cy = 2 * y + ((sigma >> 1) & 1);
-  return cell_index(P, l + 1, cx, cy);
+/* Child sigma of (x, y, z): sigma bit 0 is the x offset, bit 1 the y offset,
+ * bit 2 the z offset. */
+static int64_t child_index(const orc_params *P, int l, int x, int y, int z, int sigma) {
+  return cell_index(P, l + 1, 2 * x + (sigma & 1), 2 * y + ((sigma >> 1) & 1), 2 * z + ((sigma >> 2) & 1));
 }
 static int is_leaf(const orc_params *P, const uint8_t *tree, int l, int64_t c) {
   if (!tree_at(P, tree, l)[c]) return 0;
   if (l == P->jmax) return 1;
-  int x, y;
-  cell_coords(P, l, c, &x, &y);
-  return !tree_at(P, tree, l + 1)[child_index(P, l, x, y, 0)];
+  int x, y, z;
+  cell_coords(P, l, c, &x, &y, &z);
+  return !tree_at(P, tree, l + 1)[child_index(P, l, x, y, z, 0)];
 }
 static int is_internal(const orc_params *P, const uint8_t *tree, int l, int64_t c) {
   return tree_at(P, tree, l)[c] && !is_leaf(P, tree, l, c);
@@ -140,12 +148,20 @@ void orc_velocities(const orc_params *P, int *eta) {
                                  {1, 1},  {-1, 1}, {-1, -1}, {1, -1}};
   /* D2Q4: lambda (cos(k pi / 2), sin(k pi / 2)), k = 0..3, for every variable */
   static const int d2q4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  if (P->scheme == 5) {
+    /* D3Q6: lambda cos(pi h) along x (h = 0, 1), y (h = 2, 3), z (h = 4, 5) */
+    for (int h = 0; h < 6; ++h) {
+      eta[3 * h] = eta[3 * h + 1] = eta[3 * h + 2] = 0;
+      eta[3 * h + h / 2] = (h & 1) ? -1 : 1;
+    }
+    return;
+  }
   if (P->scheme == 4) {
-    for (int h = 0; h < P->q; ++h) { eta[2 * h] = d2q4[h & 3][0]; eta[2 * h + 1] = d2q4[h & 3][1]; }
+    for (int h = 0; h < P->q; ++h) { eta[3 * h] = d2q4[h & 3][0]; eta[3 * h + 1] = d2q4[h & 3][1]; eta[3 * h + 2] = 0; }
     return;
   }
   const int(*t)[2] = P->scheme == 1 ? d1q2 : P->scheme == 2 ? d1q3 : d2q9;
-  for (int h = 0; h < P->q; ++h) { eta[2 * h] = t[h][0]; eta[2 * h + 1] = t[h][1]; }
+  for (int h = 0; h < P->q; ++h) { eta[3 * h] = t[h][0]; eta[3 * h + 1] = t[h][1]; eta[3 * h + 2] = 0; }
 }
 
 void orc_moment_matrix(const orc_params *P, double *M) {
@@ -156,6 +172,11 @@ void orc_moment_matrix(const orc_params *P, double *M) {
     memcpy(M, m, sizeof m);
   } else if (P->scheme == 2) {
     const double m[3][3] = {{1, 1, 1}, {0, L, -L}, {0, L2, L2}};
+    memcpy(M, m, sizeof m);
+  } else if (P->scheme == 5) {
+    /* section "Three dimensional advection equation": the D3Q6 matrix */
+    const double m[6][6] = {{1, 1, 1, 1, 1, 1},       {L, -L, 0, 0, 0, 0},     {0, 0, L, -L, 0, 0},
+                            {0, 0, 0, 0, L, -L},      {L2, L2, -L2, -L2, 0, 0}, {L2, L2, 0, 0, -L2, -L2}};
     memcpy(M, m, sizeof m);
   } else if (P->scheme == 4) {
     /* section "Systems of hyperbolic conservation laws": the same D2Q4 matrix
@@ -217,6 +238,14 @@ void orc_equilibrium(const orc_params *P, const double *m, double *meq) {
     meq[0] = m[0];
     meq[1] = 0.5 * m[0] * m[0];
     meq[2] = P->eq_param * L * L * m[0];
+  } else if (P->scheme == 5) {
+    /* D3Q6 advection: m_eq = (u, V_x u, V_y u, V_z u, 0, 0) */
+    meq[0] = m[0];
+    meq[1] = P->vel[0] * m[0];
+    meq[2] = P->vel[1] * m[0];
+    meq[3] = P->vel[2] * m[0];
+    meq[4] = 0.0;
+    meq[5] = 0.0;
   } else if (P->scheme == 4) {
     /* Euler system: conserved u = (rho, rho u, rho v, E), pressure from
      * E = p / (gamma - 1) + rho (u^2 + v^2) / 2; variable i relaxes its first
@@ -283,10 +312,12 @@ static const double CG[4][3] = {{0, 0, 0}, {-0.125, 0, 0}, {-22.0 / 128, 3.0 / 1
                                 {-201.0 / 1024, 11.0 / 256, -5.0 / 1024}};
 static int gam(const orc_params *P) { return P->gamma > 0 ? P->gamma : 1; }
 
-/* Prediction of child (cx, cy) at level l from the dense data Fp of level l-1:
- * 1D:  f_parent + (-1)^dx * c1 * (f_{p+1} - f_{p-1});
- * 2D:  tensor product, f + (-1)^dx Qx + (-1)^dy Qy + (-1)^(dx+dy) Qxy. */
-double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy) {
+/* Prediction of child (cx, cy, cz) at level l from the dense data Fp of level l-1:
+ * 1D:  f_parent + (-1)^dx * Q_x,  Q_x = sum_alpha c_alpha (f_{p+alpha} - f_{p-alpha});
+ * 2D:  tensor product, ((f + (-1)^dx Qx) + (-1)^dy Qy) + (-1)^(dx+dy) Qxy;
+ * 3D:  the same with the axis terms Qx, Qy, Qz, the pair terms Qxy, Qxz, Qyz and
+ *      the triple term Qxyz, added in that order. */
+static double predict_at(const orc_params *P, const double *Fp, int l, int cx, int cy, int cz) {
   const int n = side(l - 1), g = gam(P);
   const double *c = CG[g];
   const int px = cx >> 1;
@@ -299,6 +330,59 @@ double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy)
   }
   const int py = cy >> 1;
   const double sy = (cy & 1) ? -1.0 : 1.0;
+  if (P->dim == 3) {
+    const int pz = cz >> 1;
+    const double sz = (cz & 1) ? -1.0 : 1.0;
+#define A3(a, b, t) Fp[(int64_t)wrapi(px + (a), n) + (int64_t)n * ((int64_t)wrapi(py + (b), n) + (int64_t)n * wrapi(pz + (t), n))]
+    /* axis terms, alpha ascending */
+    double Qx = c[0] * (A3(1, 0, 0) - A3(-1, 0, 0));
+    double Qy = c[0] * (A3(0, 1, 0) - A3(0, -1, 0));
+    double Qz = c[0] * (A3(0, 0, 1) - A3(0, 0, -1));
+    for (int a = 2; a <= g; ++a) {
+      Qx = Qx + c[a - 1] * (A3(a, 0, 0) - A3(-a, 0, 0));
+      Qy = Qy + c[a - 1] * (A3(0, a, 0) - A3(0, -a, 0));
+      Qz = Qz + c[a - 1] * (A3(0, 0, a) - A3(0, 0, -a));
+    }
+    /* pair terms in the plane of axes (u, v): the 2D cross term of that plane,
+     * beta (v) outer, alpha (u) inner from (1, 1) */
+#define PAIR(a, b, U) \
+  ((c[(a) - 1] * c[(b) - 1]) * (((U((a), (b)) - U(-(a), (b))) - U((a), -(b))) + U(-(a), -(b))))
+#define XY(a, b) A3(a, b, 0)
+#define XZ(a, b) A3(a, 0, b)
+#define YZ(a, b) A3(0, a, b)
+    double Qxy = 0.0, Qxz = 0.0, Qyz = 0.0;
+    for (int b = 1; b <= g; ++b)
+      for (int a = 1; a <= g; ++a) {
+        if (a == 1 && b == 1) {
+          Qxy = PAIR(1, 1, XY);
+          Qxz = PAIR(1, 1, XZ);
+          Qyz = PAIR(1, 1, YZ);
+        } else {
+          Qxy = Qxy + PAIR(a, b, XY);
+          Qxz = Qxz + PAIR(a, b, XZ);
+          Qyz = Qyz + PAIR(a, b, YZ);
+        }
+      }
+    /* triple term: tau (z) outer, beta (y), alpha (x) inner, from (1, 1, 1);
+     * the eight values with the signs of the product of the three offsets */
+    double Qxyz = 0.0;
+    for (int t = 1; t <= g; ++t)
+      for (int b = 1; b <= g; ++b)
+        for (int a = 1; a <= g; ++a) {
+          const double v = (((((((A3(a, b, t) - A3(-a, b, t)) - A3(a, -b, t)) - A3(a, b, -t)) + A3(-a, -b, t)) +
+                              A3(-a, b, -t)) + A3(a, -b, -t)) - A3(-a, -b, -t));
+          const double term = ((c[a - 1] * c[b - 1]) * c[t - 1]) * v;
+          Qxyz = (a == 1 && b == 1 && t == 1) ? term : Qxyz + term;
+        }
+    const double f0 = A3(0, 0, 0);
+#undef XY
+#undef XZ
+#undef YZ
+#undef PAIR
+#undef A3
+    return ((((((f0 + sx * Qx) + sy * Qy) + sz * Qz) + (sx * sy) * Qxy) + (sx * sz) * Qxz) +
+            (sy * sz) * Qyz) + ((sx * sy) * sz) * Qxyz;
+  }
 #define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
   double Qx = c[0] * (AT(px + 1, py) - AT(px - 1, py));
   double Qy = c[0] * (AT(px, py + 1) - AT(px, py - 1));
@@ -319,10 +403,22 @@ double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy)
 #undef AT
 }
 
-/* Projection: average of the 2^d children of (px, py), children read from the
- * dense data Fc of level l+1. */
-static double project(const orc_params *P, const double *Fc, int l, int px, int py) {
+double orc_predict(const orc_params *P, const double *Fp, int l, int cx, int cy) {
+  return predict_at(P, Fp, l, cx, cy, 0);
+}
+double orc_predict3(const orc_params *P, const double *Fp, int l, int cx, int cy, int cz) {
+  return predict_at(P, Fp, l, cx, cy, cz);
+}
+
+/* Projection: average of the 2^d children of (px, py, pz), children read from
+ * the dense data Fc of level l+1 and summed in the order of sigma. */
+static double project(const orc_params *P, const double *Fc, int l, int px, int py, int pz) {
   if (P->dim == 1) return 0.5 * (Fc[2 * px] + Fc[2 * px + 1]);
+  if (P->dim == 3) {
+    double acc = Fc[child_index(P, l, px, py, pz, 0)];
+    for (int sigma = 1; sigma < 8; ++sigma) acc = acc + Fc[child_index(P, l, px, py, pz, sigma)];
+    return 0.125 * acc;
+  }
   const int64_t n = side(l + 1);
   const double a00 = Fc[2 * px + n * (2 * py)];
   const double a10 = Fc[2 * px + 1 + n * (2 * py)];
@@ -337,10 +433,10 @@ int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values) {
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_internal(P, tree, l, c)) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
       for (int h = 0; h < P->q; ++h)
-        val_at(P, values, l, h)[c] = project(P, val_at(P, values, l + 1, h), l, x, y);
+        val_at(P, values, l, h)[c] = project(P, val_at(P, values, l + 1, h), l, x, y, z);
     }
   }
   /* Downward: cells outside the tree receive the zero-detail prediction. */
@@ -349,10 +445,10 @@ int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values) {
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (t[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
       for (int h = 0; h < P->q; ++h)
-        val_at(P, values, l, h)[c] = orc_predict(P, val_at(P, values, l - 1, h), l, x, y);
+        val_at(P, values, l, h)[c] = predict_at(P, val_at(P, values, l - 1, h), l, x, y, z);
     }
   }
   return 0;
@@ -369,16 +465,16 @@ int orc_details(const orc_params *P, const uint8_t *tree, const double *values, 
     double *Dp = D + orc_level_offset(P, l - 1);
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
-      int px, py;
-      cell_coords(P, l - 1, p, &px, &py);
-      if (!tp[p] || !tc[child_index(P, l - 1, px, py, 0)]) continue;
+      int px, py, pz;
+      cell_coords(P, l - 1, p, &px, &py, &pz);
+      if (!tp[p] || !tc[child_index(P, l - 1, px, py, pz, 0)]) continue;
       double dmax = 0.0;
       for (int h = 0; h < P->q; ++h) {
         const double *Fc = val_at(P, values, l, h), *Fp = val_at(P, values, l - 1, h);
         double s2 = 0.0;
         for (int sigma = 0; sigma < nchildren(P); ++sigma) {
-          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
-          const double d = Fc[cell_index(P, l, cx, cy)] - orc_predict(P, Fp, l, cx, cy);
+          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1), cz = 2 * pz + ((sigma >> 2) & 1);
+          const double d = Fc[cell_index(P, l, cx, cy, cz)] - predict_at(P, Fp, l, cx, cy, cz);
           if (P->metric) s2 = s2 + d * d;
           else if (fabs(d) > dmax) dmax = fabs(d);
         }
@@ -397,9 +493,9 @@ int orc_details(const orc_params *P, const uint8_t *tree, const double *values, 
  *      adaptive mesh", eq. Thresholding, eq. AdditionNeigh, refinement rule,
  *      grading definition) ---- */
 
-static void mark_group(const orc_params *P, uint8_t *tl, int l, int gx, int gy) {
-  /* all children at level l of the cell (gx, gy) of level l-1 */
-  for (int sigma = 0; sigma < nchildren(P); ++sigma) tl[child_index(P, l - 1, gx, gy, sigma)] = 1;
+static void mark_group(const orc_params *P, uint8_t *tl, int l, int gx, int gy, int gz) {
+  /* all children at level l of the cell (gx, gy, gz) of level l-1 */
+  for (int sigma = 0; sigma < nchildren(P); ++sigma) tl[child_index(P, l - 1, gx, gy, gz, sigma)] = 1;
 }
 
 /* Thresholds eps_l = 2^{d(l-J)} eps and 2^{mu_bar + d} eps_l, indexed by level. */
@@ -428,7 +524,7 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
                           const double *ref_lv, uint8_t *tnew) {
   const int J = P->jmax, jmin = P->jmin, d = P->dim;
   const int64_t total = orc_total_cells(P);
-  int eta[2 * MAXQ];
+  int eta[3 * MAXQ];
   orc_velocities(P, eta);
   uint8_t *keep = calloc((size_t)total, 1);
   if (!keep) return -1;
@@ -443,9 +539,9 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
     uint8_t *k = tree_at(P, keep, l);
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!t[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      if (Dp[cell_index(P, l - 1, x >> 1, y >> 1)] >= eps_l) k[c] = 1;
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      if (Dp[cell_index(P, l - 1, x >> 1, y >> 1, z >> 1)] >= eps_l) k[c] = 1;
     }
   }
   /* Ancestor closure: a kept group keeps the group of its parent. */
@@ -454,9 +550,9 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
     uint8_t *kp = tree_at(P, keep, l - 1);
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!k[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      mark_group(P, kp, l - 1, x >> 2, y >> 2);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      mark_group(P, kp, l - 1, x >> 2, y >> 2, z >> 2);
     }
   }
   /* H_eps: neighbours along every velocity, and children of groups whose metric
@@ -468,16 +564,16 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
     const double refine_thr = ref_lv[l];
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!k[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
       tn[c] = 1;
       for (int h = 0; h < P->q; ++h) {
-        const int64_t nb = cell_index_set(P, l, x - eta[2 * h], y - eta[2 * h + 1]);
+        const int64_t nb = cell_index_set(P, l, x - eta[3 * h], y - eta[3 * h + 1], z - eta[3 * h + 2]);
         if (nb >= 0) tn[nb] = 1;
       }
       if (l > jmin && l < J) {
-        const double Dg = D[orc_level_offset(P, l - 1) + cell_index(P, l - 1, x >> 1, y >> 1)];
-        if (Dg >= refine_thr) mark_group(P, tree_at(P, tnew, l + 1), l + 1, x, y);
+        const double Dg = D[orc_level_offset(P, l - 1) + cell_index(P, l - 1, x >> 1, y >> 1, z >> 1)];
+        if (Dg >= refine_thr) mark_group(P, tree_at(P, tnew, l + 1), l + 1, x, y, z);
       }
     }
   }
@@ -486,20 +582,22 @@ static int adapt_tree_thr(const orc_params *P, const uint8_t *told, const double
     uint8_t *tn = tree_at(P, tnew, l), *tp = tree_at(P, tnew, l - 1);
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!tn[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      mark_group(P, tn, l, x >> 1, y >> 1);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      mark_group(P, tn, l, x >> 1, y >> 1, z >> 1);
     }
+    const int g = gam(P), gy = d >= 2 ? g : 0, gz = d == 3 ? g : 0;
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!tn[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      const int px = x >> 1, py = y >> 1, g = gam(P);
-      for (int ay = (d == 2 ? -g : 0); ay <= (d == 2 ? g : 0); ++ay)
-        for (int ax = -g; ax <= g; ++ax) {
-          const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
-          if (nb >= 0) tp[nb] = 1;
-        }
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      const int px = x >> 1, py = y >> 1, pz = z >> 1;
+      for (int az = -gz; az <= gz; ++az)
+        for (int ay = -gy; ay <= gy; ++ay)
+          for (int ax = -g; ax <= g; ++ax) {
+            const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay, pz + az);
+            if (nb >= 0) tp[nb] = 1;
+          }
     }
   }
   memset(tree_at(P, tnew, jmin), 1, (size_t)ncells(P, jmin));
@@ -527,18 +625,20 @@ int orc_transfer(const orc_params *P, const uint8_t *told, const double *vold, c
 /* Index of the velocity opposite to h (eta^{h+} = -eta^h). */
 static int opposite(const orc_params *P, const int *eta, int h) {
   for (int k = 0; k < P->q; ++k)
-    if (eta[2 * k] == -eta[2 * h] && eta[2 * k + 1] == -eta[2 * h + 1]) return k;
+    if (eta[3 * k] == -eta[3 * h] && eta[3 * k + 1] == -eta[3 * h + 1] && eta[3 * k + 2] == -eta[3 * h + 2]) return k;
   return h;
 }
 
 /* Boundary sides valid: each 0..3; an axis periodic on both sides or walled on
- * both; 1D has no y sides; the reconstruction evaluation flag is 0 or 1. */
+ * both; 1D has no y sides; 3D is periodic; the reconstruction evaluation flag
+ * is 0 or 1. */
 static int bad_bc(const orc_params *P) {
   for (int k = 0; k < 4; ++k)
     if (P->bc[k] < 0 || P->bc[k] > 3) return 1;
   for (int a = 0; a < 2; ++a)
     if ((P->bc[2 * a] == 0) != (P->bc[2 * a + 1] == 0)) return 1;
   if (P->dim == 1 && (P->bc[2] || P->bc[3])) return 1;
+  if (P->dim == 3 && (P->bc[0] || P->bc[1] || P->bc[2] || P->bc[3])) return 1;
   return P->bc_eval != 0 && P->bc_eval != 1;
 }
 
@@ -552,64 +652,70 @@ static double wall_value(const orc_params *P, const double *vs, int side, int h,
                          int iy) {
   const int kind = P->bc[side];
   const int g = kind == 1 ? h : hd;
-  const double v = P->bc_eval ? val_at(P, vs, P->jmax, g)[cell_index(P, P->jmax, ix, iy)] : val_at(P, vs, l, g)[c];
+  const double v = P->bc_eval ? val_at(P, vs, P->jmax, g)[cell_index(P, P->jmax, ix, iy, 0)] : val_at(P, vs, l, g)[c];
   return kind == 3 ? -v : v;
 }
 
 int orc_transport(const orc_params *P, const uint8_t *tree, const double *vs, double *out,
                   int definition_form) {
   const int J = P->jmax, d = P->dim;
-  int eta[2 * MAXQ];
+  int eta[3 * MAXQ];
   orc_velocities(P, eta);
   if (bad_bc(P)) return -1;
   for (int l = P->jmin; l <= J; ++l) {
-    const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
+    const int n = J - l, w = 1 << n, wy = d >= 2 ? w : 1, wz = d == 3 ? w : 1;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_leaf(P, tree, l, c)) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      const int bx0 = x * w, by0 = y * wy; /* B = [bx0, bx0+w) x [by0, by0+wy) */
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      /* B = [bx0, bx0+w) x [by0, by0+wy) x [bz0, bz0+wz) */
+      const int bx0 = x * w, by0 = y * wy, bz0 = z * wz;
+#define IN_B(a, b, t) ((a) >= bx0 && (a) < bx0 + w && (b) >= by0 && (b) < by0 + wy && (t) >= bz0 && (t) < bz0 + wz)
       for (int h = 0; h < P->q; ++h) {
-        const int ex = eta[2 * h], ey = eta[2 * h + 1], hd = opposite(P, eta, h);
+        const int ex = eta[3 * h], ey = eta[3 * h + 1], ez = eta[3 * h + 2], hd = opposite(P, eta, h);
         const double *FJ = val_at(P, vs, J, h);
         const double fl = val_at(P, vs, l, h)[c];
         double res;
-        if (ex == 0 && ey == 0) {
+        if (ex == 0 && ey == 0 && ez == 0) {
           res = fl;
         } else if (n == 0) {
           const int sd = beyond_wall(P, J, x - ex, y - ey);
-          res = sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, x, y) : FJ[cell_index_wrapped(P, J, x - ex, y - ey)];
+          res = sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, x, y)
+                        : FJ[cell_index_wrapped(P, J, x - ex, y - ey, z - ez)];
         } else if (definition_form) {
           double s = 0.0;
-          for (int ky = by0; ky < by0 + wy; ++ky)
-            for (int kx = bx0; kx < bx0 + w; ++kx) {
-              const int sd = beyond_wall(P, J, kx - ex, ky - ey);
-              s += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky) : FJ[cell_index_wrapped(P, J, kx - ex, ky - ey)];
-            }
+          for (int kz = bz0; kz < bz0 + wz; ++kz)
+            for (int ky = by0; ky < by0 + wy; ++ky)
+              for (int kx = bx0; kx < bx0 + w; ++kx) {
+                const int sd = beyond_wall(P, J, kx - ex, ky - ey);
+                s += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky)
+                             : FJ[cell_index_wrapped(P, J, kx - ex, ky - ey, kz - ez)];
+              }
           res = ldexp(s, -d * n);
         } else {
           double sE = 0.0, sA = 0.0;
-          for (int ky = by0; ky < by0 + wy; ++ky)
-            for (int kx = bx0; kx < bx0 + w; ++kx) {
-              /* E = (B - eta) \ B: the cell k - eta, if it left B (beyond a wall: the condition) */
-              const int jx = kx - ex, jy = ky - ey;
-              if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy)) {
-                const int sd = beyond_wall(P, J, jx, jy);
-                sE += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky) : FJ[cell_index_wrapped(P, J, jx, jy)];
+          for (int kz = bz0; kz < bz0 + wz; ++kz)
+            for (int ky = by0; ky < by0 + wy; ++ky)
+              for (int kx = bx0; kx < bx0 + w; ++kx) {
+                /* E = (B - eta) \ B: the cell k - eta, if it left B (beyond a wall: the condition) */
+                const int jx = kx - ex, jy = ky - ey, jz = kz - ez;
+                if (!IN_B(jx, jy, jz)) {
+                  const int sd = beyond_wall(P, J, jx, jy);
+                  sE += sd >= 0 ? wall_value(P, vs, sd, h, hd, l, c, kx, ky) : FJ[cell_index_wrapped(P, J, jx, jy, jz)];
+                }
               }
-            }
-          for (int ky = by0; ky < by0 + wy; ++ky)
-            for (int kx = bx0; kx < bx0 + w; ++kx) {
-              /* A = B \ (B - eta): the cell k whose image k + eta left B */
-              const int ix = kx + ex, iy = ky + ey;
-              if (!(ix >= bx0 && ix < bx0 + w && iy >= by0 && iy < by0 + wy))
-                sA += FJ[cell_index(P, J, kx, ky)];
-            }
+          for (int kz = bz0; kz < bz0 + wz; ++kz)
+            for (int ky = by0; ky < by0 + wy; ++ky)
+              for (int kx = bx0; kx < bx0 + w; ++kx) {
+                /* A = B \ (B - eta): the cell k whose image k + eta left B */
+                if (!IN_B(kx + ex, ky + ey, kz + ez)) sA += FJ[cell_index(P, J, kx, ky, kz)];
+              }
           res = fl + ldexp(sE - sA, -d * n);
         }
         val_at(P, out, l, h)[c] = res;
       }
+#undef IN_B
     }
   }
   return 0;
@@ -686,7 +792,7 @@ done:
 int orc_uniform_step(const orc_params *P, double *fJ) {
   const int J = P->jmax, q = P->q;
   const int64_t NJ = ncells(P, J);
-  int eta[2 * MAXQ];
+  int eta[3 * MAXQ];
   double M[MAXQ * MAXQ], Minv[MAXQ * MAXQ], f[MAXQ];
   orc_velocities(P, eta);
   orc_moment_matrix(P, M);
@@ -696,11 +802,11 @@ int orc_uniform_step(const orc_params *P, double *fJ) {
   if (!g) return -1;
   for (int h = 0; h < q; ++h)
     for (int64_t c = 0; c < NJ; ++c) {
-      int x, y;
-      cell_coords(P, J, c, &x, &y);
-      const int sd = beyond_wall(P, J, x - eta[2 * h], y - eta[2 * h + 1]);
+      int x, y, z;
+      cell_coords(P, J, c, &x, &y, &z);
+      const int sd = beyond_wall(P, J, x - eta[3 * h], y - eta[3 * h + 1]);
       if (sd < 0) {
-        g[h * NJ + c] = fJ[h * NJ + cell_index_wrapped(P, J, x - eta[2 * h], y - eta[2 * h + 1])];
+        g[h * NJ + c] = fJ[h * NJ + cell_index_wrapped(P, J, x - eta[3 * h], y - eta[3 * h + 1], z - eta[3 * h + 2])];
       } else {  /* the boundary cell's own value of h (copy) or of its opposite */
         const int kind = P->bc[sd], src = kind == 1 ? h : opposite(P, eta, h);
         g[h * NJ + c] = kind == 3 ? -fJ[src * NJ + c] : fJ[src * NJ + c];
@@ -747,18 +853,19 @@ int orc_check_tree(const orc_params *P, const uint8_t *tree) {
   for (int l = P->jmin + 1; l <= P->jmax; ++l) {
     const uint8_t *t = tree_at(P, tree, l), *tp = tree_at(P, tree, l - 1);
     for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
-      int px, py, cnt = 0;
-      cell_coords(P, l - 1, p, &px, &py);
-      for (int sigma = 0; sigma < nchildren(P); ++sigma) cnt += t[child_index(P, l - 1, px, py, sigma)];
+      int px, py, pz, cnt = 0;
+      cell_coords(P, l - 1, p, &px, &py, &pz);
+      for (int sigma = 0; sigma < nchildren(P); ++sigma) cnt += t[child_index(P, l - 1, px, py, pz, sigma)];
       if (cnt != 0 && cnt != nchildren(P)) bad |= 2;
       if (cnt && !tp[p]) bad |= 4;
-      const int g = gam(P);
+      const int g = gam(P), gy = d >= 2 ? g : 0, gz = d == 3 ? g : 0;
       if (cnt)
-        for (int ay = (d == 2 ? -g : 0); ay <= (d == 2 ? g : 0); ++ay)
-          for (int ax = -g; ax <= g; ++ax) {
-            const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay);
-            if (nb >= 0 && !tp[nb]) bad |= 8;
-          }
+        for (int az = -gz; az <= gz; ++az)
+          for (int ay = -gy; ay <= gy; ++ay)
+            for (int ax = -g; ax <= g; ++ax) {
+              const int64_t nb = cell_index_set(P, l - 1, px + ax, py + ay, pz + az);
+              if (nb >= 0 && !tp[nb]) bad |= 8;
+            }
     }
   }
   return bad;
@@ -772,7 +879,7 @@ static float *valf_at(const orc_params *P, const float *v, int l, int h) {
   return (float *)v + (int64_t)P->q * orc_level_offset(P, l) + (int64_t)h * ncells(P, l);
 }
 
-static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, int cy) {
+static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, int cy, int cz) {
   const int n = side(l - 1), g = gam(P);
   float c[3];
   for (int a = 0; a < 3; ++a) c[a] = (float)CG[g][a]; /* exact in float */
@@ -785,6 +892,54 @@ static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, in
   }
   const int py = cy >> 1;
   const float sy = (cy & 1) ? -1.0f : 1.0f;
+  if (P->dim == 3) { /* predict_at's 3D expression, in float */
+    const int pz = cz >> 1;
+    const float sz = (cz & 1) ? -1.0f : 1.0f;
+#define A3(a, b, t) Fp[(int64_t)wrapi(px + (a), n) + (int64_t)n * ((int64_t)wrapi(py + (b), n) + (int64_t)n * wrapi(pz + (t), n))]
+    float Qx = c[0] * (A3(1, 0, 0) - A3(-1, 0, 0));
+    float Qy = c[0] * (A3(0, 1, 0) - A3(0, -1, 0));
+    float Qz = c[0] * (A3(0, 0, 1) - A3(0, 0, -1));
+    for (int a = 2; a <= g; ++a) {
+      Qx = Qx + c[a - 1] * (A3(a, 0, 0) - A3(-a, 0, 0));
+      Qy = Qy + c[a - 1] * (A3(0, a, 0) - A3(0, -a, 0));
+      Qz = Qz + c[a - 1] * (A3(0, 0, a) - A3(0, 0, -a));
+    }
+#define PAIR(a, b, U) \
+  ((c[(a) - 1] * c[(b) - 1]) * (((U((a), (b)) - U(-(a), (b))) - U((a), -(b))) + U(-(a), -(b))))
+#define XY(a, b) A3(a, b, 0)
+#define XZ(a, b) A3(a, 0, b)
+#define YZ(a, b) A3(0, a, b)
+    float Qxy = 0.0f, Qxz = 0.0f, Qyz = 0.0f;
+    for (int b = 1; b <= g; ++b)
+      for (int a = 1; a <= g; ++a) {
+        if (a == 1 && b == 1) {
+          Qxy = PAIR(1, 1, XY);
+          Qxz = PAIR(1, 1, XZ);
+          Qyz = PAIR(1, 1, YZ);
+        } else {
+          Qxy = Qxy + PAIR(a, b, XY);
+          Qxz = Qxz + PAIR(a, b, XZ);
+          Qyz = Qyz + PAIR(a, b, YZ);
+        }
+      }
+    float Qxyz = 0.0f;
+    for (int t = 1; t <= g; ++t)
+      for (int b = 1; b <= g; ++b)
+        for (int a = 1; a <= g; ++a) {
+          const float v = (((((((A3(a, b, t) - A3(-a, b, t)) - A3(a, -b, t)) - A3(a, b, -t)) + A3(-a, -b, t)) +
+                             A3(-a, b, -t)) + A3(a, -b, -t)) - A3(-a, -b, -t));
+          const float term = ((c[a - 1] * c[b - 1]) * c[t - 1]) * v;
+          Qxyz = (a == 1 && b == 1 && t == 1) ? term : Qxyz + term;
+        }
+    const float f0 = A3(0, 0, 0);
+#undef XY
+#undef XZ
+#undef YZ
+#undef PAIR
+#undef A3
+    return ((((((f0 + sx * Qx) + sy * Qy) + sz * Qz) + (sx * sy) * Qxy) + (sx * sz) * Qxz) + (sy * sz) * Qyz) +
+           ((sx * sy) * sz) * Qxyz;
+  }
 #define AT(a, b) Fp[(int64_t)mr_axis(P, 0, (a), n) + (int64_t)n * mr_axis(P, 1, (b), n)]
   float Qx = c[0] * (AT(px + 1, py) - AT(px - 1, py));
   float Qy = c[0] * (AT(px, py + 1) - AT(px, py - 1));
@@ -803,8 +958,13 @@ static float predict_f32(const orc_params *P, const float *Fp, int l, int cx, in
 #undef AT
 }
 
-static float project_f32(const orc_params *P, const float *Fc, int l, int px, int py) {
+static float project_f32(const orc_params *P, const float *Fc, int l, int px, int py, int pz) {
   if (P->dim == 1) return 0.5f * (Fc[2 * px] + Fc[2 * px + 1]);
+  if (P->dim == 3) {
+    float acc = Fc[child_index(P, l, px, py, pz, 0)];
+    for (int sigma = 1; sigma < 8; ++sigma) acc = acc + Fc[child_index(P, l, px, py, pz, sigma)];
+    return 0.125f * acc;
+  }
   const int64_t n = side(l + 1);
   const float a00 = Fc[2 * px + n * (2 * py)], a10 = Fc[2 * px + 1 + n * (2 * py)];
   const float a01 = Fc[2 * px + n * (2 * py + 1)], a11 = Fc[2 * px + 1 + n * (2 * py + 1)];
@@ -822,17 +982,17 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (!is_internal(P, tree, l, c)) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = project_f32(P, valf_at(P, v, l + 1, h), l, x, y);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = project_f32(P, valf_at(P, v, l + 1, h), l, x, y, z);
     }
   for (int l = P->jmin + 1; l <= P->jmax; ++l)
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncells(P, l); ++c) {
       if (tree_at(P, tree, l)[c]) continue;
-      int x, y;
-      cell_coords(P, l, c, &x, &y);
-      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = predict_f32(P, valf_at(P, v, l - 1, h), l, x, y);
+      int x, y, z;
+      cell_coords(P, l, c, &x, &y, &z);
+      for (int h = 0; h < P->q; ++h) valf_at(P, v, l, h)[c] = predict_f32(P, valf_at(P, v, l - 1, h), l, x, y, z);
     }
   for (int64_t i = 0; i < total; ++i) D[i] = -1.0;
   for (int l = P->jmin + 1; l <= P->jmax; ++l) {
@@ -840,15 +1000,16 @@ int orc_new_tree_f32(const orc_params *P, const uint8_t *tree, const float *leaf
     double *Dp = D + orc_level_offset(P, l - 1);
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < ncells(P, l - 1); ++p) {
-      int px, py;
-      cell_coords(P, l - 1, p, &px, &py);
-      if (!tp[p] || !tc[child_index(P, l - 1, px, py, 0)]) continue;
+      int px, py, pz;
+      cell_coords(P, l - 1, p, &px, &py, &pz);
+      if (!tp[p] || !tc[child_index(P, l - 1, px, py, pz, 0)]) continue;
       float dmax = 0.0f;
       for (int h = 0; h < P->q; ++h) {
         float s2 = 0.0f;
         for (int sigma = 0; sigma < nchildren(P); ++sigma) {
-          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1);
-          const float dd = valf_at(P, v, l, h)[cell_index(P, l, cx, cy)] - predict_f32(P, valf_at(P, v, l - 1, h), l, cx, cy);
+          const int cx = 2 * px + (sigma & 1), cy = 2 * py + ((sigma >> 1) & 1), cz = 2 * pz + ((sigma >> 2) & 1);
+          const float dd = valf_at(P, v, l, h)[cell_index(P, l, cx, cy, cz)] -
+                           predict_f32(P, valf_at(P, v, l - 1, h), l, cx, cy, cz);
           if (P->metric) s2 = s2 + dd * dd;
           else if (fabsf(dd) > dmax) dmax = fabsf(dd);
         }
@@ -898,7 +1059,7 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
  * (indices into level l-1) and weights such that the prediction equals
  * sum_k w[k] F[idx[k]]. Returns the number of terms (3 in 1D, 9 in 2D). */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w) {
-  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
+  if (has_walls(P) || P->scheme >= 4 || gam(P) > 1) return -1;
   const int n = side(l - 1);
   const int px = cx >> 1;
   const double sx = (cx & 1) ? -1.0 : 1.0;
@@ -911,7 +1072,7 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
   const int py = cy >> 1;
   const double sy = (cy & 1) ? -1.0 : 1.0, c2 = sx * sy * C1 * C1;
   int k = 0;
-#define PUT(a, b, ww) do { idx[k] = cell_index_wrapped(P, l - 1, (a), (b)); w[k] = (ww); ++k; } while (0)
+#define PUT(a, b, ww) do { idx[k] = cell_index_wrapped(P, l - 1, (a), (b), 0); w[k] = (ww); ++k; } while (0)
   PUT(px, py, 1.0);
   PUT(px + 1, py, sx * C1);
   PUT(px - 1, py, -sx * C1);
@@ -928,7 +1089,7 @@ int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx
 /* Transpose of orc_reconstruct: `g` holds a dense adjoint (any cell); on return
  * the leaf entries hold the adjoint of the leaf values and all others are 0. */
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
-  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
+  if (has_walls(P) || P->scheme >= 4 || gam(P) > 1) return -1;
   const double inv = 1.0 / nchildren(P);
   /* Each population is its own linear map: the populations run in parallel,
    * each with the loop order below. */
@@ -941,8 +1102,8 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
       double *gl = val_at(P, g, l, h), *gp = val_at(P, g, l - 1, h);
       for (int64_t c = 0; c < ncells(P, l); ++c) {
         if (t[c]) continue;
-        int x, y;
-        cell_coords(P, l, c, &x, &y);
+        int x, y, z;
+        cell_coords(P, l, c, &x, &y, &z);
         const int nk = orc_predict_stencil(P, l, x, y, idx, w);
         for (int k = 0; k < nk; ++k) gp[idx[k]] += w[k] * gl[c];
         gl[c] = 0.0;
@@ -952,9 +1113,9 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
       double *gl = val_at(P, g, l, h), *gc = val_at(P, g, l + 1, h);
       for (int64_t c = 0; c < ncells(P, l); ++c) {
         if (!is_internal(P, tree, l, c)) continue;
-        int x, y;
-        cell_coords(P, l, c, &x, &y);
-        for (int sigma = 0; sigma < nchildren(P); ++sigma) gc[child_index(P, l, x, y, sigma)] += inv * gl[c];
+        int x, y, z;
+        cell_coords(P, l, c, &x, &y, &z);
+        for (int sigma = 0; sigma < nchildren(P); ++sigma) gc[child_index(P, l, x, y, z, sigma)] += inv * gl[c];
         gl[c] = 0.0;
       }
     }
@@ -965,27 +1126,27 @@ int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g) {
 /* Transpose of orc_transport (E/A form): adds into the dense `gs` the adjoint of
  * the reconstruction F* from the leaf adjoints `ob` of the transported values. */
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs) {
-  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
+  if (has_walls(P) || P->scheme >= 4 || gam(P) > 1) return -1;
   const int J = P->jmax, d = P->dim;
-  int eta[2 * MAXQ];
+  int eta[3 * MAXQ];
   orc_velocities(P, eta);
   /* populations in parallel, each with the loop order below */
 #pragma omp parallel for schedule(static, 1)
   for (int h = 0; h < P->q; ++h) {
-    const int ex = eta[2 * h], ey = eta[2 * h + 1];
+    const int ex = eta[3 * h], ey = eta[3 * h + 1];
     double *GJ = val_at(P, gs, J, h);
     for (int l = P->jmin; l <= J; ++l) {
       const int n = J - l, w = 1 << n, wy = d == 2 ? w : 1;
       for (int64_t c = 0; c < ncells(P, l); ++c) {
         if (!is_leaf(P, tree, l, c)) continue;
-        int x, y;
-        cell_coords(P, l, c, &x, &y);
+        int x, y, z;
+        cell_coords(P, l, c, &x, &y, &z);
         const int bx0 = x * w, by0 = y * wy;
         const double a = val_at(P, ob, l, h)[c];
         if (ex == 0 && ey == 0) {
           val_at(P, gs, l, h)[c] += a;
         } else if (n == 0) {
-          GJ[cell_index_wrapped(P, J, x - ex, y - ey)] += a;
+          GJ[cell_index_wrapped(P, J, x - ex, y - ey, 0)] += a;
         } else {
           val_at(P, gs, l, h)[c] += a;
           const double sa = ldexp(a, -d * n);
@@ -993,9 +1154,9 @@ int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, 
             for (int kx = bx0; kx < bx0 + w; ++kx) {
               const int jx = kx - ex, jy = ky - ey;
               if (!(jx >= bx0 && jx < bx0 + w && jy >= by0 && jy < by0 + wy))
-                GJ[cell_index_wrapped(P, J, jx, jy)] += sa;
+                GJ[cell_index_wrapped(P, J, jx, jy, 0)] += sa;
               const int ix = kx + ex, iy = ky + ey;
-              if (!(ix >= bx0 && ix < bx0 + w && iy >= by0 && iy < by0 + wy)) GJ[cell_index(P, J, kx, ky)] -= sa;
+              if (!(ix >= bx0 && ix < bx0 + w && iy >= by0 && iy < by0 + wy)) GJ[cell_index(P, J, kx, ky, 0)] -= sa;
             }
         }
       }
@@ -1021,7 +1182,7 @@ void orc_equilibrium_jacobian(const orc_params *P, const double *m, double *Je) 
   const int q = P->q;
   const double L = P->lambda;
   memset(Je, 0, sizeof(double) * q * q);
-  if (P->scheme == 4) return; /* the adjoint covers schemes 1..3 (its entry points refuse 4) */
+  if (P->scheme >= 4) return; /* the adjoint covers schemes 1..3 (its entry points refuse the others) */
   if (P->scheme == 1) {
     Je[0] = 1.0;
     Je[1 * q + 0] = P->eq_param;
@@ -1105,7 +1266,7 @@ int orc_collide_T(const orc_params *P, const uint8_t *tree, const double *h, con
 /* Adjoint of the initial datum f = M^{-1} m_eq(m0) on the finest level: from the
  * adjoint abar of the finest-level values, the adjoint of m0 ([nc][N_J^d]). */
 int orc_init_T(const orc_params *P, const double *m0, const double *abar, double *mbar) {
-  if (P->scheme == 4) return -1;
+  if (P->scheme >= 4) return -1;
   const int q = P->q, J = P->jmax, nc = P->scheme == 3 ? 3 : 1;
   const int64_t NJ = ncells(P, J);
   double Minv[MAXQ * MAXQ], m[MAXQ], Je[MAXQ * MAXQ], b[MAXQ];
@@ -1150,7 +1311,7 @@ static int step_precollision(const orc_params *P, const uint8_t *told, const uin
  * adds d/ds into sbar. */
 int orc_adjoint_step(const orc_params *P, const uint8_t *told, const uint8_t *tnew, const double *vold,
                      const double *anew, double *aold, double *sbar) {
-  if (has_walls(P) || P->scheme == 4 || gam(P) > 1) return -1;
+  if (has_walls(P) || P->scheme >= 4 || gam(P) > 1) return -1;
   const int64_t total = orc_total_cells(P), n = P->q * total;
   double *h = calloc((size_t)n, sizeof(double)), *hb = calloc((size_t)n, sizeof(double));
   double *gs = calloc((size_t)n, sizeof(double));

@@ -15,7 +15,8 @@
  *
  * Flat array layouts shared with the Python wrapper:
  *   tree   uint8  [level jmin..J][cell]        1 = cell is in the complete tree
- *   values double [level jmin..J][h][cell]     cell index = x (1D), x + N_l*y (2D)
+ *   values double [level jmin..J][h][cell]     cell index = x (1D), x + N_l*y (2D),
+ *                                              x + N_l*(y + N_l*z) (3D)
  *   (vectorial D2Q4: population h = 4 i + k is velocity k of the scheme of
  *   conserved variable i; moment 4 i + j is moment j of that scheme)
  *   detail double [level jmin..J][cell]        D(parent) stored at the parent's slot
@@ -30,11 +31,13 @@ extern "C" {
 #endif
 
 typedef struct {
-  int dim;        /* 1 or 2 */
-  int q;          /* 2 (D1Q2), 3 (D1Q3), 9 (D2Q9), 16 (four D2Q4) */
+  int dim;        /* 1, 2 or 3 */
+  int q;          /* 2 (D1Q2), 3 (D1Q3), 9 (D2Q9), 16 (four D2Q4), 6 (D3Q6) */
   int scheme;     /* 1 = D1Q2 advection, 2 = D1Q3 Burgers, 3 = D2Q9 Lallemand-Luo MRT,
                      4 = vectorial D2Q4 for the Euler system (four D2Q4 schemes,
-                     one per conserved variable rho, rho u, rho v, E) */
+                     one per conserved variable rho, rho u, rho v, E),
+                     5 = D3Q6 advection (section "Three dimensional advection
+                     equation"; periodic, no adjoint) */
   int jmin, jmax; /* coarsest and finest level */
   int pad_;
   double lambda;   /* lattice velocity, Delta x / Delta t */
@@ -57,6 +60,9 @@ typedef struct {
   int gamma;
   int metric;
   int pad3_;
+  /* D3Q6: the advection velocity (V_x, V_y, V_z) of the equilibrium
+   * m_eq = (u, V_x u, V_y u, V_z u, 0, 0); unused by the other schemes. */
+  double vel[3];
 } orc_params;
 
 /* Number of cells summed over levels jmin..J, and the offset of level l. */
@@ -74,9 +80,10 @@ int orc_init(const orc_params *P, const double *m0, uint8_t *tree, double *value
  * `values` must hold the leaf values; on return it is dense on every level. */
 int orc_reconstruct(const orc_params *P, const uint8_t *tree, double *values);
 
-/* Prediction of one child cell (level l, index cx[,cy]) from the dense data of
- * level l-1 of one population. */
+/* Prediction of one child cell (level l, index cx[,cy[,cz]]) from the dense
+ * data of level l-1 of one population. */
 double orc_predict(const orc_params *P, const double *parent_level, int l, int cx, int cy);
+double orc_predict3(const orc_params *P, const double *parent_level, int l, int cx, int cy, int cz);
 
 /* Details: for every parent p at level l-1 whose children are in the tree,
  * D[l-1][p] = max_h max_children |f - prediction| (metric 0), or
@@ -111,7 +118,8 @@ int orc_step_frozen(const orc_params *P, uint8_t *tree, const uint8_t *tnew, dou
 
 /* Adjoint on frozen meshes (transposes of the step's linear maps and of the
  * linearised collision; each adds into its output in a fixed order). Periodic
- * boundaries only: with a wall they return -1. */
+ * boundaries, gamma = 1, d <= 2 and the schemes 1..3 only: otherwise they
+ * return -1. */
 int orc_predict_stencil(const orc_params *P, int l, int cx, int cy, int64_t *idx, double *w);
 int orc_reconstruct_T(const orc_params *P, const uint8_t *tree, double *g);
 int orc_transport_T(const orc_params *P, const uint8_t *tree, const double *ob, double *gs);
@@ -132,7 +140,7 @@ int orc_uniform_step(const orc_params *P, double *fJ);
 void orc_moment_matrix(const orc_params *P, double *M);
 int orc_moment_matrix_inverse(const orc_params *P, double *Minv);
 void orc_equilibrium(const orc_params *P, const double *m, double *meq);
-/* Logical velocities eta^h, layout [q][2] (y component 0 in 1D). */
+/* Logical velocities eta^h, layout [q][3] (components beyond the dimension 0). */
 void orc_velocities(const orc_params *P, int *eta);
 
 /* Host threads of the oracle's parallel per-cell loops (results do not depend

@@ -6,21 +6,24 @@ fields (point values at finest-cell centres, generated once on the host with
 numpy so that both sides receive identical bits).
 
 Parameter dictionary keys:
-  scheme   "D1Q2" | "D1Q3" | "D2Q9"
+  scheme   "D1Q2" | "D1Q3" | "D2Q9" | "D2Q4E" | "D3Q6"
   jmin, jmax, eps, mu_bar, lam (lattice velocity), eq_param (V or alpha),
+  velocity (V_x, V_y, V_z) of the D3Q6 advection,
   s        relaxation rate of every moment (0 for conserved moments)
   domain   (lo, hi) of the box along each axis
   bc       boundary of each side x-, x+, y-, y+ (BC_KINDS codes; default all
            periodic); bc_eval 0 / 1: wall values taken on the leaf / on the
            reconstruction (section "Boundary conditions")
-Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D), 3 (rho, q_x, q_y)
-or 4 (the Euler system: rho, rho u, rho v, E), cell index x + N_J * y.
+Initial fields ``m0`` have shape [nc][N_J^d] with nc = 1 (1D, D3Q6), 3 (rho,
+q_x, q_y) or 4 (the Euler system: rho, rho u, rho v, E), cell index x + N_J * y
+(3D: x + N_J * (y + N_J * z)).
 """
 from __future__ import annotations
 
 import numpy as np
 
-SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3), "D2Q4E": (2, 16, 4)}  # dim, q, conserved
+SCHEME_DIMS = {"D1Q2": (1, 2, 1), "D1Q3": (1, 3, 1), "D2Q9": (2, 9, 3), "D2Q4E": (2, 16, 4),
+               "D3Q6": (3, 6, 1)}  # dim, q, conserved
 
 
 BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
@@ -28,10 +31,11 @@ BC_KINDS = {"periodic": 0, "copy": 1, "bounce_back": 2, "anti_bounce_back": 3}
 
 def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0, lam: float = 1.0,
            eq_param: float = 0.0, domain=(0.0, 1.0), bc=None, bc_eval: int = 0, gamma: int = 1,
-           metric: str = "linf") -> dict:
+           metric: str = "linf", velocity=(0.0, 0.0, 0.0)) -> dict:
     """Parameter dictionary. ``bc``: None (periodic) or the kind of each side
     x-, x+, y-, y+ (names of BC_KINDS or their codes; 1D takes two). ``gamma``:
-    prediction stencil half-width 1..3; ``metric``: "linf" or "l2" sibling metric."""
+    prediction stencil half-width 1..3; ``metric``: "linf" or "l2" sibling metric;
+    ``velocity``: the D3Q6 advection velocity."""
     dim, q, _ = SCHEME_DIMS[scheme]
     s = [float(v) for v in s]
     assert len(s) == q
@@ -41,7 +45,8 @@ def params(scheme: str, jmin: int, jmax: int, eps: float, s, mu_bar: float = 0.0
             codes[k] = BC_KINDS[v] if isinstance(v, str) else int(v)
     return dict(scheme=scheme, dim=dim, q=q, jmin=int(jmin), jmax=int(jmax), eps=float(eps),
                 mu_bar=float(mu_bar), lam=float(lam), eq_param=float(eq_param), s=s,
-                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval), gamma=int(gamma), metric=metric)
+                domain=tuple(domain), bc=tuple(codes), bc_eval=int(bc_eval), gamma=int(gamma), metric=metric,
+                velocity=tuple(float(v) for v in velocity))
 
 
 def cell_centres(jmax: int, domain=(0.0, 1.0)) -> np.ndarray:
@@ -208,6 +213,31 @@ def vortex_amplitude_gradient(cfg: dict, mbar) -> np.ndarray:
     return s * (gx @ mb[1] + gy @ mb[2]) - (s / S) * dS * float(mb[1] @ ux + mb[2] @ uy)
 
 
+# ---------------------------------------------------------------- 3D workload
+
+def d3q6_s(s1: float = 1.4, s2: float = 1.0) -> list:
+    """Relaxation vector diag(0, s1, s1, s1, s2, s2) of the D3Q6 scheme."""
+    return [0.0, s1, s1, s1, s2, s2]
+
+
+def ball_d3q6(jmin=1, jmax=8, eps=1e-3, mu_bar=2.0, s1=1.4, s2=1.0, velocity=(0.3, 0.2, 0.1), radius=0.15,
+              gamma=1, metric="linf"):
+    """D3Q6 advection of the indicator of the ball of radius 0.15 centred at the
+    origin (section "Three dimensional advection equation": lambda = 1, s1 =
+    1.4, s2 = 1, jmin = 1, J = 8, mu_bar = 2, eps = 1e-3), on the periodic box
+    [-1, 1]^3. The paper does not state the velocity V nor the domain: V =
+    (0.3, 0.2, 0.1) (each component below lambda / 3, where the equilibrium
+    populations stay non-negative) and the box [-1, 1]^3 are this workload's
+    choice."""
+    cfg = params("D3Q6", jmin, jmax, eps, d3q6_s(s1, s2), mu_bar=mu_bar, lam=1.0, domain=(-1.0, 1.0),
+                 gamma=gamma, metric=metric, velocity=velocity)
+    cfg.update(radius=float(radius))
+    xc = cell_centres(jmax, cfg["domain"])
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")  # [z][y][x]
+    u0 = (X * X + Y * Y + Z * Z <= radius * radius).astype(np.float64)
+    return cfg, u0.reshape(1, -1).copy()
+
+
 def random_field(cfg: dict, seed: int, kind: str = "smooth") -> np.ndarray:
     """Generic seeded initial conserved moments for tests: smooth random modes plus,
     for kind="jump", a step, so that meshes get several levels."""
@@ -217,9 +247,12 @@ def random_field(cfg: dict, seed: int, kind: str = "smooth") -> np.ndarray:
     xc = (np.arange(n) + 0.5) / n
     if dim == 1:
         grids = (xc,)
-    else:
+    elif dim == 2:
         X, Y = np.meshgrid(xc, xc, indexing="xy")
         grids = (X, Y)
+    else:
+        Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")  # [z][y][x]: cell index x + N (y + N z)
+        grids = (X, Y, Z)
     fields = []
     for c in range(nc):
         f = np.zeros_like(grids[0])
@@ -240,5 +273,5 @@ def random_field(cfg: dict, seed: int, kind: str = "smooth") -> np.ndarray:
         u = fields[0]
         m0 = (0.4 * u / np.max(np.abs(u)))[None, :]
     else:
-        m0 = fields[0][None, :]
+        m0 = fields[0].reshape(1, -1)
     return np.ascontiguousarray(m0, dtype=np.float64)

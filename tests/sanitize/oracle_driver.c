@@ -31,7 +31,7 @@ static double urand(void) { /* splitmix64, in [0, 1) */
 static void run(int scheme, int jmin, int jmax, double eps, int gamma, int metric, const int bc[4], int steps) {
   orc_params P;
   memset(&P, 0, sizeof P);
-  const int dims[5] = {0, 1, 1, 2, 2}, qs[5] = {0, 2, 3, 9, 16}, ncs[5] = {0, 1, 1, 3, 4};
+  const int dims[6] = {0, 1, 1, 2, 2, 3}, qs[6] = {0, 2, 3, 9, 16, 6}, ncs[6] = {0, 1, 1, 3, 4, 1};
   P.dim = dims[scheme];
   P.q = qs[scheme];
   P.scheme = scheme;
@@ -42,7 +42,10 @@ static void run(int scheme, int jmin, int jmax, double eps, int gamma, int metri
   P.eps = eps;
   P.mu_bar = 1.0;
   for (int h = 0; h < P.q; ++h) P.s[h] = 1.5;
-  if (scheme == 1 || scheme == 2) P.s[0] = 0.0;
+  if (scheme == 1 || scheme == 2 || scheme == 5) P.s[0] = 0.0;
+  P.vel[0] = 0.3;
+  P.vel[1] = 0.2;
+  P.vel[2] = 0.1;
   if (scheme == 3) P.s[0] = P.s[1] = P.s[2] = 0.0;
   if (scheme == 4)
     for (int i = 0; i < 4; ++i) P.s[4 * i] = 0.0;
@@ -55,7 +58,7 @@ static void run(int scheme, int jmin, int jmax, double eps, int gamma, int metri
   for (int64_t c = 0; c < nJ; ++c) {
     const double x = ((double)(c % ((int64_t)1 << jmax)) + 0.5) / (double)((int64_t)1 << jmax);
     const double bump = (x > 0.3 && x < 0.6 ? 0.4 : 0.0) + 0.05 * urand();
-    if (scheme <= 2) {
+    if (scheme <= 2 || scheme == 5) {
       m0[c] = 0.5 + bump;
     } else if (scheme == 3) {
       m0[c] = 1.0 + 0.1 * bump;
@@ -83,7 +86,7 @@ static void run(int scheme, int jmin, int jmax, double eps, int gamma, int metri
   const double mass = orc_mass(&P, tree, v);
   if (!isfinite(mass)) exit(2);
   if (orc_check_tree(&P, tree)) exit(3);
-  if (gamma == 1 && !bc[0] && !bc[2] && scheme != 4) { /* the adjoint's primitives */
+  if (gamma == 1 && !bc[0] && !bc[2] && scheme <= 3) { /* the adjoint's primitives */
     double *g = calloc((size_t)(P.q * total), sizeof(double)), *go = calloc((size_t)(P.q * total), sizeof(double));
     for (int64_t k = 0; k < P.q * total; ++k) g[k] = urand();
     CHECK(orc_reconstruct_T(&P, tree, g));
@@ -110,5 +113,7 @@ int main(void) {
   run(3, 3, 6, 1e-3, 2, 1, walls2, 4);
   run(3, 2, 6, 1e-3, 1, 1, mixed, 4);
   run(4, 3, 6, 1e-3, 2, 0, walls2, 3);
+  run(5, 2, 5, 1e-3, 1, 0, per, 3);
+  run(5, 2, 4, 1e-3, 2, 1, per, 2);
   return 0;
 }

@@ -60,7 +60,7 @@ def test_oracle_under_sanitizers():
            "-fno-omit-frame-pointer", "-ffp-contract=off", "-fopenmp", "-I", os.path.join(ROOT, "oracle"),
            srcs[0], srcs[1], "-lm"]
     out = _run(_build("oracle_driver", srcs, cmd))
-    assert out.count("mass") == 7
+    assert out.count("mass") == 9
 
 
 @pytest.mark.timeout(900)
