@@ -18,12 +18,12 @@
  *
  * Data layout (shared by every host<->device exchange below):
  *   levels l = jmin..jmax are concatenated; level l holds N_l^d cells, N_l = 2^l,
- *   cell index c = x (1D) or x + N_l * y (2D);
+ *   cell index c = x (1D), x + N_l * y (2D) or x + N_l * (y + N_l * z) (3D);
  *   tree    uint8  [level][cell]      1 = the cell belongs to the complete tree;
  *   values  real   [level][h][cell]   real = double (precision 8) or float (4);
  *                                     only complete leaves carry meaningful data.
  *   moments real   [nc][N_J^d]        conserved moments on the finest level:
- *                                     nc = 1 (u) for D1Q2 / D1Q3,
+ *                                     nc = 1 (u) for D1Q2 / D1Q3 / D3Q6,
  *                                     nc = 3 (rho, q_x, q_y) for D2Q9,
  *                                     nc = 4 (rho, rho u, rho v, E) for the Euler scheme.
  *
@@ -72,12 +72,20 @@ extern "C" {
  * law p = (gamma_gas - 1) (E - rho (u^2 + v^2) / 2). Population 4 i + k is
  * velocity k of variable i, and so is moment 4 i + k. */
 #define MRLBM_D2Q4_EULER 4
+/* D3Q6 advection (section "Three dimensional advection equation"): velocities
+ * lambda cos(pi h) along x (h = 0, 1), y (h = 2, 3) and z (h = 4, 5); moments
+ * u = sum f, lambda (f0 - f1), lambda (f2 - f3), lambda (f4 - f5),
+ * lambda^2 (f0 + f1 - f2 - f3), lambda^2 (f0 + f1 - f4 - f5) with equilibria
+ * u, V_x u, V_y u, V_z u, 0, 0 (V = mrlbm_params.velocity). Three-dimensional:
+ * cell index x + N_l (y + N_l z); periodic boundaries, gamma = 1 and jmax <= 8
+ * only; no adjoint. */
+#define MRLBM_D3Q6 5
 
 typedef struct mrlbm_ctx mrlbm_ctx;
 
 typedef struct {
-  int scheme;      /* MRLBM_D1Q2, MRLBM_D1Q3, MRLBM_D2Q9 or MRLBM_D2Q4_EULER */
-  int jmin, jmax;  /* coarsest and finest level: 1 <= jmin <= jmax, jmax <= 13 (2D) / 25 (1D) */
+  int scheme;      /* MRLBM_D1Q2, MRLBM_D1Q3, MRLBM_D2Q9, MRLBM_D2Q4_EULER or MRLBM_D3Q6 */
+  int jmin, jmax;  /* coarsest and finest level: 1 <= jmin <= jmax, jmax <= 8 (3D) / 13 (2D) / 25 (1D) */
   int precision;   /* 8: populations, details and weights in double; 4: in float */
   double lambda;   /* lattice velocity dx/dt (> 0) */
   double eq_param; /* D1Q2: advection velocity V; D1Q3: alpha; D2Q9: ignored; Euler: gamma_gas > 1 */
@@ -109,6 +117,9 @@ typedef struct {
    * footnote, which the library compares squared (2^{-d} times the sum of
    * squares against the squared thresholds). May differ per instance. */
   int metric;
+  /* MRLBM_D3Q6: the advection velocity (V_x, V_y, V_z) of the equilibrium;
+   * ignored by the other schemes. */
+  double velocity[3];
 } mrlbm_params;
 
 #define MRLBM_METRIC_MAX 0

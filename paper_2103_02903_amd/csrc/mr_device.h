@@ -27,6 +27,7 @@ template <typename T>
 struct SchemeC {
   T lam, inv_lam, eq;  // lattice velocity, its inverse, V (D1Q2), alpha (D1Q3) or gamma_gas (Euler)
   T s[16];
+  T vel[3];            // D3Q6: the advection velocity (V_x, V_y, V_z)
 };
 
 // One simulation of a batch. Per-cell arrays (codes, flags, lists) of all
@@ -227,6 +228,13 @@ struct Vel<4> {  // Euler system: four D2Q4 schemes, population 4 i + k is veloc
   __host__ __device__ static constexpr int ey(int h) { return (h & 3) == 1 ? 1 : ((h & 3) == 3 ? -1 : 0); }
 };
 template <>
+struct Vel<5> {  // D3Q6: lambda cos(pi h) along x (h = 0, 1), y (2, 3) and z (4, 5)
+  static constexpr int Q = 6, DIM = 3, NC = 1;
+  __host__ __device__ static constexpr int ex(int h) { return h == 0 ? 1 : (h == 1 ? -1 : 0); }
+  __host__ __device__ static constexpr int ey(int h) { return h == 2 ? 1 : (h == 3 ? -1 : 0); }
+  __host__ __device__ static constexpr int ez(int h) { return h == 4 ? 1 : (h == 5 ? -1 : 0); }
+};
+template <>
 struct Vel<3> {  // D2Q9: rest, four axis velocities, four diagonals
   static constexpr int Q = 9, DIM = 2, NC = 3;
   __host__ __device__ static constexpr int ex(int h) {
@@ -313,11 +321,49 @@ __device__ __forceinline__ void d2q4_populations(T m0, T m1, T m2, T m3, T il, T
   f[3] = (a - c) - d;
 }
 
+// D3Q6 (section "Three dimensional advection equation"): with a = f0 + f1,
+// b = f2 + f3, c = f4 + f5 the moments are m0 = a + b + c, m1..m3 = lambda
+// (f0 - f1, f2 - f3, f4 - f5), m4 = lambda^2 (a - b), m5 = lambda^2 (a - c);
+// M^{-1}: a = (m0 + (m4 + m5) / lambda^2) / 3, b = a - m4 / lambda^2,
+// c = a - m5 / lambda^2, f0 = (a + m1 / lambda) / 2, f1 = (a - m1 / lambda) / 2,
+// and alike along y and z.
+template <typename T>
+__device__ __forceinline__ void d3q6_moments(const T *f, T *m, T L) {
+  const T a = f[0] + f[1], b = f[2] + f[3], c = f[4] + f[5];
+  m[0] = (a + b) + c;
+  m[1] = L * (f[0] - f[1]);
+  m[2] = L * (f[2] - f[3]);
+  m[3] = L * (f[4] - f[5]);
+  m[4] = (L * L) * (a - b);
+  m[5] = (L * L) * (a - c);
+}
+template <typename T>
+__device__ __forceinline__ void d3q6_populations(const T *m, T *f, T il) {
+  const T il2 = il * il, d4 = m[4] * il2, d5 = m[5] * il2;
+  const T a = (m[0] + (d4 + d5)) * T(1.0 / 3.0), b = a - d4, c = a - d5;
+  const T u = m[1] * il, v = m[2] * il, w = m[3] * il;
+  f[0] = T(0.5) * (a + u);
+  f[1] = T(0.5) * (a - u);
+  f[2] = T(0.5) * (b + v);
+  f[3] = T(0.5) * (b - v);
+  f[4] = T(0.5) * (c + w);
+  f[5] = T(0.5) * (c - w);
+}
+
 // Collision in moment space: f^* = M^{-1} (m + S (m_eq(m) - m)), m = M f; the
 // conserved moments (s = 0) are passed through untouched.
 template <int SCHEME, typename T>
 __device__ __forceinline__ void collide(T *f, const SchemeC<T> &sc) {
-  if constexpr (SCHEME == 1) {
+  if constexpr (SCHEME == 5) {  // m_eq = (u, V_x u, V_y u, V_z u, 0, 0)
+    T m[6];
+    d3q6_moments(f, m, sc.lam);
+    m[1] = m[1] + sc.s[1] * (sc.vel[0] * m[0] - m[1]);
+    m[2] = m[2] + sc.s[2] * (sc.vel[1] * m[0] - m[2]);
+    m[3] = m[3] + sc.s[3] * (sc.vel[2] * m[0] - m[3]);
+    m[4] = m[4] + sc.s[4] * (T(0) - m[4]);
+    m[5] = m[5] + sc.s[5] * (T(0) - m[5]);
+    d3q6_populations(m, f, sc.inv_lam);
+  } else if constexpr (SCHEME == 1) {
     const T m0 = f[0] + f[1];
     T m1 = sc.lam * (f[0] - f[1]);
     m1 = m1 + sc.s[1] * (sc.eq * m0 - m1);
@@ -365,7 +411,9 @@ __device__ __forceinline__ void collide(T *f, const SchemeC<T> &sc) {
 // Moments m = M f of one cell (the same bases as the collision below).
 template <int SCHEME, typename T>
 __device__ __forceinline__ void moments(const T *f, T *m, T L) {
-  if constexpr (SCHEME == 1) {
+  if constexpr (SCHEME == 5) {
+    d3q6_moments(f, m, L);
+  } else if constexpr (SCHEME == 1) {
     m[0] = f[0] + f[1];
     m[1] = L * (f[0] - f[1]);
   } else if constexpr (SCHEME == 2) {
@@ -389,7 +437,10 @@ __device__ __forceinline__ void moments(const T *f, T *m, T L) {
 // f = M^{-1} m_eq(m) from the conserved moments (initial datum of Algorithm 1).
 template <int SCHEME, typename T>
 __device__ __forceinline__ void equilibrium_populations(const T *mc, T *f, const SchemeC<T> &sc) {
-  if constexpr (SCHEME == 1) {
+  if constexpr (SCHEME == 5) {
+    const T m[6] = {mc[0], sc.vel[0] * mc[0], sc.vel[1] * mc[0], sc.vel[2] * mc[0], T(0), T(0)};
+    d3q6_populations(m, f, sc.inv_lam);
+  } else if constexpr (SCHEME == 1) {
     const T a = (sc.eq * mc[0]) * sc.inv_lam;
     f[0] = T(0.5) * (mc[0] + a);
     f[1] = T(0.5) * (mc[0] - a);

@@ -1421,7 +1421,7 @@ __global__ void __launch_bounds__(BLK) k_compact_scatter(Batch bt, const Inst<T>
     uint32_t *out = lists + (size_t)k * bt.ctotal + boff[k * nblocks + blockIdx.x];
     for (int j = threadIdx.x; j < tot[k]; j += BLK) out[j] = tag | (uint32_t)(base + ent[k][j]);
   }
-  if (!F) return;  // uniform: the adaptation's transfer follows
+  if (DIM == 3 || !F) return;  // uniform: the adaptation's transfer follows (3D: a kernel of its own)
   // The cells of the block created by the adaptation (new leaves outside the
   // old mesh) are gathered in LDS and predicted one per thread. New leaves
   // outside the old tree (these and former ghosts) get a mark for the

@@ -18,14 +18,17 @@
 
 #include "mr_adjoint.h"
 #include "mr_kernels.h"
+#include "mr_kernels3d.h"
 #include "mrlbm.h"
 
 using namespace mrlbm;
 
 namespace {
 
-int scheme_dim(int s) { return s == MRLBM_D2Q9 || s == MRLBM_D2Q4_EULER ? 2 : 1; }
-int scheme_q(int s) { return s == MRLBM_D1Q2 ? 2 : s == MRLBM_D1Q3 ? 3 : s == MRLBM_D2Q9 ? 9 : 16; }
+int scheme_dim(int s) { return s == MRLBM_D3Q6 ? 3 : s == MRLBM_D2Q9 || s == MRLBM_D2Q4_EULER ? 2 : 1; }
+int scheme_q(int s) {
+  return s == MRLBM_D1Q2 ? 2 : s == MRLBM_D1Q3 ? 3 : s == MRLBM_D2Q9 ? 9 : s == MRLBM_D3Q6 ? 6 : 16;
+}
 void scheme_eta(int s, int h, int &ex, int &ey) {
   static const int d1q2[2] = {1, -1};
   static const int d1q3[3] = {0, 1, -1};
@@ -44,10 +47,17 @@ bool conserved(int s, int i) {
 
 int validate_one(const mrlbm_params *p) {
   if (!p) return MRLBM_ERR_INVALID;
-  if (p->scheme < MRLBM_D1Q2 || p->scheme > MRLBM_D2Q4_EULER) return MRLBM_ERR_INVALID;
+  if (p->scheme < MRLBM_D1Q2 || p->scheme > MRLBM_D3Q6) return MRLBM_ERR_INVALID;
   if (p->scheme == MRLBM_D2Q4_EULER && !(p->eq_param > 1.0)) return MRLBM_ERR_INVALID;  // gamma_gas
   const int dim = scheme_dim(p->scheme);
-  const int maxj = dim == 2 ? 13 : 25;
+  const int maxj = dim == 3 ? 8 : dim == 2 ? 13 : 25;  // 3D: cells of level 8 fill the 26 bits of a list entry
+  if (dim == 3) {  // periodic, gamma = 1, finite velocity
+    for (int k = 0; k < 4; ++k)
+      if (p->bc[k] != MRLBM_PERIODIC) return MRLBM_ERR_INVALID;
+    if (p->gamma > 1) return MRLBM_ERR_INVALID;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->velocity[a])) return MRLBM_ERR_INVALID;
+  }
   if (p->jmin < 1 || p->jmax < p->jmin || p->jmax > maxj) return MRLBM_ERR_INVALID;
   if (p->precision != 4 && p->precision != 8) return MRLBM_ERR_INVALID;
   if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return MRLBM_ERR_INVALID;
@@ -295,6 +305,7 @@ void make_plan(const mrlbm_params *p, int B, Plan &P) {
     I.sc.inv_lam = 1.0 / p[i].lambda;
     I.sc.eq = p[i].eq_param;
     for (int k = 0; k < 16; ++k) I.sc.s[k] = p[i].s[k];
+    for (int k = 0; k < 3; ++k) I.sc.vel[k] = p[i].velocity[k];
     I.walls = walls_of(&p[i]);
     if (I.walls) P.any_walls = true;
     for (int k = 0; k < 4; ++k) I.bck[k] = p[i].bc[k];
@@ -662,10 +673,120 @@ hipError_t bracket_last_kernels(hipGraph_t g, hipEvent_t ev, hipGraphNode_t *n0,
 constexpr long long LEAF_KERNEL_CELLS = 1ll << 23;
 constexpr unsigned long long TIMING_PERIOD = 8;  // graph steps per timed transport launch (profile mode 1)
 
+// Step replay and dry-step timing, shared by the engines (E: the engine, with
+// its adaptation, reconstruction and transport).
+//
+// One full step replayed from a HIP graph, one graph per assignment of the
+// double buffers (a step swaps the mesh buffers and, in the transport, F). With
+// profiling on, every TIMING_PERIOD-th step replays a graph in which
+// event-record nodes bracket the transport kernel; before each such launch
+// they are pointed at two fresh events. (Each event record drains the queue,
+// some microseconds, so timing every step would slow the steps it measures.)
+template <class E>
+int step_graph_impl(mrlbm_ctx *c) {
+  const int timed = c->profiling && (c->graph_steps++ % c->timing_period == 0) ? 1 : 0;
+  const int par = c->mcur, key = 2 * c->cur + par;
+  hipGraphExec_t &g = c->graph[timed][key];
+  if (!g) {
+    const int cur0 = c->cur;
+    hipStream_t user = c->stream;
+    const bool prof = c->profiling;
+    c->stream = c->cap_stream;
+    c->profiling = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    int rc = e == hipSuccess ? E::adapt(c) : MRLBM_ERR_HIP;
+    if (rc == MRLBM_OK) E::reconstruct(c, (typename E::Real *)c->F[c->cur], c->mcur);
+    if (rc == MRLBM_OK) rc = E::transport_kernel(c);
+    if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
+    c->stream = user;
+    c->profiling = prof;
+    c->mcur = par;
+    c->cur = cur0;
+    if (rc == MRLBM_OK && e == hipSuccess && timed)
+      e = bracket_last_kernels(graph, c->ev_placeholder, &c->timed_ev[key][0], &c->timed_ev[key][1],
+                               E::transport_kernels(c));
+    if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+    if (rc == MRLBM_OK && e == hipSuccess && timed) {
+      c->timed_src[key] = graph;  // the event nodes belong to it
+      graph = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != MRLBM_OK) return rc;
+    if (e != hipSuccess) { g = nullptr; return MRLBM_ERR_HIP; }
+  }
+  if (timed) {
+    for (int k = 0; k < 2; ++k) {
+      if (c->ev_used + k == c->ev_pool.size()) {
+        hipEvent_t ev;
+        if (timing_event(&ev) != hipSuccess) return MRLBM_ERR_HIP;
+        c->ev_pool.push_back(ev);
+      }
+      if (hipGraphExecEventRecordNodeSetEvent(g, c->timed_ev[key][k], c->ev_pool[c->ev_used + k]) != hipSuccess)
+        return MRLBM_ERR_HIP;
+    }
+    c->ev_marks.push_back({PH_TRANSPORT, c->ev_used});
+    c->ev_used += 2;
+  }
+  if (hipGraphLaunch(g, c->stream) != hipSuccess) return MRLBM_ERR_HIP;
+  c->mcur = 1 - par;    // the adaptation's swap
+  c->cur = 1 - c->cur;  // the transport's swap
+  return MRLBM_OK;
+}
+
+// A step that leaves the state as it was: the adaptation writes the next mesh
+// buffers and, in the current value buffer, recomputes the values already
+// there (its reconstruction) or writes cells outside the current mesh (its
+// transfer); the transport then runs on the current mesh into the other value
+// buffer. Captured once per schedule and replayed `reps` times between HIP
+// events.
+template <class E>
+int time_dry_steps_impl(mrlbm_ctx *c, int reps, float *ms) {
+  const int cur0 = c->cur, m0 = c->mcur;
+  hipStream_t user = c->stream;
+  const bool prof = c->profiling;
+  c->stream = c->cap_stream;
+  c->profiling = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  // each replay repeats the same adaptation: every level active, as the
+  // activity history would not match the replayed meshes
+  if (e == hipSuccess) activity_reset(c);
+  int rc = e == hipSuccess ? E::adapt(c) : MRLBM_ERR_HIP;
+  c->mcur = m0;
+  if (rc == MRLBM_OK) rc = E::transport(c);
+  c->cur = cur0;
+  if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
+  c->stream = user;
+  c->profiling = prof;
+  if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc != MRLBM_OK) return rc;
+  if (e != hipSuccess) return MRLBM_ERR_HIP;
+  hipEvent_t a = nullptr, b = nullptr;
+  e = timing_event(&a);
+  if (e == hipSuccess) e = timing_event(&b);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipGraphExecDestroy(exec);
+  activity_reset(c);  // the replays left the history of their own meshes
+  if (e != hipSuccess) return MRLBM_ERR_HIP;
+  *ms /= (float)reps;
+  return MRLBM_OK;
+}
+
 // GAM = 1: a batch with gamma = 1 (the kernels that predict take it as a
 // constant); GAM = 0: gamma > 1, read per instance.
 template <int DIM, int SCHEME, typename T, int GAM>
 struct Engine {
+  using Real = T;
   static constexpr int Q = Vel<SCHEME>::Q;
   static constexpr unsigned QB = 64 * Q;
   static constexpr unsigned FB = fused_block<Q>();
@@ -946,62 +1067,7 @@ struct Engine {
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
 
-  // One full step replayed from a HIP graph, one graph per assignment of the
-  // double buffers (a step swaps the mesh buffers and, in the transport, F). With
-  // profiling on, every TIMING_PERIOD-th step replays a graph in which
-  // event-record nodes bracket the transport kernel; before each such launch
-  // they are pointed at two fresh events. (Each event record drains the queue,
-  // some microseconds, so timing every step would slow the steps it measures.)
-  static int step_graph(mrlbm_ctx *c) {
-    const int timed = c->profiling && (c->graph_steps++ % c->timing_period == 0) ? 1 : 0;
-    const int par = c->mcur, key = 2 * c->cur + par;
-    hipGraphExec_t &g = c->graph[timed][key];
-    if (!g) {
-      const int cur0 = c->cur;
-      hipStream_t user = c->stream;
-      const bool prof = c->profiling;
-      c->stream = c->cap_stream;
-      c->profiling = false;
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
-      int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
-      if (rc == MRLBM_OK) reconstruct(c, (T *)c->F[c->cur], c->mcur);
-      if (rc == MRLBM_OK) rc = transport_kernel(c);
-      if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
-      c->stream = user;
-      c->profiling = prof;
-      c->mcur = par;
-      c->cur = cur0;
-      if (rc == MRLBM_OK && e == hipSuccess && timed)
-        e = bracket_last_kernels(graph, c->ev_placeholder, &c->timed_ev[key][0], &c->timed_ev[key][1],
-                                 transport_kernels(c));
-      if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
-      if (rc == MRLBM_OK && e == hipSuccess && timed) {
-        c->timed_src[key] = graph;  // the event nodes belong to it
-        graph = nullptr;
-      }
-      if (graph) (void)hipGraphDestroy(graph);
-      if (rc != MRLBM_OK) return rc;
-      if (e != hipSuccess) { g = nullptr; return MRLBM_ERR_HIP; }
-    }
-    if (timed) {
-      for (int k = 0; k < 2; ++k) {
-        if (c->ev_used + k == c->ev_pool.size()) {
-          hipEvent_t ev;
-          if (timing_event(&ev) != hipSuccess) return MRLBM_ERR_HIP;
-          c->ev_pool.push_back(ev);
-        }
-        if (hipGraphExecEventRecordNodeSetEvent(g, c->timed_ev[key][k], c->ev_pool[c->ev_used + k]) != hipSuccess)
-          return MRLBM_ERR_HIP;
-      }
-      c->ev_marks.push_back({PH_TRANSPORT, c->ev_used});
-      c->ev_used += 2;
-    }
-    if (hipGraphLaunch(g, c->stream) != hipSuccess) return MRLBM_ERR_HIP;
-    c->mcur = 1 - par;    // the adaptation's swap
-    c->cur = 1 - c->cur;  // the transport's swap
-    return MRLBM_OK;
-  }
+  static int step_graph(mrlbm_ctx *c) { return step_graph_impl<Engine>(c); }
 
   static int init(mrlbm_ctx *c, int i, const void *mom) {
     const Plan &P = c->P;
@@ -1210,52 +1276,7 @@ struct Engine {
   }
 
   // ------------------------------------------------------------- autotuning
-  // A step that leaves the state as it was: the adaptation writes the next mesh
-  // buffers and, in the current value buffer, recomputes the values already
-  // there (its reconstruction) or writes cells outside the current mesh (its
-  // transfer); the transport then runs on the current mesh into the other value
-  // buffer. Captured once per schedule and replayed `reps` times between HIP
-  // events.
-  static int time_dry_steps(mrlbm_ctx *c, int reps, float *ms) {
-    const int cur0 = c->cur, m0 = c->mcur;
-    hipStream_t user = c->stream;
-    const bool prof = c->profiling;
-    c->stream = c->cap_stream;
-    c->profiling = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
-    // each replay repeats the same adaptation: every level active, as the
-    // activity history would not match the replayed meshes
-    if (e == hipSuccess) activity_reset(c);
-    int rc = e == hipSuccess ? adapt(c) : MRLBM_ERR_HIP;
-    c->mcur = m0;
-    if (rc == MRLBM_OK) rc = transport(c);
-    c->cur = cur0;
-    if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
-    c->stream = user;
-    c->profiling = prof;
-    if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (rc != MRLBM_OK) return rc;
-    if (e != hipSuccess) return MRLBM_ERR_HIP;
-    hipEvent_t a = nullptr, b = nullptr;
-    e = timing_event(&a);
-    if (e == hipSuccess) e = timing_event(&b);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(b);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-    (void)hipGraphExecDestroy(exec);
-    activity_reset(c);  // the replays left the history of their own meshes
-    if (e != hipSuccess) return MRLBM_ERR_HIP;
-    *ms /= (float)reps;
-    return MRLBM_OK;
-  }
+  static int time_dry_steps(mrlbm_ctx *c, int reps, float *ms) { return time_dry_steps_impl<Engine>(c, reps, ms); }
 
   static int upload_inst(mrlbm_ctx *c) {
     std::vector<Inst<T>> v(c->P.B);
@@ -1277,6 +1298,7 @@ struct Engine {
       d.sc.inv_lam = (T)s.sc.inv_lam;
       d.sc.eq = (T)s.sc.eq;
       for (int k = 0; k < 16; ++k) d.sc.s[k] = (T)s.sc.s[k];
+      for (int k = 0; k < 3; ++k) d.sc.vel[k] = (T)s.sc.vel[k];
       d.walls = s.walls;
       for (int k = 0; k < 4; ++k) d.bck[k] = s.bck[k];
       d.gamma = s.gamma;
@@ -1287,6 +1309,189 @@ struct Engine {
   }
 };
 
+// The three-dimensional engine (D3Q6, gamma = 1, periodic): the same step of
+// Algorithm 1 with the kernels of mr_kernels3d.h. Per step: the old mesh's
+// projections (fine to coarse) and ghost predictions (coarse to fine), the
+// details and their flags, thresholding, ancestor closure, neighbour addition
+// and refinement, grading, the new codes and ghost marks, the lists, the
+// transfer into the cells outside the old mesh, the new mesh's reconstruction,
+// then transport + collision into the other value buffer.
+template <typename T, int GAM>
+struct Engine<3, MRLBM_D3Q6, T, GAM> {
+  using Real = T;
+  static constexpr int DIM = 3, Q = 6;
+
+  static const Inst<T> *I(mrlbm_ctx *c) { return (const Inst<T> *)c->inst; }
+  static int transport_kernels(const mrlbm_ctx *) { return 1; }
+  static unsigned list_blocks(mrlbm_ctx *c) {  // four chunks of 64 items per block
+    return list_grid((c->P.ctotal + 4 * CHUNK - 1) / (4 * CHUNK), c->grid_all);
+  }
+  static unsigned level_list_blocks(mrlbm_ctx *c, int l) {
+    long long n = 0;
+    for (int i = 0; i < c->P.B; ++i)
+      if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (3 * l)) + CHUNK - 1) / CHUNK;
+    return list_grid((n + 3) / 4, c->grid_level);
+  }
+  static dim3 level_grid(mrlbm_ctx *c, int l) {
+    const long long n = 1ll << (3 * l);
+    return dim3((unsigned)((n + BLK * d3::CPT - 1) / (BLK * d3::CPT)), (unsigned)c->P.B);
+  }
+
+  // Lists of mesh m (every level active: the 3D passes keep no activity history).
+  static void compact(mrlbm_ctx *c, int m) {
+    const Plan &P = c->P;
+    k_fill_u32<<<1, BLK, 0, c->stream>>>((uint32_t *)c->act, (long long)ACT * P.B, (uint32_t)ACT_ALL);
+    k_compact_count<3, T><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->bcnt, P.nblocks,
+                                                             c->act, c->ne[m]);
+    k_compact_scan<T><<<P.B, 1024, 0, c->stream>>>(c->bt, I(c), c->cbp, c->bcnt, c->boff, c->lvl[m], P.nblocks,
+                                                   c->act, c->ne[m]);
+    k_compact_scatter<3, Q, T, 1><<<P.nblocks, BLK, 0, c->stream>>>(c->bt, I(c), c->binfo, c->code[m], c->boff,
+                                                                     c->lists[m], P.nblocks, nullptr, nullptr,
+                                                                     nullptr, c->act);
+  }
+
+  // Codes of the membership bytes tnew into code[m], the ghost marks, the lists.
+  static void classify(mrlbm_ctx *c, int m) {
+    const Plan &P = c->P;
+    d3::k3_classify<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->tnew, c->code[m]);
+    d3::k3_ghost_leaf<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[m]);
+    for (int l = P.maxJ; l > P.jmin; --l) d3::k3_ghost_up<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->code[m], l);
+    compact(c, m);
+  }
+
+  // Reconstruction of mesh m in F: projections fine to coarse, ghost
+  // predictions coarse to fine.
+  static void reconstruct(mrlbm_ctx *c, T *F, int m) {
+    const Plan &P = c->P;
+    const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
+    const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
+    for (int l = P.maxJ - 1; l >= P.jmin; --l)
+      d3::k3_project<T><<<level_list_blocks(c, l), BLK, 0, c->stream>>>(c->bt, I(c), F, li, c->lvl[m], l);
+    for (int l = P.jmin + 1; l <= P.maxJ; ++l)
+      d3::k3_ghost<T><<<level_list_blocks(c, l), BLK, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
+  }
+
+  static int adapt(mrlbm_ctx *c) {
+    const Plan &P = c->P;
+    const int mo = c->mcur, mn = 1 - c->mcur;
+    T *Fc = (T *)c->F[c->cur];
+    phase_mark(c, PH_ADAPT, true);
+    reconstruct(c, Fc, mo);  // the details read the tree, the transfer the ghosts
+    const uint32_t *li = c->lists[mo] + (size_t)CAT_INTERNAL * P.ctotal;
+    auto det = P.metric_mode == 0 ? d3::k3_details<T, 0> : P.metric_mode == 1 ? d3::k3_details<T, 1> : d3::k3_details<T, 2>;
+    det<<<list_blocks(c), BLK, 0, c->stream>>>(c->bt, I(c), Fc, li, c->lvl[mo], c->refg);
+    d3::k3_keep<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[mo], c->refg, c->keep, c->tnew);
+    for (int l = P.maxJ; l >= P.jmin + 2; --l) d3::k3_closure<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->keep, l);
+    d3::k3_enlarge<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->keep, c->refg, c->tnew);
+    for (int l = P.maxJ; l >= P.jmin + 1; --l) d3::k3_grade<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->tnew, l);
+    classify(c, mn);
+    // the transfer: new leaves outside the old mesh are predicted from their
+    // parent's level, whose stencil the old mesh's ghosts cover
+    d3::k3_transfer<T><<<list_blocks(c), BLK, 0, c->stream>>>(c->bt, I(c), Fc,
+                                                              c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn],
+                                                              c->code[mo]);
+    phase_mark(c, PH_ADAPT, false);
+    c->mcur = mn;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int transport(mrlbm_ctx *c, T * = nullptr) {
+    phase_mark(c, PH_RECON, true);
+    reconstruct(c, (T *)c->F[c->cur], c->mcur);
+    phase_mark(c, PH_RECON, false);
+    return transport_kernel(c);
+  }
+
+  static int transport_kernel(mrlbm_ctx *c) {
+    const Plan &P = c->P;
+    const int m = c->mcur;
+    phase_mark(c, PH_TRANSPORT, true);
+    d3::k3_transport_collide<T><<<list_blocks(c), BLK, 0, c->stream>>>(
+        c->bt, I(c), (const T *)c->F[c->cur], (T *)c->F[1 - c->cur], c->code[m],
+        c->lists[m] + (size_t)CAT_LEAF * P.ctotal, c->lvl[m], (const T *)c->W, (const T *)c->C, c->cnt);
+    phase_mark(c, PH_TRANSPORT, false);
+    c->cur = 1 - c->cur;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int step_graph(mrlbm_ctx *c) { return step_graph_impl<Engine>(c); }
+  static int time_dry_steps(mrlbm_ctx *c, int reps, float *ms) { return time_dry_steps_impl<Engine>(c, reps, ms); }
+
+  static int init(mrlbm_ctx *c, int i, const void *mom) {
+    const Plan &P = c->P;
+    T *F = (T *)c->F[c->cur];
+    const long long nf = 1ll << (3 * P.inst[i].jmax);
+    k_init_equilibrium<3, MRLBM_D3Q6, T><<<grid_cap((nf + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        I(c), i, F, (const T *)mom);
+    k_full_tree<T><<<grid_cap((P.inst[i].total + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(I(c), i,
+                                                                                                  c->code[c->mcur]);
+    compact(c, c->mcur);
+    c->has_state[i] = 1;
+    c->recon_reuse = false;
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int mass(mrlbm_ctx *c) {
+    k_mass_partial<3, Q, T><<<dim3(RED_BLOCKS, c->P.B), BLK, 0, c->stream>>>(
+        c->bt, I(c), (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal, c->lvl[c->mcur],
+        c->red, c->bad);
+    return MRLBM_OK;
+  }
+
+  static int exportl(mrlbm_ctx *c, int i, uint32_t *cells, void *vals) {
+    k_export<3, Q, T><<<grid_cap((c->P.inst[i].total + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+        I(c), i, (const T *)c->F[c->cur], c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal, c->lvl[c->mcur], cells,
+        (T *)vals);
+    return MRLBM_OK;
+  }
+
+  static int leaf_fields(mrlbm_ctx *c, int i, int what, void *out) {
+    const long long n = c->P.inst[i].total;
+    const unsigned g = grid_cap((n + BLK - 1) / BLK, DENSE_GRID);
+    const uint32_t *lf = c->lists[c->mcur] + (size_t)CAT_LEAF * c->P.ctotal;
+    if (what == MRLBM_FIELD_MOMENTS)
+      k_moments<3, MRLBM_D3Q6, T><<<g, BLK, 0, c->stream>>>(I(c), i, (const T *)c->F[c->cur], lf, c->lvl[c->mcur],
+                                                             (T *)out);
+    else
+      k_export<3, Q, T><<<g, BLK, 0, c->stream>>>(I(c), i, (const T *)c->F[c->cur], lf, c->lvl[c->mcur],
+                                                  what == MRLBM_FIELD_LEAF_TABLE ? (uint32_t *)out : nullptr,
+                                                  what == MRLBM_FIELD_POPULATIONS ? (T *)out : nullptr);
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  // The double-hat reconstruction on the finest level: the mesh's
+  // reconstruction, then every other cell outside the tree, level by level.
+  static int finest(mrlbm_ctx *c, int i, void *out) {
+    const Inst<double> &In = c->P.inst[i];
+    T *F = (T *)c->F[c->cur];
+    reconstruct(c, F, c->mcur);
+    for (int l = In.jmin + 1; l <= In.jmax; ++l)
+      d3::k3_predict_outside<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), F, c->code[c->mcur], l);
+    const size_t bytes = sizeof(T) * Q * ((size_t)1 << (3 * In.jmax));
+    HIPCHK(hipMemcpyAsync(out, F + (size_t)Q * In.loff[In.jmax], bytes, hipMemcpyDeviceToDevice, c->stream));
+    return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+  }
+
+  static int frozen(mrlbm_ctx *c, const uint8_t *trees) {
+    const Plan &P = c->P;
+    const int mo = c->mcur, mn = 1 - mo;
+    T *Fc = (T *)c->F[c->cur];
+    reconstruct(c, Fc, mo);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->tnew, trees, P.ctotal, hipMemcpyHostToDevice));
+    classify(c, mn);
+    d3::k3_transfer<T><<<list_blocks(c), BLK, 0, c->stream>>>(c->bt, I(c), Fc,
+                                                              c->lists[mn] + (size_t)CAT_LEAF * P.ctotal, c->lvl[mn],
+                                                              c->code[mo]);
+    c->mcur = mn;
+    return transport(c);
+  }
+
+  static int upload_inst(mrlbm_ctx *c) { return Engine<2, MRLBM_D2Q9, T, 1>::upload_inst(c); }
+  static int record(mrlbm_ctx *, int, int) { return MRLBM_ERR_INVALID; }
+  static int adjoint(mrlbm_ctx *, const void *, void *, double *) { return MRLBM_ERR_INVALID; }
+};
+
 template <template <int, int, typename, int> class Op, int G, typename... A>
 int dispatch_g(mrlbm_ctx *c, A... a) {
   const bool dbl = c->p[0].precision == 8;
@@ -1294,6 +1499,9 @@ int dispatch_g(mrlbm_ctx *c, A... a) {
     case MRLBM_D1Q2: return dbl ? Op<1, 1, double, G>::run(c, a...) : Op<1, 1, float, G>::run(c, a...);
     case MRLBM_D1Q3: return dbl ? Op<1, 2, double, G>::run(c, a...) : Op<1, 2, float, G>::run(c, a...);
     case MRLBM_D2Q4_EULER: return dbl ? Op<2, 4, double, G>::run(c, a...) : Op<2, 4, float, G>::run(c, a...);
+    case MRLBM_D3Q6:
+      if constexpr (G == 1) return dbl ? Op<3, 5, double, 1>::run(c, a...) : Op<3, 5, float, 1>::run(c, a...);
+      else return MRLBM_ERR_INVALID;  // validation admits gamma = 1 only
     default: return dbl ? Op<2, 3, double, G>::run(c, a...) : Op<2, 3, float, G>::run(c, a...);
   }
 }
@@ -1329,18 +1537,18 @@ template <int D, int S, typename T, int G>
 struct FrozenOp { static int run(mrlbm_ctx *c, const uint8_t *t) { return Engine<D, S, T, G>::frozen(c, t); } };
 template <int D, int S, typename T, int G>
 struct UploadOp { static int run(mrlbm_ctx *c) { return Engine<D, S, T, G>::upload_inst(c); } };
-// The adjoint covers gamma = 1 and the schemes with one to three conserved moments.
+// The adjoint covers gamma = 1 and the schemes D1Q2, D1Q3 and D2Q9.
 template <int D, int S, typename T, int G>
 struct RecordOp {
   static int run(mrlbm_ctx *c, int n, int K) {
-    if constexpr (G == 1 && S != MRLBM_D2Q4_EULER) return Engine<D, S, T, G>::record(c, n, K);
+    if constexpr (G == 1 && S <= MRLBM_D2Q9) return Engine<D, S, T, G>::record(c, n, K);
     else return MRLBM_ERR_INVALID;
   }
 };
 template <int D, int S, typename T, int G>
 struct AdjointOp {
   static int run(mrlbm_ctx *c, const void *a, void *mb, double *sb) {
-    if constexpr (G == 1 && S != MRLBM_D2Q4_EULER) return Engine<D, S, T, G>::adjoint(c, a, mb, sb);
+    if constexpr (G == 1 && S <= MRLBM_D2Q9) return Engine<D, S, T, G>::adjoint(c, a, mb, sb);
     else return MRLBM_ERR_INVALID;
   }
 };
@@ -1351,30 +1559,32 @@ bool tree_is_graded(const mrlbm_ctx *c, int inst, const uint8_t *t) {
   const Inst<double> &I = c->P.inst[inst];
   const int d = c->P.dim;
   auto at = [&](int l, long long k) { return t[I.loff[l] - I.cbase + k]; };
+  // cell (x, y, z) of level l (coordinates beyond the dimension are 0)
+  auto idx = [&](int l, long long x, long long y, long long z) { return x + ((y + (z << l)) << l); };
   for (long long k = 0; k < (1ll << (d * I.jmin)); ++k)
     if (!at(I.jmin, k)) return false;
+  const int g = I.gamma;  // grading box of half-width gamma
+  const int gy = d >= 2 ? g : 0, gz = d == 3 ? g : 0;
   for (int l = I.jmin + 1; l <= I.jmax; ++l) {
     const int np = 1 << (l - 1);
-    for (int py = 0; py < (d == 2 ? np : 1); ++py)
-      for (int px = 0; px < np; ++px) {
-        int cnt = 0;
-        for (int dy = 0; dy < (d == 2 ? 2 : 1); ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
-            const long long ci = d == 2 ? (long long)(2 * px + dx) + ((long long)(2 * py + dy) << l) : 2 * px + dx;
-            cnt += at(l, ci) ? 1 : 0;
-          }
-        if (cnt == 0) continue;
-        if (cnt != (1 << d)) return false;
-        const int g = I.gamma;  // grading box of half-width gamma
-        for (int b = (d == 2 ? -g : 0); b <= (d == 2 ? g : 0); ++b)
-          for (int a = -g; a <= g; ++a) {
-            if (((I.walls & 1) && (px + a < 0 || px + a >= np)) || ((I.walls & 2) && (py + b < 0 || py + b >= np)))
-              continue;  // no cell beyond a wall
-            const int x = (px + a) & (np - 1), y = (py + b) & (np - 1);
-            const long long pi = d == 2 ? (long long)x + ((long long)y << (l - 1)) : x;
-            if (!at(l - 1, pi)) return false;
-          }
-      }
+    for (int pz = 0; pz < (d == 3 ? np : 1); ++pz)
+      for (int py = 0; py < (d >= 2 ? np : 1); ++py)
+        for (int px = 0; px < np; ++px) {
+          int cnt = 0;
+          for (int dz = 0; dz < (d == 3 ? 2 : 1); ++dz)
+            for (int dy = 0; dy < (d >= 2 ? 2 : 1); ++dy)
+              for (int dx = 0; dx < 2; ++dx) cnt += at(l, idx(l, 2 * px + dx, 2 * py + dy, 2 * pz + dz)) ? 1 : 0;
+          if (cnt == 0) continue;
+          if (cnt != (1 << d)) return false;
+          for (int e = -gz; e <= gz; ++e)
+            for (int b = -gy; b <= gy; ++b)
+              for (int a = -g; a <= g; ++a) {
+                if (((I.walls & 1) && (px + a < 0 || px + a >= np)) || ((I.walls & 2) && (py + b < 0 || py + b >= np)))
+                  continue;  // no cell beyond a wall
+                const int x = (px + a) & (np - 1), y = (py + b) & (np - 1), z = (pz + e) & (np - 1);
+                if (!at(l - 1, idx(l - 1, x, y, z))) return false;
+              }
+        }
   }
   return true;
 }
@@ -1388,10 +1598,11 @@ bool refines_by_one(const mrlbm_ctx *c, int inst, const uint8_t *old, const uint
   const int d = c->P.dim;
   for (int l = I.jmin + 1; l <= I.jmax; ++l) {
     const long long n = 1ll << (d * l), o = I.loff[l] - I.cbase, op = I.loff[l - 1] - I.cbase;
+    const long long m = (1ll << l) - 1;
     for (long long k = 0; k < n; ++k) {
       if (!t[o + k] || old[o + k]) continue;
-      const long long x = d == 2 ? (k & ((1ll << l) - 1)) : k, y = d == 2 ? (k >> l) : 0;
-      const long long pk = d == 2 ? (x >> 1) + ((y >> 1) << (l - 1)) : (x >> 1);
+      const long long x = k & m, y = (k >> l) & m, z = k >> (2 * l);
+      const long long pk = (x >> 1) + (((y >> 1) + ((z >> 1) << (l - 1))) << (l - 1));
       if (!old[op + pk]) return false;
     }
   }
@@ -1560,11 +1771,13 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   // (gamma = 1: the fast kernels' periodic tables; unused for gamma > 1)
   std::vector<double> W((size_t)nn * q * ws, 0.0), C((size_t)nn * q * cs, 0.0), w25(q * 25), c36(q * 36);
   ImpulseSums imp1(1);
+  const bool d3q6 = p[0].scheme == MRLBM_D3Q6;  // the D1Q2 rows of the velocity's sign (see mr_kernels3d.h)
   for (int n = 1; n <= P.nmax && P.gamma == 1; ++n) {
-    transport_tables(p[0].scheme, n, w25.data(), c36.data(), 0, 0, nullptr, 1, &imp1);
+    transport_tables(d3q6 ? MRLBM_D1Q2 : p[0].scheme, n, w25.data(), c36.data(), 0, 0, nullptr, 1, &imp1);
     for (int h = 0; h < q; ++h) {
-      for (int k = 0; k < ws; ++k) W[((size_t)(n - 1) * q + h) * ws + k] = d == 2 ? w25[h * 25 + k] : w25[h * 25 + 10 + k];
-      for (int k = 0; k < cs; ++k) C[((size_t)(n - 1) * q + h) * cs + k] = d == 2 ? c36[h * 36 + k] : c36[h * 36 + 12 + k];
+      const int hs = d3q6 ? (h & 1) : h;
+      for (int k = 0; k < ws; ++k) W[((size_t)(n - 1) * q + h) * ws + k] = d == 2 ? w25[hs * 25 + k] : w25[hs * 25 + 10 + k];
+      for (int k = 0; k < cs; ++k) C[((size_t)(n - 1) * q + h) * cs + k] = d == 2 ? c36[hs * 36 + k] : c36[hs * 36 + 12 + k];
     }
   }
   // the general path's tables, per wall case (index wx + 3 wy; case 0: no wall
@@ -1872,7 +2085,7 @@ int mrlbm_adjoint_workspace_size(const mrlbm_ctx *c, int nsteps, int ckpt_every,
 int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every) {
   if (!c || !adj_workspace || nsteps < 1 || ckpt_every < 1 || c->P.B != 1) return MRLBM_ERR_INVALID;
   if (c->P.inst[0].walls) return MRLBM_ERR_INVALID;  // the adjoint covers periodic boundaries
-  if (c->p[0].scheme == MRLBM_D2Q4_EULER || c->P.gamma > 1) return MRLBM_ERR_INVALID;
+  if (c->p[0].scheme == MRLBM_D2Q4_EULER || c->p[0].scheme == MRLBM_D3Q6 || c->P.gamma > 1) return MRLBM_ERR_INVALID;
   if (!c->all_ready()) return MRLBM_ERR_STATE;
   if (bytes < adj_layout(c->P, nsteps, ckpt_every).bytes) return MRLBM_ERR_CAPACITY;
   c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);

@@ -16,7 +16,7 @@ from .workloads import SCHEME_DIMS
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmrlbm.so")
 
-SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3, "D2Q4E": 4}
+SCHEME_IDS = {"D1Q2": 1, "D1Q3": 2, "D2Q9": 3, "D2Q4E": 4, "D3Q6": 5}
 METRIC_IDS = {"linf": 0, "l2": 1}  # sibling metric of the details: max norm, or its l2 form
 STATUS = {0: "ok", -1: "invalid argument", -2: "buffer too small", -3: "non-finite leaf value",
           -4: "HIP runtime error", -5: "call out of order", -6: "device-side wait gave up"}
@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("lam", ctypes.c_double), ("eq_param", ctypes.c_double),
                 ("eps", ctypes.c_double), ("mu_bar", ctypes.c_double), ("s", ctypes.c_double * 16),
-                ("bc", ctypes.c_int * 4), ("gamma", ctypes.c_int), ("metric", ctypes.c_int)]
+                ("bc", ctypes.c_int * 4), ("gamma", ctypes.c_int), ("metric", ctypes.c_int),
+                ("velocity", ctypes.c_double * 3)]
 
     @classmethod
     def from_cfg(cls, cfg: dict, precision: int = 8) -> "Params":
@@ -51,7 +52,8 @@ class Params(ctypes.Structure):
         return cls(SCHEME_IDS[cfg["scheme"]], int(cfg["jmin"]), int(cfg["jmax"]), int(precision),
                    float(cfg.get("lam", 1.0)), float(cfg.get("eq_param", 0.0)), float(cfg["eps"]),
                    float(cfg.get("mu_bar", 0.0)), (ctypes.c_double * 16)(*s), (ctypes.c_int * 4)(*bc),
-                   int(cfg.get("gamma", 1)), METRIC_IDS[cfg.get("metric", "linf")])
+                   int(cfg.get("gamma", 1)), METRIC_IDS[cfg.get("metric", "linf")],
+                   (ctypes.c_double * 3)(*[float(v) for v in cfg.get("velocity", (0.0, 0.0, 0.0))]))
 
 
 class Counters(ctypes.Structure):

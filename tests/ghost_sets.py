@@ -24,9 +24,10 @@ def _dilate(m: np.ndarray, r: int) -> np.ndarray:
 
 def _parents(m: np.ndarray) -> np.ndarray:
     """Cells of the coarser level with at least one child in m."""
-    if m.ndim == 1:
-        return m[0::2] | m[1::2]
-    return m[0::2, 0::2] | m[1::2, 0::2] | m[0::2, 1::2] | m[1::2, 1::2]
+    out = np.zeros(tuple(n // 2 for n in m.shape), bool)
+    for off in np.ndindex(*([2] * m.ndim)):
+        out |= m[tuple(slice(o, None, 2) for o in off)]
+    return out
 
 
 def _children(m: np.ndarray) -> np.ndarray:
@@ -55,6 +56,31 @@ def ghost_sets(o, tree, gamma=1):
         need = _dilate(S[l], 2 * gamma)
         if l < o.jmax:
             need |= _dilate(_parents(G[l + 1]), gamma)
+        G[l] = need & ~T[l]
+    return G
+
+
+def _axis_rows(m: np.ndarray, r: int) -> np.ndarray:
+    """m and its shifts by up to r cells along each axis separately."""
+    out = m.copy()
+    for ax in range(m.ndim):
+        for d in range(1, r + 1):
+            out |= np.roll(m, d, axis=ax) | np.roll(m, -d, axis=ax)
+    return out
+
+
+def ghost_sets_3d(o, tree):
+    """The ghosts of the three-dimensional (D3Q6) path, per level l > jmin: the
+    cells outside the tree in the 3^3 box of a leaf of level l (the parent
+    stencil of a child the next adaptation may create there) or in its rows
+    of +-2 cells along the axes (its transport: each velocity lies along one
+    axis), or in the 3^3 box of the parent of a ghost of level l+1."""
+    T, S, _ = tree_sets(o, tree)
+    G = {}
+    for l in range(o.jmax, o.jmin, -1):
+        need = _dilate(S[l], 1) | _axis_rows(S[l], 2)
+        if l < o.jmax:
+            need |= _dilate(_parents(G[l + 1]), 1)
         G[l] = need & ~T[l]
     return G
 

@@ -35,12 +35,12 @@ int main() {
   std::mt19937_64 gen(7);
   // parameter checks and plans over a sweep of valid and invalid sets
   int ok = 0;
-  for (int scheme = 0; scheme <= 5; ++scheme)
+  for (int scheme = 0; scheme <= 6; ++scheme)
     for (int jmin = 0; jmin <= 4; ++jmin)
       for (int jmax : {jmin, jmin + 3, 13, 14, 25, 26})
         for (int g = 0; g <= 4; ++g)
           for (int walls = 0; walls < 3; ++walls) {
-            if (scheme < 1 || scheme > 4) {
+            if (scheme < 1 || scheme > 5) {
               mrlbm_params p = base(1, 2, 5);
               p.scheme = scheme;
               size_t b = 0;
@@ -51,9 +51,12 @@ int main() {
             p.gamma = g;
             p.metric = walls == 2 ? MRLBM_METRIC_L2 : MRLBM_METRIC_MAX;
             if (walls) p.bc[0] = p.bc[1] = MRLBM_BOUNCE_BACK;
+            if (scheme == MRLBM_D3Q6) p.velocity[0] = 0.3;
             size_t b = 0;
             const int rc = mrlbm_workspace_size(&p, 1, &b);
             EXPECT(rc == MRLBM_OK || rc == MRLBM_ERR_INVALID);
+            if (scheme == MRLBM_D3Q6)  // 3D: periodic, gamma = 1, jmax <= 8
+              EXPECT((rc == MRLBM_OK) == (jmin >= 1 && jmax <= 8 && g <= 1 && walls == 0));
             if (rc == MRLBM_OK) {
               ++ok;
               EXPECT(b > 0);

@@ -69,6 +69,27 @@ def test_workspace_size_and_parameter_validation():
     assert mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)) == -1
 
 
+def test_3d_parameter_validation():
+    def ws(**kw):
+        cfg = W.params("D3Q6", 2, 6, 1e-3, W.d3q6_s(), mu_bar=2.0, velocity=(0.3, 0.2, 0.1))
+        cfg.update(kw)
+        p = mrlbm.Params.from_cfg(cfg, 8)
+        n = ctypes.c_size_t(0)
+        return mrlbm.lib().mrlbm_workspace_size(ctypes.byref(p), 1, ctypes.byref(n)), n.value
+
+    rc, n = ws()
+    assert rc == 0 and n > 2 * 6 * 8 * sum(8 ** l for l in range(2, 7))
+    assert ws(jmax=8)[0] == 0
+    assert ws(jmax=9)[0] == -1                # 8^9 cells do not fit a 26-bit list entry
+    assert ws(gamma=2)[0] == -1               # gamma = 1 only
+    assert ws(metric="l2")[0] == 0
+    assert ws(bc=(2, 2, 0, 0))[0] == -1       # periodic only
+    assert ws(velocity=(float("nan"), 0.0, 0.0))[0] == -1
+    assert ws(s=[0.5, 1.4, 1.4, 1.4, 1.0, 1.0])[0] == -1  # the conserved moment must not relax
+    W_, C_ = np.zeros((6, 25)), np.zeros((6, 36))
+    assert mrlbm.lib().mrlbm_transport_tables(5, 2, W_.ctypes.data, C_.ctypes.data) == -1  # no 3D table
+
+
 def test_batch_validation():
     a = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 7, 1e-3, W.d2q9_s(1.5, 1.8)), 4)
     b = mrlbm.Params.from_cfg(W.params("D2Q9", 3, 9, 1e-4, W.d2q9_s(1.5, 1.9)), 4)

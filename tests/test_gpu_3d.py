@@ -1,0 +1,211 @@
+"""The three-dimensional path (D3Q6 advection, section "Three dimensional
+advection equation"; the d = 3 prediction of section "Projection and prediction
+operators") on the GPU, through the C-ABI, against the oracle.
+
+One-step replays as in test_gpu_parity: from the GPU state before a step, the
+oracle's step (FP64; FP32: the oracle's float mesh decision, then its FP64 step
+from the upcast state) must give the GPU's mesh bit for bit and its leaf values
+within 1e-12 (FP64) or 1e-5 (FP32) relative. Also: the ghost sets against their
+definition, the finest-level reconstruction, the uniform limit, mass
+conservation, batches, set_state and the frozen-mesh step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02903_amd import workloads as W
+
+from test_gpu_parity import TOL64, leaf_err
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_02903_amd import mrlbm
+
+    mrlbm.lib()
+    return mrlbm
+
+
+def _cfg(jmin, jmax, eps, mu_bar=1.0, metric="linf", vel=(0.3, 0.2, 0.1)):
+    return W.params("D3Q6", jmin, jmax, eps, W.d3q6_s(1.4, 1.0), mu_bar=mu_bar, lam=1.0, metric=metric,
+                    velocity=vel)
+
+
+def _replay(mr, o, sim, steps, precision):
+    levels = set()
+    for k in range(steps):
+        tg, vg = sim.get_state()
+        t_o, v_o = tg.copy(), vg.astype(np.float64)
+        if precision == 8:
+            o.step(t_o, v_o)
+        else:
+            o.step_frozen(t_o, o.new_tree_f32(tg, vg), v_o)
+        sim.step(1)
+        tg2, vg2 = sim.get_state()
+        assert np.array_equal(tg2, t_o), "mesh differs at step %d" % (k + 1)
+        assert o.check_tree(tg2) == 0
+        e = leaf_err(o, t_o, vg2, v_o)
+        assert e <= (TOL64 if precision == 8 else TOL32), "field error %g at step %d" % (e, k + 1)
+        levels |= {l for l, c in enumerate(o.leaf_counts(tg2)) if c}
+    return levels
+
+
+CASES = [
+    # kind, jmin, jmax, eps, mu_bar, metric, seed, steps
+    ("ball", 2, 5, 1e-3, 2.0, "linf", 0, 12),
+    ("ball", 1, 6, 1e-3, 2.0, "l2", 0, 8),
+    ("jump", 2, 5, 1e-2, 1.0, "linf", 3, 8),
+    ("jump", 2, 5, 3e-2, 1.0, "l2", 4, 8),
+]
+
+
+@pytest.mark.parametrize("kind,jmin,jmax,eps,mu_bar,metric,seed,steps", CASES)
+@pytest.mark.parametrize("precision", [8, 4])
+def test_d3q6_step_replay(mr, kind, jmin, jmax, eps, mu_bar, metric, seed, steps, precision):
+    if kind == "ball":
+        cfg, m0 = W.ball_d3q6(jmin=jmin, jmax=jmax, eps=eps, mu_bar=mu_bar, metric=metric)
+    else:
+        cfg = _cfg(jmin, jmax, eps, mu_bar, metric)
+        m0 = W.random_field(cfg, seed, "jump")
+    print("d3q6", kind, jmin, jmax, eps, metric, "precision", precision, flush=True)
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    if precision == 8:
+        t0, v0 = o.init(m0)
+        tg, vg = sim.get_state()
+        assert np.array_equal(tg, t0) and leaf_err(o, t0, vg, v0) <= TOL64
+    levels = _replay(mr, o, sim, steps, precision)
+    assert len(levels) >= 2
+    if precision == 8:
+        fin = sim.fields("finest").cpu().numpy()
+        tg, vg = sim.get_state()
+        want = o.finest(tg, vg).reshape(o.q, -1)
+        assert np.max(np.abs(fin - want)) <= 1e-12 * max(1.0, float(np.max(np.abs(want))))
+    sim.close()
+
+
+def test_d3q6_ghost_sets_match_definition(mr):
+    from ghost_sets import ghost_sets_3d
+
+    cfg, m0 = W.ball_d3q6(jmin=2, jmax=6)
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    seen = 0
+    for k in range(4):
+        sim.step(2)
+        tree, _ = sim.get_state()
+        G = ghost_sets_3d(o, tree)
+        want = np.array([int(G[l].sum()) if l in G else 0 for l in range(o.jmax + 1)])
+        got = sim.stats()["ghosts"]
+        assert np.array_equal(got, want), "after %d steps: %s vs %s" % (2 * k + 2, got, want)
+        leaves = np.array(o.leaf_counts(tree))
+        assert np.array_equal(sim.stats()["leaves"], leaves)
+        seen += int(want.sum())
+    assert seen > 0
+    sim.close()
+
+
+def test_d3q6_uniform_limit_and_mass(mr):
+    """eps = 0 keeps the full finest mesh: the step is the reference scheme on
+    level J (the oracle's uniform step), and the mass is conserved."""
+    cfg = _cfg(2, 5, 0.0)
+    m0 = W.random_field(cfg, 8, "jump")
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    t0, v0 = o.init(m0)
+    fJ = o.values_level(v0, o.jmax).reshape(o.q, -1).copy()
+    mass0 = sim.stats()["mass"]
+    for _ in range(6):
+        sim.step(1)
+        o.uniform_step(fJ)
+    tg, vg = sim.get_state()
+    assert o.leaf_counts(tg)[o.jmax] == o.ncells(o.jmax)
+    got = o.values_level(vg, o.jmax).reshape(o.q, -1)
+    assert np.max(np.abs(got - fJ)) <= 1e-13
+    assert abs(sim.stats()["mass"] - mass0) <= 1e-12 * abs(mass0)
+    sim.close()
+
+
+def test_d3q6_mass_conserved_adaptive(mr):
+    cfg, m0 = W.ball_d3q6(jmin=2, jmax=6)
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    mass0 = sim.stats()["mass"]
+    sim.step(20)
+    assert abs(sim.stats()["mass"] - mass0) <= 1e-12 * abs(mass0)
+    sim.close()
+
+
+def test_d3q6_batch_of_instances(mr):
+    """A batch shares jmin; each instance keeps its own J, threshold, metric and
+    velocity, and every instance's step replays on the oracle."""
+    cfgs = [W.ball_d3q6(jmin=2, jmax=5)[0], _cfg(2, 4, 1e-2, metric="l2", vel=(-0.2, 0.1, 0.25)),
+            W.ball_d3q6(jmin=2, jmax=6, eps=3e-3)[0]]
+    m0s = [W.ball_d3q6(jmin=2, jmax=5)[1], W.random_field(cfgs[1], 5, "jump"), W.ball_d3q6(jmin=2, jmax=6)[1]]
+    bat = mr.Batch(cfgs, precision=8)
+    for i, m in enumerate(m0s):
+        bat.init_equilibrium(i, m)
+    oracles = [oracle.Oracle(c) for c in cfgs]
+    for k in range(5):
+        pre = [bat.get_state(i) for i in range(len(cfgs))]
+        bat.step(1)
+        for i, o in enumerate(oracles):
+            t_o, v_o = pre[i][0].copy(), pre[i][1].astype(np.float64)
+            o.step(t_o, v_o)
+            tg, vg = bat.get_state(i)
+            assert np.array_equal(tg, t_o), "instance %d mesh differs at step %d" % (i, k)
+            assert leaf_err(o, t_o, vg, v_o) <= TOL64
+    bat.close()
+
+
+def test_d3q6_set_state_and_frozen_step(mr):
+    """A state set from the oracle steps like the oracle; a frozen step on the
+    oracle's next mesh equals the oracle's frozen step."""
+    cfg, m0 = W.ball_d3q6(jmin=2, jmax=5)
+    o = oracle.Oracle(cfg)
+    t, v = o.init(m0)
+    o.step(t, v, 3)
+    sim = mr.Sim(cfg, precision=8)
+    sim.init_equilibrium(m0)
+    sim.set_state(t, v)
+    tg, vg = sim.get_state()
+    assert np.array_equal(tg, t)
+    tnext = o.new_tree_from_state(t, v)
+    t2, v2 = t.copy(), v.copy()
+    o.step_frozen(t2, tnext, v2)
+    sim.step_frozen(tnext)
+    tg, vg = sim.get_state()
+    assert np.array_equal(tg, t2) and leaf_err(o, t2, vg, v2) <= TOL64
+    sim.step(1)
+    o.step(t2, v2)
+    tg, vg = sim.get_state()
+    assert np.array_equal(tg, t2) and leaf_err(o, t2, vg, v2) <= TOL64
+    sim.close()
+
+
+def test_d3q6_refuses_walls_gamma_and_adjoint(mr):
+    cfg = _cfg(2, 4, 1e-3)
+    cfg["bc"] = (2, 2, 0, 0)
+    with pytest.raises(mr.MrlbmError):
+        mr.Sim(cfg)
+    cfg = _cfg(2, 4, 1e-3)
+    cfg["gamma"] = 2
+    with pytest.raises(mr.MrlbmError):
+        mr.Sim(cfg)
+    sim = mr.Sim(_cfg(2, 4, 1e-3))
+    sim.init_equilibrium(W.random_field(_cfg(2, 4, 1e-3), 1))
+    with pytest.raises(mr.MrlbmError) as e:
+        sim.forward_record(4, 2)
+    assert e.value.status == -1
+    sim.close()
