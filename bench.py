@@ -15,7 +15,7 @@ sample.
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision 8|4]
   python bench.py --copy-calibration     (plain copy kernel of known size only)
   python bench.py --adjoint-only 4       (the adjoint leg only, 4 or 8: for a kernel trace)
-  python bench.py --scope-only [NAME]    (the walls, gamma, l2 and Euler workloads only)
+  python bench.py --scope-only [NAME]    (the walls, gamma, l2, Euler and 3D workloads only)
 """
 from __future__ import annotations
 
@@ -239,7 +239,8 @@ def timed_run(items, precision, steps, warmup, keep_state_of=None, tune=True, sc
                compression_rate_mean=1.0 - leaf_updates / max(1, steps) / finest,
                mass_final=sum(st["mass"] for st in stats),
                tuning=tuning,
-               transport_kernel="k_transport_collide_%s" % ("leaf" if tuning["transport_variant"] == 1 else "pop"),
+               transport_kernel=("k3_transport_collide" if d == 3 else
+                                 "k_transport_collide_%s" % ("leaf" if tuning["transport_variant"] == 1 else "pop")),
                final_leaves_by_levels_above_finest={str(k): by_n[k] for k in sorted(by_n)})
     return res, sim, state0
 
@@ -394,6 +395,10 @@ def scope_row_workloads():
          "3..10 (1024^2 finest), eps 1e-3", 4),
         ("euler_d2q4_riemann_1024_fp64", [W.riemann_d2q4e(jmin=3, jmax=10, eps=1e-3, seed=0)],
          "the same Euler run in FP64", 8),
+        ("d3q6_ball_256_fp32", [W.ball_d3q6()],
+         "D3Q6 advection of a ball indicator (radius 0.15, periodic [-1, 1]^3, V = (0.3, 0.2, 0.1)), levels "
+         "1..8 (256^3 finest), mu_bar 2, eps 1e-3, s = (1.4, 1)", 4),
+        ("d3q6_ball_256_fp64", [W.ball_d3q6()], "the same 3D run in FP64", 8),
     ]
 
 

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libmrlbm.so")
 SOURCES = [os.path.join(PKG, "csrc", "mrlbm.hip")]
-DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("mr_device.h", "mr_kernels.h", "mr_adjoint.h")] + [
+DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("mr_device.h", "mr_kernels.h", "mr_kernels3d.h", "mr_adjoint.h")] + [
     os.path.join(ROOT, "include", "mrlbm.h")]
 
 HIPCC_FLAGS = [

@@ -460,6 +460,9 @@ __device__ __forceinline__ Run16 ld16(const uint8_t *__restrict__ p, long long c
   if (vec) {
     const uint4 v = *reinterpret_cast<const uint4 *>(p + c0);
     r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+  } else if (c0 + 16 <= nl && (((uintptr_t)(p + c0)) & 7u) == 0) {  // two 8-byte halves (3D levels)
+    const uint2 a = *reinterpret_cast<const uint2 *>(p + c0), b = *reinterpret_cast<const uint2 *>(p + c0 + 8);
+    r.w[0] = a.x; r.w[1] = a.y; r.w[2] = b.x; r.w[3] = b.y;
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) r.w[k] = 0;

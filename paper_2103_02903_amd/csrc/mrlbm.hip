@@ -1332,9 +1332,13 @@ struct Engine<3, MRLBM_D3Q6, T, GAM> {
       if (l >= c->P.jmin && l <= c->P.inst[i].jmax) n += ((1ll << (3 * l)) + CHUNK - 1) / CHUNK;
     return list_grid((n + 3) / 4, c->grid_level);
   }
-  static dim3 level_grid(mrlbm_ctx *c, int l) {
+  static dim3 level_grid(mrlbm_ctx *c, int l) {  // CPT cells per thread
     const long long n = 1ll << (3 * l);
     return dim3((unsigned)((n + BLK * d3::CPT - 1) / (BLK * d3::CPT)), (unsigned)c->P.B);
+  }
+  static dim3 level_word_grid(mrlbm_ctx *c, int l) {  // one word of eight cells per thread
+    const long long n = 1ll << (3 * l);
+    return dim3((unsigned)((n / 8 + BLK - 1) / BLK), (unsigned)c->P.B);
   }
 
   // Lists of mesh m (every level active: the 3D passes keep no activity history).
@@ -1350,12 +1354,23 @@ struct Engine<3, MRLBM_D3Q6, T, GAM> {
                                                                      nullptr, c->act);
   }
 
+  // Levels up to lc of every chain share one launch (one block per instance),
+  // finer levels take a launch each: levels of at most 4096 cells with 32
+  // instances or more, else of at most 512 (a larger level spreads better over
+  // the blocks of a launch of its own).
+  static int coarse_cap(const mrlbm_ctx *c) { return std::min(c->P.B >= 32 ? 4 : 3, c->P.maxJ); }
+
   // Codes of the membership bytes tnew into code[m], the ghost marks, the lists.
   static void classify(mrlbm_ctx *c, int m) {
     const Plan &P = c->P;
-    d3::k3_classify<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->tnew, c->code[m]);
-    d3::k3_ghost_leaf<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[m]);
-    for (int l = P.maxJ; l > P.jmin; --l) d3::k3_ghost_up<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->code[m], l);
+    const int lc = coarse_cap(c);
+    uint8_t *gm = c->mark;  // ghost flags (the 3D engine keeps no reconstruction marks)
+    d3::k3_classify<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->tnew, c->code[m], gm);
+    d3::k3_ghost_leaf<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[m], gm);
+    for (int l = P.maxJ; l > std::max(P.jmin, lc); --l)
+      d3::k3_ghost_up<T><<<level_word_grid(c, l), BLK, 0, c->stream>>>(I(c), c->code[m], gm, l);
+    if (lc > P.jmin) d3::k3_dense_coarse<T, 2><<<P.B, CBLK, 0, c->stream>>>(I(c), gm, c->code[m], lc);
+    d3::k3_ghost_codes<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[m], gm);
     compact(c, m);
   }
 
@@ -1363,11 +1378,14 @@ struct Engine<3, MRLBM_D3Q6, T, GAM> {
   // predictions coarse to fine.
   static void reconstruct(mrlbm_ctx *c, T *F, int m) {
     const Plan &P = c->P;
+    const int lc = coarse_cap(c);
     const uint32_t *li = c->lists[m] + (size_t)CAT_INTERNAL * P.ctotal;
     const uint32_t *lg = c->lists[m] + (size_t)CAT_GHOST * P.ctotal;
-    for (int l = P.maxJ - 1; l >= P.jmin; --l)
+    for (int l = P.maxJ - 1; l > lc; --l)
       d3::k3_project<T><<<level_list_blocks(c, l), BLK, 0, c->stream>>>(c->bt, I(c), F, li, c->lvl[m], l);
-    for (int l = P.jmin + 1; l <= P.maxJ; ++l)
+    d3::k3_project_coarse<T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, li, c->lvl[m], lc);
+    if (lc > P.jmin) d3::k3_ghost_coarse<T><<<P.B, CBLK, 0, c->stream>>>(I(c), F, lg, c->lvl[m], lc);
+    for (int l = std::max(P.jmin, lc) + 1; l <= P.maxJ; ++l)
       d3::k3_ghost<T><<<level_list_blocks(c, l), BLK, 0, c->stream>>>(c->bt, I(c), F, lg, c->lvl[m], l);
   }
 
@@ -1381,9 +1399,14 @@ struct Engine<3, MRLBM_D3Q6, T, GAM> {
     auto det = P.metric_mode == 0 ? d3::k3_details<T, 0> : P.metric_mode == 1 ? d3::k3_details<T, 1> : d3::k3_details<T, 2>;
     det<<<list_blocks(c), BLK, 0, c->stream>>>(c->bt, I(c), Fc, li, c->lvl[mo], c->refg);
     d3::k3_keep<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->code[mo], c->refg, c->keep, c->tnew);
-    for (int l = P.maxJ; l >= P.jmin + 2; --l) d3::k3_closure<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->keep, l);
+    const int lc = coarse_cap(c);
+    for (int l = P.maxJ; l >= std::max(P.jmin + 2, lc + 1); --l)
+      d3::k3_closure<T><<<level_word_grid(c, l), BLK, 0, c->stream>>>(I(c), c->keep, l);
+    if (lc >= P.jmin + 2) d3::k3_dense_coarse<T, 0><<<P.B, CBLK, 0, c->stream>>>(I(c), c->keep, nullptr, lc);
     d3::k3_enlarge<T><<<P.nblocks, BLK, 0, c->stream>>>(I(c), c->binfo, c->keep, c->refg, c->tnew);
-    for (int l = P.maxJ; l >= P.jmin + 1; --l) d3::k3_grade<T><<<level_grid(c, l), BLK, 0, c->stream>>>(I(c), c->tnew, l);
+    for (int l = P.maxJ; l >= std::max(P.jmin + 1, lc + 1); --l)
+      d3::k3_grade<T><<<level_word_grid(c, l), BLK, 0, c->stream>>>(I(c), c->tnew, l);
+    if (lc >= P.jmin + 1) d3::k3_dense_coarse<T, 1><<<P.B, CBLK, 0, c->stream>>>(I(c), c->tnew, nullptr, lc);
     classify(c, mn);
     // the transfer: new leaves outside the old mesh are predicted from their
     // parent's level, whose stencil the old mesh's ghosts cover
