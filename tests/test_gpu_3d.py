@@ -209,3 +209,21 @@ def test_d3q6_refuses_walls_gamma_and_adjoint(mr):
         sim.forward_record(4, 2)
     assert e.value.status == -1
     sim.close()
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_d3q6_paper_size_replay(mr, precision):
+    """The benchmarked configuration (the ball at levels 1..8, 256^3 finest cells,
+    graph replay with the autotuned launch schedule): after 40 steps, two steps
+    replay on the oracle, whose dense levels hold about 19 M cells."""
+    cfg, m0 = W.ball_d3q6()
+    print("d3q6 paper size, precision", precision, flush=True)
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.step(30)
+    sim.autotune(reps=3)
+    sim.step(10)
+    levels = _replay(mr, o, sim, 2, precision)
+    assert len(levels) >= 4
+    sim.close()
