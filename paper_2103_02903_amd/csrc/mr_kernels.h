@@ -1507,6 +1507,35 @@ __device__ __forceinline__ T detail_correction(T acc, int l, int x, int y, const
   return acc;
 }
 
+// Neighbours (bits as in refined_neighbours) whose children's details enter the
+// transport of velocity (ex, ey): the sums of an axis velocity collapse onto the
+// leaf's row or column (the children of a cell average to the cell along the
+// other axis), so only the two neighbours along the axis carry nonzero
+// correction weights; the others are skipped (their terms would add 0).
+//
+// For a leaf one level above the finest (n = 1) the sets E and A lie within
+// one finest cell of the leaf's faces, and only the upwind neighbours (offsets
+// a in {0, -ex}, b in {0, -ey}) carry weights.
+template <int DIM>
+__host__ __device__ constexpr unsigned correction_mask(int ex, int ey) {
+  return DIM == 1 ? 0x3u : (ey == 0 && ex != 0) ? 0x18u : (ex == 0 && ey != 0) ? 0x42u : 0xffu;
+}
+template <int DIM>
+__host__ __device__ constexpr unsigned upwind_mask(int ex, int ey) {
+  unsigned m = 0;
+  for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if (a == 0 && b == 0) continue;
+      if ((a == 0 || a == -ex) && (b == 0 || b == -ey)) m |= 1u << bit;
+      ++bit;
+    }
+  return m;
+}
+template <int DIM>
+__host__ __device__ constexpr unsigned correction_mask(int ex, int ey, int n) {
+  return correction_mask<DIM>(ex, ey) & (n == 1 ? upwind_mask<DIM>(ex, ey) : 0xffu);
+}
+
 // Population h of the leaf (l, c): Fl / Ff point at population h of levels l and
 // l+1, cl at the codes of level l, W / Cw at the weights of (n, h).
 template <int DIM, int SCHEME, typename T>
@@ -1537,7 +1566,8 @@ __device__ __forceinline__ T transport_pop(int h, int l, int J, uint32_t c, int 
       for (int a = -2; a <= 2; ++a) acc = fma(W[(b + 2) * 5 + a + 2], Fl[row + wrapl(x + a, l)], acc);
     }
   }
-  if (nbr) acc = detail_correction<DIM, T>(acc, l, x, y, Fl, Ff, Cw, nbr);
+  if (nbr & correction_mask<DIM>(ex, ey, n))
+    acc = detail_correction<DIM, T>(acc, l, x, y, Fl, Ff, Cw, nbr & correction_mask<DIM>(ex, ey, n));
   return fma((T)ldexp(1.0, -DIM * n), acc, Fl[c]);
 }
 
@@ -2150,10 +2180,12 @@ __device__ __forceinline__ void leaf_update_level(const Inst<T> &In, int l, uint
     }
     if (nbr) {
 #pragma unroll
-      for (int h = 0; h < Q; ++h)
-        if (V::ex(h) != 0 || V::ey(h) != 0)
+      for (int h = 0; h < Q; ++h) {
+        const unsigned m = nbr & correction_mask<DIM>(V::ex(h), V::ey(h), n);
+        if ((V::ex(h) != 0 || V::ey(h) != 0) && m)
           acc[h] = detail_correction_call<DIM, T>(acc[h], l, x, y, Fl0 + h * nl, Ff0 + h * nf,
-                                                  Ct + ((long long)nn * Q + h) * CS, nbr);
+                                                  Ct + ((long long)nn * Q + h) * CS, m);
+      }
     }
 #pragma unroll
     for (int h = 0; h < Q; ++h) f[h] = (V::ex(h) == 0 && V::ey(h) == 0) ? fc[h] : fma(scale, acc[h], fc[h]);

@@ -142,6 +142,30 @@ def _exact_sum(n, m, e, a):
     return sum(v.get(i, Fr(0)) for i in range(-e, (1 << n) - e))
 
 
+@pytest.mark.parametrize("scheme", ["D2Q9", "D2Q4E"])
+def test_skipped_detail_corrections_have_zero_weight(scheme):
+    """The transport kernels skip the detail corrections of the neighbours off
+    the axis of an axis velocity, and for a leaf one level above the finest
+    those not upwind: their correction weights must be zero (the children of a
+    cell average to it along the other axis; at n = 1 E and A lie within one
+    finest cell of the faces)."""
+    for n in range(1, 9):
+        _, C = mrlbm.transport_tables(scheme, n)
+        C = np.asarray(C).reshape(-1, 6, 6)  # [h][y2][y1], children offsets -2..3 from 2k
+        d2q9 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+        d2q4 = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+        eta = d2q9 if scheme == "D2Q9" else [d2q4[h & 3] for h in range(16)]
+        for h, (ex, ey) in enumerate(eta):
+            for b in (-1, 0, 1):
+                for a in (-1, 0, 1):
+                    if (a, b) == (0, 0):
+                        continue
+                    on_axis = (ex == 0) == (ey == 0) or ((b == 0) if ey == 0 else (a == 0))
+                    upwind = a in (0, -ex) and b in (0, -ey)  # n = 1: the upwind neighbours only
+                    if not on_axis or (n == 1 and not upwind):
+                        assert not np.any(C[h][2 * b + 2:2 * b + 4, 2 * a + 2:2 * a + 4]), (n, h, a, b)
+
+
 @pytest.mark.parametrize("scheme", ["D1Q2", "D1Q3", "D2Q9"])
 @pytest.mark.parametrize("n", [1, 2, 3, 5])
 def test_transport_tables_are_exact(scheme, n):
