@@ -177,17 +177,82 @@ __global__ void __launch_bounds__(BLK) k_adj_collide(Batch bt, const Inst<T> *__
   }
 }
 
-// Transpose of the MR transport: scatter the adjoint hb of the transported
-// values of every leaf into the adjoint gs of the reconstruction it read.
+// Transpose of the MR transport, in two launches. First, every cell of the
+// mesh (leaf, internal or ghost: the cells a leaf's transport reads at its own
+// level) gathers what the leaves of its level took from it: its own value (a
+// leaf's identity term), the flattened weights of the leaves within +-2 (their
+// 5^d boxes) times 2^{-dn} and the leaves' adjoints hb, or at the finest level
+// the leaf it streamed to. A cell is written by one thread, so no atomics.
+template <int DIM, int SCHEME, typename T>
+__global__ void __launch_bounds__(BLK) k_adj_transport_gather(Batch bt, const Inst<T> *__restrict__ I,
+                                                              const T *__restrict__ hb, T *__restrict__ gs,
+                                                              const uint8_t *__restrict__ code,
+                                                              const uint32_t *__restrict__ lists,
+                                                              const int *__restrict__ lvl, const T *__restrict__ Wt) {
+  using V = Vel<SCHEME>;
+  constexpr int Q = V::Q, WS = DIM == 2 ? 25 : 5;
+  __shared__ SegLDS s;
+  const int cat = blockIdx.y;  // CAT_LEAF, CAT_INTERNAL, CAT_GHOST
+  load_segments(s, I, lvl, bt.B, cat, -1);
+  const uint32_t *lst = lists + (size_t)cat * bt.ctotal;
+  MRLBM_CHUNK_LOOP(s, bt.B)
+  const Inst<T> &In = I[i];
+  const uint32_t e = lst[s.beg[i] + item];
+  const int l = (int)(e >> LEVEL_SHIFT);
+  const uint32_t c = e & CELL_MASK;
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const int J = In.jmax, n = J - l;
+  const long long nl = ncells_d(DIM, l);
+  const uint8_t *cl = code + In.loff[l];
+  auto at = [&](int a, int b) -> long long {
+    return cidx<DIM>(l, wrapl(x + a, l), DIM == 2 ? wrapl(y + b, l) : 0);
+  };
+  // the leaves of the 5^d box around the cell: bit (b + 2) * 5 + (a + 2)
+  uint32_t lm = 0;
+  for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b)
+    for (int a = -2; a <= 2; ++a)
+      if (cl[at(a, b)] == C_LEAF) lm |= 1u << ((b + 2) * 5 + a + 2);
+  if (!lm) continue;
+  const bool own = (lm >> 12) & 1u;
+  const T scale = n > 0 ? (T)ldexp(1.0, -DIM * n) : T(0);
+  for (int hh = 0; hh < Q; ++hh) {
+    const int ex = V::ex(hh), ey = V::ey(hh);
+    const T *Hl = hb + (long long)Q * In.loff[l] + hh * nl;
+    T acc = T(0);
+    if (ex == 0 && ey == 0) {
+      if (own) acc = Hl[c];
+    } else if (n == 0) {  // the finest leaf c + eta streamed from here
+      if ((lm >> ((ey + 2) * 5 + ex + 2)) & 1u) acc = Hl[at(ex, ey)];
+    } else {
+      const T *W = Wt + ((long long)(n - 1) * Q + hh) * WS;
+      T sacc = T(0);
+      for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b)
+        for (int a = -2; a <= 2; ++a) {
+          // the leaf at offset (-a, -b) weighted this cell with W(a, b)
+          if (!((lm >> ((2 - b) * 5 + 2 - a)) & 1u)) continue;
+          const T w = DIM == 2 ? W[(b + 2) * 5 + a + 2] : W[a + 2];
+          if (w != T(0)) sacc += w * Hl[at(-a, -b)];
+        }
+      acc = scale * sacc;
+      if (own) acc += Hl[c];
+    }
+    if (acc != T(0)) gs[(long long)Q * In.loff[l] + hh * nl + c] += acc;
+  }
+  MRLBM_CHUNK_END
+}
+
+// Second, the detail corrections: a leaf next to a finer cell scatters its
+// weighted adjoint into that cell's children and, through the prediction they
+// were compared with, into the parent level (atomic adds).
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) k_adj_transport(Batch bt, const Inst<T> *__restrict__ I,
                                                        const T *__restrict__ hb, T *__restrict__ gs,
                                                        const uint8_t *__restrict__ code,
                                                        const uint32_t *__restrict__ leaves,
-                                                       const int *__restrict__ lvl, const T *__restrict__ Wt,
-                                                       const T *__restrict__ Ct) {
+                                                       const int *__restrict__ lvl, const T *__restrict__ Ct) {
   using V = Vel<SCHEME>;
-  constexpr int Q = V::Q, WS = DIM == 2 ? 25 : 5, CS = DIM == 2 ? 36 : 6;
+  constexpr int Q = V::Q, CS = DIM == 2 ? 36 : 6;
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_LEAF, -1);
   MRLBM_CHUNK_LOOP(s, bt.B)
@@ -195,49 +260,41 @@ __global__ void __launch_bounds__(BLK) k_adj_transport(Batch bt, const Inst<T> *
   const uint32_t e = leaves[s.beg[i] + item];
   const int l = (int)(e >> LEVEL_SHIFT);
   const uint32_t c = e & CELL_MASK;
+  const int J = In.jmax, n = J - l;
+  if (n == 0) continue;
   int x, y;
   coords<DIM>(l, c, x, y);
-  const int J = In.jmax, n = J - l;
+  const unsigned nbr = refined_neighbours<DIM>(code + In.loff[l], l, x, y);
+  if (!nbr) continue;
   const long long nl = ncells_d(DIM, l);
-  const unsigned nbr = n > 0 ? refined_neighbours<DIM>(code + In.loff[l], l, x, y) : 0u;
   for (int hh = 0; hh < Q; ++hh) {
     const int ex = V::ex(hh), ey = V::ey(hh);
+    const unsigned m = nbr & correction_mask<DIM>(ex, ey, n);
+    if ((ex == 0 && ey == 0) || !m) continue;
     const T v = hb[(long long)Q * In.loff[l] + hh * nl + c];
-    T *Gl = gs + (long long)Q * In.loff[l] + hh * nl;
-    if (ex == 0 && ey == 0) { atomicAdd(&Gl[c], v); continue; }
-    if (n == 0) { atomicAdd(&Gl[cidx<DIM>(J, wrapl(x - ex, J), wrapl(y - ey, J))], v); continue; }
-    atomicAdd(&Gl[c], v);
     const T sv = (T)ldexp(1.0, -DIM * n) * v;
-    const T *W = Wt + ((long long)(n - 1) * Q + hh) * WS;
-    for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b)
-      for (int a = -2; a <= 2; ++a) {
-        const T w = DIM == 2 ? W[(b + 2) * 5 + a + 2] : W[a + 2];
-        if (w == T(0)) continue;
-        atomicAdd(&Gl[cidx<DIM>(l, wrapl(x + a, l), DIM == 2 ? wrapl(y + b, l) : 0)], w * sv);
+    T *Gl = gs + (long long)Q * In.loff[l] + hh * nl;
+    const T *Cw = Ct + ((long long)(n - 1) * Q + hh) * CS;
+    T *Gf = gs + (long long)Q * In.loff[l + 1] + hh * ncells_d(DIM, l + 1);
+    for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
+      for (int a = -1; a <= 1; ++a) {
+        if (a == 0 && b == 0) continue;
+        const int k = bit++;
+        if (!(m & (1u << k))) continue;
+        const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
+        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
+            const T cw = Cw[y2 * 6 + y1] * sv;
+            if (cw == T(0)) continue;
+            const int cx = 2 * px + dx, cy = 2 * py + dy;
+            atomicAdd(&Gf[cidx<DIM>(l + 1, cx, cy)], cw);  // the child's own value
+            long long idx[9];
+            T w[9];
+            const int nk = predict_stencil<DIM, T>(l + 1, cx, cy, idx, w);  // minus its prediction
+            for (int k2 = 0; k2 < nk; ++k2) atomicAdd(&Gl[idx[k2]], -w[k2] * cw);
+          }
       }
-    if (nbr) {
-      const T *Cw = Ct + ((long long)(n - 1) * Q + hh) * CS;
-      T *Gf = gs + (long long)Q * In.loff[l + 1] + hh * ncells_d(DIM, l + 1);
-      for (int b = (DIM == 2 ? -1 : 0), bit = 0; b <= (DIM == 2 ? 1 : 0); ++b)
-        for (int a = -1; a <= 1; ++a) {
-          if (a == 0 && b == 0) continue;
-          const int k = bit++;
-          if (!(nbr & (1u << k))) continue;
-          const int px = wrapl(x + a, l), py = DIM == 2 ? wrapl(y + b, l) : 0;
-          for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-              const int y1 = 2 * a + dx + 2, y2 = DIM == 2 ? 2 * b + dy + 2 : 0;
-              const T cw = Cw[y2 * 6 + y1] * sv;
-              if (cw == T(0)) continue;
-              const int cx = 2 * px + dx, cy = 2 * py + dy;
-              atomicAdd(&Gf[cidx<DIM>(l + 1, cx, cy)], cw);  // the child's own value
-              long long idx[9];
-              T w[9];
-              const int nk = predict_stencil<DIM, T>(l + 1, cx, cy, idx, w);  // minus its prediction
-              for (int k2 = 0; k2 < nk; ++k2) atomicAdd(&Gl[idx[k2]], -w[k2] * cw);
-            }
-        }
-    }
   }
   MRLBM_CHUNK_END
 }
@@ -290,6 +347,56 @@ __global__ void __launch_bounds__(BLK) k_adj_project(Batch bt, const Inst<T> *__
       for (int dx = 0; dx < 2; ++dx) Gc[cidx<DIM>(l + 1, 2 * x + dx, 2 * y + dy)] += v;
   }
   MRLBM_CHUNK_END
+}
+
+// The coarse levels (up to lc) of both transposes in one launch, one block of
+// CBLK threads per instance: the ghost transposes of levels lc .. jmin+1, then
+// the projection transposes of levels jmin .. lc-1, with a block barrier after
+// each level (the finer ghost levels run before, the finer projection levels
+// after).
+template <int DIM, int Q, typename T>
+__global__ void __launch_bounds__(CBLK) k_adj_coarse(const Inst<T> *__restrict__ I, T *__restrict__ G,
+                                                     const uint32_t *__restrict__ lg, const uint32_t *__restrict__ li,
+                                                     const int *__restrict__ lvl, int lc) {
+  const Inst<T> &In = I[blockIdx.x];
+  const int *Lg = lvl + (blockIdx.x * NCAT + CAT_GHOST) * LVL_STRIDE;
+  const int *Li = lvl + (blockIdx.x * NCAT + CAT_INTERNAL) * LVL_STRIDE;
+  const int top = min(lc, In.jmax);
+  for (int l = top; l >= In.jmin + 1; --l) {
+    for (int k = Lg[l] + (int)threadIdx.x; k < Lg[l + 1]; k += CBLK) {
+      const uint32_t c = lg[k] & CELL_MASK;
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      long long idx[9];
+      T w[9];
+      const int nk = predict_stencil<DIM, T>(l, x, y, idx, w);
+      for (int hh = 0; hh < Q; ++hh) {
+        T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
+        T *Gp = G + (long long)Q * In.loff[l - 1] + hh * ncells_d(DIM, l - 1);
+        const T v = Gl[c];
+        Gl[c] = T(0);
+        for (int k2 = 0; k2 < nk; ++k2) atomicAdd(&Gp[idx[k2]], w[k2] * v);
+      }
+    }
+    __syncthreads();
+  }
+  const T inv = DIM == 2 ? T(0.25) : T(0.5);
+  for (int l = In.jmin; l <= top - 1; ++l) {
+    for (int k = Li[l] + (int)threadIdx.x; k < Li[l + 1]; k += CBLK) {
+      const uint32_t c = li[k] & CELL_MASK;
+      int x, y;
+      coords<DIM>(l, c, x, y);
+      for (int hh = 0; hh < Q; ++hh) {
+        T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
+        T *Gc = G + (long long)Q * In.loff[l + 1] + hh * ncells_d(DIM, l + 1);
+        const T v = inv * Gl[c];
+        Gl[c] = T(0);
+        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+          for (int dx = 0; dx < 2; ++dx) Gc[cidx<DIM>(l + 1, 2 * x + dx, 2 * y + dy)] += v;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Transpose of the transfer: a new leaf that was an old tree or ghost cell read

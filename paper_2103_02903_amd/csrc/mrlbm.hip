@@ -1191,14 +1191,17 @@ struct Engine {
 
   // Reconstruction transpose on mesh `ms` in the dense adjoint G: ghost
   // predictions pushed up from the finest level, then projections pushed down.
+  // Levels up to the coarse cap in one launch (k_adj_coarse), finer levels a
+  // launch each.
   static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms) {
     const Plan &P = c->P;
-    for (int l = P.maxJ; l >= P.jmin + 1; --l)
-      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, ms.lists + (size_t)CAT_GHOST * P.ctotal,
-                                                              ms.lvl, l);
-    for (int l = P.jmin; l <= P.maxJ - 1; ++l)
-      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G,
-                                                                ms.lists + (size_t)CAT_INTERNAL * P.ctotal, ms.lvl, l);
+    const int lc = std::max(P.jmin, coarse_cap(c));
+    const uint32_t *lg = ms.lists + (size_t)CAT_GHOST * P.ctotal, *li = ms.lists + (size_t)CAT_INTERNAL * P.ctotal;
+    for (int l = P.maxJ; l > lc; --l)
+      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, lg, ms.lvl, l);
+    k_adj_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), G, lg, li, ms.lvl, lc);
+    for (int l = lc; l <= P.maxJ - 1; ++l)
+      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, li, ms.lvl, l);
   }
 
   static int adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sbar) {
@@ -1252,8 +1255,10 @@ struct Engine {
         zero(c, Go, fbytes);
         k_adj_collide<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(
             c->bt, I(c), mm, (const T *)(w + L.tape_h + j * L.F_b), A, Hb, leaves_n, mn.lvl, spart);
+        k_adj_transport_gather<DIM, SCHEME, T><<<dim3(ADJ_GRID, NCAT), BLK, 0, c->stream>>>(
+            c->bt, I(c), Hb, Gs, mn.code, mn.lists, mn.lvl, (const T *)c->W);
         k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
-                                                                         (const T *)c->W, (const T *)c->C);
+                                                                         (const T *)c->C);
         reconstruct_T(c, Gs, mn);
         k_adj_transfer<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Gs, Go, mo.code, leaves_n, mn.lvl);
         reconstruct_T(c, Go, mo);
