@@ -403,7 +403,10 @@ const char *mrlbm_status_string(int status);
  *   C[h][36]: weight of the detail of the level-(l+1) cell at offset (y1, y2)
  *             in [-2, 3]^2 from 2k, index (y2 + 2) * 6 + (y1 + 2) (1D: only
  *             the row y2 = 0 nonzero).
- * Pure host computation (no device, no context). Errors: MRLBM_ERR_INVALID. */
+ * Pure host computation (no device, no context). Errors: MRLBM_ERR_INVALID,
+ * also for MRLBM_D3Q6, which has no table of its own: its leaves apply the
+ * D1Q2 rows of their velocity's sign along the velocity's axis (the sums of
+ * the 3D reconstruction over a face collapse onto the leaf's row). */
 int mrlbm_transport_tables(int scheme, int n, double *W, double *C);
 
 /* The tables of the general transport path (walls, gamma > 1): as above for a
