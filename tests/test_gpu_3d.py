@@ -85,11 +85,40 @@ def test_d3q6_step_replay(mr, kind, jmin, jmax, eps, mu_bar, metric, seed, steps
         assert np.array_equal(tg, t0) and leaf_err(o, t0, vg, v0) <= TOL64
     levels = _replay(mr, o, sim, steps, precision)
     assert len(levels) >= 2
-    if precision == 8:
+    if precision == 8:  # the same projection and prediction expressions in the same order: bit for bit
         fin = sim.fields("finest").cpu().numpy()
         tg, vg = sim.get_state()
-        want = o.finest(tg, vg).reshape(o.q, -1)
-        assert np.max(np.abs(fin - want)) <= 1e-12 * max(1.0, float(np.max(np.abs(want))))
+        assert np.array_equal(fin, o.finest(tg, vg).reshape(o.q, -1))
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_d3q6_fields_match_oracle(mr, precision):
+    """mrlbm_fields in 3D: the leaf table in (level, cell) order, the leaf
+    populations, the moments M f with the printed D3Q6 matrix."""
+    cfg, m0 = W.ball_d3q6(jmin=2, jmax=6)
+    o = oracle.Oracle(cfg)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.step(5)
+    tree, vals = sim.get_state()
+    table = sim.fields("leaf_table").cpu().numpy().astype(np.uint32)
+    pops = sim.fields("populations").cpu().numpy()
+    lv, cell = table >> 26, table & ((1 << 26) - 1)
+    want_l, want_c = [], []
+    for l in range(o.jmin, o.jmax + 1):
+        idx = np.flatnonzero(o.leaf_mask(tree, l).ravel())
+        want_l.append(np.full(idx.size, l))
+        want_c.append(idx)
+    assert np.array_equal(lv, np.concatenate(want_l)) and np.array_equal(cell, np.concatenate(want_c))
+    for l in range(o.jmin, o.jmax + 1):
+        sel = lv == l
+        assert np.array_equal(pops[sel], o.values_level(vals, l).reshape(o.q, -1)[:, cell[sel]].T)
+    mom = sim.fields("moments").cpu().numpy().astype(np.float64)
+    want = pops.astype(np.float64) @ o.moment_matrix().T
+    assert np.max(np.abs(mom - want) / np.maximum(1.0, np.abs(want))) <= (1e-13 if precision == 8 else 2e-6)
+    cells, lvals = sim.leaves()
+    assert np.array_equal(cells.cpu().numpy().astype(np.uint32), table)
     sim.close()
 
 
