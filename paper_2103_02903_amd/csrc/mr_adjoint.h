@@ -182,18 +182,28 @@ __global__ void __launch_bounds__(BLK) k_adj_collide(Batch bt, const Inst<T> *__
 // level) gathers what the leaves of its level took from it: its own value (a
 // leaf's identity term), the flattened weights of the leaves within +-2 (their
 // 5^d boxes) times 2^{-dn} and the leaves' adjoints hb, or at the finest level
-// the leaf it streamed to. A cell is written by one thread, so no atomics.
+// the leaf it streamed to. A cell and population is written by one thread, so
+// no atomics. One population per grid layer (blockIdx.z): a thread's chain of
+// dependent memory accesses is then the list entry, the codes of the box, the
+// box's adjoints and the update, whatever the number of populations. The
+// layer's weights (one row of 5^d per level difference) are staged in LDS.
+constexpr int ADJ_GATHER_GRID = 32;
 template <int DIM, int SCHEME, typename T>
 __global__ void __launch_bounds__(BLK) k_adj_transport_gather(Batch bt, const Inst<T> *__restrict__ I,
                                                               const T *__restrict__ hb, T *__restrict__ gs,
                                                               const uint8_t *__restrict__ code,
                                                               const uint32_t *__restrict__ lists,
-                                                              const int *__restrict__ lvl, const T *__restrict__ Wt) {
+                                                              const int *__restrict__ lvl, const T *__restrict__ Wt,
+                                                              int nmax) {
   using V = Vel<SCHEME>;
   constexpr int Q = V::Q, WS = DIM == 2 ? 25 : 5;
+  constexpr int MAXN = DIM == 2 ? 12 : 24;  // J - jmin: at most 12 in 2D (J <= 13), 24 in 1D (J <= 25)
+  __shared__ T Ws[MAXN * WS];
   __shared__ SegLDS s;
+  const int hh = blockIdx.z, ex = V::ex(hh), ey = V::ey(hh);
+  for (int k = threadIdx.x; k < nmax * WS; k += BLK) Ws[k] = Wt[((k / WS) * Q + hh) * WS + k % WS];
   const int cat = blockIdx.y;  // CAT_LEAF, CAT_INTERNAL, CAT_GHOST
-  load_segments(s, I, lvl, bt.B, cat, -1);
+  load_segments(s, I, lvl, bt.B, cat, -1);  // its first barrier also publishes Ws
   const uint32_t *lst = lists + (size_t)cat * bt.ctotal;
   MRLBM_CHUNK_LOOP(s, bt.B)
   const Inst<T> &In = I[i];
@@ -215,30 +225,32 @@ __global__ void __launch_bounds__(BLK) k_adj_transport_gather(Batch bt, const In
       if (cl[at(a, b)] == C_LEAF) lm |= 1u << ((b + 2) * 5 + a + 2);
   if (!lm) continue;
   const bool own = (lm >> 12) & 1u;
-  const T scale = n > 0 ? (T)ldexp(1.0, -DIM * n) : T(0);
-  for (int hh = 0; hh < Q; ++hh) {
-    const int ex = V::ex(hh), ey = V::ey(hh);
-    const T *Hl = hb + (long long)Q * In.loff[l] + hh * nl;
-    T acc = T(0);
-    if (ex == 0 && ey == 0) {
-      if (own) acc = Hl[c];
-    } else if (n == 0) {  // the finest leaf c + eta streamed from here
-      if ((lm >> ((ey + 2) * 5 + ex + 2)) & 1u) acc = Hl[at(ex, ey)];
-    } else {
-      const T *W = Wt + ((long long)(n - 1) * Q + hh) * WS;
-      T sacc = T(0);
-      for (int b = (DIM == 2 ? -2 : 0); b <= (DIM == 2 ? 2 : 0); ++b)
-        for (int a = -2; a <= 2; ++a) {
-          // the leaf at offset (-a, -b) weighted this cell with W(a, b)
-          if (!((lm >> ((2 - b) * 5 + 2 - a)) & 1u)) continue;
-          const T w = DIM == 2 ? W[(b + 2) * 5 + a + 2] : W[a + 2];
-          if (w != T(0)) sacc += w * Hl[at(-a, -b)];
-        }
-      acc = scale * sacc;
-      if (own) acc += Hl[c];
+  const T *Hl = hb + (long long)Q * In.loff[l] + hh * nl;
+  T acc = T(0);
+  if (ex == 0 && ey == 0) {
+    if (own) acc = Hl[c];
+  } else if (n == 0) {  // the finest leaf c + eta streamed from here
+    if ((lm >> ((ey + 2) * 5 + ex + 2)) & 1u) acc = Hl[at(ex, ey)];
+  } else {
+    const T *W = Ws + (n - 1) * WS;
+    // slot k = (b + 2) * 5 + (a + 2): the leaf at offset (-a, -b) weighted this
+    // cell with W(a, b); every load first, then the sum in slot order
+    T hv[WS];
+    bool use[WS];
+#pragma unroll
+    for (int k = 0; k < WS; ++k) {
+      const int a = k % 5 - 2, b = DIM == 2 ? k / 5 - 2 : 0;
+      use[k] = ((lm >> ((2 - b) * 5 + 2 - a)) & 1u) && W[k] != T(0);
+      hv[k] = use[k] ? Hl[at(-a, -b)] : T(0);
     }
-    if (acc != T(0)) gs[(long long)Q * In.loff[l] + hh * nl + c] += acc;
+    T sacc = T(0);
+#pragma unroll
+    for (int k = 0; k < WS; ++k)
+      if (use[k]) sacc += W[k] * hv[k];
+    acc = (T)ldexp(1.0, -DIM * n) * sacc;
+    if (own) acc += Hl[c];
   }
+  if (acc != T(0)) gs[(long long)Q * In.loff[l] + hh * nl + c] += acc;
   MRLBM_CHUNK_END
 }
 
@@ -299,6 +311,58 @@ __global__ void __launch_bounds__(BLK) k_adj_transport(Batch bt, const Inst<T> *
   MRLBM_CHUNK_END
 }
 
+// Transpose of the ghost prediction of cell c of level l: its adjoint goes to
+// the parent's 3^d box at level l-1 (atomic adds) and its slot is cleared. The
+// populations are all read before the first write: the slots of the two
+// levels are distinct, and the reads then need one memory round trip.
+template <int DIM, int Q, typename T>
+__device__ __forceinline__ void adj_ghost_cell(const Inst<T> &In, T *__restrict__ G, int l, uint32_t c) {
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  long long idx[9];
+  T w[9];
+  const int nk = predict_stencil<DIM, T>(l, x, y, idx, w);
+  const long long nl = ncells_d(DIM, l), np = ncells_d(DIM, l - 1);
+  T *Gl = G + (long long)Q * In.loff[l], *Gp = G + (long long)Q * In.loff[l - 1];
+  T v[Q];
+#pragma unroll
+  for (int hh = 0; hh < Q; ++hh) v[hh] = Gl[hh * nl + c];
+#pragma unroll
+  for (int hh = 0; hh < Q; ++hh) {
+    Gl[hh * nl + c] = T(0);
+    for (int k = 0; k < nk; ++k) atomicAdd(&Gp[hh * np + idx[k]], w[k] * v[hh]);
+  }
+}
+
+// Transpose of the projection onto internal cell c of level l: its adjoint
+// times 2^-d goes to its 2^d children (each child has this one parent, so no
+// atomics) and its slot is cleared; every read comes before the first write.
+template <int DIM, int Q, typename T>
+__device__ __forceinline__ void adj_project_cell(const Inst<T> &In, T *__restrict__ G, int l, uint32_t c) {
+  constexpr int NCH = DIM == 2 ? 4 : 2;
+  const T inv = DIM == 2 ? T(0.25) : T(0.5);
+  int x, y;
+  coords<DIM>(l, c, x, y);
+  const long long nl = ncells_d(DIM, l), nf = ncells_d(DIM, l + 1);
+  T *Gl = G + (long long)Q * In.loff[l], *Gc = G + (long long)Q * In.loff[l + 1];
+  long long ch[NCH];
+  for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
+    for (int dx = 0; dx < 2; ++dx) ch[dy * 2 + dx] = cidx<DIM>(l + 1, 2 * x + dx, 2 * y + dy);
+  T v[Q], cv[Q][NCH];
+#pragma unroll
+  for (int hh = 0; hh < Q; ++hh) {
+    v[hh] = inv * Gl[hh * nl + c];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) cv[hh][k] = Gc[hh * nf + ch[k]];
+  }
+#pragma unroll
+  for (int hh = 0; hh < Q; ++hh) {
+    Gl[hh * nl + c] = T(0);
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) Gc[hh * nf + ch[k]] = cv[hh][k] + v[hh];
+  }
+}
+
 // Transpose of the ghost predictions of level l: push each ghost's adjoint to
 // its parent's 3^d box at level l-1 (run from the finest level down).
 template <int DIM, int Q, typename T>
@@ -307,20 +371,7 @@ __global__ void __launch_bounds__(BLK) k_adj_ghost(Batch bt, const Inst<T> *__re
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_GHOST, l);
   MRLBM_CHUNK_LOOP(s, bt.B)
-  const Inst<T> &In = I[i];
-  const uint32_t c = lst[s.beg[i] + item] & CELL_MASK;
-  int x, y;
-  coords<DIM>(l, c, x, y);
-  long long idx[9];
-  T w[9];
-  const int nk = predict_stencil<DIM, T>(l, x, y, idx, w);
-  for (int hh = 0; hh < Q; ++hh) {
-    T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
-    T *Gp = G + (long long)Q * In.loff[l - 1] + hh * ncells_d(DIM, l - 1);
-    const T v = Gl[c];
-    Gl[c] = T(0);
-    for (int k = 0; k < nk; ++k) atomicAdd(&Gp[idx[k]], w[k] * v);
-  }
+  adj_ghost_cell<DIM, Q, T>(I[i], G, l, lst[s.beg[i] + item] & CELL_MASK);
   MRLBM_CHUNK_END
 }
 
@@ -332,20 +383,8 @@ __global__ void __launch_bounds__(BLK) k_adj_project(Batch bt, const Inst<T> *__
                                                      int l) {
   __shared__ SegLDS s;
   load_segments(s, I, lvl, bt.B, CAT_INTERNAL, l);
-  const T inv = DIM == 2 ? T(0.25) : T(0.5);
   MRLBM_CHUNK_LOOP(s, bt.B)
-  const Inst<T> &In = I[i];
-  const uint32_t c = lst[s.beg[i] + item] & CELL_MASK;
-  int x, y;
-  coords<DIM>(l, c, x, y);
-  for (int hh = 0; hh < Q; ++hh) {
-    T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
-    T *Gc = G + (long long)Q * In.loff[l + 1] + hh * ncells_d(DIM, l + 1);
-    const T v = inv * Gl[c];
-    Gl[c] = T(0);
-    for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-      for (int dx = 0; dx < 2; ++dx) Gc[cidx<DIM>(l + 1, 2 * x + dx, 2 * y + dy)] += v;
-  }
+  adj_project_cell<DIM, Q, T>(I[i], G, l, lst[s.beg[i] + item] & CELL_MASK);
   MRLBM_CHUNK_END
 }
 
@@ -363,38 +402,11 @@ __global__ void __launch_bounds__(CBLK) k_adj_coarse(const Inst<T> *__restrict__
   const int *Li = lvl + (blockIdx.x * NCAT + CAT_INTERNAL) * LVL_STRIDE;
   const int top = min(lc, In.jmax);
   for (int l = top; l >= In.jmin + 1; --l) {
-    for (int k = Lg[l] + (int)threadIdx.x; k < Lg[l + 1]; k += CBLK) {
-      const uint32_t c = lg[k] & CELL_MASK;
-      int x, y;
-      coords<DIM>(l, c, x, y);
-      long long idx[9];
-      T w[9];
-      const int nk = predict_stencil<DIM, T>(l, x, y, idx, w);
-      for (int hh = 0; hh < Q; ++hh) {
-        T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
-        T *Gp = G + (long long)Q * In.loff[l - 1] + hh * ncells_d(DIM, l - 1);
-        const T v = Gl[c];
-        Gl[c] = T(0);
-        for (int k2 = 0; k2 < nk; ++k2) atomicAdd(&Gp[idx[k2]], w[k2] * v);
-      }
-    }
+    for (int k = Lg[l] + (int)threadIdx.x; k < Lg[l + 1]; k += CBLK) adj_ghost_cell<DIM, Q, T>(In, G, l, lg[k] & CELL_MASK);
     __syncthreads();
   }
-  const T inv = DIM == 2 ? T(0.25) : T(0.5);
   for (int l = In.jmin; l <= top - 1; ++l) {
-    for (int k = Li[l] + (int)threadIdx.x; k < Li[l + 1]; k += CBLK) {
-      const uint32_t c = li[k] & CELL_MASK;
-      int x, y;
-      coords<DIM>(l, c, x, y);
-      for (int hh = 0; hh < Q; ++hh) {
-        T *Gl = G + (long long)Q * In.loff[l] + hh * ncells_d(DIM, l);
-        T *Gc = G + (long long)Q * In.loff[l + 1] + hh * ncells_d(DIM, l + 1);
-        const T v = inv * Gl[c];
-        Gl[c] = T(0);
-        for (int dy = 0; dy < (DIM == 2 ? 2 : 1); ++dy)
-          for (int dx = 0; dx < 2; ++dx) Gc[cidx<DIM>(l + 1, 2 * x + dx, 2 * y + dy)] += v;
-      }
-    }
+    for (int k = Li[l] + (int)threadIdx.x; k < Li[l + 1]; k += CBLK) adj_project_cell<DIM, Q, T>(In, G, l, li[k] & CELL_MASK);
     __syncthreads();
   }
 }

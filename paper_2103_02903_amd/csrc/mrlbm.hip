@@ -1255,8 +1255,8 @@ struct Engine {
         zero(c, Go, fbytes);
         k_adj_collide<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(
             c->bt, I(c), mm, (const T *)(w + L.tape_h + j * L.F_b), A, Hb, leaves_n, mn.lvl, spart);
-        k_adj_transport_gather<DIM, SCHEME, T><<<dim3(ADJ_GRID, NCAT), BLK, 0, c->stream>>>(
-            c->bt, I(c), Hb, Gs, mn.code, mn.lists, mn.lvl, (const T *)c->W);
+        k_adj_transport_gather<DIM, SCHEME, T><<<dim3(ADJ_GATHER_GRID, NCAT, Q), BLK, 0, c->stream>>>(
+            c->bt, I(c), Hb, Gs, mn.code, mn.lists, mn.lvl, (const T *)c->W, P.nmax);
         k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
                                                                          (const T *)c->C);
         reconstruct_T(c, Gs, mn);
