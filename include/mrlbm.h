@@ -320,7 +320,9 @@ int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
  * whose meshes are held fixed (the adjoint of collision + MR transport +
  * transfer on each recorded mesh; no derivative through the thresholding).
  * Checkpoints every `ckpt_every` steps; each segment is recomputed forward with
- * a tape of its meshes and pre-collision populations, then swept backwards.
+ * a tape of its meshes and pre-collision populations, then swept backwards
+ * (the workspace holds two such tapes: the recomputation of one segment runs
+ * on the context stream while the previous one is swept on a second stream).
  * Periodic boundaries, gamma = 1 and the schemes D1Q2, D1Q3 and D2Q9 only
  * (MRLBM_ERR_INVALID with a wall, gamma > 1 or the Euler scheme). */
 
@@ -333,7 +335,8 @@ int mrlbm_adjoint_workspace_size(const mrlbm_ctx *ctx, int nsteps, int ckpt_ever
  * Errors: MRLBM_ERR_CAPACITY if the workspace is too small. */
 int mrlbm_forward_record(mrlbm_ctx *ctx, void *adj_workspace, size_t bytes, int nsteps, int ckpt_every);
 
-/* Backward sweep of the recorded run. `abar_final` (device, values layout of the
+/* Backward sweep of the recorded run (creates and destroys a stream of default
+ * priority for the sweep). `abar_final` (device, values layout of the
  * final state; only complete-leaf entries are read) is dJ/d(final leaf values);
  * writes dJ/d(initial conserved moments) to `mbar0` (device, [nc][N_J^d], context
  * precision; meaningful when the run started from mrlbm_init_equilibrium) and

@@ -461,9 +461,9 @@ void moment_mats(int scheme, double lam, double *M, double *Minv) {
 }
 
 // Layout of the adjoint workspace: one checkpoint (codes and populations) every
-// K steps, and for one segment of K steps the tape (each step's new mesh and
-// pre-collision populations), the mesh the segment starts from, and four
-// adjoint buffers.
+// K steps; for two segments of K steps (the one being swept backwards and the
+// one being recomputed) the tape (each step's new mesh and pre-collision
+// populations) and the mesh the segment starts from; four adjoint buffers.
 struct AdjLayout {
   int nck;
   size_t code_b, F_b, lists_b, lvl_b;
@@ -482,13 +482,13 @@ AdjLayout adj_layout(const Plan &P, int nsteps, int K) {
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   L.ck_code = take(L.code_b * std::max(1, L.nck));
   L.ck_F = take(L.F_b * std::max(1, L.nck));
-  L.tape_code = take(L.code_b * K);
-  L.tape_lists = take(L.lists_b * K);
-  L.tape_lvl = take(L.lvl_b * K);
-  L.tape_h = take(L.F_b * K);
-  L.st_code = take(L.code_b);
-  L.st_lists = take(L.lists_b);
-  L.st_lvl = take(L.lvl_b);
+  L.tape_code = take(L.code_b * K * 2);  // tape b of a field starts at b times its size
+  L.tape_lists = take(L.lists_b * K * 2);
+  L.tape_lvl = take(L.lvl_b * K * 2);
+  L.tape_h = take(L.F_b * K * 2);
+  L.st_code = take(L.code_b * 2);
+  L.st_lists = take(L.lists_b * 2);
+  L.st_lvl = take(L.lvl_b * 2);
   L.A = take(L.F_b);
   L.Hb = take(L.F_b);
   L.Gs = take(L.F_b);
@@ -1161,9 +1161,10 @@ struct Engine {
     (void)hipMemcpyAsync(lvl, c->lvl[m], sizeof(int) * P.B * NCAT * LVL_STRIDE, hipMemcpyDeviceToDevice, c->stream);
   }
 
-  static void zero(mrlbm_ctx *c, void *p, size_t bytes) {
+  static void zero(mrlbm_ctx *c, void *p, size_t bytes) { zero(p, bytes, c->stream); }
+  static void zero(void *p, size_t bytes, hipStream_t st) {
     const long long n4 = (long long)(bytes / 4);
-    k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>((uint32_t *)p, n4, 0u);
+    k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, st>>>((uint32_t *)p, n4, 0u);
   }
 
   static int record(mrlbm_ctx *c, int nsteps, int K) {
@@ -1193,16 +1194,48 @@ struct Engine {
   // predictions pushed up from the finest level, then projections pushed down.
   // Levels up to the coarse cap in one launch (k_adj_coarse), finer levels a
   // launch each.
-  static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms) {
+  static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms, hipStream_t st) {
     const Plan &P = c->P;
     const int lc = std::max(P.jmin, coarse_cap(c));
     const uint32_t *lg = ms.lists + (size_t)CAT_GHOST * P.ctotal, *li = ms.lists + (size_t)CAT_INTERNAL * P.ctotal;
     for (int l = P.maxJ; l > lc; --l)
-      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, lg, ms.lvl, l);
-    k_adj_coarse<DIM, Q, T><<<P.B, CBLK, 0, c->stream>>>(I(c), G, lg, li, ms.lvl, lc);
+      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, lg, ms.lvl, l);
+    k_adj_coarse<DIM, Q, T><<<P.B, CBLK, 0, st>>>(I(c), G, lg, li, ms.lvl, lc);
     for (int l = lc; l <= P.maxJ - 1; ++l)
-      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), G, li, ms.lvl, l);
+      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, li, ms.lvl, l);
   }
+
+  // A second stream and its events for the adjoint sweep, and the graphs of
+  // the segment recomputations (one per tape), released on scope exit.
+  struct SweepStream {
+    hipStream_t s = nullptr;
+    hipEvent_t rec[2] = {nullptr, nullptr}, rev[2] = {nullptr, nullptr}, start = nullptr;
+    hipGraphExec_t seg[2] = {nullptr, nullptr};
+    hipGraphExec_t sw[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [tape][adjoint buffer in A]
+    hipError_t init() {
+      hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipEventCreateWithFlags(&rec[b], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&rev[b], hipEventDisableTiming);
+      }
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+      return e;
+    }
+    ~SweepStream() {
+      if (s) (void)hipStreamSynchronize(s);
+      for (int b = 0; b < 2; ++b) {
+        if (rec[b]) (void)hipEventDestroy(rec[b]);
+        if (rev[b]) (void)hipEventDestroy(rev[b]);
+      }
+      if (start) (void)hipEventDestroy(start);
+      for (int b = 0; b < 2; ++b) {
+        if (seg[b]) (void)hipGraphExecDestroy(seg[b]);
+        for (int a = 0; a < 2; ++a)
+          if (sw[b][a]) (void)hipGraphExecDestroy(sw[b][a]);
+      }
+      if (s) (void)hipStreamDestroy(s);
+    }
+  };
 
   static int adjoint(mrlbm_ctx *c, const void *abar_final, void *mbar0, double *sbar) {
     const Plan &P = c->P;
@@ -1220,55 +1253,151 @@ struct Engine {
         mm.Minv[k] = (T)Minv[k];
       }
     }
-    zero(c, spart, sizeof(double) * 9 * ADJ_GRID);
+    // The segments' recomputations run on the context stream and their reverse
+    // sweeps on a second one, through two tapes: segment k-1 is recomputed
+    // (tape (k-1) & 1) while segment k is swept (tape k & 1). Both are chains
+    // of small launches on one instance, so they overlap on the GPU.
+    SweepStream ss;
+    HIPCHK(ss.init());
+    const hipStream_t rs = ss.s;
+    HIPCHK(hipEventRecord(ss.start, c->stream));  // the caller's work before this call
+    HIPCHK(hipStreamWaitEvent(rs, ss.start, 0));
+    zero(spart, sizeof(double) * 9 * ADJ_GRID, rs);
     (void)hipMemcpyAsync(A, abar_final, L.F_b <= P.rs * P.q * P.ctotal ? L.F_b : P.rs * P.q * P.ctotal,
-                         hipMemcpyDeviceToDevice, c->stream);
+                         hipMemcpyDeviceToDevice, rs);
     const size_t fbytes = P.rs * P.q * P.ctotal;
-    for (int seg = L.nck - 1; seg >= 0; --seg) {
-      const int n0 = seg * K, n1 = std::min(n0 + K, nsteps), steps = n1 - n0;
-      // restore the checkpoint and rebuild its lists
-      (void)hipMemcpyAsync(c->code[c->mcur], w + L.ck_code + seg * L.code_b, P.ctotal, hipMemcpyDeviceToDevice,
-                           c->stream);
-      (void)hipMemcpyAsync(c->F[c->cur], w + L.ck_F + seg * L.F_b, fbytes, hipMemcpyDeviceToDevice, c->stream);
+    auto tape_mesh = [&](int b, int j) {  // step j of tape b; j = -1: the segment's starting mesh
+      if (j < 0)
+        return Mesh{(const uint8_t *)(w + L.st_code + b * L.code_b), (const uint32_t *)(w + L.st_lists + b * L.lists_b),
+                    (const int *)(w + L.st_lvl + b * L.lvl_b)};
+      const size_t k = (size_t)b * K + j;
+      return Mesh{(const uint8_t *)(w + L.tape_code + k * L.code_b),
+                  (const uint32_t *)(w + L.tape_lists + k * L.lists_b), (const int *)(w + L.tape_lvl + k * L.lvl_b)};
+    };
+    auto tape_h = [&](int b, int j) { return (T *)(w + L.tape_h + ((size_t)b * K + j) * L.F_b); };
+    auto seg_steps = [&](int seg) { return std::min(seg * K + K, nsteps) - seg * K; };
+    // from the restored checkpoint: rebuild its lists and recompute the segment
+    // into tape b, taping each step's new mesh and pre-collision values
+    auto segment_body = [&](int b, int steps) -> int {
       activity_reset(c);  // the other code buffer and tnew hold later meshes
       compact(c, c->mcur);
-      copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code), (uint32_t *)(w + L.st_lists), (int *)(w + L.st_lvl));
-      // recompute the segment, taping each step's new mesh and pre-collision values
+      copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code + b * L.code_b), (uint32_t *)(w + L.st_lists + b * L.lists_b),
+                    (int *)(w + L.st_lvl + b * L.lvl_b));
       for (int j = 0; j < steps; ++j) {
         int rc = adapt(c);
-        if (!rc) rc = transport(c, (T *)(w + L.tape_h + j * L.F_b));
+        if (!rc) rc = transport(c, tape_h(b, j));
         if (rc) return rc;
-        copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.tape_code + j * L.code_b),
-                      (uint32_t *)(w + L.tape_lists + j * L.lists_b), (int *)(w + L.tape_lvl + j * L.lvl_b));
+        const size_t k = (size_t)b * K + j;
+        copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.tape_code + k * L.code_b),
+                      (uint32_t *)(w + L.tape_lists + k * L.lists_b), (int *)(w + L.tape_lvl + k * L.lvl_b));
       }
-      // reverse sweep over the segment
+      return MRLBM_OK;
+    };
+    // A full segment (K steps) runs as a graph captured at its first use, one
+    // per tape; the checkpoint is restored into the buffers of parity 0 first,
+    // so every replay starts from the same buffers. Context stream.
+    int mK = 0, cK = 0;  // the buffer parities after a full segment
+    auto recompute = [&](int seg) -> int {
+      const int b = seg & 1, steps = seg_steps(seg);
+      c->mcur = 0;
+      c->cur = 0;
+      (void)hipMemcpyAsync(c->code[0], w + L.ck_code + seg * L.code_b, P.ctotal, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(c->F[0], w + L.ck_F + seg * L.F_b, fbytes, hipMemcpyDeviceToDevice, c->stream);
+      int rc = MRLBM_OK;
+      if (steps < K || !c->use_graph) {
+        rc = segment_body(b, steps);
+      } else {
+        if (!ss.seg[b]) {
+          hipStream_t user = c->stream;
+          const bool prof = c->profiling;
+          c->stream = c->cap_stream;
+          c->profiling = false;
+          hipGraph_t graph = nullptr;
+          hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+          rc = e == hipSuccess ? segment_body(b, steps) : MRLBM_ERR_HIP;
+          if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &graph);
+          c->stream = user;
+          c->profiling = prof;
+          if (rc == MRLBM_OK && e == hipSuccess) e = hipGraphInstantiate(&ss.seg[b], graph, nullptr, nullptr, 0);
+          if (graph) (void)hipGraphDestroy(graph);
+          if (rc == MRLBM_OK && e != hipSuccess) {
+            ss.seg[b] = nullptr;
+            rc = MRLBM_ERR_HIP;
+          }
+          mK = c->mcur;
+          cK = c->cur;
+        }
+        if (rc == MRLBM_OK && hipGraphLaunch(ss.seg[b], c->stream) != hipSuccess) rc = MRLBM_ERR_HIP;
+        c->mcur = mK;
+        c->cur = cK;
+      }
+      if (rc) return rc;
+      return hipEventRecord(ss.rec[b], c->stream) == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+    };
+    // the reverse sweep over tape b (its last `steps` steps first)
+    auto sweep_body = [&](int b, int steps, hipStream_t st) {
       for (int j = steps - 1; j >= 0; --j) {
-        const Mesh mn{(const uint8_t *)(w + L.tape_code + j * L.code_b),
-                      (const uint32_t *)(w + L.tape_lists + j * L.lists_b), (const int *)(w + L.tape_lvl + j * L.lvl_b)};
-        const Mesh mo = j > 0 ? Mesh{(const uint8_t *)(w + L.tape_code + (j - 1) * L.code_b),
-                                     (const uint32_t *)(w + L.tape_lists + (j - 1) * L.lists_b),
-                                     (const int *)(w + L.tape_lvl + (j - 1) * L.lvl_b)}
-                              : Mesh{(const uint8_t *)(w + L.st_code), (const uint32_t *)(w + L.st_lists),
-                                     (const int *)(w + L.st_lvl)};
+        const Mesh mn = tape_mesh(b, j), mo = tape_mesh(b, j - 1);
         const uint32_t *leaves_n = mn.lists + (size_t)CAT_LEAF * P.ctotal;
-        zero(c, Gs, fbytes);
-        zero(c, Go, fbytes);
-        k_adj_collide<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(
-            c->bt, I(c), mm, (const T *)(w + L.tape_h + j * L.F_b), A, Hb, leaves_n, mn.lvl, spart);
-        k_adj_transport_gather<DIM, SCHEME, T><<<dim3(ADJ_GATHER_GRID, NCAT, Q), BLK, 0, c->stream>>>(
+        zero(Gs, fbytes, st);
+        zero(Go, fbytes, st);
+        k_adj_collide<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), mm, tape_h(b, j), A, Hb, leaves_n, mn.lvl,
+                                                                spart);
+        k_adj_transport_gather<DIM, SCHEME, T><<<dim3(ADJ_GATHER_GRID, NCAT, Q), BLK, 0, st>>>(
             c->bt, I(c), Hb, Gs, mn.code, mn.lists, mn.lvl, (const T *)c->W, P.nmax);
-        k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
-                                                                         (const T *)c->C);
-        reconstruct_T(c, Gs, mn);
-        k_adj_transfer<DIM, Q, T><<<ADJ_GRID, BLK, 0, c->stream>>>(c->bt, I(c), Gs, Go, mo.code, leaves_n, mn.lvl);
-        reconstruct_T(c, Go, mo);
+        k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
+                                                                  (const T *)c->C);
+        reconstruct_T(c, Gs, mn, st);
+        k_adj_transfer<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), Gs, Go, mo.code, leaves_n, mn.lvl);
+        reconstruct_T(c, Go, mo, st);
         std::swap(A, Go);
       }
+    };
+    // The sweep of a recomputed segment on the second stream; a full segment
+    // as a graph captured at its first use per tape and per buffer then in A
+    // (the two buffers A and Go trade places every step).
+    T *const A0 = A;
+    auto sweep = [&](int seg) -> int {
+      const int b = seg & 1, steps = seg_steps(seg);
+      if (hipStreamWaitEvent(rs, ss.rec[b], 0) != hipSuccess) return MRLBM_ERR_HIP;
+      if (steps < K || !c->use_graph) {
+        sweep_body(b, steps, rs);
+      } else {
+        hipGraphExec_t &g = ss.sw[b][A == A0 ? 0 : 1];
+        if (!g) {  // capturing swaps A and Go as the steps do
+          hipGraph_t graph = nullptr;
+          hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+          if (e == hipSuccess) {
+            sweep_body(b, steps, c->cap_stream);
+            e = hipStreamEndCapture(c->cap_stream, &graph);
+          }
+          if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+          if (graph) (void)hipGraphDestroy(graph);
+          if (e != hipSuccess) {
+            g = nullptr;
+            return MRLBM_ERR_HIP;
+          }
+        } else if (steps & 1) {
+          std::swap(A, Go);
+        }
+        if (hipGraphLaunch(g, rs) != hipSuccess) return MRLBM_ERR_HIP;
+      }
+      return hipEventRecord(ss.rev[b], rs) == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+    };
+    int rc = recompute(L.nck - 1);
+    for (int seg = L.nck - 1; seg >= 0 && !rc; --seg) {
+      rc = sweep(seg);
+      if (rc || seg == 0) break;
+      // segment seg-1 overwrites the tape that the sweep of segment seg+1 read
+      if (seg + 1 < L.nck && hipStreamWaitEvent(c->stream, ss.rev[(seg + 1) & 1], 0) != hipSuccess) rc = MRLBM_ERR_HIP;
+      if (!rc) rc = recompute(seg - 1);
     }
+    if (rc) return rc;
     // the recorded run started from the full finest mesh of checkpoint 0
     const long long nf = 1ll << (DIM * P.inst[0].jmax);
-    k_adj_init<DIM, SCHEME, T><<<grid_cap((nf + BLK - 1) / BLK, DENSE_GRID), BLK, 0, c->stream>>>(
+    k_adj_init<DIM, SCHEME, T><<<grid_cap((nf + BLK - 1) / BLK, DENSE_GRID), BLK, 0, rs>>>(
         I(c), mm, (const T *)(w + L.ck_F), A, (T *)mbar0);
+    HIPCHK(hipStreamSynchronize(rs));
     std::vector<double> part(9 * ADJ_GRID);
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(part.data(), spart, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
