@@ -87,6 +87,35 @@ def test_gpu_adjoint_matches_oracle(mr, scheme, jmin, jmax, nsteps, K, seed, pre
     sim.close()
 
 
+@pytest.mark.parametrize("K", [3, 4])
+def test_adjoint_graph_replay_matches_eager_launches(mr, K):
+    """The adjoint's full segments run as captured graphs (a recomputation and a
+    sweep per tape, the sweep also per buffer holding the running adjoint); with
+    the launch schedule's graph switch off every launch is eager. Both orders of
+    the two streams give the same gradient (up to the order of atomic adds):
+    odd and even K, four full segments and a partial one."""
+    import torch
+
+    cfg = _cfg("D2Q9", 2, 6, 1e-3)
+    m0 = W.random_field(cfg, 11, "smooth")
+    nsteps = 4 * K + 2
+    out = []
+    for graph in (1, 0):
+        sim = mr.Sim(cfg, precision=8)
+        t = sim.tuning()
+        sim.set_tuning(t["transport_variant"], t["list_grid_all"], t["list_grid_level"], graph=graph,
+                       pair_links=t["pair_links"])
+        sim.init_equilibrium(m0)
+        sim.forward_record(nsteps, K)
+        t_fin, v_fin = sim.get_state()
+        _, abar = ke_functional(oracle.Oracle(cfg), t_fin, v_fin.astype(np.float64))
+        mbar, sbar = sim.adjoint(torch.from_numpy(abar).to(sim.device))
+        out.append((mbar.double().cpu().numpy(), np.array(sbar)))
+        sim.close()
+    assert _rel(out[0][0], out[1][0]) <= 1e-12
+    assert _rel(out[0][1], out[1][1]) <= 1e-12
+
+
 def test_adjoint_rejects_batches_and_unrecorded_runs(mr):
     import torch
 
