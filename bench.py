@@ -477,6 +477,16 @@ def variants(args, head):
     out["adjoint_fp32"]["accuracy"] = ("max |dJ/dm0 (FP32) - dJ/dm0 (FP64)| / max |dJ/dm0 (FP64)| = %.2e, each "
                                        "precision on the meshes it chose itself" % rel)
     out["adjoint_fp32"]["fp32_vs_fp64"] = out["adjoint_fp32"]["value"] / out["adjoint_fp64"]["value"]
+    # the same gradient with one segment: the recorded forward tapes every step
+    # (about 4.3 MB per step here) and the adjoint recomputes nothing
+    at = adjoint_run(args.adjoint_steps, args.adjoint_steps, 4)
+    grad_ms = (at["t_record"] + at["t_adjoint"]) * 1e3
+    out["adjoint_fp32_taped"] = dict(
+        workload="as adjoint_fp32, with one checkpoint: every step taped during the recorded forward",
+        value=at["leaf_updates"] / (at["t_record"] + at["t_adjoint"]),
+        unit="forward leaf updates/s of the gradient computation (record + adjoint)",
+        gradient_ms=grad_ms, forward_ms=at["t_forward"] * 1e3, gradient_over_forward=grad_ms / (at["t_forward"] * 1e3),
+        vs_checkpointed=float(torch.max(torch.abs(at["mbar"] - a32["mbar"])) / torch.max(torch.abs(a32["mbar"]))))
     out["scope_rows"] = scope_rows(args)
     return out
 

@@ -323,6 +323,9 @@ int mrlbm_read_counters(mrlbm_ctx *ctx, mrlbm_counters *out);
  * a tape of its meshes and pre-collision populations, then swept backwards
  * (the workspace holds two such tapes: the recomputation of one segment runs
  * on the context stream while the previous one is swept on a second stream).
+ * With ckpt_every >= nsteps (one segment) the recorded forward writes the tape
+ * itself, the workspace holds one tape of nsteps steps, and the adjoint
+ * recomputes nothing: the HBM-for-time trade when the tape fits.
  * Periodic boundaries, gamma = 1 and the schemes D1Q2, D1Q3 and D2Q9 only
  * (MRLBM_ERR_INVALID with a wall, gamma > 1 or the Euler scheme). */
 

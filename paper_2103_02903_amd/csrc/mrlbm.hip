@@ -462,8 +462,9 @@ void moment_mats(int scheme, double lam, double *M, double *Minv) {
 
 // Layout of the adjoint workspace: one checkpoint (codes and populations) every
 // K steps; for two segments of K steps (the one being swept backwards and the
-// one being recomputed) the tape (each step's new mesh and pre-collision
-// populations) and the mesh the segment starts from; four adjoint buffers.
+// one being recomputed; one when a single segment covers the run) the tape
+// (each step's new mesh and pre-collision populations) and the mesh the
+// segment starts from; four adjoint buffers.
 struct AdjLayout {
   int nck;
   size_t code_b, F_b, lists_b, lvl_b;
@@ -482,13 +483,14 @@ AdjLayout adj_layout(const Plan &P, int nsteps, int K) {
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   L.ck_code = take(L.code_b * std::max(1, L.nck));
   L.ck_F = take(L.F_b * std::max(1, L.nck));
-  L.tape_code = take(L.code_b * K * 2);  // tape b of a field starts at b times its size
-  L.tape_lists = take(L.lists_b * K * 2);
-  L.tape_lvl = take(L.lvl_b * K * 2);
-  L.tape_h = take(L.F_b * K * 2);
-  L.st_code = take(L.code_b * 2);
-  L.st_lists = take(L.lists_b * 2);
-  L.st_lvl = take(L.lvl_b * 2);
+  const size_t nt = L.nck > 1 ? 2 : 1, Kt = std::min(K, nsteps);  // tape b of a field starts at b times its size
+  L.tape_code = take(L.code_b * Kt * nt);
+  L.tape_lists = take(L.lists_b * Kt * nt);
+  L.tape_lvl = take(L.lvl_b * Kt * nt);
+  L.tape_h = take(L.F_b * Kt * nt);
+  L.st_code = take(L.code_b * nt);
+  L.st_lists = take(L.lists_b * nt);
+  L.st_lvl = take(L.lvl_b * nt);
   L.A = take(L.F_b);
   L.Hb = take(L.F_b);
   L.Gs = take(L.F_b);
@@ -541,6 +543,7 @@ struct mrlbm_ctx {
   // adjoint: checkpoints and tape of a recorded run (workspace owned by the caller)
   char *adj_ws;
   int adj_nsteps, adj_K;
+  bool adj_taped;  // the recorded forward wrote the tape (a single segment)
   // HIP graphs of one step, captured on a private stream: [plain (0) or with
   // event-record nodes around the transport kernel (1)][2 * cur + mcur]. The
   // timed graphs keep their source graph and event nodes, whose events are
@@ -1167,9 +1170,38 @@ struct Engine {
     k_fill_u32<<<grid_cap((n4 + BLK - 1) / BLK, DENSE_GRID), BLK, 0, st>>>((uint32_t *)p, n4, 0u);
   }
 
+  // From the current state (a restored checkpoint, or the recorded run's
+  // start): rebuild the lists and run `steps` steps into tape b of the adjoint
+  // workspace, taping each step's new mesh and pre-collision values.
+  static int tape_segment(mrlbm_ctx *c, const AdjLayout &L, int K, int b, int steps) {
+    char *w = c->adj_ws;
+    activity_reset(c);  // the other code buffer and tnew hold later meshes
+    compact(c, c->mcur);
+    copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code + b * L.code_b), (uint32_t *)(w + L.st_lists + b * L.lists_b),
+                  (int *)(w + L.st_lvl + b * L.lvl_b));
+    for (int j = 0; j < steps; ++j) {
+      const size_t k = (size_t)b * K + j;
+      int rc = adapt(c);
+      if (!rc) rc = transport(c, (T *)(w + L.tape_h + k * L.F_b));
+      if (rc) return rc;
+      copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.tape_code + k * L.code_b),
+                    (uint32_t *)(w + L.tape_lists + k * L.lists_b), (int *)(w + L.tape_lvl + k * L.lvl_b));
+    }
+    return MRLBM_OK;
+  }
+
   static int record(mrlbm_ctx *c, int nsteps, int K) {
     const AdjLayout L = adj_layout(c->P, nsteps, K);
     char *w = c->adj_ws;
+    if (L.nck == 1) {  // one segment: the run is taped now and the adjoint recomputes nothing
+      (void)hipMemcpyAsync(w + L.ck_code, c->code[c->mcur], c->P.ctotal, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(w + L.ck_F, c->F[c->cur], c->P.rs * c->P.q * c->P.ctotal, hipMemcpyDeviceToDevice,
+                           c->stream);
+      const int rc = tape_segment(c, L, K, 0, nsteps);
+      if (rc) return rc;
+      c->adj_taped = true;
+      return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
+    }
     for (int n = 0; n < nsteps; ++n) {
       if (n % K == 0) {
         const int k = n / K;
@@ -1276,26 +1308,12 @@ struct Engine {
     };
     auto tape_h = [&](int b, int j) { return (T *)(w + L.tape_h + ((size_t)b * K + j) * L.F_b); };
     auto seg_steps = [&](int seg) { return std::min(seg * K + K, nsteps) - seg * K; };
-    // from the restored checkpoint: rebuild its lists and recompute the segment
-    // into tape b, taping each step's new mesh and pre-collision values
-    auto segment_body = [&](int b, int steps) -> int {
-      activity_reset(c);  // the other code buffer and tnew hold later meshes
-      compact(c, c->mcur);
-      copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.st_code + b * L.code_b), (uint32_t *)(w + L.st_lists + b * L.lists_b),
-                    (int *)(w + L.st_lvl + b * L.lvl_b));
-      for (int j = 0; j < steps; ++j) {
-        int rc = adapt(c);
-        if (!rc) rc = transport(c, tape_h(b, j));
-        if (rc) return rc;
-        const size_t k = (size_t)b * K + j;
-        copy_mesh_out(c, c->mcur, (uint8_t *)(w + L.tape_code + k * L.code_b),
-                      (uint32_t *)(w + L.tape_lists + k * L.lists_b), (int *)(w + L.tape_lvl + k * L.lvl_b));
-      }
-      return MRLBM_OK;
-    };
+    auto segment_body = [&](int b, int steps) { return tape_segment(c, L, K, b, steps); };
     // A full segment (K steps) runs as a graph captured at its first use, one
-    // per tape; the checkpoint is restored into the buffers of parity 0 first,
+    // per tape, when there are four full segments or more (each graph is then
+    // replayed); the checkpoint is restored into the buffers of parity 0 first,
     // so every replay starts from the same buffers. Context stream.
+    const bool graphs = c->use_graph && nsteps / K >= 4;
     int mK = 0, cK = 0;  // the buffer parities after a full segment
     auto recompute = [&](int seg) -> int {
       const int b = seg & 1, steps = seg_steps(seg);
@@ -1304,7 +1322,7 @@ struct Engine {
       (void)hipMemcpyAsync(c->code[0], w + L.ck_code + seg * L.code_b, P.ctotal, hipMemcpyDeviceToDevice, c->stream);
       (void)hipMemcpyAsync(c->F[0], w + L.ck_F + seg * L.F_b, fbytes, hipMemcpyDeviceToDevice, c->stream);
       int rc = MRLBM_OK;
-      if (steps < K || !c->use_graph) {
+      if (steps < K || !graphs) {
         rc = segment_body(b, steps);
       } else {
         if (!ss.seg[b]) {
@@ -1360,7 +1378,7 @@ struct Engine {
     auto sweep = [&](int seg) -> int {
       const int b = seg & 1, steps = seg_steps(seg);
       if (hipStreamWaitEvent(rs, ss.rec[b], 0) != hipSuccess) return MRLBM_ERR_HIP;
-      if (steps < K || !c->use_graph) {
+      if (steps < K || !graphs) {
         sweep_body(b, steps, rs);
       } else {
         hipGraphExec_t &g = ss.sw[b][A == A0 ? 0 : 1];
@@ -1384,7 +1402,9 @@ struct Engine {
       }
       return hipEventRecord(ss.rev[b], rs) == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
     };
-    int rc = recompute(L.nck - 1);
+    // a run of one segment was taped by the recorded forward itself
+    int rc = c->adj_taped ? (hipEventRecord(ss.rec[0], c->stream) == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP)
+                          : recompute(L.nck - 1);
     for (int seg = L.nck - 1; seg >= 0 && !rc; --seg) {
       rc = sweep(seg);
       if (rc || seg == 0) break;
@@ -1902,6 +1922,7 @@ int create_ctx(const mrlbm_params *p, int batch, void *workspace, size_t ws_byte
   c->adj_ws = nullptr;
   c->adj_nsteps = 0;
   c->adj_K = 0;
+  c->adj_taped = false;
   c->use_graph = static_dev < 0;  // a static context creates no capture stream: kernels launched one by one
   c->cap_stream = nullptr;
   for (auto &row : c->graph)
@@ -2248,6 +2269,7 @@ int mrlbm_forward_record(mrlbm_ctx *c, void *adj_workspace, size_t bytes, int ns
   c->adj_ws = (char *)(((uintptr_t)adj_workspace + 255) & ~(uintptr_t)255);
   c->adj_nsteps = nsteps;
   c->adj_K = ckpt_every;
+  c->adj_taped = false;
   return dispatch<RecordOp>(c, nsteps, ckpt_every);
 }
 
