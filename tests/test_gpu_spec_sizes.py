@@ -138,6 +138,34 @@ def _frozen_J(mr, o, cfg, m0, trees):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
+def test_vortex_256_adjoint_800_steps_one_segment(mr, precision):
+    """The same gradient with one checkpoint: the recorded forward tapes all 800
+    steps (3.4 GB in FP32) and the adjoint sweeps without recomputing; against
+    the oracle's frozen-mesh gradient on the GPU's meshes, at the tolerances of
+    the checkpointed run below."""
+    import torch
+
+    cfg, m0 = W.random_vortex_d2q9()
+    nsteps = 800
+    o = oracle.Oracle(cfg)
+    trees = _mesh_sequence(mr, cfg, m0, nsteps, precision)
+    sim = mr.Sim(cfg, precision=precision)
+    sim.init_equilibrium(m0)
+    sim.forward_record(nsteps, nsteps)
+    t_fin, v_fin = sim.get_state()
+    assert np.array_equal(t_fin, trees[-1])
+    _, abar = ke_functional(o, t_fin, v_fin.astype(np.float64), REGION)
+    mbar_g, sbar_g = sim.adjoint(torch.from_numpy(abar).to(sim.device))
+    sim.close()
+    mbar_o, sbar_o = o.gradient_frozen(m0, trees, abar)
+    r_m = _rel(mbar_g.double().cpu().numpy(), mbar_o)
+    r_s = abs((sbar_g[7] + sbar_g[8]) - (sbar_o[7] + sbar_o[8])) / abs(sbar_o[7] + sbar_o[8])
+    print("one segment, fp%d: dJ/dm0 rel %.3e, dJ/ds2 rel %.3e" % (8 * precision, r_m, r_s), flush=True)
+    tol = 3e-13 if precision == 8 else 2.5e-4
+    assert r_m <= tol and r_s <= tol
+
+
+@pytest.mark.parametrize("precision", [8, 4])
 def test_vortex_256_adjoint_800_steps(mr, precision):
     import torch
 
