@@ -468,7 +468,8 @@ void moment_mats(int scheme, double lam, double *M, double *Minv) {
 struct AdjLayout {
   int nck;
   size_t code_b, F_b, lists_b, lvl_b;
-  size_t ck_code, ck_F, tape_code, tape_lists, tape_lvl, tape_h, st_code, st_lists, st_lvl, A, Hb, Gs, Go, spart, bytes;
+  size_t ck_code, ck_F, tape_code, tape_lists, tape_lvl, tape_h, st_code, st_lists, st_lvl, A, Hb, Gs, Go, spart, rec_lvl,
+      bytes;
 };
 constexpr int ADJ_GRID = 512;
 
@@ -496,6 +497,7 @@ AdjLayout adj_layout(const Plan &P, int nsteps, int K) {
   L.Gs = take(L.F_b);
   L.Go = take(L.F_b);
   L.spart = take(sizeof(double) * 9 * ADJ_GRID);
+  L.rec_lvl = take(L.lvl_b * ((size_t)nsteps + 1));  // list bounds of every mesh of the recorded run
   L.bytes = o + 256;
   return L;
 }
@@ -1199,9 +1201,14 @@ struct Engine {
                            c->stream);
       const int rc = tape_segment(c, L, K, 0, nsteps);
       if (rc) return rc;
+      (void)hipMemcpyAsync(w + L.rec_lvl, w + L.st_lvl, L.lvl_b, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(w + L.rec_lvl + L.lvl_b, w + L.tape_lvl, L.lvl_b * nsteps, hipMemcpyDeviceToDevice,
+                           c->stream);
       c->adj_taped = true;
       return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
     }
+    const size_t lvl_bytes = sizeof(int) * c->P.B * NCAT * LVL_STRIDE;
+    (void)hipMemcpyAsync(w + L.rec_lvl, c->lvl[c->mcur], lvl_bytes, hipMemcpyDeviceToDevice, c->stream);
     for (int n = 0; n < nsteps; ++n) {
       if (n % K == 0) {
         const int k = n / K;
@@ -1218,6 +1225,8 @@ struct Engine {
         if (!rc) rc = transport(c);
       }
       if (rc) return rc;
+      (void)hipMemcpyAsync(w + L.rec_lvl + (n + 1) * L.lvl_b, c->lvl[c->mcur], lvl_bytes, hipMemcpyDeviceToDevice,
+                           c->stream);
     }
     return hipPeekAtLastError() == hipSuccess ? MRLBM_OK : MRLBM_ERR_HIP;
   }
@@ -1226,15 +1235,17 @@ struct Engine {
   // predictions pushed up from the finest level, then projections pushed down.
   // Levels up to the coarse cap in one launch (k_adj_coarse), finer levels a
   // launch each.
-  static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms, hipStream_t st) {
+  // Levels whose ghost (internal) list is empty in every mesh of the run
+  // (bits of gm, im clear) get no launch: it would do nothing.
+  static void reconstruct_T(mrlbm_ctx *c, T *G, const Mesh &ms, hipStream_t st, uint64_t gm, uint64_t im) {
     const Plan &P = c->P;
     const int lc = std::max(P.jmin, coarse_cap(c));
     const uint32_t *lg = ms.lists + (size_t)CAT_GHOST * P.ctotal, *li = ms.lists + (size_t)CAT_INTERNAL * P.ctotal;
     for (int l = P.maxJ; l > lc; --l)
-      k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, lg, ms.lvl, l);
+      if ((gm >> l) & 1u) k_adj_ghost<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, lg, ms.lvl, l);
     k_adj_coarse<DIM, Q, T><<<P.B, CBLK, 0, st>>>(I(c), G, lg, li, ms.lvl, lc);
     for (int l = lc; l <= P.maxJ - 1; ++l)
-      k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, li, ms.lvl, l);
+      if ((im >> l) & 1u) k_adj_project<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), G, li, ms.lvl, l);
   }
 
   // A second stream and its events for the adjoint sweep, and the graphs of
@@ -1283,6 +1294,23 @@ struct Engine {
       for (int k = 0; k < 81; ++k) {
         mm.M[k] = (T)M[k];
         mm.Minv[k] = (T)Minv[k];
+      }
+    }
+    // the levels whose ghost or internal list is non-empty in some mesh of the
+    // recorded run (the list bounds the recorded forward kept)
+    uint64_t gmask = 0, imask = 0;
+    {
+      std::vector<int> bounds((size_t)(nsteps + 1) * (L.lvl_b / sizeof(int)));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      HIPCHK(hipMemcpy(bounds.data(), w + L.rec_lvl, L.lvl_b * ((size_t)nsteps + 1), hipMemcpyDeviceToHost));
+      const int jmin = P.inst[0].jmin, jmax = P.inst[0].jmax;
+      for (int n = 0; n <= nsteps; ++n) {
+        const int *Lv = bounds.data() + (size_t)n * (L.lvl_b / sizeof(int));
+        const int *Lg = Lv + CAT_GHOST * LVL_STRIDE, *Li = Lv + CAT_INTERNAL * LVL_STRIDE;
+        for (int l = jmin; l <= jmax; ++l) {
+          if (Lg[l + 1] > Lg[l]) gmask |= 1ull << l;
+          if (Li[l + 1] > Li[l]) imask |= 1ull << l;
+        }
       }
     }
     // The segments' recomputations run on the context stream and their reverse
@@ -1365,9 +1393,9 @@ struct Engine {
             c->bt, I(c), Hb, Gs, mn.code, mn.lists, mn.lvl, (const T *)c->W, P.nmax);
         k_adj_transport<DIM, SCHEME, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), Hb, Gs, mn.code, leaves_n, mn.lvl,
                                                                   (const T *)c->C);
-        reconstruct_T(c, Gs, mn, st);
+        reconstruct_T(c, Gs, mn, st, gmask, imask);
         k_adj_transfer<DIM, Q, T><<<ADJ_GRID, BLK, 0, st>>>(c->bt, I(c), Gs, Go, mo.code, leaves_n, mn.lvl);
-        reconstruct_T(c, Go, mo, st);
+        reconstruct_T(c, Go, mo, st, gmask, imask);
         std::swap(A, Go);
       }
     };
